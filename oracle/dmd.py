@@ -1,0 +1,225 @@
+"""Plain FP64 CPU oracle of the DMD hot path.  TEST INFRASTRUCTURE ONLY.
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  The product path (the HIP library and its Python binding)
+never calls it.  It shares no code with the GPU path: it uses NumPy / LAPACK in
+float64 / complex128 and writes every step the way the paper defines it.
+
+Paper: Chen et al., "Fast Subspace Fluid Simulation with a Temporally-Aware
+Basis" (ACM TOG 2025).
+
+Readings where the paper is silent or garbled (each also listed in the design doc):
+  * X = U S V^T is the ordinary thin SVD (the paper's Sec. 3.1 swaps the names
+    of the singular-vector factors).
+  * Modes are the exact DMD modes  Phi = X' V_r S_r^-1 W  (the paper writes the
+    projected relation w_i = U^T phi_i; both give identical reconstructions once
+    the amplitudes absorb the scale).
+  * Projections use the pseudo-inverse Phi^+ (DMD modes are not orthogonal);
+    the paper's Phi^* is read as Phi^+, as its Sec. 6.2 writes.
+  * The amplitudes are b = Phi^+ x_0 (least squares on the first snapshot).
+  * Re() is taken after the sum over modes.
+  * Powers are lambda^e = exp(e * Log lambda) on the principal branch, for
+    integer e (arbitrary time step, Sec. 4.4) and real e = t / dt (Sec. 6.1).
+  * lambda = 0: 0^0 = 1, 0^k = 0 for k > 0.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class DMDFit:
+    """Result of a fit: eigenvalues, full-space complex modes, amplitudes.
+
+    lam: (r,) complex128;  phi: (N, r) complex128 (N may be a row subset);
+    b: (r,) complex128;  sigma: (r,) singular values kept;  atilde: (r, r) reduced
+    operator;  w: (r, r) eigenvectors of atilde;  v: (m-1, r) right singular
+    vectors kept.
+    """
+
+    lam: np.ndarray
+    phi: np.ndarray
+    b: np.ndarray
+    sigma: np.ndarray
+    atilde: np.ndarray
+    w: np.ndarray
+    v: np.ndarray
+
+
+def split_snapshots(Z):
+    """X = [u_0 .. u_{T-1}], X' = [u_1 .. u_T]: Sec. 3.1, eq. reduced_koopman."""
+    Z = np.asarray(Z, dtype=np.float64)
+    return Z[:, :-1], Z[:, 1:]
+
+
+def thin_svd(X):
+    """Thin SVD X = U diag(s) V^T with s descending (LAPACK gesdd)."""
+    U, s, Vt = np.linalg.svd(X, full_matrices=False)
+    return U, s, Vt.T
+
+
+def thin_svd_qr_route(Z):
+    """Thin SVD of X = Z[:, :-1] through a Householder QR of Z.
+
+    Z = Q R, so X = Q R[:, :-1] and the SVD of the small R[:, :-1] gives the SVD
+    of X with U = Q U_R.  Returns (U, s, V, QtXp) where QtXp = Q^T X' = R[:, 1:].
+    """
+    Q, R = np.linalg.qr(np.asarray(Z, dtype=np.float64))
+    Ur, s, Vt = np.linalg.svd(R[:, :-1], full_matrices=False)
+    return Q @ Ur, s, Vt.T, Ur.T @ R[:, 1:]
+
+
+def reduced_operator(Ur_t_Xp, V_r, s_r):
+    """Atilde = U_r^T X' V_r S_r^-1 (Sec. 3.1, after eq. reduced_koopman_solution).
+
+    Ur_t_Xp is the r x (m-1) product U_r^T X'.
+    """
+    return (Ur_t_Xp @ V_r) / s_r[None, :]
+
+
+def dmd_from_svd(Xp, U_t_Xp, s, V, r, x0):
+    """Steps shared by the exact and randomized oracles once an SVD is known.
+
+    U_t_Xp: U^T X' for all available left singular vectors (rows beyond r are
+    ignored); s, V: singular values and right singular vectors (descending).
+    """
+    s_r = s[:r]
+    V_r = V[:, :r]
+    at = reduced_operator(U_t_Xp[:r], V_r, s_r)          # r x r
+    lam, W = np.linalg.eig(at)                             # LAPACK geev, unit columns
+    M = (V_r / s_r[None, :]) @ W                           # (m-1) x r complex
+    phi = Xp @ M                                           # exact modes X' V S^-1 W
+    b = np.linalg.lstsq(phi, x0.astype(np.complex128), rcond=None)[0]   # b = Phi^+ x0
+    order = canonical_order(lam)
+    return DMDFit(lam[order], phi[:, order], b[order], s_r.copy(), at, W[:, order], V_r)
+
+
+def fit_exact(Z, r, route="svd"):
+    """Exact DMD of rank r (Sec. 3.1, eqs. reduced_koopman .. reduced_koopman_simulation).
+
+    route="svd": thin SVD of X by LAPACK; route="qr": the same SVD through a
+    Householder QR of Z (see thin_svd_qr_route).
+    """
+    X, Xp = split_snapshots(Z)
+    if route == "svd":
+        U, s, V = thin_svd(X)
+        U_t_Xp = U[:, :r].T @ Xp
+    elif route == "qr":
+        _, s, V, U_t_Xp = thin_svd_qr_route(Z)
+    else:
+        raise ValueError(route)
+    return dmd_from_svd(Xp, U_t_Xp, s, V, r, X[:, 0])
+
+
+def range_finder(X, Omega, q):
+    """Randomized subspace iteration (Halko, Martinsson & Tropp 2011, Alg. 4.4).
+
+    Y = X Omega, Q = qr(Y); then q times: W = qr(X^T Q), Q = qr(X W).  Householder
+    QR throughout.  This is the basis Q with X ~ Q Q^T X of Sec. 4.3.
+    """
+    Q, _ = np.linalg.qr(X @ Omega)
+    for _ in range(q):
+        Wq, _ = np.linalg.qr(X.T @ Q)
+        Q, _ = np.linalg.qr(X @ Wq)
+    return Q
+
+
+def fit_randomized(Z, r, Omega, q):
+    """FP64 randomized twin of the GPU fit (Sec. 4.3 then Sec. 3.1).
+
+    Uses the given sketch Omega ((m-1) x l, the values handed to the GPU), the
+    basis Q from range_finder, B = Q^T X and Q^T X' from one product Q^T Z, the
+    SVD of the small B, then the same reduced operator / eigen / mode / amplitude
+    steps as the exact DMD.
+    """
+    X, Xp = split_snapshots(Z)
+    Q = range_finder(X, np.asarray(Omega, dtype=np.float64), q)
+    Bz = Q.T @ np.asarray(Z, dtype=np.float64)
+    B, Bp = Bz[:, :-1], Bz[:, 1:]
+    Ub, s, Vt = np.linalg.svd(B, full_matrices=False)
+    return dmd_from_svd(Xp, Ub.T @ Bp, s, Vt.T, r, X[:, 0])
+
+
+def canonical_order(lam):
+    """Ascending |arg lambda|, ties by descending |lambda|, conjugate pairs with Im > 0 first.
+
+    (The paper sorts modes by the size of the imaginary part, Sec. 6.3.1.)
+    """
+    lam = np.asarray(lam)
+    keys = [(round(abs(np.angle(z)), 12), -round(abs(z), 12), -np.sign(z.imag), i)
+            for i, z in enumerate(lam)]
+    return np.array([k[-1] for k in sorted(keys)], dtype=np.int64)
+
+
+def powers(lam, e):
+    """lambda^e = exp(e * Log lambda) for an array of exponents e (Sec. 4.4, Sec. 6.1).
+
+    Returns an (r, len(e)) complex128 array.  lambda = 0 gives 1 for e = 0 and 0
+    for e > 0.
+    """
+    lam = np.asarray(lam, dtype=np.complex128)
+    e = np.asarray(e, dtype=np.float64)
+    out = np.zeros((lam.size, e.size), dtype=np.complex128)
+    nz = lam != 0
+    out[nz] = np.exp(np.outer(np.log(lam[nz]), e))
+    if (~nz).any():
+        out[~nz] = np.where(e == 0, 1.0, 0.0)[None, :]
+    return out
+
+
+def reconstruct(phi, lam, b, ks):
+    """U[:, j] = Re(Phi diag(lambda^{k_j}) b): eq. large_time_step (Sec. 4.4)."""
+    P = powers(lam, ks) * np.asarray(b, dtype=np.complex128)[:, None]
+    return (np.asarray(phi, dtype=np.complex128) @ P).real
+
+
+def integrate(phi, lam, b, ts, dt=1.0):
+    """u(t) = Re(Phi exp(Omega t) b) with Omega = Log(Lambda) / dt: eq. edit_temporal (Sec. 6.1)."""
+    Om = np.log(np.asarray(lam, dtype=np.complex128)) / dt
+    P = np.exp(np.outer(Om, np.asarray(ts, dtype=np.float64))) * np.asarray(b)[:, None]
+    return (np.asarray(phi, dtype=np.complex128) @ P).real
+
+
+def project(phi, u):
+    """z = Phi^+ u: eq. projection (Sec. 3.1)."""
+    return np.linalg.lstsq(np.asarray(phi, dtype=np.complex128),
+                           np.asarray(u, dtype=np.complex128), rcond=None)[0]
+
+
+def loss(phi, lam, b, Xt, ks):
+    """L(lambda, b) = sum_j || x_{k_j} - Re(Phi (b * lambda^{k_j})) ||^2."""
+    R = np.asarray(Xt, dtype=np.float64) - reconstruct(phi, lam, b, ks)
+    return float(np.sum(R * R))
+
+
+def loss_grad(phi, lam, b, Xt, ks):
+    """Closed-form gradient of L with respect to lambda and b.
+
+    With R_j = x_j - Re(Phi c_j), c_ij = b_i lambda_i^{k_j} and G = Phi^T R
+    (transpose, not conjugate transpose):
+        dL/dc_ij  = -2 conj(G_ij)                 (as  dL/dRe + i dL/dIm)
+        grad_b_i  = -2 conj( sum_j G_ij lambda_i^{k_j} )
+        grad_l_i  = -2 conj( sum_j G_ij k_j b_i lambda_i^{k_j - 1} )
+    which is the convention of complex autograd (grad = dL/dRe + i dL/dIm).
+    """
+    phi = np.asarray(phi, dtype=np.complex128)
+    lam = np.asarray(lam, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    ks = np.asarray(ks, dtype=np.float64)
+    R = np.asarray(Xt, dtype=np.float64) - reconstruct(phi, lam, b, ks)
+    G = phi.T @ R                                              # r x ncols complex
+    Pk = powers(lam, ks)                                       # lambda^k
+    Pkm1 = np.zeros_like(Pk)
+    for j, k in enumerate(ks):                                 # k lambda^{k-1}, 0 when k = 0
+        if k != 0:
+            Pkm1[:, j] = k * powers(lam, [k - 1])[:, 0]
+    grad_b = -2.0 * np.conj(np.sum(G * Pk, axis=1))
+    grad_l = -2.0 * np.conj(np.sum(G * Pkm1, axis=1) * b)
+    return float(np.sum(R * R)), grad_l, grad_b
+
+
+def koopman_least_squares(X, Xp):
+    """K = X' X^+ : the minimiser of ||X' - K X||_F (Sec. 3.1, eq. reduced_koopman_solution)."""
+    return Xp @ np.linalg.pinv(X)

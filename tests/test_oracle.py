@@ -1,0 +1,381 @@
+"""Pins of the FP64 oracle against mathematics the paper fixes (CPU only).
+
+The paper prints no numerical worked example, eigenvalue table or field error
+value, so no pin here uses a number from it ("parity unpinned" by the paper);
+every pin comes from a closed form, a textbook special case, an invariant the
+paper states, or brute force on tiny inputs.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle.metrics import eig_errors, field_errors
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _truth(g):
+    lam = np.concatenate([g.lam, np.conj(g.lam)])
+    return lam
+
+
+# ---------------------------------------------------------------- closed form
+@pytest.mark.parametrize("seed", [102, 103, 104])
+def test_closed_form_linear_system(seed):
+    """Noise-free snapshots of a rank-16 linear system: DMD returns its eigenvalues
+    and rebuilds the data (Sec. 3.1: a mode representable in the reduced space
+    keeps its eigenvalue)."""
+    cfg = synth.config("c1-cf", seed=seed)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    e = eig_errors(f.lam, _truth(g))
+    assert e["max_rel"] <= 1e-10
+    U = oracle.reconstruct(f.phi, f.lam, f.b, np.arange(cfg.m))
+    assert field_errors(U, g.Z)["max_frame"] <= 1e-12
+
+
+def test_rotation_golden():
+    """Hand-built 2x2 rotation-scaling system lifted to 5 DOFs (tests/golden/rotation_2x2.json).
+
+    u_{j+1} = P A P^T u_j with A = rho [[cos t, -sin t], [sin t, cos t]] and P
+    with orthonormal columns; its nonzero Koopman eigenvalues are rho e^{+-it}.
+    """
+    with open(os.path.join(GOLDEN, "rotation_2x2.json")) as fh:
+        gd = json.load(fh)
+    rho, th = gd["rho"], gd["theta"]
+    P = np.array(gd["P"], dtype=np.float64)
+    A = rho * np.array([[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]])
+    u = P @ np.array(gd["y0"], dtype=np.float64)
+    Z = np.empty((5, gd["m"]))
+    for j in range(gd["m"]):
+        Z[:, j] = u
+        u = P @ (A @ (P.T @ u))
+    f = oracle.fit_exact(Z, 2)
+    expect = np.array([rho * complex(math.cos(th), math.sin(th)),
+                       rho * complex(math.cos(th), -math.sin(th))])
+    assert np.allclose(f.lam, expect, rtol=0, atol=1e-13)
+    assert f.lam[0].imag > 0          # canonical order: Im > 0 member first
+    # stored expectation written by hand from the closed form
+    assert abs(f.lam[0] - complex(*gd["lambda_plus"])) <= 1e-12
+    U = oracle.reconstruct(f.phi, f.lam, f.b, np.arange(gd["m"]))
+    assert np.abs(U - Z).max() <= 1e-13
+
+
+# ---------------------------------------------------------- textbook / brute
+def test_textbook_koopman_tiny():
+    """At full rank, DMD eigenvalues are the nonzero eigenvalues of K = X' X^+ and
+    K Phi = Phi Lambda (Sec. 3.1, eq. reduced_koopman_solution)."""
+    rng = np.random.default_rng(7)
+    N, m = 9, 6
+    Z = rng.standard_normal((N, m))
+    X, Xp = oracle.split_snapshots(Z)
+    r = m - 1
+    f = oracle.fit_exact(Z, r)
+    K = oracle.koopman_least_squares(X, Xp)
+    ev = np.linalg.eigvals(K)
+    ev = ev[np.argsort(-np.abs(ev))][:r]
+    assert eig_errors(f.lam, ev)["max_rel"] <= 1e-10
+    res = K @ f.phi - f.phi * f.lam[None, :]
+    assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(f.phi)
+
+
+def test_var1_special_case():
+    """More frames than DOFs: full-rank DMD is the VAR(1) least-squares fit X' = A X
+    (Sec. 7, eq. var) and its eigenvalues are those of A."""
+    rng = np.random.default_rng(11)
+    N, m = 4, 40
+    A = rng.standard_normal((N, N)) * 0.4
+    Z = np.empty((N, m))
+    Z[:, 0] = rng.standard_normal(N)
+    for j in range(1, m):
+        Z[:, j] = A @ Z[:, j - 1] + 1e-2 * rng.standard_normal(N)
+    X, Xp = oracle.split_snapshots(Z)
+    A_ls = np.linalg.lstsq(X.T, Xp.T, rcond=None)[0].T
+    f = oracle.fit_exact(Z, N)
+    assert eig_errors(f.lam, np.linalg.eigvals(A_ls))["max_rel"] <= 1e-11
+
+
+@pytest.mark.parametrize("shape", [(7, 5), (30, 9), (12, 13)])
+def test_svd_routes_brute_force(shape):
+    """Thin SVD by LAPACK, by the QR route, and by eig(X^T X) agree on tiny inputs."""
+    rng = np.random.default_rng(sum(shape))
+    Z = rng.standard_normal(shape)
+    X, Xp = oracle.split_snapshots(Z)
+    U, s, V = oracle.thin_svd(X)
+    U2, s2, V2, QtXp = oracle.thin_svd_qr_route(Z)
+    ev = np.sort(np.linalg.eigvalsh(X.T @ X))[::-1][:len(s)]
+    assert np.allclose(s, s2, rtol=1e-12, atol=1e-13)
+    assert np.allclose(s ** 2, ev, rtol=1e-10, atol=1e-12)
+    assert np.allclose((U * s) @ V.T, X, atol=1e-12)
+    assert np.allclose((U2 * s2) @ V2.T, X, atol=1e-12)
+    k = min(len(s), Z.shape[1] - 1)
+    assert np.allclose(np.abs(U2[:, :k].T @ Xp), np.abs(QtXp[:k]), atol=1e-11)
+
+
+def test_routes_agree_on_fit():
+    """Exact DMD through LAPACK SVD and through the QR route give the same result."""
+    cfg = synth.config("c1-cf", seed=103)
+    g = synth.generate(cfg)
+    f1 = oracle.fit_exact(g.Z, cfg.r, route="svd")
+    f2 = oracle.fit_exact(g.Z, cfg.r, route="qr")
+    assert eig_errors(f1.lam, f2.lam)["max_rel"] <= 1e-12
+    ks = np.arange(100)
+    U1 = oracle.reconstruct(f1.phi, f1.lam, f1.b, ks)
+    U2 = oracle.reconstruct(f2.phi, f2.lam, f2.b, ks)
+    assert field_errors(U2, U1)["max_frame"] <= 1e-11
+
+
+# --------------------------------------------------------------- randomized
+def test_randomized_equals_exact_low_rank():
+    """Halko et al.: with rank(X) <= l the randomized range finder is exact, so the
+    randomized twin equals the exact DMD (Sec. 4.3)."""
+    cfg = synth.Config("lowrank", (2, 32, 32), 60, 10, 0.95, 0.0, 31, r=20,
+                       p=6, q=1, jitter=True)
+    g = synth.generate(cfg)
+    Z = g.Z.astype(np.float64)
+    fe = oracle.fit_exact(Z, cfg.r)
+    fr = oracle.fit_randomized(Z, cfg.r, g.Omega, cfg.q)
+    assert eig_errors(fr.lam, fe.lam)["max_rel"] <= 1e-9
+    ks = np.arange(cfg.m)
+    Ue = oracle.reconstruct(fe.phi, fe.lam, fe.b, ks)
+    Ur = oracle.reconstruct(fr.phi, fr.lam, fr.b, ks)
+    assert field_errors(Ur, Ue)["max_frame"] <= 1e-9
+
+
+def test_randomized_equals_exact_well_posed():
+    """Signal far above the noise and r equal to the signal rank: twin == exact."""
+    cfg = synth.Config("wp", (2, 48, 48), 120, 30, 0.95, 1e-6, 202, r=60, p=10,
+                       q=2, jitter=True)
+    g = synth.generate(cfg)
+    Z = g.Z.astype(np.float64)
+    fe = oracle.fit_exact(Z, cfg.r)
+    fr = oracle.fit_randomized(Z, cfg.r, g.Omega, cfg.q)
+    assert eig_errors(fr.lam, fe.lam)["max_rel"] <= 1e-8
+    assert eig_errors(fe.lam, _truth(g))["max_rel"] <= 1e-4
+    ks = np.arange(cfg.m)
+    Ue = oracle.reconstruct(fe.phi, fe.lam, fe.b, ks)
+    Ur = oracle.reconstruct(fr.phi, fr.lam, fr.b, ks)
+    assert field_errors(Ur, Ue)["max_frame"] <= 1e-8
+
+
+def test_range_finder_orthonormal():
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((200, 40))
+    Q = oracle.range_finder(X, rng.standard_normal((40, 12)), 2)
+    assert np.allclose(Q.T @ Q, np.eye(12), atol=1e-13)
+
+
+# --------------------------------------------------------------- invariants
+def _periodic_diff(n):
+    D = np.zeros((n, n))
+    for i in range(n):
+        D[i, (i + 1) % n] = 0.5
+        D[i, (i - 1) % n] = -0.5
+    return D
+
+
+def test_constraint_inherited():
+    """C X = 0 implies C Phi = 0 (Sec. 4.5): divergence-free data give
+    divergence-free modes."""
+    n = 16
+    D = _periodic_diff(n)
+    I = np.eye(n)
+    Dx = np.kron(I, D)          # d/dx on a row-major n x n grid
+    Dy = np.kron(D, I)
+    C = np.hstack([Dx, Dy])     # discrete divergence of (u, v)
+    rng = np.random.default_rng(5)
+    nc = 6
+    psi = rng.standard_normal((n * n, nc)) + 1j * rng.standard_normal((n * n, nc))
+    modes = np.vstack([Dy @ psi, -(Dx @ psi)])
+    lam = synth.draw_eigs(rng, nc, 0.9, jitter=True)
+    b = synth.draw_amplitudes(rng, nc)
+    Z = synth.snapshots(modes, lam, b, 40, 0.0, rng)
+    assert np.linalg.norm(C @ Z) <= 1e-13 * np.linalg.norm(C) * np.linalg.norm(Z)
+    f = oracle.fit_exact(Z, 2 * nc)
+    rel = np.linalg.norm(C @ f.phi) / (np.linalg.norm(C) * np.linalg.norm(f.phi))
+    assert rel <= 1e-14
+
+
+def test_powers_exp_log_vs_repeated_multiplication():
+    """lambda^k by exp(k Log lambda) equals k single steps (Sec. 4.4 vs eq.
+    reduced_koopman_simulation)."""
+    rng = np.random.default_rng(9)
+    lam = synth.draw_eigs(rng, 20, 0.95)
+    P = oracle.powers(lam, [5000])[:, 0]
+    z = np.ones_like(lam)
+    for _ in range(5000):
+        z = z * lam
+    assert np.max(np.abs(P - z) / np.abs(z)) <= 1e-12
+    P0 = oracle.powers(np.array([0.0, 0.5]), [0, 1, 2])
+    assert np.allclose(P0, [[1, 0, 0], [1, 0.5, 0.25]])
+
+
+def test_time_reversal_round_trip():
+    """Lambda^-1 reverses the reduced dynamics (Sec. 6.2, eq. reverse_simulation)."""
+    cfg = synth.config("c1-cf", seed=104)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    k = 37
+    zk = f.b * oracle.powers(f.lam, [k])[:, 0]
+    back = zk * oracle.powers(f.lam, [-k])[:, 0]
+    assert np.allclose(back, f.b, rtol=1e-12, atol=1e-14)
+    Uback = oracle.reconstruct(f.phi, f.lam, zk, [-k])
+    assert field_errors(Uback, g.Z[:, :1])["max_frame"] <= 1e-11
+
+
+def test_integrate_matches_integer_steps_and_semigroup():
+    """exp(Omega t) at t = k dt equals Lambda^k; exp(Omega(t1+t2)) = exp(Omega t1) exp(Omega t2)."""
+    cfg = synth.config("c1-cf", seed=102)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    dt = 0.25
+    ks = np.array([0, 1, 7, 64])
+    U1 = oracle.reconstruct(f.phi, f.lam, f.b, ks)
+    U2 = oracle.integrate(f.phi, f.lam, f.b, ks * dt, dt=dt)
+    assert field_errors(U2, U1)["max_frame"] <= 1e-13
+    t1, t2 = 3.3, 11.45
+    b1 = f.b * np.exp(np.log(f.lam) / dt * t1)
+    Ua = oracle.integrate(f.phi, f.lam, f.b, [t1 + t2], dt=dt)
+    Ub = oracle.integrate(f.phi, f.lam, b1, [t2], dt=dt)
+    assert field_errors(Ub, Ua)["max_frame"] <= 1e-12
+
+
+def test_project_recovers_amplitudes():
+    """z = Phi^+ u (eq. projection) applied to the k = 0 reconstruction returns b."""
+    cfg = synth.config("c1-cf", seed=103)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    u0 = oracle.reconstruct(f.phi, f.lam, f.b, [0])[:, 0]
+    z = oracle.project(f.phi, u0)
+    assert np.allclose(z, f.b, rtol=1e-10, atol=1e-12)
+
+
+# ------------------------------------------------------------------ adjoint
+def _small_problem(seed=21, N=40, r=6, ncols=9):
+    rng = np.random.default_rng(seed)
+    phi = rng.standard_normal((N, r)) + 1j * rng.standard_normal((N, r))
+    lam = synth.draw_eigs(rng, r, 0.9)
+    b = synth.draw_amplitudes(rng, r)
+    Xt = rng.standard_normal((N, ncols))
+    ks = np.arange(ncols)
+    return phi, lam, b, Xt, ks
+
+
+def test_adjoint_matches_autograd():
+    torch = pytest.importorskip("torch")
+    phi, lam, b, Xt, ks = _small_problem()
+    L, gl, gb = oracle.loss_grad(phi, lam, b, Xt, ks)
+    tl = torch.tensor(lam, dtype=torch.complex128, requires_grad=True)
+    tb = torch.tensor(b, dtype=torch.complex128, requires_grad=True)
+    tphi = torch.tensor(phi, dtype=torch.complex128)
+    tk = torch.tensor(ks, dtype=torch.float64)
+    P = torch.exp(torch.outer(torch.log(tl), tk.to(torch.complex128))) * tb[:, None]
+    R = torch.tensor(Xt) - (tphi @ P).real
+    Lt = (R * R).sum()
+    Lt.backward()
+    assert abs(L - Lt.item()) <= 1e-12 * abs(L)
+    assert np.allclose(gl, tl.grad.numpy(), rtol=1e-10, atol=1e-10)
+    assert np.allclose(gb, tb.grad.numpy(), rtol=1e-10, atol=1e-10)
+
+
+def test_adjoint_matches_finite_differences():
+    """Central differences (h = 1e-6) on Re and Im parts separately."""
+    phi, lam, b, Xt, ks = _small_problem(seed=22)
+    _, gl, gb = oracle.loss_grad(phi, lam, b, Xt, ks)
+    h = 1e-6
+    for which, g in (("lam", gl), ("b", gb)):
+        for i in range(len(lam)):
+            for unit in (1.0, 1j):
+                lp, ln, bp, bn = lam.copy(), lam.copy(), b.copy(), b.copy()
+                if which == "lam":
+                    lp[i] += h * unit
+                    ln[i] -= h * unit
+                else:
+                    bp[i] += h * unit
+                    bn[i] -= h * unit
+                fd = (oracle.loss(phi, lp, bp, Xt, ks) - oracle.loss(phi, ln, bn, Xt, ks)) / (2 * h)
+                an = g[i].real if unit == 1.0 else g[i].imag
+                assert abs(fd - an) <= 1e-6 * max(1.0, abs(an)), (which, i, unit, fd, an)
+
+
+def test_loss_zero_at_exact_model():
+    cfg = synth.config("c1-cf", seed=102)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    ks = np.arange(cfg.m)
+    L, gl, gb = oracle.loss_grad(f.phi, f.lam, f.b, g.Z, ks)
+    assert L <= 1e-20 * np.sum(g.Z ** 2)
+    assert np.max(np.abs(gb)) <= 1e-8
+
+
+# ------------------------------------------------------------------ metrics
+def test_metrics_invariant_to_order_and_folding():
+    rng = np.random.default_rng(2)
+    lam = synth.draw_eigs(rng, 10, 0.9)
+    perm = rng.permutation(10)
+    assert eig_errors(lam[perm], lam)["max_rel"] == 0.0
+    phi = rng.standard_normal((8, 2)) + 1j * rng.standard_normal((8, 2))
+    folded = np.stack([phi[:, 0].real, phi[:, 0].imag, phi[:, 1].real], axis=1)
+    cm = oracle.complex_modes_from_folded(folded, [1, 2, 0])
+    assert np.allclose(cm[:, 0], phi[:, 0]) and np.allclose(cm[:, 1], np.conj(phi[:, 0]))
+    assert np.allclose(cm[:, 2], phi[:, 1].real)
+
+
+def test_canonical_order():
+    lam = np.array([0.9 * np.exp(-0.3j), 0.5, 0.9 * np.exp(0.3j), 0.95])
+    o = oracle.canonical_order(lam)
+    assert list(o) == [3, 1, 2, 0]
+
+
+# ---------------------------------------------- planted mistakes are caught
+def test_planted_missing_sigma_inverse_is_caught(monkeypatch):
+    """Dropping S_r^-1 from the reduced operator must break the closed-form pin."""
+    import oracle.dmd as od
+    monkeypatch.setattr(od, "reduced_operator", lambda UtXp, V, s: UtXp @ V)
+    cfg = synth.config("c1-cf", seed=102)
+    g = synth.generate(cfg)
+    f = od.fit_exact(g.Z, cfg.r)
+    assert eig_errors(f.lam, _truth(g))["max_rel"] > 1e-3
+
+
+def test_planted_gradient_sign_is_caught(monkeypatch):
+    """A dropped conjugate in the gradient must disagree with finite differences."""
+    import oracle.dmd as od
+    phi, lam, b, Xt, ks = _small_problem(seed=23)
+    real = od.loss_grad
+    monkeypatch.setattr(od, "loss_grad", lambda *a: (lambda L, gl, gb: (L, np.conj(gl), gb))(*real(*a)))
+    _, gl, _ = od.loss_grad(phi, lam, b, Xt, ks)
+    h = 1e-6
+    lp, ln = lam.copy(), lam.copy()
+    lp[0] += 1j * h
+    ln[0] -= 1j * h
+    fd = (od.loss(phi, lp, b, Xt, ks) - od.loss(phi, ln, b, Xt, ks)) / (2 * h)
+    assert abs(fd - gl[0].imag) > 1e-3 * max(1.0, abs(fd))
+
+
+def test_planted_swapped_snapshots_is_caught(monkeypatch):
+    """Swapping X and X' (fitting the backward map) must break the closed-form pin."""
+    import oracle.dmd as od
+    real = od.split_snapshots
+    monkeypatch.setattr(od, "split_snapshots", lambda Z: real(Z)[::-1])
+    cfg = synth.config("c1-cf", seed=103)
+    g = synth.generate(cfg)
+    f = od.fit_exact(g.Z, cfg.r)
+    assert eig_errors(f.lam, _truth(g))["max_rel"] > 1e-3
+
+
+def test_planted_wrong_real_part_is_caught(monkeypatch):
+    """Taking Im instead of Re of the mode sum must break the rebuild pin."""
+    import oracle.dmd as od
+    monkeypatch.setattr(od, "reconstruct", lambda phi, lam, b, ks: (
+        np.asarray(phi) @ (od.powers(lam, ks) * np.asarray(b)[:, None])).imag)
+    cfg = synth.config("c1-cf", seed=102)
+    g = synth.generate(cfg)
+    f = od.fit_exact(g.Z, cfg.r)
+    U = od.reconstruct(f.phi, f.lam, f.b, np.arange(cfg.m))
+    assert field_errors(U, g.Z)["max_frame"] > 1e-3
