@@ -1,0 +1,285 @@
+/*
+ * dmdmi.h - C ABI of the MI355X (gfx950) DMD hot path.
+ *
+ * Method: Dynamic Mode Decomposition as used by Chen et al., "Fast Subspace
+ * Fluid Simulation with a Temporally-Aware Basis" (ACM TOG 2025):
+ *   - snapshot pair X = [u_0 .. u_{T-1}], X' = [u_1 .. u_T]     (Sec. 3.1, eq. reduced_koopman)
+ *   - K = X' V S^-1 U^T from the thin SVD X = U S V^T, truncated to rank r,
+ *     reduced operator Atilde = U_r^T X' V_r S_r^-1, its eigen-decomposition
+ *     Atilde W = W Lambda                                        (Sec. 3.1, eq. reduced_koopman_solution)
+ *   - randomized SVD: X ~ Q Q^T X, B = Q^T X, SVD of the small B (Sec. 4.3)
+ *   - amplitudes z = Phi^+ u                                     (Sec. 3.1, eq. projection)
+ *   - u(t + k dt) = Phi Lambda^k z(t) in one product             (Sec. 4.4, eq. large_time_step)
+ *   - u(t) = Phi exp(Omega t) z with Omega = Log(Lambda)/dt      (Sec. 6.1, eq. edit_temporal)
+ *   - Lambda^-1 runs the reduced model backwards                 (Sec. 6.2, eq. reverse_simulation)
+ *
+ * Conventions shared by every call
+ *   - All device memory (inputs, outputs, model arrays, workspace) is owned by
+ *     the caller.  The library never allocates or frees device memory; each
+ *     call that needs scratch memory has a *_workspace_size query.
+ *   - `stream` is a hipStream_t passed as void*.  Every call only enqueues work
+ *     on that stream, except dmd_fit without DMD_FIT_ASYNC, which waits for the
+ *     stream to reach the end of the fit and returns the fit's device status.
+ *   - Host arrays are borrowed for the duration of the call only.
+ *   - Inputs are never modified.
+ *   - Matrices are column-major unless stated otherwise; leading dimensions and
+ *     sizes are 64-bit and counted in elements.
+ *   - Errors: every call returns a dmd_status.  Argument validation happens on
+ *     the host before any HIP call; on error nothing is enqueued.  Errors found
+ *     on the device during a fit (Cholesky breakdown, rank loss, eigen-solver
+ *     non-convergence) are written to model->info[0] and returned by the
+ *     synchronous dmd_fit.  No exception or exit() crosses the ABI.  On error
+ *     the outputs are unspecified and nothing leaks.
+ *
+ * Model storage (real "folded" modes).  For real snapshots the DMD eigenvalues
+ * and modes come in exact complex-conjugate pairs.  The model stores each pair
+ * (phi, conj(phi)) as two real columns [Re phi, Im phi] and each real mode as
+ * one real column, the storage LAPACK uses for real eigenvectors.  kind[i] = 0
+ * marks a real mode, kind[i] = 1 / kind[i+1] = 2 a conjugate pair whose complex
+ * modes are phi_i = P[:, i] + 1j P[:, i+1] and phi_{i+1} = conj(phi_i).
+ * lam[] and b[] hold all r complex values (both members of each pair), so
+ * they can be edited independently; Re() of the mode sum is always taken.
+ * Mode order: ascending |arg lambda|, ties by descending |lambda|, the member
+ * with Im lambda > 0 first (the paper orders modes by the size of their
+ * imaginary part, Sec. 6.3.1).
+ */
+#ifndef DMDMI_H
+#define DMDMI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DMDMI_ABI_VERSION 1
+
+/* Status codes. */
+typedef enum dmd_status {
+    DMD_OK = 0,
+    DMD_ERR_ARG = 1,            /* null pointer, bad enum, misaligned pointer or leading dimension */
+    DMD_ERR_SHAPE = 2,          /* r > m-1, l > m-1, l > N, K <= 0, ... */
+    DMD_ERR_WORKSPACE = 3,      /* workspace smaller than the *_workspace_size query */
+    DMD_ERR_NONFINITE = 4,      /* NaN or Inf in the input (only with DMD_FIT_CHECK_FINITE) */
+    DMD_ERR_CHOL_BREAKDOWN = 5, /* CholeskyQR failed even after the shifted retry */
+    DMD_ERR_RANK = 6,           /* sigma_r <= rank_tol * sigma_1 */
+    DMD_ERR_EIG_NOCONV = 7,     /* Jacobi or Francis QR iteration limit reached */
+    DMD_ERR_DOMAIN = 8,         /* reserved: lambda = 0 raised to a negative or fractional power */
+    DMD_ERR_OVERFLOW = 9,       /* reserved: |b| |lambda|^k beyond the output type's range */
+    DMD_ERR_HIP = 10,           /* a HIP runtime call failed */
+    DMD_ERR_UNSUPPORTED = 11    /* size beyond what a single-workgroup small-matrix kernel holds */
+} dmd_status;
+
+/* Element types. */
+typedef enum dmd_dtype { DMD_F32 = 0, DMD_F64 = 1 } dmd_dtype;
+
+/* Fit precision. */
+typedef enum dmd_fit_precision {
+    /* Randomized SVD; FP32 streaming GEMMs (MFMA, FP32 accumulate); FP64 Gram
+     * products, Cholesky, small SVD, eigen-decomposition; FP32 modes. X is FP32. */
+    DMD_FIT_MIXED = 0,
+    /* The same randomized algorithm entirely in FP64 (the plain path). X is FP64. */
+    DMD_FIT_FP64_RANDOMIZED = 1,
+    /* Exact thin SVD of X (no sketch) through the FP64 Gram of the snapshots
+     * (method of snapshots).  X is FP64; m-1 <= DMD_MAX_SMALL. */
+    DMD_FIT_FP64_EXACT = 2
+} dmd_fit_precision;
+
+/* Reconstruction arithmetic. */
+typedef enum dmd_recon_mode {
+    DMD_RECON_FP64 = 0,   /* FP64 modes, FP64 MFMA, FP64 output */
+    DMD_RECON_FP32 = 1,   /* FP32 modes, FP32 MFMA, FP32 output */
+    DMD_RECON_BF16 = 2,   /* modes and coefficients rounded to BF16, FP32 accumulate/output */
+    DMD_RECON_BF16X3 = 3  /* split-BF16 (hi+lo, three products), FP32 accumulate/output */
+} dmd_recon_mode;
+
+/* Limits of the single-workgroup FP64 kernels (packed matrices held in LDS). */
+#define DMD_MAX_SMALL 192   /* l = r + p, and m-1 for DMD_FIT_FP64_EXACT */
+#define DMD_MAX_RANK 160    /* r (nonsymmetric eigen-solver) */
+
+/* Fit flags. */
+#define DMD_FIT_ASYNC 1u         /* do not wait for the stream; status stays in model->info[0] */
+#define DMD_FIT_CHECK_FINITE 2u  /* scan X and X' for NaN/Inf first */
+
+/* Options of a fit. */
+typedef struct dmd_fit_opts {
+    int32_t r;          /* rank (number of modes), 1 <= r */
+    int32_t p;          /* oversampling, l = r + p columns in the sketch (randomized) */
+    int32_t q;          /* power iterations (randomized), >= 0 */
+    int32_t precision;  /* dmd_fit_precision */
+    double dt;          /* time between snapshots (> 0), stored in the model */
+    double rank_tol;    /* > 0: fail with DMD_ERR_RANK when sigma_r <= rank_tol * sigma_1 */
+    const void* omega;  /* device (m-1) x l Gaussian sketch, column-major, ld = m-1, same
+                           element type as X; NULL for DMD_FIT_FP64_EXACT.  The sketch is an
+                           input so that a reference implementation can use the same draw. */
+    uint32_t flags;     /* DMD_FIT_* */
+    int32_t reserved;
+} dmd_fit_opts;
+
+/* Number of int32 words in model->info. */
+#define DMD_INFO_WORDS 8
+/* info[0] status, [1] Jacobi sweeps, [2] Francis QR iterations, [3] shifted
+ * CholeskyQR retries, [4..7] reserved. */
+
+/* A DMD model; every pointer is device memory owned by the caller. */
+typedef struct dmd_model {
+    int64_t n;        /* rows N (grid DOFs) */
+    int32_t r;        /* number of modes */
+    int32_t dtype;    /* dmd_dtype of phi */
+    double dt;        /* time step of the snapshots */
+    void* phi;        /* N x ldphi, ROW-major (the r mode values of a grid point are
+                         contiguous), folded real storage; columns r..ldphi-1 are zero */
+    int64_t ldphi;    /* >= dmd_phi_ld(r) */
+    double* lam;      /* r complex eigenvalues, interleaved (re, im) */
+    double* b;        /* r complex amplitudes, interleaved (re, im) */
+    double* sigma;    /* r singular values kept by the fit (written by dmd_fit) */
+    int32_t* kind;    /* r entries, 0 real / 1 first of pair / 2 second of pair */
+    int32_t* info;    /* DMD_INFO_WORDS status / diagnostic words (written by dmd_fit) */
+} dmd_model;
+
+/* One scene of a batched fit. */
+typedef struct dmd_scene {
+    const void* x;    /* device X, N x ncols */
+    const void* xp;   /* device X', N x ncols */
+    int64_t n;
+    int32_t ncols;    /* m - 1 */
+    int32_t xdtype;   /* dmd_dtype of X and X' */
+    int64_t ldx;
+    int64_t ldxp;
+    dmd_fit_opts opts;
+    void* ws;         /* this scene's workspace (dmd_fit_workspace_size) */
+    size_t ws_bytes;
+} dmd_scene;
+
+typedef struct dmd_graph dmd_graph;  /* opaque captured launch graph */
+
+/* ABI version (DMDMI_ABI_VERSION). */
+int32_t dmd_abi_version(void);
+
+/* Static description of a status code (never NULL). */
+const char* dmd_status_string(int32_t status);
+
+/* Minimal leading dimension of phi for r modes: r rounded up to 32. */
+int64_t dmd_phi_ld(int32_t r);
+
+/* Workspace bytes for dmd_fit on an N x ncols snapshot pair of element type xdtype. */
+int32_t dmd_fit_workspace_size(int64_t n, int32_t ncols, int32_t xdtype,
+                               const dmd_fit_opts* opts, size_t* bytes);
+
+/*
+ * Fit a rank-r DMD model to the snapshot pair (X, X').
+ *   x, xp    device, N x ncols (ncols = m-1), column-major with leading dimensions
+ *            ldx, ldxp >= N.  When xp == x + ldx elements and ldxp == ldx (the two
+ *            shifted views of one snapshot buffer Z, eq. reduced_koopman) the
+ *            projection reads Z in one pass.
+ *   xdtype   DMD_F32 for DMD_FIT_MIXED, DMD_F64 otherwise.
+ *   model    caller-filled: n, phi (N x ldphi, dtype = F32 for MIXED else F64),
+ *            ldphi, lam, b, sigma, kind, info; the fit sets r, dtype, dt and writes
+ *            every array.
+ * Steps (Sec. 4.3 then Sec. 3.1): sketch Y = X Omega; CholeskyQR2 (FP64 Gram);
+ * q power iterations W = orth(X^T Q), Y = X W; B = Q^T [X X']; eigen-decomposition
+ * of the FP64 Gram B B^T by Jacobi (singular values and left vectors of B);
+ * Atilde = U_r^T B' V_r S_r^-1; Hessenberg + Francis double-shift QR for
+ * lambda and W; exact modes Phi = X' V_r S_r^-1 W; b = Phi^+ x_0.
+ * Returns the device status unless DMD_FIT_ASYNC is set.
+ */
+int32_t dmd_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t ncols,
+                int64_t ldx, int64_t ldxp, int32_t xdtype, const dmd_fit_opts* opts,
+                void* ws, size_t ws_bytes, dmd_model* model);
+
+/* Workspace bytes for dmd_reconstruct / dmd_integrate of K frames at rank r. */
+int32_t dmd_reconstruct_workspace_size(int32_t r, int32_t K, int32_t mode, size_t* bytes);
+
+/*
+ * U[:, j] = Re( Phi diag(lambda^{k_j}) b ), j = 0..K-1 (Sec. 4.4, eq. large_time_step;
+ * negative k runs the model backwards, Sec. 6.2).
+ *   k_host  host, K integer exponents (copied to the workspace, stream-ordered)
+ *   mode    dmd_recon_mode; DMD_RECON_FP64 needs an F64 model and an FP64 U,
+ *           the other modes an F32 model and an FP32 U
+ *   U       device, N x K column-major (frame j contiguous), ldu >= N
+ * lambda^k is evaluated in FP64 as exp(k Log lambda) (0^0 = 1, 0^k = 0 for k > 0);
+ * lambda = 0 with k < 0 gives non-finite values.
+ */
+int32_t dmd_reconstruct(void* stream, const dmd_model* model, const int64_t* k_host,
+                        int32_t K, int32_t mode, void* U, int64_t ldu, void* ws,
+                        size_t ws_bytes);
+
+/*
+ * U[:, j] = Re( Phi exp(Omega t_j) b ), Omega = Log(Lambda) / dt (Sec. 6.1,
+ * eq. edit_temporal), principal branch, for real times t_host[0..T-1].
+ * Same layout, modes and workspace as dmd_reconstruct (K = T).
+ */
+int32_t dmd_integrate(void* stream, const dmd_model* model, const double* t_host,
+                      int32_t T, int32_t mode, void* U, int64_t ldu, void* ws,
+                      size_t ws_bytes);
+
+/* Workspace bytes for dmd_project. */
+int32_t dmd_project_workspace_size(int64_t n, int32_t r, size_t* bytes);
+
+/*
+ * z = Phi^+ u (Sec. 3.1, eq. projection): least-squares reduced state of a full
+ * state u (device, N values of the model's dtype).  z: device, r complex
+ * (interleaved), conjugate-paired like lam.  FP64 Gram of Phi + Cholesky solve.
+ */
+int32_t dmd_project(void* stream, const dmd_model* model, const void* u, double* z,
+                    void* ws, size_t ws_bytes);
+
+/* Workspace bytes for dmd_loss_grad. */
+int32_t dmd_loss_grad_workspace_size(int64_t n, int32_t r, int32_t ncols, int32_t dtype,
+                                     size_t* bytes);
+
+/*
+ * Loss and adjoint of the full-space reconstruction with the modes held fixed:
+ *   L(lambda, b) = sum_j || x_j - Re(Phi (b .* lambda^{k_j})) ||^2
+ *   G = Phi^T R (transpose), grad_b = -2 conj(sum_j G_ij lambda_i^{k_j}),
+ *   grad_lambda = -2 conj(sum_j G_ij k_j b_i lambda_i^{k_j - 1})
+ * (gradients as dL/dRe + i dL/dIm, the complex-autograd convention).
+ *   lam, b   device, r complex each (the variables; the model's lam/b are ignored)
+ *   xt       device target frames, N x ncols column-major, ldxt >= N, model dtype
+ *   k_host   host, ncols exponents (frame j of xt is compared with lambda^{k_j})
+ *   out      device, 1 + 4r doubles: loss, grad_lambda (r complex), grad_b (r complex)
+ * The residual and G run as MFMA GEMMs in the model's precision; loss, lambda^k
+ * and the r-reductions are FP64.
+ */
+int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam,
+                      const double* b, const void* xt, int64_t ldxt, const int64_t* k_host,
+                      int32_t ncols, double* out, void* ws, size_t ws_bytes);
+
+/*
+ * Fit several independent scenes.  Each scene's fit runs on its own forked
+ * stream (default priority) joined back into `stream`, so the latency-bound
+ * small-matrix stages of different scenes overlap.  With capture != 0 the whole
+ * batch is captured once into a HIP graph returned in *graph (nothing runs until
+ * dmd_graph_launch); otherwise it is enqueued directly.  Scenes must use
+ * DMD_FIT_ASYNC semantics (statuses land in each model's info[0]).
+ */
+int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes,
+                        dmd_model* models, int32_t capture, dmd_graph** graph);
+
+/* Launch a captured batch on `stream`. */
+int32_t dmd_graph_launch(dmd_graph* graph, void* stream);
+
+/* Destroy a captured batch and the streams it forked. */
+int32_t dmd_graph_destroy(dmd_graph* graph);
+
+/*
+ * Autotuner for the reconstruction kernel: times each candidate tile shape on
+ * the given model and output, keeps the fastest for this (mode, r, N, K) class
+ * in the in-process table (used by later dmd_reconstruct calls) and appends it
+ * to the text cache file `cache_path` (may be NULL).  best_cfg receives the
+ * chosen candidate index.
+ */
+int32_t dmd_autotune_reconstruct(void* stream, const dmd_model* model, int32_t K,
+                                 int32_t mode, void* U, int64_t ldu, void* ws,
+                                 size_t ws_bytes, const char* cache_path,
+                                 int32_t* best_cfg);
+
+/* Load autotuner entries from a cache file written by dmd_autotune_reconstruct. */
+int32_t dmd_autotune_load(const char* cache_path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMDMI_H */

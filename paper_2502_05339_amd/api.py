@@ -1,0 +1,440 @@
+"""Python binding of the MI355X DMD library: argument marshalling over the C ABI.
+
+Every step of the method runs in the HIP library (libdmdmi.so); this module only
+allocates torch tensors for outputs and workspace, fills the C structs and calls
+the C entry points on torch's current HIP stream.  There is no CPU fallback: a
+missing library or GPU raises.
+
+Layouts
+  * snapshots: a (m, N) tensor whose row j is frame u_j (row-major (m, N) is the
+    column-major N x m matrix Z of the C ABI); X = Z[:-1], X' = Z[1:].
+  * Model.phi: (N, ldphi) row-major folded real modes (see include/dmdmi.h).
+  * reconstructions: (K, N) tensors, row k = frame k.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (DMD_F32, DMD_F64, FIT_ASYNC, FIT_CHECK_FINITE, FIT_FP64_EXACT, FIT_FP64_RANDOMIZED,
+                   FIT_MIXED, RECON_BF16, RECON_BF16X3, RECON_FP32, RECON_FP64, check)
+
+PRECISIONS = {"mixed": FIT_MIXED, "fp64": FIT_FP64_RANDOMIZED, "fp64_exact": FIT_FP64_EXACT}
+RECON_MODES = {"fp64": RECON_FP64, "fp32": RECON_FP32, "bf16": RECON_BF16, "bf16x3": RECON_BF16X3}
+
+_ws_cache: dict = {}
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _require_gpu(t: torch.Tensor, name: str):
+    if not torch.cuda.is_available():
+        raise RuntimeError("the DMD library needs a HIP GPU (no CPU fallback)")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """A cached byte workspace per (device, stream), grown on demand (stream-ordered reuse)."""
+    key = (str(device), _stream())
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else t.data_ptr()
+
+
+def _size_t():
+    return ctypes.c_size_t(0)
+
+
+@dataclasses.dataclass
+class Model:
+    """A fitted (or prescribed) DMD model held in device memory."""
+
+    phi: torch.Tensor      # (N, ldphi) float32/float64, folded real modes
+    lam: torch.Tensor      # (r,) complex128
+    b: torch.Tensor        # (r,) complex128
+    sigma: torch.Tensor    # (r,) float64
+    kind: torch.Tensor     # (r,) int32
+    info: torch.Tensor     # (8,) int32
+    dt: float = 1.0
+
+    @property
+    def n(self) -> int:
+        return self.phi.shape[0]
+
+    @property
+    def r(self) -> int:
+        return self.lam.shape[0]
+
+    @property
+    def dtype_code(self) -> int:
+        return DMD_F32 if self.phi.dtype == torch.float32 else DMD_F64
+
+    def struct(self, lam: torch.Tensor | None = None, b: torch.Tensor | None = None) -> _lib.ModelStruct:
+        s = _lib.ModelStruct()
+        s.n = self.n
+        s.r = self.r
+        s.dtype = self.dtype_code
+        s.dt = float(self.dt)
+        s.phi = self.phi.data_ptr()
+        s.ldphi = self.phi.stride(0)
+        s.lam = (self.lam if lam is None else lam).data_ptr()
+        s.b = (self.b if b is None else b).data_ptr()
+        s.sigma = self.sigma.data_ptr()
+        s.kind = self.kind.data_ptr()
+        s.info = self.info.data_ptr()
+        return s
+
+    @staticmethod
+    def empty(n: int, r: int, dtype: torch.dtype, device, dt: float = 1.0) -> "Model":
+        ld = int(_lib.lib().dmd_phi_ld(r))
+        return Model(
+            phi=torch.zeros((n, ld), dtype=dtype, device=device),
+            lam=torch.zeros(r, dtype=torch.complex128, device=device),
+            b=torch.zeros(r, dtype=torch.complex128, device=device),
+            sigma=torch.zeros(r, dtype=torch.float64, device=device),
+            kind=torch.zeros(r, dtype=torch.int32, device=device),
+            info=torch.zeros(_lib.INFO_WORDS, dtype=torch.int32, device=device),
+            dt=dt,
+        )
+
+    @staticmethod
+    def from_pairs(phi_pairs: np.ndarray, lam_pairs: np.ndarray, b_pairs: np.ndarray, dtype=torch.float32,
+                   device="cuda", dt: float = 1.0) -> "Model":
+        """Prescribed model with exact conjugate pairs: modes {phi, conj(phi)}, eigenvalues
+        {lam, conj(lam)}, amplitudes {b, conj(b)}; lam_pairs should have Im > 0."""
+        nc = lam_pairs.shape[0]
+        r = 2 * nc
+        n = phi_pairs.shape[0]
+        m = Model.empty(n, r, dtype, device, dt)
+        folded = np.zeros((n, m.phi.shape[1]), dtype=np.float64 if dtype == torch.float64 else np.float32)
+        folded[:, 0:r:2] = phi_pairs.real
+        folded[:, 1:r:2] = phi_pairs.imag
+        m.phi.copy_(torch.from_numpy(folded))
+        lam = np.empty(r, dtype=np.complex128)
+        bb = np.empty(r, dtype=np.complex128)
+        lam[0::2], lam[1::2] = lam_pairs, np.conj(lam_pairs)
+        bb[0::2], bb[1::2] = b_pairs, np.conj(b_pairs)
+        kind = np.tile(np.array([1, 2], dtype=np.int32), nc)
+        m.lam.copy_(torch.from_numpy(lam))
+        m.b.copy_(torch.from_numpy(bb))
+        m.kind.copy_(torch.from_numpy(kind))
+        return m
+
+    # ---- host views
+    def lam_host(self) -> np.ndarray:
+        return self.lam.cpu().numpy()
+
+    def b_host(self) -> np.ndarray:
+        return self.b.cpu().numpy()
+
+    def kind_host(self) -> np.ndarray:
+        return self.kind.cpu().numpy()
+
+    def complex_modes(self, rows=None) -> np.ndarray:
+        """Complex modes (N x r, or a row subset) built from the folded storage."""
+        ph = self.phi[:, : self.r] if rows is None else self.phi[rows, : self.r]
+        ph = ph.double().cpu().numpy()
+        kind = self.kind_host()
+        out = np.zeros((ph.shape[0], self.r), dtype=np.complex128)
+        i = 0
+        while i < self.r:
+            if kind[i] == 0:
+                out[:, i] = ph[:, i]
+                i += 1
+            else:
+                out[:, i] = ph[:, i] + 1j * ph[:, i + 1]
+                out[:, i + 1] = np.conj(out[:, i])
+                i += 2
+        return out
+
+    # ---- evaluation
+    def reconstruct(self, ks, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+        return reconstruct(self, ks, mode, out)
+
+    def integrate(self, ts, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+        return integrate(self, ts, mode, out)
+
+    def project(self, u: torch.Tensor) -> torch.Tensor:
+        return project(self, u)
+
+    # ---- checkpoint
+    def save(self, path: str):
+        np.savez(path, phi=self.phi.cpu().numpy(), lam=self.lam_host(), b=self.b_host(),
+                 sigma=self.sigma.cpu().numpy(), kind=self.kind_host(), dt=np.float64(self.dt),
+                 version=np.int32(_lib.lib().dmd_abi_version()))
+
+    @staticmethod
+    def load(path: str, device="cuda") -> "Model":
+        with np.load(path, allow_pickle=False) as z:
+            phi = torch.from_numpy(z["phi"]).to(device)
+            m = Model(phi=phi, lam=torch.from_numpy(z["lam"]).to(device), b=torch.from_numpy(z["b"]).to(device),
+                      sigma=torch.from_numpy(z["sigma"]).to(device), kind=torch.from_numpy(z["kind"]).to(device),
+                      info=torch.zeros(_lib.INFO_WORDS, dtype=torch.int32, device=device), dt=float(z["dt"]))
+        return m
+
+
+def _xview(Z: torch.Tensor | None, X: torch.Tensor | None, Xp: torch.Tensor | None):
+    """(x_ptr, xp_ptr, n, ncols, ldx, ldxp, dtype_code) from a snapshot buffer or an (X, X') pair."""
+    if Z is not None:
+        if Z.dim() != 2 or Z.stride(1) != 1:
+            raise ValueError("snapshots must be a (m, N) tensor with unit stride along N")
+        m, n = Z.shape
+        x, xp, ld, ldp = Z.data_ptr(), Z[1].data_ptr(), Z.stride(0), Z.stride(0)
+        ncols = m - 1
+        dt = Z.dtype
+    else:
+        if X.shape != Xp.shape or X.stride(1) != 1 or Xp.stride(1) != 1:
+            raise ValueError("X and X' must be (m-1, N) tensors with unit stride along N")
+        ncols, n = X.shape
+        x, xp, ld, ldp = X.data_ptr(), Xp.data_ptr(), X.stride(0), Xp.stride(0)
+        dt = X.dtype
+    code = DMD_F32 if dt == torch.float32 else DMD_F64
+    return x, xp, n, ncols, ld, ldp, code
+
+
+def fit_opts(r: int, p: int = 10, q: int = 2, precision: str = "mixed", omega: torch.Tensor | None = None,
+             dt: float = 1.0, rank_tol: float = 0.0, check_finite: bool = False, asynchronous: bool = False):
+    o = _lib.FitOpts()
+    o.r, o.p, o.q = int(r), int(p), int(q)
+    o.precision = PRECISIONS[precision]
+    o.dt = float(dt)
+    o.rank_tol = float(rank_tol)
+    o.omega = _ptr(omega)
+    o.flags = (FIT_CHECK_FINITE if check_finite else 0) | (FIT_ASYNC if asynchronous else 0)
+    return o
+
+
+def fit(Z: torch.Tensor | None = None, r: int = 0, *, X: torch.Tensor | None = None, Xp: torch.Tensor | None = None,
+        p: int = 10, q: int = 2, omega: torch.Tensor | None = None, precision: str = "mixed", dt: float = 1.0,
+        rank_tol: float = 0.0, check_finite: bool = False, asynchronous: bool = False) -> Model:
+    """Fit a rank-r DMD model (Sec. 4.3 randomized SVD, then Sec. 3.1).
+
+    Z: (m, N) snapshots (or X, Xp: (m-1, N) each); omega: (l, m-1) tensor holding the
+    column-major (m-1) x l Gaussian sketch (i.e. omega.T is the sketch), same dtype as Z;
+    precision: "mixed" (FP32 input), "fp64" (FP64 input, randomized) or "fp64_exact".
+    """
+    src = Z if Z is not None else X
+    _require_gpu(src, "snapshots")
+    x, xp, n, ncols, ld, ldp, code = _xview(Z, X, Xp)
+    o = fit_opts(r, p, q, precision, omega, dt, rank_tol, check_finite, asynchronous)
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    check(L.dmd_fit_workspace_size(n, ncols, code, ctypes.byref(o), ctypes.byref(nb)), "dmd_fit_workspace_size")
+    ws = _workspace(nb.value, src.device)
+    model = Model.empty(n, r, torch.float32 if code == DMD_F32 else torch.float64, src.device, dt)
+    ms = model.struct()
+    st = L.dmd_fit(_stream(), x, xp, n, ncols, ld, ldp, code, ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                   ctypes.byref(ms))
+    check(st, "dmd_fit")
+    return model
+
+
+def _default_mode(model: Model) -> str:
+    return "fp64" if model.dtype_code == DMD_F64 else "bf16x3"
+
+
+def _recon_common(model: Model, K: int, mode: str | None, out: torch.Tensor | None):
+    mode = mode or _default_mode(model)
+    mcode = RECON_MODES[mode]
+    odt = torch.float64 if mcode == RECON_FP64 else torch.float32
+    if out is None:
+        out = torch.empty((K, model.n), dtype=odt, device=model.phi.device)
+    if out.dtype != odt or out.shape[0] != K or out.shape[1] != model.n or out.stride(1) != 1:
+        raise ValueError("output must be a (K, N) tensor of the mode's dtype with unit stride along N")
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    check(L.dmd_reconstruct_workspace_size(model.r, K, mcode, ctypes.byref(nb)), "dmd_reconstruct_workspace_size")
+    ws = _workspace(nb.value, model.phi.device)
+    return mcode, out, ws
+
+
+def reconstruct(model: Model, ks, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """U[k] = Re(Phi diag(lambda^k) b) for every integer k in ks (Sec. 4.4)."""
+    _require_gpu(model.phi, "model.phi")
+    k = np.ascontiguousarray(np.asarray(ks, dtype=np.int64).ravel())
+    mcode, out, ws = _recon_common(model, k.size, mode, out)
+    ms = model.struct()
+    st = _lib.lib().dmd_reconstruct(_stream(), ctypes.byref(ms), k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    k.size, mcode, out.data_ptr(), out.stride(0), ws.data_ptr(), ws.numel())
+    check(st, "dmd_reconstruct")
+    return out
+
+
+def integrate(model: Model, ts, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
+    """U[j] = Re(Phi exp(Omega t_j) b), Omega = Log(Lambda)/dt (Sec. 6.1)."""
+    _require_gpu(model.phi, "model.phi")
+    t = np.ascontiguousarray(np.asarray(ts, dtype=np.float64).ravel())
+    mcode, out, ws = _recon_common(model, t.size, mode, out)
+    ms = model.struct()
+    st = _lib.lib().dmd_integrate(_stream(), ctypes.byref(ms), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  t.size, mcode, out.data_ptr(), out.stride(0), ws.data_ptr(), ws.numel())
+    check(st, "dmd_integrate")
+    return out
+
+
+def project(model: Model, u: torch.Tensor) -> torch.Tensor:
+    """z = Phi^+ u (Sec. 3.1, eq. projection); returns (r,) complex128 on the device."""
+    _require_gpu(u, "u")
+    if u.dtype != model.phi.dtype or u.numel() != model.n or not u.is_contiguous():
+        raise ValueError("u must be a contiguous N-vector of the model's dtype")
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    check(L.dmd_project_workspace_size(model.n, model.r, ctypes.byref(nb)), "dmd_project_workspace_size")
+    ws = _workspace(nb.value, u.device)
+    z = torch.empty(model.r, dtype=torch.complex128, device=u.device)
+    ms = model.struct()
+    check(L.dmd_project(_stream(), ctypes.byref(ms), u.data_ptr(), z.data_ptr(), ws.data_ptr(), ws.numel()),
+          "dmd_project")
+    return z
+
+
+def loss_grad(model: Model, lam: torch.Tensor, b: torch.Tensor, X: torch.Tensor, ks):
+    """(loss, grad_lambda, grad_b) of sum_j ||x_j - Re(Phi (b lambda^{k_j}))||^2 (modes fixed).
+
+    X: (ncols, N) target frames (row j = frame compared with lambda^{k_j}), model dtype.
+    Gradients follow complex autograd (dL/dRe + i dL/dIm).  Returns device tensors.
+    """
+    _require_gpu(X, "X")
+    if X.dtype != model.phi.dtype or X.stride(1) != 1 or X.shape[1] != model.n:
+        raise ValueError("X must be (ncols, N) of the model's dtype with unit stride along N")
+    lam = lam.detach().to(torch.complex128).contiguous()
+    b = b.detach().to(torch.complex128).contiguous()
+    k = np.ascontiguousarray(np.asarray(ks, dtype=np.int64).ravel())
+    if k.size != X.shape[0]:
+        raise ValueError("one exponent per target frame")
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    check(L.dmd_loss_grad_workspace_size(model.n, model.r, k.size, model.dtype_code, ctypes.byref(nb)),
+          "dmd_loss_grad_workspace_size")
+    ws = _workspace(nb.value, X.device)
+    out = torch.empty(1 + 4 * model.r, dtype=torch.float64, device=X.device)
+    ms = model.struct()
+    st = L.dmd_loss_grad(_stream(), ctypes.byref(ms), lam.data_ptr(), b.data_ptr(), X.data_ptr(), X.stride(0),
+                         k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k.size, out.data_ptr(), ws.data_ptr(),
+                         ws.numel())
+    check(st, "dmd_loss_grad")
+    r = model.r
+    gl = torch.view_as_complex(out[1:1 + 2 * r].view(r, 2))
+    gb = torch.view_as_complex(out[1 + 2 * r:].view(r, 2))
+    return out[0], gl, gb
+
+
+class DMDLoss(torch.autograd.Function):
+    """L(lambda, b) = sum_j ||x_j - Re(Phi (b .* lambda^{k_j}))||^2 with the modes fixed.
+
+    forward runs the library's fused residual / adjoint; backward returns the
+    gradients it produced (hand-written adjoint, no autograd graph through the kernels).
+    """
+
+    @staticmethod
+    def forward(ctx, lam, b, model: Model, X: torch.Tensor, ks):
+        loss, gl, gb = loss_grad(model, lam, b, X, ks)
+        ctx.save_for_backward(gl.clone(), gb.clone())
+        return loss.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        gl, gb = ctx.saved_tensors
+        return g * gl, g * gb, None, None, None
+
+
+def refit(model: Model, X: torch.Tensor, ks, steps: int = 200, lr: float = 1e-3, optimizer: str = "adam"):
+    """Refit lambda and b by gradient steps on the full-space loss (modes fixed).
+
+    A noise-robust refit in the spirit of OptDMD (Sec. 4.2): every snapshot of the
+    horizon enters the loss at once.  Returns (lam, b, losses) and leaves the model
+    unchanged.
+    """
+    lam = model.lam.clone().requires_grad_(True)
+    b = model.b.clone().requires_grad_(True)
+    opt = torch.optim.Adam([lam, b], lr=lr) if optimizer == "adam" else torch.optim.SGD([lam, b], lr=lr)
+    losses = []
+    for _ in range(steps):
+        opt.zero_grad(set_to_none=True)
+        loss = DMDLoss.apply(lam, b, model, X, ks)
+        loss.backward()
+        opt.step()
+        losses.append(loss.detach())
+    return lam.detach(), b.detach(), torch.stack(losses).cpu().numpy()
+
+
+class BatchedFit:
+    """Several independent fits captured once into a HIP graph (one forked stream per scene)."""
+
+    def __init__(self, scenes, capture: bool = True):
+        """scenes: list of dicts with keys Z (m, N tensor), r, p, q, omega, precision, dt."""
+        L = _lib.lib()
+        self.models = []
+        self._keep = []
+        n = len(scenes)
+        self._sc = (_lib.SceneStruct * n)()
+        self._ms = (_lib.ModelStruct * n)()
+        for i, s in enumerate(scenes):
+            Z = s["Z"]
+            _require_gpu(Z, "Z")
+            x, xp, nn, ncols, ld, ldp, code = _xview(Z, None, None)
+            o = fit_opts(s["r"], s.get("p", 10), s.get("q", 2), s.get("precision", "mixed"), s.get("omega"),
+                         s.get("dt", 1.0), 0.0, False, True)
+            nb = ctypes.c_size_t(0)
+            check(L.dmd_fit_workspace_size(nn, ncols, code, ctypes.byref(o), ctypes.byref(nb)), "workspace")
+            ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=Z.device)
+            m = Model.empty(nn, s["r"], torch.float32 if code == DMD_F32 else torch.float64, Z.device,
+                            s.get("dt", 1.0))
+            self.models.append(m)
+            self._keep += [Z, ws, s.get("omega")]
+            sc = self._sc[i]
+            sc.x, sc.xp, sc.n, sc.ncols, sc.xdtype, sc.ldx, sc.ldxp = x, xp, nn, ncols, code, ld, ldp
+            sc.opts = o
+            sc.ws, sc.ws_bytes = ws.data_ptr(), ws.numel()
+            self._ms[i] = m.struct()
+        self.graph = ctypes.c_void_p(0)
+        self.capture = capture
+        if capture:
+            check(L.dmd_fit_batched(_stream(), n, self._sc, self._ms, 1, ctypes.byref(self.graph)),
+                  "dmd_fit_batched")
+        else:
+            check(L.dmd_fit_batched(_stream(), n, self._sc, self._ms, 0, None), "dmd_fit_batched")
+
+    def launch(self):
+        if not self.capture:
+            raise RuntimeError("not captured")
+        check(_lib.lib().dmd_graph_launch(self.graph, _stream()), "dmd_graph_launch")
+
+    def statuses(self):
+        return [int(m.info[0].item()) for m in self.models]
+
+    def close(self):
+        if self.capture and self.graph.value:
+            _lib.lib().dmd_graph_destroy(self.graph)
+            self.graph = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_reconstruct(model: Model, K: int, mode: str | None = None, cache_path: str | None = None) -> int:
+    """Time the reconstruction kernel's tile-shape candidates on this model; keep the fastest."""
+    mcode, out, ws = _recon_common(model, K, mode, None)
+    ms = model.struct()
+    best = ctypes.c_int32(-1)
+    st = _lib.lib().dmd_autotune_reconstruct(_stream(), ctypes.byref(ms), K, mcode, out.data_ptr(), out.stride(0),
+                                             ws.data_ptr(), ws.numel(),
+                                             None if cache_path is None else cache_path.encode(), ctypes.byref(best))
+    check(st, "dmd_autotune_reconstruct")
+    return best.value

@@ -1,0 +1,712 @@
+// Host orchestration and the extern "C" boundary of the DMD hot path.
+//
+// Every entry point validates its arguments on the host before the first HIP
+// call, carves the caller's workspace with the same routine that answers the
+// size query, and only enqueues kernels on the caller's stream.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+using namespace dmd;
+
+namespace {
+
+// ---------------------------------------------------------------- workspace carving
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <typename T> T* take(size_t count) {
+        off = (size_t)round_up((int64_t)off, 256);
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    size_t bytes() const { return (size_t)round_up((int64_t)off, 256); }
+};
+
+#define HIPCHK(x)                                   \
+    do {                                            \
+        hipError_t e_ = (x);                        \
+        if (e_ != hipSuccess) return DMD_ERR_HIP;   \
+    } while (0)
+
+size_t esize(int dt) { return dt == DMD_F32 ? 4 : 8; }
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+std::once_flag g_init_once;
+void lib_init();
+
+// ---------------------------------------------------------------- fit plan
+struct FitArgs {
+    const void* x;
+    const void* xp;
+    int64_t n;
+    int ncols;
+    int64_t ldx, ldxp;
+    int xdtype;
+    dmd_fit_opts o;
+    bool shifted;   // X' is the one-column shift of X inside one snapshot buffer Z
+};
+
+bool is_shifted_view(const void* x, const void* xp, int64_t ldx, int64_t ldxp, int dt)
+{
+    return x && ldx == ldxp && (uintptr_t)xp == (uintptr_t)x + (uintptr_t)(ldx * (dt == DMD_F32 ? 4 : 8));
+}
+
+int32_t validate_fit(const FitArgs& a, const dmd_model* model, bool need_ptrs)
+{
+    const dmd_fit_opts& o = a.o;
+    if (a.n < 1 || a.ncols < 1) return DMD_ERR_SHAPE;
+    if (o.precision < DMD_FIT_MIXED || o.precision > DMD_FIT_FP64_EXACT) return DMD_ERR_ARG;
+    if (a.xdtype != (o.precision == DMD_FIT_MIXED ? DMD_F32 : DMD_F64)) return DMD_ERR_ARG;
+    if (o.r < 1 || o.r > a.ncols || o.r > a.n) return DMD_ERR_SHAPE;
+    if (o.r > DMD_MAX_RANK) return DMD_ERR_UNSUPPORTED;
+    if (!(o.dt > 0.0) || !isfinite(o.dt)) return DMD_ERR_ARG;
+    if (o.rank_tol < 0.0 || !isfinite(o.rank_tol)) return DMD_ERR_ARG;
+    if (o.precision == DMD_FIT_FP64_EXACT) {
+        if (a.ncols > DMD_MAX_SMALL) return DMD_ERR_UNSUPPORTED;
+    } else {
+        if (o.p < 0 || o.q < 0 || o.q > 64) return DMD_ERR_ARG;
+        const int l = o.r + o.p;
+        if (l > a.ncols || l > a.n) return DMD_ERR_SHAPE;
+        if (l > DMD_MAX_SMALL) return DMD_ERR_UNSUPPORTED;
+        if (need_ptrs && !o.omega) return DMD_ERR_ARG;
+    }
+    if (need_ptrs) {
+        if (!a.x || !a.xp || !model) return DMD_ERR_ARG;
+        if (a.ldx < a.n || a.ldxp < a.n) return DMD_ERR_ARG;
+        if (!model->phi || !model->lam || !model->b || !model->sigma || !model->kind || !model->info)
+            return DMD_ERR_ARG;
+        if (model->n != a.n) return DMD_ERR_SHAPE;
+        const int64_t rp = dmd_phi_ld(o.r);
+        if (model->ldphi < rp || model->ldphi % 32 != 0 || model->ldphi > 16 * NN_MAX_CB) return DMD_ERR_ARG;
+        if (!aligned16(model->phi)) return DMD_ERR_ARG;
+    }
+    return DMD_OK;
+}
+
+// Carves (and, with base != nullptr, enqueues) the whole fit.
+int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
+{
+    const bool run = cv.base != nullptr;
+    const dmd_fit_opts& o = a.o;
+    const int r = o.r, mm = a.ncols;
+    const int64_t n = a.n;
+    const int fdt = a.xdtype;
+    const bool mixed = o.precision == DMD_FIT_MIXED;
+    const bool exact = o.precision == DMD_FIT_FP64_EXACT;
+    const int l = exact ? mm : r + o.p;
+    const bool shifted = a.shifted;
+    const int64_t ldphi = model ? model->ldphi : dmd_phi_ld(r);
+    const int64_t ldy = round_up(n, 4);
+    const double u = 1.1102230246251565e-16;
+
+    int32_t* flags = cv.take<int32_t>(16);
+    int32_t* info = model ? model->info : nullptr;
+    // partial buffer: largest TN product of the fit
+    const int wide = shifted ? mm + 1 : mm;
+    int64_t maxprod = (int64_t)std::max({(int64_t)l * wide, (int64_t)mm * l, (int64_t)l * l,
+                                         (int64_t)r * r, (int64_t)r, (int64_t)wide * wide});
+    double* P = cv.take<double>((size_t)TN_MAX_SPLITS * maxprod);
+    double* G = cv.take<double>((size_t)std::max(l, wide) * std::max(l, wide));
+    double* Rinv = cv.take<double>((size_t)l * l);
+    float* Rinv32 = cv.take<float>((size_t)l * l);
+    double* evals = cv.take<double>((size_t)std::max(l, mm));
+    double* Ueig = cv.take<double>((size_t)std::max(l, mm) * std::max(l, mm));
+    double* sigma = cv.take<double>((size_t)r);
+    double* Vs = cv.take<double>((size_t)mm * r);
+    double* T1 = cv.take<double>((size_t)std::max(l, mm) * r);
+    double* At = cv.take<double>((size_t)r * r);
+    double* W = cv.take<double>((size_t)r * r);
+    double* M = cv.take<double>((size_t)mm * r);
+    void* Mf = cv.take<char>((size_t)mm * ldphi * esize(fdt));
+    double* PhiG = cv.take<double>((size_t)r * r);
+    double* rhs = cv.take<double>((size_t)r);
+    double* RinvPhi = cv.take<double>((size_t)r * r);
+    void* eigws = cv.take<char>(eig_workspace_bytes(r));
+    double* Gxp2 = (exact && !shifted) ? cv.take<double>((size_t)mm * mm) : nullptr;
+    void* Y = nullptr;
+    double* Wt = nullptr;
+    void* Wtf = nullptr;
+    double* Bx = nullptr;
+    double* Bp = nullptr;
+    if (!exact) {
+        Y = cv.take<char>((size_t)ldy * l * esize(fdt));
+        Wt = cv.take<double>((size_t)mm * l);
+        Wtf = cv.take<char>((size_t)mm * l * esize(fdt));
+        if (shifted) {
+            Bx = cv.take<double>((size_t)l * (mm + 1));
+            Bp = Bx + l;
+        } else {
+            Bx = cv.take<double>((size_t)l * mm);
+            Bp = cv.take<double>((size_t)l * mm);
+        }
+    }
+    if (!run) return DMD_OK;
+
+    HIPCHK(fill_i32(st, info, DMD_INFO_WORDS, 0));
+    HIPCHK(fill_i32(st, flags, 16, 0));
+    if (o.flags & DMD_FIT_CHECK_FINITE) {
+        HIPCHK(check_finite(st, fdt, a.x, a.ldx, n, mm, info));
+        HIPCHK(check_finite(st, fdt, a.xp, a.ldxp, n, mm, info));
+    }
+    const void* Xp = a.xp;
+    const int64_t ldxp = a.ldxp;
+
+    if (!exact) {
+        const int cdt = mixed ? DMD_F32 : DMD_F64;   // MFMA type of the streaming products
+        // CholeskyQR2 of an N x l (or mm x l) matrix in place, with a shifted first pass
+        // on breakdown and then a conditional third pass (shifted CholeskyQR3).
+        auto cholqr = [&](void* Yb, int64_t ld, int64_t rows, int dtype, int32_t* flag) -> int32_t {
+            HIPCHK(fill_i32(st, flag, 1, 0));
+            const double shift_scale = 11.0 * ((double)rows * l + (double)l * (l + 1)) * u;
+            for (int pass = 0; pass < 3; ++pass) {
+                const int32_t* skip = pass == 2 ? flag : nullptr;
+                HIPCHK(gemm_tn(st, dtype, DMD_F64, Yb, ld, 0, l, Yb, ld, 0, l, 1, rows, P, G, l, nullptr, 0, skip));
+                HIPCHK(chol_inv(st, G, l, l, Rinv, l, dtype == DMD_F32 ? Rinv32 : nullptr, l,
+                                pass == 0 ? shift_scale : 0.0, pass == 0 ? flag : nullptr, info, skip));
+                HIPCHK(gemm_nn(st, dtype, Yb, ld, dtype == DMD_F32 ? (const void*)Rinv32 : (const void*)Rinv, l,
+                               Yb, ld, 0, rows, l, l, skip));
+            }
+            return DMD_OK;
+        };
+        // sketch Y = X Omega (Sec. 4.3)
+        HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, o.omega, mm, Y, ldy, 0, n, mm, l, nullptr));
+        if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 0)) return e;
+        // power iterations: W = orth(X^T Q), Y = X W, Q = orth(Y)
+        for (int it = 0; it < o.q; ++it) {
+            HIPCHK(gemm_tn(st, fdt, cdt, a.x, a.ldx, 0, mm, Y, ldy, 0, l, 0, n, P, Wt, mm, nullptr, 0, nullptr));
+            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 1)) return e;
+            if (fdt == DMD_F32) HIPCHK(to_f32(st, mm, l, l, Wt, mm, (float*)Wtf, mm));
+            else HIPCHK(copy_f64(st, mm, l, l, Wt, mm, (double*)Wtf, mm));
+            HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, Wtf, mm, Y, ldy, 0, n, mm, l, nullptr));
+            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 2)) return e;
+        }
+        // projection B = Q^T X, B' = Q^T X' (one pass over Z when X' is the shifted view)
+        if (shifted) {
+            HIPCHK(gemm_tn(st, fdt, cdt, Y, ldy, 0, l, a.x, a.ldx, 0, mm + 1, 0, n, P, Bx, l, nullptr, 0, nullptr));
+        } else {
+            HIPCHK(gemm_tn(st, fdt, cdt, Y, ldy, 0, l, a.x, a.ldx, 0, mm, 0, n, P, Bx, l, nullptr, 0, nullptr));
+            HIPCHK(gemm_tn(st, fdt, cdt, Y, ldy, 0, l, Xp, ldxp, 0, mm, 0, n, P, Bp, l, nullptr, 0, nullptr));
+        }
+        // SVD of B through the Jacobi eigen-decomposition of B B^T
+        HIPCHK(small_gemm(st, 0, 1, l, l, mm, 1.0, Bx, l, Bx, l, 0.0, G, l));
+        HIPCHK(sym_eig(st, G, l, l, evals, Ueig, info));
+        HIPCHK(sigma_from_evals(st, evals, r, o.rank_tol, sigma, model->sigma, info));
+        // Vs = V_r S_r^-1 = B^T U_r S_r^-2
+        HIPCHK(small_gemm(st, 1, 0, mm, r, l, 1.0, Bx, l, Ueig, l, 0.0, Vs, mm));
+        HIPCHK(scale_cols(st, mm, r, Vs, mm, sigma, 1));
+        HIPCHK(scale_cols(st, mm, r, Vs, mm, sigma, 1));
+        // Atilde = U_r^T B' V_r S_r^-1
+        HIPCHK(small_gemm(st, 0, 0, l, r, mm, 1.0, Bp, l, Vs, mm, 0.0, T1, l));
+        HIPCHK(small_gemm(st, 1, 0, r, r, l, 1.0, Ueig, l, T1, l, 0.0, At, r));
+    } else {
+        // method of snapshots: Gram of [X X'] in FP64
+        double* Gxx;
+        double* Gxp;
+        int64_t ldg;
+        if (shifted) {
+            HIPCHK(gemm_tn(st, DMD_F64, DMD_F64, a.x, a.ldx, 0, mm + 1, a.x, a.ldx, 0, mm + 1, 1, n, P, G, mm + 1,
+                           nullptr, 0, nullptr));
+            Gxx = G;
+            Gxp = G + (mm + 1);
+            ldg = mm + 1;
+        } else {
+            HIPCHK(gemm_tn(st, DMD_F64, DMD_F64, a.x, a.ldx, 0, mm, a.x, a.ldx, 0, mm, 1, n, P, G, mm, nullptr, 0, nullptr));
+            HIPCHK(gemm_tn(st, DMD_F64, DMD_F64, a.x, a.ldx, 0, mm, Xp, ldxp, 0, mm, 0, n, P, Gxp2, mm, nullptr, 0, nullptr));
+            Gxx = G;
+            Gxp = Gxp2;
+            ldg = mm;
+        }
+        HIPCHK(sym_eig(st, Gxx, ldg, mm, evals, Ueig, info));
+        HIPCHK(sigma_from_evals(st, evals, r, o.rank_tol, sigma, model->sigma, info));
+        HIPCHK(copy_f64(st, mm, r, r, Ueig, mm, Vs, mm));
+        HIPCHK(scale_cols(st, mm, r, Vs, mm, sigma, 1));
+        // Atilde = S^-1 V_r^T (X^T X') V_r S^-1
+        double* T2 = M;   // scratch (mm x r), overwritten below
+        HIPCHK(small_gemm(st, 0, 0, mm, r, mm, 1.0, Gxp, ldg, Vs, mm, 0.0, T2, mm));
+        HIPCHK(small_gemm(st, 1, 0, r, r, mm, 1.0, Vs, mm, T2, mm, 0.0, At, r));
+    }
+    // eigen-decomposition, canonical order, folded eigenvectors
+    HIPCHK(nonsym_eig(st, At, r, r, eigws, model->lam, model->kind, W, info));
+    // exact modes Phi = X' V_r S_r^-1 W
+    HIPCHK(small_gemm(st, 0, 0, mm, r, r, 1.0, Vs, mm, W, r, 0.0, M, mm));
+    if (fdt == DMD_F32) HIPCHK(to_f32(st, mm, r, (int)ldphi, M, mm, (float*)Mf, mm));
+    else HIPCHK(copy_f64(st, mm, r, (int)ldphi, M, mm, (double*)Mf, mm));
+    HIPCHK(gemm_nn(st, fdt, Xp, ldxp, Mf, mm, model->phi, ldphi, 1, n, mm, (int)ldphi, nullptr));
+    // amplitudes b = Phi^+ x0 from the FP64 Gram of Phi
+    HIPCHK(gemm_tn(st, fdt, DMD_F64, model->phi, ldphi, 1, r, model->phi, ldphi, 1, r, 1, n, P, PhiG, r, nullptr, 0, nullptr));
+    HIPCHK(gemm_tn(st, fdt, DMD_F64, model->phi, ldphi, 1, r, a.x, a.ldx, 0, 1, 0, n, P, rhs, r, nullptr, 0, nullptr));
+    HIPCHK(chol_inv(st, PhiG, r, r, RinvPhi, r, nullptr, 0, 11.0 * ((double)n * r + (double)r * (r + 1)) * u,
+                    flags + 3, info, nullptr));
+    HIPCHK(amplitudes(st, r, RinvPhi, r, rhs, model->kind, model->b));
+    return DMD_OK;
+}
+
+// ---------------------------------------------------------------- reconstruction plan
+struct ReconPlan {
+    int64_t* kdev;
+    double* expo;
+    void* chi;
+    void* clo;
+};
+
+size_t c_elem(int mode) { return mode == DMD_RECON_FP64 ? 8 : (mode == DMD_RECON_FP32 ? 4 : 2); }
+
+ReconPlan recon_carve(Carver& cv, int r, int K, int mode)
+{
+    ReconPlan p;
+    const int rp = (int)dmd_phi_ld(r);
+    const int Kp = (int)round_up(K, RECON_KPAD);
+    p.kdev = cv.take<int64_t>((size_t)K);
+    p.expo = cv.take<double>((size_t)K);
+    p.chi = cv.take<char>((size_t)Kp * rp * c_elem(mode));
+    p.clo = mode == DMD_RECON_BF16X3 ? cv.take<char>((size_t)Kp * rp * 2) : nullptr;
+    return p;
+}
+
+int32_t validate_model(const dmd_model* m)
+{
+    if (!m || !m->phi || !m->lam || !m->b || !m->kind) return DMD_ERR_ARG;
+    if (m->n < 1 || m->r < 1) return DMD_ERR_SHAPE;
+    if (m->r > RECON_MAX_RP) return DMD_ERR_UNSUPPORTED;
+    if (m->dtype != DMD_F32 && m->dtype != DMD_F64) return DMD_ERR_ARG;
+    if (m->ldphi < dmd_phi_ld(m->r) || m->ldphi % 32 != 0) return DMD_ERR_ARG;
+    if (!aligned16(m->phi)) return DMD_ERR_ARG;
+    return DMD_OK;
+}
+
+// ---------------------------------------------------------------- autotuner table
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;
+
+std::tuple<int, int, int, int> tune_key(int mode, int rp, int64_t N, int K)
+{
+    int ln = 0, lk = 0;
+    while ((int64_t(1) << (ln + 1)) <= N) ++ln;
+    while ((1 << (lk + 1)) <= K) ++lk;
+    return std::make_tuple(mode, rp, ln, lk);
+}
+
+int tune_lookup(int mode, int rp, int64_t N, int K)
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(tune_key(mode, rp, N, K));
+    return it == g_tune.end() ? 0 : it->second;
+}
+
+int32_t load_cache(const char* path)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return DMD_ERR_ARG;
+    char line[256];
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    while (fgets(line, sizeof line, f)) {
+        int mode, rp, ln, lk, cfg;
+        double us;
+        if (line[0] == '#') continue;
+        if (sscanf(line, "%d %d %d %d %d %lf", &mode, &rp, &ln, &lk, &cfg, &us) == 6 && cfg >= 0 && cfg < RECON_NCFG)
+            g_tune[std::make_tuple(mode, rp, ln, lk)] = cfg;
+    }
+    fclose(f);
+    return DMD_OK;
+}
+
+void lib_init()
+{
+    (void)device_cu_count();
+    (void)prepare_kernels();
+    const char* c = getenv("DMDMI_AUTOTUNE_CACHE");
+    if (c && *c) load_cache(c);
+}
+
+int32_t recon_enqueue(hipStream_t st, const dmd_model* m, const int64_t* k_host, const double* t_host,
+                      int K, int mode, void* U, int64_t ldu, void* ws, size_t ws_bytes, int cfg_override)
+{
+    if (int32_t e = validate_model(m)) return e;
+    if (K < 1) return DMD_ERR_SHAPE;
+    if (mode < DMD_RECON_FP64 || mode > DMD_RECON_BF16X3) return DMD_ERR_ARG;
+    if ((mode == DMD_RECON_FP64) != (m->dtype == DMD_F64)) return DMD_ERR_ARG;
+    if (!U || ldu < m->n) return DMD_ERR_ARG;
+    if (!k_host && !t_host) return DMD_ERR_ARG;
+    Carver dry(nullptr);
+    recon_carve(dry, m->r, K, mode);
+    if (!ws || ws_bytes < dry.bytes()) return DMD_ERR_WORKSPACE;
+    std::call_once(g_init_once, lib_init);
+    Carver cv(ws);
+    ReconPlan p = recon_carve(cv, m->r, K, mode);
+    const int rp = (int)dmd_phi_ld(m->r);
+    const int Kp = (int)round_up(K, RECON_KPAD);
+    if (k_host) {
+        HIPCHK(hipMemcpyAsync(p.kdev, k_host, (size_t)K * sizeof(int64_t), hipMemcpyHostToDevice, st));
+        HIPCHK(exponents(st, p.kdev, nullptr, 1.0, K, p.expo));
+    } else {
+        HIPCHK(hipMemcpyAsync(p.expo, t_host, (size_t)K * sizeof(double), hipMemcpyHostToDevice, st));
+        HIPCHK(exponents(st, nullptr, p.expo, 1.0 / m->dt, K, p.expo));
+    }
+    HIPCHK(powers_pack(st, m->lam, m->b, m->kind, m->r, p.expo, K, Kp, rp, mode, p.chi, p.clo));
+    ReconArgs ra{};
+    ra.mode = mode;
+    ra.phi = m->phi; ra.ldphi = m->ldphi; ra.N = m->n; ra.rp = rp;
+    ra.c_hi = p.chi; ra.c_lo = p.clo; ra.K = K;
+    ra.U = U; ra.ldu = ldu;
+    const int vw = mode == DMD_RECON_FP64 ? 2 : 4;
+    ra.vec_store = (ldu % vw == 0) && aligned16(U);
+    const int cfg = cfg_override >= 0 ? cfg_override : tune_lookup(mode, rp, m->n, K);
+    HIPCHK(recon_launch(st, ra, cfg));
+    return DMD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== extern "C"
+extern "C" {
+
+int32_t dmd_abi_version(void) { return DMDMI_ABI_VERSION; }
+
+const char* dmd_status_string(int32_t s)
+{
+    switch (s) {
+    case DMD_OK: return "ok";
+    case DMD_ERR_ARG: return "invalid argument (null pointer, enum, alignment or leading dimension)";
+    case DMD_ERR_SHAPE: return "inconsistent or unsupported shape";
+    case DMD_ERR_WORKSPACE: return "workspace too small";
+    case DMD_ERR_NONFINITE: return "non-finite value in the input";
+    case DMD_ERR_CHOL_BREAKDOWN: return "CholeskyQR breakdown (sketch numerically rank deficient)";
+    case DMD_ERR_RANK: return "sigma_r below the rank tolerance";
+    case DMD_ERR_EIG_NOCONV: return "eigen-solver did not converge";
+    case DMD_ERR_DOMAIN: return "lambda = 0 raised to a negative or fractional power";
+    case DMD_ERR_OVERFLOW: return "result outside the output type's range";
+    case DMD_ERR_HIP: return "HIP runtime error";
+    case DMD_ERR_UNSUPPORTED: return "size beyond the small-matrix kernels' limits";
+    default: return "unknown status";
+    }
+}
+
+int64_t dmd_phi_ld(int32_t r) { return round_up(std::max(r, 1), 32); }
+
+int32_t dmd_fit_workspace_size(int64_t n, int32_t ncols, int32_t xdtype, const dmd_fit_opts* opts, size_t* bytes)
+{
+    if (!opts || !bytes) return DMD_ERR_ARG;
+    FitArgs a{nullptr, nullptr, n, ncols, n, n, xdtype, *opts, false};
+    if (int32_t e = validate_fit(a, nullptr, false)) return e;
+    // size for the larger of the two projection layouts
+    Carver c1(nullptr);
+    fit_plan(c1, nullptr, a, nullptr);
+    a.shifted = true;
+    Carver c2(nullptr);
+    fit_plan(c2, nullptr, a, nullptr);
+    *bytes = std::max(c1.bytes(), c2.bytes());
+    return DMD_OK;
+}
+
+int32_t dmd_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t ncols, int64_t ldx,
+                int64_t ldxp, int32_t xdtype, const dmd_fit_opts* opts, void* ws, size_t ws_bytes,
+                dmd_model* model)
+{
+    if (!opts) return DMD_ERR_ARG;
+    FitArgs a{x, xp, n, ncols, ldx, ldxp, xdtype, *opts, is_shifted_view(x, xp, ldx, ldxp, xdtype)};
+    if (int32_t e = validate_fit(a, model, true)) return e;
+    size_t need = 0;
+    if (int32_t e = dmd_fit_workspace_size(n, ncols, xdtype, opts, &need)) return e;
+    if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    std::call_once(g_init_once, lib_init);
+    hipStream_t st = (hipStream_t)stream;
+    model->r = opts->r;
+    model->dtype = xdtype;
+    model->dt = opts->dt;
+    Carver cv(ws);
+    if (int32_t e = fit_plan(cv, st, a, model)) return e;
+    if (opts->flags & DMD_FIT_ASYNC) return DMD_OK;
+    int32_t status = 0;
+    HIPCHK(hipMemcpyAsync(&status, model->info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return status;
+}
+
+int32_t dmd_reconstruct_workspace_size(int32_t r, int32_t K, int32_t mode, size_t* bytes)
+{
+    if (!bytes) return DMD_ERR_ARG;
+    if (r < 1 || K < 1) return DMD_ERR_SHAPE;
+    if (mode < DMD_RECON_FP64 || mode > DMD_RECON_BF16X3) return DMD_ERR_ARG;
+    Carver c(nullptr);
+    recon_carve(c, r, K, mode);
+    *bytes = c.bytes();
+    return DMD_OK;
+}
+
+int32_t dmd_reconstruct(void* stream, const dmd_model* model, const int64_t* k_host, int32_t K, int32_t mode,
+                        void* U, int64_t ldu, void* ws, size_t ws_bytes)
+{
+    if (!k_host) return DMD_ERR_ARG;
+    return recon_enqueue((hipStream_t)stream, model, k_host, nullptr, K, mode, U, ldu, ws, ws_bytes, -1);
+}
+
+int32_t dmd_integrate(void* stream, const dmd_model* model, const double* t_host, int32_t T, int32_t mode,
+                      void* U, int64_t ldu, void* ws, size_t ws_bytes)
+{
+    if (!t_host) return DMD_ERR_ARG;
+    if (model && !(model->dt > 0.0)) return DMD_ERR_ARG;
+    for (int32_t j = 0; t_host && j < T; ++j)
+        if (!isfinite(t_host[j])) return DMD_ERR_ARG;
+    return recon_enqueue((hipStream_t)stream, model, nullptr, t_host, T, mode, U, ldu, ws, ws_bytes, -1);
+}
+
+int32_t dmd_project_workspace_size(int64_t n, int32_t r, size_t* bytes)
+{
+    if (!bytes) return DMD_ERR_ARG;
+    if (n < 1 || r < 1) return DMD_ERR_SHAPE;
+    Carver c(nullptr);
+    c.take<double>((size_t)TN_MAX_SPLITS * r * r);
+    c.take<double>((size_t)r * r);
+    c.take<double>((size_t)r);
+    c.take<double>((size_t)r * r);
+    c.take<int32_t>(16);
+    *bytes = c.bytes();
+    return DMD_OK;
+}
+
+int32_t dmd_project(void* stream, const dmd_model* model, const void* u, double* z, void* ws, size_t ws_bytes)
+{
+    if (int32_t e = validate_model(model)) return e;
+    if (!u || !z) return DMD_ERR_ARG;
+    size_t need = 0;
+    dmd_project_workspace_size(model->n, model->r, &need);
+    if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    std::call_once(g_init_once, lib_init);
+    hipStream_t st = (hipStream_t)stream;
+    const int r = model->r;
+    const int64_t n = model->n;
+    Carver cv(ws);
+    double* P = cv.take<double>((size_t)TN_MAX_SPLITS * r * r);
+    double* PhiG = cv.take<double>((size_t)r * r);
+    double* rhs = cv.take<double>((size_t)r);
+    double* Rinv = cv.take<double>((size_t)r * r);
+    int32_t* scratch = cv.take<int32_t>(16);
+    HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, model->phi, model->ldphi, 1, r, 1, n,
+                   P, PhiG, r, nullptr, 0, nullptr));
+    HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, u, n, 0, 1, 0, n, P, rhs, r, nullptr,
+                   0, nullptr));
+    HIPCHK(fill_i32(st, scratch, 16, 0));
+    HIPCHK(chol_inv(st, PhiG, r, r, Rinv, r, nullptr, 0, 0.0, nullptr, scratch, nullptr));
+    HIPCHK(amplitudes(st, r, Rinv, r, rhs, model->kind, z));
+    return DMD_OK;
+}
+
+int32_t dmd_loss_grad_workspace_size(int64_t n, int32_t r, int32_t ncols, int32_t dtype, size_t* bytes)
+{
+    if (!bytes) return DMD_ERR_ARG;
+    if (n < 1 || r < 1 || ncols < 1) return DMD_ERR_SHAPE;
+    if (dtype != DMD_F32 && dtype != DMD_F64) return DMD_ERR_ARG;
+    const int mode = dtype == DMD_F64 ? DMD_RECON_FP64 : DMD_RECON_FP32;
+    Carver c(nullptr);
+    recon_carve(c, r, ncols, mode);
+    c.take<char>((size_t)round_up(n, 4) * ncols * esize(dtype));
+    c.take<double>(4096);
+    c.take<double>((size_t)TN_MAX_SPLITS * r * ncols);
+    c.take<double>((size_t)r * ncols);
+    *bytes = c.bytes();
+    return DMD_OK;
+}
+
+int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam, const double* b, const void* xt,
+                      int64_t ldxt, const int64_t* k_host, int32_t ncols, double* out, void* ws, size_t ws_bytes)
+{
+    if (int32_t e = validate_model(model)) return e;
+    if (!lam || !b || !xt || !k_host || !out) return DMD_ERR_ARG;
+    if (ncols < 1) return DMD_ERR_SHAPE;
+    if (ldxt < model->n) return DMD_ERR_ARG;
+    if ((int64_t)model->r * ncols > TN_MAX_OUT) return DMD_ERR_UNSUPPORTED;
+    size_t need = 0;
+    dmd_loss_grad_workspace_size(model->n, model->r, ncols, model->dtype, &need);
+    if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    std::call_once(g_init_once, lib_init);
+    hipStream_t st = (hipStream_t)stream;
+    const int r = model->r, rp = (int)dmd_phi_ld(r);
+    const int64_t n = model->n, ldr = round_up(n, 4);
+    const int mode = model->dtype == DMD_F64 ? DMD_RECON_FP64 : DMD_RECON_FP32;
+    Carver cv(ws);
+    ReconPlan p = recon_carve(cv, r, ncols, mode);
+    void* R = cv.take<char>((size_t)ldr * ncols * esize(model->dtype));
+    double* ss = cv.take<double>(4096);
+    double* P = cv.take<double>((size_t)TN_MAX_SPLITS * r * ncols);
+    double* G = cv.take<double>((size_t)r * ncols);
+    HIPCHK(hipMemcpyAsync(p.kdev, k_host, (size_t)ncols * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(exponents(st, p.kdev, nullptr, 1.0, ncols, p.expo));
+    HIPCHK(powers_pack(st, lam, b, model->kind, r, p.expo, ncols, (int)round_up(ncols, RECON_KPAD), rp, mode, p.chi, nullptr));
+    int grid = 0;
+    ReconArgs ra{};
+    ra.mode = mode;
+    ra.phi = model->phi; ra.ldphi = model->ldphi; ra.N = n; ra.rp = rp;
+    ra.c_hi = p.chi; ra.c_lo = nullptr; ra.K = ncols;
+    ra.U = R; ra.ldu = ldr; ra.vec_store = 1;
+    ra.xt = xt; ra.ldxt = ldxt; ra.ss_partial = ss; ra.grid_out = &grid;
+    HIPCHK(recon_launch(st, ra, 0));
+    if (grid > 4096) return DMD_ERR_UNSUPPORTED;
+    HIPCHK(gemm_tn(st, model->dtype, model->dtype, model->phi, model->ldphi, 1, r, R, ldr, 0, ncols, 0, n, P, G, r,
+                   nullptr, 0, nullptr));
+    HIPCHK(grad_reduce(st, r, ncols, G, lam, b, model->kind, p.expo, ss, grid, out));
+    return DMD_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batched fit + graphs
+struct dmd_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+};
+
+extern "C" {
+
+int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes, dmd_model* models, int32_t capture,
+                        dmd_graph** graph)
+{
+    if (nscenes < 1 || !scenes || !models) return DMD_ERR_ARG;
+    if (capture && !graph) return DMD_ERR_ARG;
+    for (int i = 0; i < nscenes; ++i) {
+        const dmd_scene& sc = scenes[i];
+        FitArgs a{sc.x, sc.xp, sc.n, sc.ncols, sc.ldx, sc.ldxp, sc.xdtype, sc.opts,
+                  is_shifted_view(sc.x, sc.xp, sc.ldx, sc.ldxp, sc.xdtype)};
+        if (int32_t e = validate_fit(a, &models[i], true)) return e;
+        size_t need = 0;
+        if (int32_t e = dmd_fit_workspace_size(sc.n, sc.ncols, sc.xdtype, &sc.opts, &need)) return e;
+        if (!sc.ws || sc.ws_bytes < need) return DMD_ERR_WORKSPACE;
+    }
+    std::call_once(g_init_once, lib_init);
+    hipStream_t origin = (hipStream_t)stream;
+    dmd_graph* g = new dmd_graph();
+    auto cleanup = [&](int32_t code) {
+        for (auto e : g->events) hipEventDestroy(e);
+        for (auto s : g->streams) hipStreamDestroy(s);
+        if (g->exec) hipGraphExecDestroy(g->exec);
+        if (g->graph) hipGraphDestroy(g->graph);
+        delete g;
+        return code;
+    };
+    g->events.resize(nscenes + 1, nullptr);
+    g->streams.resize(nscenes, nullptr);
+    for (int i = 0; i <= nscenes; ++i)
+        if (hipEventCreateWithFlags(&g->events[i], hipEventDisableTiming) != hipSuccess) return cleanup(DMD_ERR_HIP);
+    for (int i = 0; i < nscenes; ++i)
+        if (hipStreamCreateWithFlags(&g->streams[i], hipStreamNonBlocking) != hipSuccess) return cleanup(DMD_ERR_HIP);
+    if (capture && hipStreamBeginCapture(origin, hipStreamCaptureModeGlobal) != hipSuccess) return cleanup(DMD_ERR_HIP);
+    int32_t status = DMD_OK;
+    if (hipEventRecord(g->events[nscenes], origin) != hipSuccess) status = DMD_ERR_HIP;
+    for (int i = 0; i < nscenes && status == DMD_OK; ++i) {
+        const dmd_scene& sc = scenes[i];
+        FitArgs a{sc.x, sc.xp, sc.n, sc.ncols, sc.ldx, sc.ldxp, sc.xdtype, sc.opts,
+                  is_shifted_view(sc.x, sc.xp, sc.ldx, sc.ldxp, sc.xdtype)};
+        a.o.flags |= DMD_FIT_ASYNC;
+        models[i].r = sc.opts.r;
+        models[i].dtype = sc.xdtype;
+        models[i].dt = sc.opts.dt;
+        if (hipStreamWaitEvent(g->streams[i], g->events[nscenes], 0) != hipSuccess) { status = DMD_ERR_HIP; break; }
+        Carver cv(sc.ws);
+        status = fit_plan(cv, g->streams[i], a, &models[i]);
+        if (status != DMD_OK) break;
+        if (hipEventRecord(g->events[i], g->streams[i]) != hipSuccess) { status = DMD_ERR_HIP; break; }
+        if (hipStreamWaitEvent(origin, g->events[i], 0) != hipSuccess) { status = DMD_ERR_HIP; break; }
+    }
+    if (capture) {
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(origin, &gr);
+        g->graph = gr;
+        if (status != DMD_OK) return cleanup(status);
+        if (e != hipSuccess || !gr) return cleanup(DMD_ERR_HIP);
+        if (hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess) return cleanup(DMD_ERR_HIP);
+        *graph = g;
+        return DMD_OK;
+    }
+    if (status != DMD_OK) { hipStreamSynchronize(origin); return cleanup(status); }
+    if (hipStreamSynchronize(origin) != hipSuccess) return cleanup(DMD_ERR_HIP);
+    return cleanup(DMD_OK);
+}
+
+int32_t dmd_graph_launch(dmd_graph* graph, void* stream)
+{
+    if (!graph || !graph->exec) return DMD_ERR_ARG;
+    HIPCHK(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return DMD_OK;
+}
+
+int32_t dmd_graph_destroy(dmd_graph* graph)
+{
+    if (!graph) return DMD_ERR_ARG;
+    if (graph->exec) hipGraphExecDestroy(graph->exec);
+    if (graph->graph) hipGraphDestroy(graph->graph);
+    for (auto e : graph->events) hipEventDestroy(e);
+    for (auto s : graph->streams) hipStreamDestroy(s);
+    delete graph;
+    return DMD_OK;
+}
+
+int32_t dmd_autotune_reconstruct(void* stream, const dmd_model* model, int32_t K, int32_t mode, void* U, int64_t ldu,
+                                 void* ws, size_t ws_bytes, const char* cache_path, int32_t* best_cfg)
+{
+    if (int32_t e = validate_model(model)) return e;
+    if (K < 1) return DMD_ERR_SHAPE;
+    std::vector<int64_t> ks((size_t)K);
+    for (int j = 0; j < K; ++j) ks[j] = j;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return DMD_ERR_HIP; }
+    int best = 0;
+    float best_ms = 1e30f;
+    int32_t status = DMD_OK;
+    for (int cfg = 0; cfg < RECON_NCFG && status == DMD_OK; ++cfg) {
+        status = recon_enqueue(st, model, ks.data(), nullptr, K, mode, U, ldu, ws, ws_bytes, cfg);   // warm-up
+        if (status) break;
+        hipEventRecord(e0, st);
+        for (int rep = 0; rep < 3 && status == DMD_OK; ++rep)
+            status = recon_enqueue(st, model, ks.data(), nullptr, K, mode, U, ldu, ws, ws_bytes, cfg);
+        hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) { status = DMD_ERR_HIP; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_ms) { best_ms = ms; best = cfg; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (status != DMD_OK) return status;
+    const int rp = (int)dmd_phi_ld(model->r);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune[tune_key(mode, rp, model->n, K)] = best;
+    }
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            auto k = tune_key(mode, rp, model->n, K);
+            fprintf(f, "%d %d %d %d %d %.3f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), best,
+                    best_ms / 3.0f * 1000.0f);
+            fclose(f);
+        }
+    }
+    if (best_cfg) *best_cfg = best;
+    return DMD_OK;
+}
+
+int32_t dmd_autotune_load(const char* cache_path)
+{
+    if (!cache_path) return DMD_ERR_ARG;
+    return load_cache(cache_path);
+}
+
+}  // extern "C"

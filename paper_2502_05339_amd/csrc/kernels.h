@@ -1,0 +1,100 @@
+// Internal launchers of the gfx950 kernels (host-callable, enqueue only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dmdmi.h"
+
+namespace dmd {
+
+constexpr int NN_MAX_CB = 12;          // gemm_nn: n <= 192 output columns
+constexpr int TN_MAX_SPLITS = 256;     // gemm_tn: row splits (FP64 partials)
+constexpr int64_t TN_MAX_OUT = 320 * 320;
+constexpr int RECON_MAX_RP = 160;      // padded rank held in registers by the reconstruction
+constexpr int RECON_KPAD = 64;         // frame padding of the coefficient matrix
+constexpr int SMALL_MAX = DMD_MAX_SMALL;
+constexpr int EIG_MAX = DMD_MAX_RANK;
+
+__global__ void fill_f64_kernel(double* p, int64_t n, double v);
+__global__ void fill_f32_kernel(float* p, int64_t n, float v);
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v);
+
+int device_cu_count();
+hipError_t fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v);
+// One-time per-kernel attributes (LDS above 64 KiB); called before any capture.
+hipError_t prepare_kernels();
+hipError_t gemm_prepare();
+hipError_t small_prepare();
+hipError_t eig_prepare();
+
+// ---- tall-skinny GEMMs (gemm.hip)
+hipError_t gemm_nn(hipStream_t s, int dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
+                   void* C, int64_t ldc, int c_rowmajor, int64_t N, int K, int n,
+                   const int32_t* skip_unless);
+hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A, int64_t lda,
+                   int a_rowmajor, int ka, const void* B, int64_t ldb, int b_rowmajor, int nb,
+                   int sym, int64_t N, double* P, double* out, int64_t ldo, float* out32,
+                   int64_t ldo32, const int32_t* skip_unless);
+size_t gemm_tn_partial_bytes(int64_t N, int ka, int nb);
+
+// ---- reconstruction (recon.hip)
+struct ReconArgs {
+    int mode;
+    const void* phi; int64_t ldphi; int64_t N; int rp;
+    const void* c_hi; const void* c_lo; int K;
+    void* U; int64_t ldu; int vec_store;
+    const void* xt; int64_t ldxt; double* ss_partial;   // residual epilogue (adjoint)
+    int* grid_out;
+};
+constexpr int RECON_NCFG = 3;
+hipError_t recon_launch(hipStream_t s, const ReconArgs& ra, int cfg);
+hipError_t powers_pack(hipStream_t s, const double* lam, const double* b, const int32_t* kind, int r,
+                       const double* expo, int K, int Kp, int rp, int mode, void* hi, void* lo);
+hipError_t exponents(hipStream_t s, const int64_t* k, const double* t, double inv_dt, int K, double* e);
+
+// ---- small FP64 matrices (small.hip)
+// Cholesky G = R^T R of an n x n SPD matrix and R^-1 (upper).  On breakdown retry
+// once with a diagonal shift (flagging *shifted = 1); a second failure writes
+// DMD_ERR_CHOL_BREAKDOWN to info[0] and an identity R^-1.
+hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* Rinv, int64_t ldr,
+                    float* Rinv32, int64_t ldr32, double shift_scale, int32_t* shifted,
+                    int32_t* info, const int32_t* skip_unless);
+// Jacobi eigen-decomposition of a symmetric n x n matrix: eigenvalues descending,
+// eigenvectors in the columns of Vout (n x n, ld n).
+hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* evals, double* Vout,
+                   int32_t* info);
+// C = alpha op(A) op(B) + beta C, all FP64 column-major, small sizes.
+hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
+                      const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                      double* C, int64_t ldc);
+// Scale column j of A (m x n) by d[j] (or 1/d[j] with inv): A(:, j) *= f(d[j]).
+hipError_t scale_cols(hipStream_t s, int m, int n, double* A, int64_t lda, const double* d, int mode);
+// sigma = sqrt(max(evals, 0))[0..r), rank check against rank_tol.
+hipError_t sigma_from_evals(hipStream_t s, const double* evals, int r, double rank_tol, double* sigma,
+                            double* sigma_out, int32_t* info);
+// Copy a double matrix into float (m x n), zero-filling columns n..n_pad-1.
+hipError_t to_f32(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, float* B,
+                  int64_t ldb);
+hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, double* B,
+                    int64_t ldb);
+// Least-squares amplitudes from the Gram of the folded modes: beta = G^-1 rhs via
+// Rinv, then complex b for each (real | pair) mode.
+hipError_t amplitudes(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs,
+                      const int32_t* kind, double* b);
+hipError_t check_finite(hipStream_t s, int dtype, const void* X, int64_t ld, int64_t N, int ncols,
+                        int32_t* info);
+
+// ---- nonsymmetric eigen-decomposition (eig.hip)
+size_t eig_workspace_bytes(int n);
+// lam (2n doubles), kind (n), W (n x n folded real eigenvectors, ld n) sorted in
+// the canonical order; M = Vs W (m x n) where Vs = V_r S_r^-1 (m x n, ld ldv).
+hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* ws, double* lam,
+                      int32_t* kind, double* W, int32_t* info);
+
+// ---- adjoint (adjoint.hip)
+hipError_t grad_reduce(hipStream_t s, int r, int ncols, const double* G, const double* lam,
+                       const double* b, const int32_t* kind, const double* expo,
+                       const double* ss_partial, int nss, double* out);
+
+}  // namespace dmd

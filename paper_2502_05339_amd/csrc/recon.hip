@@ -1,0 +1,393 @@
+// Batched evaluation of the fitted model on MFMA (gfx950).
+//
+//  powers_pack : the coefficient matrix C (frame-major, [Kp][rp]) of
+//                U = Re(Phi diag(lambda^e) b) in the folded real mode basis, with
+//                lambda^e evaluated in FP64 as exp(e Log lambda)
+//                (Sec. 4.4, eq. large_time_step; Sec. 6.1, eq. edit_temporal).
+//  recon       : U (N x K, column-major) = Phi (N x rp, row-major) * C^T, as one
+//                persistent GEMM over (row tile, frame chunk) work items.  The
+//                row tile of Phi stays in registers while the frames stream
+//                through LDS-staged chunks of C; every output element is written
+//                exactly once with non-temporal 16-byte stores.
+//                With RESID the epilogue forms R = Xt - U instead, and the FP64
+//                sum of squares of R (the adjoint's loss) per work-group.
+#include "common.h"
+#include "kernels.h"
+
+namespace dmd {
+
+// ---------------------------------------------------------------- coefficients
+// Folded basis: kind 0 -> C = Re(b lambda^e); a pair (i, i+1) with members
+// c1 = b_i lambda_i^e and c2 = b_{i+1} lambda_{i+1}^e has
+//   C_i = Re c1 + Re c2,   C_{i+1} = Im c2 - Im c1
+// because Re(phi c1 + conj(phi) c2) = Re(phi)(Re c1 + Re c2) + Im(phi)(Im c2 - Im c1).
+__device__ __forceinline__ double folded_coeff(const double* lam, const double* b,
+                                               const int32_t* kind, int r, int i, double e)
+{
+    int kd = kind[i];
+    if ((kd == 1 && i + 1 >= r) || (kd == 2 && i == 0) || kd < 0 || kd > 2) kd = 0;   // malformed pair marker
+    if (kd == 0) {
+        cplx c = cmul({b[2 * i], b[2 * i + 1]}, cpow_real({lam[2 * i], lam[2 * i + 1]}, e));
+        return c.re;
+    }
+    const int i1 = (kd == 1) ? i : i - 1;
+    const int i2 = i1 + 1;
+    cplx c1 = cmul({b[2 * i1], b[2 * i1 + 1]}, cpow_real({lam[2 * i1], lam[2 * i1 + 1]}, e));
+    cplx c2 = cmul({b[2 * i2], b[2 * i2 + 1]}, cpow_real({lam[2 * i2], lam[2 * i2 + 1]}, e));
+    return (kd == 1) ? (c1.re + c2.re) : (c2.im - c1.im);
+}
+
+__global__ void powers_pack_kernel(const double* __restrict__ lam, const double* __restrict__ b,
+                                   const int32_t* __restrict__ kind, int r,
+                                   const double* __restrict__ expo, int K, int Kp, int rp,
+                                   int mode, void* out_hi, void* out_lo)
+{
+    const int64_t tot = (int64_t)Kp * rp;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(idx % rp);
+        const int j = (int)(idx / rp);
+        double v = 0.0;
+        if (i < r && j < K) v = folded_coeff(lam, b, kind, r, i, expo[j]);
+        switch (mode) {
+        case DMD_RECON_FP64: ((double*)out_hi)[idx] = v; break;
+        case DMD_RECON_FP32: ((float*)out_hi)[idx] = (float)v; break;
+        case DMD_RECON_BF16: ((__bf16*)out_hi)[idx] = (__bf16)(float)v; break;
+        default: {
+            const float f = (float)v;
+            const __bf16 h = (__bf16)f;
+            ((__bf16*)out_hi)[idx] = h;
+            ((__bf16*)out_lo)[idx] = (__bf16)(f - (float)h);
+        }
+        }
+    }
+}
+
+// Integer exponents to doubles; real times t to t / dt.
+__global__ void exponents_kernel(const int64_t* __restrict__ k, const double* __restrict__ t,
+                                 double inv_dt, int K, double* __restrict__ e)
+{
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < K; j += gridDim.x * blockDim.x)
+        e[j] = k ? (double)k[j] : t[j] * inv_dt;
+}
+
+// ---------------------------------------------------------------- reconstruction
+template <int MODE> struct RTraits;
+template <> struct RTraits<DMD_RECON_FP64> {
+    typedef double Tphi; typedef double Tc; typedef double Tout; typedef doublex4 V;
+    static constexpr int KW = 16;   // modes per k-group
+};
+template <> struct RTraits<DMD_RECON_FP32> {
+    typedef float Tphi; typedef float Tc; typedef float Tout; typedef floatx4 V;
+    static constexpr int KW = 16;
+};
+template <> struct RTraits<DMD_RECON_BF16> {
+    typedef float Tphi; typedef __bf16 Tc; typedef float Tout; typedef floatx4 V;
+    static constexpr int KW = 32;
+};
+template <> struct RTraits<DMD_RECON_BF16X3> {
+    typedef float Tphi; typedef __bf16 Tc; typedef float Tout; typedef floatx4 V;
+    static constexpr int KW = 32;
+};
+
+template <int MODE> struct AFrag;
+template <> struct AFrag<DMD_RECON_FP64> { double v[4]; };
+template <> struct AFrag<DMD_RECON_FP32> { float v[4]; };
+template <> struct AFrag<DMD_RECON_BF16> { bf16x8 hi; };
+template <> struct AFrag<DMD_RECON_BF16X3> { bf16x8 hi, lo; };
+
+template <int MODE>
+__device__ __forceinline__ void load_a(AFrag<MODE>& f, const typename RTraits<MODE>::Tphi* p, bool ok)
+{
+    if constexpr (MODE == DMD_RECON_FP64) {
+        if (ok) {
+            double2 x = reinterpret_cast<const double2*>(p)[0];
+            double2 y = reinterpret_cast<const double2*>(p)[1];
+            f.v[0] = x.x; f.v[1] = x.y; f.v[2] = y.x; f.v[3] = y.y;
+        } else {
+            f.v[0] = f.v[1] = f.v[2] = f.v[3] = 0.0;
+        }
+    } else if constexpr (MODE == DMD_RECON_FP32) {
+        float4 x = ok ? reinterpret_cast<const float4*>(p)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+        f.v[0] = x.x; f.v[1] = x.y; f.v[2] = x.z; f.v[3] = x.w;
+    } else {
+        float4 x = ok ? reinterpret_cast<const float4*>(p)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 y = ok ? reinterpret_cast<const float4*>(p)[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float xs[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const __bf16 h = (__bf16)xs[e];
+            f.hi[e] = h;
+            if constexpr (MODE == DMD_RECON_BF16X3) f.lo[e] = (__bf16)(xs[e] - (float)h);
+        }
+    }
+}
+
+template <int MODE, int RBW, int FCB, bool RESID>
+__global__ void __launch_bounds__(256)
+recon_kernel(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi, int64_t N, int rp,
+             const typename RTraits<MODE>::Tc* __restrict__ Chi,
+             const typename RTraits<MODE>::Tc* __restrict__ Clo, int K,
+             typename RTraits<MODE>::Tout* U, int64_t ldu, int vec_store,
+             const typename RTraits<MODE>::Tout* __restrict__ Xt, int64_t ldxt,
+             double* __restrict__ ss_partial,
+             int n_rowtiles, int n_fchunks, int frames_per_chunk)
+{
+    typedef RTraits<MODE> Tr;
+    typedef typename Tr::Tc Tc;
+    typedef typename Tr::Tout Tout;
+    typedef typename Tr::V V;
+    constexpr int KW = Tr::KW;
+    constexpr int KGMAX = RECON_MAX_RP / KW;
+    constexpr int FC = FCB * 16;
+    constexpr int CPAD = 16 / sizeof(Tc);               // 16-byte row pad in LDS
+    constexpr int CLD = RECON_MAX_RP + CPAD;
+    constexpr bool X3 = (MODE == DMD_RECON_BF16X3);
+    constexpr int WG_ROWS = 4 * RBW * 16;
+
+    __shared__ __align__(16) Tc Cs_hi[FC * CLD];
+    __shared__ __align__(16) Tc Cs_lo[X3 ? FC * CLD : 1];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lg = lane >> 4;
+    const int nkg = rp / KW;
+    const int cld = rp + CPAD;          // LDS leading dimension actually used
+
+    AFrag<MODE> a[RBW][KGMAX];
+    int cur_rt = -1;
+    double ss = 0.0;
+    const int64_t n_items = (int64_t)n_rowtiles * n_fchunks;
+
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int rt = (int)(item / n_fchunks);
+        const int fc = (int)(item % n_fchunks);
+        const int64_t tile_row0 = (int64_t)rt * WG_ROWS + wave * RBW * 16;
+        if (rt != cur_rt) {
+#pragma unroll
+            for (int rb = 0; rb < RBW; ++rb) {
+                const int64_t row = tile_row0 + rb * 16 + l16;
+                const bool ok = row < N;
+                const typename Tr::Tphi* prow = phi + (ok ? row : 0) * ldphi;
+#pragma unroll
+                for (int kg = 0; kg < KGMAX; ++kg) {
+                    if (kg < nkg) {
+                        const int m0 = (KW == 16) ? (kg * 16 + 4 * lg) : (kg * 32 + 8 * lg);
+                        load_a<MODE>(a[rb][kg], prow + m0, ok);
+                    }
+                }
+            }
+            cur_rt = rt;
+        }
+        const int f_begin = fc * frames_per_chunk;
+        const int f_end = min(K, f_begin + frames_per_chunk);
+        for (int f0 = f_begin; f0 < f_end; f0 += FC) {
+            __syncthreads();
+            // ---- stage coefficients of frames [f0, f0 + FC) (zero-padded rows exist up to Kp)
+            {
+                constexpr int VE = 16 / sizeof(Tc);       // elements per 16-byte move
+                const int per_row = rp / VE;
+                for (int idx = tid; idx < FC * per_row; idx += 256) {
+                    const int fr = idx / per_row, c = (idx % per_row) * VE;
+                    const int64_t src = (int64_t)(f0 + fr) * rp + c;
+                    *reinterpret_cast<float4*>(&Cs_hi[fr * cld + c]) = *reinterpret_cast<const float4*>(&Chi[src]);
+                    if constexpr (X3)
+                        *reinterpret_cast<float4*>(&Cs_lo[fr * cld + c]) = *reinterpret_cast<const float4*>(&Clo[src]);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int cb = 0; cb < FCB; ++cb) {
+                V acc[RBW];
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb) acc[rb] = zero_acc<V>();
+                const Tc* crow_hi = Cs_hi + (cb * 16 + l16) * cld;
+                const Tc* crow_lo = Cs_lo + (cb * 16 + l16) * cld;
+#pragma unroll
+                for (int kg = 0; kg < KGMAX; ++kg) {
+                    if (kg < nkg) {
+                        if constexpr (MODE == DMD_RECON_FP32 || MODE == DMD_RECON_FP64) {
+                            const Tc* bp = crow_hi + kg * 16 + 4 * lg;
+                            Tc bv[4];
+                            if constexpr (MODE == DMD_RECON_FP32) {
+                                float4 x = *reinterpret_cast<const float4*>(bp);
+                                bv[0] = x.x; bv[1] = x.y; bv[2] = x.z; bv[3] = x.w;
+                            } else {
+                                double2 x = reinterpret_cast<const double2*>(bp)[0];
+                                double2 y = reinterpret_cast<const double2*>(bp)[1];
+                                bv[0] = x.x; bv[1] = x.y; bv[2] = y.x; bv[3] = y.y;
+                            }
+#pragma unroll
+                            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                                for (int rb = 0; rb < RBW; ++rb)
+                                    acc[rb] = mfma(a[rb][kg].v[s], bv[s], acc[rb]);
+                        } else {
+                            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(crow_hi + kg * 32 + 8 * lg);
+                            if constexpr (X3) {
+                                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(crow_lo + kg * 32 + 8 * lg);
+#pragma unroll
+                                for (int rb = 0; rb < RBW; ++rb) {
+                                    acc[rb] = mfma_bf16(a[rb][kg].lo, bh, acc[rb]);
+                                    acc[rb] = mfma_bf16(a[rb][kg].hi, bl, acc[rb]);
+                                    acc[rb] = mfma_bf16(a[rb][kg].hi, bh, acc[rb]);
+                                }
+                            } else {
+#pragma unroll
+                                for (int rb = 0; rb < RBW; ++rb)
+                                    acc[rb] = mfma_bf16(a[rb][kg].hi, bh, acc[rb]);
+                            }
+                        }
+                    }
+                }
+                // ---- epilogue: lane holds rows 4*lg..4*lg+3 of frame cb*16 + l16
+                const int frame = f0 + cb * 16 + l16;
+                if (frame < f_end) {
+#pragma unroll
+                    for (int rb = 0; rb < RBW; ++rb) {
+                        const int64_t row = tile_row0 + rb * 16 + 4 * lg;
+                        if (row >= N) continue;
+                        Tout* dst = U + (int64_t)frame * ldu + row;
+                        Tout o[4];
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) o[v] = (Tout)acc[rb][v];
+                        if constexpr (RESID) {
+                            const Tout* src = Xt + (int64_t)frame * ldxt + row;
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                if (row + v < N) {
+                                    o[v] = src[v] - o[v];
+                                    ss += (double)o[v] * (double)o[v];
+                                }
+                            }
+                        }
+                        if (vec_store && row + 4 <= N) {
+                            if constexpr (sizeof(Tout) == 4) {
+                                floatx4 w = {o[0], o[1], o[2], o[3]};
+                                if constexpr (RESID) *reinterpret_cast<floatx4*>(dst) = w;
+                                else __builtin_nontemporal_store(w, reinterpret_cast<floatx4*>(dst));
+                            } else {
+                                typedef double doublex2 __attribute__((ext_vector_type(2)));
+                                doublex2 w0 = {(double)o[0], (double)o[1]}, w1 = {(double)o[2], (double)o[3]};
+                                if constexpr (RESID) {
+                                    reinterpret_cast<doublex2*>(dst)[0] = w0;
+                                    reinterpret_cast<doublex2*>(dst)[1] = w1;
+                                } else {
+                                    __builtin_nontemporal_store(w0, reinterpret_cast<doublex2*>(dst));
+                                    __builtin_nontemporal_store(w1, reinterpret_cast<doublex2*>(dst) + 1);
+                                }
+                            }
+                        } else {
+#pragma unroll
+                            for (int v = 0; v < 4; ++v)
+                                if (row + v < N) dst[v] = o[v];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if constexpr (RESID) {
+        __shared__ double red[4];
+        ss = wave_sum(ss);
+        if (lane == 0) red[wave] = ss;
+        __syncthreads();
+        if (tid == 0) ss_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// ---------------------------------------------------------------- launch
+static int g_cu_count = 0;
+int device_cu_count()
+{
+    if (g_cu_count == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess) return 256;
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return 256;
+        g_cu_count = p.multiProcessorCount > 0 ? p.multiProcessorCount : 256;
+    }
+    return g_cu_count;
+}
+
+template <int MODE, int RBW, int FCB, bool RESID>
+static hipError_t launch_recon_t(hipStream_t s, const ReconArgs& ra, int grid_per_cu)
+{
+    typedef RTraits<MODE> Tr;
+    constexpr int WG_ROWS = 4 * RBW * 16;
+    constexpr int FC = FCB * 16;
+    const int n_rowtiles = (int)ceil_div(ra.N, WG_ROWS);
+    const int max_grid = device_cu_count() * grid_per_cu;
+    int n_fchunks = 1;
+    const int max_fchunks = (int)ceil_div(ra.K, FC);
+    if (n_rowtiles < 2 * max_grid) n_fchunks = (int)std::min<int64_t>(max_fchunks, ceil_div(2 * max_grid, n_rowtiles));
+    if (n_fchunks < 1) n_fchunks = 1;
+    const int fpc = (int)round_up(ceil_div(ra.K, n_fchunks), FC);
+    n_fchunks = (int)ceil_div(ra.K, fpc);
+    const int64_t items = (int64_t)n_rowtiles * n_fchunks;
+    const int grid = (int)std::min<int64_t>(items, max_grid);
+    hipLaunchKernelGGL((recon_kernel<MODE, RBW, FCB, RESID>), dim3(grid), dim3(256), 0, s,
+                       (const typename Tr::Tphi*)ra.phi, ra.ldphi, ra.N, ra.rp,
+                       (const typename Tr::Tc*)ra.c_hi, (const typename Tr::Tc*)ra.c_lo, ra.K,
+                       (typename Tr::Tout*)ra.U, ra.ldu, ra.vec_store,
+                       (const typename Tr::Tout*)ra.xt, ra.ldxt, ra.ss_partial,
+                       n_rowtiles, n_fchunks, fpc);
+    if (ra.grid_out) *ra.grid_out = grid;
+    return hipGetLastError();
+}
+
+// Tile-shape candidates (index = autotuner config id).
+template <bool RESID>
+static hipError_t dispatch_recon(hipStream_t s, const ReconArgs& ra, int cfg)
+{
+    switch (ra.mode) {
+    case DMD_RECON_FP64:
+        switch (cfg) {
+        case 1: return launch_recon_t<DMD_RECON_FP64, 1, 1, RESID>(s, ra, 2);
+        case 2: return launch_recon_t<DMD_RECON_FP64, 2, 2, RESID>(s, ra, 1);
+        default: return launch_recon_t<DMD_RECON_FP64, 1, 2, RESID>(s, ra, 2);
+        }
+    case DMD_RECON_FP32:
+        switch (cfg) {
+        case 1: return launch_recon_t<DMD_RECON_FP32, 1, 2, RESID>(s, ra, 4);
+        case 2: return launch_recon_t<DMD_RECON_FP32, 2, 4, RESID>(s, ra, 2);
+        default: return launch_recon_t<DMD_RECON_FP32, 2, 2, RESID>(s, ra, 2);
+        }
+    case DMD_RECON_BF16:
+        switch (cfg) {
+        case 1: return launch_recon_t<DMD_RECON_BF16, 2, 2, RESID>(s, ra, 4);
+        case 2: return launch_recon_t<DMD_RECON_BF16, 4, 4, RESID>(s, ra, 2);
+        default: return launch_recon_t<DMD_RECON_BF16, 4, 2, RESID>(s, ra, 2);
+        }
+    default:
+        switch (cfg) {
+        case 1: return launch_recon_t<DMD_RECON_BF16X3, 2, 2, RESID>(s, ra, 4);
+        case 2: return launch_recon_t<DMD_RECON_BF16X3, 4, 4, RESID>(s, ra, 2);
+        default: return launch_recon_t<DMD_RECON_BF16X3, 4, 2, RESID>(s, ra, 2);
+        }
+    }
+}
+
+hipError_t recon_launch(hipStream_t s, const ReconArgs& ra, int cfg)
+{
+    if (ra.N <= 0 || ra.K <= 0) return hipSuccess;
+    return ra.xt ? dispatch_recon<true>(s, ra, cfg) : dispatch_recon<false>(s, ra, cfg);
+}
+
+hipError_t powers_pack(hipStream_t s, const double* lam, const double* b, const int32_t* kind, int r,
+                       const double* expo, int K, int Kp, int rp, int mode, void* hi, void* lo)
+{
+    const int64_t tot = (int64_t)Kp * rp;
+    const int blocks = (int)std::min<int64_t>(ceil_div(tot, 256), 2048);
+    hipLaunchKernelGGL(powers_pack_kernel, dim3(blocks), dim3(256), 0, s, lam, b, kind, r, expo, K,
+                       Kp, rp, mode, hi, lo);
+    return hipGetLastError();
+}
+
+hipError_t exponents(hipStream_t s, const int64_t* k, const double* t, double inv_dt, int K, double* e)
+{
+    hipLaunchKernelGGL(exponents_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(K, 256), 256)), dim3(256), 0, s,
+                       k, t, inv_dt, K, e);
+    return hipGetLastError();
+}
+
+}  // namespace dmd

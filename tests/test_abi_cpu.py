@@ -1,0 +1,221 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+declared symbol, its structs match the header, and every argument error that
+validation catches before the first HIP call is reported."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dmdmi.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2502_05339_amd import _lib
+    return _lib.lib()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dmd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_no_extra_exports():
+    out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(ROOT, "paper_2502_05339_amd", "libdmdmi.so")],
+                         capture_output=True, text=True, check=True).stdout
+    exported = sorted(set(re.findall(r" T (dmd_[a-z0-9_]+)", out)))
+    assert exported == _declared_functions()
+
+
+def test_version_and_strings(L):
+    from paper_2502_05339_amd import _lib
+    assert L.dmd_abi_version() == 1
+    for code in range(0, 12):
+        assert len(_lib.status_string(code)) >= 2
+    assert "unknown" in _lib.status_string(99)
+    assert L.dmd_phi_ld(1) == 32 and L.dmd_phi_ld(150) == 160 and L.dmd_phi_ld(160) == 160
+
+
+def test_struct_layout_matches_header():
+    from paper_2502_05339_amd import _lib
+    src = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "dmdmi.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(dmd_fit_opts), sizeof(dmd_model), sizeof(dmd_scene));
+  printf("%zu %zu %zu\n", offsetof(dmd_fit_opts, omega), offsetof(dmd_model, info), offsetof(dmd_scene, ws_bytes));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    sizes = list(map(int, out))
+    assert sizes[:3] == [ctypes.sizeof(_lib.FitOpts), ctypes.sizeof(_lib.ModelStruct), ctypes.sizeof(_lib.SceneStruct)]
+    assert sizes[3] == _lib.FitOpts.omega.offset
+    assert sizes[4] == _lib.ModelStruct.info.offset
+    assert sizes[5] == _lib.SceneStruct.ws_bytes.offset
+
+
+def _opts(r=10, p=4, q=1, precision="mixed", omega=0x1000):
+    from paper_2502_05339_amd import fit_opts
+    o = fit_opts(r, p, q, precision)
+    o.omega = omega
+    return o
+
+
+def _ws_size(L, n, ncols, dtype, o):
+    nb = ctypes.c_size_t(0)
+    st = L.dmd_fit_workspace_size(n, ncols, dtype, ctypes.byref(o), ctypes.byref(nb))
+    return st, nb.value
+
+
+@pytest.mark.parametrize("n,ncols,r,p,expect", [
+    (1000, 30, 10, 4, 0),
+    (1000, 30, 31, 0, 2),      # r > m-1
+    (1000, 30, 25, 10, 2),     # l > m-1
+    (10, 30, 8, 4, 2),         # l > N
+    (0, 30, 8, 4, 2),          # empty
+    (1000, 400, 170, 10, 11),  # r beyond the eigen-solver limit
+    (1000, 400, 150, 60, 11),  # l beyond the small-matrix limit
+])
+def test_fit_shape_validation(L, n, ncols, r, p, expect):
+    st, _ = _ws_size(L, n, ncols, 0, _opts(r, p))
+    assert st == expect
+
+
+def test_fit_dtype_and_enum_validation(L):
+    assert _ws_size(L, 1000, 30, 1, _opts(precision="mixed"))[0] == 1       # mixed needs FP32
+    assert _ws_size(L, 1000, 30, 0, _opts(precision="fp64"))[0] == 1        # fp64 needs FP64
+    o = _opts()
+    o.precision = 7
+    assert _ws_size(L, 1000, 30, 0, o)[0] == 1
+    o = _opts()
+    o.dt = 0.0
+    assert _ws_size(L, 1000, 30, 0, o)[0] == 1
+    o = _opts(r=16, p=0, q=0, precision="fp64_exact")
+    assert _ws_size(L, 8192, 64, 1, o)[0] == 0
+    assert _ws_size(L, 8192, 250, 1, _opts(r=16, p=0, q=0, precision="fp64_exact"))[0] == 11
+
+
+def test_workspace_sizes_scale(L):
+    st, small = _ws_size(L, 131072, 199, 0, _opts(150, 10, 2))
+    st2, big = _ws_size(L, 6291456, 299, 0, _opts(150, 10, 2))
+    assert st == st2 == 0
+    # the sketch Y (N x l floats) dominates
+    assert big >= 6291456 * 160 * 4
+    assert small < 400 * 2 ** 20
+
+
+def _model_struct(n=1000, r=10, dtype=0, ldphi=32, phi=0x10000):
+    from paper_2502_05339_amd import _lib
+    m = _lib.ModelStruct()
+    m.n, m.r, m.dtype, m.dt, m.phi, m.ldphi = n, r, dtype, 1.0, phi, ldphi
+    m.lam = m.b = m.sigma = m.kind = m.info = 0x20000
+    return m
+
+
+def test_fit_pointer_and_workspace_errors(L):
+    o = _opts()
+    m = _model_struct()
+    # null X
+    assert L.dmd_fit(None, None, 0x100, 1000, 30, 1000, 1000, 0, ctypes.byref(o), 0x1000, 1 << 30, ctypes.byref(m)) == 1
+    # misaligned phi
+    m2 = _model_struct(phi=0x10004)
+    assert L.dmd_fit(None, 0x100, 0x200, 1000, 30, 1000, 1000, 0, ctypes.byref(o), 0x1000, 1 << 30,
+                     ctypes.byref(m2)) == 1
+    # ldphi not a multiple of 32
+    m3 = _model_struct(ldphi=40)
+    assert L.dmd_fit(None, 0x100, 0x200, 1000, 30, 1000, 1000, 0, ctypes.byref(o), 0x1000, 1 << 30,
+                     ctypes.byref(m3)) == 1
+    # model rows differ from X rows
+    m4 = _model_struct(n=999)
+    assert L.dmd_fit(None, 0x100, 0x200, 1000, 30, 1000, 1000, 0, ctypes.byref(o), 0x1000, 1 << 30,
+                     ctypes.byref(m4)) == 2
+    # leading dimension smaller than N
+    assert L.dmd_fit(None, 0x100, 0x200, 1000, 30, 999, 1000, 0, ctypes.byref(o), 0x1000, 1 << 30,
+                     ctypes.byref(m)) == 1
+    # missing sketch
+    o2 = _opts(omega=0)
+    assert L.dmd_fit(None, 0x100, 0x200, 1000, 30, 1000, 1000, 0, ctypes.byref(o2), 0x1000, 1 << 30,
+                     ctypes.byref(m)) == 1
+    # workspace too small
+    _, need = _ws_size(L, 1000, 30, 0, o)
+    assert L.dmd_fit(None, 0x100, 0x200, 1000, 30, 1000, 1000, 0, ctypes.byref(o), 0x1000, need - 1,
+                     ctypes.byref(m)) == 3
+
+
+def test_reconstruct_validation(L):
+    from paper_2502_05339_amd import _lib
+    m = _model_struct(r=10)
+    ks = (ctypes.c_int64 * 4)(0, 1, 2, 3)
+    nb = ctypes.c_size_t(0)
+    assert L.dmd_reconstruct_workspace_size(10, 4, 3, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert L.dmd_reconstruct_workspace_size(10, 0, 3, ctypes.byref(nb)) == 2
+    assert L.dmd_reconstruct_workspace_size(10, 4, 9, ctypes.byref(nb)) == 1
+    # FP64 mode on an FP32 model
+    assert L.dmd_reconstruct(None, ctypes.byref(m), ks, 4, 0, 0x1000, 1000, 0x2000, 1 << 20) == 1
+    # K = 0
+    assert L.dmd_reconstruct(None, ctypes.byref(m), ks, 0, 1, 0x1000, 1000, 0x2000, 1 << 20) == 2
+    # ldu < N
+    assert L.dmd_reconstruct(None, ctypes.byref(m), ks, 4, 1, 0x1000, 999, 0x2000, 1 << 20) == 1
+    # small workspace
+    L.dmd_reconstruct_workspace_size(10, 4, 1, ctypes.byref(nb))
+    assert L.dmd_reconstruct(None, ctypes.byref(m), ks, 4, 1, 0x1000, 1000, 0x2000, nb.value - 1) == 3
+    # rank beyond the reconstruction's register tile
+    big = _model_struct(r=200, ldphi=224)
+    assert L.dmd_reconstruct(None, ctypes.byref(big), ks, 4, 1, 0x1000, 1000, 0x2000, 1 << 20) == 11
+    # non-finite time
+    ts = (ctypes.c_double * 2)(0.0, float("nan"))
+    assert L.dmd_integrate(None, ctypes.byref(m), ts, 2, 1, 0x1000, 1000, 0x2000, 1 << 20) == 1
+    assert _lib.DMD_OK == 0
+
+
+def test_project_and_loss_validation(L):
+    m = _model_struct(r=10)
+    nb = ctypes.c_size_t(0)
+    assert L.dmd_project_workspace_size(1000, 10, ctypes.byref(nb)) == 0
+    assert L.dmd_project(None, ctypes.byref(m), None, 0x100, 0x1000, 1 << 20) == 1
+    assert L.dmd_project(None, ctypes.byref(m), 0x100, 0x200, 0x1000, 0) == 3
+    assert L.dmd_loss_grad_workspace_size(1000, 10, 20, 0, ctypes.byref(nb)) == 0
+    ks = (ctypes.c_int64 * 2)(0, 1)
+    assert L.dmd_loss_grad(None, ctypes.byref(m), 0x100, 0x100, 0x100, 999, ks, 2, 0x300, 0x1000, 1 << 20) == 1
+    assert L.dmd_loss_grad(None, ctypes.byref(m), 0x100, 0x100, 0x100, 1000, ks, 2, 0x300, 0x1000, 0) == 3
+
+
+def test_batched_validation(L):
+    from paper_2502_05339_amd import _lib
+    sc = (_lib.SceneStruct * 1)()
+    ms = (_lib.ModelStruct * 1)()
+    assert L.dmd_fit_batched(None, 0, sc, ms, 0, None) == 1
+    sc[0].n, sc[0].ncols, sc[0].xdtype, sc[0].ldx, sc[0].ldxp = 1000, 30, 0, 1000, 1000
+    sc[0].x, sc[0].xp = 0x100, 0x200
+    sc[0].opts = _opts(r=40, p=4)          # r > m-1
+    ms[0] = _model_struct()
+    assert L.dmd_fit_batched(None, 1, sc, ms, 0, None) == 2
+    assert L.dmd_graph_launch(None, None) == 1
+    assert L.dmd_graph_destroy(None) == 1
+
+
+def test_binding_refuses_cpu_tensors():
+    import torch
+    import paper_2502_05339_amd as dmd
+    Z = torch.zeros((10, 100), dtype=torch.float32)
+    with pytest.raises((RuntimeError, ValueError)):
+        dmd.fit(Z, 4)

@@ -1,0 +1,136 @@
+"""GPU parity of the hand-written adjoint (loss and gradients in lambda and b with
+the modes fixed) against the FP64 oracle's closed form, through the C ABI.
+
+Tolerances: FP64 model 1e-10 relative; FP32 model 1e-4 relative (the residual and
+Phi^T R run as FP32 MFMA GEMMs; lambda^k and the r-reductions stay FP64).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import model_from_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _perturbed(f, rng, scale=1e-3):
+    lam = f.lam.copy()
+    b = f.b.copy()
+    lam += scale * (rng.standard_normal(lam.size) + 1j * rng.standard_normal(lam.size))
+    b += scale * (rng.standard_normal(b.size) + 1j * rng.standard_normal(b.size))
+    return lam, b
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
+def test_loss_grad_matches_closed_form(gpu_lib, dtype, tol):
+    import paper_2502_05339_amd as dmd
+    cfg = synth.config("c1-cf", seed=103)
+    _print(f"case: loss/grad c1-cf {dtype}")
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    m = model_from_oracle(f, dtype)
+    rng = np.random.default_rng(1)
+    lam, b = _perturbed(f, rng)
+    ks = np.arange(cfg.m)
+    X = torch.from_numpy(np.ascontiguousarray(g.Z.T)).to(dtype).cuda()
+    L, gl, gb = dmd.loss_grad(m, torch.from_numpy(lam).cuda(), torch.from_numpy(b).cuda(), X, ks)
+    phi = m.complex_modes()
+    Xo = X.double().cpu().numpy().T
+    Lo, glo, gbo = oracle.loss_grad(phi, lam, b, Xo, ks)
+    _print(f"  loss {L.item():.6e} vs {Lo:.6e}")
+    assert abs(L.item() - Lo) <= tol * abs(Lo)
+    assert _relerr(gl.cpu().numpy(), glo) <= tol
+    assert _relerr(gb.cpu().numpy(), gbo) <= tol
+
+
+def test_loss_grad_c4_shape_with_strided_targets(gpu_lib):
+    """c4 shape (N = 131072, 200 frames, rank-40 system, noise 1e-2) on an FP32 model,
+    arbitrary k-list and a strided target buffer."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.config("c4")
+    _print("case: loss/grad c4 shape fp32")
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z.astype(np.float64), cfg.r)
+    m = model_from_oracle(f, torch.float32)
+    rng = np.random.default_rng(2)
+    lam, b = _perturbed(f, rng, 1e-4)
+    ks = np.arange(cfg.m)[::-1].copy()
+    big = torch.zeros((cfg.m, cfg.N + 64), dtype=torch.float32, device="cuda")
+    big[:, : cfg.N] = torch.from_numpy(np.ascontiguousarray(g.Z.T))
+    X = big[:, : cfg.N]
+    L, gl, gb = dmd.loss_grad(m, torch.from_numpy(lam).cuda(), torch.from_numpy(b).cuda(), X, ks)
+    rows = np.arange(cfg.N)
+    phi = m.complex_modes(rows)
+    Lo, glo, gbo = oracle.loss_grad(phi, lam, b, g.Z.astype(np.float64)[:, ::-1], np.arange(cfg.m))
+    # the oracle above uses k = 0..m-1 against reversed targets, i.e. the same pairs
+    _print(f"  loss {L.item():.6e} vs {Lo:.6e}")
+    assert abs(L.item() - Lo) <= 1e-4 * abs(Lo)
+    assert _relerr(gl.cpu().numpy(), glo) <= 1e-4
+    assert _relerr(gb.cpu().numpy(), gbo) <= 1e-4
+
+
+def test_autograd_function_and_refit(gpu_lib):
+    """DMDLoss behind torch.autograd gives the library's gradient, and gradient steps
+    from a perturbed start lower the loss (the refit of Sec. 4.2's motivation)."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.config("c1-cf", seed=104)
+    _print("case: DMDLoss autograd + refit")
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    m = model_from_oracle(f, torch.float64)
+    rng = np.random.default_rng(3)
+    lam0, b0 = _perturbed(f, rng, 1e-3)
+    ks = np.arange(cfg.m)
+    X = torch.from_numpy(np.ascontiguousarray(g.Z.T)).cuda()
+    lam = torch.from_numpy(lam0).cuda().requires_grad_(True)
+    b = torch.from_numpy(b0).cuda().requires_grad_(True)
+    loss = dmd.DMDLoss.apply(lam, b, m, X, ks)
+    (2.0 * loss).backward()
+    _, gl, gb = dmd.loss_grad(m, lam.detach(), b.detach(), X, ks)
+    assert torch.allclose(lam.grad, 2.0 * gl) and torch.allclose(b.grad, 2.0 * gb)
+    m.lam.copy_(torch.from_numpy(lam0))
+    m.b.copy_(torch.from_numpy(b0))
+    lam1, b1, losses = dmd.refit(m, X, ks, steps=60, lr=2e-4)
+    _print(f"  refit loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+    assert losses[-1] < 0.1 * losses[0]
+
+
+def test_finite_differences_fp64(gpu_lib):
+    """Central differences (h = 1e-6) of the GPU loss match the GPU gradient (FP64 model)."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.Config("fd", (2, 24, 24), 30, 4, 0.9, 1e-3, 77, r=8, p=0, q=0, dtype="f64")
+    _print("case: finite differences of the GPU loss")
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    m = model_from_oracle(f, torch.float64)
+    rng = np.random.default_rng(4)
+    lam, b = _perturbed(f, rng, 1e-2)
+    ks = np.arange(cfg.m)
+    X = torch.from_numpy(np.ascontiguousarray(g.Z.T)).cuda()
+    t = lambda a: torch.from_numpy(a).cuda()
+    _, gl, gb = dmd.loss_grad(m, t(lam), t(b), X, ks)
+    gl, gb = gl.cpu().numpy(), gb.cpu().numpy()
+    h = 1e-6
+    for which, gvec in (("lam", gl), ("b", gb)):
+        for i in (0, 3, 6):
+            for unit in (1.0, 1j):
+                lp, ln, bp, bn = lam.copy(), lam.copy(), b.copy(), b.copy()
+                if which == "lam":
+                    lp[i] += h * unit; ln[i] -= h * unit
+                else:
+                    bp[i] += h * unit; bn[i] -= h * unit
+                Lp = dmd.loss_grad(m, t(lp), t(bp), X, ks)[0].item()
+                Ln = dmd.loss_grad(m, t(ln), t(bn), X, ks)[0].item()
+                fd = (Lp - Ln) / (2 * h)
+                an = gvec[i].real if unit == 1.0 else gvec[i].imag
+                assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (which, i, unit, fd, an)

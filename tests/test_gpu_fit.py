@@ -1,0 +1,252 @@
+"""GPU parity of the fit (Sec. 4.3 randomized SVD, Sec. 3.1 exact DMD) against the
+FP64 oracle, through the C ABI.
+
+Gates (the tolerances come from the target accuracy of the mixed-precision
+path: 1e-5 relative in lambda and 1e-4 in the fields):
+  G1  FP64 exact path on the noise-free closed form: lambda <= 1e-10 against the
+      prescribed eigenvalues, snapshots rebuilt to <= 1e-12.
+  G2  mixed path against the FP64 randomized twin fed the same sketch: fields
+      <= 1e-4, amplitude-weighted lambda <= 1e-5.
+  G3  mixed path against the exact oracle on the well-posed variant: max-relative
+      lambda <= 1e-5, fields <= 1e-4.
+Eigenvalue sets are compared after an optimal matching; modes only through the
+fields they produce (their scale is not unique).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import max_frame_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+def _gpu_fit(g, cfg, precision):
+    import paper_2502_05339_amd as dmd
+    dt = torch.float64 if precision != "mixed" else torch.float32
+    Z = torch.from_numpy(np.ascontiguousarray(g.Z.T).astype(np.float64 if dt == torch.float64 else np.float32)).cuda()
+    om = None
+    if precision != "fp64_exact":
+        Om = np.ascontiguousarray(g.Omega.T).astype(np.float64 if dt == torch.float64 else np.float32)
+        om = torch.from_numpy(Om).cuda()
+    m = dmd.fit(Z, cfg.r, p=cfg.p, q=cfg.q, omega=om, precision=precision)
+    return m, Z
+
+
+def _fields(m, ks, mode, rows=None):
+    U = m.reconstruct(ks, mode)
+    if rows is not None:
+        U = U[:, torch.from_numpy(rows).cuda()]
+    return U.cpu().numpy()
+
+
+def _weights(m):
+    phi = m.complex_modes()
+    return np.abs(m.b_host()) * np.linalg.norm(phi, axis=0)
+
+
+@pytest.mark.parametrize("seed", [102, 103, 104])
+def test_g1_fp64_exact_closed_form(gpu_lib, seed):
+    cfg = synth.config("c1-cf", seed=seed)
+    _print(f"case: G1 c1-cf seed {seed}, fp64_exact")
+    g = synth.generate(cfg)
+    m, Z = _gpu_fit(g, cfg, "fp64_exact")
+    truth = np.concatenate([g.lam, np.conj(g.lam)])
+    e = oracle.eig_errors(m.lam_host(), truth)
+    _print(f"  lambda max rel {e['max_rel']:.3e}")
+    assert e["max_rel"] <= 1e-10
+    U = _fields(m, np.arange(cfg.m), "fp64")
+    err = max_frame_rel(U, g.Z.T)
+    _print(f"  rebuild max-frame {err:.3e}")
+    assert err <= 1e-12
+    kind = m.kind_host()
+    assert set(kind.tolist()) <= {0, 1, 2}
+    lam = m.lam_host()
+    assert np.all(np.diff(np.abs(np.angle(lam))) >= -1e-12)      # canonical order
+
+
+def test_fp64_exact_vs_oracle_literal_c1(gpu_lib):
+    """Literal c1 (noise 1e-8, ill-conditioned frequencies): the FP64 path and the
+    oracle agree on the fields to well below the noise level."""
+    cfg = synth.config("c1")
+    _print("case: c1 literal fp64_exact vs oracle")
+    g = synth.generate(cfg)
+    m, Z = _gpu_fit(g, cfg, "fp64_exact")
+    f = oracle.fit_exact(g.Z, cfg.r)
+    ks = np.arange(cfg.K)
+    U = _fields(m, ks, "fp64")
+    Uo = oracle.reconstruct(f.phi, f.lam, f.b, ks).T
+    err = max_frame_rel(U, Uo)
+    _print(f"  fields vs oracle {err:.3e}")
+    assert err <= 1e-6
+    s = m.sigma.cpu().numpy()
+    assert np.allclose(s[:8], f.sigma[:8], rtol=1e-10)
+
+
+def _small_randomized_cfg(sigma=1e-4, seed=211, jitter=False):
+    return synth.Config("c2-small", (2, 96, 96), 120, 30, 0.95, sigma, seed, r=60, p=10, q=2, jitter=jitter)
+
+
+@pytest.mark.parametrize("precision,tol_lam,tol_field", [("mixed", 1e-5, 1e-4), ("fp64", 1e-9, 1e-9)])
+def test_randomized_vs_twin_small(gpu_lib, precision, tol_lam, tol_field):
+    cfg = _small_randomized_cfg()
+    _print(f"case: small randomized {precision} vs FP64 twin")
+    g = synth.generate(cfg)
+    if precision == "fp64":
+        g.Omega = g.Omega.astype(np.float64)
+    m, Z = _gpu_fit(g, cfg, precision)
+    Zd = g.Z.astype(np.float64)
+    tw = oracle.fit_randomized(Zd, cfg.r, g.Omega.astype(np.float64), cfg.q)
+    e = oracle.eig_errors(m.lam_host(), tw.lam, weights=None)
+    w = oracle.amplitude_weights(tw.phi, tw.b)
+    ia, ib = oracle.match_eigs(m.lam_host(), tw.lam)
+    d = np.abs(m.lam_host()[ia] - tw.lam[ib])
+    wrel = float(np.sum(w[ib] * d) / np.sum(w[ib] * np.abs(tw.lam[ib])))
+    ks = np.arange(cfg.m)
+    U = _fields(m, ks, "fp64" if precision == "fp64" else "fp32")
+    Uo = oracle.reconstruct(tw.phi, tw.lam, tw.b, ks).T
+    ferr = max_frame_rel(U, Uo)
+    _print(f"  lambda max {e['max_rel']:.3e} weighted {wrel:.3e} fields {ferr:.3e}")
+    assert wrel <= tol_lam
+    assert ferr <= tol_field
+    assert int(m.info[0].item()) == 0
+
+
+def test_g3_mixed_vs_exact_well_posed_c2(gpu_lib):
+    """Full-size c2-wp (N = 131072, m = 200, r = 150, p = 10, q = 2)."""
+    cfg = synth.config("c2-wp")
+    _print("case: G3 c2-wp mixed vs exact oracle (full size)")
+    g = synth.generate(cfg)
+    m, Z = _gpu_fit(g, cfg, "mixed")
+    f = oracle.fit_exact(g.Z.astype(np.float64), cfg.r)
+    e = oracle.eig_errors(m.lam_host(), f.lam)
+    rows = np.sort(np.random.default_rng(5).choice(cfg.N, 4096, replace=False))
+    ks = np.arange(cfg.m)
+    U = _fields(m, ks, "fp32", rows)
+    Uo = oracle.reconstruct(f.phi[rows], f.lam, f.b, ks).T
+    ferr = max_frame_rel(U, Uo)
+    _print(f"  lambda max {e['max_rel']:.3e} fields {ferr:.3e}")
+    assert e["max_rel"] <= 1e-5
+    assert ferr <= 1e-4
+
+
+def test_g2_mixed_vs_twin_c2(gpu_lib):
+    """Full-size literal c2 (noise 1e-4): the rank-150 cut lies in the noise bulk, so the
+    gate is the twin fed the same sketch, with the amplitude-weighted eigenvalue error."""
+    cfg = synth.config("c2")
+    _print("case: G2 c2 mixed vs FP64 twin (full size)")
+    g = synth.generate(cfg)
+    m, Z = _gpu_fit(g, cfg, "mixed")
+    tw = oracle.fit_randomized(g.Z.astype(np.float64), cfg.r, g.Omega.astype(np.float64), cfg.q)
+    w = oracle.amplitude_weights(tw.phi, tw.b)
+    ia, ib = oracle.match_eigs(m.lam_host(), tw.lam)
+    d = np.abs(m.lam_host()[ia] - tw.lam[ib])
+    wrel = float(np.sum(w[ib] * d) / np.sum(w[ib] * np.abs(tw.lam[ib])))
+    rows = np.sort(np.random.default_rng(6).choice(cfg.N, 4096, replace=False))
+    ks = np.arange(cfg.m)
+    U = _fields(m, ks, "fp32", rows)
+    Uo = oracle.reconstruct(tw.phi[rows], tw.lam, tw.b, ks).T
+    ferr = max_frame_rel(U, Uo)
+    _print(f"  lambda weighted {wrel:.3e} max {np.max(d / np.abs(tw.lam[ib])):.3e} fields {ferr:.3e}")
+    assert wrel <= 1e-5
+    assert ferr <= 1e-4
+
+
+def test_fit_separate_x_xp_matches_shifted_view(gpu_lib):
+    """X and X' passed as separate buffers give the same model as the shifted views of Z."""
+    import paper_2502_05339_amd as dmd
+    cfg = _small_randomized_cfg(seed=212)
+    _print("case: separate X / X' buffers")
+    g = synth.generate(cfg)
+    m1, Z = _gpu_fit(g, cfg, "mixed")
+    X = Z[:-1].clone()
+    Xp = Z[1:].clone()
+    om = torch.from_numpy(np.ascontiguousarray(g.Omega.T)).cuda()
+    m2 = dmd.fit(None, cfg.r, X=X, Xp=Xp, p=cfg.p, q=cfg.q, omega=om)
+    assert np.allclose(m1.lam_host(), m2.lam_host(), rtol=1e-6, atol=1e-6)
+
+
+def test_fit_errors_raise(gpu_lib):
+    import paper_2502_05339_amd as dmd
+    _print("case: error statuses")
+    Z = torch.zeros((20, 1000), dtype=torch.float32, device="cuda")
+    om = torch.zeros((30, 19), dtype=torch.float32, device="cuda")
+    with pytest.raises(dmd.DMDError) as ei:
+        dmd.fit(Z, 25, p=5, omega=om)
+    assert ei.value.code == 2
+    # rank tolerance: snapshots of a rank-4 system, ask for r = 8 with a tolerance
+    rng = np.random.default_rng(0)
+    cfg = synth.Config("rk", (4000,), 40, 2, 0.9, 0.0, 5, r=8, p=0, q=0, dtype="f64")
+    g = synth.generate(cfg)
+    Zd = torch.from_numpy(np.ascontiguousarray(g.Z.T)).cuda()
+    with pytest.raises(dmd.DMDError) as ei:
+        dmd.fit(Zd, 8, p=0, q=0, precision="fp64_exact", rank_tol=1e-8)
+    assert ei.value.code == 6
+    # non-finite input, checked on request
+    Zn = torch.randn((40, 4000), dtype=torch.float64, device="cuda")
+    Zn[3, 17] = float("nan")
+    with pytest.raises(dmd.DMDError) as ei:
+        dmd.fit(Zn, 4, p=0, q=0, precision="fp64_exact", check_finite=True)
+    assert ei.value.code == 4
+
+
+def test_rank_deficient_sketch_reports_or_recovers(gpu_lib):
+    """Noise-free rank-16 data with l = 26: CholeskyQR breaks down; the shifted retry
+    either recovers (status 0, info[3] > 0) or the call reports breakdown; it never
+    returns silently non-finite eigenvalues."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.Config("rd", (2, 48, 48), 60, 8, 0.95, 0.0, 41, r=16, p=10, q=1, jitter=True)
+    _print("case: rank-deficient sketch")
+    g = synth.generate(cfg)
+    try:
+        m, Z = _gpu_fit(g, cfg, "mixed")
+        assert np.all(np.isfinite(m.lam_host()))
+        truth = np.concatenate([g.lam, np.conj(g.lam)])
+        e = oracle.eig_errors(m.lam_host(), truth)
+        _print(f"  recovered: lambda max {e['max_rel']:.3e}, shifted retries {int(m.info[3].item())}")
+        assert e["max_rel"] <= 1e-4
+    except dmd.DMDError as err:
+        _print(f"  reported: {err}")
+        assert err.code == 5
+
+
+def test_fit_deterministic(gpu_lib):
+    cfg = _small_randomized_cfg(seed=213)
+    _print("case: bitwise-repeatable fit")
+    g = synth.generate(cfg)
+    m1, _ = _gpu_fit(g, cfg, "mixed")
+    m2, _ = _gpu_fit(g, cfg, "mixed")
+    assert torch.equal(m1.phi, m2.phi) and torch.equal(m1.lam, m2.lam) and torch.equal(m1.b, m2.b)
+
+
+def test_batched_graph_matches_single_fits(gpu_lib):
+    """Uneven scenes fitted in one captured graph, replayed three times with eager work
+    and synchronisation in between: every replay equals the single-call fits bitwise."""
+    import paper_2502_05339_amd as dmd
+    _print("case: batched fit graph (3 scenes)")
+    scenes, singles = [], []
+    for i, (N, m_) in enumerate([(20000, 60), (7777, 45), (33000, 80)]):
+        cfg = synth.Config(f"s{i}", (N,), m_, 12, 0.95, 1e-4, 600 + i, r=24, p=6, q=1)
+        g = synth.generate(cfg)
+        m1, Z = _gpu_fit(g, cfg, "mixed")
+        singles.append(m1)
+        om = torch.from_numpy(np.ascontiguousarray(g.Omega.T)).cuda()
+        scenes.append(dict(Z=Z, r=cfg.r, p=cfg.p, q=cfg.q, omega=om))
+    bf = dmd.BatchedFit(scenes, capture=True)
+    for rep in range(3):
+        for mm in bf.models:
+            mm.phi.zero_()
+            mm.lam.zero_()
+        bf.launch()
+        torch.cuda.synchronize()
+        _ = torch.randn(1000, device="cuda").sum().item()
+        assert bf.statuses() == [0, 0, 0]
+        for a, b in zip(bf.models, singles):
+            assert torch.equal(a.lam, b.lam) and torch.equal(a.phi, b.phi) and torch.equal(a.b, b.b)
+    bf.close()
