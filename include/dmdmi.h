@@ -130,7 +130,7 @@ typedef struct dmd_model {
     double dt;        /* time step of the snapshots */
     void* phi;        /* N x ldphi, ROW-major (the r mode values of a grid point are
                          contiguous), folded real storage; columns r..ldphi-1 are zero */
-    int64_t ldphi;    /* >= dmd_phi_ld(r) */
+    int64_t ldphi;    /* >= dmd_phi_ld(r), a multiple of 32, at most 192 */
     double* lam;      /* r complex eigenvalues, interleaved (re, im) */
     double* b;        /* r complex amplitudes, interleaved (re, im) */
     double* sigma;    /* r singular values kept by the fit (written by dmd_fit) */
@@ -206,6 +206,20 @@ int32_t dmd_reconstruct(void* stream, const dmd_model* model, const int64_t* k_h
                         size_t ws_bytes);
 
 /*
+ * The two halves of dmd_reconstruct, for callers that evaluate one exponent list
+ * many times (the coefficients depend only on lambda, b and the exponents):
+ *   prepare: exponents (k_host integers, or t_host / dt when k_host is NULL) and the
+ *            FP64 coefficients b lambda^e, packed for `mode`, into the workspace;
+ *   apply:   the reconstruction GEMM from a workspace filled by prepare with the
+ *            same model, K and mode (nothing is checked across the two calls).
+ */
+int32_t dmd_reconstruct_prepare(void* stream, const dmd_model* model, const int64_t* k_host,
+                                const double* t_host, int32_t K, int32_t mode, void* ws,
+                                size_t ws_bytes);
+int32_t dmd_reconstruct_apply(void* stream, const dmd_model* model, int32_t K, int32_t mode,
+                              void* U, int64_t ldu, void* ws, size_t ws_bytes);
+
+/*
  * U[:, j] = Re( Phi exp(Omega t_j) b ), Omega = Log(Lambda) / dt (Sec. 6.1,
  * eq. edit_temporal), principal branch, for real times t_host[0..T-1].
  * Same layout, modes and workspace as dmd_reconstruct (K = T).
@@ -251,8 +265,9 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam,
  * stream (default priority) joined back into `stream`, so the latency-bound
  * small-matrix stages of different scenes overlap.  With capture != 0 the whole
  * batch is captured once into a HIP graph returned in *graph (nothing runs until
- * dmd_graph_launch); otherwise it is enqueued directly.  Scenes must use
- * DMD_FIT_ASYNC semantics (statuses land in each model's info[0]).
+ * dmd_graph_launch); capture needs a created stream (the null stream is refused
+ * with DMD_ERR_ARG).  Without capture the batch runs and the call waits for it.
+ * Scenes use DMD_FIT_ASYNC semantics (statuses land in each model's info[0]).
  */
 int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes,
                         dmd_model* models, int32_t capture, dmd_graph** graph);

@@ -4,10 +4,11 @@ The compute runs in libdmdmi.so (hand-written HIP kernels for gfx950); this
 package is the thin Python binding.  See include/dmdmi.h for the C ABI.
 """
 from ._lib import DMDError, lib, status_string
-from .api import (BatchedFit, DMDLoss, Model, autotune_reconstruct, fit, fit_opts, integrate, loss_grad,
-                  project, reconstruct, refit)
+from .api import (BatchedFit, DMDLoss, Model, PreparedReconstruction, autotune_reconstruct, fit, fit_opts,
+                  integrate, loss_grad, project, reconstruct, refit)
 
 __all__ = [
-    "DMDError", "lib", "status_string", "BatchedFit", "DMDLoss", "Model", "autotune_reconstruct", "fit",
+    "DMDError", "lib", "status_string", "BatchedFit", "DMDLoss", "Model", "PreparedReconstruction",
+    "autotune_reconstruct", "fit",
     "fit_opts", "integrate", "loss_grad", "project", "reconstruct", "refit",
 ]

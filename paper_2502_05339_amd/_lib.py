@@ -63,6 +63,10 @@ _SIGS = {
     "dmd_reconstruct_workspace_size": (c_int32, [c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
     "dmd_reconstruct": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_int64), c_int32,
                                   c_int32, c_void_p, c_int64, c_void_p, c_size_t]),
+    "dmd_reconstruct_prepare": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_int64),
+                                          ctypes.POINTER(c_double), c_int32, c_int32, c_void_p, c_size_t]),
+    "dmd_reconstruct_apply": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_int32, c_int32, c_void_p, c_int64,
+                                        c_void_p, c_size_t]),
     "dmd_integrate": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_double), c_int32,
                                 c_int32, c_void_p, c_int64, c_void_p, c_size_t]),
     "dmd_project_workspace_size": (c_int32, [c_int64, c_int32, ctypes.POINTER(c_size_t)]),

@@ -273,6 +273,41 @@ def reconstruct(model: Model, ks, mode: str | None = None, out: torch.Tensor | N
     return out
 
 
+class PreparedReconstruction:
+    """Coefficients b lambda^k for one exponent list, kept in a private workspace so
+    that the reconstruction GEMM can be replayed (dmd_reconstruct_prepare / _apply)."""
+
+    def __init__(self, model: Model, ks=None, ts=None, mode: str | None = None):
+        _require_gpu(model.phi, "model.phi")
+        self.model = model
+        self.mode = mode or _default_mode(model)
+        self.mcode = RECON_MODES[self.mode]
+        L = _lib.lib()
+        if ks is not None:
+            self._k = np.ascontiguousarray(np.asarray(ks, dtype=np.int64).ravel())
+            kp, tp, K = self._k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), None, self._k.size
+        else:
+            self._t = np.ascontiguousarray(np.asarray(ts, dtype=np.float64).ravel())
+            kp, tp, K = None, self._t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self._t.size
+        self.K = K
+        nb = ctypes.c_size_t(0)
+        check(L.dmd_reconstruct_workspace_size(model.r, K, self.mcode, ctypes.byref(nb)), "workspace")
+        self.ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=model.phi.device)
+        ms = model.struct()
+        check(L.dmd_reconstruct_prepare(_stream(), ctypes.byref(ms), kp, tp, K, self.mcode, self.ws.data_ptr(),
+                                        self.ws.numel()), "dmd_reconstruct_prepare")
+
+    def apply(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        odt = torch.float64 if self.mcode == RECON_FP64 else torch.float32
+        if out is None:
+            out = torch.empty((self.K, self.model.n), dtype=odt, device=self.model.phi.device)
+        ms = self.model.struct()
+        check(_lib.lib().dmd_reconstruct_apply(_stream(), ctypes.byref(ms), self.K, self.mcode, out.data_ptr(),
+                                               out.stride(0), self.ws.data_ptr(), self.ws.numel()),
+              "dmd_reconstruct_apply")
+        return out
+
+
 def integrate(model: Model, ts, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
     """U[j] = Re(Phi exp(Omega t_j) b), Omega = Log(Lambda)/dt (Sec. 6.1)."""
     _require_gpu(model.phi, "model.phi")
@@ -327,8 +362,8 @@ def loss_grad(model: Model, lam: torch.Tensor, b: torch.Tensor, X: torch.Tensor,
                          ws.numel())
     check(st, "dmd_loss_grad")
     r = model.r
-    gl = torch.view_as_complex(out[1:1 + 2 * r].view(r, 2))
-    gb = torch.view_as_complex(out[1 + 2 * r:].view(r, 2))
+    gl = torch.view_as_complex(out[1:1 + 2 * r].clone().view(r, 2))
+    gb = torch.view_as_complex(out[1 + 2 * r:].clone().view(r, 2))
     return out[0], gl, gb
 
 
@@ -402,16 +437,26 @@ class BatchedFit:
             self._ms[i] = m.struct()
         self.graph = ctypes.c_void_p(0)
         self.capture = capture
-        if capture:
-            check(L.dmd_fit_batched(_stream(), n, self._sc, self._ms, 1, ctypes.byref(self.graph)),
-                  "dmd_fit_batched")
-        else:
-            check(L.dmd_fit_batched(_stream(), n, self._sc, self._ms, 0, None), "dmd_fit_batched")
+        # capture and replay on a stream of our own (default priority): the legacy null
+        # stream cannot be captured
+        self.stream = torch.cuda.Stream(device=scenes[0]["Z"].device)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(self.stream):
+            if capture:
+                check(L.dmd_fit_batched(_stream(), n, self._sc, self._ms, 1, ctypes.byref(self.graph)),
+                      "dmd_fit_batched")
+            else:
+                check(L.dmd_fit_batched(_stream(), n, self._sc, self._ms, 0, None), "dmd_fit_batched")
+        torch.cuda.current_stream().wait_stream(self.stream)
 
     def launch(self):
+        """Replay the captured batch, ordered after the caller's current stream."""
         if not self.capture:
             raise RuntimeError("not captured")
-        check(_lib.lib().dmd_graph_launch(self.graph, _stream()), "dmd_graph_launch")
+        cur = torch.cuda.current_stream()
+        self.stream.wait_stream(cur)
+        check(_lib.lib().dmd_graph_launch(self.graph, self.stream.cuda_stream), "dmd_graph_launch")
+        cur.wait_stream(self.stream)
 
     def statuses(self):
         return [int(m.info[0].item()) for m in self.models]

@@ -333,18 +333,25 @@ void lib_init()
     if (c && *c) load_cache(c);
 }
 
-int32_t recon_enqueue(hipStream_t st, const dmd_model* m, const int64_t* k_host, const double* t_host,
-                      int K, int mode, void* U, int64_t ldu, void* ws, size_t ws_bytes, int cfg_override)
+int32_t recon_validate(const dmd_model* m, int K, int mode, size_t ws_bytes, const void* ws)
 {
     if (int32_t e = validate_model(m)) return e;
     if (K < 1) return DMD_ERR_SHAPE;
     if (mode < DMD_RECON_FP64 || mode > DMD_RECON_BF16X3) return DMD_ERR_ARG;
     if ((mode == DMD_RECON_FP64) != (m->dtype == DMD_F64)) return DMD_ERR_ARG;
-    if (!U || ldu < m->n) return DMD_ERR_ARG;
-    if (!k_host && !t_host) return DMD_ERR_ARG;
     Carver dry(nullptr);
     recon_carve(dry, m->r, K, mode);
     if (!ws || ws_bytes < dry.bytes()) return DMD_ERR_WORKSPACE;
+    return DMD_OK;
+}
+
+// exponents + packed coefficients into the workspace
+int32_t recon_prepare(hipStream_t st, const dmd_model* m, const int64_t* k_host, const double* t_host, int K,
+                      int mode, void* ws, size_t ws_bytes)
+{
+    if (!k_host && !t_host) return DMD_ERR_ARG;
+    if (int32_t e = recon_validate(m, K, mode, ws_bytes, ws)) return e;
+    if (!k_host && !(m->dt > 0.0)) return DMD_ERR_ARG;
     std::call_once(g_init_once, lib_init);
     Carver cv(ws);
     ReconPlan p = recon_carve(cv, m->r, K, mode);
@@ -358,6 +365,19 @@ int32_t recon_enqueue(hipStream_t st, const dmd_model* m, const int64_t* k_host,
         HIPCHK(exponents(st, nullptr, p.expo, 1.0 / m->dt, K, p.expo));
     }
     HIPCHK(powers_pack(st, m->lam, m->b, m->kind, m->r, p.expo, K, Kp, rp, mode, p.chi, p.clo));
+    return DMD_OK;
+}
+
+// the reconstruction GEMM from prepared coefficients
+int32_t recon_apply(hipStream_t st, const dmd_model* m, int K, int mode, void* U, int64_t ldu, void* ws,
+                    size_t ws_bytes, int cfg_override)
+{
+    if (int32_t e = recon_validate(m, K, mode, ws_bytes, ws)) return e;
+    if (!U || ldu < m->n) return DMD_ERR_ARG;
+    std::call_once(g_init_once, lib_init);
+    Carver cv(ws);
+    ReconPlan p = recon_carve(cv, m->r, K, mode);
+    const int rp = (int)dmd_phi_ld(m->r);
     ReconArgs ra{};
     ra.mode = mode;
     ra.phi = m->phi; ra.ldphi = m->ldphi; ra.N = m->n; ra.rp = rp;
@@ -368,6 +388,15 @@ int32_t recon_enqueue(hipStream_t st, const dmd_model* m, const int64_t* k_host,
     const int cfg = cfg_override >= 0 ? cfg_override : tune_lookup(mode, rp, m->n, K);
     HIPCHK(recon_launch(st, ra, cfg));
     return DMD_OK;
+}
+
+int32_t recon_enqueue(hipStream_t st, const dmd_model* m, const int64_t* k_host, const double* t_host,
+                      int K, int mode, void* U, int64_t ldu, void* ws, size_t ws_bytes, int cfg_override)
+{
+    if (int32_t e = recon_validate(m, K, mode, ws_bytes, ws)) return e;
+    if (!U || ldu < m->n) return DMD_ERR_ARG;
+    if (int32_t e = recon_prepare(st, m, k_host, t_host, K, mode, ws, ws_bytes)) return e;
+    return recon_apply(st, m, K, mode, U, ldu, ws, ws_bytes, cfg_override);
 }
 
 }  // namespace
@@ -453,6 +482,20 @@ int32_t dmd_reconstruct(void* stream, const dmd_model* model, const int64_t* k_h
 {
     if (!k_host) return DMD_ERR_ARG;
     return recon_enqueue((hipStream_t)stream, model, k_host, nullptr, K, mode, U, ldu, ws, ws_bytes, -1);
+}
+
+int32_t dmd_reconstruct_prepare(void* stream, const dmd_model* model, const int64_t* k_host, const double* t_host,
+                                int32_t K, int32_t mode, void* ws, size_t ws_bytes)
+{
+    for (int32_t j = 0; !k_host && t_host && j < K; ++j)
+        if (!isfinite(t_host[j])) return DMD_ERR_ARG;
+    return recon_prepare((hipStream_t)stream, model, k_host, t_host, K, mode, ws, ws_bytes);
+}
+
+int32_t dmd_reconstruct_apply(void* stream, const dmd_model* model, int32_t K, int32_t mode, void* U, int64_t ldu,
+                              void* ws, size_t ws_bytes)
+{
+    return recon_apply((hipStream_t)stream, model, K, mode, U, ldu, ws, ws_bytes, -1);
 }
 
 int32_t dmd_integrate(void* stream, const dmd_model* model, const double* t_host, int32_t T, int32_t mode,
@@ -579,6 +622,7 @@ int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes, 
 {
     if (nscenes < 1 || !scenes || !models) return DMD_ERR_ARG;
     if (capture && !graph) return DMD_ERR_ARG;
+    if (capture && !stream) return DMD_ERR_ARG;   // the legacy null stream cannot be captured
     for (int i = 0; i < nscenes; ++i) {
         const dmd_scene& sc = scenes[i];
         FitArgs a{sc.x, sc.xp, sc.n, sc.ncols, sc.ldx, sc.ldxp, sc.xdtype, sc.opts,
@@ -670,12 +714,13 @@ int32_t dmd_autotune_reconstruct(void* stream, const dmd_model* model, int32_t K
     int best = 0;
     float best_ms = 1e30f;
     int32_t status = DMD_OK;
+    status = recon_prepare(st, model, ks.data(), nullptr, K, mode, ws, ws_bytes);
     for (int cfg = 0; cfg < RECON_NCFG && status == DMD_OK; ++cfg) {
-        status = recon_enqueue(st, model, ks.data(), nullptr, K, mode, U, ldu, ws, ws_bytes, cfg);   // warm-up
+        status = recon_apply(st, model, K, mode, U, ldu, ws, ws_bytes, cfg);   // warm-up
         if (status) break;
         hipEventRecord(e0, st);
         for (int rep = 0; rep < 3 && status == DMD_OK; ++rep)
-            status = recon_enqueue(st, model, ks.data(), nullptr, K, mode, U, ldu, ws, ws_bytes, cfg);
+            status = recon_apply(st, model, K, mode, U, ldu, ws, ws_bytes, cfg);
         hipEventRecord(e1, st);
         if (hipEventSynchronize(e1) != hipSuccess) { status = DMD_ERR_HIP; break; }
         float ms = 0.f;

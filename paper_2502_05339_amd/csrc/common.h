@@ -18,7 +18,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 // All three use the 16x16 output tile with the same lane layout:
 //   A operand: lane l supplies A[i = l % 16][k-group l / 16]
 //   B operand: lane l supplies B[k-group l / 16][j = l % 16]
-//   D:         lane l holds D[4 * (l / 16) + v][l % 16], v = 0..3
+//   D:         lane l holds D[acc_row(l, v)][l % 16], v = 0..3 (see acc_row)
 // For f32 / f64 the k-group is one k index (depth 4); for bf16 it is 8
 // consecutive k indices (depth 32).
 __device__ __forceinline__ floatx4 mfma_f32(float a, float b, floatx4 c) {
@@ -37,6 +37,13 @@ template <> struct Acc<double> { typedef doublex4 type; };
 
 __device__ __forceinline__ floatx4 mfma(float a, float b, floatx4 c) { return mfma_f32(a, b, c); }
 __device__ __forceinline__ doublex4 mfma(double a, double b, doublex4 c) { return mfma_f64(a, b, c); }
+
+// Row (within the 16x16 tile) of accumulator element v held by `lane`.  The f32
+// and bf16 16x16 instructions give lane l rows 4*(l/16)+v; the f64 16x16x4
+// instruction gives rows l/16 + 4v (columns are l % 16 for all three).
+template <typename V> __device__ __forceinline__ int acc_row(int lane, int v);
+template <> __device__ __forceinline__ int acc_row<floatx4>(int lane, int v) { return 4 * (lane >> 4) + v; }
+template <> __device__ __forceinline__ int acc_row<doublex4>(int lane, int v) { return (lane >> 4) + 4 * v; }
 
 template <typename V> __device__ __forceinline__ V zero_acc() {
     V z;

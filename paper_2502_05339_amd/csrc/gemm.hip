@@ -121,25 +121,26 @@ gemm_nn_kernel(const T* A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     // ---- epilogue
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-        const int64_t rbase = row0 + wave * 16 * RB + rb * 16 + 4 * (lane >> 4);
+        const int64_t tile0 = row0 + wave * 16 * RB + rb * 16;
 #pragma unroll
         for (int cb = 0; cb < NBW; ++cb) {
             if (cb >= ncb) continue;
             const int col = cb * 16 + (lane & 15);
             if (col >= n) continue;
-            if (c_rowmajor) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (rbase + v < N) C[(rbase + v) * ldc + col] = acc[rb][cb][v];
-            } else {
-                T* dst = C + (int64_t)col * ldc + rbase;
-                if (VEC && sizeof(T) == 4 && rbase + 4 <= N) {
+            if constexpr (sizeof(T) == 4) {
+                const int64_t rbase = tile0 + 4 * (lane >> 4);     // 4 consecutive rows
+                if (!c_rowmajor && VEC && rbase + 4 <= N) {
                     float4 o = make_float4(acc[rb][cb][0], acc[rb][cb][1], acc[rb][cb][2], acc[rb][cb][3]);
-                    *reinterpret_cast<float4*>(dst) = o;
-                } else {
+                    *reinterpret_cast<float4*>(C + (int64_t)col * ldc + rbase) = o;
+                    continue;
+                }
+            }
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (rbase + v < N) dst[v] = acc[rb][cb][v];
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = tile0 + acc_row<V>(lane, v);
+                if (row < N) {
+                    if (c_rowmajor) C[row * ldc + col] = acc[rb][cb][v];
+                    else C[(int64_t)col * ldc + row] = acc[rb][cb][v];
                 }
             }
         }
@@ -294,7 +295,7 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
             const int j = boff[t] + (lane & 15);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = aoff[t] + 4 * (lane >> 4) + v;
+                const int i = aoff[t] + acc_row<V>(lane, v);
                 if (i < ka && j < nb) out[(int64_t)j * ka + i] = (double)acc[t][v];
             }
         }

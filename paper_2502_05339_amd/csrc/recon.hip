@@ -239,47 +239,55 @@ recon_kernel(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi
                         }
                     }
                 }
-                // ---- epilogue: lane holds rows 4*lg..4*lg+3 of frame cb*16 + l16
+                // ---- epilogue: lane holds rows acc_row(lane, v) of frame cb*16 + l16
                 const int frame = f0 + cb * 16 + l16;
                 if (frame < f_end) {
 #pragma unroll
                     for (int rb = 0; rb < RBW; ++rb) {
-                        const int64_t row = tile_row0 + rb * 16 + 4 * lg;
-                        if (row >= N) continue;
-                        Tout* dst = U + (int64_t)frame * ldu + row;
-                        Tout o[4];
+                        const int64_t tile0 = tile_row0 + rb * 16;
+                        if constexpr (sizeof(Tout) == 4) {
+                            // f32 / bf16 accumulators: 4 consecutive rows per lane
+                            const int64_t row = tile0 + 4 * lg;
+                            if (row >= N) continue;
+                            Tout* dst = U + (int64_t)frame * ldu + row;
+                            Tout o[4];
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) o[v] = (Tout)acc[rb][v];
-                        if constexpr (RESID) {
-                            const Tout* src = Xt + (int64_t)frame * ldxt + row;
+                            for (int v = 0; v < 4; ++v) o[v] = (Tout)acc[rb][v];
+                            if constexpr (RESID) {
+                                const Tout* src = Xt + (int64_t)frame * ldxt + row;
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                if (row + v < N) {
-                                    o[v] = src[v] - o[v];
-                                    ss += (double)o[v] * (double)o[v];
+                                for (int v = 0; v < 4; ++v) {
+                                    if (row + v < N) {
+                                        o[v] = src[v] - o[v];
+                                        ss += (double)o[v] * (double)o[v];
+                                    }
                                 }
                             }
-                        }
-                        if (vec_store && row + 4 <= N) {
-                            if constexpr (sizeof(Tout) == 4) {
+                            if (vec_store && row + 4 <= N) {
                                 floatx4 w = {o[0], o[1], o[2], o[3]};
                                 if constexpr (RESID) *reinterpret_cast<floatx4*>(dst) = w;
                                 else __builtin_nontemporal_store(w, reinterpret_cast<floatx4*>(dst));
                             } else {
-                                typedef double doublex2 __attribute__((ext_vector_type(2)));
-                                doublex2 w0 = {(double)o[0], (double)o[1]}, w1 = {(double)o[2], (double)o[3]};
-                                if constexpr (RESID) {
-                                    reinterpret_cast<doublex2*>(dst)[0] = w0;
-                                    reinterpret_cast<doublex2*>(dst)[1] = w1;
-                                } else {
-                                    __builtin_nontemporal_store(w0, reinterpret_cast<doublex2*>(dst));
-                                    __builtin_nontemporal_store(w1, reinterpret_cast<doublex2*>(dst) + 1);
-                                }
+#pragma unroll
+                                for (int v = 0; v < 4; ++v)
+                                    if (row + v < N) dst[v] = o[v];
                             }
                         } else {
+                            // f64 accumulators: rows lg, lg + 4, lg + 8, lg + 12
 #pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                if (row + v < N) dst[v] = o[v];
+                            for (int v = 0; v < 4; ++v) {
+                                const int64_t row = tile0 + acc_row<V>(lane, v);
+                                if (row >= N) continue;
+                                Tout o = (Tout)acc[rb][v];
+                                Tout* dst = U + (int64_t)frame * ldu + row;
+                                if constexpr (RESID) {
+                                    o = Xt[(int64_t)frame * ldxt + row] - o;
+                                    ss += (double)o * (double)o;
+                                    *dst = o;
+                                } else {
+                                    __builtin_nontemporal_store(o, dst);
+                                }
+                            }
                         }
                     }
                 }
