@@ -156,6 +156,9 @@ def main():
     m = step()
     torch.cuda.synchronize()
     st = int(m.info[0].item())
+    info = m.info.cpu().tolist()
+    print(f"# fit info: status {info[0]}, Jacobi sweeps {info[1]}, Francis iterations {info[2]}, "
+          f"shifted CholeskyQR retries {info[3]}", file=sys.stderr, flush=True)
     if st != 0:
         print(json.dumps({"error": f"fit status {st}: {dmd.status_string(st)}"}), flush=True)
         sys.exit(1)

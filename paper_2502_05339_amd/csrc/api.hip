@@ -113,6 +113,11 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
     const int64_t ldphi = model ? model->ldphi : dmd_phi_ld(r);
     const int64_t ldy = round_up(n, 4);
     const double u = 1.1102230246251565e-16;
+    // Convergence of the FP64 small factors: full FP64 accuracy on the FP64 paths; on the
+    // mixed path (FP32 data, 1e-5 eigenvalue target) 1e-13 relative is 8 orders below the
+    // data's own rounding, and saves the last Jacobi sweeps and QR iterations.
+    const double jac_tol = mixed ? 1e-13 : 4.5e-16;
+    const double defl_tol = mixed ? 1e-13 : 2.220446049250313e-16;
 
     int32_t* flags = cv.take<int32_t>(16);
     int32_t* info = model ? model->info : nullptr;
@@ -136,6 +141,9 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
     double* PhiG = cv.take<double>((size_t)r * r);
     double* rhs = cv.take<double>((size_t)r);
     double* RinvPhi = cv.take<double>((size_t)r * r);
+    double* beta = cv.take<double>((size_t)r);
+    double* rhs2 = cv.take<double>((size_t)r);
+    void* res = cv.take<char>((size_t)n * esize(fdt));
     void* eigws = cv.take<char>(eig_workspace_bytes(r));
     double* Gxp2 = (exact && !shifted) ? cv.take<double>((size_t)mm * mm) : nullptr;
     void* Y = nullptr;
@@ -170,10 +178,13 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
         const int cdt = mixed ? DMD_F32 : DMD_F64;   // MFMA type of the streaming products
         // CholeskyQR2 of an N x l (or mm x l) matrix in place, with a shifted first pass
         // on breakdown and then a conditional third pass (shifted CholeskyQR3).
-        auto cholqr = [&](void* Yb, int64_t ld, int64_t rows, int dtype, int32_t* flag) -> int32_t {
+        // `two` = false: a single pass (an intermediate basis of the power iteration only
+        // has to be well conditioned; the next pass re-orthonormalises it)
+        auto cholqr = [&](void* Yb, int64_t ld, int64_t rows, int dtype, int32_t* flag, bool two) -> int32_t {
             HIPCHK(fill_i32(st, flag, 1, 0));
             const double shift_scale = 11.0 * ((double)rows * l + (double)l * (l + 1)) * u;
             for (int pass = 0; pass < 3; ++pass) {
+                if (pass == 1 && !two) break;
                 const int32_t* skip = pass == 2 ? flag : nullptr;
                 HIPCHK(gemm_tn(st, dtype, DMD_F64, Yb, ld, 0, l, Yb, ld, 0, l, 1, rows, P, G, l, nullptr, 0, skip));
                 HIPCHK(chol_inv(st, G, l, l, Rinv, l, dtype == DMD_F32 ? Rinv32 : nullptr, l,
@@ -185,15 +196,15 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
         };
         // sketch Y = X Omega (Sec. 4.3)
         HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, o.omega, mm, Y, ldy, 0, n, mm, l, nullptr));
-        if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 0)) return e;
+        if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 0, o.q == 0)) return e;
         // power iterations: W = orth(X^T Q), Y = X W, Q = orth(Y)
         for (int it = 0; it < o.q; ++it) {
             HIPCHK(gemm_tn(st, fdt, cdt, a.x, a.ldx, 0, mm, Y, ldy, 0, l, 0, n, P, Wt, mm, nullptr, 0, nullptr));
-            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 1)) return e;
+            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 1, false)) return e;
             if (fdt == DMD_F32) HIPCHK(to_f32(st, mm, l, l, Wt, mm, (float*)Wtf, mm));
             else HIPCHK(copy_f64(st, mm, l, l, Wt, mm, (double*)Wtf, mm));
             HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, Wtf, mm, Y, ldy, 0, n, mm, l, nullptr));
-            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 2)) return e;
+            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 2, it == o.q - 1)) return e;
         }
         // projection B = Q^T X, B' = Q^T X' (one pass over Z when X' is the shifted view)
         if (shifted) {
@@ -204,7 +215,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
         }
         // SVD of B through the Jacobi eigen-decomposition of B B^T
         HIPCHK(small_gemm(st, 0, 1, l, l, mm, 1.0, Bx, l, Bx, l, 0.0, G, l));
-        HIPCHK(sym_eig(st, G, l, l, evals, Ueig, info));
+        HIPCHK(sym_eig(st, G, l, l, evals, Ueig, info, jac_tol));
         HIPCHK(sigma_from_evals(st, evals, r, o.rank_tol, sigma, model->sigma, info));
         // Vs = V_r S_r^-1 = B^T U_r S_r^-2
         HIPCHK(small_gemm(st, 1, 0, mm, r, l, 1.0, Bx, l, Ueig, l, 0.0, Vs, mm));
@@ -231,7 +242,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
             Gxp = Gxp2;
             ldg = mm;
         }
-        HIPCHK(sym_eig(st, Gxx, ldg, mm, evals, Ueig, info));
+        HIPCHK(sym_eig(st, Gxx, ldg, mm, evals, Ueig, info, jac_tol));
         HIPCHK(sigma_from_evals(st, evals, r, o.rank_tol, sigma, model->sigma, info));
         HIPCHK(copy_f64(st, mm, r, r, Ueig, mm, Vs, mm));
         HIPCHK(scale_cols(st, mm, r, Vs, mm, sigma, 1));
@@ -241,7 +252,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
         HIPCHK(small_gemm(st, 1, 0, r, r, mm, 1.0, Vs, mm, T2, mm, 0.0, At, r));
     }
     // eigen-decomposition, canonical order, folded eigenvectors
-    HIPCHK(nonsym_eig(st, At, r, r, eigws, model->lam, model->kind, W, info));
+    HIPCHK(nonsym_eig(st, At, r, r, eigws, model->lam, model->kind, W, info, defl_tol));
     // exact modes Phi = X' V_r S_r^-1 W
     HIPCHK(small_gemm(st, 0, 0, mm, r, r, 1.0, Vs, mm, W, r, 0.0, M, mm));
     if (fdt == DMD_F32) HIPCHK(to_f32(st, mm, r, (int)ldphi, M, mm, (float*)Mf, mm));
@@ -252,7 +263,14 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
     HIPCHK(gemm_tn(st, fdt, DMD_F64, model->phi, ldphi, 1, r, a.x, a.ldx, 0, 1, 0, n, P, rhs, r, nullptr, 0, nullptr));
     HIPCHK(chol_inv(st, PhiG, r, r, RinvPhi, r, nullptr, 0, 11.0 * ((double)n * r + (double)r * (r + 1)) * u,
                     flags + 3, info, nullptr));
-    HIPCHK(amplitudes(st, r, RinvPhi, r, rhs, model->kind, model->b));
+    HIPCHK(normal_solve(st, r, RinvPhi, r, rhs, beta, 0));
+    if (fdt == DMD_F64) {
+        // one step of iterative refinement: beta += G^-1 Phi^T (x0 - Phi beta)
+        HIPCHK(residual(st, fdt, n, r, model->phi, ldphi, beta, a.x, res));
+        HIPCHK(gemm_tn(st, fdt, DMD_F64, model->phi, ldphi, 1, r, res, n, 0, 1, 0, n, P, rhs2, r, nullptr, 0, nullptr));
+        HIPCHK(normal_solve(st, r, RinvPhi, r, rhs2, beta, 1));
+    }
+    HIPCHK(beta_to_b(st, r, beta, model->kind, model->b));
     return DMD_OK;
 }
 
@@ -518,6 +536,9 @@ int32_t dmd_project_workspace_size(int64_t n, int32_t r, size_t* bytes)
     c.take<double>((size_t)r);
     c.take<double>((size_t)r * r);
     c.take<int32_t>(16);
+    c.take<double>((size_t)r);
+    c.take<double>((size_t)r);
+    c.take<double>((size_t)n);
     *bytes = c.bytes();
     return DMD_OK;
 }
@@ -539,13 +560,23 @@ int32_t dmd_project(void* stream, const dmd_model* model, const void* u, double*
     double* rhs = cv.take<double>((size_t)r);
     double* Rinv = cv.take<double>((size_t)r * r);
     int32_t* scratch = cv.take<int32_t>(16);
+    double* beta = cv.take<double>((size_t)r);
+    double* rhs2 = cv.take<double>((size_t)r);
+    void* res = cv.take<double>((size_t)n);
     HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, model->phi, model->ldphi, 1, r, 1, n,
                    P, PhiG, r, nullptr, 0, nullptr));
     HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, u, n, 0, 1, 0, n, P, rhs, r, nullptr,
                    0, nullptr));
     HIPCHK(fill_i32(st, scratch, 16, 0));
     HIPCHK(chol_inv(st, PhiG, r, r, Rinv, r, nullptr, 0, 0.0, nullptr, scratch, nullptr));
-    HIPCHK(amplitudes(st, r, Rinv, r, rhs, model->kind, z));
+    HIPCHK(normal_solve(st, r, Rinv, r, rhs, beta, 0));
+    if (model->dtype == DMD_F64) {   // one step of iterative refinement
+        HIPCHK(residual(st, model->dtype, n, r, model->phi, model->ldphi, beta, u, res));
+        HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, res, n, 0, 1, 0, n, P, rhs2, r,
+                       nullptr, 0, nullptr));
+        HIPCHK(normal_solve(st, r, Rinv, r, rhs2, beta, 1));
+    }
+    HIPCHK(beta_to_b(st, r, beta, model->kind, z));
     return DMD_OK;
 }
 

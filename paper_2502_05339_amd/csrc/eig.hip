@@ -63,93 +63,164 @@ static EigWs eig_carve(void* ws, int n)
 }
 
 // ====================================================================== 1. Hessenberg
-__global__ void __launch_bounds__(1024)
-hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, double* V, double* tau)
+// One Householder step k on H (accessor `h(i, j)` over column-major storage):
+//   v: reflector of H[k+1.., k];  H <- P H P with P = I - tau v v^T.
+// Left update (rows k+1.., columns k+1..): one wave per column.  Right update (all
+// rows, columns k+1..): the row products are split over 4 thread quarters, each
+// taking every fourth column (coalesced column-major reads), partial sums via LDS.
+template <typename Acc>
+__device__ void hess_step(Acc h, int k, int n, double* vs, double* part, double* red, double* sh,
+                          double* V, double* tau)
 {
-    __shared__ double sh_beta, sh_tau, sh_scale;
-    __shared__ double red[16];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-    for (int64_t e = tid; e < (int64_t)n * n; e += blockDim.x) {
-        const int i = (int)(e % n), j = (int)(e / n);
-        H[e] = A[(int64_t)j * lda + i];
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    double p2 = 0.0;
+    for (int i = k + 2 + tid; i < n; i += nt) { const double x = h(i, k); p2 += x * x; }
+    p2 = wave_sum(p2);
+    if (lane == 0) red[wave] = p2;
+    __syncthreads();
+    if (tid == 0) {
+        double xn2 = 0.0;
+        for (int w = 0; w < nw; ++w) xn2 += red[w];
+        const double alpha = h(k + 1, k);
+        if (xn2 == 0.0) { sh[0] = 0.0; sh[1] = alpha; sh[2] = 0.0; }
+        else {
+            const double nrm = sqrt(alpha * alpha + xn2);
+            const double beta = alpha >= 0.0 ? -nrm : nrm;
+            sh[0] = (beta - alpha) / beta;
+            sh[1] = beta;
+            sh[2] = 1.0 / (alpha - beta);
+        }
+    }
+    __syncthreads();
+    const double tk = sh[0], sc = sh[2];
+    for (int i = k + 1 + tid; i < n; i += nt) {
+        const double v = (i == k + 1) ? 1.0 : h(i, k) * sc;
+        vs[i] = v;
+        V[(int64_t)k * n + i] = v;
+    }
+    __syncthreads();
+    if (tk != 0.0) {
+        // left: H[k+1.., j] -= tau v (v^T H[k+1.., j])
+        for (int j = k + 1 + wave; j < n; j += nw) {
+            double d = 0.0;
+            for (int i = k + 1 + lane; i < n; i += 64) d += vs[i] * h(i, j);
+            d = wave_sum(d) * tk;
+            for (int i = k + 1 + lane; i < n; i += 64) h(i, j) -= d * vs[i];
+        }
+        __syncthreads();
+        // right: H[i, k+1..] -= tau (H[i, k+1..] v) v^T for all rows i
+        const int q4 = tid >> 8, i0 = tid & 255;          // 4 quarters x 256 rows
+        for (int i = i0; i < n; i += 256) {
+            double d = 0.0;
+            for (int j = k + 1 + q4; j < n; j += 4) d += h(i, j) * vs[j];
+            part[q4 * n + i] = d;
+        }
+        __syncthreads();
+        for (int i = i0; i < n; i += 256) {
+            const double d = (part[i] + part[n + i] + part[2 * n + i] + part[3 * n + i]) * tk;
+            for (int j = k + 1 + q4; j < n; j += 4) h(i, j) -= d * vs[j];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        tau[k] = tk;
+        if (tk != 0.0) h(k + 1, k) = sh[1];
+    }
+    for (int i = k + 2 + tid; i < n; i += nt) h(i, k) = 0.0;
+    __syncthreads();
+}
+
+struct GAcc {
+    double* p; int n;
+    __device__ __forceinline__ double& operator()(int i, int j) const { return p[(int64_t)j * n + i]; }
+};
+struct LAcc {   // columns jbase..n-1 in LDS
+    double* p; int n; int jbase;
+    __device__ __forceinline__ double& operator()(int i, int j) const { return p[(j - jbase) * n + i]; }
+};
+
+__global__ void __launch_bounds__(1024)
+hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, double* V, double* tau, int jbase)
+{
+    extern __shared__ double hsm[];
+    double* vs = hsm;                 // n
+    double* part = vs + n;            // 4n
+    double* red = part + 4 * n;       // 16
+    double* sh = red + 16;            // 4
+    double* Hl = sh + 4;              // n x (n - jbase)
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e % n, j = e / n;
+        const double a = A[(int64_t)j * lda + i];
+        if (jbase == 0) Hl[j * n + i] = a;   // everything fits in LDS
+        else H[e] = a;                       // global first; columns >= jbase move to LDS later
         V[e] = 0.0;
     }
-    for (int i = tid; i < n; i += blockDim.x) tau[i] = 0.0;
+    for (int i = tid; i < n; i += nt) tau[i] = 0.0;
     __syncthreads();
-    for (int k = 0; k + 2 < n; ++k) {
-        // reflector for x = H[k+1..n-1, k]
-        double part = 0.0;
-        for (int i = k + 2 + tid; i < n; i += blockDim.x) { const double v = H[(int64_t)k * n + i]; part += v * v; }
-        part = wave_sum(part);
-        if (lane == 0) red[wave] = part;
-        __syncthreads();
-        if (tid == 0) {
-            double xn2 = 0.0;
-            for (int w = 0; w < nw; ++w) xn2 += red[w];
-            const double alpha = H[(int64_t)k * n + k + 1];
-            if (xn2 == 0.0) {
-                sh_tau = 0.0; sh_beta = alpha; sh_scale = 0.0;
-            } else {
-                const double nrm = sqrt(alpha * alpha + xn2);
-                const double beta = alpha >= 0.0 ? -nrm : nrm;
-                sh_tau = (beta - alpha) / beta;
-                sh_scale = 1.0 / (alpha - beta);
-                sh_beta = beta;
-            }
+    GAcc g{H, n};
+    LAcc l{Hl, n, jbase};
+    // steps whose trailing columns do not fit in LDS run on global memory
+    for (int k = 0; k + 2 < n && k < jbase; ++k) hess_step(g, k, n, vs, part, red, sh, V, tau);
+    __syncthreads();
+    if (jbase > 0) {
+        // columns jbase.. were only touched by the global-memory steps in global memory
+        for (int e = tid; e < n * (n - jbase); e += nt) {
+            const int i = e % n, j = jbase + e / n;
+            Hl[(j - jbase) * n + i] = H[(int64_t)j * n + i];
         }
         __syncthreads();
-        const double tk = sh_tau, sc = sh_scale;
-        // v (v_0 = 1) into column k of V; H[k+1, k] = beta, below = 0
-        for (int i = k + 1 + tid; i < n; i += blockDim.x)
-            V[(int64_t)k * n + i] = (i == k + 1) ? 1.0 : H[(int64_t)k * n + i] * sc;
-        __syncthreads();
-        __threadfence_block();
-        if (tk != 0.0) {
-            const double* v = V + (int64_t)k * n;
-            // left: H[k+1.., j] -= tau v (v^T H[k+1.., j]),  j = k+1 .. n-1  (one wave per column)
-            for (int j = k + 1 + wave; j < n; j += nw) {
-                double* col = H + (int64_t)j * n;
-                double s = 0.0;
-                for (int i = k + 1 + lane; i < n; i += 64) s += v[i] * col[i];
-                s = wave_sum(s) * tk;
-                for (int i = k + 1 + lane; i < n; i += 64) col[i] -= s * v[i];
-            }
-            __syncthreads();
-            __threadfence_block();
-            // right: H[i, k+1..] -= tau (H[i, k+1..] v) v^T,  all rows  (one wave per row)
-            for (int i = wave; i < n; i += nw) {
-                double s = 0.0;
-                for (int j = k + 1 + lane; j < n; j += 64) s += H[(int64_t)j * n + i] * v[j];
-                s = wave_sum(s) * tk;
-                for (int j = k + 1 + lane; j < n; j += 64) H[(int64_t)j * n + i] -= s * v[j];
-            }
-            __syncthreads();
-            __threadfence_block();
-        }
-        if (tid == 0) {
-            tau[k] = tk;
-            if (tk != 0.0) H[(int64_t)k * n + k + 1] = sh_beta;
-        }
-        for (int i = k + 2 + tid; i < n; i += blockDim.x) H[(int64_t)k * n + i] = 0.0;
-        __syncthreads();
-        __threadfence_block();
+    }
+    for (int k = jbase; k + 2 < n; ++k) hess_step(l, k, n, vs, part, red, sh, V, tau);
+    __syncthreads();
+    for (int e = tid; e < n * (n - jbase); e += nt) {
+        const int i = e % n, j = jbase + e / n;
+        H[(int64_t)j * n + i] = Hl[(j - jbase) * n + i];
     }
 }
 
+static int hess_jbase(int n)
+{
+    const int budget = (160 * 1024 - 512) / 8 - (5 * n + 20);   // doubles left for columns
+    int cols = budget / n;
+    if (cols >= n) return 0;
+    return n - cols;
+}
+
 // ====================================================================== 2. Francis QR
-struct HP {   // packed Hessenberg with 3 sub-diagonals: column j holds rows 0..min(j+3, n-1)
+// Packed Hessenberg with 3 sub-diagonals: column j holds rows 0..min(j+3, n-1), i.e.
+// min(j+4, n) entries; the offset of column j is computed, not looked up.
+__host__ __device__ __forceinline__ int hp_col(int j, int n) {
+    if (n <= 4) return j * n;
+    if (j <= n - 3) return j * (j + 7) / 2;
+    return (n - 3) * (n + 4) / 2 + (j - (n - 3)) * n;
+}
+constexpr int CH = 32;                    // bulge-chase steps per delayed-update chunk
+// delayed-update tasks per thread: rows above + columns right (< n each) + Z rows, in
+// strips of 8 window columns, over 256 threads
+constexpr int DT = ((2 * DMD_MAX_RANK + 16) * ((CH + 4 + 7) / 8) + 255) / 256;
+
+struct HP {
     double* a;
-    const int* cs;
-    __device__ __forceinline__ double& operator()(int i, int j) const { return a[cs[j] + i]; }
+    int n;
+    __device__ __forceinline__ double& operator()(int i, int j) const { return a[hp_col(j, n) + i]; }
 };
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ __forceinline__ void house3(double x, double y, double z, double* v1, double* v2, double* tau, double* beta)
 {
     const double nrm = sqrt(x * x + y * y + z * z);
     if (nrm == 0.0 || (y == 0.0 && z == 0.0)) { *tau = 0.0; *v1 = 0.0; *v2 = 0.0; *beta = x; return; }
     const double b = x >= 0.0 ? -nrm : nrm;
-    *tau = (b - x) / b;
-    const double sc = 1.0 / (x - b);
+    const double d = x - b;                 // |d| >= |x|, never zero here
+    const double ibd = 1.0 / (b * d);       // one division gives 1/b and 1/d
+    *tau = -d * d * ibd;                    // (b - x) / b
+    const double sc = b * ibd;              // 1 / (x - b)
     *v1 = y * sc;
     *v2 = z * sc;
     *beta = b;
@@ -158,29 +229,24 @@ __device__ __forceinline__ void house3(double x, double y, double z, double* v1,
 __global__ void __launch_bounds__(256)
 francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __restrict__ Vg,
                const double* __restrict__ taug, double* Wraw, double* wr, double* wi, int32_t* kind0,
-               double* Xall, int32_t* info)
+               double* Xall, int32_t* info, double defl_tol)
 {
     extern __shared__ double sm[];
-    int* cs = reinterpret_cast<int*>(sm);                       // n + 1 ints
-    int* blk = cs + (n + 1);                                    // n ints
-    const int ioff = (int)round_up(2 * n + 1, 2) / 2;           // in doubles
+    int* blk = reinterpret_cast<int*>(sm);                      // n ints
+    const int ioff = (int)round_up(n, 2) / 2;                   // in doubles
     double* Hs = sm + ioff;
     __shared__ int sh_l, sh_stop, sh_iter_total;
     __shared__ double sh_v[4];   // rotation of a 2x2 block split
     __shared__ double sh_nxt[3]; // vector of the next bulge reflector
+    __shared__ int sh_lc[2];     // deflation search result (double-buffered)
     __shared__ double sh_red[4];
 
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-    if (tid == 0) {
-        int acc = 0;
-        for (int j = 0; j < n; ++j) { cs[j] = acc; acc += min(j + 4, n); }
-        cs[n] = acc;
-    }
-    __syncthreads();
-    const int hsize = cs[n];
+    const int hsize = hp_col(n, n);
     double* Zs = Hs + hsize;                                    // nr x n
     double* xs = Zs + (int64_t)nr * n;                          // nw x 2n (eigenvector scratch)
-    HP H{Hs, cs};
+    double* Us = xs + (int64_t)nw * 2 * n;                      // (CH+4)^2 chunk transform
+    HP H{Hs, n};
     const int r0 = blockIdx.x * nr;
     const int nrows = min(nr, n - r0);
 
@@ -216,29 +282,33 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
         __syncthreads();
     }
     const double hnorm = sh_red[0];
-    const double eps = 2.220446049250313e-16;
-    int hi = n - 1;
-    int its = 0;
+    const double eps = defl_tol;             // deflation: |h(k,k-1)| <= eps (|h(k-1,k-1)| + |h(k,k)|)
     if (tid == 0) { sh_stop = 0; sh_iter_total = 0; }
     __syncthreads();
-    while (hi >= 0) {
-        // deflation point: largest l <= hi with negligible H(l, l-1)
-        if (tid == 0) {
-            int l = 0;
-            for (int k = hi; k >= 1; --k) {
-                double s = fabs(H(k - 1, k - 1)) + fabs(H(k, k));
-                if (s == 0.0) s = hnorm;
-                if (fabs(H(k, k - 1)) <= eps * s) { H(k, k - 1) = 0.0; l = k; break; }
-            }
-            sh_l = l;
-        }
+    // ---- implicit double-shift QR (all waves; two barriers per bulge step)
+    {
+        int hi = n - 1, its = 0, total = 0, parity = 0;
+        bool stop = false;
+        if (tid == 0) { sh_lc[0] = 0; sh_lc[1] = 0; }
         __syncthreads();
-        const int l = sh_l;
-        if (l == hi) { hi -= 1; its = 0; __syncthreads(); continue; }
-        if (l == hi - 1) {
-            // 2x2 block (p, q): split it if its eigenvalues are real
-            const int p = hi - 1, q = hi;
+        while (hi >= 0) {
+            // deflation point: largest l <= hi with negligible H(l, l-1), searched in parallel
+            for (int k = hi - tid; k >= 1; k -= nt) {
+                double sd = fabs(H(k - 1, k - 1)) + fabs(H(k, k));
+                if (sd == 0.0) sd = hnorm;
+                if (fabs(H(k, k - 1)) <= eps * sd) { atomicMax(&sh_lc[parity], k); break; }
+            }
+            __syncthreads();
+            const int l = sh_lc[parity];
             if (tid == 0) {
+                sh_lc[parity ^ 1] = 0;
+                if (l > 0) H(l, l - 1) = 0.0;   // deflate exactly (read again only after a barrier)
+            }
+            parity ^= 1;
+            if (l == hi) { hi -= 1; its = 0; __syncthreads(); continue; }
+            if (l == hi - 1) {
+                // 2x2 block (p, q): split it if its eigenvalues are real
+                const int p = hi - 1, q = hi;
                 const double a = H(p, p), b = H(p, q), c = H(q, p), d = H(q, q);
                 double cs_ = 1.0, sn_ = 0.0;
                 bool rot = false;
@@ -255,125 +325,181 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
                         if (nr_ > 0.0) { cs_ = e1 / nr_; sn_ = e2 / nr_; rot = true; }
                     }
                 }
-                sh_v[0] = cs_; sh_v[1] = sn_; sh_v[2] = rot ? 1.0 : 0.0;
+                __syncthreads();
+                if (rot) {
+                    for (int j = p + tid; j < n; j += nt) {          // rows p, q <- G^T rows
+                        const double x = H(p, j), y = H(q, j);
+                        H(p, j) = cs_ * x + sn_ * y;
+                        H(q, j) = -sn_ * x + cs_ * y;
+                    }
+                    __syncthreads();
+                    for (int i = tid; i <= q; i += nt) {             // columns p, q <- columns G
+                        const double x = H(i, p), y = H(i, q);
+                        H(i, p) = cs_ * x + sn_ * y;
+                        H(i, q) = -sn_ * x + cs_ * y;
+                    }
+                    for (int rl = tid; rl < nrows; rl += nt) {
+                        const double x = Zs[rl * n + p], y = Zs[rl * n + q];
+                        Zs[rl * n + p] = cs_ * x + sn_ * y;
+                        Zs[rl * n + q] = -sn_ * x + cs_ * y;
+                    }
+                    __syncthreads();
+                    if (tid == 0) H(q, p) = 0.0;
+                }
+                hi -= 2; its = 0;
+                __syncthreads();
+                continue;
             }
-            __syncthreads();
-            if (sh_v[2] != 0.0) {
-                const double c = sh_v[0], s = sh_v[1];
-                // rows p, q <- G^T rows (columns p..n-1)
-                for (int j = p + tid; j < n; j += nt) {
-                    const double x = H(p, j), y = H(q, j);
-                    H(p, j) = c * x + s * y;
-                    H(q, j) = -s * x + c * y;
+            ++its;
+            if (++total > 40 * n) { stop = true; break; }   // uniform: every thread counts alike
+            // shifts: eigenvalues of the trailing 2x2 block (exceptional shifts at 10 and 20)
+            double s, t;
+            if (its == 10 || its == 20) {
+                const double w = fabs(H(hi, hi - 1)) + (hi >= 2 ? fabs(H(hi - 1, hi - 2)) : 0.0);
+                s = 2.0 * H(hi, hi) + 1.5 * w;
+                t = (H(hi, hi) + 0.75 * w) * (H(hi, hi) + 0.75 * w);
+            } else {
+                s = H(hi - 1, hi - 1) + H(hi, hi);
+                t = H(hi - 1, hi - 1) * H(hi, hi) - H(hi - 1, hi) * H(hi, hi - 1);
+            }
+            // first column of (H - mu1)(H - mu2) on the active block
+            const double x0 = H(l, l) * H(l, l) + H(l, l + 1) * H(l + 1, l) - s * H(l, l) + t;
+            const double y0 = H(l + 1, l) * (H(l, l) + H(l + 1, l + 1) - s);
+            const double z0 = H(l + 1, l) * H(l + 2, l + 1);
+            __syncthreads();   // every thread has read the shift inputs before H changes
+            // The bulge is chased in chunks of at most CH steps (steps l .. hi-2 use 3x3
+            // reflectors, step hi-1 the final 2x2 one).  Within a chunk one wave updates only
+            // the window [ws, we] of H and accumulates the chunk's reflectors into U (W x W);
+            // afterwards all waves apply U to the rows above the window, the columns right
+            // of it and this work-group's rows of Z.
+            for (int k0 = l; k0 <= hi - 1; k0 += CH) {
+                const int k1 = min(k0 + CH, hi);             // steps k0 .. k1-1
+                const int ws = max(l, k0 - 1);
+                const int we = min(hi, k1 + 2);
+                const int W = we - ws + 1;
+                if (wave == 0) {
+                    for (int e = lane; e < W * W; e += 64) Us[e] = (e % W == e / W) ? 1.0 : 0.0;   // U = I
+                    for (int k = k0; k < k1; ++k) {
+                        const bool last = (k == hi - 1);
+                        double x, y, z;
+                        if (k == l) { x = x0; y = y0; z = last ? 0.0 : z0; }
+                        else { x = H(k, k - 1); y = H(k + 1, k - 1); z = last ? 0.0 : H(k + 2, k - 1); }
+                        double v1, v2, tk, beta;
+                        house3(x, y, z, &v1, &v2, &tk, &beta);
+                        if (last) v2 = 0.0;
+                        wave_sync();   // x, y, z read before the rows change
+                        if (tk != 0.0) {
+                            const int c0 = max(l, k - 1);
+                            const int j = c0 + lane;                  // left: rows k..k+2, window columns
+                            if (j <= we) {
+                                double* hk = &H(k, j);
+                                if (last) {
+                                    const double w = (hk[0] + v1 * hk[1]) * tk;
+                                    hk[0] -= w; hk[1] -= w * v1;
+                                } else {
+                                    const double w = (hk[0] + v1 * hk[1] + v2 * hk[2]) * tk;
+                                    hk[0] -= w; hk[1] -= w * v1; hk[2] -= w * v2;
+                                }
+                            }
+                            wave_sync();
+                            if (lane == 0 && k > l) {
+                                H(k, k - 1) = beta; H(k + 1, k - 1) = 0.0;
+                                if (!last) H(k + 2, k - 1) = 0.0;
+                            }
+                            const int i = ws + lane;                  // right: window rows, columns k..k+2
+                            if (i <= min(k + 3, hi)) {
+                                double* c0p = &H(0, k);
+                                double* c1p = &H(0, k + 1);
+                                if (last) {
+                                    const double w = (c0p[i] + v1 * c1p[i]) * tk;
+                                    c0p[i] -= w; c1p[i] -= w * v1;
+                                } else {
+                                    double* c2p = &H(0, k + 2);
+                                    const double w = (c0p[i] + v1 * c1p[i] + v2 * c2p[i]) * tk;
+                                    c0p[i] -= w; c1p[i] -= w * v1; c2p[i] -= w * v2;
+                                }
+                            }
+                            if (lane < W) {                           // U <- U P_k
+                                double* u = Us + lane;                // row `lane`, column stride W
+                                const int cb = k - ws;
+                                if (last) {
+                                    const double w = (u[cb * W] + v1 * u[(cb + 1) * W]) * tk;
+                                    u[cb * W] -= w; u[(cb + 1) * W] -= w * v1;
+                                } else {
+                                    const double w = (u[cb * W] + v1 * u[(cb + 1) * W] + v2 * u[(cb + 2) * W]) * tk;
+                                    u[cb * W] -= w; u[(cb + 1) * W] -= w * v1; u[(cb + 2) * W] -= w * v2;
+                                }
+                            }
+                            wave_sync();
+                        }
+                    }
                 }
                 __syncthreads();
-                // columns p, q <- columns G (rows 0..q)
-                for (int i = tid; i <= q; i += nt) {
-                    const double x = H(i, p), y = H(i, q);
-                    H(i, p) = c * x + s * y;
-                    H(i, q) = -s * x + c * y;
-                }
-                for (int rl = tid; rl < nrows; rl += nt) {
-                    const double x = Zs[rl * n + p], y = Zs[rl * n + q];
-                    Zs[rl * n + p] = c * x + s * y;
-                    Zs[rl * n + q] = -s * x + c * y;
+                // delayed updates with U (column-major W x W in Us):
+                //   rows [0, ws) of the window columns:       H(i, ws+c) <- sum_m H(i, ws+m) U(m, c)
+                //   window rows of columns (we, n):            H(ws+r, j) <- sum_m U(m, r) H(ws+m, j)
+                //   this work-group's rows of Z:               Z(rl, ws+c) <- sum_m Z(rl, ws+m) U(m, c)
+                const int nstrip = (W + 7) / 8;
+                const int ta = ws * nstrip, tb = (n - 1 - we) * nstrip, tc = nrows * nstrip;
+                const int ntask = ta + tb + tc;
+                double outv[DT][8];
+#pragma unroll
+                for (int q = 0; q < DT; ++q) {
+                    const int task = tid + q * nt;
+                    if (task >= ntask) continue;
+                    double vin[CH + 4];
+                    int strip;
+                    if (task < ta) {
+                        const int i = task / nstrip; strip = task % nstrip;
+#pragma unroll
+                        for (int m = 0; m < CH + 4; ++m) vin[m] = m < W ? H(i, ws + m) : 0.0;
+                    } else if (task < ta + tb) {
+                        const int j = we + 1 + (task - ta) / nstrip; strip = (task - ta) % nstrip;
+                        const double* col = &H(ws, j);
+#pragma unroll
+                        for (int m = 0; m < CH + 4; ++m) vin[m] = m < W ? col[m] : 0.0;
+                    } else {
+                        const int rl = (task - ta - tb) / nstrip; strip = (task - ta - tb) % nstrip;
+                        const double* z = Zs + rl * n + ws;
+#pragma unroll
+                        for (int m = 0; m < CH + 4; ++m) vin[m] = m < W ? z[m] : 0.0;
+                    }
+                    const bool transposed = (task >= ta && task < ta + tb);
+#pragma unroll
+                    for (int c8 = 0; c8 < 8; ++c8) {
+                        const int c = strip * 8 + c8;
+                        double acc = 0.0;
+                        if (c < W) {
+#pragma unroll
+                            for (int m = 0; m < CH + 4; ++m)
+                                if (m < W) acc += vin[m] * (transposed ? Us[c * W + m] : Us[m + c * W]);
+                        }
+                        outv[q][c8] = acc;
+                    }
                 }
                 __syncthreads();
-                if (tid == 0) H(q, p) = 0.0;
+#pragma unroll
+                for (int q = 0; q < DT; ++q) {
+                    const int task = tid + q * nt;
+                    if (task >= ntask) continue;
+#pragma unroll
+                    for (int c8 = 0; c8 < 8; ++c8) {
+                        if (task < ta) {
+                            const int i = task / nstrip, c = (task % nstrip) * 8 + c8;
+                            if (c < W) H(i, ws + c) = outv[q][c8];
+                        } else if (task < ta + tb) {
+                            const int j = we + 1 + (task - ta) / nstrip, r = ((task - ta) % nstrip) * 8 + c8;
+                            if (r < W) H(ws + r, j) = outv[q][c8];
+                        } else {
+                            const int rl = (task - ta - tb) / nstrip, c = ((task - ta - tb) % nstrip) * 8 + c8;
+                            if (c < W) Zs[rl * n + ws + c] = outv[q][c8];
+                        }
+                    }
+                }
+                __syncthreads();
             }
-            hi -= 2; its = 0;
-            __syncthreads();
-            continue;
         }
-        ++its;
-        if (tid == 0) { ++sh_iter_total; if (sh_iter_total > 40 * n) sh_stop = 1; }
-        __syncthreads();
-        if (sh_stop) break;
-        // shifts: eigenvalues of the trailing 2x2 block (exceptional shifts at 10 and 20)
-        double s, t;
-        if (its == 10 || its == 20) {
-            const double w = fabs(H(hi, hi - 1)) + (hi >= 2 ? fabs(H(hi - 1, hi - 2)) : 0.0);
-            s = 2.0 * H(hi, hi) + 1.5 * w;
-            t = (H(hi, hi) + 0.75 * w) * (H(hi, hi) + 0.75 * w);
-        } else {
-            s = H(hi - 1, hi - 1) + H(hi, hi);
-            t = H(hi - 1, hi - 1) * H(hi, hi) - H(hi - 1, hi) * H(hi, hi - 1);
-        }
-        // first column of (H - mu1)(H - mu2) on the active block
-        double x = H(l, l) * H(l, l) + H(l, l + 1) * H(l + 1, l) - s * H(l, l) + t;
-        double y = H(l + 1, l) * (H(l, l) + H(l + 1, l + 1) - s);
-        double z = H(l + 1, l) * H(l + 2, l + 1);
-        __syncthreads();   // every thread has read the shift inputs before H changes
-        for (int k = l; k <= hi - 2; ++k) {
-            if (k > l) { x = sh_nxt[0]; y = sh_nxt[1]; z = sh_nxt[2]; }
-            double v1, v2, tk, beta;
-            house3(x, y, z, &v1, &v2, &tk, &beta);
-            if (tk != 0.0) {
-                const int c0 = max(l, k - 1);
-                // left: rows k..k+2, columns c0..n-1
-                for (int j = c0 + tid; j < n; j += nt) {
-                    double* hk = &H(k, j);
-                    const double w = (hk[0] + v1 * hk[1] + v2 * hk[2]) * tk;
-                    hk[0] -= w; hk[1] -= w * v1; hk[2] -= w * v2;
-                }
-            }
-            __syncthreads();
-            if (tk != 0.0) {
-                if (tid == 0 && k > l) { H(k, k - 1) = beta; H(k + 1, k - 1) = 0.0; H(k + 2, k - 1) = 0.0; }
-                // right: columns k..k+2, rows 0..min(k+3, hi)
-                const int rmax = min(k + 3, hi);
-                for (int i = tid; i <= rmax; i += nt) {
-                    double& a0 = H(i, k);
-                    double& a1 = H(i, k + 1);
-                    double& a2 = H(i, k + 2);
-                    const double w = (a0 + v1 * a1 + v2 * a2) * tk;
-                    a0 -= w; a1 -= w * v1; a2 -= w * v2;
-                }
-                for (int rl = tid; rl < nrows; rl += nt) {
-                    double* zr = Zs + rl * n + k;
-                    const double w = (zr[0] + v1 * zr[1] + v2 * zr[2]) * tk;
-                    zr[0] -= w; zr[1] -= w * v1; zr[2] -= w * v2;
-                }
-            }
-            // the next reflector's vector is column k, rows k+1..k+3 (copied so that the
-            // next left update may overwrite H while slower threads still read it)
-            for (int i = tid; i <= min(k + 3, n - 1); i += nt)   // same row mapping as the update
-                if (i >= k + 1) sh_nxt[i - k - 1] = (i <= hi) ? H(i, k) : 0.0;
-            __syncthreads();
-        }
-        // final 2-vector reflector on rows / columns hi-1, hi
-        {
-            const int k = hi - 1;
-            double xx, yy;
-            if (k > l) { xx = sh_nxt[0]; yy = sh_nxt[1]; }
-            else { xx = x; yy = y; }
-            double v1, v2, tk, beta;
-            house3(xx, yy, 0.0, &v1, &v2, &tk, &beta);
-            if (tk != 0.0) {
-                const int c0 = max(l, k - 1);
-                for (int j = c0 + tid; j < n; j += nt) {
-                    double* hk = &H(k, j);
-                    const double w = (hk[0] + v1 * hk[1]) * tk;
-                    hk[0] -= w; hk[1] -= w * v1;
-                }
-            }
-            __syncthreads();
-            if (tk != 0.0) {
-                if (tid == 0 && k > l) { H(k, k - 1) = beta; H(k + 1, k - 1) = 0.0; }
-                for (int i = tid; i <= hi; i += nt) {
-                    double& a0 = H(i, k);
-                    double& a1 = H(i, k + 1);
-                    const double w = (a0 + v1 * a1) * tk;
-                    a0 -= w; a1 -= w * v1;
-                }
-                for (int rl = tid; rl < nrows; rl += nt) {
-                    double* zr = Zs + rl * n + k;
-                    const double w = (zr[0] + v1 * zr[1]) * tk;
-                    zr[0] -= w; zr[1] -= w * v1;
-                }
-            }
-            __syncthreads();
-        }
+        if (tid == 0) { sh_stop = stop ? 1 : 0; sh_iter_total = total; }
     }
     __syncthreads();
     if (sh_stop) {
@@ -567,24 +693,25 @@ __global__ void sort_modes_kernel(int n, const double* __restrict__ wr, const do
 }
 
 hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* ws, double* lam,
-                      int32_t* kind, double* W, int32_t* info)
+                      int32_t* kind, double* W, int32_t* info, double defl_tol)
 {
     if (n <= 0) return hipSuccess;
     if (n > EIG_MAX) return hipErrorInvalidValue;
     EigWs w = eig_carve(ws, n);
-    hipLaunchKernelGGL(hessenberg_kernel, dim3(1), dim3(1024), 0, s, A, lda, n, w.H, w.V, w.tau);
+    const int jb = hess_jbase(n);
+    const size_t hlds = ((size_t)5 * n + 20 + (size_t)n * (n - jb)) * 8;
+    hipLaunchKernelGGL(hessenberg_kernel, dim3(1), dim3(1024), hlds, s, A, lda, n, w.H, w.V, w.tau, jb);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nr = eig_rows_per_wg(n);
     const int grid = eig_grid(n);
-    int hsize = 0;
-    for (int j = 0; j < n; ++j) hsize += std::min(j + 4, n);
+    const int hsize = hp_col(n, n);
     const int nw = 4;
-    const size_t lds = (size_t)(round_up(2 * n + 1, 2) / 2) * 8 + (size_t)hsize * 8 + (size_t)nr * n * 8 +
-                       (size_t)nw * 2 * n * 8;
+    const size_t lds = (size_t)(round_up(n, 2) / 2) * 8 + (size_t)hsize * 8 + (size_t)nr * n * 8 +
+                       (size_t)nw * 2 * n * 8 + (size_t)(CH + 4) * (CH + 4) * 8;
     if (lds > 160 * 1024 - 512) return hipErrorInvalidValue;
     hipLaunchKernelGGL(francis_kernel, dim3(grid), dim3(64 * nw), lds, s, n, nr, w.H, w.V, w.tau, w.Wraw,
-                       w.wr, w.wi, w.kind0, w.X, info);
+                       w.wr, w.wi, w.kind0, w.X, info, defl_tol);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sort_modes_kernel, dim3(1), dim3(256), n * sizeof(int), s, n, w.wr, w.wi, w.kind0,
@@ -594,6 +721,9 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
 
 hipError_t eig_prepare()
 {
+    hipError_t e = hipFuncSetAttribute((const void*)hessenberg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024 - 256);
+    if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)francis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
 }
 

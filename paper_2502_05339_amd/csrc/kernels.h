@@ -62,8 +62,9 @@ hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* 
                     int32_t* info, const int32_t* skip_unless);
 // Jacobi eigen-decomposition of a symmetric n x n matrix: eigenvalues descending,
 // eigenvectors in the columns of Vout (n x n, ld n).
+// rtol: rotate while |a_pq| > rtol sqrt(|a_pp a_qq|) (about 2 ulp for full FP64 accuracy).
 hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* evals, double* Vout,
-                   int32_t* info);
+                   int32_t* info, double rtol);
 // C = alpha op(A) op(B) + beta C, all FP64 column-major, small sizes.
 hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
@@ -79,9 +80,15 @@ hipError_t to_f32(hipStream_t s, int m, int n, int n_pad, const double* A, int64
 hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, double* B,
                     int64_t ldb);
 // Least-squares amplitudes from the Gram of the folded modes: beta = G^-1 rhs via
-// Rinv, then complex b for each (real | pair) mode.
+// Rinv (beta_ws: r doubles), then complex b for each (real | pair) mode.
 hipError_t amplitudes(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs,
-                      const int32_t* kind, double* b);
+                      const int32_t* kind, double* b, double* beta_ws);
+hipError_t normal_solve(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs, double* beta,
+                        int accumulate);
+hipError_t beta_to_b(hipStream_t s, int r, const double* beta, const int32_t* kind, double* b);
+// res = x - Phi beta (one FP64 dot per row), in the model's element type
+hipError_t residual(hipStream_t s, int dtype, int64_t N, int r, const void* phi, int64_t ldphi, const double* beta,
+                    const void* x, void* res);
 hipError_t check_finite(hipStream_t s, int dtype, const void* X, int64_t ld, int64_t N, int ncols,
                         int32_t* info);
 
@@ -89,8 +96,10 @@ hipError_t check_finite(hipStream_t s, int dtype, const void* X, int64_t ld, int
 size_t eig_workspace_bytes(int n);
 // lam (2n doubles), kind (n), W (n x n folded real eigenvectors, ld n) sorted in
 // the canonical order; M = Vs W (m x n) where Vs = V_r S_r^-1 (m x n, ld ldv).
+// defl_tol: relative size below which a sub-diagonal entry of the Hessenberg form is
+// treated as zero (machine epsilon for full FP64 accuracy).
 hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* ws, double* lam,
-                      int32_t* kind, double* W, int32_t* info);
+                      int32_t* kind, double* W, int32_t* info, double defl_tol);
 
 // ---- adjoint (adjoint.hip)
 hipError_t grad_reduce(hipStream_t s, int r, int ncols, const double* G, const double* lam,

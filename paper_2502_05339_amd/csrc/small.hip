@@ -17,9 +17,8 @@
 namespace dmd {
 
 // ====================================================================== Cholesky
-__device__ __forceinline__ int64_t lp_idx(int i, int j, int n) {   // packed lower, i >= j
-    return (int64_t)j * n - (int64_t)j * (j - 1) / 2 + (i - j);
-}
+// packed lower triangle by columns: L(i, j), i >= j, at lp_col(j, n) + i
+__device__ __forceinline__ int lp_col(int j, int n) { return j * n - j * (j + 1) / 2; }
 
 __global__ void __launch_bounds__(1024)
 chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, int64_t ldr,
@@ -28,140 +27,96 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
 {
     if (skip_unless && *skip_unless == 0) return;
     extern __shared__ double L[];
-    __shared__ int fail;
     __shared__ double shift;
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+#define LP(i, j) L[lp_col(j, n) + (i)]
 
-    // R^-1 starts as zero (its strictly lower part stays zero)
-    for (int64_t e = tid; e < (int64_t)n * n; e += nt) Rinv[(e / n) * ldr + (e % n)] = 0.0;
-
-    int attempt = 0;
-    for (;;) {
+    bool fail = false;
+    for (int attempt = 0; attempt < 2; ++attempt) {
         if (tid == 0) {
-            fail = 0;
-            if (attempt == 1) {
-                double tr = 0.0;
+            double tr = 0.0;
+            if (attempt == 1)
                 for (int j = 0; j < n; ++j) tr += fabs(G[(int64_t)j * ldg + j]);
-                shift = shift_scale * tr;
-            } else {
-                shift = 0.0;
-            }
+            shift = shift_scale * tr;
         }
         __syncthreads();
-        for (int64_t e = tid; e < (int64_t)n * n; e += nt) {
-            const int i = (int)(e % n), j = (int)(e / n);
-            if (i >= j) L[lp_idx(i, j, n)] = G[(int64_t)j * ldg + i] + (i == j ? shift : 0.0);
+        for (int e = tid; e < n * n; e += nt) {
+            const int i = e % n, j = e / n;
+            if (i >= j) LP(i, j) = G[(int64_t)j * ldg + i] + (i == j ? shift : 0.0);
         }
         __syncthreads();
+        // right-looking Cholesky, two barriers per column
+        fail = false;
         for (int j = 0; j < n; ++j) {
-            if (tid == 0) {
-                const double d = L[lp_idx(j, j, n)];
-                if (!(d > 0.0) || !isfinite(d)) fail = 1;
-                else L[lp_idx(j, j, n)] = sqrt(d);
-            }
+            const double d = LP(j, j);
+            if (!(d > 0.0) || !isfinite(d)) { fail = true; break; }   // uniform decision
+            const double ljj = sqrt(d), inv = 1.0 / ljj;
+            for (int i = j + 1 + tid; i < n; i += nt) LP(i, j) *= inv;
             __syncthreads();
-            if (fail) break;
-            const double inv = 1.0 / L[lp_idx(j, j, n)];
-            for (int i = j + 1 + tid; i < n; i += nt) L[lp_idx(i, j, n)] *= inv;
-            __syncthreads();
-            const int m = n - j - 1;
-            for (int idx = tid; idx < m * m; idx += nt) {
-                const int c = j + 1 + idx / m, i = j + 1 + idx % m;
-                if (i >= c) L[lp_idx(i, c, n)] -= L[lp_idx(i, j, n)] * L[lp_idx(c, j, n)];
+            if (tid == 0) LP(j, j) = ljj;
+            // trailing update: one wave per column c, lanes over rows i >= c
+            for (int c = j + 1 + wave; c < n; c += nw) {
+                const double lcj = LP(c, j);
+                double* colc = &L[lp_col(c, n)];
+                const double* colj = &L[lp_col(j, n)];
+                for (int i = c + lane; i < n; i += 64) colc[i] -= colj[i] * lcj;
             }
             __syncthreads();
         }
         if (!fail) break;
         if (attempt == 0 && shift_scale > 0.0) {
-            attempt = 1;
             if (tid == 0 && shifted) *shifted = 1;
             if (tid == 0 && info) atomicAdd(&info[3], 1);
             __syncthreads();
             continue;
         }
+        break;
+    }
+    if (fail) {
         // breakdown: report, and leave an identity so that later stages stay finite
         if (tid == 0) set_status(info, DMD_ERR_CHOL_BREAKDOWN);
-        __syncthreads();
-        for (int i = tid; i < n; i += nt) Rinv[(int64_t)i * ldr + i] = 1.0;
-        __syncthreads();
-        __threadfence_block();
-        if (Rinv32)
-            for (int64_t e = tid; e < (int64_t)n * n; e += nt)
-                Rinv32[(e / n) * ldr32 + (e % n)] = (float)Rinv[(e / n) * ldr + (e % n)];
+        for (int e = tid; e < n * n; e += nt) {
+            const int i = e % n, j = e / n;
+            const double v = i == j ? 1.0 : 0.0;
+            Rinv[(int64_t)j * ldr + i] = v;
+            if (Rinv32) Rinv32[(int64_t)j * ldr32 + i] = (float)v;
+        }
         return;
     }
-
-    // ---- inverse of the lower factor L by 16 x 16 blocks; R^-1 = (L^-1)^T is stored:
-    //      Linv(a, b) lives at Rinv[a * ldr + b]  (i.e. R^-1(b, a)).
-    const int nb = (n + 15) / 16;
-    // step 1: diagonal blocks, one wave per block, lane c < 16 computes column c
-    if (wave < nb && lane < 16) {
-        const int b0 = wave * 16, c = lane;
-        double x[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int gi = b0 + i;
-            if (gi >= n || i < c || b0 + c >= n) { x[i] = 0.0; continue; }
-            if (i == c) { x[i] = 1.0 / L[lp_idx(gi, gi, n)]; continue; }
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < i; ++k)
-                if (k >= c) s += L[lp_idx(gi, b0 + k, n)] * x[k];
-            x[i] = -s / L[lp_idx(gi, gi, n)];
+    // ---- in-place inverse of L, right to left:
+    //      Linv(j+1:, j) = -Linv(j+1:, j+1:) L(j+1:, j) / L(j, j),  Linv(j, j) = 1 / L(j, j)
+    //      Row i's product is split over NP = nt / 256 thread groups (every NP-th column);
+    //      partial sums meet in LDS (no cross-lane shuffles).
+    double* part = L + n * (n + 1) / 2;          // NP x n partial sums
+    const int NP = nt >> 8;                      // 4 with 1024 threads
+    const int grp = tid >> 8, ri = tid & 255;
+    for (int j = n - 1; j >= 0; --j) {
+        const double inv = 1.0 / LP(j, j);       // read before anyone overwrites the diagonal
+        for (int i = j + 1 + ri; i < n; i += 256) {
+            double acc = 0.0;
+            for (int c = j + 1 + grp; c <= i; c += NP) acc += LP(i, c) * LP(c, j);
+            part[grp * n + i] = acc;
         }
-        if (b0 + c < n) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (b0 + i < n) Rinv[(int64_t)(b0 + i) * ldr + (b0 + c)] = x[i];
-        }
-    }
-    __syncthreads();
-    __threadfence_block();
-    // step 2: wave j computes block column j: Linv_ij = -Dinv_i * sum_{c=j}^{i-1} L_ic Linv_cj
-    if (wave < nb) {
-        const int j = wave;
-        const int tj = lane & 15, tg = lane >> 4;       // entries (tg + 4q, tj), q = 0..3
-        for (int i = j + 1; i < nb; ++i) {
-            double T[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int c = j; c < i; ++c) {
-                for (int k = 0; k < 16; ++k) {
-                    const int col = 16 * c + k;
-                    if (col >= n) break;
-                    const double lv = (16 * j + tj < n) ? Rinv[(int64_t)col * ldr + 16 * j + tj] : 0.0;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int row = 16 * i + tg + 4 * q;
-                        if (row < n) T[q] += L[lp_idx(row, col, n)] * lv;
-                    }
-                }
+        __syncthreads();
+        if (grp == 0) {
+            for (int i = j + 1 + ri; i < n; i += 256) {
+                double acc = 0.0;
+                for (int g = 0; g < NP; ++g) acc += part[g * n + i];
+                LP(i, j) = -inv * acc;
             }
-            // gather column tj of T: T[k][tj] sits in lane tj + 16 * (k % 4), slot k / 4
-            double Tc[16];
-#pragma unroll
-            for (int g = 0; g < 4; ++g)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) Tc[g + 4 * q] = __shfl(T[q], tj + 16 * g, 64);
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int ti = tg + 4 * q;
-                const int row = 16 * i + ti;
-                double s = 0.0;
-#pragma unroll
-                for (int k = 0; k < 16; ++k) {
-                    const int kr = 16 * i + k;
-                    if (kr < n && row < n) s += Rinv[(int64_t)row * ldr + kr] * Tc[k];
-                }
-                if (row < n && 16 * j + tj < n) Rinv[(int64_t)row * ldr + 16 * j + tj] = -s;
-            }
-            __threadfence_block();
+            if (ri == 0) LP(j, j) = inv;
         }
+        __syncthreads();
     }
-    __syncthreads();
-    __threadfence_block();
-    if (Rinv32)
-        for (int64_t e = tid; e < (int64_t)n * n; e += nt)
-            Rinv32[(e / n) * ldr32 + (e % n)] = (float)Rinv[(e / n) * ldr + (e % n)];
+    // ---- R^-1 = L^-T (upper), zero below the diagonal
+    for (int e = tid; e < n * n; e += nt) {
+        const int r = e % n, c = e / n;     // element (r, c) of R^-1
+        const double v = (c >= r) ? LP(c, r) : 0.0;
+        Rinv[(int64_t)c * ldr + r] = v;
+        if (Rinv32) Rinv32[(int64_t)c * ldr32 + r] = (float)v;
+    }
+#undef LP
 }
 
 hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* Rinv, int64_t ldr,
@@ -170,22 +125,17 @@ hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* 
 {
     if (n <= 0) return hipSuccess;
     if (n > SMALL_MAX) return hipErrorInvalidValue;
-    const size_t lds = (size_t)n * (n + 1) / 2 * sizeof(double);
+    const size_t lds = ((size_t)n * (n + 1) / 2 + 4 * (size_t)n) * sizeof(double);
     hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), lds, s, G, ldg, n, Rinv, ldr, Rinv32,
                        ldr32, shift_scale, shifted, info, skip_unless);
     return hipGetLastError();
 }
 
 // ====================================================================== Jacobi
-__device__ __forceinline__ int64_t up_idx(int i, int j) {   // packed upper, i <= j
-    return (int64_t)j * (j + 1) / 2 + i;
+__device__ __forceinline__ int up_idx(int i, int j) {   // packed upper, i <= j
+    return j * (j + 1) / 2 + i;
 }
-__device__ __forceinline__ double sym_get(const double* A, int i, int j) {
-    return i <= j ? A[up_idx(i, j)] : A[up_idx(j, i)];
-}
-__device__ __forceinline__ void sym_set(double* A, int i, int j, double v) {
-    if (i <= j) A[up_idx(i, j)] = v; else A[up_idx(j, i)] = v;
-}
+__device__ __forceinline__ int sym_idx(int i, int j) { return i <= j ? up_idx(i, j) : up_idx(j, i); }
 // Round-robin (circle) schedule on n2 (even) players: in round t, pair k.
 __device__ __forceinline__ void rr_pair(int k, int t, int n2, int* p, int* q) {
     const int m = n2 - 1;
@@ -196,16 +146,19 @@ __device__ __forceinline__ void rr_pair(int k, int t, int n2, int* p, int* q) {
     *q = max(a, b);
 }
 
-__global__ void __launch_bounds__(1024)
+constexpr int JAC_THREADS = 1024;
+constexpr int JAC_BLK = ((SMALL_MAX / 2) * (SMALL_MAX / 2 + 1) / 2 + JAC_THREADS - 1) / JAC_THREADS;
+
+__global__ void __launch_bounds__(JAC_THREADS)
 jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* evals,
-              double* Vout, int32_t* info)
+              double* Vout, int32_t* info, double rtol)
 {
     extern __shared__ double sm[];
     const int n2 = n + (n & 1);
     const int np = n2 / 2;
     double* A = sm;                                   // n(n+1)/2
-    double* Vs = A + (int64_t)n * (n + 1) / 2;        // nr x n
-    double* cs = Vs + (int64_t)nr * n;                // np
+    double* Vs = A + n * (n + 1) / 2;                 // nr x n
+    double* cs = Vs + nr * n;                         // np
     double* sn = cs + np;                             // np
     double* tn = sn + np;                             // np
     int* pp = reinterpret_cast<int*>(tn + np);        // np
@@ -218,13 +171,25 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
     const int r0 = blockIdx.x * nr;
     const int nrows = min(nr, n - r0);
 
-    for (int64_t e = tid; e < (int64_t)n * n; e += nt) {
-        const int i = (int)(e % n), j = (int)(e / n);
+    for (int e = tid; e < n * n; e += nt) {
+        const int i = e % n, j = e / n;
         if (i <= j) A[up_idx(i, j)] = S[(int64_t)j * lds + i];
     }
     for (int e = tid; e < nr * n; e += nt) {
         const int rl = e / n, c = e % n;
         Vs[e] = (rl < nrows && r0 + rl == c) ? 1.0 : 0.0;
+    }
+    // this thread's pairs of pairs (k1 <= k2), fixed for every round
+    const int nblk = np * (np + 1) / 2;
+    int bk1[JAC_BLK], bk2[JAC_BLK];
+#pragma unroll
+    for (int t = 0; t < JAC_BLK; ++t) {
+        const int b = tid + t * nt;
+        int k2 = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
+        while (k2 * (k2 + 1) / 2 > b) --k2;
+        while ((k2 + 1) * (k2 + 2) / 2 <= b) ++k2;
+        bk2[t] = b < nblk ? k2 : -1;
+        bk1[t] = b - k2 * (k2 + 1) / 2;
     }
     __syncthreads();
     if (tid == 0) {
@@ -233,8 +198,7 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
         dmax_s = d;
     }
     __syncthreads();
-    const double floor_abs = 1e-17 * dmax_s;
-    const int nblk = np * (np + 1) / 2;
+    const double floor_abs = (rtol > 1e-15 ? 1e-3 * rtol : 1e-17) * dmax_s;
 
     int sweep = 0;
     bool converged = false;
@@ -249,7 +213,7 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
                 if (q < n) {
                     const double apq = A[up_idx(p, q)];
                     const double app = A[up_idx(p, p)], aqq = A[up_idx(q, q)];
-                    if (fabs(apq) > floor_abs && fabs(apq) > 1e-15 * sqrt(fabs(app) * fabs(aqq))) {
+                    if (fabs(apq) > floor_abs && fabs(apq) > rtol * sqrt(fabs(app) * fabs(aqq))) {
                         const double tau = (aqq - app) / (2.0 * apq);
                         tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + tt * tt);
@@ -261,48 +225,39 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
             }
             __syncthreads();
             // 2x2 blocks of every pair of pairs: B' = J1^T B J2 (independent, disjoint entries)
-            for (int bidx = tid; bidx < nblk; bidx += nt) {
-                int k2 = (int)((sqrtf(8.0f * (float)bidx + 1.0f) - 1.0f) * 0.5f);
-                while (k2 * (k2 + 1) / 2 > bidx) --k2;
-                while ((k2 + 1) * (k2 + 2) / 2 <= bidx) ++k2;
-                const int k1 = bidx - k2 * (k2 + 1) / 2;
+#pragma unroll
+            for (int u = 0; u < JAC_BLK; ++u) {
+                const int k2 = bk2[u];
+                if (k2 < 0) continue;
+                const int k1 = bk1[u];
                 const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
-                if (q1 >= n || q2 >= n) {
-                    // one pair involves the padding player: only its real index rotates
-                    if (k1 == k2) continue;
-                    const bool r1 = q1 < n, r2 = q2 < n;
-                    if (!r1 && !r2) continue;
-                    if (r1) {   // pair 1 real, pair 2 = (p2, pad): rotate column p2 against rows p1, q1
-                        const double c1 = cs[k1], s1 = sn[k1];
-                        const double x = sym_get(A, p1, p2), y = sym_get(A, q1, p2);
-                        sym_set(A, p1, p2, c1 * x - s1 * y);
-                        sym_set(A, q1, p2, s1 * x + c1 * y);
-                    } else {
-                        const double c2 = cs[k2], s2 = sn[k2];
-                        const double x = sym_get(A, p1, p2), y = sym_get(A, p1, q2);
-                        sym_set(A, p1, p2, c2 * x - s2 * y);
-                        sym_set(A, p1, q2, s2 * x + c2 * y);
-                    }
-                    continue;
-                }
                 if (k1 == k2) {
                     const double t1 = tn[k1];
-                    if (t1 == 0.0) continue;
+                    if (t1 == 0.0 || q1 >= n) continue;
                     const double apq = A[up_idx(p1, q1)];
                     A[up_idx(p1, p1)] -= t1 * apq;
                     A[up_idx(q1, q1)] += t1 * apq;
                     A[up_idx(p1, q1)] = 0.0;
                     continue;
                 }
-                const double c1 = cs[k1], s1 = sn[k1], c2 = cs[k2], s2 = sn[k2];
-                const double b00 = sym_get(A, p1, p2), b01 = sym_get(A, p1, q2);
-                const double b10 = sym_get(A, q1, p2), b11 = sym_get(A, q1, q2);
+                const bool r1 = q1 < n, r2 = q2 < n;
+                const double c1 = r1 ? cs[k1] : 1.0, s1 = r1 ? sn[k1] : 0.0;
+                const double c2 = r2 ? cs[k2] : 1.0, s2 = r2 ? sn[k2] : 0.0;
+                if (s1 == 0.0 && s2 == 0.0) continue;
+                const int i00 = sym_idx(p1, p2);
+                const int i10 = sym_idx(q1 < n ? q1 : p1, p2);
+                const int i01 = sym_idx(p1, q2 < n ? q2 : p2);
+                const int i11 = sym_idx(q1 < n ? q1 : p1, q2 < n ? q2 : p2);
+                const double b00 = A[i00];
+                const double b01 = r2 ? A[i01] : 0.0;
+                const double b10 = r1 ? A[i10] : 0.0;
+                const double b11 = (r1 && r2) ? A[i11] : 0.0;
                 const double x00 = c2 * b00 - s2 * b01, x01 = s2 * b00 + c2 * b01;
                 const double x10 = c2 * b10 - s2 * b11, x11 = s2 * b10 + c2 * b11;
-                sym_set(A, p1, p2, c1 * x00 - s1 * x10);
-                sym_set(A, p1, q2, c1 * x01 - s1 * x11);
-                sym_set(A, q1, p2, s1 * x00 + c1 * x10);
-                sym_set(A, q1, q2, s1 * x01 + c1 * x11);
+                A[i00] = c1 * x00 - s1 * x10;
+                if (r2) A[i01] = c1 * x01 - s1 * x11;
+                if (r1) A[i10] = s1 * x00 + c1 * x10;
+                if (r1 && r2) A[i11] = s1 * x01 + c1 * x11;
             }
             // eigenvector rows owned by this work-group: V <- V J
             for (int e = tid; e < nrows * np; e += nt) {
@@ -346,7 +301,7 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
 }
 
 hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* evals, double* Vout,
-                   int32_t* info)
+                   int32_t* info, double rtol)
 {
     if (n <= 0) return hipSuccess;
     if (n > SMALL_MAX) return hipErrorInvalidValue;
@@ -359,7 +314,8 @@ hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* e
     if (nr > n) nr = n;
     const int grid = (int)ceil_div(n, nr);
     const size_t lds_bytes = fixed + (size_t)nr * n * 8;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(1024), lds_bytes, s, S, lds, n, nr, evals, Vout, info);
+    hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(JAC_THREADS), lds_bytes, s, S, lds, n, nr, evals, Vout, info,
+                       rtol);
     return hipGetLastError();
 }
 
@@ -470,16 +426,12 @@ hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int
     return hipGetLastError();
 }
 
-// beta = R^-1 R^-T rhs  (the normal equations G beta = rhs with G = R^T R), then the
-// complex amplitudes of the folded basis: a pair (i, i+1) contributes
-// Re(phi) beta_i + Im(phi) beta_{i+1} = 2 Re(phi b_i) with b_i = (beta_i - i beta_{i+1}) / 2.
-__global__ void amplitudes_kernel(int r, const double* __restrict__ Rinv, int64_t ldr,
-                                  const double* __restrict__ rhs, const int32_t* __restrict__ kind,
-                                  double* __restrict__ b)
+// beta (+)= R^-1 R^-T rhs  (the normal equations G beta = rhs with G = R^T R)
+__global__ void normal_solve_kernel(int r, const double* __restrict__ Rinv, int64_t ldr,
+                                    const double* __restrict__ rhs, double* __restrict__ beta, int accumulate)
 {
     extern __shared__ double sh[];
     double* t = sh;          // r
-    double* beta = sh + r;   // r
     const int tid = threadIdx.x;
     for (int i = tid; i < r; i += blockDim.x) {          // t = R^-T rhs
         double s = 0.0;
@@ -490,10 +442,17 @@ __global__ void amplitudes_kernel(int r, const double* __restrict__ Rinv, int64_
     for (int i = tid; i < r; i += blockDim.x) {          // beta = R^-1 t
         double s = 0.0;
         for (int j = i; j < r; ++j) s += Rinv[(int64_t)j * ldr + i] * t[j];
-        beta[i] = s;
+        beta[i] = accumulate ? beta[i] + s : s;
     }
-    __syncthreads();
-    for (int i = tid; i < r; i += blockDim.x) {
+}
+
+// Complex amplitudes of the folded basis from the real coefficients beta: a pair
+// (i, i+1) contributes Re(phi) beta_i + Im(phi) beta_{i+1} = 2 Re(phi b_i) with
+// b_i = (beta_i - i beta_{i+1}) / 2 and b_{i+1} = conj(b_i).
+__global__ void beta_to_b_kernel(int r, const double* __restrict__ beta, const int32_t* __restrict__ kind,
+                                 double* __restrict__ b)
+{
+    for (int i = threadIdx.x; i < r; i += blockDim.x) {
         int kd = kind[i];
         if ((kd == 1 && i + 1 >= r) || (kd == 2 && i == 0) || kd < 0 || kd > 2) kd = 0;
         if (kd == 0) { b[2 * i] = beta[i]; b[2 * i + 1] = 0.0; }
@@ -502,11 +461,53 @@ __global__ void amplitudes_kernel(int r, const double* __restrict__ Rinv, int64_
     }
 }
 
-hipError_t amplitudes(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs,
-                      const int32_t* kind, double* b)
+// res = x - Phi beta  (Phi row-major N x r with leading dimension ldphi), FP64 sums
+template <typename T>
+__global__ void residual_kernel(int64_t N, int r, const T* __restrict__ phi, int64_t ldphi,
+                                const double* __restrict__ beta, const T* __restrict__ x, T* __restrict__ res)
 {
-    hipLaunchKernelGGL(amplitudes_kernel, dim3(1), dim3(256), 2 * r * sizeof(double), s, r, Rinv, ldr, rhs, kind, b);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+        const T* row = phi + i * ldphi;
+        double s = 0.0;
+        for (int c = 0; c < r; ++c) s += (double)row[c] * beta[c];
+        res[i] = (T)((double)x[i] - s);
+    }
+}
+
+hipError_t normal_solve(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs, double* beta,
+                        int accumulate)
+{
+    hipLaunchKernelGGL(normal_solve_kernel, dim3(1), dim3(256), r * sizeof(double), s, r, Rinv, ldr, rhs, beta,
+                       accumulate);
     return hipGetLastError();
+}
+
+hipError_t beta_to_b(hipStream_t s, int r, const double* beta, const int32_t* kind, double* b)
+{
+    hipLaunchKernelGGL(beta_to_b_kernel, dim3(1), dim3(256), 0, s, r, beta, kind, b);
+    return hipGetLastError();
+}
+
+hipError_t residual(hipStream_t s, int dtype, int64_t N, int r, const void* phi, int64_t ldphi, const double* beta,
+                    const void* x, void* res)
+{
+    const int blocks = (int)std::min<int64_t>(ceil_div(N, 256), 2048);
+    if (dtype == DMD_F32)
+        hipLaunchKernelGGL(residual_kernel<float>, dim3(blocks), dim3(256), 0, s, N, r, (const float*)phi, ldphi,
+                           beta, (const float*)x, (float*)res);
+    else
+        hipLaunchKernelGGL(residual_kernel<double>, dim3(blocks), dim3(256), 0, s, N, r, (const double*)phi, ldphi,
+                           beta, (const double*)x, (double*)res);
+    return hipGetLastError();
+}
+
+// project / amplitudes helper used outside the fit: beta = G^-1 rhs then complex b
+hipError_t amplitudes(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs,
+                      const int32_t* kind, double* b, double* beta_ws)
+{
+    hipError_t e = normal_solve(s, r, Rinv, ldr, rhs, beta_ws, 0);
+    if (e != hipSuccess) return e;
+    return beta_to_b(s, r, beta_ws, kind, b);
 }
 
 template <typename T>
