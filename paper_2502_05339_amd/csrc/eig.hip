@@ -191,14 +191,13 @@ static int hess_jbase(int n)
 // Packed Hessenberg with 3 sub-diagonals: column j holds rows 0..min(j+3, n-1), i.e.
 // min(j+4, n) entries; the offset of column j is computed, not looked up.
 __host__ __device__ __forceinline__ int hp_col(int j, int n) {
-    if (n <= 4) return j * n;
-    if (j <= n - 3) return j * (j + 7) / 2;
-    return (n - 3) * (n + 4) / 2 + (j - (n - 3)) * n;
+    const int head = (j * (j + 7)) >> 1;                             // columns 0..j-1 all hold i+4 rows
+    const int tail = (((n - 3) * (n + 4)) >> 1) + (j - (n - 3)) * n;  // full columns from n-3 on
+    return n <= 4 ? j * n : (j <= n - 3 ? head : tail);
 }
-constexpr int CH = 32;                    // bulge-chase steps per delayed-update chunk
-// delayed-update tasks per thread: rows above + columns right (< n each) + Z rows, in
-// strips of 8 window columns, over 256 threads
-constexpr int DT = ((2 * DMD_MAX_RANK + 16) * ((CH + 4 + 7) / 8) + 255) / 256;
+constexpr int FR_THREADS = 256;
+// row-update roles use threads 1..n, Z-slab roles the last 16, plus one deferred-write thread
+static_assert(EIG_MAX + 1 + 1 + 16 <= FR_THREADS, "francis_kernel thread roles overlap");
 
 struct HP {
     double* a;
@@ -226,7 +225,50 @@ __device__ __forceinline__ void house3(double x, double y, double z, double* v1,
     *beta = b;
 }
 
-__global__ void __launch_bounds__(256)
+// 1/sqrt(s) and 1/s for s > 0 (normal range): the hardware estimates (about 23 correct
+// bits) refined by two Newton steps each, which leaves an error of a few ulp.
+__device__ __forceinline__ double rsqrt_nr(double s)
+{
+    double r = __builtin_amdgcn_rsq(s);
+    const double hs = 0.5 * s;
+    r = r * fma(-hs * r, r, 1.5);
+    r = r * fma(-hs * r, r, 1.5);
+    return r;
+}
+__device__ __forceinline__ double rcp_nr(double s)
+{
+    double r = __builtin_amdgcn_rcp(s);
+    r = fma(r, fma(-s, r, 1.0), r);
+    r = fma(r, fma(-s, r, 1.0), r);
+    return r;
+}
+
+// Reflector of the bulge step in unnormalised form: P = I - t u u^T with u = (d, y, z),
+// d = x - beta, beta = -sign(x) ||(x, y, z)||, and t = 2 / (u^T u) taken from the u that
+// is actually used, so P is orthogonal to rounding whatever the error of the norm.
+// P (x, y, z)^T = (beta, 0, 0)^T.  t = 0 when y = z = 0 (P = I).
+__device__ __forceinline__ void reflector3(double x, double y, double z, double* d, double* t, double* beta)
+{
+    const double yz = fma(y, y, z * z);
+    const double sig = fma(x, x, yz);
+    if (yz == 0.0 || !(sig >= 1e-280)) {      // nothing to annihilate, or too small to scale safely
+        if (yz == 0.0) { *t = 0.0; *d = 0.0; *beta = x; return; }
+        double v1, v2, tau, b;
+        house3(x, y, z, &v1, &v2, &tau, &b);
+        // same reflector: u = (x - b) (1, v1, v2), t = tau / (x - b)^2
+        const double dd = x - b;
+        *d = dd; *t = tau / (dd * dd); *beta = b;
+        return;
+    }
+    const double r = rsqrt_nr(sig);
+    const double nrm = sig * r;
+    const double dd = x >= 0.0 ? x + nrm : x - nrm;
+    *d = dd;
+    *beta = x >= 0.0 ? -nrm : nrm;
+    *t = 2.0 * rcp_nr(fma(dd, dd, yz));
+}
+
+__global__ void __launch_bounds__(FR_THREADS)
 francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __restrict__ Vg,
                const double* __restrict__ taug, double* Wraw, double* wr, double* wi, int32_t* kind0,
                double* Xall, int32_t* info, double defl_tol)
@@ -237,7 +279,6 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
     double* Hs = sm + ioff;
     __shared__ int sh_l, sh_stop, sh_iter_total;
     __shared__ double sh_v[4];   // rotation of a 2x2 block split
-    __shared__ double sh_nxt[3]; // vector of the next bulge reflector
     __shared__ int sh_lc[2];     // deflation search result (double-buffered)
     __shared__ double sh_red[4];
 
@@ -245,7 +286,6 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
     const int hsize = hp_col(n, n);
     double* Zs = Hs + hsize;                                    // nr x n
     double* xs = Zs + (int64_t)nr * n;                          // nw x 2n (eigenvector scratch)
-    double* Us = xs + (int64_t)nw * 2 * n;                      // (CH+4)^2 chunk transform
     HP H{Hs, n};
     const int r0 = blockIdx.x * nr;
     const int nrows = min(nr, n - r0);
@@ -285,10 +325,23 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
     const double eps = defl_tol;             // deflation: |h(k,k-1)| <= eps (|h(k-1,k-1)| + |h(k,k)|)
     if (tid == 0) { sh_stop = 0; sh_iter_total = 0; }
     __syncthreads();
-    // ---- implicit double-shift QR (all waves; two barriers per bulge step)
+    // ---- implicit double-shift QR (all waves; one barrier per bulge step)
+    // Roles within bulge step k (reflector P_k on rows/columns k .. k+m-1, m = 3, or 2
+    // for the final step of a sweep), fixed by the thread index:
+    //   tid <= min(k+3, hi)      column update of row tid; the rows k .. k+m-1 first
+    //                            apply the row update to their corner entries
+    //   k+m <= tid-1 < n         row update of column tid-1
+    //   tid >= nt - nrows        column update of one row of this work-group's Z slab
+    //   tid == nt - nrows - 1    deferred write of the column that step k-1 reduced
+    // The roles touch disjoint entries, so the only barrier is the one that ends the step.
     {
         int hi = n - 1, its = 0, total = 0, parity = 0;
         bool stop = false;
+        const int zt0 = nt - nrows;              // first Z-role thread
+        const int pend_t = zt0 - 1;              // thread doing the deferred writes
+        const bool zrole = tid >= zt0;
+        // offset (from Hs) of this thread's row-update column tid-1 or Z-slab row
+        const int base_t = (tid >= 1 && tid <= n) ? hp_col(tid - 1, n) : (zrole ? hsize + (tid - zt0) * n : 0);
         if (tid == 0) { sh_lc[0] = 0; sh_lc[1] = 0; }
         __syncthreads();
         while (hi >= 0) {
@@ -367,137 +420,79 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
             const double y0 = H(l + 1, l) * (H(l, l) + H(l + 1, l + 1) - s);
             const double z0 = H(l + 1, l) * H(l + 2, l + 1);
             __syncthreads();   // every thread has read the shift inputs before H changes
-            // The bulge is chased in chunks of at most CH steps (steps l .. hi-2 use 3x3
-            // reflectors, step hi-1 the final 2x2 one).  Within a chunk one wave updates only
-            // the window [ws, we] of H and accumulates the chunk's reflectors into U (W x W);
-            // afterwards all waves apply U to the rows above the window, the columns right
-            // of it and this work-group's rows of Z.
-            for (int k0 = l; k0 <= hi - 1; k0 += CH) {
-                const int k1 = min(k0 + CH, hi);             // steps k0 .. k1-1
-                const int ws = max(l, k0 - 1);
-                const int we = min(hi, k1 + 2);
-                const int W = we - ws + 1;
-                if (wave == 0) {
-                    for (int e = lane; e < W * W; e += 64) Us[e] = (e % W == e / W) ? 1.0 : 0.0;   // U = I
-                    for (int k = k0; k < k1; ++k) {
-                        const bool last = (k == hi - 1);
-                        double x, y, z;
-                        if (k == l) { x = x0; y = y0; z = last ? 0.0 : z0; }
-                        else { x = H(k, k - 1); y = H(k + 1, k - 1); z = last ? 0.0 : H(k + 2, k - 1); }
-                        double v1, v2, tk, beta;
-                        house3(x, y, z, &v1, &v2, &tk, &beta);
-                        if (last) v2 = 0.0;
-                        wave_sync();   // x, y, z read before the rows change
-                        if (tk != 0.0) {
-                            const int c0 = max(l, k - 1);
-                            const int j = c0 + lane;                  // left: rows k..k+2, window columns
-                            if (j <= we) {
-                                double* hk = &H(k, j);
-                                if (last) {
-                                    const double w = (hk[0] + v1 * hk[1]) * tk;
-                                    hk[0] -= w; hk[1] -= w * v1;
-                                } else {
-                                    const double w = (hk[0] + v1 * hk[1] + v2 * hk[2]) * tk;
-                                    hk[0] -= w; hk[1] -= w * v1; hk[2] -= w * v2;
-                                }
-                            }
-                            wave_sync();
-                            if (lane == 0 && k > l) {
-                                H(k, k - 1) = beta; H(k + 1, k - 1) = 0.0;
-                                if (!last) H(k + 2, k - 1) = 0.0;
-                            }
-                            const int i = ws + lane;                  // right: window rows, columns k..k+2
-                            if (i <= min(k + 3, hi)) {
-                                double* c0p = &H(0, k);
-                                double* c1p = &H(0, k + 1);
-                                if (last) {
-                                    const double w = (c0p[i] + v1 * c1p[i]) * tk;
-                                    c0p[i] -= w; c1p[i] -= w * v1;
-                                } else {
-                                    double* c2p = &H(0, k + 2);
-                                    const double w = (c0p[i] + v1 * c1p[i] + v2 * c2p[i]) * tk;
-                                    c0p[i] -= w; c1p[i] -= w * v1; c2p[i] -= w * v2;
-                                }
-                            }
-                            if (lane < W) {                           // U <- U P_k
-                                double* u = Us + lane;                // row `lane`, column stride W
-                                const int cb = k - ws;
-                                if (last) {
-                                    const double w = (u[cb * W] + v1 * u[(cb + 1) * W]) * tk;
-                                    u[cb * W] -= w; u[(cb + 1) * W] -= w * v1;
-                                } else {
-                                    const double w = (u[cb * W] + v1 * u[(cb + 1) * W] + v2 * u[(cb + 2) * W]) * tk;
-                                    u[cb * W] -= w; u[(cb + 1) * W] -= w * v1; u[(cb + 2) * W] -= w * v2;
-                                }
-                            }
-                            wave_sync();
-                        }
+            int pk = -1;       // column reduced by the previous step, written one step late
+            double pbeta = 0.0;
+            // packed offsets of columns k-1 .. k+2, advanced by the column lengths min(j+4, n)
+            int hm = hp_col(max(l - 1, 0), n), hk0 = hp_col(l, n), hk1 = hp_col(l + 1, n), hk2 = hp_col(l + 2, n);
+            double e0 = 0.0, e1 = 0.0, e2 = 0.0;   // this thread's operands, carried between steps
+            int prole = 0;
+            for (int k = l; k <= hi - 1; ++k) {
+                const int m = (k == hi - 1) ? 2 : 3;
+                const int crow = min(k + 3, hi);
+                if (k > l) { hm = hk0; hk0 = hk1; hk1 = hk2; hk2 += min(k + 5, n); }
+                // ---- loads, all issued before the reflector is formed
+                double x = x0, y = y0, z = z0;
+                if (k > l) { x = Hs[hm + k]; y = Hs[hm + k + 1]; z = Hs[hm + k + 2]; }
+                // role: 1 column update of row tid, 2 row update of column tid-1, 3 Z row
+                const bool colr = tid <= crow;
+                const int role = colr ? 1 : (zrole ? 3 : ((tid - 1 >= k + m && tid <= n) ? 2 : 0));
+                const int o0 = colr ? hk0 + tid : base_t + k;
+                const int o1 = colr ? hk1 + tid : base_t + k + 1;
+                const int o2 = colr ? hk2 + tid : base_t + k + 2;
+                // a thread that keeps its role finds two of its operands in registers (the
+                // entries it updated in the previous step); only the third is new
+                if (role != prole || k == l) { e0 = Hs[o0]; e1 = Hs[o1]; }
+                e2 = Hs[o2];
+                prole = role;
+                // the corner C(a, b) = H(k+a, k+b) is needed only by the waves holding rows k..k+m-1
+                const bool cw = (wave == (k >> 6)) || (wave == ((k + m - 1) >> 6));
+                double c00 = 0.0, c10 = 0.0, c20 = 0.0, c01 = 0.0, c11 = 0.0, c21 = 0.0, c02 = 0.0, c12 = 0.0, c22 = 0.0;
+                if (cw) {
+                    c00 = Hs[hk0 + k]; c10 = Hs[hk0 + k + 1]; c20 = Hs[hk0 + k + 2];
+                    c01 = Hs[hk1 + k]; c11 = Hs[hk1 + k + 1]; c21 = Hs[hk1 + k + 2];
+                    c02 = Hs[hk2 + k]; c12 = Hs[hk2 + k + 1]; c22 = Hs[hk2 + k + 2];
+                }
+                if (m == 2) { z = 0.0; e2 = 0.0; c20 = 0.0; c21 = 0.0; c02 = 0.0; c12 = 0.0; c22 = 0.0; }
+                double d, t, beta;
+                reflector3(x, y, z, &d, &t, &beta);
+                // ---- P_k = I - t u u^T, u = (d, y, z), applied to the operands: rows k..k+m-1
+                // of the corner first take the row update (s_b), then every role applies the
+                // same formula (P is symmetric, so rows and columns transform alike)
+                if (t != 0.0) {
+                    if (cw) {
+                        const double s0 = (d * c00 + y * c10 + z * c20) * t;
+                        const double s1 = (d * c01 + y * c11 + z * c21) * t;
+                        const double s2 = (d * c02 + y * c12 + z * c22) * t;
+                        const int a = tid - k;
+                        const double ua = !colr ? 0.0 : (a == 0 ? d : (a == 1 ? y : (a == 2 ? z : 0.0)));
+                        e0 -= ua * s0;
+                        e1 -= ua * s1;
+                        e2 -= ua * s2;
+                    }
+                    const double w = (d * e0 + y * e1 + z * e2) * t;
+                    e0 -= w * d;
+                    e1 -= w * y;
+                    e2 -= w * z;
+                    if (role != 0) {
+                        Hs[o0] = e0;
+                        Hs[o1] = e1;
+                        if (m == 3) Hs[o2] = e2;
                     }
                 }
-                __syncthreads();
-                // delayed updates with U (column-major W x W in Us):
-                //   rows [0, ws) of the window columns:       H(i, ws+c) <- sum_m H(i, ws+m) U(m, c)
-                //   window rows of columns (we, n):            H(ws+r, j) <- sum_m U(m, r) H(ws+m, j)
-                //   this work-group's rows of Z:               Z(rl, ws+c) <- sum_m Z(rl, ws+m) U(m, c)
-                const int nstrip = (W + 7) / 8;
-                const int ta = ws * nstrip, tb = (n - 1 - we) * nstrip, tc = nrows * nstrip;
-                const int ntask = ta + tb + tc;
-                double outv[DT][8];
-#pragma unroll
-                for (int q = 0; q < DT; ++q) {
-                    const int task = tid + q * nt;
-                    if (task >= ntask) continue;
-                    double vin[CH + 4];
-                    int strip;
-                    if (task < ta) {
-                        const int i = task / nstrip; strip = task % nstrip;
-#pragma unroll
-                        for (int m = 0; m < CH + 4; ++m) vin[m] = m < W ? H(i, ws + m) : 0.0;
-                    } else if (task < ta + tb) {
-                        const int j = we + 1 + (task - ta) / nstrip; strip = (task - ta) % nstrip;
-                        const double* col = &H(ws, j);
-#pragma unroll
-                        for (int m = 0; m < CH + 4; ++m) vin[m] = m < W ? col[m] : 0.0;
-                    } else {
-                        const int rl = (task - ta - tb) / nstrip; strip = (task - ta - tb) % nstrip;
-                        const double* z = Zs + rl * n + ws;
-#pragma unroll
-                        for (int m = 0; m < CH + 4; ++m) vin[m] = m < W ? z[m] : 0.0;
-                    }
-                    const bool transposed = (task >= ta && task < ta + tb);
-#pragma unroll
-                    for (int c8 = 0; c8 < 8; ++c8) {
-                        const int c = strip * 8 + c8;
-                        double acc = 0.0;
-                        if (c < W) {
-#pragma unroll
-                            for (int m = 0; m < CH + 4; ++m)
-                                if (m < W) acc += vin[m] * (transposed ? Us[c * W + m] : Us[m + c * W]);
-                        }
-                        outv[q][c8] = acc;
-                    }
+                if (tid == pend_t && pk >= 0) {             // column pk: (beta, 0, 0) below its subdiagonal
+                    H(pk + 1, pk) = pbeta; H(pk + 2, pk) = 0.0;
+                    if (pk + 3 <= hi) H(pk + 3, pk) = 0.0;
                 }
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < DT; ++q) {
-                    const int task = tid + q * nt;
-                    if (task >= ntask) continue;
-#pragma unroll
-                    for (int c8 = 0; c8 < 8; ++c8) {
-                        if (task < ta) {
-                            const int i = task / nstrip, c = (task % nstrip) * 8 + c8;
-                            if (c < W) H(i, ws + c) = outv[q][c8];
-                        } else if (task < ta + tb) {
-                            const int j = we + 1 + (task - ta) / nstrip, r = ((task - ta) % nstrip) * 8 + c8;
-                            if (r < W) H(ws + r, j) = outv[q][c8];
-                        } else {
-                            const int rl = (task - ta - tb) / nstrip, c = ((task - ta - tb) % nstrip) * 8 + c8;
-                            if (c < W) Zs[rl * n + ws + c] = outv[q][c8];
-                        }
-                    }
-                }
+                if (k > l) { pk = k - 1; pbeta = beta; }
+                // operands of the next step: this step's second and third entries
+                e0 = e1; e1 = e2;
                 __syncthreads();
             }
+            if (tid == pend_t && pk >= 0) {
+                H(pk + 1, pk) = pbeta; H(pk + 2, pk) = 0.0;
+                if (pk + 3 <= hi) H(pk + 3, pk) = 0.0;
+            }
+            __syncthreads();
         }
         if (tid == 0) { sh_stop = stop ? 1 : 0; sh_iter_total = total; }
     }
@@ -706,9 +701,9 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
     const int nr = eig_rows_per_wg(n);
     const int grid = eig_grid(n);
     const int hsize = hp_col(n, n);
-    const int nw = 4;
+    const int nw = FR_THREADS / 64;
     const size_t lds = (size_t)(round_up(n, 2) / 2) * 8 + (size_t)hsize * 8 + (size_t)nr * n * 8 +
-                       (size_t)nw * 2 * n * 8 + (size_t)(CH + 4) * (CH + 4) * 8;
+                       (size_t)nw * 2 * n * 8;
     if (lds > 160 * 1024 - 512) return hipErrorInvalidValue;
     hipLaunchKernelGGL(francis_kernel, dim3(grid), dim3(64 * nw), lds, s, n, nr, w.H, w.V, w.tau, w.Wraw,
                        w.wr, w.wi, w.kind0, w.X, info, defl_tol);
