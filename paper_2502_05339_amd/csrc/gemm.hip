@@ -8,6 +8,8 @@
 //            Used for the Gram products of CholeskyQR (FP64 MFMA), X^T Q, the
 //            projection Q^T Z (one pass over both X and X'), Phi^T Phi, Phi^T x0 and
 //            the adjoint's Phi^T R.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -29,138 +31,130 @@ hipError_t fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v) {
 }
 
 // ------------------------------------------------------------------------ NN
-// Work-group: 256 threads = 4 waves stacked in rows; each wave owns 16*RB rows
-// and all n (<= 16*NBW) columns; the work-group tile is 64*RB rows x n.  The k
-// dimension is consumed in chunks of KC = 16, each staged through LDS (A as
-// [k][row], B as [k][col]) so that MFMA operand reads are bank-conflict free.
-template <typename T, int RB, int NBW, bool VEC>
+// Work-group: 256 threads = 4 waves; each wave owns WR = 16*VW consecutive rows
+// (VW = 16 / sizeof(T): 4 FP32 or 2 FP64 rows per 16-byte load) and all n
+// (<= 16*NB) columns.  The A operand comes straight from memory: in k-step s, lane
+// l loads the VW consecutive rows r0 + VW*(l%16) .. of column k0 + 4s + l/16 with
+// one vector load, and element e of that vector is lane l's A operand of MFMA
+// row-block e.  Row-block e of a wave therefore holds the rows {r0 + VW*i + e},
+// i = 0..15: a permutation of the wave's rows that the epilogue undoes, since it
+// puts VW consecutive rows of one column in one lane again (vector stores of C).
+// B is staged through LDS in chunks of KB rows as [k][col].  C may alias A (each
+// wave reads all of its rows of A before it writes them), which the in-place
+// CholeskyQR apply Q = Y R^-1 relies on.
+template <typename T, int NB, bool VEC>
 __global__ void __launch_bounds__(256)
 gemm_nn_kernel(const T* A, int64_t lda, const T* __restrict__ B, int64_t ldb,
                T* C, int64_t ldc, int c_rowmajor, int64_t N, int K, int n,
                const int32_t* skip_unless)
 {
     if (skip_unless && *skip_unless == 0) return;
-    constexpr int KC = 16;
-    constexpr int BM = 64 * RB;
-    constexpr int PADA = (sizeof(T) == 4) ? 4 : 2;
-    constexpr int NP = 16 * NBW;
-    __shared__ T As[KC][BM + PADA];
-    __shared__ T Bs[KC][NP + PADA];
-
+    constexpr int VW = 16 / sizeof(T);
+    constexpr int WR = 16 * VW;
+    constexpr int KB = 32;
+    constexpr int NP = 16 * NB;
+    constexpr int PADB = (sizeof(T) == 4) ? 4 : 2;
+    __shared__ T Bs[KB][NP + PADB];
     typedef typename Acc<T>::type V;
+    typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type VT;
+
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
-    const int64_t row0 = (int64_t)blockIdx.x * BM;
-    const int ncb = (n + 15) / 16;
+    const int kq = lane >> 4;
+    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * WR;
+    const int64_t rl = r0 + VW * (lane & 15);
 
-    V acc[RB][NBW];
+    V acc[VW][NB];
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
+    for (int e = 0; e < VW; ++e)
 #pragma unroll
-        for (int cb = 0; cb < NBW; ++cb) acc[rb][cb] = zero_acc<V>();
+        for (int cb = 0; cb < NB; ++cb) acc[e][cb] = zero_acc<V>();
 
-    for (int k0 = 0; k0 < K; k0 += KC) {
-        // ---- stage A chunk: BM rows x KC columns (column-major in global)
-        if constexpr (VEC) {
-            constexpr int VW = 16 / sizeof(T);          // elements per 16-byte load
-            constexpr int NV = BM / VW * KC;
-            for (int idx = tid; idx < NV; idx += 256) {
-                int i = (idx % (BM / VW)) * VW;
-                int kk = idx / (BM / VW);
-                int64_t row = row0 + i;
-                int kcol = k0 + kk;
-                const T* src = A + (int64_t)kcol * lda + row;
-                if (kcol < K && row + VW <= N) {
-                    if constexpr (sizeof(T) == 4) {
-                        float4 v = *reinterpret_cast<const float4*>(src);
-                        As[kk][i] = v.x; As[kk][i + 1] = v.y; As[kk][i + 2] = v.z; As[kk][i + 3] = v.w;
-                    } else {
-                        double2 v = *reinterpret_cast<const double2*>(src);
-                        As[kk][i] = v.x; As[kk][i + 1] = v.y;
-                    }
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VW; ++e)
-                        As[kk][i + e] = (kcol < K && row + e < N) ? src[e] : T(0);
-                }
-            }
-        } else {
-            for (int idx = tid; idx < BM * KC; idx += 256) {
-                int i = idx % BM, kk = idx / BM;
-                int64_t row = row0 + i;
-                int kcol = k0 + kk;
-                As[kk][i] = (kcol < K && row < N) ? A[(int64_t)kcol * lda + row] : T(0);
-            }
-        }
-        // ---- stage B chunk: KC x NP
-        for (int idx = tid; idx < KC * NP; idx += 256) {
-            int kk = idx % KC, j = idx / KC;
-            int kr = k0 + kk;
+    for (int k0 = 0; k0 < K; k0 += KB) {
+        for (int idx = tid; idx < KB * NP; idx += 256) {
+            const int kk = idx % KB, j = idx / KB;
+            const int kr = k0 + kk;
             Bs[kk][j] = (kr < K && j < n) ? B[(int64_t)j * ldb + kr] : T(0);
         }
         __syncthreads();
 #pragma unroll
-        for (int ks = 0; ks < KC / 4; ++ks) {
-            const int kk = ks * 4 + (lane >> 4);
-            T a[RB];
+        for (int ks = 0; ks < KB; ks += 4) {
+            const int k = k0 + ks + kq;
+            T a[VW];
+            const T* src = A + (int64_t)k * lda + rl;
+            if (VEC && k < K && rl + VW <= N) {
+                const VT v = *reinterpret_cast<const VT*>(src);
+                if constexpr (VW == 4) { a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w; }
+                else { a[0] = v.x; a[1] = v.y; }
+            } else {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) a[rb] = As[kk][wave * 16 * RB + rb * 16 + (lane & 15)];
-#pragma unroll
-            for (int cb = 0; cb < NBW; ++cb) {
-                if (cb < ncb) {
-                    T bv = Bs[kk][cb * 16 + (lane & 15)];
-#pragma unroll
-                    for (int rb = 0; rb < RB; ++rb) acc[rb][cb] = mfma(a[rb], bv, acc[rb][cb]);
-                }
+                for (int e = 0; e < VW; ++e) a[e] = (k < K && rl + e < N) ? src[e] : T(0);
             }
+            T bv[NB];
+#pragma unroll
+            for (int cb = 0; cb < NB; ++cb) bv[cb] = Bs[ks + kq][cb * 16 + (lane & 15)];
+#pragma unroll
+            for (int e = 0; e < VW; ++e)
+#pragma unroll
+                for (int cb = 0; cb < NB; ++cb) acc[e][cb] = mfma(a[e], bv[cb], acc[e][cb]);
         }
         __syncthreads();
     }
 
-    // ---- epilogue
+    // ---- epilogue: row-block e, tile row i  ->  row r0 + VW*i + e
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        const int64_t tile0 = row0 + wave * 16 * RB + rb * 16;
+    for (int cb = 0; cb < NB; ++cb) {
+        const int col = cb * 16 + (lane & 15);
+        if (col >= n) continue;
 #pragma unroll
-        for (int cb = 0; cb < NBW; ++cb) {
-            if (cb >= ncb) continue;
-            const int col = cb * 16 + (lane & 15);
-            if (col >= n) continue;
-            if constexpr (sizeof(T) == 4) {
-                const int64_t rbase = tile0 + 4 * (lane >> 4);     // 4 consecutive rows
-                if (!c_rowmajor && VEC && rbase + 4 <= N) {
-                    float4 o = make_float4(acc[rb][cb][0], acc[rb][cb][1], acc[rb][cb][2], acc[rb][cb][3]);
-                    *reinterpret_cast<float4*>(C + (int64_t)col * ldc + rbase) = o;
-                    continue;
-                }
-            }
+        for (int v = 0; v < 4; ++v) {
+            const int64_t row = r0 + VW * acc_row<V>(lane, v);
+            if (!c_rowmajor && VEC && row + VW <= N) {
+                VT o;
+                if constexpr (VW == 4) { o.x = acc[0][cb][v]; o.y = acc[1][cb][v]; o.z = acc[2][cb][v]; o.w = acc[3][cb][v]; }
+                else { o.x = acc[0][cb][v]; o.y = acc[1][cb][v]; }
+                *reinterpret_cast<VT*>(C + (int64_t)col * ldc + row) = o;
+            } else {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t row = tile0 + acc_row<V>(lane, v);
-                if (row < N) {
-                    if (c_rowmajor) C[row * ldc + col] = acc[rb][cb][v];
-                    else C[(int64_t)col * ldc + row] = acc[rb][cb][v];
+                for (int e = 0; e < VW; ++e) {
+                    if (row + e < N) {
+                        if (c_rowmajor) C[(row + e) * ldc + col] = acc[e][cb][v];
+                        else C[(int64_t)col * ldc + row + e] = acc[e][cb][v];
+                    }
                 }
             }
         }
     }
 }
 
-template <typename T, int RB, int NBW>
+template <typename T, int NB>
 static hipError_t launch_nn_t(hipStream_t s, const T* A, int64_t lda, const T* B, int64_t ldb,
                               T* C, int64_t ldc, int c_rowmajor, int64_t N, int K, int n,
                               const int32_t* skip_unless)
 {
-    constexpr int BM = 64 * RB;
+    constexpr int BM = 4 * 16 * (16 / sizeof(T));
     dim3 grid((unsigned)ceil_div(N, BM));
     const int vw = 16 / sizeof(T);
     bool vec = (lda % vw == 0) && ((uintptr_t)A % 16 == 0) && (c_rowmajor || ((ldc % vw == 0) && ((uintptr_t)C % 16 == 0)));
     if (vec)
-        hipLaunchKernelGGL((gemm_nn_kernel<T, RB, NBW, true>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless);
+        hipLaunchKernelGGL((gemm_nn_kernel<T, NB, true>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless);
     else
-        hipLaunchKernelGGL((gemm_nn_kernel<T, RB, NBW, false>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless);
+        hipLaunchKernelGGL((gemm_nn_kernel<T, NB, false>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless);
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_nn_any(hipStream_t s, const T* a, int64_t lda, const T* b, int64_t ldb, T* c, int64_t ldc,
+                                int c_rowmajor, int64_t N, int K, int n, const int32_t* skip_unless)
+{
+    const int ncb = (n + 15) / 16;
+    if (ncb <= 2)  return launch_nn_t<T, 2>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 4)  return launch_nn_t<T, 4>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 6)  return launch_nn_t<T, 6>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 8)  return launch_nn_t<T, 8>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 10) return launch_nn_t<T, 10>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    return launch_nn_t<T, NN_MAX_CB>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
 }
 
 hipError_t gemm_nn(hipStream_t s, int dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
@@ -169,17 +163,9 @@ hipError_t gemm_nn(hipStream_t s, int dtype, const void* A, int64_t lda, const v
 {
     if (N <= 0 || n <= 0) return hipSuccess;
     if (n > 16 * NN_MAX_CB) return hipErrorInvalidValue;
-    if (dtype == DMD_F32) {
-        const float* a = (const float*)A; const float* b = (const float*)B; float* c = (float*)C;
-        if (n <= 64)  return launch_nn_t<float, 2, 4>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-        if (n <= 128) return launch_nn_t<float, 2, 8>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-        return launch_nn_t<float, 2, NN_MAX_CB>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-    } else {
-        const double* a = (const double*)A; const double* b = (const double*)B; double* c = (double*)C;
-        if (n <= 64)  return launch_nn_t<double, 1, 4>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-        if (n <= 128) return launch_nn_t<double, 1, 8>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-        return launch_nn_t<double, 1, NN_MAX_CB>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-    }
+    if (dtype == DMD_F32)
+        return launch_nn_any<float>(s, (const float*)A, lda, (const float*)B, ldb, (float*)C, ldc, c_rowmajor, N, K, n, skip_unless);
+    return launch_nn_any<double>(s, (const double*)A, lda, (const double*)B, ldb, (double*)C, ldc, c_rowmajor, N, K, n, skip_unless);
 }
 
 // ------------------------------------------------------------------------ TN
@@ -194,178 +180,353 @@ __device__ __forceinline__ void block_decode(int b, int sym, int nbi, int* bi, i
     *bi = b - j * (j + 1) / 2;
 }
 
-// Work-group: 512 threads = 8 waves.  Rows are consumed in chunks of RC staged in
-// LDS as [row][col]; the output's 16x16 blocks are dealt round-robin to the waves
-// (each wave holds up to MAXB accumulators).  gridDim.x = row splits, gridDim.y =
-// groups of 8*MAXB output blocks.
-template <typename Tin, typename Tc, int RC, int MAXB>
-__global__ void __launch_bounds__(512)
+// Work-group: 512 threads = 8 waves.  Rows are consumed in chunks of RC, staged in
+// LDS as [row][col] (so each MFMA operand read is 16 consecutive columns of one row)
+// with two buffers: the next chunk is fetched from memory into registers with 16-byte
+// loads while the current one feeds the MFMAs, then written to the other buffer, one
+// barrier per chunk.  Output tiling: the 16x16 blocks of C form an nbi x nbj grid; a
+// work-group (blockIdx.y) takes a 2RI x 4RJ tile of it and each of its 8 waves a
+// RI x RJ piece, so a row step of a wave reads RI + RJ operand fragments for RI*RJ
+// MFMAs.
+// Blocks past the grid edge are clamped onto the last block (recomputed, not stored),
+// which keeps the MFMA loop free of branches.  A symmetric product (B = A) stages A
+// only and computes the full square.  gridDim.x = row splits.
+constexpr int TN_THREADS = 512;
+constexpr int TN_MAXT = 4;     // staged 16-byte vectors per thread and chunk
+
+__host__ __device__ constexpr int tn_ld(int ncol_p, int esz) {
+    // row stride of a staged chunk: 16 elements past a multiple of 64 (FP32) or 32
+    // (FP64) so that the four k-rows of one operand read fall in different banks
+    return esz == 4 ? ((ncol_p + 63) / 64) * 64 + 16 : ((ncol_p + 31) / 32) * 32 + 16;
+}
+
+// One staging task moves VWI consecutive elements of one operand: VWI rows of a
+// column (column-major operand) or VWI columns of a row (row-major operand).  The
+// tasks of a thread are the same for every chunk, so they are decoded once.
+template <typename Tin, typename Tc>
+struct TnStage {
+    static constexpr int VWI = 16 / sizeof(Tin);
+    typedef typename std::conditional<sizeof(Tin) == 4, float4, double2>::type VT;
+    __host__ __device__ static int ntasks(int rowmajor, int ncol, int ncol_p, int rc) {
+        return rowmajor ? rc * (ncol_p / VWI) : ncol * (rc / VWI);
+    }
+    const Tin* src;     // element of row 0 of the split's first chunk
+    int64_t step;       // elements to advance per row of chunk offset (1 or ld)
+    int soff;           // LDS element offset of the first element (buffer-relative)
+    int sstride;        // LDS stride between the VWI elements
+    int roff;           // row of the task inside the chunk (first of VWI rows if column-major)
+    int rowmajor;       // 0 / 1
+    int cvalid;         // row-major: number of the VWI columns that exist (guard of the scalar path)
+    __device__ void init(const Tin* X, int64_t ld, int rm, int ncol, int ncol_p, int rc, int t, int ldsld, int base) {
+        rowmajor = rm;
+        if (rm) {
+            const int per = ncol_p / VWI;
+            const int rr = t / per, cq = t % per;
+            src = X + (int64_t)rr * ld + VWI * cq;
+            step = ld;
+            soff = base + rr * ldsld + VWI * cq;
+            sstride = 1;
+            roff = rr;
+            cvalid = min(VWI, max(0, ncol - VWI * cq));
+        } else {
+            const int per = rc / VWI;
+            const int c = t / per, q = t % per;
+            src = X + (int64_t)c * ld + VWI * q;
+            step = 1;
+            soff = base + VWI * q * ldsld + c;
+            sstride = ldsld;
+            roff = VWI * q;
+            cvalid = VWI;
+        }
+    }
+    __device__ VT load(int64_t c0, int64_t r_end, int vec) const {
+        VT v;
+        Tin* pv = reinterpret_cast<Tin*>(&v);
+        const Tin* p = src + c0 * step;
+        const int64_t row = c0 + roff;
+        if (rowmajor) {
+            if (vec && row < r_end) v = *reinterpret_cast<const VT*>(p);
+            else {
+#pragma unroll
+                for (int e = 0; e < VWI; ++e) pv[e] = (row < r_end && e < cvalid) ? p[e] : Tin(0);
+            }
+        } else {
+            if (vec && row + VWI <= r_end) v = *reinterpret_cast<const VT*>(p);
+            else {
+#pragma unroll
+                for (int e = 0; e < VWI; ++e) pv[e] = (row + e < r_end) ? p[e] : Tin(0);
+            }
+        }
+        return v;
+    }
+    __device__ void store(Tc* buf, const VT& v) const {
+        const Tin* pv = reinterpret_cast<const Tin*>(&v);
+#pragma unroll
+        for (int e = 0; e < VWI; ++e) buf[soff + e * sstride] = (Tc)pv[e];
+    }
+};
+
+template <typename Tin, typename Tc, int RC, int RI, int RJ>
+__global__ void __launch_bounds__(TN_THREADS)
 gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
                const Tin* __restrict__ B, int64_t ldb, int b_rowmajor, int nb,
-               int sym, int64_t N, int64_t rows_per_split, double* __restrict__ P,
+               int sym, int64_t N, int64_t rows_per_split, int vec, double* __restrict__ P,
                const int32_t* skip_unless)
 {
     if (skip_unless && *skip_unless == 0) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Tc* smem = reinterpret_cast<Tc*>(smem_raw);
+    typedef TnStage<Tin, Tc> St;
+    typedef typename St::VT VT;
     typedef typename Acc<Tc>::type V;
-    constexpr int PAD = (sizeof(Tc) == 4) ? 16 : 8;
     const int ka_p = (int)round_up(ka, 16), nb_p = (int)round_up(nb, 16);
-    const int lda_s = ka_p + PAD, ldb_s = nb_p + PAD;
-    Tc* As = smem;
-    Tc* Bs = sym ? smem : smem + RC * lda_s;
+    const int lda_s = tn_ld(ka_p, sizeof(Tc)), ldb_s = tn_ld(nb_p, sizeof(Tc));
+    const int bufsz = RC * lda_s + (sym ? 0 : RC * ldb_s);
+    Tc* buf0 = reinterpret_cast<Tc*>(smem_raw);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform -> scalar registers
     const int nbi = ka_p / 16, nbj = nb_p / 16;
-    // enumerate blocks: column-major over (bi, bj); symmetric keeps bi <= bj
     const int64_t split = blockIdx.x;
     const int64_t r_begin = split * rows_per_split;
     const int64_t r_end = min(N, r_begin + rows_per_split);
 
-    const int nblocks = sym ? nbj * (nbj + 1) / 2 : nbi * nbj;
-    const int first = blockIdx.y * 8 * MAXB;
-    int aoff[MAXB], boff[MAXB];
-    uint32_t valid = 0;
+    // this wave's RI x RJ piece of the work-group's 2RI x 4RJ tile
+    const int ntj = (int)ceil_div(nbj, 4 * RJ);
+    const int ti = blockIdx.y / ntj, tj = blockIdx.y % ntj;
+    const int bi0 = ti * 2 * RI + (wave >> 2) * RI;
+    const int bj0 = tj * 4 * RJ + (wave & 3) * RJ;
+    V acc[RI][RJ];
 #pragma unroll
-    for (int t = 0; t < MAXB; ++t) {
-        const int b = first + wave + 8 * t;
-        int bi, bj;
-        block_decode(b, sym, nbi, &bi, &bj);
-        if (b < nblocks) valid |= 1u << t;
-        aoff[t] = __builtin_amdgcn_readfirstlane(bi * 16);
-        boff[t] = __builtin_amdgcn_readfirstlane(bj * 16);
-    }
-    V acc[MAXB];
+    for (int i = 0; i < RI; ++i)
 #pragma unroll
-    for (int t = 0; t < MAXB; ++t) acc[t] = zero_acc<V>();
+        for (int j = 0; j < RJ; ++j) acc[i][j] = zero_acc<V>();
 
-    for (int64_t c0 = r_begin; c0 < r_end; c0 += RC) {
-        // ---- stage A rows [c0, c0+RC) x ka_p
-        if (a_rowmajor) {
-            for (int idx = tid; idx < RC * ka_p; idx += 512) {
-                int c = idx % ka_p, rr = idx / ka_p;
-                int64_t row = c0 + rr;
-                As[rr * lda_s + c] = (row < r_end && c < ka) ? (Tc)A[row * lda + c] : Tc(0);
-            }
-        } else {
-            for (int idx = tid; idx < RC * ka_p; idx += 512) {
-                int rr = idx % RC, c = idx / RC;
-                int64_t row = c0 + rr;
-                As[rr * lda_s + c] = (row < r_end && c < ka) ? (Tc)A[(int64_t)c * lda + row] : Tc(0);
-            }
-        }
-        if (!sym) {
-            if (b_rowmajor) {
-                for (int idx = tid; idx < RC * nb_p; idx += 512) {
-                    int c = idx % nb_p, rr = idx / nb_p;
-                    int64_t row = c0 + rr;
-                    Bs[rr * ldb_s + c] = (row < r_end && c < nb) ? (Tc)B[row * ldb + c] : Tc(0);
-                }
-            } else {
-                for (int idx = tid; idx < RC * nb_p; idx += 512) {
-                    int rr = idx % RC, c = idx / RC;
-                    int64_t row = c0 + rr;
-                    Bs[rr * ldb_s + c] = (row < r_end && c < nb) ? (Tc)B[(int64_t)c * ldb + row] : Tc(0);
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll 1
+    const int na = St::ntasks(a_rowmajor, ka, ka_p, RC);
+    const int nbt = sym ? 0 : St::ntasks(b_rowmajor, nb, nb_p, RC);
+    const int ntask = na + nbt;
+    St task[TN_MAXT];
+    bool has[TN_MAXT];
+#pragma unroll
+    for (int q = 0; q < TN_MAXT; ++q) {
+        const int t = tid + q * TN_THREADS;
+        has[q] = t < ntask;
+        if (t < na) task[q].init(A + r_begin * (a_rowmajor ? lda : 1), lda, a_rowmajor, ka, ka_p, RC, t, lda_s, 0);
+        else task[q].init(B + r_begin * (b_rowmajor ? ldb : 1), ldb, b_rowmajor, nb, nb_p, RC,
+                          has[q] ? t - na : 0, ldb_s, RC * lda_s);
+    }
+    VT pre[TN_MAXT];
+    auto fetch = [&](int64_t c0) {   // c0: chunk offset inside the split
+#pragma unroll
+        for (int q = 0; q < TN_MAXT; ++q)
+            if (has[q]) pre[q] = task[q].load(c0, r_end - r_begin, vec);
+    };
+    auto put = [&](Tc* buf) {
+#pragma unroll
+        for (int q = 0; q < TN_MAXT; ++q)
+            if (has[q]) task[q].store(buf, pre[q]);
+    };
+
+    const int64_t nchunk = ceil_div(r_end - r_begin, (int64_t)RC);
+    if (nchunk > 0) {
+        fetch(0);
+        put(buf0);
+    }
+    __syncthreads();
+    // clamped fragment columns (in elements)
+    const int amax = (nbi - 1) * 16, bmax = (nbj - 1) * 16;
+    for (int64_t ci = 0; ci < nchunk; ++ci) {
+        Tc* cur = buf0 + (ci & 1) * bufsz;
+        Tc* nxt = buf0 + ((ci + 1) & 1) * bufsz;
+        const bool more = ci + 1 < nchunk;
+        if (more) fetch((ci + 1) * RC);
+        const Tc* As = cur;
+        const Tc* Bs = sym ? cur : cur + RC * lda_s;
+        const int bld = sym ? lda_s : ldb_s;
+#pragma unroll
         for (int ks = 0; ks < RC / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
             const Tc* arow = As + kk * lda_s + (lane & 15);
-            const Tc* brow = Bs + kk * (sym ? lda_s : ldb_s) + (lane & 15);
+            const Tc* brow = Bs + kk * bld + (lane & 15);
+            Tc av[RI], bv[RJ];
 #pragma unroll
-            for (int t = 0; t < MAXB; ++t) {
-                if (valid & (1u << t)) {
-                    Tc av = arow[aoff[t]];
-                    Tc bv = brow[boff[t]];
-                    acc[t] = mfma(av, bv, acc[t]);
-                }
-            }
+            for (int i = 0; i < RI; ++i) av[i] = arow[min((bi0 + i) * 16, amax)];
+#pragma unroll
+            for (int j = 0; j < RJ; ++j) bv[j] = brow[min((bj0 + j) * 16, bmax)];
+#pragma unroll
+            for (int i = 0; i < RI; ++i)
+#pragma unroll
+                for (int j = 0; j < RJ; ++j) acc[i][j] = mfma(av[i], bv[j], acc[i][j]);
         }
+        if (more) put(nxt);
         __syncthreads();
     }
 
     double* out = P + split * (int64_t)ka * nb;
 #pragma unroll
-    for (int t = 0; t < MAXB; ++t) {
-        if (valid & (1u << t)) {
-            const int j = boff[t] + (lane & 15);
+    for (int i = 0; i < RI; ++i) {
+#pragma unroll
+        for (int j = 0; j < RJ; ++j) {
+            if (bi0 + i >= nbi || bj0 + j >= nbj) continue;
+            const int jj = (bj0 + j) * 16 + (lane & 15);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = aoff[t] + acc_row<V>(lane, v);
-                if (i < ka && j < nb) out[(int64_t)j * ka + i] = (double)acc[t][v];
+                const int ii = (bi0 + i) * 16 + acc_row<V>(lane, v);
+                if (ii < ka && jj < nb) out[(int64_t)jj * ka + ii] = (double)acc[i][j][v];
             }
         }
     }
 }
 
-// out(i, j) = sum_s P_s(i, j), summed in split order.  In symmetric mode only the
-// upper block triangle of P is valid and the rest is mirrored.
-__global__ void reduce_partials_kernel(const double* __restrict__ P, int nsplit, int ka, int nb,
-                                       int sym, double* out, int64_t ldo, float* out32,
-                                       int64_t ldo32, const int32_t* skip_unless)
+// out(i, j) = sum_s P_s(i, j) in a fixed order: work-group = 64 consecutive outputs x
+// RQ split ranges; thread (o, q) sums the splits s = q, q + RQ, ... of output o, and
+// the RQ partial sums are added in q order.  In symmetric mode the lower blocks are
+// taken from the mirrored upper ones (the products compute the full square, but the
+// mirror keeps the output exactly symmetric).
+constexpr int RQ = 8;
+__global__ void __launch_bounds__(64 * RQ)
+reduce_partials_kernel(const double* __restrict__ P, int nsplit, int ka, int nb,
+                       int sym, double* out, int64_t ldo, float* out32,
+                       int64_t ldo32, const int32_t* skip_unless)
 {
     if (skip_unless && *skip_unless == 0) return;
+    __shared__ double part[RQ][64];
     const int64_t tot = (int64_t)ka * nb;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        int i = (int)(e % ka), j = (int)(e / ka);
+    const int o = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t e = (int64_t)blockIdx.x * 64 + o;
+    double s = 0.0;
+    int i = 0, j = 0;
+    if (e < tot) {
+        i = (int)(e % ka); j = (int)(e / ka);
         int si = i, sj = j;
         if (sym && (i / 16) > (j / 16)) { si = j; sj = i; }
         const double* p = P + (int64_t)sj * ka + si;
-        double s = 0.0;
-        for (int k = 0; k < nsplit; ++k) s += p[(int64_t)k * tot];
-        if (out) out[(int64_t)j * ldo + i] = s;
-        if (out32) out32[(int64_t)j * ldo32 + i] = (float)s;
+        for (int k = q; k < nsplit; k += RQ) s += p[(int64_t)k * tot];
+    }
+    part[q][o] = s;
+    __syncthreads();
+    if (q == 0 && e < tot) {
+        double t = part[0][o];
+#pragma unroll
+        for (int k = 1; k < RQ; ++k) t += part[k][o];
+        if (out) out[(int64_t)j * ldo + i] = t;
+        if (out32) out32[(int64_t)j * ldo32 + i] = (float)t;
     }
 }
 
 static int tn_splits(int64_t N, int rc) {
-    int64_t s = N / (int64_t)(rc * 16);
+    int64_t s = ceil_div(N, (int64_t)rc);
     if (s < 1) s = 1;
     if (s > TN_MAX_SPLITS) s = TN_MAX_SPLITS;
     return (int)s;
 }
 
+template <typename Tin, typename Tc>
+static size_t tn_lds(int rc, int ka, int nb, int sym) {
+    const size_t per = (size_t)rc * tn_ld((int)round_up(ka, 16), sizeof(Tc)) +
+                       (sym ? 0 : (size_t)rc * tn_ld((int)round_up(nb, 16), sizeof(Tc)));
+    return 2 * per * sizeof(Tc);
+}
+
+// wave tiles (RI x RJ output blocks) instantiated per accumulator type
+#define TN_TILES_F32(X, Ti, Tc, RC) X(Ti, Tc, RC, 2, 2) X(Ti, Tc, RC, 3, 3) X(Ti, Tc, RC, 5, 1) \
+    X(Ti, Tc, RC, 5, 4) X(Ti, Tc, RC, 5, 5) X(Ti, Tc, RC, 7, 3) X(Ti, Tc, RC, 10, 3)
+#define TN_TILES_F64(X, Ti, Tc, RC) X(Ti, Tc, RC, 2, 2) X(Ti, Tc, RC, 3, 3) X(Ti, Tc, RC, 4, 4) \
+    X(Ti, Tc, RC, 5, 1) X(Ti, Tc, RC, 5, 3)
+#define TN_INSTANCES(X) \
+    TN_TILES_F32(X, float, float, 16) TN_TILES_F32(X, float, float, 8) \
+    TN_TILES_F64(X, float, double, 16) TN_TILES_F64(X, float, double, 8) \
+    TN_TILES_F64(X, double, double, 16) TN_TILES_F64(X, double, double, 8)
+
 hipError_t gemm_prepare()
 {
-    hipError_t e;
-    e = hipFuncSetAttribute((const void*)gemm_tn_kernel<float, float, 32, 24>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)gemm_tn_kernel<float, double, 16, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)gemm_tn_kernel<double, double, 16, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    hipError_t e = hipSuccess;
+#define TN_ATTR(Ti, Tc, RC, RI, RJ) \
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_tn_kernel<Ti, Tc, RC, RI, RJ>, \
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    TN_INSTANCES(TN_ATTR)
+#undef TN_ATTR
+    return e;
 }
 
 size_t gemm_tn_partial_bytes(int64_t N, int ka, int nb) {
     return (size_t)TN_MAX_SPLITS * (size_t)ka * (size_t)nb * sizeof(double);
 }
 
+template <typename Tin, typename Tc, int RC, int RI, int RJ>
+static hipError_t launch_tn_k(hipStream_t s, const Tin* A, int64_t lda, int a_rm, int ka,
+                              const Tin* B, int64_t ldb, int b_rm, int nb, int sym, int64_t N, int vec,
+                              double* P, int* nsplit_out, const int32_t* skip_unless)
+{
+    const int nbi = (int)ceil_div(ka, 16), nbj = (int)ceil_div(nb, 16);
+    const int gy = (int)(ceil_div(nbi, 2 * RI) * ceil_div(nbj, 4 * RJ));
+    const int ns = tn_splits(N, RC);
+    const int64_t rps = round_up(ceil_div(N, ns), RC);
+    const int ns_eff = (int)ceil_div(N, rps);
+    const size_t lds = tn_lds<Tin, Tc>(RC, ka, nb, sym);
+    hipLaunchKernelGGL((gemm_tn_kernel<Tin, Tc, RC, RI, RJ>), dim3(ns_eff, gy), dim3(TN_THREADS), lds, s,
+                       A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, rps, vec, P, skip_unless);
+    *nsplit_out = ns_eff;
+    return hipGetLastError();
+}
+
+// Wave tile: the instantiated shape that covers the block grid with the fewest
+// work-groups per row split, then the least recomputed (clamped) blocks.
+template <typename Tin, typename Tc, int RC>
+static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_rm, int ka,
+                               const Tin* B, int64_t ldb, int b_rm, int nb, int sym, int64_t N, int vec,
+                               double* P, int* nsplit_out, const int32_t* skip_unless)
+{
+    const int nbi = (int)ceil_div(ka, 16), nbj = (int)ceil_div(nb, 16);
+    int best = -1;
+    int64_t best_cost = INT64_MAX;
+    int idx = 0;
+    auto consider = [&](int ri, int rj) {
+        const int64_t gy = ceil_div(nbi, 2 * ri) * ceil_div(nbj, 4 * rj);
+        const int64_t cost = gy * 100000 + gy * 8 * ri * rj;   // fewest re-reads first, then MFMA work
+        if (cost < best_cost) { best_cost = cost; best = idx; }
+        ++idx;
+    };
+#define TN_CASE(k, RI, RJ) \
+    case k: return launch_tn_k<Tin, Tc, RC, RI, RJ>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
+    if constexpr (sizeof(Tc) == 4) {
+        consider(2, 2); consider(3, 3); consider(5, 1); consider(5, 4); consider(5, 5); consider(7, 3); consider(10, 3);
+        switch (best) {
+            TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 4) TN_CASE(4, 5, 5) TN_CASE(5, 7, 3)
+            default: return launch_tn_k<Tin, Tc, RC, 10, 3>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
+        }
+    } else {
+        consider(2, 2); consider(3, 3); consider(4, 4); consider(5, 1); consider(5, 3);
+        switch (best) {
+            TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 4, 4) TN_CASE(3, 5, 1)
+            default: return launch_tn_k<Tin, Tc, RC, 5, 3>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
+        }
+    }
+#undef TN_CASE
+}
+
+// Largest row chunk whose two LDS buffers and staging registers fit.
 template <typename Tin, typename Tc>
 static hipError_t launch_tn_t(hipStream_t s, const Tin* A, int64_t lda, int a_rm, int ka,
                               const Tin* B, int64_t ldb, int b_rm, int nb, int sym, int64_t N,
                               double* P, int* nsplit_out, const int32_t* skip_unless)
 {
-    constexpr int RC = (sizeof(Tc) == 4) ? 32 : 16;
-    constexpr int MAXB = (sizeof(Tc) == 4) ? 24 : 16;
-    constexpr int PAD = (sizeof(Tc) == 4) ? 16 : 8;
+    typedef TnStage<Tin, Tc> St;
+    constexpr int VWI = St::VWI;
+    // 16-byte loads need aligned bases and leading dimensions; row-major operands are
+    // read up to the padded width, so they also need ld >= that width
+    auto ok = [&](const Tin* X, int64_t ld, int rm, int nc) {
+        if ((uintptr_t)X % 16 || ld % VWI) return false;
+        return !rm || ld >= round_up(nc, 16);
+    };
+    const int vec = ok(A, lda, a_rm, ka) && (sym || ok(B, ldb, b_rm, nb)) ? 1 : 0;
     const int ka_p = (int)round_up(ka, 16), nb_p = (int)round_up(nb, 16);
-    const int nbi = ka_p / 16, nbj = nb_p / 16;
-    const int nblocks = sym ? nbj * (nbj + 1) / 2 : nbi * nbj;
-    const int gy = (int)ceil_div(nblocks, 8 * MAXB);
-    const int ns = tn_splits(N, RC);
-    const int64_t rps = round_up(ceil_div(N, ns), RC);
-    const int ns_eff = (int)ceil_div(N, rps);
-    size_t lds = (size_t)RC * (ka_p + PAD) * sizeof(Tc);
-    if (!sym) lds += (size_t)RC * (nb_p + PAD) * sizeof(Tc);
-    if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gemm_tn_kernel<Tin, Tc, RC, MAXB>), dim3(ns_eff, gy), dim3(512), lds, s,
-                       A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, rps, P, skip_unless);
-    *nsplit_out = ns_eff;
-    return hipGetLastError();
+    auto fits = [&](int rc) {
+        const int64_t tasks = (int64_t)St::ntasks(a_rm, ka, ka_p, rc) + (sym ? 0 : St::ntasks(b_rm, nb, nb_p, rc));
+        return tn_lds<Tin, Tc>(rc, ka, nb, sym) <= 160 * 1024 && tasks <= (int64_t)TN_THREADS * TN_MAXT;
+    };
+    if (fits(16)) return launch_tn_rc<Tin, Tc, 16>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
+    if (fits(8)) return launch_tn_rc<Tin, Tc, 8>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
+    return hipErrorInvalidValue;
 }
 
 hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A, int64_t lda,
@@ -391,9 +552,8 @@ hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A
     }
     if (e != hipSuccess) return e;
     const int64_t tot = (int64_t)ka * nb;
-    int blocks = (int)std::min<int64_t>(ceil_div(tot, 256), 1024);
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(blocks), dim3(256), 0, s, P, ns, ka, nb, sym,
-                       out, ldo, out32, ldo32, skip_unless);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(tot, (int64_t)64)), dim3(64 * RQ), 0, s, P, ns,
+                       ka, nb, sym, out, ldo, out32, ldo32, skip_unless);
     return hipGetLastError();
 }
 

@@ -17,23 +17,76 @@
 namespace dmd {
 
 // ====================================================================== Cholesky
-// packed lower triangle by columns: L(i, j), i >= j, at lp_col(j, n) + i
-__device__ __forceinline__ int lp_col(int j, int n) { return j * n - j * (j + 1) / 2; }
+// G = L L^T and X = L^-1 in one sweep over the columns j (one barrier per step).
+// Threads [0, nt/2) hold 4x4 tiles of the lower triangle of the trailing matrix (G,
+// updated in place), threads [nt/2, nt) tiles of X (the forward substitution
+// L X = I, started from X = I), CH_TPT tiles each, in registers.  Step j needs
+// column j of the updated G and row j of X; their owners wrote both, not yet scaled,
+// into a double-buffered LDS vector during step j-1, so every thread scales by
+// s_j = 1/sqrt(G'(j,j)) itself:
+//     L(i, j) = G'(i, j) s_j,  X(j, c) = X'(j, c) s_j,
+//     G'(i, c) -= L(i, j) L(c, j)   (c > j),     X'(i, c) -= L(i, j) X(j, c)   (i > j).
+// Entries outside the active ranges take a zero factor, so both triangles stay exact
+// without per-element branches.  Rows of X are kept unscaled (row j is final after
+// step j-1) and scaled by s_j on output, R^-1 = L^-T = X^T.
+constexpr int CH_T = (SMALL_MAX + 3) / 4;
+// (threads, tiles per thread): each half of the threads covers T(T+1)/2 tiles, T = ceil(n/4)
+constexpr int CH_THREADS_A = 1024, CH_TPT_A = 2;     // n <= 176
+constexpr int CH_THREADS_B = 512, CH_TPT_B = (CH_T * (CH_T + 1) / 2 + CH_THREADS_B / 2 - 1) / (CH_THREADS_B / 2);
 
-__global__ void __launch_bounds__(1024)
+__device__ __forceinline__ void tri_decode(int u, int* ti, int* tc)
+{
+    int t = (int)((sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
+    while (t * (t + 1) / 2 > u) --t;
+    while ((t + 1) * (t + 2) / 2 <= u) ++t;
+    *ti = t;
+    *tc = u - t * (t + 1) / 2;
+}
+
+// attempt 0 factors G as given; when it breaks down and shift_scale > 0 it only sets
+// *shifted, and attempt 1 (launched right after, a no-op unless *shifted is set)
+// factors G + shift_scale * trace(G) * I.  A breakdown without a further attempt
+// reports DMD_ERR_CHOL_BREAKDOWN and leaves the identity.
+template <int CH_THREADS, int CH_TPT>
+__global__ void __launch_bounds__(CH_THREADS)
 chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, int64_t ldr,
-                float* Rinv32, int64_t ldr32, double shift_scale, int32_t* shifted,
+                float* Rinv32, int64_t ldr32, double shift_scale, int attempt, int32_t* shifted,
                 int32_t* info, const int32_t* skip_unless)
 {
     if (skip_unless && *skip_unless == 0) return;
-    extern __shared__ double L[];
+    if (attempt == 1 && (!shifted || *shifted == 0)) return;
+    __shared__ double colbuf[2][4 * CH_T];
+    __shared__ double xrow[2][4 * CH_T];
+    __shared__ double sdiag[4 * CH_T];      // s_j, for scaling the rows of X on output
     __shared__ double shift;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-#define LP(i, j) L[lp_col(j, n) + (i)]
+    constexpr int HALF = CH_THREADS / 2;
+    const int tid = threadIdx.x;
+    const bool xs = tid >= HALF;            // this thread holds tiles of X (else of G)
+    const int ht = xs ? tid - HALF : tid;
+    const int T = (n + 3) / 4, TT = T * (T + 1) / 2;
+
+    // tiles are numbered column by column (tile column tc outer), so the tiles of one
+    // wave share their columns and retire together: a G tile is final once its last
+    // column is <= j, an X tile does nothing before step c0 and after its last row
+    int rc[CH_TPT];                         // (4 ti) << 16 | 4 tc, or -1
+#pragma unroll
+    for (int q = 0; q < CH_TPT; ++q) {
+        const int u = ht + q * HALF;
+        int ti = 0, tc = 0;
+        if (u < TT) {
+            // upper-triangle decode of u read column-major = lower triangle read row by row of the
+            // transpose: (a, b) with a <= b  ->  tile (ti, tc) = (T-1-a, T-1-b) reversed order
+            int a, b;
+            tri_decode(u, &b, &a);          // b >= a
+            ti = T - 1 - a;
+            tc = T - 1 - b;
+            rc[q] = (4 * ti) << 16 | (4 * tc);
+        } else rc[q] = -1;
+    }
+    double t[CH_TPT][4][4];
 
     bool fail = false;
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    {
         if (tid == 0) {
             double tr = 0.0;
             if (attempt == 1)
@@ -41,42 +94,88 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
             shift = shift_scale * tr;
         }
         __syncthreads();
-        for (int e = tid; e < n * n; e += nt) {
-            const int i = e % n, j = e / n;
-            if (i >= j) LP(i, j) = G[(int64_t)j * ldg + i] + (i == j ? shift : 0.0);
+        const double sh = shift;
+        // initial tiles and the step-0 broadcasts (column 0 of G, row 0 of X)
+#pragma unroll
+        for (int q = 0; q < CH_TPT; ++q) {
+            const int r0 = rc[q] >> 16, c0 = rc[q] & 0xffff;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int i = r0 + a, c = c0 + b;
+                    double v = (i == c) ? 1.0 : 0.0;
+                    if (!xs && rc[q] >= 0 && i < n && c < n) v = G[(int64_t)c * ldg + i] + (i == c ? sh : 0.0);
+                    t[q][a][b] = v;
+                }
+            if (rc[q] >= 0 && !xs && c0 == 0) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) colbuf[0][r0 + a] = t[q][a][0];
+            }
         }
+        if (tid == HALF) xrow[0][0] = 1.0;
         __syncthreads();
-        // right-looking Cholesky, two barriers per column
         fail = false;
         for (int j = 0; j < n; ++j) {
-            const double d = LP(j, j);
-            if (!(d > 0.0) || !isfinite(d)) { fail = true; break; }   // uniform decision
-            const double ljj = sqrt(d), inv = 1.0 / ljj;
-            for (int i = j + 1 + tid; i < n; i += nt) LP(i, j) *= inv;
-            __syncthreads();
-            if (tid == 0) LP(j, j) = ljj;
-            // trailing update: one wave per column c, lanes over rows i >= c
-            for (int c = j + 1 + wave; c < n; c += nw) {
-                const double lcj = LP(c, j);
-                double* colc = &L[lp_col(c, n)];
-                const double* colj = &L[lp_col(j, n)];
-                for (int i = c + lane; i < n; i += 64) colc[i] -= colj[i] * lcj;
+            const int bsel = j & 1;
+            const double d = colbuf[bsel][j];
+            if (!(d > 0.0) || !isfinite(d)) { fail = true; break; }   // uniform: every thread reads d
+            const double s = 1.0 / sqrt(d);
+            if (tid == 0) sdiag[j] = s;
+            const int jn = j + 1;
+#pragma unroll
+            for (int q = 0; q < CH_TPT; ++q) {
+                if (rc[q] < 0) continue;
+                const int r0 = rc[q] >> 16, c0 = rc[q] & 0xffff;
+                // retired or not yet reached: no update and nothing to broadcast
+                if (xs ? (r0 + 3 < j || c0 > jn) : (c0 + 3 < j)) continue;
+                double lr[4], fc[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) lr[a] = r0 + a > j ? colbuf[bsel][r0 + a] * s : 0.0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int c = c0 + b;
+                    fc[b] = xs ? (c <= j ? xrow[bsel][c] * s : 0.0) : (c > j ? colbuf[bsel][c] * s : 0.0);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) t[q][a][b] -= lr[a] * fc[b];
+                // broadcasts for step j+1: column j+1 of G (rows >= j+1), row j+1 of X (cols <= j+1)
+                // (constant register indices only: a selected column or row is stored under a
+                // per-column / per-row predicate)
+                if (!xs) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (c0 + b == jn) {
+#pragma unroll
+                            for (int a = 0; a < 4; ++a)
+                                if (r0 + a >= jn) colbuf[bsel ^ 1][r0 + a] = t[q][a][b];
+                        }
+                } else {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+                        if (r0 + a == jn) {
+#pragma unroll
+                            for (int b = 0; b < 4; ++b)
+                                if (c0 + b <= jn) xrow[bsel ^ 1][c0 + b] = t[q][a][b];
+                        }
+                }
             }
             __syncthreads();
         }
-        if (!fail) break;
-        if (attempt == 0 && shift_scale > 0.0) {
-            if (tid == 0 && shifted) *shifted = 1;
-            if (tid == 0 && info) atomicAdd(&info[3], 1);
-            __syncthreads();
-            continue;
+    }
+    if (fail && attempt == 0 && shift_scale > 0.0 && shifted) {
+        if (tid == 0) {
+            *shifted = 1;
+            if (info) atomicAdd(&info[3], 1);
         }
-        break;
+        return;
     }
     if (fail) {
         // breakdown: report, and leave an identity so that later stages stay finite
         if (tid == 0) set_status(info, DMD_ERR_CHOL_BREAKDOWN);
-        for (int e = tid; e < n * n; e += nt) {
+        for (int e = tid; e < n * n; e += CH_THREADS) {
             const int i = e % n, j = e / n;
             const double v = i == j ? 1.0 : 0.0;
             Rinv[(int64_t)j * ldr + i] = v;
@@ -84,39 +183,36 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
         }
         return;
     }
-    // ---- in-place inverse of L, right to left:
-    //      Linv(j+1:, j) = -Linv(j+1:, j+1:) L(j+1:, j) / L(j, j),  Linv(j, j) = 1 / L(j, j)
-    //      Row i's product is split over NP = nt / 256 thread groups (every NP-th column);
-    //      partial sums meet in LDS (no cross-lane shuffles).
-    double* part = L + n * (n + 1) / 2;          // NP x n partial sums
-    const int NP = nt >> 8;                      // 4 with 1024 threads
-    const int grp = tid >> 8, ri = tid & 255;
-    for (int j = n - 1; j >= 0; --j) {
-        const double inv = 1.0 / LP(j, j);       // read before anyone overwrites the diagonal
-        for (int i = j + 1 + ri; i < n; i += 256) {
-            double acc = 0.0;
-            for (int c = j + 1 + grp; c <= i; c += NP) acc += LP(i, c) * LP(c, j);
-            part[grp * n + i] = acc;
-        }
-        __syncthreads();
-        if (grp == 0) {
-            for (int i = j + 1 + ri; i < n; i += 256) {
-                double acc = 0.0;
-                for (int g = 0; g < NP; ++g) acc += part[g * n + i];
-                LP(i, j) = -inv * acc;
+    // R^-1(r, c) = X(c, r) = X'(c, r) s_c: upper triangle from the X tiles, zeros below
+    if (xs) {
+#pragma unroll
+        for (int q = 0; q < CH_TPT; ++q) {
+            if (rc[q] < 0) continue;
+            const int r0 = rc[q] >> 16, c0 = rc[q] & 0xffff;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int i = r0 + a;
+                if (i >= n) continue;
+                const double si = sdiag[i];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int c = c0 + b;
+                    if (c <= i) {
+                        const double v = t[q][a][b] * si;
+                        Rinv[(int64_t)i * ldr + c] = v;
+                        if (Rinv32) Rinv32[(int64_t)i * ldr32 + c] = (float)v;
+                    }
+                }
             }
-            if (ri == 0) LP(j, j) = inv;
         }
-        __syncthreads();
     }
-    // ---- R^-1 = L^-T (upper), zero below the diagonal
-    for (int e = tid; e < n * n; e += nt) {
-        const int r = e % n, c = e / n;     // element (r, c) of R^-1
-        const double v = (c >= r) ? LP(c, r) : 0.0;
-        Rinv[(int64_t)c * ldr + r] = v;
-        if (Rinv32) Rinv32[(int64_t)c * ldr32 + r] = (float)v;
+    for (int e = tid; e < n * n; e += CH_THREADS) {
+        const int r = e % n, c = e / n;
+        if (r > c) {
+            Rinv[(int64_t)c * ldr + r] = 0.0;
+            if (Rinv32) Rinv32[(int64_t)c * ldr32 + r] = 0.0f;
+        }
     }
-#undef LP
 }
 
 hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* Rinv, int64_t ldr,
@@ -125,10 +221,20 @@ hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* 
 {
     if (n <= 0) return hipSuccess;
     if (n > SMALL_MAX) return hipErrorInvalidValue;
-    const size_t lds = ((size_t)n * (n + 1) / 2 + 4 * (size_t)n) * sizeof(double);
-    hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(1024), lds, s, G, ldg, n, Rinv, ldr, Rinv32,
-                       ldr32, shift_scale, shifted, info, skip_unless);
-    return hipGetLastError();
+    const int T = (n + 3) / 4;
+    const bool small = T * (T + 1) / 2 <= (CH_THREADS_A / 2) * CH_TPT_A;
+    const int attempts = (shift_scale > 0.0 && shifted) ? 2 : 1;
+    for (int at = 0; at < attempts; ++at) {
+        if (small)
+            hipLaunchKernelGGL((chol_inv_kernel<CH_THREADS_A, CH_TPT_A>), dim3(1), dim3(CH_THREADS_A), 0, s, G, ldg,
+                               n, Rinv, ldr, Rinv32, ldr32, shift_scale, at, shifted, info, skip_unless);
+        else
+            hipLaunchKernelGGL((chol_inv_kernel<CH_THREADS_B, CH_TPT_B>), dim3(1), dim3(CH_THREADS_B), 0, s, G, ldg,
+                               n, Rinv, ldr, Rinv32, ldr32, shift_scale, at, shifted, info, skip_unless);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ====================================================================== Jacobi
@@ -536,7 +642,7 @@ hipError_t check_finite(hipStream_t s, int dtype, const void* X, int64_t ld, int
 
 hipError_t small_prepare()
 {
-    hipError_t e = hipFuncSetAttribute((const void*)chol_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
+    hipError_t e = hipSuccess;
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
 }
