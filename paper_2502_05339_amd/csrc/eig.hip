@@ -17,6 +17,8 @@
 //  3. sort_modes_kernel (1 work-group): canonical order (ascending |arg lambda|,
 //     ties by descending |lambda|, Im > 0 member of a pair first), lambda, kind
 //     and the permuted folded eigenvectors (pair -> [Re w, Im w], LAPACK storage).
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -426,13 +428,18 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
             int hm = hp_col(max(l - 1, 0), n), hk0 = hp_col(l, n), hk1 = hp_col(l + 1, n), hk2 = hp_col(l + 2, n);
             double e0 = 0.0, e1 = 0.0, e2 = 0.0;   // this thread's operands, carried between steps
             int prole = 0;
-            for (int k = l; k <= hi - 1; ++k) {
-                const int m = (k == hi - 1) ? 2 : 3;
-                const int crow = min(k + 3, hi);
-                if (k > l) { hm = hk0; hk0 = hk1; hk1 = hk2; hk2 += min(k + 5, n); }
+            // One bulge step k.  G (general) covers the first step of the sweep (vector from
+            // the shift polynomial) and the last two (the block ends: m = 2 or rows past
+            // hi); every other step takes the lean path with m = 3 and rows up to k+3.
+            auto step = [&](const int k, auto general) {
+                constexpr bool G = decltype(general)::value;
+                const int m = G ? ((k == hi - 1) ? 2 : 3) : 3;
+                const int crow = G ? min(k + 3, hi) : k + 3;
+                if (!G || k > l) { hm = hk0; hk0 = hk1; hk1 = hk2; hk2 += min(k + 5, n); }
                 // ---- loads, all issued before the reflector is formed
-                double x = x0, y = y0, z = z0;
-                if (k > l) { x = Hs[hm + k]; y = Hs[hm + k + 1]; z = Hs[hm + k + 2]; }
+                double x, y, z;
+                if (G && k == l) { x = x0; y = y0; z = z0; }
+                else { x = Hs[hm + k]; y = Hs[hm + k + 1]; z = Hs[hm + k + 2]; }
                 // role: 1 column update of row tid, 2 row update of column tid-1, 3 Z row
                 const bool colr = tid <= crow;
                 const int role = colr ? 1 : (zrole ? 3 : ((tid - 1 >= k + m && tid <= n) ? 2 : 0));
@@ -441,7 +448,7 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
                 const int o2 = colr ? hk2 + tid : base_t + k + 2;
                 // a thread that keeps its role finds two of its operands in registers (the
                 // entries it updated in the previous step); only the third is new
-                if (role != prole || k == l) { e0 = Hs[o0]; e1 = Hs[o1]; }
+                if (role != prole || (G && k == l)) { e0 = Hs[o0]; e1 = Hs[o1]; }
                 e2 = Hs[o2];
                 prole = role;
                 // the corner C(a, b) = H(k+a, k+b) is needed only by the waves holding rows k..k+m-1
@@ -452,7 +459,7 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
                     c01 = Hs[hk1 + k]; c11 = Hs[hk1 + k + 1]; c21 = Hs[hk1 + k + 2];
                     c02 = Hs[hk2 + k]; c12 = Hs[hk2 + k + 1]; c22 = Hs[hk2 + k + 2];
                 }
-                if (m == 2) { z = 0.0; e2 = 0.0; c20 = 0.0; c21 = 0.0; c02 = 0.0; c12 = 0.0; c22 = 0.0; }
+                if (G && m == 2) { z = 0.0; e2 = 0.0; c20 = 0.0; c21 = 0.0; c02 = 0.0; c12 = 0.0; c22 = 0.0; }
                 double d, t, beta;
                 reflector3(x, y, z, &d, &t, &beta);
                 // ---- P_k = I - t u u^T, u = (d, y, z), applied to the operands: rows k..k+m-1
@@ -476,18 +483,21 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
                     if (role != 0) {
                         Hs[o0] = e0;
                         Hs[o1] = e1;
-                        if (m == 3) Hs[o2] = e2;
+                        if (!G || m == 3) Hs[o2] = e2;
                     }
                 }
                 if (tid == pend_t && pk >= 0) {             // column pk: (beta, 0, 0) below its subdiagonal
                     H(pk + 1, pk) = pbeta; H(pk + 2, pk) = 0.0;
                     if (pk + 3 <= hi) H(pk + 3, pk) = 0.0;
                 }
-                if (k > l) { pk = k - 1; pbeta = beta; }
+                if (!G || k > l) { pk = k - 1; pbeta = beta; }
                 // operands of the next step: this step's second and third entries
                 e0 = e1; e1 = e2;
                 __syncthreads();
-            }
+            };
+            step(l, std::true_type{});
+            for (int k = l + 1; k <= hi - 3; ++k) step(k, std::false_type{});
+            for (int k = max(l + 1, hi - 2); k <= hi - 1; ++k) step(k, std::true_type{});
             if (tid == pend_t && pk >= 0) {
                 H(pk + 1, pk) = pbeta; H(pk + 2, pk) = 0.0;
                 if (pk + 3 <= hi) H(pk + 3, pk) = 0.0;
