@@ -263,10 +263,12 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam,
 /*
  * Fit several independent scenes.  Each scene's fit runs on its own forked
  * stream (default priority) joined back into `stream`, so the latency-bound
- * small-matrix stages of different scenes overlap.  With capture != 0 the whole
- * batch is captured once into a HIP graph returned in *graph (nothing runs until
- * dmd_graph_launch); capture needs a created stream (the null stream is refused
- * with DMD_ERR_ARG).  Without capture the batch runs and the call waits for it.
+ * small-matrix stages of different scenes overlap.  With capture != 0 the batch
+ * first runs once (the call waits for it: the runtime loads each kernel's code on
+ * its first launch, which a capturing stream does not allow), then is captured into
+ * a HIP graph returned in *graph for dmd_graph_launch; capture needs a created
+ * stream (the null stream is refused with DMD_ERR_ARG).  Without capture the batch
+ * runs and the call waits for it.
  * Scenes use DMD_FIT_ASYNC semantics (statuses land in each model's info[0]).
  */
 int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes,

@@ -47,7 +47,14 @@ size_t esize(int dt) { return dt == DMD_F32 ? 4 : 8; }
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 std::once_flag g_init_once;
+hipError_t g_init_error = hipSuccess;
 void lib_init();
+// one-time set-up (kernel LDS limits, autotune cache); its failure fails every call
+static int32_t ensure_init()
+{
+    std::call_once(g_init_once, lib_init);
+    return g_init_error == hipSuccess ? DMD_OK : DMD_ERR_HIP;
+}
 
 // ---------------------------------------------------------------- fit plan
 struct FitArgs {
@@ -346,7 +353,7 @@ int32_t load_cache(const char* path)
 void lib_init()
 {
     (void)device_cu_count();
-    (void)prepare_kernels();
+    g_init_error = prepare_kernels();
     const char* c = getenv("DMDMI_AUTOTUNE_CACHE");
     if (c && *c) load_cache(c);
 }
@@ -370,7 +377,7 @@ int32_t recon_prepare(hipStream_t st, const dmd_model* m, const int64_t* k_host,
     if (!k_host && !t_host) return DMD_ERR_ARG;
     if (int32_t e = recon_validate(m, K, mode, ws_bytes, ws)) return e;
     if (!k_host && !(m->dt > 0.0)) return DMD_ERR_ARG;
-    std::call_once(g_init_once, lib_init);
+    if (int32_t e0 = ensure_init()) return e0;
     Carver cv(ws);
     ReconPlan p = recon_carve(cv, m->r, K, mode);
     const int rp = (int)dmd_phi_ld(m->r);
@@ -392,7 +399,7 @@ int32_t recon_apply(hipStream_t st, const dmd_model* m, int K, int mode, void* U
 {
     if (int32_t e = recon_validate(m, K, mode, ws_bytes, ws)) return e;
     if (!U || ldu < m->n) return DMD_ERR_ARG;
-    std::call_once(g_init_once, lib_init);
+    if (int32_t e0 = ensure_init()) return e0;
     Carver cv(ws);
     ReconPlan p = recon_carve(cv, m->r, K, mode);
     const int rp = (int)dmd_phi_ld(m->r);
@@ -470,7 +477,7 @@ int32_t dmd_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t 
     size_t need = 0;
     if (int32_t e = dmd_fit_workspace_size(n, ncols, xdtype, opts, &need)) return e;
     if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
-    std::call_once(g_init_once, lib_init);
+    if (int32_t e0 = ensure_init()) return e0;
     hipStream_t st = (hipStream_t)stream;
     model->r = opts->r;
     model->dtype = xdtype;
@@ -550,7 +557,7 @@ int32_t dmd_project(void* stream, const dmd_model* model, const void* u, double*
     size_t need = 0;
     dmd_project_workspace_size(model->n, model->r, &need);
     if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
-    std::call_once(g_init_once, lib_init);
+    if (int32_t e0 = ensure_init()) return e0;
     hipStream_t st = (hipStream_t)stream;
     const int r = model->r;
     const int64_t n = model->n;
@@ -607,7 +614,7 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam, c
     size_t need = 0;
     dmd_loss_grad_workspace_size(model->n, model->r, ncols, model->dtype, &need);
     if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
-    std::call_once(g_init_once, lib_init);
+    if (int32_t e0 = ensure_init()) return e0;
     hipStream_t st = (hipStream_t)stream;
     const int r = model->r, rp = (int)dmd_phi_ld(r);
     const int64_t n = model->n, ldr = round_up(n, 4);
@@ -663,7 +670,7 @@ int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes, 
         if (int32_t e = dmd_fit_workspace_size(sc.n, sc.ncols, sc.xdtype, &sc.opts, &need)) return e;
         if (!sc.ws || sc.ws_bytes < need) return DMD_ERR_WORKSPACE;
     }
-    std::call_once(g_init_once, lib_init);
+    if (int32_t e0 = ensure_init()) return e0;
     hipStream_t origin = (hipStream_t)stream;
     dmd_graph* g = new dmd_graph();
     auto cleanup = [&](int32_t code) {
@@ -680,24 +687,35 @@ int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes, 
         if (hipEventCreateWithFlags(&g->events[i], hipEventDisableTiming) != hipSuccess) return cleanup(DMD_ERR_HIP);
     for (int i = 0; i < nscenes; ++i)
         if (hipStreamCreateWithFlags(&g->streams[i], hipStreamNonBlocking) != hipSuccess) return cleanup(DMD_ERR_HIP);
-    if (capture && hipStreamBeginCapture(origin, hipStreamCaptureModeGlobal) != hipSuccess) return cleanup(DMD_ERR_HIP);
+    // fork: every scene on its own stream after the origin's prior work, joined back into origin
+    auto enqueue_all = [&]() -> int32_t {
+        if (hipEventRecord(g->events[nscenes], origin) != hipSuccess) return DMD_ERR_HIP;
+        for (int i = 0; i < nscenes; ++i) {
+            const dmd_scene& sc = scenes[i];
+            FitArgs a{sc.x, sc.xp, sc.n, sc.ncols, sc.ldx, sc.ldxp, sc.xdtype, sc.opts,
+                      is_shifted_view(sc.x, sc.xp, sc.ldx, sc.ldxp, sc.xdtype)};
+            a.o.flags |= DMD_FIT_ASYNC;
+            models[i].r = sc.opts.r;
+            models[i].dtype = sc.xdtype;
+            models[i].dt = sc.opts.dt;
+            if (hipStreamWaitEvent(g->streams[i], g->events[nscenes], 0) != hipSuccess) return DMD_ERR_HIP;
+            Carver cv(sc.ws);
+            if (int32_t st = fit_plan(cv, g->streams[i], a, &models[i])) return st;
+            if (hipEventRecord(g->events[i], g->streams[i]) != hipSuccess) return DMD_ERR_HIP;
+            if (hipStreamWaitEvent(origin, g->events[i], 0) != hipSuccess) return DMD_ERR_HIP;
+        }
+        return DMD_OK;
+    };
     int32_t status = DMD_OK;
-    if (hipEventRecord(g->events[nscenes], origin) != hipSuccess) status = DMD_ERR_HIP;
-    for (int i = 0; i < nscenes && status == DMD_OK; ++i) {
-        const dmd_scene& sc = scenes[i];
-        FitArgs a{sc.x, sc.xp, sc.n, sc.ncols, sc.ldx, sc.ldxp, sc.xdtype, sc.opts,
-                  is_shifted_view(sc.x, sc.xp, sc.ldx, sc.ldxp, sc.xdtype)};
-        a.o.flags |= DMD_FIT_ASYNC;
-        models[i].r = sc.opts.r;
-        models[i].dtype = sc.xdtype;
-        models[i].dt = sc.opts.dt;
-        if (hipStreamWaitEvent(g->streams[i], g->events[nscenes], 0) != hipSuccess) { status = DMD_ERR_HIP; break; }
-        Carver cv(sc.ws);
-        status = fit_plan(cv, g->streams[i], a, &models[i]);
-        if (status != DMD_OK) break;
-        if (hipEventRecord(g->events[i], g->streams[i]) != hipSuccess) { status = DMD_ERR_HIP; break; }
-        if (hipStreamWaitEvent(origin, g->events[i], 0) != hipSuccess) { status = DMD_ERR_HIP; break; }
+    if (capture) {
+        // one eager pass first: the runtime loads a kernel's code on its first launch, which
+        // is not allowed while a stream is being captured
+        status = enqueue_all();
+        if (hipStreamSynchronize(origin) != hipSuccess && status == DMD_OK) status = DMD_ERR_HIP;
+        if (status != DMD_OK) return cleanup(status);
+        if (hipStreamBeginCapture(origin, hipStreamCaptureModeGlobal) != hipSuccess) return cleanup(DMD_ERR_HIP);
     }
+    status = enqueue_all();
     if (capture) {
         hipGraph_t gr = nullptr;
         hipError_t e = hipStreamEndCapture(origin, &gr);

@@ -644,7 +644,7 @@ hipError_t small_prepare()
 {
     hipError_t e = hipSuccess;
     if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
+    return hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
 }
 
 }  // namespace dmd

@@ -141,7 +141,7 @@ def _gauss_transfer(n, sigma):
     return np.exp(-2.0 * (math.pi * sigma * f) ** 2)
 
 
-def smooth_modes(rng, n_grid, nc, sigma_cells=4.0, dtype=np.complex64):
+def smooth_modes(rng, n_grid, nc, sigma_cells=4.0, dtype=np.complex64, progress=None):
     """Spatially smooth complex modes on a component-major grid.
 
     Each component of each mode is complex white noise on the grid, blurred by a
@@ -166,10 +166,12 @@ def smooth_modes(rng, n_grid, nc, sigma_cells=4.0, dtype=np.complex64):
             out[c * per:(c + 1) * per, i] = np.fft.ifftn(np.fft.fftn(w) * mult).ravel()
         nrm = np.linalg.norm(out[:, i].astype(np.complex128))
         out[:, i] /= nrm
+        if progress is not None and (i + 1) % 10 == 0:
+            progress(f"smooth modes {i + 1}/{nc}")
     return out
 
 
-def snapshots(modes, lam, b, m, sigma, rng, out_dtype=np.float64, row_block=1 << 18):
+def snapshots(modes, lam, b, m, sigma, rng, out_dtype=np.float64, row_block=1 << 18, progress=None):
     """Z[:, j] = Re(modes @ s(j)) + sigma * eps_j with s(0) = b, s(j+1) = lam * s(j).
 
     The state is advanced one frame at a time (a recurrence, not a power).  The
@@ -189,9 +191,13 @@ def snapshots(modes, lam, b, m, sigma, rng, out_dtype=np.float64, row_block=1 <<
         re = blk.real.astype(np.float64)
         im = blk.imag.astype(np.float64)
         Z[r0:r0 + row_block, :] = re @ Sr - im @ Si
+        if progress is not None and (r0 // row_block) % 8 == 7:
+            progress(f"snapshot rows {min(N, r0 + row_block)}/{N}")
     if sigma > 0:
         for j in range(m):
             Z[:, j] += sigma * rng.standard_normal(N)
+            if progress is not None and j % 50 == 49:
+                progress(f"noise columns {j + 1}/{m}")
     return Z
 
 
@@ -215,17 +221,19 @@ class Generated:
     Omega: np.ndarray | None
 
 
-def generate(cfg: Config, with_sketch=True) -> Generated:
-    """Draw one workload: modes, |lambda|, arg(lambda), b, noise; then the sketch."""
+def generate(cfg: Config, with_sketch=True, progress=None) -> Generated:
+    """Draw one workload: modes, |lambda|, arg(lambda), b, noise; then the sketch.
+
+    ``progress``, if given, is called with a short text now and then (long draws)."""
     rng = np.random.default_rng(cfg.seed)
     if cfg.modes == "orthonormal":
         modes = orthonormal_modes(rng, cfg.N, cfg.nc)
     else:
-        modes = smooth_modes(rng, cfg.n_grid, cfg.nc)
+        modes = smooth_modes(rng, cfg.n_grid, cfg.nc, progress=progress)
     lam = draw_eigs(rng, cfg.nc, cfg.lam_lo, cfg.arg, cfg.jitter)
     b = draw_amplitudes(rng, cfg.nc)
     dt = np.float64 if cfg.dtype == "f64" else np.float32
-    Z = snapshots(modes, lam, b, cfg.m, cfg.sigma, rng, out_dtype=np.float64)
+    Z = snapshots(modes, lam, b, cfg.m, cfg.sigma, rng, out_dtype=np.float64, progress=progress)
     if dt is np.float32:
         Z = np.asfortranarray(Z.astype(np.float32))
     Om = sketch(cfg.seed, cfg.m, cfg.l, dtype=dt) if (with_sketch and cfg.p > 0) else None
@@ -256,7 +264,7 @@ def c5b_config(scene: Scene) -> Config:
                   p=10, q=2, K=100)
 
 
-def synthetic_model(cfg: Config, modes_dtype=np.float32):
+def synthetic_model(cfg: Config, modes_dtype=np.float32, progress=None):
     """A prescribed (not fitted) model with exact conjugate pairs, for reconstruction-only work.
 
     Returns (phi_pairs, lam, b): phi_pairs is N x nc complex (one member of each
@@ -267,7 +275,7 @@ def synthetic_model(cfg: Config, modes_dtype=np.float32):
     if cfg.modes == "orthonormal":
         modes = orthonormal_modes(rng, cfg.N, cfg.nc)
     else:
-        modes = smooth_modes(rng, cfg.n_grid, cfg.nc)
+        modes = smooth_modes(rng, cfg.n_grid, cfg.nc, progress=progress)
     lam = draw_eigs(rng, cfg.nc, cfg.lam_lo, cfg.arg, cfg.jitter)
     b = draw_amplitudes(rng, cfg.nc)
     return modes.astype(np.complex64 if modes_dtype == np.float32 else np.complex128), lam, b
