@@ -413,7 +413,7 @@ hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* e
     if (n > SMALL_MAX) return hipErrorInvalidValue;
     const int n2 = n + (n & 1), np = n2 / 2;
     const size_t fixed = (size_t)n * (n + 1) / 2 * 8 + (size_t)np * (3 * 8 + 2 * 4) + (size_t)n * 4 + 64;
-    const size_t budget = 160 * 1024 - 512;
+    const size_t budget = 160 * 1024 - 1024;   // the kernel's LDS attribute (static LDS is 16 bytes)
     if (fixed + (size_t)n * 8 > budget) return hipErrorInvalidValue;
     int nr = (int)((budget - fixed) / ((size_t)n * 8));
     if (nr > 32) nr = 32;
