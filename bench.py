@@ -164,6 +164,9 @@ def main():
 
     m = step()
     torch.cuda.synchronize()
+    # tile shape of the reconstruction for this (mode, r, N, K) class, chosen by timing
+    recon_cfg = {mode: dmd.autotune_reconstruct(m, cfg.K, mode) for mode in ("bf16x3", "fp32")}
+    print(f"# reconstruction tile configs (autotuned): {recon_cfg}", file=sys.stderr, flush=True)
     st = int(m.info[0].item())
     info = m.info.cpu().tolist()
     print(f"# fit info: status {info[0]}, Jacobi sweeps {info[1]}, Francis iterations {info[2]}, "
@@ -253,7 +256,8 @@ def main():
                                "N=131072 (2x256x256), m=200, r=150, p=10, q=2, noise 1e-4",
                    "N": cfg.N, "m": cfg.m, "r": cfg.r, "p": cfg.p, "q": cfg.q, "K": cfg.K,
                    "fit": "mixed (FP32 MFMA streaming, FP64 Gram/small factors)",
-                   "reconstruction": "bf16x3 (split-BF16 MFMA, FP32 accumulate)"},
+                   "reconstruction": "bf16x3 (split-BF16 MFMA, FP32 accumulate)",
+                   "recon_tile_config": recon_cfg},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "mixed": {"fit_ms": round(fit_ms, 4), "recon_ms": round(recon_ms, 4),
@@ -394,7 +398,9 @@ def run_c5a(args):
     U = torch.empty((cfg.K, cfg.N), dtype=torch.float32, device="cuda")
     _say(f"output buffer {U.numel() * 4 / 2 ** 30:.1f} GiB")
     res = {}
+    tiles = {}
     for mode in ("bf16", "bf16x3", "fp32"):
+        tiles[mode] = dmd.autotune_reconstruct(model, cfg.K, mode)
         prep = dmd.PreparedReconstruction(model, ks, mode=mode)
         prep.apply(U)
         torch.cuda.synchronize()
@@ -439,6 +445,7 @@ def run_c5a(args):
                      "unit": "GB/s", "frac": round(bytes_alg / (t * 1e-3) / HBM_PEAK, 4), "traffic": None,
                      "kernel": "recon_kernel<bf16>", "bytes_per_launch": bytes_alg, "launch_ms": round(t, 3)},
         "modes_ms": {k: round(v, 3) for k, v in res.items()},
+        "recon_tile_config": tiles,
         "accuracy": {"reference": "FP64 oracle reconstruction on 2048 sampled rows, all frames",
                      "field_max_frame_rel": err},
         "cpu_baseline": cpu,

@@ -47,7 +47,7 @@ struct ReconArgs {
     const void* xt; int64_t ldxt; double* ss_partial;   // residual epilogue (adjoint)
     int* grid_out;
 };
-constexpr int RECON_NCFG = 3;
+constexpr int RECON_NCFG = 6;
 hipError_t recon_launch(hipStream_t s, const ReconArgs& ra, int cfg);
 hipError_t powers_pack(hipStream_t s, const double* lam, const double* b, const int32_t* kind, int r,
                        const double* expo, int K, int Kp, int rp, int mode, void* hi, void* lo);

@@ -123,9 +123,232 @@ __device__ __forceinline__ void load_a(AFrag<MODE>& f, const typename RTraits<MO
     }
 }
 
+// Coefficient rows of FC frames (16-byte moves, thread-strided) from global memory to
+// registers, and from registers to an LDS buffer with row stride cld.
+template <int PREF, bool X3, typename Tc>
+__device__ __forceinline__ void recon_fetch(float4 (&hi)[PREF], float4 (&lo)[PREF], const Tc* __restrict__ Chi,
+                                            const Tc* __restrict__ Clo, int tid, int per_row, int f0, int rp,
+                                            int FC, int VE)
+{
+#pragma unroll
+    for (int q = 0; q < PREF; ++q) {
+        const int idx = tid + q * 256;
+        if (idx < FC * per_row) {
+            const int fr = idx / per_row, c = (idx % per_row) * VE;
+            const int64_t src = (int64_t)(f0 + fr) * rp + c;
+            hi[q] = *reinterpret_cast<const float4*>(&Chi[src]);
+            if constexpr (X3) lo[q] = *reinterpret_cast<const float4*>(&Clo[src]);
+        }
+    }
+}
+template <int PREF, bool X3, typename Tc>
+__device__ __forceinline__ void recon_put(const float4 (&hi)[PREF], const float4 (&lo)[PREF], Tc* Sh, Tc* Sl,
+                                          int tid, int per_row, int cld, int FC, int VE)
+{
+#pragma unroll
+    for (int q = 0; q < PREF; ++q) {
+        const int idx = tid + q * 256;
+        if (idx < FC * per_row) {
+            const int fr = idx / per_row, c = (idx % per_row) * VE;
+            *reinterpret_cast<float4*>(&Sh[fr * cld + c]) = hi[q];
+            if constexpr (X3) *reinterpret_cast<float4*>(&Sl[fr * cld + c]) = lo[q];
+        }
+    }
+}
+
+// Work items are (row tile, chunk of FC frames) pairs, numbered row tile major; work-
+// group g takes the contiguous run [g*ipw, (g+1)*ipw), so consecutive items mostly
+// share their row tile (the tile of Phi is loaded into registers once per tile).  The
+// coefficients of the next item are fetched into registers while the current item's
+// MFMAs run, then stored to the other of two LDS buffers: one barrier per item.
+template <int MODE, int RBW, int FCB, bool RESID>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2)))
+recon_kernel(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi, int64_t N, int rp,
+             const typename RTraits<MODE>::Tc* __restrict__ Chi,
+             const typename RTraits<MODE>::Tc* __restrict__ Clo, int K,
+             typename RTraits<MODE>::Tout* U, int64_t ldu, int vec_store,
+             const typename RTraits<MODE>::Tout* __restrict__ Xt, int64_t ldxt,
+             double* __restrict__ ss_partial,
+             int n_rowtiles, int n_fchunks, int items_per_wg)
+{
+    typedef RTraits<MODE> Tr;
+    typedef typename Tr::Tc Tc;
+    typedef typename Tr::Tout Tout;
+    typedef typename Tr::V V;
+    constexpr int KW = Tr::KW;
+    constexpr int KGMAX = RECON_MAX_RP / KW;
+    constexpr int FC = FCB * 16;
+    constexpr int CPAD = 16 / sizeof(Tc);               // 16-byte row pad in LDS
+    constexpr int CLD = RECON_MAX_RP + CPAD;
+    constexpr bool X3 = (MODE == DMD_RECON_BF16X3);
+    constexpr int WG_ROWS = 4 * RBW * 16;
+    constexpr int VE = 16 / sizeof(Tc);                 // elements per 16-byte move
+    constexpr int PREF = (FC * (RECON_MAX_RP / VE) + 255) / 256;   // 16-byte moves per thread
+
+    __shared__ __align__(16) Tc Cs_hi[2][FC * CLD];
+    __shared__ __align__(16) Tc Cs_lo[X3 ? 2 : 1][X3 ? FC * CLD : 1];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l16 = lane & 15, lg = lane >> 4;
+    const int nkg = rp / KW;
+    const int cld = rp + CPAD;          // LDS leading dimension actually used
+    const int per_row = rp / VE;
+
+    AFrag<MODE> a[RBW][KGMAX];
+    int cur_rt = -1;
+    double ss = 0.0;
+    const int64_t n_items = (int64_t)n_rowtiles * n_fchunks;
+    const int64_t it_begin = (int64_t)blockIdx.x * items_per_wg;
+    const int64_t it_end = min(n_items, it_begin + items_per_wg);
+
+    float4 pre_hi[PREF], pre_lo[PREF];
+    if (it_begin < it_end) {
+        recon_fetch<PREF, X3>(pre_hi, pre_lo, Chi, Clo, tid, per_row, (int)(it_begin % n_fchunks) * FC, rp, FC, VE);
+        recon_put<PREF, X3>(pre_hi, pre_lo, Cs_hi[0], Cs_lo[0], tid, per_row, cld, FC, VE);
+    }
+    __syncthreads();
+    for (int64_t item = it_begin; item < it_end; ++item) {
+        const int buf = (int)((item - it_begin) & 1);
+        const bool more = item + 1 < it_end;
+        if (more) recon_fetch<PREF, X3>(pre_hi, pre_lo, Chi, Clo, tid, per_row, (int)((item + 1) % n_fchunks) * FC, rp, FC, VE);
+        const int rt = (int)(item / n_fchunks);
+        const int f0 = (int)(item % n_fchunks) * FC;
+        const int f_end = min(K, f0 + FC);
+        const int64_t tile_row0 = (int64_t)rt * WG_ROWS + wave * RBW * 16;
+        if (rt != cur_rt) {
+#pragma unroll
+            for (int rb = 0; rb < RBW; ++rb) {
+                const int64_t row = tile_row0 + rb * 16 + l16;
+                const bool ok = row < N;
+                const typename Tr::Tphi* prow = phi + (ok ? row : 0) * ldphi;
+#pragma unroll
+                for (int kg = 0; kg < KGMAX; ++kg) {
+                    if (kg < nkg) {
+                        const int m0 = (KW == 16) ? (kg * 16 + 4 * lg) : (kg * 32 + 8 * lg);
+                        load_a<MODE>(a[rb][kg], prow + m0, ok);
+                    }
+                }
+            }
+            cur_rt = rt;
+        }
+        {
+#pragma unroll
+            for (int cb = 0; cb < FCB; ++cb) {
+                V acc[RBW];
+#pragma unroll
+                for (int rb = 0; rb < RBW; ++rb) acc[rb] = zero_acc<V>();
+                const Tc* crow_hi = Cs_hi[buf] + (cb * 16 + l16) * cld;
+                const Tc* crow_lo = Cs_lo[X3 ? buf : 0] + (cb * 16 + l16) * cld;
+#pragma unroll
+                for (int kg = 0; kg < KGMAX; ++kg) {
+                    if (kg < nkg) {
+                        if constexpr (MODE == DMD_RECON_FP32 || MODE == DMD_RECON_FP64) {
+                            const Tc* bp = crow_hi + kg * 16 + 4 * lg;
+                            Tc bv[4];
+                            if constexpr (MODE == DMD_RECON_FP32) {
+                                float4 x = *reinterpret_cast<const float4*>(bp);
+                                bv[0] = x.x; bv[1] = x.y; bv[2] = x.z; bv[3] = x.w;
+                            } else {
+                                double2 x = reinterpret_cast<const double2*>(bp)[0];
+                                double2 y = reinterpret_cast<const double2*>(bp)[1];
+                                bv[0] = x.x; bv[1] = x.y; bv[2] = y.x; bv[3] = y.y;
+                            }
+#pragma unroll
+                            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                                for (int rb = 0; rb < RBW; ++rb)
+                                    acc[rb] = mfma(a[rb][kg].v[s], bv[s], acc[rb]);
+                        } else {
+                            const bf16x8 bh = *reinterpret_cast<const bf16x8*>(crow_hi + kg * 32 + 8 * lg);
+                            if constexpr (X3) {
+                                const bf16x8 bl = *reinterpret_cast<const bf16x8*>(crow_lo + kg * 32 + 8 * lg);
+#pragma unroll
+                                for (int rb = 0; rb < RBW; ++rb) {
+                                    acc[rb] = mfma_bf16(a[rb][kg].lo, bh, acc[rb]);
+                                    acc[rb] = mfma_bf16(a[rb][kg].hi, bl, acc[rb]);
+                                    acc[rb] = mfma_bf16(a[rb][kg].hi, bh, acc[rb]);
+                                }
+                            } else {
+#pragma unroll
+                                for (int rb = 0; rb < RBW; ++rb)
+                                    acc[rb] = mfma_bf16(a[rb][kg].hi, bh, acc[rb]);
+                            }
+                        }
+                    }
+                }
+                // ---- epilogue: lane holds rows acc_row(lane, v) of frame cb*16 + l16
+                const int frame = f0 + cb * 16 + l16;
+                if (frame < f_end) {
+#pragma unroll
+                    for (int rb = 0; rb < RBW; ++rb) {
+                        const int64_t tile0 = tile_row0 + rb * 16;
+                        if constexpr (sizeof(Tout) == 4) {
+                            // f32 / bf16 accumulators: 4 consecutive rows per lane
+                            const int64_t row = tile0 + 4 * lg;
+                            if (row >= N) continue;
+                            Tout* dst = U + (int64_t)frame * ldu + row;
+                            Tout o[4];
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) o[v] = (Tout)acc[rb][v];
+                            if constexpr (RESID) {
+                                const Tout* src = Xt + (int64_t)frame * ldxt + row;
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    if (row + v < N) {
+                                        o[v] = src[v] - o[v];
+                                        ss += (double)o[v] * (double)o[v];
+                                    }
+                                }
+                            }
+                            if (vec_store && row + 4 <= N) {
+                                floatx4 w = {o[0], o[1], o[2], o[3]};
+                                if constexpr (RESID) *reinterpret_cast<floatx4*>(dst) = w;
+                                else __builtin_nontemporal_store(w, reinterpret_cast<floatx4*>(dst));
+                            } else {
+#pragma unroll
+                                for (int v = 0; v < 4; ++v)
+                                    if (row + v < N) dst[v] = o[v];
+                            }
+                        } else {
+                            // f64 accumulators: rows lg, lg + 4, lg + 8, lg + 12
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const int64_t row = tile0 + acc_row<V>(lane, v);
+                                if (row >= N) continue;
+                                Tout o = (Tout)acc[rb][v];
+                                Tout* dst = U + (int64_t)frame * ldu + row;
+                                if constexpr (RESID) {
+                                    o = Xt[(int64_t)frame * ldxt + row] - o;
+                                    ss += (double)o * (double)o;
+                                    *dst = o;
+                                } else {
+                                    __builtin_nontemporal_store(o, dst);
+                                }
+                            }
+                        }
+                    }
+                }
+            }
+        }
+        if (more) recon_put<PREF, X3>(pre_hi, pre_lo, Cs_hi[buf ^ 1], Cs_lo[X3 ? (buf ^ 1) : 0], tid, per_row, cld, FC, VE);
+        __syncthreads();
+    }
+    if constexpr (RESID) {
+        __shared__ double red[4];
+        ss = wave_sum(ss);
+        if (lane == 0) red[wave] = ss;
+        __syncthreads();
+        if (tid == 0) ss_partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// Single-buffered variant (an autotuner candidate): each work item is a row tile and a
+// range of frames; the coefficients of each FC-frame chunk are staged between two
+// barriers.  It suits very long frame ranges in plain BF16 better than the prefetching
+// kernel above on some shapes, so the autotuner times both.
 template <int MODE, int RBW, int FCB, bool RESID>
 __global__ void __launch_bounds__(256)
-recon_kernel(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi, int64_t N, int rp,
+recon_kernel_sb(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi, int64_t N, int rp,
              const typename RTraits<MODE>::Tc* __restrict__ Chi,
              const typename RTraits<MODE>::Tc* __restrict__ Clo, int K,
              typename RTraits<MODE>::Tout* U, int64_t ldu, int vec_store,
@@ -325,6 +548,28 @@ static hipError_t launch_recon_t(hipStream_t s, const ReconArgs& ra, int grid_pe
     constexpr int FC = FCB * 16;
     const int n_rowtiles = (int)ceil_div(ra.N, WG_ROWS);
     const int max_grid = device_cu_count() * grid_per_cu;
+    const int n_fc = (int)ceil_div(ra.K, FC);               // items are single chunks of FC frames
+    const int64_t items = (int64_t)n_rowtiles * n_fc;
+    const int64_t ipw = ceil_div(items, (int64_t)max_grid);
+    const int grid = (int)ceil_div(items, ipw);
+    hipLaunchKernelGGL((recon_kernel<MODE, RBW, FCB, RESID>), dim3(grid), dim3(256), 0, s,
+                       (const typename Tr::Tphi*)ra.phi, ra.ldphi, ra.N, ra.rp,
+                       (const typename Tr::Tc*)ra.c_hi, (const typename Tr::Tc*)ra.c_lo, ra.K,
+                       (typename Tr::Tout*)ra.U, ra.ldu, ra.vec_store,
+                       (const typename Tr::Tout*)ra.xt, ra.ldxt, ra.ss_partial,
+                       n_rowtiles, n_fc, (int)ipw);
+    if (ra.grid_out) *ra.grid_out = grid;
+    return hipGetLastError();
+}
+
+template <int MODE, int RBW, int FCB, bool RESID>
+static hipError_t launch_recon_sb(hipStream_t s, const ReconArgs& ra, int grid_per_cu)
+{
+    typedef RTraits<MODE> Tr;
+    constexpr int WG_ROWS = 4 * RBW * 16;
+    constexpr int FC = FCB * 16;
+    const int n_rowtiles = (int)ceil_div(ra.N, WG_ROWS);
+    const int max_grid = device_cu_count() * grid_per_cu;
     int n_fchunks = 1;
     const int max_fchunks = (int)ceil_div(ra.K, FC);
     if (n_rowtiles < 2 * max_grid) n_fchunks = (int)std::min<int64_t>(max_fchunks, ceil_div(2 * max_grid, n_rowtiles));
@@ -333,7 +578,7 @@ static hipError_t launch_recon_t(hipStream_t s, const ReconArgs& ra, int grid_pe
     n_fchunks = (int)ceil_div(ra.K, fpc);
     const int64_t items = (int64_t)n_rowtiles * n_fchunks;
     const int grid = (int)std::min<int64_t>(items, max_grid);
-    hipLaunchKernelGGL((recon_kernel<MODE, RBW, FCB, RESID>), dim3(grid), dim3(256), 0, s,
+    hipLaunchKernelGGL((recon_kernel_sb<MODE, RBW, FCB, RESID>), dim3(grid), dim3(256), 0, s,
                        (const typename Tr::Tphi*)ra.phi, ra.ldphi, ra.N, ra.rp,
                        (const typename Tr::Tc*)ra.c_hi, (const typename Tr::Tc*)ra.c_lo, ra.K,
                        (typename Tr::Tout*)ra.U, ra.ldu, ra.vec_store,
@@ -343,7 +588,8 @@ static hipError_t launch_recon_t(hipStream_t s, const ReconArgs& ra, int grid_pe
     return hipGetLastError();
 }
 
-// Tile-shape candidates (index = autotuner config id).
+// Tile-shape candidates (index = autotuner config id): <row blocks per wave, frame
+// blocks per item>, work-groups per CU.
 template <bool RESID>
 static hipError_t dispatch_recon(hipStream_t s, const ReconArgs& ra, int cfg)
 {
@@ -352,24 +598,36 @@ static hipError_t dispatch_recon(hipStream_t s, const ReconArgs& ra, int cfg)
         switch (cfg) {
         case 1: return launch_recon_t<DMD_RECON_FP64, 1, 1, RESID>(s, ra, 2);
         case 2: return launch_recon_t<DMD_RECON_FP64, 2, 2, RESID>(s, ra, 1);
+        case 3: return launch_recon_t<DMD_RECON_FP64, 1, 2, RESID>(s, ra, 1);
+        case 4: return launch_recon_t<DMD_RECON_FP64, 1, 1, RESID>(s, ra, 4);
+        case 5: return launch_recon_sb<DMD_RECON_FP64, 1, 2, RESID>(s, ra, 2);
         default: return launch_recon_t<DMD_RECON_FP64, 1, 2, RESID>(s, ra, 2);
         }
     case DMD_RECON_FP32:
         switch (cfg) {
         case 1: return launch_recon_t<DMD_RECON_FP32, 1, 2, RESID>(s, ra, 4);
         case 2: return launch_recon_t<DMD_RECON_FP32, 2, 4, RESID>(s, ra, 2);
+        case 3: return launch_recon_t<DMD_RECON_FP32, 2, 2, RESID>(s, ra, 1);
+        case 4: return launch_recon_t<DMD_RECON_FP32, 1, 4, RESID>(s, ra, 3);
+        case 5: return launch_recon_sb<DMD_RECON_FP32, 2, 2, RESID>(s, ra, 2);
         default: return launch_recon_t<DMD_RECON_FP32, 2, 2, RESID>(s, ra, 2);
         }
     case DMD_RECON_BF16:
         switch (cfg) {
         case 1: return launch_recon_t<DMD_RECON_BF16, 2, 2, RESID>(s, ra, 4);
         case 2: return launch_recon_t<DMD_RECON_BF16, 4, 4, RESID>(s, ra, 2);
+        case 3: return launch_recon_t<DMD_RECON_BF16, 2, 4, RESID>(s, ra, 3);
+        case 4: return launch_recon_t<DMD_RECON_BF16, 4, 2, RESID>(s, ra, 1);
+        case 5: return launch_recon_sb<DMD_RECON_BF16, 4, 2, RESID>(s, ra, 2);
         default: return launch_recon_t<DMD_RECON_BF16, 4, 2, RESID>(s, ra, 2);
         }
     default:
         switch (cfg) {
         case 1: return launch_recon_t<DMD_RECON_BF16X3, 2, 2, RESID>(s, ra, 4);
         case 2: return launch_recon_t<DMD_RECON_BF16X3, 4, 4, RESID>(s, ra, 2);
+        case 3: return launch_recon_t<DMD_RECON_BF16X3, 2, 4, RESID>(s, ra, 3);
+        case 4: return launch_recon_t<DMD_RECON_BF16X3, 4, 2, RESID>(s, ra, 1);
+        case 5: return launch_recon_sb<DMD_RECON_BF16X3, 4, 2, RESID>(s, ra, 2);
         default: return launch_recon_t<DMD_RECON_BF16X3, 4, 2, RESID>(s, ra, 2);
         }
     }
