@@ -8,9 +8,12 @@
 //                persistent GEMM over (row tile, frame chunk) work items.  The
 //                row tile of Phi stays in registers while the frames stream
 //                through LDS-staged chunks of C; every output element is written
-//                exactly once with non-temporal 16-byte stores.
+//                exactly once with non-temporal 16-byte stores, after a pass through
+//                LDS that makes each store instruction cover whole row runs of a frame.
 //                With RESID the epilogue forms R = Xt - U instead, and the FP64
 //                sum of squares of R (the adjoint's loss) per work-group.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -124,34 +127,125 @@ __device__ __forceinline__ void load_a(AFrag<MODE>& f, const typename RTraits<MO
 }
 
 // Coefficient rows of FC frames (16-byte moves, thread-strided) from global memory to
-// registers, and from registers to an LDS buffer with row stride cld.
+// registers, and from registers to an LDS buffer with row stride cld (>= rp + 16 bytes).
+// The moves in flight live in one vector value of 4*PREF floats, not an array: private
+// arrays share the compiler's register budget with the fragment array a[][], and past it
+// they go to scratch.  Both copies are straight-line code.
+template <int PREF> using PrefV = float __attribute__((ext_vector_type(4 * PREF)));
+
+template <int PREF>
+__device__ __forceinline__ float4 pref_get(const PrefV<PREF>& v, int q)
+{
+    return make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+template <int PREF>
+__device__ __forceinline__ void pref_set(PrefV<PREF>& v, int q, float4 x)
+{
+    v[4 * q] = x.x; v[4 * q + 1] = x.y; v[4 * q + 2] = x.z; v[4 * q + 3] = x.w;
+}
+
 template <int PREF, bool X3, typename Tc>
-__device__ __forceinline__ void recon_fetch(float4 (&hi)[PREF], float4 (&lo)[PREF], const Tc* __restrict__ Chi,
+__device__ __forceinline__ void recon_fetch(PrefV<PREF>& hi, PrefV<PREF>& lo, const Tc* __restrict__ Chi,
                                             const Tc* __restrict__ Clo, int tid, int per_row, int f0, int rp,
                                             int FC, int VE)
 {
 #pragma unroll
     for (int q = 0; q < PREF; ++q) {
-        const int idx = tid + q * 256;
-        if (idx < FC * per_row) {
-            const int fr = idx / per_row, c = (idx % per_row) * VE;
-            const int64_t src = (int64_t)(f0 + fr) * rp + c;
-            hi[q] = *reinterpret_cast<const float4*>(&Chi[src]);
-            if constexpr (X3) lo[q] = *reinterpret_cast<const float4*>(&Clo[src]);
-        }
+        // a move past the chunk re-reads its first piece (recon_put drops it)
+        const int idx = tid + q * 256 < FC * per_row ? tid + q * 256 : 0;
+        const int fr = idx / per_row, c = (idx % per_row) * VE;
+        const int64_t src = (int64_t)(f0 + fr) * rp + c;
+        pref_set<PREF>(hi, q, *reinterpret_cast<const float4*>(&Chi[src]));
+        if constexpr (X3) pref_set<PREF>(lo, q, *reinterpret_cast<const float4*>(&Clo[src]));
     }
 }
 template <int PREF, bool X3, typename Tc>
-__device__ __forceinline__ void recon_put(const float4 (&hi)[PREF], const float4 (&lo)[PREF], Tc* Sh, Tc* Sl,
+__device__ __forceinline__ void recon_put(const PrefV<PREF>& hi, const PrefV<PREF>& lo, Tc* Sh, Tc* Sl,
                                           int tid, int per_row, int cld, int FC, int VE)
 {
 #pragma unroll
     for (int q = 0; q < PREF; ++q) {
+        // a move past the chunk lands in the row pad of frame 0, which no MFMA operand
+        // reads (columns >= rp = per_row * VE)
         const int idx = tid + q * 256;
-        if (idx < FC * per_row) {
-            const int fr = idx / per_row, c = (idx % per_row) * VE;
-            *reinterpret_cast<float4*>(&Sh[fr * cld + c]) = hi[q];
-            if constexpr (X3) *reinterpret_cast<float4*>(&Sl[fr * cld + c]) = lo[q];
+        const bool ok = idx < FC * per_row;
+        const int fr = idx / per_row, c = (idx % per_row) * VE;
+        const int off = ok ? fr * cld + c : per_row * VE;
+        *reinterpret_cast<float4*>(&Sh[off]) = pref_get<PREF>(hi, q);
+        if constexpr (X3) *reinterpret_cast<float4*>(&Sl[off]) = pref_get<PREF>(lo, q);
+    }
+}
+
+// Intra-wave ordering of the LDS tile used by recon_store (every lane writes, then
+// other lanes of the same wave read).
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Epilogue of one 16-frame block.  The wave holds RW = 16*RBW consecutive rows of
+// frames fb .. fb+15, in the MFMA layout (lane l: frame fb + l%16, 16-row pieces).
+// Stored as is, one store instruction would write 16 frames x 64 bytes, half of a
+// 128-byte line per frame.  The block goes through the wave's own LDS tile st
+// (16 x (RW + pad) elements) and comes back frame-major: each lane then holds 16
+// contiguous bytes of one frame and each instruction writes 4*RW (FP32) or 8*RW (FP64)
+// contiguous bytes per frame.  With RESID the stored value is Xt - U and its square
+// is added to ss.  Frames >= f_end and rows >= N are not written.
+template <typename Tout, typename V, int RBW, bool RESID>
+__device__ __forceinline__ void recon_store(const V (&acc)[RBW], Tout* st, int lane, int fb, int f_end,
+                                            int64_t row0, int64_t N, Tout* U, int64_t ldu, int vec_store,
+                                            const Tout* __restrict__ Xt, int64_t ldxt, double& ss)
+{
+    constexpr int RW = 16 * RBW;
+    constexpr int VEC = 16 / sizeof(Tout);    // elements per 16-byte piece
+    constexpr int SLD = RW + VEC;             // tile row stride (one piece of pad)
+    constexpr int LPF = RW / VEC;             // lanes per frame on the way out
+    constexpr int FPI = 64 / LPF;             // frames per store instruction
+    typedef typename std::conditional<sizeof(Tout) == 4, floatx4, doublex2>::type OV;
+    const int l16 = lane & 15;
+    wave_sync_lds();                          // the previous block's reads are done
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb) {
+        Tout* t = st + l16 * SLD + rb * 16;
+        if constexpr (sizeof(Tout) == 4) {
+            *reinterpret_cast<floatx4*>(t + acc_row<V>(lane, 0)) = acc[rb];
+        } else {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) t[acc_row<V>(lane, v)] = acc[rb][v];
+        }
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int q = 0; q < 16 / FPI; ++q) {
+        const int fl = q * FPI + lane / LPF;
+        const int rr = (lane % LPF) * VEC;
+        const int frame = fb + fl;
+        const int64_t row = row0 + rr;
+        // a vector, not an array: private arrays count against the compiler's budget for
+        // keeping such arrays in registers, which the fragment array a[][] nearly fills
+        OV o = *reinterpret_cast<const OV*>(st + fl * SLD + rr);
+        if (frame >= f_end || row >= N) continue;
+        Tout* dst = U + (int64_t)frame * ldu + row;
+        const bool full = vec_store && row + VEC <= N;
+        if constexpr (RESID) {
+            const Tout* src = Xt + (int64_t)frame * ldxt + row;
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                if (row + v < N) {
+                    o[v] = src[v] - o[v];
+                    ss += (double)o[v] * (double)o[v];
+                }
+            }
+        }
+        if (full) {
+            if constexpr (RESID) *reinterpret_cast<OV*>(dst) = o;
+            else __builtin_nontemporal_store(o, reinterpret_cast<OV*>(dst));
+        } else {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+                if (row + v < N) dst[v] = o[v];
         }
     }
 }
@@ -187,6 +281,7 @@ recon_kernel(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi
 
     __shared__ __align__(16) Tc Cs_hi[2][FC * CLD];
     __shared__ __align__(16) Tc Cs_lo[X3 ? 2 : 1][X3 ? FC * CLD : 1];
+    __shared__ __align__(16) Tout Ost[4][16 * (16 * RBW + 16 / sizeof(Tout))];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lg = lane >> 4;
@@ -201,7 +296,7 @@ recon_kernel(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi
     const int64_t it_begin = (int64_t)blockIdx.x * items_per_wg;
     const int64_t it_end = min(n_items, it_begin + items_per_wg);
 
-    float4 pre_hi[PREF], pre_lo[PREF];
+    PrefV<PREF> pre_hi, pre_lo;
     if (it_begin < it_end) {
         recon_fetch<PREF, X3>(pre_hi, pre_lo, Chi, Clo, tid, per_row, (int)(it_begin % n_fchunks) * FC, rp, FC, VE);
         recon_put<PREF, X3>(pre_hi, pre_lo, Cs_hi[0], Cs_lo[0], tid, per_row, cld, FC, VE);
@@ -276,58 +371,8 @@ recon_kernel(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi
                         }
                     }
                 }
-                // ---- epilogue: lane holds rows acc_row(lane, v) of frame cb*16 + l16
-                const int frame = f0 + cb * 16 + l16;
-                if (frame < f_end) {
-#pragma unroll
-                    for (int rb = 0; rb < RBW; ++rb) {
-                        const int64_t tile0 = tile_row0 + rb * 16;
-                        if constexpr (sizeof(Tout) == 4) {
-                            // f32 / bf16 accumulators: 4 consecutive rows per lane
-                            const int64_t row = tile0 + 4 * lg;
-                            if (row >= N) continue;
-                            Tout* dst = U + (int64_t)frame * ldu + row;
-                            Tout o[4];
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) o[v] = (Tout)acc[rb][v];
-                            if constexpr (RESID) {
-                                const Tout* src = Xt + (int64_t)frame * ldxt + row;
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    if (row + v < N) {
-                                        o[v] = src[v] - o[v];
-                                        ss += (double)o[v] * (double)o[v];
-                                    }
-                                }
-                            }
-                            if (vec_store && row + 4 <= N) {
-                                floatx4 w = {o[0], o[1], o[2], o[3]};
-                                if constexpr (RESID) *reinterpret_cast<floatx4*>(dst) = w;
-                                else __builtin_nontemporal_store(w, reinterpret_cast<floatx4*>(dst));
-                            } else {
-#pragma unroll
-                                for (int v = 0; v < 4; ++v)
-                                    if (row + v < N) dst[v] = o[v];
-                            }
-                        } else {
-                            // f64 accumulators: rows lg, lg + 4, lg + 8, lg + 12
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int64_t row = tile0 + acc_row<V>(lane, v);
-                                if (row >= N) continue;
-                                Tout o = (Tout)acc[rb][v];
-                                Tout* dst = U + (int64_t)frame * ldu + row;
-                                if constexpr (RESID) {
-                                    o = Xt[(int64_t)frame * ldxt + row] - o;
-                                    ss += (double)o * (double)o;
-                                    *dst = o;
-                                } else {
-                                    __builtin_nontemporal_store(o, dst);
-                                }
-                            }
-                        }
-                    }
-                }
+                recon_store<Tout, V, RBW, RESID>(acc, Ost[wave], lane, f0 + cb * 16, f_end, tile_row0, N,
+                                                 U, ldu, vec_store, Xt, ldxt, ss);
             }
         }
         if (more) recon_put<PREF, X3>(pre_hi, pre_lo, Cs_hi[buf ^ 1], Cs_lo[X3 ? (buf ^ 1) : 0], tid, per_row, cld, FC, VE);
@@ -370,6 +415,7 @@ recon_kernel_sb(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ld
 
     __shared__ __align__(16) Tc Cs_hi[FC * CLD];
     __shared__ __align__(16) Tc Cs_lo[X3 ? FC * CLD : 1];
+    __shared__ __align__(16) Tout Ost[4][16 * (16 * RBW + 16 / sizeof(Tout))];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, lg = lane >> 4;
@@ -462,58 +508,8 @@ recon_kernel_sb(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ld
                         }
                     }
                 }
-                // ---- epilogue: lane holds rows acc_row(lane, v) of frame cb*16 + l16
-                const int frame = f0 + cb * 16 + l16;
-                if (frame < f_end) {
-#pragma unroll
-                    for (int rb = 0; rb < RBW; ++rb) {
-                        const int64_t tile0 = tile_row0 + rb * 16;
-                        if constexpr (sizeof(Tout) == 4) {
-                            // f32 / bf16 accumulators: 4 consecutive rows per lane
-                            const int64_t row = tile0 + 4 * lg;
-                            if (row >= N) continue;
-                            Tout* dst = U + (int64_t)frame * ldu + row;
-                            Tout o[4];
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) o[v] = (Tout)acc[rb][v];
-                            if constexpr (RESID) {
-                                const Tout* src = Xt + (int64_t)frame * ldxt + row;
-#pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    if (row + v < N) {
-                                        o[v] = src[v] - o[v];
-                                        ss += (double)o[v] * (double)o[v];
-                                    }
-                                }
-                            }
-                            if (vec_store && row + 4 <= N) {
-                                floatx4 w = {o[0], o[1], o[2], o[3]};
-                                if constexpr (RESID) *reinterpret_cast<floatx4*>(dst) = w;
-                                else __builtin_nontemporal_store(w, reinterpret_cast<floatx4*>(dst));
-                            } else {
-#pragma unroll
-                                for (int v = 0; v < 4; ++v)
-                                    if (row + v < N) dst[v] = o[v];
-                            }
-                        } else {
-                            // f64 accumulators: rows lg, lg + 4, lg + 8, lg + 12
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const int64_t row = tile0 + acc_row<V>(lane, v);
-                                if (row >= N) continue;
-                                Tout o = (Tout)acc[rb][v];
-                                Tout* dst = U + (int64_t)frame * ldu + row;
-                                if constexpr (RESID) {
-                                    o = Xt[(int64_t)frame * ldxt + row] - o;
-                                    ss += (double)o * (double)o;
-                                    *dst = o;
-                                } else {
-                                    __builtin_nontemporal_store(o, dst);
-                                }
-                            }
-                        }
-                    }
-                }
+                recon_store<Tout, V, RBW, RESID>(acc, Ost[wave], lane, f0 + cb * 16, f_end, tile_row0, N,
+                                                 U, ldu, vec_store, Xt, ldxt, ss);
             }
         }
     }
