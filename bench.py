@@ -65,9 +65,10 @@ def _traffic(bytes_alg):
         return None
 
 
-def cpu_baseline(g, cfg, rows_sample=16384):
-    """The FP64 oracle on the host: the randomized twin fit on the full input, plus the
-    reconstruction of all K frames and one loss/gradient on a row sample, scaled to N."""
+def cpu_baseline(g, cfg, rows_sample=65536):
+    """The FP64 oracle on the host: the randomized twin fit on the full input (repeated up
+    to three times, about 6 s, mean taken), plus the reconstruction of all K frames and one
+    loss/gradient on a row sample, scaled to N: about 10 s of host work in all."""
     import numpy as np
 
     import oracle
@@ -77,9 +78,12 @@ def cpu_baseline(g, cfg, rows_sample=16384):
     except Exception:
         threads = os.cpu_count() or 1
     Zd = g.Z.astype(np.float64)
-    t0 = time.perf_counter()
-    tw = oracle.fit_randomized(Zd, cfg.r, g.Omega.astype(np.float64), cfg.q)
-    t_fit = time.perf_counter() - t0
+    t_fits = []
+    while len(t_fits) < 3 and sum(t_fits) < 6.0:
+        t0 = time.perf_counter()
+        tw = oracle.fit_randomized(Zd, cfg.r, g.Omega.astype(np.float64), cfg.q)
+        t_fits.append(time.perf_counter() - t0)
+    t_fit = sum(t_fits) / len(t_fits)
     rows = np.sort(np.random.default_rng(1).choice(cfg.N, rows_sample, replace=False))
     ks = np.arange(cfg.K)
     t0 = time.perf_counter()
@@ -95,7 +99,7 @@ def cpu_baseline(g, cfg, rows_sample=16384):
         "cores": int(threads),
         "kind": "oracle",
         "sample": (f"one step of the FP64 NumPy oracle: randomized-SVD twin fit on the full input "
-                   f"({t_fit:.2f} s), reconstruction of all {cfg.K} frames ({t_rec:.2f} s) and one "
+                   f"({t_fit:.2f} s, mean of {len(t_fits)}), reconstruction of all {cfg.K} frames ({t_rec:.2f} s) and one "
                    f"loss+gradient over {cfg.m} frames ({t_adj:.2f} s), the latter two measured on "
                    f"{rows_sample} of {cfg.N} rows and scaled linearly to N"),
         "fit_s": round(t_fit, 3),
