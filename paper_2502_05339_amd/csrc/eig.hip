@@ -9,11 +9,13 @@
 //     deflation, producing the real Schur form T; each work-group rebuilds and
 //     updates only its own nr rows of the Schur vectors Z (Z = Q * product of
 //     the QR reflectors), so no work-group ever waits for another.  2 x 2
-//     diagonal blocks with real eigenvalues are split by a rotation.  Then the
-//     eigenvectors of T are found by back-substitution (one wave per eigenvalue,
-//     complex arithmetic for conjugate pairs), normalised to unit 2-norm (Z is
-//     orthogonal, so the norm carries over) and multiplied by the work-group's
-//     rows of Z.
+//     diagonal blocks with real eigenvalues are split by a rotation.  T, its block
+//     structure and Z go to global scratch.
+//  2b. eigvec_kernel (one single-wave work-group per eigenvalue): the eigenvector x
+//     of T by back-substitution, column by column (each lane keeps the residual of
+//     its rows, so a row costs one complex product and a broadcast), normalised to
+//     unit 2-norm (Z is orthogonal, so the norm carries over), then the column
+//     Z x of the eigenvector matrix (folded: [Re, Im] for a conjugate pair).
 //  3. sort_modes_kernel (1 work-group): canonical order (ascending |arg lambda|,
 //     ties by descending |lambda|, Im > 0 member of a pair first), lambda, kind
 //     and the permuted folded eigenvectors (pair -> [Re w, Im w], LAPACK storage).
@@ -33,7 +35,9 @@ struct EigWs {
     double* wr;     // n
     double* wi;     // n
     int32_t* kind0; // n
-    double* X;      // grid x n x n per-work-group eigenvectors of T
+    double* Z;      // n x n Schur vectors, column-major
+    double* T;      // real Schur form, packed as in francis_kernel (<= n x n), then max |T_ij|
+    int32_t* blk;   // n: 0 real eigenvalue, 1/2 first/second of a 2 x 2 block
 };
 
 static int eig_rows_per_wg(int n) { return n <= 64 ? 8 : 16; }
@@ -42,8 +46,7 @@ static int eig_grid(int n) { return (int)ceil_div(n, eig_rows_per_wg(n)); }
 size_t eig_workspace_bytes(int n)
 {
     size_t nn = (size_t)n * n;
-    return (3 * nn + 4 * (size_t)n) * sizeof(double) + (size_t)n * sizeof(int32_t) + 64 +
-           (size_t)eig_grid(n) * nn * sizeof(double) + 256;
+    return (5 * nn + 2 + 4 * (size_t)n) * sizeof(double) + 2 * (size_t)round_up((int64_t)n * sizeof(int32_t), 64) + 256;
 }
 
 static EigWs eig_carve(void* ws, int n)
@@ -54,13 +57,15 @@ static EigWs eig_carve(void* ws, int n)
     w.H = p; p += nn;
     w.V = p; p += nn;
     w.Wraw = p; p += nn;
+    w.Z = p; p += nn;
+    w.T = p; p += nn + 2;                // + max |T_ij|
     w.tau = p; p += n;
     w.wr = p; p += n;
     w.wi = p; p += n;
     p += n;
     w.kind0 = (int32_t*)p;
     p = (double*)((char*)p + round_up((int64_t)n * sizeof(int32_t), 64));
-    w.X = p;
+    w.blk = (int32_t*)p;
     return w;
 }
 
@@ -272,8 +277,8 @@ __device__ __forceinline__ void reflector3(double x, double y, double z, double*
 
 __global__ void __launch_bounds__(FR_THREADS)
 francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __restrict__ Vg,
-               const double* __restrict__ taug, double* Wraw, double* wr, double* wi, int32_t* kind0,
-               double* Xall, int32_t* info, double defl_tol)
+               const double* __restrict__ taug, double* Zg, double* Tg, int32_t* blkg, double* wr, double* wi,
+               int32_t* kind0, int32_t* info, double defl_tol)
 {
     extern __shared__ double sm[];
     int* blk = reinterpret_cast<int*>(sm);                      // n ints
@@ -287,7 +292,6 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
     const int hsize = hp_col(n, n);
     double* Zs = Hs + hsize;                                    // nr x n
-    double* xs = Zs + (int64_t)nr * n;                          // nw x 2n (eigenvector scratch)
     HP H{Hs, n};
     const int r0 = blockIdx.x * nr;
     const int nrows = min(nr, n - r0);
@@ -535,124 +539,163 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
             }
         }
     }
-    // ---- eigenvectors of T, one wave per eigenvalue unit; x in LDS scratch (re, im)
-    double* X = Xall + (int64_t)blockIdx.x * n * n;
-    __syncthreads();
-    {
+    // ---- T, max |T_ij| (stored after T), the block structure and this work-group's rows
+    // of Z to global scratch
+    if (blockIdx.x == 0) {
         double mx = 0.0;
         for (int j = tid; j < n; j += nt)
             for (int i = 0; i <= min(j + 1, n - 1); ++i) mx = fmax(mx, fabs(H(i, j)));
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+        __syncthreads();
         if (lane == 0) sh_red[wave] = mx;
         __syncthreads();
-        if (tid == 0) { double m = 0.0; for (int w = 0; w < nw; ++w) m = fmax(m, sh_red[w]); sh_red[0] = m; }
-        __syncthreads();
+        if (tid == 0) { double m = 0.0; for (int w = 0; w < nw; ++w) m = fmax(m, sh_red[w]); Tg[hsize] = m; }
+        for (int e = tid; e < hsize; e += nt) Tg[e] = Hs[e];
+        for (int k = tid; k < n; k += nt) blkg[k] = blk[k];
     }
-    const double tnorm = sh_red[0];
-    const double smin = fmax(eps * tnorm, 1e-290);
-    double* xr = xs + (int64_t)wave * 2 * n;
-    double* xi = xr + n;
-    for (int k = 0; k < n; ++k) {
-        if (blk[k] == 2) continue;
-        // unit owner: round-robin over units by wave
-        int unit = 0;
-        for (int u = 0; u < k; ++u) if (blk[u] != 2) ++unit;
-        if (unit % nw != wave) continue;
-        const bool pair = blk[k] == 1;
-        const int top = pair ? k + 1 : k;
-        double lre, lim;
-        if (!pair) { lre = H(k, k); lim = 0.0; }
-        else {
-            const double a = H(k, k), b = H(k, k + 1), c = H(k + 1, k), d = H(k + 1, k + 1);
-            const double hp = 0.5 * (a - d);
-            lre = 0.5 * (a + d);
-            lim = sqrt(fmax(-(hp * hp + b * c), 0.0));
-        }
-        for (int i = lane; i < n; i += 64) { xr[i] = 0.0; xi[i] = 0.0; }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (lane == 0) {
-            if (!pair) { xr[k] = 1.0; }
-            else {
-                const double a = H(k, k), b = H(k, k + 1), c = H(k + 1, k), d = H(k + 1, k + 1);
-                // eigenvector of [[a b][c d]] for lre + i lim: (b, lambda - a) or (lambda - d, c)
-                double e1r = b, e1i = 0.0, e2r = lre - a, e2i = lim;
-                double f1r = lre - d, f1i = lim, f2r = c, f2i = 0.0;
-                if (e1r * e1r + e2r * e2r + e2i * e2i < f1r * f1r + f1i * f1i + f2r * f2r) {
-                    e1r = f1r; e1i = f1i; e2r = f2r; e2i = f2i;
-                }
-                xr[k] = e1r; xi[k] = e1i; xr[k + 1] = e2r; xi[k + 1] = e2i;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        int i = k - 1;
-        while (i >= 0) {
-            const bool two = (blk[i] == 2);
-            const int ia = two ? i - 1 : i;
-            // r_row = -sum_{j = i+1 .. top} T(row, j) x_j   for row in {ia, i}
-            double s0r = 0.0, s0i = 0.0, s1r = 0.0, s1i = 0.0;
-            for (int j = i + 1 + lane; j <= top; j += 64) {
-                const double t1 = H(i, j);
-                s1r += t1 * xr[j]; s1i += t1 * xi[j];
-                if (two) { const double t0 = H(ia, j); s0r += t0 * xr[j]; s0i += t0 * xi[j]; }
-            }
-            s1r = -wave_sum(s1r); s1i = -wave_sum(s1i);
-            if (two) { s0r = -wave_sum(s0r); s0i = -wave_sum(s0i); }
-            if (lane == 0) {
-                if (!two) {
-                    cplx dd = {H(i, i) - lre, -lim};
-                    if (fabs(dd.re) + fabs(dd.im) < smin) dd = {smin, 0.0};
-                    cplx v = cdiv({s1r, s1i}, dd);
-                    xr[i] = v.re; xi[i] = v.im;
-                } else {
-                    // [[T(ia,ia)-lam, T(ia,i)], [T(i,ia), T(i,i)-lam]] [x_ia; x_i] = [s0; s1]
-                    cplx a11 = {H(ia, ia) - lre, -lim}, a12 = {H(ia, i), 0.0};
-                    cplx a21 = {H(i, ia), 0.0}, a22 = {H(i, i) - lre, -lim};
-                    cplx det = csub(cmul(a11, a22), cmul(a12, a21));
-                    if (fabs(det.re) + fabs(det.im) < smin * smin) det = {smin * smin, 0.0};
-                    cplx x0 = cdiv(csub(cmul({s0r, s0i}, a22), cmul(a12, {s1r, s1i})), det);
-                    cplx x1 = cdiv(csub(cmul(a11, {s1r, s1i}), cmul(a21, {s0r, s0i})), det);
-                    xr[ia] = x0.re; xi[ia] = x0.im; xr[i] = x1.re; xi[i] = x1.im;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            // guard against overflow: rescale when the entries grow large
-            double mx = 0.0;
-            for (int j = ia + lane; j <= top; j += 64) mx = fmax(mx, fabs(xr[j]) + fabs(xi[j]));
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-            if (mx > 1e100) {
-                for (int j = ia + lane; j <= top; j += 64) { xr[j] *= 1e-100; xi[j] *= 1e-100; }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-            }
-            i = ia - 1;
-        }
-        // normalise (complex 2-norm) and store the folded columns
-        double nn2 = 0.0;
-        for (int j = lane; j <= top; j += 64) nn2 += xr[j] * xr[j] + xi[j] * xi[j];
-        nn2 = wave_sum(nn2);
-        const double inv = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 0.0;
-        for (int j = lane; j < n; j += 64) {
-            X[(int64_t)k * n + j] = xr[j] * inv;
-            if (pair) X[(int64_t)(k + 1) * n + j] = xi[j] * inv;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-    __syncthreads();
-    __threadfence_block();
-    // ---- W rows of this work-group = Z_slab X
     for (int e = tid; e < nrows * n; e += nt) {
         const int rl = e % nrows, c = e / nrows;
-        const double* xc = X + (int64_t)c * n;
-        const double* z = Zs + rl * n;
-        double s = 0.0;
-        for (int m = 0; m < n; ++m) s += z[m] * xc[m];
-        Wraw[(int64_t)c * n + r0 + rl] = s;
+        Zg[(int64_t)c * n + r0 + rl] = Zs[rl * n + c];
+    }
+}
+
+// ====================================================================== 2b. eigenvectors
+// Eigenvector of the quasi-triangular T for eigenvalue index k (lambda = lre + i lim; a
+// pair's first member has lim > 0), by back-substitution on (T - lambda) x = 0 with x_j = 0
+// for j > top.  Column-oriented: lane l keeps the residuals r_i = -sum_{j > i} T(i, j) x_j
+// of rows i = l, l + 64, l + 128; once x_i (or the pair x_ia, x_i of a 2 x 2 block) is known
+// from the owner lane's residual, every lane subtracts T(i', i) x_i from its rows i' above.
+// Tiny pivots are raised to smin; entries past 1e100 rescale x and r.
+constexpr int EV_SLOTS = (EIG_MAX + 63) / 64;
+static_assert(EV_SLOTS <= 4, "eigvec_kernel keeps at most 4 rows per lane");
+// rows of one lane, as one vector value: a run-time element index on a vector stays in
+// registers, where the same index on a private array would put it in scratch
+typedef double evrow __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ double bcast(double v, int src)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+__global__ void __launch_bounds__(64)
+eigvec_kernel(int n, const double* __restrict__ Tg, const int32_t* __restrict__ blkg,
+              const double* __restrict__ Zg, double* __restrict__ Wraw, double eps)
+{
+    extern __shared__ __align__(16) double evs[];
+    const int k = blockIdx.x, lane = threadIdx.x;
+    const int bk = blkg[k];
+    if (bk == 2) return;                                   // second member: done with the first
+    const bool pair = bk == 1;
+    const int top = pair ? k + 1 : k;
+    const int tsize = hp_col(top + 1, n);                  // columns 0..top of T
+    double* Ts = evs;
+    double* xs = evs + round_up(hp_col(n, n), 2);          // 2n: normalised Re, Im of x
+    int* bs = reinterpret_cast<int*>(xs + 2 * n);          // n: block structure
+    for (int e = lane; e < tsize; e += 64) Ts[e] = Tg[e];
+    for (int e = lane; e < n; e += 64) bs[e] = blkg[e];
+    __syncthreads();
+    HP T{Ts, n};
+
+    const double smin = fmax(eps * Tg[hp_col(n, n)], 1e-290);   // max |T_ij| is stored after T
+    double lre, lim;
+    cplx xk, xk1 = {0.0, 0.0};
+    if (!pair) { lre = T(k, k); lim = 0.0; xk = {1.0, 0.0}; }
+    else {
+        const double a = T(k, k), b = T(k, k + 1), c = T(k + 1, k), d = T(k + 1, k + 1);
+        const double hp = 0.5 * (a - d);
+        lre = 0.5 * (a + d);
+        lim = sqrt(fmax(-(hp * hp + b * c), 0.0));
+        // eigenvector of [[a b][c d]] for lre + i lim: (b, lambda - a) or (lambda - d, c)
+        double e1r = b, e1i = 0.0, e2r = lre - a, e2i = lim;
+        const double f1r = lre - d, f1i = lim, f2r = c, f2i = 0.0;
+        if (e1r * e1r + e2r * e2r + e2i * e2i < f1r * f1r + f1i * f1i + f2r * f2r) {
+            e1r = f1r; e1i = f1i; e2r = f2r; e2i = f2i;
+        }
+        xk = {e1r, e1i};
+        xk1 = {e2r, e2i};
+    }
+    // this lane's rows: residuals and solution entries
+    evrow rr, ri, xr, xi;
+#pragma unroll
+    for (int s = 0; s < EV_SLOTS; ++s) {
+        const int row = lane + 64 * s;
+        rr[s] = 0.0; ri[s] = 0.0;
+        xr[s] = row == k ? xk.re : (pair && row == k + 1 ? xk1.re : 0.0);
+        xi[s] = row == k ? xk.im : (pair && row == k + 1 ? xk1.im : 0.0);
+        if (row < k) {
+            const double t0 = T(row, k);
+            rr[s] = -t0 * xk.re; ri[s] = -t0 * xk.im;
+            if (pair) { const double t1 = T(row, k + 1); rr[s] -= t1 * xk1.re; ri[s] -= t1 * xk1.im; }
+        }
+    }
+    int i = k - 1;
+    while (i >= 0) {
+        const bool two = bs[i] == 2;
+        const int ia = two ? i - 1 : i;
+        // residuals of rows ia, i from their owner lanes
+        auto slot_val = [&](const evrow& v, int row) { return bcast(v[row >> 6], row & 63); };
+        cplx x1, x0 = {0.0, 0.0};
+        const cplx s1 = {slot_val(rr, i), slot_val(ri, i)};
+        if (!two) {
+            cplx d = {T(i, i) - lre, -lim};
+            if (fabs(d.re) + fabs(d.im) < smin) d = {smin, 0.0};
+            x1 = cdiv(s1, d);
+        } else {
+            const cplx s0 = {slot_val(rr, ia), slot_val(ri, ia)};
+            // [[T(ia,ia)-lam, T(ia,i)], [T(i,ia), T(i,i)-lam]] [x_ia; x_i] = [s0; s1]
+            const cplx a11 = {T(ia, ia) - lre, -lim}, a12 = {T(ia, i), 0.0};
+            const cplx a21 = {T(i, ia), 0.0}, a22 = {T(i, i) - lre, -lim};
+            cplx det = csub(cmul(a11, a22), cmul(a12, a21));
+            if (fabs(det.re) + fabs(det.im) < smin * smin) det = {smin * smin, 0.0};
+            x0 = cdiv(csub(cmul(s0, a22), cmul(a12, s1)), det);
+            x1 = cdiv(csub(cmul(a11, s1), cmul(a21, s0)), det);
+        }
+        // guard against overflow: rescale x and r when the new entries grow large
+        const double big = fmax(fabs(x1.re) + fabs(x1.im), fabs(x0.re) + fabs(x0.im));
+        const double sc = big > 1e100 ? 1e-100 : 1.0;
+        x1.re *= sc; x1.im *= sc; x0.re *= sc; x0.im *= sc;
+#pragma unroll
+        for (int s = 0; s < EV_SLOTS; ++s) {
+            const int row = lane + 64 * s;
+            rr[s] *= sc; ri[s] *= sc; xr[s] *= sc; xi[s] *= sc;
+            if (row == i) { xr[s] = x1.re; xi[s] = x1.im; }
+            if (two && row == ia) { xr[s] = x0.re; xi[s] = x0.im; }
+            if (row < ia) {
+                const double t1 = T(row, i);
+                rr[s] -= t1 * x1.re; ri[s] -= t1 * x1.im;
+                if (two) { const double t0 = T(row, ia); rr[s] -= t0 * x0.re; ri[s] -= t0 * x0.im; }
+            }
+        }
+        i = ia - 1;
+    }
+    // normalise (complex 2-norm) and stage x for the product with Z
+    double nn2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < EV_SLOTS; ++s) nn2 += xr[s] * xr[s] + xi[s] * xi[s];
+    nn2 = wave_sum(nn2);
+    const double inv = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 0.0;
+#pragma unroll
+    for (int s = 0; s < EV_SLOTS; ++s) {
+        const int row = lane + 64 * s;
+        if (row < n) { xs[row] = xr[s] * inv; xs[n + row] = xi[s] * inv; }
+    }
+    __syncthreads();
+    // W[:, k] = Z Re(x) (and W[:, k+1] = Z Im(x) for a pair); Z is column-major
+#pragma unroll
+    for (int s = 0; s < EV_SLOTS; ++s) {
+        const int row = lane + 64 * s;
+        if (row >= n) continue;
+        double wre = 0.0, wim = 0.0;
+        for (int j = 0; j <= top; ++j) {
+            const double z = Zg[(int64_t)j * n + row];
+            wre += z * xs[j];
+            wim += z * xs[n + j];
+        }
+        Wraw[(int64_t)k * n + row] = wre;
+        if (pair) Wraw[(int64_t)(k + 1) * n + row] = wim;
     }
 }
 
@@ -712,11 +755,14 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
     const int grid = eig_grid(n);
     const int hsize = hp_col(n, n);
     const int nw = FR_THREADS / 64;
-    const size_t lds = (size_t)(round_up(n, 2) / 2) * 8 + (size_t)hsize * 8 + (size_t)nr * n * 8 +
-                       (size_t)nw * 2 * n * 8;
+    const size_t lds = (size_t)(round_up(n, 2) / 2) * 8 + (size_t)hsize * 8 + (size_t)nr * n * 8;
     if (lds > 160 * 1024 - 512) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(francis_kernel, dim3(grid), dim3(64 * nw), lds, s, n, nr, w.H, w.V, w.tau, w.Wraw,
-                       w.wr, w.wi, w.kind0, w.X, info, defl_tol);
+    hipLaunchKernelGGL(francis_kernel, dim3(grid), dim3(64 * nw), lds, s, n, nr, w.H, w.V, w.tau, w.Z, w.T,
+                       w.blk, w.wr, w.wi, w.kind0, info, defl_tol);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t evlds = ((size_t)round_up(hsize, 2) + 2 * (size_t)n) * 8 + (size_t)n * 4;
+    hipLaunchKernelGGL(eigvec_kernel, dim3(n), dim3(64), evlds, s, n, w.T, w.blk, w.Z, w.Wraw, defl_tol);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sort_modes_kernel, dim3(1), dim3(256), n * sizeof(int), s, n, w.wr, w.wi, w.kind0,
