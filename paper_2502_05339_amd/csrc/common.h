@@ -69,6 +69,25 @@ __device__ __forceinline__ void set_status(int32_t* info, int32_t code) {
     if (info) atomicCAS(info, 0, code);
 }
 
+// ---------------------------------------------------------------- fast FP64 reciprocals
+// 1/sqrt(s) for s > 0 and 1/s for s != 0 (normal range): the hardware estimates (about 23
+// correct bits) refined by two Newton steps each, which leaves an error of a few ulp.
+__device__ __forceinline__ double rsqrt_nr(double s)
+{
+    double r = __builtin_amdgcn_rsq(s);
+    const double hs = 0.5 * s;
+    r = r * fma(-hs * r, r, 1.5);
+    r = r * fma(-hs * r, r, 1.5);
+    return r;
+}
+__device__ __forceinline__ double rcp_nr(double s)
+{
+    double r = __builtin_amdgcn_rcp(s);
+    r = fma(r, fma(-s, r, 1.0), r);
+    r = fma(r, fma(-s, r, 1.0), r);
+    return r;
+}
+
 // ---------------------------------------------------------------- complex (FP64)
 struct cplx { double re, im; };
 __device__ __forceinline__ cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }

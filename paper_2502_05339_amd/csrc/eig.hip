@@ -203,6 +203,7 @@ __host__ __device__ __forceinline__ int hp_col(int j, int n) {
     return n <= 4 ? j * n : (j <= n - 3 ? head : tail);
 }
 constexpr int FR_THREADS = 256;
+constexpr int FR_ZROWS = 4;   // Z-slab rows per wave in the setup (rows per work-group <= 16)
 // row-update roles use threads 1..n, Z-slab roles the last 16, plus one deferred-write thread
 static_assert(EIG_MAX + 1 + 1 + 16 <= FR_THREADS, "francis_kernel thread roles overlap");
 
@@ -230,24 +231,6 @@ __device__ __forceinline__ void house3(double x, double y, double z, double* v1,
     *v1 = y * sc;
     *v2 = z * sc;
     *beta = b;
-}
-
-// 1/sqrt(s) and 1/s for s > 0 (normal range): the hardware estimates (about 23 correct
-// bits) refined by two Newton steps each, which leaves an error of a few ulp.
-__device__ __forceinline__ double rsqrt_nr(double s)
-{
-    double r = __builtin_amdgcn_rsq(s);
-    const double hs = 0.5 * s;
-    r = r * fma(-hs * r, r, 1.5);
-    r = r * fma(-hs * r, r, 1.5);
-    return r;
-}
-__device__ __forceinline__ double rcp_nr(double s)
-{
-    double r = __builtin_amdgcn_rcp(s);
-    r = fma(r, fma(-s, r, 1.0), r);
-    r = fma(r, fma(-s, r, 1.0), r);
-    return r;
 }
 
 // Reflector of the bulge step in unnormalised form: P = I - t u u^T with u = (d, y, z),
@@ -301,16 +284,53 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
     // Z slab = rows r0.. of Q = P_0 P_1 ... P_{n-3}: start from identity rows, apply reflectors on the right
     for (int e = tid; e < nr * n; e += nt) { const int rl = e / n, c = e % n; Zs[e] = (rl < nrows && r0 + rl == c) ? 1.0 : 0.0; }
     __syncthreads();
-    for (int k = 0; k + 2 < n; ++k) {
-        const double tk = taug[k];
-        if (tk == 0.0) continue;
-        const double* v = Vg + (int64_t)k * n;
-        for (int rl = wave; rl < nrows; rl += nw) {
-            double* z = Zs + rl * n;
-            double s = 0.0;
-            for (int j = k + 1 + lane; j < n; j += 64) s += z[j] * v[j];
-            s = wave_sum(s) * tk;
-            for (int j = k + 1 + lane; j < n; j += 64) z[j] -= s * v[j];
+    // Each wave takes rows wave, wave + nw, ... of the slab (at most FR_ZROWS) through all
+    // reflectors together: one load of v_k per reflector (issued one reflector ahead),
+    // interleaved row products, one pass of updates.
+    {
+        static_assert(EIG_MAX <= 3 * 64, "Z slab setup keeps 3 columns per lane");
+        auto load_v = [&](int k, double& a0, double& a1, double& a2) {
+            const double* v = Vg + (int64_t)k * n;
+            const int j0 = k + 1 + lane;
+            a0 = (j0 < n) ? v[j0] : 0.0;
+            a1 = (j0 + 64 < n) ? v[j0 + 64] : 0.0;
+            a2 = (j0 + 128 < n) ? v[j0 + 128] : 0.0;
+        };
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+        if (n > 2) load_v(0, v0, v1, v2);
+        for (int k = 0; k + 2 < n; ++k) {
+            const double tk = taug[k];
+            double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+            if (k + 3 < n) load_v(k + 1, w0, w1, w2);
+            const int j0 = k + 1 + lane;
+            if (tk != 0.0) {
+                doublex4 d = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int a = 0; a < FR_ZROWS; ++a) {
+                    const int rl = wave + a * nw;
+                    if (rl < nrows) {
+                        const double* z = Zs + rl * n;
+                        double t = 0.0;
+                        if (j0 < n) t = fma(z[j0], v0, t);
+                        if (j0 + 64 < n) t = fma(z[j0 + 64], v1, t);
+                        if (j0 + 128 < n) t = fma(z[j0 + 128], v2, t);
+                        d[a] = t;
+                    }
+                }
+#pragma unroll
+                for (int a = 0; a < FR_ZROWS; ++a) d[a] = wave_sum(d[a]) * tk;
+#pragma unroll
+                for (int a = 0; a < FR_ZROWS; ++a) {
+                    const int rl = wave + a * nw;
+                    if (rl < nrows) {
+                        double* z = Zs + rl * n;
+                        if (j0 < n) z[j0] -= d[a] * v0;
+                        if (j0 + 64 < n) z[j0 + 64] -= d[a] * v1;
+                        if (j0 + 128 < n) z[j0 + 128] -= d[a] * v2;
+                    }
+                }
+            }
+            v0 = w0; v1 = w1; v2 = w2;
         }
     }
     __syncthreads();

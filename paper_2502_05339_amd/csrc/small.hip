@@ -242,34 +242,37 @@ __device__ __forceinline__ int up_idx(int i, int j) {   // packed upper, i <= j
     return j * (j + 1) / 2 + i;
 }
 __device__ __forceinline__ int sym_idx(int i, int j) { return i <= j ? up_idx(i, j) : up_idx(j, i); }
-// Round-robin (circle) schedule on n2 (even) players: in round t, pair k.
-__device__ __forceinline__ void rr_pair(int k, int t, int n2, int* p, int* q) {
-    const int m = n2 - 1;
-    int a, b;
-    if (k == 0) { a = 0; b = 1 + (t % m); }
-    else { a = 1 + ((t + k) % m); b = 1 + ((t - k + m) % m); }
-    *p = min(a, b);
-    *q = max(a, b);
+// Round-robin (circle) schedule on n2 (even) players, m = n2 - 1 rounds: in round t
+// (0 <= t < m), pair 0 is (0, 1 + t) and pair k >= 1 is {1 + (t + k) mod m, 1 + (t - k) mod m}
+// (one conditional add or subtract each, no integer division).
+__device__ __forceinline__ void rr_pair(int k, int t, int m, int* p, int* q) {
+    if (k == 0) { *p = 0; *q = 1 + t; return; }
+    int a = t + k;
+    if (a >= m) a -= m;
+    int b = t - k;
+    if (b < 0) b += m;
+    *p = 1 + min(a, b);
+    *q = 1 + max(a, b);
 }
 
 constexpr int JAC_THREADS = 1024;
 constexpr int JAC_BLK = ((SMALL_MAX / 2) * (SMALL_MAX / 2 + 1) / 2 + JAC_THREADS - 1) / JAC_THREADS;
+constexpr int JAC_VT = ((SMALL_MAX / 2) * 32 + JAC_THREADS - 1) / JAC_THREADS;   // V-update tasks per thread
 
 __global__ void __launch_bounds__(JAC_THREADS)
 jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* evals,
               double* Vout, int32_t* info, double rtol)
 {
-    extern __shared__ double sm[];
+    extern __shared__ __align__(16) double sm[];
     const int n2 = n + (n & 1);
     const int np = n2 / 2;
-    double* A = sm;                                   // n(n+1)/2
-    double* Vs = A + n * (n + 1) / 2;                 // nr x n
-    double* cs = Vs + nr * n;                         // np
-    double* sn = cs + np;                             // np
-    double* tn = sn + np;                             // np
-    int* pp = reinterpret_cast<int*>(tn + np);        // np
-    int* qq = pp + np;                                // np
-    int* rank = qq + np;                              // n
+    const int m = n2 - 1;
+    double* A = sm;                                               // n(n+1)/2 (rounded to even)
+    double* Vs = A + round_up(n * (n + 1) / 2, 2);                // nr x n (rounded to even)
+    double2* rcs = reinterpret_cast<double2*>(Vs + round_up(nr * n, 2));   // np: (c, s)
+    double* tn = reinterpret_cast<double*>(rcs + np);             // np
+    int2* rpq = reinterpret_cast<int2*>(tn + round_up(np, 2));    // np: (p, q)
+    int* rank = reinterpret_cast<int*>(rpq + np);                 // n
     __shared__ int rot_count;
     __shared__ double dmax_s;
 
@@ -297,6 +300,14 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
         bk2[t] = b < nblk ? k2 : -1;
         bk1[t] = b - k2 * (k2 + 1) / 2;
     }
+    // this thread's V-update tasks (row of the slab, pair), fixed for every round
+    int vt_rl[JAC_VT], vt_k[JAC_VT];
+#pragma unroll
+    for (int u = 0; u < JAC_VT; ++u) {
+        const int e = tid + u * nt;
+        vt_rl[u] = e / np;
+        vt_k[u] = e % np;
+    }
     __syncthreads();
     if (tid == 0) {
         double d = 0.0;
@@ -311,23 +322,29 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
     for (; sweep < 40; ++sweep) {
         if (tid == 0) rot_count = 0;
         __syncthreads();
-        for (int t = 0; t < n2 - 1; ++t) {
+        for (int t = 0; t < m; ++t) {
             for (int k = tid; k < np; k += nt) {
                 int p, q;
-                rr_pair(k, t, n2, &p, &q);
+                rr_pair(k, t, m, &p, &q);
                 double c = 1.0, s = 0.0, tt = 0.0;
                 if (q < n) {
                     const double apq = A[up_idx(p, q)];
                     const double app = A[up_idx(p, p)], aqq = A[up_idx(q, q)];
                     if (fabs(apq) > floor_abs && fabs(apq) > rtol * sqrt(fabs(app) * fabs(aqq))) {
-                        const double tau = (aqq - app) / (2.0 * apq);
-                        tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + tt * tt);
+                        // tan(theta) of the rotation that zeroes a_pq, the smaller root; |tau| stays
+                        // below about 1e17 because |a_pq| > floor_abs
+                        const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+                        const double u = fma(tau, tau, 1.0);
+                        const double root = u * rsqrt_nr(u);                  // sqrt(1 + tau^2)
+                        tt = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + root);
+                        c = rsqrt_nr(fma(tt, tt, 1.0));
                         s = tt * c;
                         atomicAdd(&rot_count, 1);
                     }
                 }
-                pp[k] = p; qq[k] = q; cs[k] = c; sn[k] = s; tn[k] = tt;
+                rpq[k] = make_int2(p, q);
+                rcs[k] = make_double2(c, s);
+                tn[k] = tt;
             }
             __syncthreads();
             // 2x2 blocks of every pair of pairs: B' = J1^T B J2 (independent, disjoint entries)
@@ -336,7 +353,8 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
                 const int k2 = bk2[u];
                 if (k2 < 0) continue;
                 const int k1 = bk1[u];
-                const int p1 = pp[k1], q1 = qq[k1], p2 = pp[k2], q2 = qq[k2];
+                const int2 pq1 = rpq[k1];
+                const int p1 = pq1.x, q1 = pq1.y;
                 if (k1 == k2) {
                     const double t1 = tn[k1];
                     if (t1 == 0.0 || q1 >= n) continue;
@@ -346,9 +364,12 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
                     A[up_idx(p1, q1)] = 0.0;
                     continue;
                 }
+                const int2 pq2 = rpq[k2];
+                const int p2 = pq2.x, q2 = pq2.y;
                 const bool r1 = q1 < n, r2 = q2 < n;
-                const double c1 = r1 ? cs[k1] : 1.0, s1 = r1 ? sn[k1] : 0.0;
-                const double c2 = r2 ? cs[k2] : 1.0, s2 = r2 ? sn[k2] : 0.0;
+                const double2 cs1 = rcs[k1], cs2 = rcs[k2];
+                const double c1 = r1 ? cs1.x : 1.0, s1 = r1 ? cs1.y : 0.0;
+                const double c2 = r2 ? cs2.x : 1.0, s2 = r2 ? cs2.y : 0.0;
                 if (s1 == 0.0 && s2 == 0.0) continue;
                 const int i00 = sym_idx(p1, p2);
                 const int i10 = sym_idx(q1 < n ? q1 : p1, p2);
@@ -366,14 +387,16 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
                 if (r1 && r2) A[i11] = s1 * x01 + c1 * x11;
             }
             // eigenvector rows owned by this work-group: V <- V J
-            for (int e = tid; e < nrows * np; e += nt) {
-                const int rl = e / np, k = e % np;
-                const int p = pp[k], q = qq[k];
-                if (q >= n || tn[k] == 0.0) continue;
-                const double c = cs[k], s = sn[k];
-                const double vp = Vs[rl * n + p], vq = Vs[rl * n + q];
-                Vs[rl * n + p] = c * vp - s * vq;
-                Vs[rl * n + q] = s * vp + c * vq;
+#pragma unroll
+            for (int u = 0; u < JAC_VT; ++u) {
+                const int rl = vt_rl[u], k = vt_k[u];
+                if (rl >= nrows) continue;
+                const int2 pq = rpq[k];
+                if (pq.y >= n || tn[k] == 0.0) continue;
+                const double2 cs = rcs[k];
+                const double vp = Vs[rl * n + pq.x], vq = Vs[rl * n + pq.y];
+                Vs[rl * n + pq.x] = cs.x * vp - cs.y * vq;
+                Vs[rl * n + pq.y] = cs.y * vp + cs.x * vq;
             }
             __syncthreads();
         }
@@ -412,14 +435,16 @@ hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* e
     if (n <= 0) return hipSuccess;
     if (n > SMALL_MAX) return hipErrorInvalidValue;
     const int n2 = n + (n & 1), np = n2 / 2;
-    const size_t fixed = (size_t)n * (n + 1) / 2 * 8 + (size_t)np * (3 * 8 + 2 * 4) + (size_t)n * 4 + 64;
+    // A (rounded to even), (c, s), t (rounded to even), (p, q), the ranks; V rows rounded to even
+    const size_t fixed = (size_t)round_up((int64_t)n * (n + 1) / 2, 2) * 8 + (size_t)np * 16 +
+                         (size_t)round_up(np, 2) * 8 + (size_t)np * 8 + (size_t)n * 4 + 16;
     const size_t budget = 160 * 1024 - 1024;   // the kernel's LDS attribute (static LDS is 16 bytes)
-    if (fixed + (size_t)n * 8 > budget) return hipErrorInvalidValue;
-    int nr = (int)((budget - fixed) / ((size_t)n * 8));
+    if (fixed + (size_t)n * 8 + 8 > budget) return hipErrorInvalidValue;
+    int nr = (int)((budget - fixed - 8) / ((size_t)n * 8));
     if (nr > 32) nr = 32;
     if (nr > n) nr = n;
     const int grid = (int)ceil_div(n, nr);
-    const size_t lds_bytes = fixed + (size_t)nr * n * 8;
+    const size_t lds_bytes = fixed + (size_t)round_up((int64_t)nr * n, 2) * 8;
     hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(JAC_THREADS), lds_bytes, s, S, lds, n, nr, evals, Vout, info,
                        rtol);
     return hipGetLastError();
