@@ -64,6 +64,14 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// Intra-wave ordering of LDS writes and later reads by other lanes of the same wave.
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // First error wins: record a device-side status code.
 __device__ __forceinline__ void set_status(int32_t* info, int32_t code) {
     if (info) atomicCAS(info, 0, code);

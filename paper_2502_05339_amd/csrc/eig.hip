@@ -213,11 +213,6 @@ struct HP {
     __device__ __forceinline__ double& operator()(int i, int j) const { return a[hp_col(j, n) + i]; }
 };
 
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 __device__ __forceinline__ void house3(double x, double y, double z, double* v1, double* v2, double* tau, double* beta)
 {

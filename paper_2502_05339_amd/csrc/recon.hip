@@ -176,15 +176,6 @@ __device__ __forceinline__ void recon_put(const PrefV<PREF>& hi, const PrefV<PRE
     }
 }
 
-// Intra-wave ordering of the LDS tile used by recon_store (every lane writes, then
-// other lanes of the same wave read).
-__device__ __forceinline__ void wave_sync_lds()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Epilogue of one 16-frame block.  The wave holds RW = 16*RBW consecutive rows of
 // frames fb .. fb+15, in the MFMA layout (lane l: frame fb + l%16, 16-row pieces).
 // Stored as is, one store instruction would write 16 frames x 64 bytes, half of a

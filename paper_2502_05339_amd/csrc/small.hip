@@ -1,10 +1,10 @@
 // Small FP64 dense kernels of the fit (latency-bound, single or few work-groups).
 //
 //  chol_inv   Cholesky factor of a Gram matrix and the inverse of the factor, for
-//             CholeskyQR (Q = Y R^-1).  One work-group; the factor lives packed in
-//             LDS; the inverse is formed by 16x16 blocks (diagonal blocks first,
-//             then one wave per block column).  Breakdown -> one retry with a
-//             diagonal shift (shifted CholeskyQR), then a status code.
+//             CholeskyQR (Q = Y R^-1).  One work-group; 16 x 16 blocks in LDS,
+//             FP64 MFMA block updates, block column by block column.
+//             Breakdown -> one retry with a diagonal shift (shifted CholeskyQR),
+//             then a status code.
 //  sym_eig    cyclic Jacobi eigen-decomposition of a symmetric matrix with a
 //             round-robin parallel ordering.  Every work-group holds the whole
 //             (packed) matrix in LDS and performs the same rotations; each one
@@ -16,155 +16,154 @@
 
 namespace dmd {
 
-// ====================================================================== Cholesky
-// G = L L^T and X = L^-1 in one sweep over the columns j (one barrier per step).
-// Threads [0, nt/2) hold 4x4 tiles of the lower triangle of the trailing matrix (G,
-// updated in place), threads [nt/2, nt) tiles of X (the forward substitution
-// L X = I, started from X = I), CH_TPT tiles each, in registers.  Step j needs
-// column j of the updated G and row j of X; their owners wrote both, not yet scaled,
-// into a double-buffered LDS vector during step j-1, so every thread scales by
-// s_j = 1/sqrt(G'(j,j)) itself:
-//     L(i, j) = G'(i, j) s_j,  X(j, c) = X'(j, c) s_j,
-//     G'(i, c) -= L(i, j) L(c, j)   (c > j),     X'(i, c) -= L(i, j) X(j, c)   (i > j).
-// Entries outside the active ranges take a zero factor, so both triangles stay exact
-// without per-element branches.  Rows of X are kept unscaled (row j is final after
-// step j-1) and scaled by s_j on output, R^-1 = L^-T = X^T.
-constexpr int CH_T = (SMALL_MAX + 3) / 4;
-// (threads, tiles per thread): each half of the threads covers T(T+1)/2 tiles, T = ceil(n/4)
-constexpr int CH_THREADS_A = 1024, CH_TPT_A = 2;     // n <= 176
-constexpr int CH_THREADS_B = 512, CH_TPT_B = (CH_T * (CH_T + 1) / 2 + CH_THREADS_B / 2 - 1) / (CH_THREADS_B / 2);
 
-__device__ __forceinline__ void tri_decode(int u, int* ti, int* tc)
+// ====================================================================== Cholesky
+// G = L L^T and X = L^-1 by 16 x 16 blocks in one work-group of 16 waves, every block in
+// LDS (padded rows): the lower blocks of G, overwritten by L and then by X, and the
+// inverses S_p = L_pp^-1 of the diagonal blocks.  Cholesky, for each block column p:
+//   D  one wave factors block (p, p) in place and forms S_p by the same column sweep on
+//      [G_pp | I] (unscaled entries times 1/d, rows of S scaled by 1/sqrt(d));
+//   P  L_ip = G_ip S_p^T (i > p), one wave per block, FP64 MFMA, in place;
+//   U  G_ij -= L_ip L_jp^T (i >= j > p), FP64 MFMA; wave 0 takes block (p+1, p+1) alone
+//      and runs D for p+1 right after it.
+// Inverse, in place, block column j from the last to the first (the blocks right of j
+// already hold X):  X_jj = S_j,  X_ij = -(sum_{k=j+1..i} X_ik L_kj) S_j  (i > j), computed
+// into registers, written after a barrier.  R^-1 = L^-T = X^T.  Rows and columns past n
+// are padded with the identity.
+constexpr int CM_THREADS = 1024;
+constexpr int CM_NW = CM_THREADS / 64;
+constexpr int CM_T = (SMALL_MAX + 15) / 16;                  // block rows
+constexpr int CM_LD = 17;                                    // padded row stride of LDS blocks
+constexpr int CM_BLK = 16 * CM_LD;
+
+__host__ __device__ __forceinline__ int cm_g(int I, int J) { return I * (I + 1) / 2 + J; }   // I >= J
+
+// dynamic LDS of chol_inv_kernel for n
+static size_t cm_lds_bytes(int n)
 {
-    int t = (int)((sqrtf(8.0f * (float)u + 1.0f) - 1.0f) * 0.5f);
-    while (t * (t + 1) / 2 > u) --t;
-    while ((t + 1) * (t + 2) / 2 <= u) ++t;
-    *ti = t;
-    *tc = u - t * (t + 1) / 2;
+    const int T = (n + 15) / 16;
+    return (size_t)(T * (T + 1) / 2 + T) * CM_BLK * sizeof(double);
 }
+
+// column sweep of one 16 x 16 diagonal block by one wave: Db (G'_pp) is consumed, Sb
+// receives S = L_pp^-1.  Returns false on a non-positive or non-finite pivot.
+__device__ __forceinline__ bool cm_diag(double* Db, double* Sb, int lane)
+{
+    const int i = lane >> 2, c0 = (lane & 3) * 4;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Sb[i * CM_LD + c0 + b] = (i == c0 + b) ? 1.0 : 0.0;
+    wave_sync_lds();
+    for (int j = 0; j < 16; ++j) {
+        const double d = Db[j * CM_LD + j];
+        if (!(d > 0.0) || !isfinite(d)) return false;           // uniform
+        const double sj = rsqrt_nr(d);
+        const double lij = Db[i * CM_LD + j] * (sj * sj);
+        double gc[4], xr[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) { gc[b] = Db[(c0 + b) * CM_LD + j]; xr[b] = Sb[j * CM_LD + c0 + b]; }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int c = c0 + b;
+            if (i > j && c > j && c <= i) Db[i * CM_LD + c] -= lij * gc[b];
+            if (i > j && c <= j) Sb[i * CM_LD + c] -= lij * xr[b];
+            if (i == j && c <= j) Sb[i * CM_LD + c] = xr[b] * sj;
+        }
+        wave_sync_lds();
+    }
+    return true;
+}
+
+// A operand of block M (row-major, padded) for k-group kk: M[l16][4 kk + lg]; its B
+// operand: M[4 kk + lg][l16].  Accumulators hold rows acc_row(lane, v), column l16.
+__device__ __forceinline__ double cm_a(const double* M, int kk, int l16, int lg) { return M[l16 * CM_LD + 4 * kk + lg]; }
+__device__ __forceinline__ double cm_b(const double* M, int kk, int l16, int lg) { return M[(4 * kk + lg) * CM_LD + l16]; }
 
 // attempt 0 factors G as given; when it breaks down and shift_scale > 0 it only sets
 // *shifted, and attempt 1 (launched right after, a no-op unless *shifted is set)
 // factors G + shift_scale * trace(G) * I.  A breakdown without a further attempt
 // reports DMD_ERR_CHOL_BREAKDOWN and leaves the identity.
-template <int CH_THREADS, int CH_TPT>
-__global__ void __launch_bounds__(CH_THREADS)
+__global__ void __launch_bounds__(CM_THREADS)
 chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, int64_t ldr,
                 float* Rinv32, int64_t ldr32, double shift_scale, int attempt, int32_t* shifted,
                 int32_t* info, const int32_t* skip_unless)
 {
     if (skip_unless && *skip_unless == 0) return;
     if (attempt == 1 && (!shifted || *shifted == 0)) return;
-    __shared__ double colbuf[2][4 * CH_T];
-    __shared__ double xrow[2][4 * CH_T];
-    __shared__ double sdiag[4 * CH_T];      // s_j, for scaling the rows of X on output
+    extern __shared__ __align__(16) double cm_sm[];
     __shared__ double shift;
-    constexpr int HALF = CH_THREADS / 2;
-    const int tid = threadIdx.x;
-    const bool xs = tid >= HALF;            // this thread holds tiles of X (else of G)
-    const int ht = xs ? tid - HALF : tid;
-    const int T = (n + 3) / 4, TT = T * (T + 1) / 2;
+    __shared__ int sh_fail;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l16 = lane & 15, lg = lane >> 4;
+    const int T = (n + 15) / 16, NG = T * (T + 1) / 2;
+    double* Gs = cm_sm;                     // NG blocks, block (I, J) at cm_g(I, J)
+    double* Ss = cm_sm + NG * CM_BLK;       // T blocks
+    auto gblk = [&](int I, int J) { return Gs + cm_g(I, J) * CM_BLK; };
 
-    // tiles are numbered column by column (tile column tc outer), so the tiles of one
-    // wave share their columns and retire together: a G tile is final once its last
-    // column is <= j, an X tile does nothing before step c0 and after its last row
-    int rc[CH_TPT];                         // (4 ti) << 16 | 4 tc, or -1
-#pragma unroll
-    for (int q = 0; q < CH_TPT; ++q) {
-        const int u = ht + q * HALF;
-        int ti = 0, tc = 0;
-        if (u < TT) {
-            // upper-triangle decode of u read column-major = lower triangle read row by row of the
-            // transpose: (a, b) with a <= b  ->  tile (ti, tc) = (T-1-a, T-1-b) reversed order
-            int a, b;
-            tri_decode(u, &b, &a);          // b >= a
-            ti = T - 1 - a;
-            tc = T - 1 - b;
-            rc[q] = (4 * ti) << 16 | (4 * tc);
-        } else rc[q] = -1;
+    if (tid == 0) {
+        double tr = 0.0;
+        if (attempt == 1)
+            for (int j = 0; j < n; ++j) tr += fabs(G[(int64_t)j * ldg + j]);
+        shift = shift_scale * tr;
+        sh_fail = 0;
     }
-    double t[CH_TPT][4][4];
+    __syncthreads();
+    const double sh = shift;
+    // lower blocks of G (the lower triangle only, also for both halves of a diagonal block)
+    for (int e = tid; e < NG * 256; e += CM_THREADS) {
+        const int b = e >> 8, r = (e >> 4) & 15, c = e & 15;
+        int I = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
+        if (I * (I + 1) / 2 > b) --I;
+        if ((I + 1) * (I + 2) / 2 <= b) ++I;
+        const int J = b - I * (I + 1) / 2;
+        const int row = I * 16 + c, col = J * 16 + r;         // consecutive threads: consecutive rows
+        const int rlo = max(row, col), clo = min(row, col);
+        const double x = (row < n && col < n) ? G[(int64_t)clo * ldg + rlo] + (row == col ? sh : 0.0)
+                                              : (row == col ? 1.0 : 0.0);
+        Gs[b * CM_BLK + c * CM_LD + r] = x;
+    }
+    __syncthreads();
+    if (wave == 0 && !cm_diag(gblk(0, 0), Ss, lane) && lane == 0) sh_fail = 1;
+    __syncthreads();
 
-    bool fail = false;
-    {
-        if (tid == 0) {
-            double tr = 0.0;
-            if (attempt == 1)
-                for (int j = 0; j < n; ++j) tr += fabs(G[(int64_t)j * ldg + j]);
-            shift = shift_scale * tr;
+    for (int p = 0; p < T && !sh_fail; ++p) {
+        const double* Sp = Ss + p * CM_BLK;
+        // ---- P: L_ip = G_ip S_p^T, one wave per block, in place
+        for (int I = p + 1 + wave; I < T; I += CM_NW) {
+            double* M = gblk(I, p);
+            doublex4 c = zero_acc<doublex4>();
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) c = mfma_f64(cm_a(M, kk, l16, lg), cm_a(Sp, kk, l16, lg), c);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) M[acc_row<doublex4>(lane, v) * CM_LD + l16] = c[v];
         }
         __syncthreads();
-        const double sh = shift;
-        // initial tiles and the step-0 broadcasts (column 0 of G, row 0 of X)
+        // ---- U: G_ij -= L_ip L_jp^T for i >= j > p; block (p+1, p+1) and D(p+1) on wave 0
+        const int h = T - p - 1;                              // block rows below p
+        const int nu = h * (h + 1) / 2;                       // blocks (i, j), i >= j > p
+        for (int e = (wave == 0 ? 0 : wave); e < (wave == 0 ? min(nu, 1) : nu); e += (wave == 0 ? 1 : CM_NW - 1)) {
+            // e -> (J, I): block columns J = p+1.. in turn, rows I = J..T-1 (e = 0 is (p+1, p+1))
+            int J = p + 1, r = e;
+            while (r >= T - J) { r -= T - J; ++J; }
+            const int I = J + r;
+            double* M = gblk(I, J);
+            const double* La = gblk(I, p);
+            const double* Lb = gblk(J, p);
+            doublex4 c;
 #pragma unroll
-        for (int q = 0; q < CH_TPT; ++q) {
-            const int r0 = rc[q] >> 16, c0 = rc[q] & 0xffff;
+            for (int v = 0; v < 4; ++v) c[v] = M[acc_row<doublex4>(lane, v) * CM_LD + l16];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int kk = 0; kk < 4; ++kk) c = mfma_f64(-cm_a(La, kk, l16, lg), cm_a(Lb, kk, l16, lg), c);
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int i = r0 + a, c = c0 + b;
-                    double v = (i == c) ? 1.0 : 0.0;
-                    if (!xs && rc[q] >= 0 && i < n && c < n) v = G[(int64_t)c * ldg + i] + (i == c ? sh : 0.0);
-                    t[q][a][b] = v;
-                }
-            if (rc[q] >= 0 && !xs && c0 == 0) {
-#pragma unroll
-                for (int a = 0; a < 4; ++a) colbuf[0][r0 + a] = t[q][a][0];
-            }
+            for (int v = 0; v < 4; ++v) M[acc_row<doublex4>(lane, v) * CM_LD + l16] = c[v];
         }
-        if (tid == HALF) xrow[0][0] = 1.0;
+        if (wave == 0 && p + 1 < T) {
+            wave_sync_lds();
+            if (!cm_diag(gblk(p + 1, p + 1), Ss + (p + 1) * CM_BLK, lane) && lane == 0) sh_fail = 1;
+        }
         __syncthreads();
-        fail = false;
-        for (int j = 0; j < n; ++j) {
-            const int bsel = j & 1;
-            const double d = colbuf[bsel][j];
-            if (!(d > 0.0) || !isfinite(d)) { fail = true; break; }   // uniform: every thread reads d
-            const double s = 1.0 / sqrt(d);
-            if (tid == 0) sdiag[j] = s;
-            const int jn = j + 1;
-#pragma unroll
-            for (int q = 0; q < CH_TPT; ++q) {
-                if (rc[q] < 0) continue;
-                const int r0 = rc[q] >> 16, c0 = rc[q] & 0xffff;
-                // retired or not yet reached: no update and nothing to broadcast
-                if (xs ? (r0 + 3 < j || c0 > jn) : (c0 + 3 < j)) continue;
-                double lr[4], fc[4];
-#pragma unroll
-                for (int a = 0; a < 4; ++a) lr[a] = r0 + a > j ? colbuf[bsel][r0 + a] * s : 0.0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int c = c0 + b;
-                    fc[b] = xs ? (c <= j ? xrow[bsel][c] * s : 0.0) : (c > j ? colbuf[bsel][c] * s : 0.0);
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a)
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) t[q][a][b] -= lr[a] * fc[b];
-                // broadcasts for step j+1: column j+1 of G (rows >= j+1), row j+1 of X (cols <= j+1)
-                // (constant register indices only: a selected column or row is stored under a
-                // per-column / per-row predicate)
-                if (!xs) {
-#pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        if (c0 + b == jn) {
-#pragma unroll
-                            for (int a = 0; a < 4; ++a)
-                                if (r0 + a >= jn) colbuf[bsel ^ 1][r0 + a] = t[q][a][b];
-                        }
-                } else {
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
-                        if (r0 + a == jn) {
-#pragma unroll
-                            for (int b = 0; b < 4; ++b)
-                                if (c0 + b <= jn) xrow[bsel ^ 1][c0 + b] = t[q][a][b];
-                        }
-                }
-            }
-            __syncthreads();
-        }
     }
+    const bool fail = sh_fail != 0;
     if (fail && attempt == 0 && shift_scale > 0.0 && shifted) {
         if (tid == 0) {
             *shifted = 1;
@@ -175,7 +174,7 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
     if (fail) {
         // breakdown: report, and leave an identity so that later stages stay finite
         if (tid == 0) set_status(info, DMD_ERR_CHOL_BREAKDOWN);
-        for (int e = tid; e < n * n; e += CH_THREADS) {
+        for (int e = tid; e < n * n; e += CM_THREADS) {
             const int i = e % n, j = e / n;
             const double v = i == j ? 1.0 : 0.0;
             Rinv[(int64_t)j * ldr + i] = v;
@@ -183,35 +182,42 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
         }
         return;
     }
-    // R^-1(r, c) = X(c, r) = X'(c, r) s_c: upper triangle from the X tiles, zeros below
-    if (xs) {
+    // ---- X = L^-1 in place, block column j from the last to the first
+    for (int j = T - 2; j >= 0; --j) {
+        const int I = j + 1 + wave;                           // one block row per wave (T - 1 <= 16)
+        doublex4 x = zero_acc<doublex4>();
+        if (I < T) {
+            // W^T = sum_k L_kj^T X_ik^T (X_ii = S_i), then X_ij = -W S_j
+            doublex4 wt = zero_acc<doublex4>();
+            for (int K = j + 1; K <= I; ++K) {
+                const double* Lk = gblk(K, j);
+                const double* Xk = K == I ? Ss + I * CM_BLK : gblk(I, K);
 #pragma unroll
-        for (int q = 0; q < CH_TPT; ++q) {
-            if (rc[q] < 0) continue;
-            const int r0 = rc[q] >> 16, c0 = rc[q] & 0xffff;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int i = r0 + a;
-                if (i >= n) continue;
-                const double si = sdiag[i];
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int c = c0 + b;
-                    if (c <= i) {
-                        const double v = t[q][a][b] * si;
-                        Rinv[(int64_t)i * ldr + c] = v;
-                        if (Rinv32) Rinv32[(int64_t)i * ldr32 + c] = (float)v;
-                    }
-                }
+                for (int kk = 0; kk < 4; ++kk) wt = mfma_f64(cm_b(Lk, kk, l16, lg), cm_a(Xk, kk, l16, lg), wt);
             }
+            const double* Sj = Ss + j * CM_BLK;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) x = mfma_f64(-wt[kk], cm_b(Sj, kk, l16, lg), x);
         }
+        __syncthreads();                                       // every read of column j is done
+        if (I < T) {
+            double* M = gblk(I, j);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) M[acc_row<doublex4>(lane, v) * CM_LD + l16] = x[v];
+        }
+        __syncthreads();
     }
-    for (int e = tid; e < n * n; e += CH_THREADS) {
+    // R^-1(r, c) = X(c, r) for r <= c, zero below
+    for (int e = tid; e < n * n; e += CM_THREADS) {
         const int r = e % n, c = e / n;
-        if (r > c) {
-            Rinv[(int64_t)c * ldr + r] = 0.0;
-            if (Rinv32) Rinv32[(int64_t)c * ldr32 + r] = 0.0f;
+        double v = 0.0;
+        if (r <= c) {
+            const int I = c >> 4, J = r >> 4;
+            const double* M = I == J ? Ss + I * CM_BLK : gblk(I, J);
+            v = M[(c & 15) * CM_LD + (r & 15)];
         }
+        Rinv[(int64_t)c * ldr + r] = v;
+        if (Rinv32) Rinv32[(int64_t)c * ldr32 + r] = (float)v;
     }
 }
 
@@ -221,16 +227,13 @@ hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* 
 {
     if (n <= 0) return hipSuccess;
     if (n > SMALL_MAX) return hipErrorInvalidValue;
-    const int T = (n + 3) / 4;
-    const bool small = T * (T + 1) / 2 <= (CH_THREADS_A / 2) * CH_TPT_A;
+    static_assert(CM_T - 1 <= CM_NW, "chol_inv_kernel: one block row per wave in the inverse");
+    const size_t lds = cm_lds_bytes(n);
+    if (lds > 160 * 1024 - 1024) return hipErrorInvalidValue;
     const int attempts = (shift_scale > 0.0 && shifted) ? 2 : 1;
     for (int at = 0; at < attempts; ++at) {
-        if (small)
-            hipLaunchKernelGGL((chol_inv_kernel<CH_THREADS_A, CH_TPT_A>), dim3(1), dim3(CH_THREADS_A), 0, s, G, ldg,
-                               n, Rinv, ldr, Rinv32, ldr32, shift_scale, at, shifted, info, skip_unless);
-        else
-            hipLaunchKernelGGL((chol_inv_kernel<CH_THREADS_B, CH_TPT_B>), dim3(1), dim3(CH_THREADS_B), 0, s, G, ldg,
-                               n, Rinv, ldr, Rinv32, ldr32, shift_scale, at, shifted, info, skip_unless);
+        hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CM_THREADS), lds, s, G, ldg, n, Rinv, ldr, Rinv32, ldr32,
+                           shift_scale, at, shifted, info, skip_unless);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -667,7 +670,8 @@ hipError_t check_finite(hipStream_t s, int dtype, const void* X, int64_t ld, int
 
 hipError_t small_prepare()
 {
-    hipError_t e = hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)chol_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024 - 1024);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
 }
