@@ -2,7 +2,8 @@
 //
 // Real nonsymmetric n x n matrix (n <= DMD_MAX_RANK), three kernels:
 //  1. hessenberg_kernel (1 work-group): Householder reduction A = Q H Q^T, H in
-//     global scratch, the reflectors (v_k, tau_k) kept for rebuilding Q.
+//     registers across the work-group, the reflectors (v_k, tau_k) kept for
+//     rebuilding Q.
 //  2. francis_kernel (ceil(n / nr) work-groups): every work-group holds H packed
 //     in LDS (upper Hessenberg plus the two extra sub-diagonals a double-shift
 //     bulge needs) and runs the same implicit double-shift QR iteration with
@@ -70,128 +71,147 @@ static EigWs eig_carve(void* ws, int n)
 }
 
 // ====================================================================== 1. Hessenberg
-// One Householder step k on H (accessor `h(i, j)` over column-major storage):
-//   v: reflector of H[k+1.., k];  H <- P H P with P = I - tau v v^T.
-// Left update (rows k+1.., columns k+1..): one wave per column.  Right update (all
-// rows, columns k+1..): the row products are split over 4 thread quarters, each
-// taking every fourth column (coalesced column-major reads), partial sums via LDS.
-template <typename Acc>
-__device__ void hess_step(Acc h, int k, int n, double* vs, double* part, double* red, double* sh,
-                          double* V, double* tau)
-{
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-    double p2 = 0.0;
-    for (int i = k + 2 + tid; i < n; i += nt) { const double x = h(i, k); p2 += x * x; }
-    p2 = wave_sum(p2);
-    if (lane == 0) red[wave] = p2;
-    __syncthreads();
-    if (tid == 0) {
-        double xn2 = 0.0;
-        for (int w = 0; w < nw; ++w) xn2 += red[w];
-        const double alpha = h(k + 1, k);
-        if (xn2 == 0.0) { sh[0] = 0.0; sh[1] = alpha; sh[2] = 0.0; }
-        else {
-            const double nrm = sqrt(alpha * alpha + xn2);
-            const double beta = alpha >= 0.0 ? -nrm : nrm;
-            sh[0] = (beta - alpha) / beta;
-            sh[1] = beta;
-            sh[2] = 1.0 / (alpha - beta);
-        }
-    }
-    __syncthreads();
-    const double tk = sh[0], sc = sh[2];
-    for (int i = k + 1 + tid; i < n; i += nt) {
-        const double v = (i == k + 1) ? 1.0 : h(i, k) * sc;
-        vs[i] = v;
-        V[(int64_t)k * n + i] = v;
-    }
-    __syncthreads();
-    if (tk != 0.0) {
-        // left: H[k+1.., j] -= tau v (v^T H[k+1.., j])
-        for (int j = k + 1 + wave; j < n; j += nw) {
-            double d = 0.0;
-            for (int i = k + 1 + lane; i < n; i += 64) d += vs[i] * h(i, j);
-            d = wave_sum(d) * tk;
-            for (int i = k + 1 + lane; i < n; i += 64) h(i, j) -= d * vs[i];
-        }
-        __syncthreads();
-        // right: H[i, k+1..] -= tau (H[i, k+1..] v) v^T for all rows i
-        const int q4 = tid >> 8, i0 = tid & 255;          // 4 quarters x 256 rows
-        for (int i = i0; i < n; i += 256) {
-            double d = 0.0;
-            for (int j = k + 1 + q4; j < n; j += 4) d += h(i, j) * vs[j];
-            part[q4 * n + i] = d;
-        }
-        __syncthreads();
-        for (int i = i0; i < n; i += 256) {
-            const double d = (part[i] + part[n + i] + part[2 * n + i] + part[3 * n + i]) * tk;
-            for (int j = k + 1 + q4; j < n; j += 4) h(i, j) -= d * vs[j];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        tau[k] = tk;
-        if (tk != 0.0) h(k + 1, k) = sh[1];
-    }
-    for (int i = k + 2 + tid; i < n; i += nt) h(i, k) = 0.0;
-    __syncthreads();
-}
-
-struct GAcc {
-    double* p; int n;
-    __device__ __forceinline__ double& operator()(int i, int j) const { return p[(int64_t)j * n + i]; }
-};
-struct LAcc {   // columns jbase..n-1 in LDS
-    double* p; int n; int jbase;
-    __device__ __forceinline__ double& operator()(int i, int j) const { return p[(j - jbase) * n + i]; }
-};
+// Householder reduction A = Q H Q^T, H held in registers: thread (ib, jb) of a 32 x 32
+// grid keeps H(ib + 32 a, jb + 32 c), a, c < HS_N.  Step k, reflector P = I - tau v v^T of
+// column k (rows k+1..):  with u = H v, w = H^T v and gamma = v^T H v taken from H before
+// the step, P H P = H - tau (v w^T + u v^T) + tau^2 gamma v v^T on columns > k, and column
+// k becomes (.., beta, 0, ..).  u, w and gamma are summed from per-thread partials in LDS
+// (fixed order).  While the others update their entries, wave 0 forms the next column and
+// the next reflector.  Three barriers per step.
+constexpr int HS_N = (EIG_MAX + 31) / 32;
 
 __global__ void __launch_bounds__(1024)
-hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, double* V, double* tau, int jbase)
+hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, double* V, double* tau)
 {
-    extern __shared__ double hsm[];
-    double* vs = hsm;                 // n
-    double* part = vs + n;            // 4n
-    double* red = part + 4 * n;       // 16
-    double* sh = red + 16;            // 4
-    double* Hl = sh + 4;              // n x (n - jbase)
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int e = tid; e < n * n; e += nt) {
-        const int i = e % n, j = e / n;
-        const double a = A[(int64_t)j * lda + i];
-        if (jbase == 0) Hl[j * n + i] = a;   // everything fits in LDS
-        else H[e] = a;                       // global first; columns >= jbase move to LDS later
-        V[e] = 0.0;
-    }
-    for (int i = tid; i < n; i += nt) tau[i] = 0.0;
+    __shared__ double col[EIG_MAX];           // column k of H (rows > k), for v
+    __shared__ double colpre[EIG_MAX];        // column k + 1 before step k
+    __shared__ double us[EIG_MAX], ws[EIG_MAX];
+    __shared__ double upart[32 * EIG_MAX];    // partial u per column group jb
+    __shared__ double wpart[32 * EIG_MAX];    // partial w per row group ib
+    __shared__ double gpart[1024];
+    __shared__ double refl[4];                // tau, beta, 1 / (alpha - beta), gamma
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ib = 2 * wave + (lane >> 5), jb = lane & 31;
+
+    double h[HS_N][HS_N];
+#pragma unroll
+    for (int a = 0; a < HS_N; ++a)
+#pragma unroll
+        for (int c = 0; c < HS_N; ++c) {
+            const int i = ib + 32 * a, j = jb + 32 * c;
+            h[a][c] = (i < n && j < n) ? A[(int64_t)j * lda + i] : 0.0;
+        }
+    for (int e = tid; e < n * n; e += 1024) V[e] = 0.0;
+    for (int i = tid; i < n; i += 1024) tau[i] = 0.0;
+    // reflector data of column k from the column in col[]: (tau, beta, scale); wave-wide
+    auto reflector = [&](int k) {
+        double x2 = 0.0;
+        for (int i = k + 2 + lane; i < n; i += 64) { const double x = col[i]; x2 = fma(x, x, x2); }
+        x2 = wave_sum(x2);
+        const double alpha = col[k + 1];
+        double tk = 0.0, beta = alpha, sc = 0.0;
+        if (x2 != 0.0) {
+            const double nrm = sqrt(alpha * alpha + x2);
+            beta = alpha >= 0.0 ? -nrm : nrm;
+            tk = (beta - alpha) / beta;
+            sc = 1.0 / (alpha - beta);
+        }
+        if (lane == 0) { refl[0] = tk; refl[1] = beta; refl[2] = sc; }
+    };
+    if (n > 2 && jb == 0)
+#pragma unroll
+        for (int a = 0; a < HS_N; ++a)
+            if (ib + 32 * a < n) col[ib + 32 * a] = h[a][0];
     __syncthreads();
-    GAcc g{H, n};
-    LAcc l{Hl, n, jbase};
-    // steps whose trailing columns do not fit in LDS run on global memory
-    for (int k = 0; k + 2 < n && k < jbase; ++k) hess_step(g, k, n, vs, part, red, sh, V, tau);
+    if (n > 2 && wave == 0) reflector(0);
     __syncthreads();
-    if (jbase > 0) {
-        // columns jbase.. were only touched by the global-memory steps in global memory
-        for (int e = tid; e < n * (n - jbase); e += nt) {
-            const int i = e % n, j = jbase + e / n;
-            Hl[(j - jbase) * n + i] = H[(int64_t)j * n + i];
+
+    for (int k = 0; k + 2 < n; ++k) {
+        const double tk = refl[0], beta = refl[1], sc = refl[2];
+        auto vof = [&](int i) { return i == k + 1 ? 1.0 : (i > k + 1 && i < n ? col[i] * sc : 0.0); };
+        double vr[HS_N], vc[HS_N];
+#pragma unroll
+        for (int a = 0; a < HS_N; ++a) { vr[a] = vof(ib + 32 * a); vc[a] = vof(jb + 32 * a); }
+        if (wave == 1) {
+            for (int i = k + 1 + lane; i < n; i += 64) V[(int64_t)k * n + i] = vof(i);
+            if (lane == 0) tau[k] = tk;
+        }
+        // ---- partials of u = H v, w = H^T v, gamma = v^T H v; column k + 1 before the step
+        double g = 0.0;
+#pragma unroll
+        for (int a = 0; a < HS_N; ++a) {
+            double t = 0.0;
+#pragma unroll
+            for (int c = 0; c < HS_N; ++c) t = fma(h[a][c], vc[c], t);
+            const int i = ib + 32 * a;
+            if (i < n) upart[jb * EIG_MAX + i] = t;
+        }
+#pragma unroll
+        for (int c = 0; c < HS_N; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int a = 0; a < HS_N; ++a) t = fma(vr[a], h[a][c], t);
+            g = fma(t, vc[c], g);
+            const int j = jb + 32 * c;
+            if (j < n) wpart[ib * EIG_MAX + j] = t;
+            if (j == k + 1)
+#pragma unroll
+                for (int a = 0; a < HS_N; ++a)
+                    if (ib + 32 * a < n) colpre[ib + 32 * a] = h[a][c];
+        }
+        gpart[tid] = g;
+        __syncthreads();
+        // ---- sums in a fixed order
+        if (tid < n) {
+            double t = 0.0;
+            for (int q = 0; q < 32; ++q) t += upart[q * EIG_MAX + tid];
+            us[tid] = t;
+        } else if (tid >= 256 && tid - 256 < n) {
+            const int j = tid - 256;
+            double t = 0.0;
+            for (int q = 0; q < 32; ++q) t += wpart[q * EIG_MAX + j];
+            ws[j] = t;
+        } else if (wave == 15) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) t += gpart[q * 64 + lane];
+            t = wave_sum(t);
+            if (lane == 0) refl[3] = t;
+        }
+        __syncthreads();
+        // ---- H <- P H P on columns > k; column k -> (.., beta, 0, ..)
+        const double tg = tk * tk * refl[3];
+#pragma unroll
+        for (int a = 0; a < HS_N; ++a) {
+            const int i = ib + 32 * a;
+            const double ui = us[i < n ? i : 0];
+#pragma unroll
+            for (int c = 0; c < HS_N; ++c) {
+                const int j = jb + 32 * c;
+                if (j > k && j < n) h[a][c] -= tk * fma(vr[a], ws[j], ui * vc[c]) - tg * vr[a] * vc[c];
+                if (j == k && tk != 0.0 && i == k + 1) h[a][c] = beta;
+                if (j == k && i > k + 1) h[a][c] = 0.0;
+            }
+        }
+        // ---- wave 0: column k + 1 after the step, and the reflector of step k + 1
+        if (wave == 0 && k + 3 < n) {
+            const double wk = ws[k + 1], vk = k + 1 < n ? 1.0 : 0.0;    // v_{k+1} = 1
+            for (int i = k + 2 + lane; i < n; i += 64) {
+                const double vi = vof(i);
+                col[i] = colpre[i] - (tk * fma(vi, wk, us[i] * vk) - tg * vi * vk);
+            }
+            wave_sync_lds();
+            reflector(k + 1);
         }
         __syncthreads();
     }
-    for (int k = jbase; k + 2 < n; ++k) hess_step(l, k, n, vs, part, red, sh, V, tau);
-    __syncthreads();
-    for (int e = tid; e < n * (n - jbase); e += nt) {
-        const int i = e % n, j = jbase + e / n;
-        H[(int64_t)j * n + i] = Hl[(j - jbase) * n + i];
-    }
-}
-
-static int hess_jbase(int n)
-{
-    const int budget = (160 * 1024 - 512) / 8 - (5 * n + 20);   // doubles left for columns
-    int cols = budget / n;
-    if (cols >= n) return 0;
-    return n - cols;
+#pragma unroll
+    for (int a = 0; a < HS_N; ++a)
+#pragma unroll
+        for (int c = 0; c < HS_N; ++c) {
+            const int i = ib + 32 * a, j = jb + 32 * c;
+            if (i < n && j < n) H[(int64_t)j * n + i] = h[a][c];
+        }
 }
 
 // ====================================================================== 2. Francis QR
@@ -761,9 +781,7 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
     if (n <= 0) return hipSuccess;
     if (n > EIG_MAX) return hipErrorInvalidValue;
     EigWs w = eig_carve(ws, n);
-    const int jb = hess_jbase(n);
-    const size_t hlds = ((size_t)5 * n + 20 + (size_t)n * (n - jb)) * 8;
-    hipLaunchKernelGGL(hessenberg_kernel, dim3(1), dim3(1024), hlds, s, A, lda, n, w.H, w.V, w.tau, jb);
+    hipLaunchKernelGGL(hessenberg_kernel, dim3(1), dim3(1024), 0, s, A, lda, n, w.H, w.V, w.tau);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int nr = eig_rows_per_wg(n);
@@ -787,7 +805,7 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
 
 hipError_t eig_prepare()
 {
-    hipError_t e = hipFuncSetAttribute((const void*)hessenberg_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)eigvec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024 - 256);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)francis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
