@@ -31,18 +31,22 @@ hipError_t fill_i32(hipStream_t s, int32_t* p, int64_t n, int32_t v) {
 }
 
 // ------------------------------------------------------------------------ NN
-// Work-group: 256 threads = 4 waves; each wave owns WR = 16*VW consecutive rows
-// (VW = 16 / sizeof(T): 4 FP32 or 2 FP64 rows per 16-byte load) and all n
-// (<= 16*NB) columns.  The A operand comes straight from memory: in k-step s, lane
-// l loads the VW consecutive rows r0 + VW*(l%16) .. of column k0 + 4s + l/16 with
-// one vector load, and element e of that vector is lane l's A operand of MFMA
-// row-block e.  Row-block e of a wave therefore holds the rows {r0 + VW*i + e},
-// i = 0..15: a permutation of the wave's rows that the epilogue undoes, since it
-// puts VW consecutive rows of one column in one lane again (vector stores of C).
-// B is staged through LDS in chunks of KB rows as [k][col].  C may alias A (each
-// wave reads all of its rows of A before it writes them), which the in-place
-// CholeskyQR apply Q = Y R^-1 relies on.
-template <typename T, int NB, bool VEC>
+// Work-group: 256 threads = 4 waves; the waves form (4 / CS) row groups x CS column
+// groups.  Each wave owns WR = 16*VW consecutive rows (VW = 16 / sizeof(T): 4 FP32 or
+// 2 FP64 rows per 16-byte load) and NB / CS of the 16-column blocks, so that its
+// accumulators leave room for several waves per SIMD (the A operand streams from
+// memory; other waves cover its latency).  The A operand comes straight from memory: in
+// k-step s, lane l loads the VW consecutive rows r0 + VW*(l%16) .. of column
+// k0 + 4s + l/16 with one vector load, and element e of that vector is lane l's A
+// operand of MFMA row-block e.  Row-block e of a wave therefore holds the rows
+// {r0 + VW*i + e}, i = 0..15: a permutation of the wave's rows that the epilogue undoes,
+// since it puts VW consecutive rows of one column in one lane again (vector stores of
+// C).  B is staged through LDS in chunks of KB rows as [k][col], two buffers: chunk c+1
+// (B and the A operands) is fetched into registers while chunk c feeds the MFMAs, one
+// barrier per chunk.  C may alias A (every wave reads all of its rows of A before any
+// wave writes them: the last chunk's reads precede the final barrier), which the
+// in-place CholeskyQR apply Q = Y R^-1 relies on.
+template <typename T, int NB, int CS, bool VEC>
 __global__ void __launch_bounds__(256)
 gemm_nn_kernel(const T* A, int64_t lda, const T* __restrict__ B, int64_t ldb,
                T* C, int64_t ldc, int c_rowmajor, int64_t N, int K, int n,
@@ -51,10 +55,15 @@ gemm_nn_kernel(const T* A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     if (skip_unless && *skip_unless == 0) return;
     constexpr int VW = 16 / sizeof(T);
     constexpr int WR = 16 * VW;
-    constexpr int KB = 32;
+    constexpr int KB = 16;
     constexpr int NP = 16 * NB;
+    constexpr int NBW = NB / CS;                 // column blocks per wave
+    constexpr int RG = 4 / CS;                   // row groups per work-group
+    static_assert(NB % CS == 0 && 4 % CS == 0, "column split must divide the blocks and the waves");
     constexpr int PADB = (sizeof(T) == 4) ? 4 : 2;
-    __shared__ T Bs[KB][NP + PADB];
+    constexpr int BPT = (KB * NP + 255) / 256;   // staged B elements per thread and chunk
+    constexpr int NKS = KB / 4;                  // k-steps per chunk
+    __shared__ T Bs[2][KB][NP + PADB];
     typedef typename Acc<T>::type V;
     typedef typename std::conditional<sizeof(T) == 4, float4, double2>::type VT;
 
@@ -62,50 +71,82 @@ gemm_nn_kernel(const T* A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int kq = lane >> 4;
-    const int64_t r0 = ((int64_t)blockIdx.x * 4 + wave) * WR;
+    const int cg = wave % CS;                    // column group
+    const int64_t r0 = ((int64_t)blockIdx.x * RG + wave / CS) * WR;
     const int64_t rl = r0 + VW * (lane & 15);
 
-    V acc[VW][NB];
+    V acc[VW][NBW];
 #pragma unroll
     for (int e = 0; e < VW; ++e)
 #pragma unroll
-        for (int cb = 0; cb < NB; ++cb) acc[e][cb] = zero_acc<V>();
+        for (int cb = 0; cb < NBW; ++cb) acc[e][cb] = zero_acc<V>();
 
-    for (int k0 = 0; k0 < K; k0 += KB) {
-        for (int idx = tid; idx < KB * NP; idx += 256) {
+    // Software pipeline: while chunk c feeds the MFMAs, chunk c+1's B (to the other LDS
+    // buffer after the MFMAs) and its A operands (registers) are in flight.
+    T bpre[BPT];
+    VT apre[NKS], acur[NKS];
+    auto fetch_b = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < BPT; ++q) {
+            const int idx = tid + q * 256;
             const int kk = idx % KB, j = idx / KB;
             const int kr = k0 + kk;
-            Bs[kk][j] = (kr < K && j < n) ? B[(int64_t)j * ldb + kr] : T(0);
+            bpre[q] = (idx < KB * NP && kr < K && j < n) ? B[(int64_t)j * ldb + kr] : T(0);
         }
-        __syncthreads();
+    };
+    auto put_b = [&](int buf) {
 #pragma unroll
-        for (int ks = 0; ks < KB; ks += 4) {
-            const int k = k0 + ks + kq;
-            T a[VW];
+        for (int q = 0; q < BPT; ++q) {
+            const int idx = tid + q * 256;
+            if (idx < KB * NP) Bs[buf][idx % KB][idx / KB] = bpre[q];
+        }
+    };
+    auto fetch_a = [&](int k0) {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            const int k = k0 + 4 * ks + kq;
             const T* src = A + (int64_t)k * lda + rl;
-            if (VEC && k < K && rl + VW <= N) {
-                const VT v = *reinterpret_cast<const VT*>(src);
-                if constexpr (VW == 4) { a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w; }
-                else { a[0] = v.x; a[1] = v.y; }
-            } else {
+            VT v;
+            if (VEC && k < K && rl + VW <= N) v = *reinterpret_cast<const VT*>(src);
+            else {
+                T* pv = reinterpret_cast<T*>(&v);
 #pragma unroll
-                for (int e = 0; e < VW; ++e) a[e] = (k < K && rl + e < N) ? src[e] : T(0);
+                for (int e = 0; e < VW; ++e) pv[e] = (k < K && rl + e < N) ? src[e] : T(0);
             }
-            T bv[NB];
+            apre[ks] = v;
+        }
+    };
+
+    const int nchunk = (K + KB - 1) / KB;
+    fetch_b(0);
+    fetch_a(0);
+    put_b(0);
+    __syncthreads();
+    for (int c = 0; c < nchunk; ++c) {
+        const int buf = c & 1;
+        const bool more = c + 1 < nchunk;
 #pragma unroll
-            for (int cb = 0; cb < NB; ++cb) bv[cb] = Bs[ks + kq][cb * 16 + (lane & 15)];
+        for (int ks = 0; ks < NKS; ++ks) acur[ks] = apre[ks];
+        if (more) { fetch_b((c + 1) * KB); fetch_a((c + 1) * KB); }
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            const T* av = reinterpret_cast<const T*>(&acur[ks]);
+            T bv[NBW];
+#pragma unroll
+            for (int cb = 0; cb < NBW; ++cb) bv[cb] = Bs[buf][4 * ks + kq][(cg * NBW + cb) * 16 + (lane & 15)];
 #pragma unroll
             for (int e = 0; e < VW; ++e)
 #pragma unroll
-                for (int cb = 0; cb < NB; ++cb) acc[e][cb] = mfma(a[e], bv[cb], acc[e][cb]);
+                for (int cb = 0; cb < NBW; ++cb) acc[e][cb] = mfma(av[e], bv[cb], acc[e][cb]);
         }
+        if (more) put_b(buf ^ 1);
         __syncthreads();
     }
 
     // ---- epilogue: row-block e, tile row i  ->  row r0 + VW*i + e
 #pragma unroll
-    for (int cb = 0; cb < NB; ++cb) {
-        const int col = cb * 16 + (lane & 15);
+    for (int cb = 0; cb < NBW; ++cb) {
+        const int col = (cg * NBW + cb) * 16 + (lane & 15);
         if (col >= n) continue;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -128,33 +169,34 @@ gemm_nn_kernel(const T* A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     }
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int CS>
 static hipError_t launch_nn_t(hipStream_t s, const T* A, int64_t lda, const T* B, int64_t ldb,
                               T* C, int64_t ldc, int c_rowmajor, int64_t N, int K, int n,
                               const int32_t* skip_unless)
 {
-    constexpr int BM = 4 * 16 * (16 / sizeof(T));
+    constexpr int BM = (4 / CS) * 16 * (16 / sizeof(T));
     dim3 grid((unsigned)ceil_div(N, BM));
     const int vw = 16 / sizeof(T);
     bool vec = (lda % vw == 0) && ((uintptr_t)A % 16 == 0) && (c_rowmajor || ((ldc % vw == 0) && ((uintptr_t)C % 16 == 0)));
     if (vec)
-        hipLaunchKernelGGL((gemm_nn_kernel<T, NB, true>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless);
+        hipLaunchKernelGGL((gemm_nn_kernel<T, NB, CS, true>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless);
     else
-        hipLaunchKernelGGL((gemm_nn_kernel<T, NB, false>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless);
+        hipLaunchKernelGGL((gemm_nn_kernel<T, NB, CS, false>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless);
     return hipGetLastError();
 }
 
+// Column blocks NB >= 4 are split over two waves (CS = 2).
 template <typename T>
 static hipError_t launch_nn_any(hipStream_t s, const T* a, int64_t lda, const T* b, int64_t ldb, T* c, int64_t ldc,
                                 int c_rowmajor, int64_t N, int K, int n, const int32_t* skip_unless)
 {
     const int ncb = (n + 15) / 16;
-    if (ncb <= 2)  return launch_nn_t<T, 2>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-    if (ncb <= 4)  return launch_nn_t<T, 4>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-    if (ncb <= 6)  return launch_nn_t<T, 6>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-    if (ncb <= 8)  return launch_nn_t<T, 8>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-    if (ncb <= 10) return launch_nn_t<T, 10>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
-    return launch_nn_t<T, NN_MAX_CB>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 2)  return launch_nn_t<T, 2, 1>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 4)  return launch_nn_t<T, 4, 2>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 6)  return launch_nn_t<T, 6, 2>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 8)  return launch_nn_t<T, 8, 2>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    if (ncb <= 10) return launch_nn_t<T, 10, 2>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
+    return launch_nn_t<T, NN_MAX_CB, 2>(s, a, lda, b, ldb, c, ldc, c_rowmajor, N, K, n, skip_unless);
 }
 
 hipError_t gemm_nn(hipStream_t s, int dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
