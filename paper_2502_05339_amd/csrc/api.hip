@@ -132,7 +132,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
     const int wide = shifted ? mm + 1 : mm;
     int64_t maxprod = (int64_t)std::max({(int64_t)l * wide, (int64_t)mm * l, (int64_t)l * l,
                                          (int64_t)r * r, (int64_t)r, (int64_t)wide * wide});
-    double* P = cv.take<double>((size_t)TN_MAX_SPLITS * maxprod);
+    double* P = cv.take<double>((size_t)tn_max_splits(n) * maxprod);
     double* G = cv.take<double>((size_t)std::max(l, wide) * std::max(l, wide));
     double* Rinv = cv.take<double>((size_t)l * l);
     float* Rinv32 = cv.take<float>((size_t)l * l);
@@ -538,7 +538,7 @@ int32_t dmd_project_workspace_size(int64_t n, int32_t r, size_t* bytes)
     if (!bytes) return DMD_ERR_ARG;
     if (n < 1 || r < 1) return DMD_ERR_SHAPE;
     Carver c(nullptr);
-    c.take<double>((size_t)TN_MAX_SPLITS * r * r);
+    c.take<double>((size_t)tn_max_splits(n) * r * r);
     c.take<double>((size_t)r * r);
     c.take<double>((size_t)r);
     c.take<double>((size_t)r * r);
@@ -562,7 +562,7 @@ int32_t dmd_project(void* stream, const dmd_model* model, const void* u, double*
     const int r = model->r;
     const int64_t n = model->n;
     Carver cv(ws);
-    double* P = cv.take<double>((size_t)TN_MAX_SPLITS * r * r);
+    double* P = cv.take<double>((size_t)tn_max_splits(n) * r * r);
     double* PhiG = cv.take<double>((size_t)r * r);
     double* rhs = cv.take<double>((size_t)r);
     double* Rinv = cv.take<double>((size_t)r * r);
@@ -597,7 +597,7 @@ int32_t dmd_loss_grad_workspace_size(int64_t n, int32_t r, int32_t ncols, int32_
     recon_carve(c, r, ncols, mode);
     c.take<char>((size_t)round_up(n, 4) * ncols * esize(dtype));
     c.take<double>(4096);
-    c.take<double>((size_t)TN_MAX_SPLITS * r * ncols);
+    c.take<double>((size_t)tn_max_splits(n) * r * ncols);
     c.take<double>((size_t)r * ncols);
     *bytes = c.bytes();
     return DMD_OK;
@@ -623,7 +623,7 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam, c
     ReconPlan p = recon_carve(cv, r, ncols, mode);
     void* R = cv.take<char>((size_t)ldr * ncols * esize(model->dtype));
     double* ss = cv.take<double>(4096);
-    double* P = cv.take<double>((size_t)TN_MAX_SPLITS * r * ncols);
+    double* P = cv.take<double>((size_t)tn_max_splits(n) * r * ncols);
     double* G = cv.take<double>((size_t)r * ncols);
     HIPCHK(hipMemcpyAsync(p.kdev, k_host, (size_t)ncols * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIPCHK(exponents(st, p.kdev, nullptr, 1.0, ncols, p.expo));

@@ -8,6 +8,7 @@
 //            Used for the Gram products of CholeskyQR (FP64 MFMA), X^T Q, the
 //            projection Q^T Z (one pass over both X and X'), Phi^T Phi, Phi^T x0 and
 //            the adjoint's Phi^T R.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -419,6 +420,130 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
     }
 }
 
+// Symmetric product P_s = A[rows_s]^T A[rows_s] (the Gram matrices), nbi <= 2*SB_MAXW*8
+// block rows: only the upper block triangle is formed (the reduction mirrors it).  The
+// 16x16 blocks are grouped in 2x2 super-blocks; the upper super-blocks (si <= sj) are
+// dealt to the 8 waves, at most SB_MAXW each, so no wave forms more than 4*SB_MAXW
+// blocks.  Staging as in gemm_tn_kernel (two LDS buffers, one barrier per chunk).
+constexpr int SB_MAXW = 2;
+template <typename Tin, typename Tc, int RC>
+__global__ void __launch_bounds__(TN_THREADS)
+gemm_sym_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
+                int64_t N, int64_t rows_per_split, int vec, double* __restrict__ P,
+                const int32_t* skip_unless)
+{
+    if (skip_unless && *skip_unless == 0) return;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    typedef TnStage<Tin, Tc> St;
+    typedef typename St::VT VT;
+    typedef typename Acc<Tc>::type V;
+    const int ka_p = (int)round_up(ka, 16);
+    const int lda_s = tn_ld(ka_p, sizeof(Tc));
+    const int bufsz = RC * lda_s;
+    Tc* buf0 = reinterpret_cast<Tc*>(smem_raw);
+
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nbi = ka_p / 16, sbn = (nbi + 1) / 2, nsb = sbn * (sbn + 1) / 2;
+    const int64_t split = blockIdx.x;
+    const int64_t r_begin = split * rows_per_split;
+    const int64_t r_end = min(N, r_begin + rows_per_split);
+
+    // this wave's super-blocks (column-major over the upper triangle): block rows 2si, 2si+1
+    // and block columns 2sj, 2sj+1, clamped to the last block (recomputed, not stored)
+    int sr[SB_MAXW], sc[SB_MAXW];
+    bool sv[SB_MAXW];
+#pragma unroll
+    for (int q = 0; q < SB_MAXW; ++q) {
+        const int sb = wave + q * (TN_THREADS / 64);
+        sv[q] = sb < nsb;
+        int si = 0, sj = 0;
+        if (sv[q]) block_decode(sb, 1, sbn, &si, &sj);
+        sr[q] = si; sc[q] = sj;
+    }
+    V acc[SB_MAXW][2][2];
+#pragma unroll
+    for (int q = 0; q < SB_MAXW; ++q)
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) acc[q][a][b] = zero_acc<V>();
+
+    const int ntask = St::ntasks(a_rowmajor, ka, ka_p, RC);
+    St task[TN_MAXT];
+    bool has[TN_MAXT];
+#pragma unroll
+    for (int q = 0; q < TN_MAXT; ++q) {
+        const int t = tid + q * TN_THREADS;
+        has[q] = t < ntask;
+        task[q].init(A + r_begin * (a_rowmajor ? lda : 1), lda, a_rowmajor, ka, ka_p, RC, has[q] ? t : 0, lda_s, 0);
+    }
+    VT pre[TN_MAXT];
+    auto fetch = [&](int64_t c0) {
+#pragma unroll
+        for (int q = 0; q < TN_MAXT; ++q)
+            if (has[q]) pre[q] = task[q].load(c0, r_end - r_begin, vec);
+    };
+    auto put = [&](Tc* buf) {
+#pragma unroll
+        for (int q = 0; q < TN_MAXT; ++q)
+            if (has[q]) task[q].store(buf, pre[q]);
+    };
+
+    const int64_t nchunk = ceil_div(r_end - r_begin, (int64_t)RC);
+    if (nchunk > 0) {
+        fetch(0);
+        put(buf0);
+    }
+    __syncthreads();
+    const int amax = (nbi - 1) * 16;
+    for (int64_t ci = 0; ci < nchunk; ++ci) {
+        Tc* cur = buf0 + (ci & 1) * bufsz;
+        Tc* nxt = buf0 + ((ci + 1) & 1) * bufsz;
+        const bool more = ci + 1 < nchunk;
+        if (more) fetch((ci + 1) * RC);
+#pragma unroll
+        for (int ks = 0; ks < RC / 4; ++ks) {
+            const int kk = ks * 4 + (lane >> 4);
+            const Tc* row = cur + kk * lda_s + (lane & 15);
+#pragma unroll
+            for (int q = 0; q < SB_MAXW; ++q) {
+                if (!sv[q]) continue;                                 // wave-uniform
+                Tc av[2], bv[2];
+#pragma unroll
+                for (int a = 0; a < 2; ++a) av[a] = row[min((2 * sr[q] + a) * 16, amax)];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) bv[b] = row[min((2 * sc[q] + b) * 16, amax)];
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[q][a][b] = mfma(av[a], bv[b], acc[q][a][b]);
+            }
+        }
+        if (more) put(nxt);
+        __syncthreads();
+    }
+
+    double* out = P + split * (int64_t)ka * ka;
+#pragma unroll
+    for (int q = 0; q < SB_MAXW; ++q) {
+        if (!sv[q]) continue;
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+                const int bi = 2 * sr[q] + a, bj = 2 * sc[q] + b;
+                if (bi >= nbi || bj >= nbi || bi > bj) continue;
+                const int jj = bj * 16 + (lane & 15);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int ii = bi * 16 + acc_row<V>(lane, v);
+                    if (ii < ka && jj < ka) out[(int64_t)jj * ka + ii] = (double)acc[q][a][b][v];
+                }
+            }
+    }
+}
+
 // out(i, j) = sum_s P_s(i, j) in a fixed order: work-group = 64 consecutive outputs x
 // RQ split ranges; thread (o, q) sums the splits s = q, q + RQ, ... of output o, and
 // the RQ partial sums are added in q order.  In symmetric mode the lower blocks are
@@ -455,12 +580,15 @@ reduce_partials_kernel(const double* __restrict__ P, int nsplit, int ka, int nb,
     }
 }
 
+// Row splits: one chunk or more per split up to 256 splits, and for long products at
+// least 32 chunks per split up to TN_MAX_SPLITS (more work-groups in flight per CU).
 static int tn_splits(int64_t N, int rc) {
-    int64_t s = ceil_div(N, (int64_t)rc);
-    if (s < 1) s = 1;
-    if (s > TN_MAX_SPLITS) s = TN_MAX_SPLITS;
-    return (int)s;
+    const int64_t chunks = ceil_div(N, (int64_t)rc);
+    int64_t s = std::max(std::min<int64_t>(chunks, 256), std::min<int64_t>(ceil_div(chunks, (int64_t)32), TN_MAX_SPLITS));
+    return (int)std::max<int64_t>(s, 1);
 }
+// largest split count over the chunk sizes used (8 and 16 rows)
+int tn_max_splits(int64_t N) { return std::max(tn_splits(N, 8), tn_splits(N, 16)); }
 
 template <typename Tin, typename Tc>
 static size_t tn_lds(int rc, int ka, int nb, int sym) {
@@ -487,11 +615,17 @@ hipError_t gemm_prepare()
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     TN_INSTANCES(TN_ATTR)
 #undef TN_ATTR
+#define SYM_ATTR(Ti, Tc, RC) \
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_sym_kernel<Ti, Tc, RC>, \
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    SYM_ATTR(float, float, 16) SYM_ATTR(float, float, 8) SYM_ATTR(float, double, 16) SYM_ATTR(float, double, 8)
+    SYM_ATTR(double, double, 16) SYM_ATTR(double, double, 8)
+#undef SYM_ATTR
     return e;
 }
 
 size_t gemm_tn_partial_bytes(int64_t N, int ka, int nb) {
-    return (size_t)TN_MAX_SPLITS * (size_t)ka * (size_t)nb * sizeof(double);
+    return (size_t)tn_max_splits(N) * (size_t)ka * (size_t)nb * sizeof(double);
 }
 
 template <typename Tin, typename Tc, int RC, int RI, int RJ>
@@ -514,11 +648,28 @@ static hipError_t launch_tn_k(hipStream_t s, const Tin* A, int64_t lda, int a_rm
 // Wave tile: the instantiated shape that covers the block grid with the fewest
 // work-groups per row split, then the least recomputed (clamped) blocks.
 template <typename Tin, typename Tc, int RC>
+static hipError_t launch_sym_k(hipStream_t s, const Tin* A, int64_t lda, int a_rm, int ka, int64_t N, int vec,
+                               double* P, int* nsplit_out, const int32_t* skip_unless)
+{
+    const int ns = tn_splits(N, RC);
+    const int64_t rps = round_up(ceil_div(N, ns), RC);
+    const int ns_eff = (int)ceil_div(N, rps);
+    const size_t lds = tn_lds<Tin, Tc>(RC, ka, ka, 1);
+    hipLaunchKernelGGL((gemm_sym_kernel<Tin, Tc, RC>), dim3(ns_eff), dim3(TN_THREADS), lds, s,
+                       A, lda, a_rm, ka, N, rps, vec, P, skip_unless);
+    *nsplit_out = ns_eff;
+    return hipGetLastError();
+}
+
+template <typename Tin, typename Tc, int RC>
 static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_rm, int ka,
                                const Tin* B, int64_t ldb, int b_rm, int nb, int sym, int64_t N, int vec,
                                double* P, int* nsplit_out, const int32_t* skip_unless)
 {
     const int nbi = (int)ceil_div(ka, 16), nbj = (int)ceil_div(nb, 16);
+    // symmetric products whose upper super-blocks fit the waves: triangle-only kernel
+    if (sym && ((nbi + 1) / 2) * ((nbi + 1) / 2 + 1) / 2 <= SB_MAXW * (TN_THREADS / 64))
+        return launch_sym_k<Tin, Tc, RC>(s, A, lda, a_rm, ka, N, vec, P, nsplit_out, skip_unless);
     int best = -1;
     int64_t best_cost = INT64_MAX;
     int idx = 0;

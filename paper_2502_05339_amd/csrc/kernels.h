@@ -9,7 +9,7 @@
 namespace dmd {
 
 constexpr int NN_MAX_CB = 12;          // gemm_nn: n <= 192 output columns
-constexpr int TN_MAX_SPLITS = 256;     // gemm_tn: row splits (FP64 partials)
+constexpr int TN_MAX_SPLITS = 1024;    // gemm_tn: row splits (FP64 partials), at most
 constexpr int64_t TN_MAX_OUT = 320 * 320;
 constexpr int RECON_MAX_RP = 160;      // padded rank held in registers by the reconstruction
 constexpr int RECON_KPAD = 64;         // frame padding of the coefficient matrix
@@ -37,6 +37,7 @@ hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A
                    int sym, int64_t N, double* P, double* out, int64_t ldo, float* out32,
                    int64_t ldo32, const int32_t* skip_unless);
 size_t gemm_tn_partial_bytes(int64_t N, int ka, int nb);
+int tn_max_splits(int64_t N);          // row splits (FP64 partial products) gemm_tn uses for N rows
 
 // ---- reconstruction (recon.hip)
 struct ReconArgs {
