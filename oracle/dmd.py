@@ -21,10 +21,16 @@ Readings where the paper is silent or garbled (each also listed in the design doc):
   * Powers are lambda^e = exp(e * Log lambda) on the principal branch, for
     integer e (arbitrary time step, Sec. 4.4) and real e = t / dt (Sec. 6.1).
   * lambda = 0: 0^0 = 1, 0^k = 0 for k > 0.
+  * Temporal editing (Sec. 6.1): the printed sum drops the imaginary unit in
+    front of sin(k theta); it is read as exp(i k theta).  "Adjusting" Re(Omega)
+    and Im(Omega) is read as Re Omega' = s_re Re Omega + c_re and
+    Im Omega' = s_im Im Omega; the mode weight w multiplies the amplitude.
+    lambda = 0 (no logarithm) stays 0 under any edit.
 """
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 
@@ -180,6 +186,69 @@ def integrate(phi, lam, b, ts, dt=1.0):
     Om = np.log(np.asarray(lam, dtype=np.complex128)) / dt
     P = np.exp(np.outer(Om, np.asarray(ts, dtype=np.float64))) * np.asarray(b)[:, None]
     return (np.asarray(phi, dtype=np.complex128) @ P).real
+
+
+LOW_FREQ_CUT = 0.01
+
+
+def frequency_clusters(lam, dt, cut=LOW_FREQ_CUT):
+    """Cluster label of each mode (Sec. 6.1): 0 when |Im Omega| < cut (low frequency), else 1.
+
+    Omega = Log(lambda) / dt, so Im Omega = arg(lambda) / dt.
+    """
+    lam = np.asarray(lam, dtype=np.complex128)
+    theta = np.arctan2(lam.imag, lam.real)
+    return np.where(np.abs(theta / dt) < cut, 0, 1).astype(np.int32)
+
+
+def edit_modes(lam, b, dt, w, re_scale, re_shift, im_scale):
+    """Temporal editing of eq. edit_temporal (Sec. 6.1), one parameter set per mode.
+
+    Each eigenvalue is written as lambda = r exp(i theta) with r its modulus and
+    theta = atan2(Im, Re) its phase, so Omega = (log r + i theta) / dt.  The
+    edited rate and frequency are
+        Re Omega' = re_scale * Re Omega + re_shift,   Im Omega' = im_scale * Im Omega,
+    giving r' = exp(Re Omega' dt), theta' = Im Omega' dt and
+    lambda' = r' (cos theta' + i sin theta').  The mode's weight w scales its
+    amplitude: b' = w b.  Returns (lambda', b').
+    """
+    lam = np.asarray(lam, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    r = lam.size
+    w, re_scale, re_shift, im_scale = (np.broadcast_to(np.asarray(v, dtype=np.float64), (r,))
+                                       for v in (w, re_scale, re_shift, im_scale))
+    lam_new = np.zeros(r, dtype=np.complex128)
+    for i in range(r):
+        mod = abs(lam[i])
+        if mod == 0.0:
+            continue
+        theta = math.atan2(lam[i].imag, lam[i].real)
+        om_re = math.log(mod) / dt
+        om_im = theta / dt
+        om_re_new = re_scale[i] * om_re + re_shift[i]
+        om_im_new = im_scale[i] * om_im
+        mod_new = math.exp(om_re_new * dt)
+        th_new = om_im_new * dt
+        lam_new[i] = complex(mod_new * math.cos(th_new), mod_new * math.sin(th_new))
+    return lam_new, w * b
+
+
+def cluster_edit(lam, b, dt, weight, re_scale, re_shift, im_scale, cut=LOW_FREQ_CUT):
+    """edit_modes with one parameter set per frequency cluster (index 0 low, 1 high).
+
+    Returns (lambda', b', clusters).
+    """
+    c = frequency_clusters(lam, dt, cut)
+    pick = lambda v: np.asarray(v, dtype=np.float64)[c]
+    lam_new, b_new = edit_modes(lam, b, dt, pick(weight), pick(re_scale), pick(re_shift), pick(im_scale))
+    return lam_new, b_new, c
+
+
+def reverse(phi, lam, u, ks):
+    """Backward roll-out of eq. reverse_simulation (Sec. 6.2): z = Phi^+ u, then
+    u(t - k dt) = Re(Phi Lambda^-k z) for k in ks, with u the state at time t."""
+    z = project(phi, u)
+    return reconstruct(phi, lam, z, -np.asarray(ks, dtype=np.float64))
 
 
 def project(phi, u):

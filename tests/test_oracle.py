@@ -228,6 +228,88 @@ def test_time_reversal_round_trip():
     assert field_errors(Uback, g.Z[:, :1])["max_frame"] <= 1e-11
 
 
+# ---------------------------------------------------- temporal editing (Sec. 6.1)
+def _edit_case(seed=41, nc=12, dt=0.5):
+    rng = np.random.default_rng(seed)
+    lam_p = synth.draw_eigs(rng, nc, 0.9, arg=(0.001, 2.5))
+    lam = np.concatenate([lam_p, np.conj(lam_p), [0.93, -0.7]])
+    b = np.concatenate([synth.draw_amplitudes(rng, nc)] * 2 + [[0.4 - 0.1j, 1.2 + 0.3j]])
+    b[nc:2 * nc] = np.conj(b[:nc])
+    return lam, b, dt
+
+
+def test_edit_identity():
+    """Unit weights and scales and zero shift leave every eigenvalue and amplitude unchanged."""
+    lam, b, dt = _edit_case()
+    l2, b2 = oracle.edit_modes(lam, b, dt, 1.0, 1.0, 0.0, 1.0)
+    assert np.max(np.abs(l2 - lam) / np.abs(lam)) <= 4e-16 * 8
+    assert np.array_equal(b2, b)
+
+
+def test_edit_closed_forms():
+    """Doubling Omega squares lambda, negating it inverts lambda, a shift of
+    log(s)/dt scales lambda by s, a zero frequency scale leaves |lambda|."""
+    lam, b, dt = _edit_case(dt=0.37)
+    l2, _ = oracle.edit_modes(lam, b, dt, 1.0, 2.0, 0.0, 2.0)
+    assert np.max(np.abs(l2 - lam * lam) / np.abs(lam * lam)) <= 1e-14
+    li, _ = oracle.edit_modes(lam, b, dt, 1.0, -1.0, 0.0, -1.0)
+    assert np.max(np.abs(li - 1.0 / lam) * np.abs(lam)) <= 1e-14
+    ls, _ = oracle.edit_modes(lam, b, dt, 1.0, 1.0, math.log(1.5) / dt, 1.0)
+    assert np.max(np.abs(ls - 1.5 * lam) / np.abs(lam)) <= 1e-14
+    la, _ = oracle.edit_modes(lam, b, dt, 1.0, 1.0, 0.0, 0.0)
+    assert np.max(np.abs(la - np.abs(lam)) / np.abs(lam)) <= 1e-15
+    lu, _ = oracle.edit_modes(lam, b, dt, 1.0, 0.0, 0.0, 1.0)
+    assert np.max(np.abs(lu - lam / np.abs(lam))) <= 1e-15
+    lz, bz = oracle.edit_modes(np.array([0.0, 0.5]), np.array([1.0, 1.0]), dt, 3.0, 2.0, 0.1, 2.0)
+    assert lz[0] == 0 and np.array_equal(bz, [3.0, 3.0])
+
+
+def test_edit_clusters_brute_force():
+    """|Im Omega| = |arg lambda| / dt against the 0.01 cut, by hand."""
+    dt = 0.5
+    th = np.array([0.0, 0.004, -0.004, 0.0049, 0.0051, 0.006, -0.2, np.pi])
+    lam = 0.9 * np.exp(1j * th)
+    lam[-1] = -0.9
+    c = oracle.frequency_clusters(lam, dt)
+    assert list(c) == [0, 0, 0, 0, 1, 1, 1, 1]
+    assert list(oracle.frequency_clusters(lam, 1.0)) == [0, 0, 0, 0, 0, 0, 1, 1]
+
+
+def test_edit_reconstruction_semigroup_and_weights():
+    """Reconstructing the Omega-doubled model at k equals the original at 2k;
+    cluster weights (a, c) give a U_low + c U_high."""
+    cfg = synth.config("c1-cf", seed=102)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    dt = 0.25
+    ks = np.array([0, 1, 5, 33])
+    l2, b2 = oracle.edit_modes(f.lam, f.b, dt, 1.0, 2.0, 0.0, 2.0)
+    U2 = oracle.reconstruct(f.phi, l2, b2, ks)
+    U1 = oracle.reconstruct(f.phi, f.lam, f.b, 2 * ks)
+    assert field_errors(U2, U1)["max_frame"] <= 1e-12
+    cut = np.median(np.abs(np.angle(f.lam))) / dt
+    lw, bw, c = oracle.cluster_edit(f.lam, f.b, dt, (2.0, 3.0), (1, 1), (0, 0), (1, 1), cut=cut)
+    assert 0 < c.sum() < c.size
+    assert np.array_equal(lw, oracle.edit_modes(f.lam, f.b, dt, 1, 1, 0, 1)[0])
+    Uw = oracle.reconstruct(f.phi, lw, bw, ks)
+    lo, hi = c == 0, c == 1
+    Ulo = oracle.reconstruct(f.phi[:, lo], f.lam[lo], f.b[lo], ks)
+    Uhi = oracle.reconstruct(f.phi[:, hi], f.lam[hi], f.b[hi], ks)
+    assert field_errors(Uw, 2 * Ulo + 3 * Uhi)["max_frame"] <= 1e-12
+
+
+def test_reverse_recovers_earlier_snapshots():
+    """Backward roll-out from the last snapshot of an exactly linear sequence
+    returns the earlier snapshots (Sec. 6.2, eq. reverse_simulation)."""
+    cfg = synth.config("c1-cf", seed=103)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    T = g.Z.shape[1] - 1
+    ks = np.array([1, 2, 10, T])
+    U = oracle.reverse(f.phi, f.lam, g.Z[:, T], ks)
+    assert field_errors(U, g.Z[:, T - ks])["max_frame"] <= 1e-9
+
+
 def test_integrate_matches_integer_steps_and_semigroup():
     """exp(Omega t) at t = k dt equals Lambda^k; exp(Omega(t1+t2)) = exp(Omega t1) exp(Omega t2)."""
     cfg = synth.config("c1-cf", seed=102)
@@ -379,3 +461,26 @@ def test_planted_wrong_real_part_is_caught(monkeypatch):
     f = od.fit_exact(g.Z, cfg.r)
     U = od.reconstruct(f.phi, f.lam, f.b, np.arange(cfg.m))
     assert field_errors(U, g.Z)["max_frame"] > 1e-3
+
+
+def test_planted_cluster_without_dt_is_caught(monkeypatch):
+    """Comparing arg(lambda) instead of arg(lambda)/dt with the cut must fail the cluster pin."""
+    import oracle.dmd as od
+    real = od.frequency_clusters
+    monkeypatch.setattr(od, "frequency_clusters", lambda lam, dt, cut=0.01: real(lam, 1.0, cut))
+    th = np.array([0.0049, 0.0051])
+    assert list(od.frequency_clusters(0.9 * np.exp(1j * th), 0.5)) != [0, 1]
+
+
+def test_planted_edit_without_imaginary_unit_is_caught(monkeypatch):
+    """The printed form cos + sin (no i) must fail the squaring pin."""
+    import oracle.dmd as od
+    real = od.edit_modes
+
+    def garbled(lam, b, dt, w, s_re, c_re, s_im):
+        l2, b2 = real(lam, b, dt, w, s_re, c_re, s_im)
+        return np.abs(l2) * (np.cos(np.angle(l2)) + np.sin(np.angle(l2))), b2
+    monkeypatch.setattr(od, "edit_modes", garbled)
+    lam, b, dt = _edit_case()
+    l2, _ = od.edit_modes(lam, b, dt, 1.0, 2.0, 0.0, 2.0)
+    assert np.max(np.abs(l2 - lam * lam) / np.abs(lam * lam)) > 1e-3
