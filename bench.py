@@ -200,6 +200,13 @@ def main():
     recon32_ms = _events_ms(lambda: prep32.apply(Ubuf), reps)
     adj_ms = _events_ms(lambda: dmd.loss_grad(m, m.lam, m.b, Z, kfit), reps)
     recon_full_ms = _events_ms(lambda: dmd.reconstruct(m, ks, "bf16x3", out=Ubuf), reps)
+    # temporal editing (Sec. 6.1) and backward roll-out (Sec. 6.2) on the same model
+    edit_kw = dict(weight=(1.0, 1.5), re_scale=(1.0, 0.9), im_scale=(1.0, 1.5))
+    edit_ms = _events_ms(lambda: dmd.edit_modes(m, **edit_kw), reps)
+    em, _ = dmd.edit_modes(m, **edit_kw)
+    edited_recon_ms = _events_ms(lambda: dmd.reconstruct(em, ks, "bf16x3", out=Ubuf), reps)
+    u_last = Z[-1].contiguous()
+    reverse_ms = _events_ms(lambda: dmd.reverse(m, u_last, ks + 1, "bf16x3", out=Ubuf), reps)
 
     fp64 = None
     if not args.no_fp64:
@@ -268,6 +275,9 @@ def main():
                   "recon_with_coeffs_ms": round(recon_full_ms, 4),
                   "frames_per_s": round(cfg.K / (recon_ms * 1e-3), 1),
                   "recon_fp32_ms": round(recon32_ms, 4), "loss_grad_ms": round(adj_ms, 4)},
+        "editing": {"edit_ms": round(edit_ms, 4), "edited_recon_ms": round(edited_recon_ms, 4),
+                    "reverse_ms": round(reverse_ms, 4),
+                    "reverse": "project the last snapshot, then 1000 frames of Lambda^-k (bf16x3)"},
         "fp64": fp64,
         "accuracy": accuracy,
         "paper_context": {"precompute_s": 79.0, "subspace_step_us": 8.9,

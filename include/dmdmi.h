@@ -228,6 +228,41 @@ int32_t dmd_integrate(void* stream, const dmd_model* model, const double* t_host
                       int32_t T, int32_t mode, void* U, int64_t ldu, void* ws,
                       size_t ws_bytes);
 
+/* Temporal edit of the modes by frequency cluster (Sec. 6.1, eq. edit_temporal). */
+typedef struct dmd_edit {
+    double freq_cut;     /* a mode with |Im Omega| < freq_cut is in cluster 0 (low frequency),
+                            the others in cluster 1; Sec. 6.1 uses 0.01 */
+    double weight[2];    /* amplitude factor w of cluster 0 / 1: b' = w b */
+    double re_scale[2];  /* Re Omega' = re_scale * Re Omega + re_shift (decay / growth rate) */
+    double re_shift[2];
+    double im_scale[2];  /* Im Omega' = im_scale * Im Omega (angular frequency) */
+} dmd_edit;
+
+/*
+ * Edited eigenvalues and amplitudes for playback (Sec. 6.1, eq. edit_temporal).
+ * With Omega = Log(lambda) / dt = (log|lambda| + i arg lambda) / dt (principal branch,
+ * dt = model->dt), each mode gets
+ *   lambda' = exp(Omega' dt),  Re Omega' = re_scale Re Omega + re_shift,
+ *   Im Omega' = im_scale Im Omega,  b' = w b,
+ * with its cluster's parameters, or with its own row of mode_edit when that is not NULL.
+ * lambda = 0 gives lambda' = 0.  Reconstructing a model whose lam / b point at
+ * lam_out / b_out (same phi and kind) plays back the edited flow; re_scale = im_scale = -1
+ * gives lambda^-1, the reversed dynamics of Sec. 6.2.  A conjugate pair keeps conjugate
+ * eigenvalues under cluster edits (both members have the same |Im Omega|).
+ *   model       reads r, dt, lam, b (device); phi is not read
+ *   edit        host; every field finite, freq_cut >= 0
+ *   mode_edit   device, r rows of 4 doubles (w, re_scale, re_shift, im_scale), row-major,
+ *               or NULL to use the cluster parameters
+ *   lam_out     device, r complex (interleaved); may be model->lam (in-place edit)
+ *   b_out       device, r complex; may be model->b
+ *   cluster_out device, r int32 cluster labels, or NULL
+ * Errors: DMD_ERR_ARG for a missing pointer, dt <= 0 or a non-finite / negative field of
+ * edit; nothing is enqueued then.  Stream-ordered, no workspace, no synchronisation.
+ */
+int32_t dmd_edit_modes(void* stream, const dmd_model* model, const dmd_edit* edit,
+                       const double* mode_edit, double* lam_out, double* b_out,
+                       int32_t* cluster_out);
+
 /* Workspace bytes for dmd_project. */
 int32_t dmd_project_workspace_size(int64_t n, int32_t r, size_t* bytes);
 

@@ -4,11 +4,11 @@ The compute runs in libdmdmi.so (hand-written HIP kernels for gfx950); this
 package is the thin Python binding.  See include/dmdmi.h for the C ABI.
 """
 from ._lib import DMDError, lib, status_string
-from .api import (BatchedFit, DMDLoss, Model, PreparedReconstruction, autotune_reconstruct, fit, fit_opts,
-                  integrate, loss_grad, project, reconstruct, refit)
+from .api import (BatchedFit, DMDLoss, Model, PreparedReconstruction, autotune_reconstruct, edit_modes, fit,
+                  fit_opts, integrate, loss_grad, project, reconstruct, refit, reverse)
 
 __all__ = [
     "DMDError", "lib", "status_string", "BatchedFit", "DMDLoss", "Model", "PreparedReconstruction",
-    "autotune_reconstruct", "fit",
-    "fit_opts", "integrate", "loss_grad", "project", "reconstruct", "refit",
+    "autotune_reconstruct", "edit_modes", "fit",
+    "fit_opts", "integrate", "loss_grad", "project", "reconstruct", "refit", "reverse",
 ]

@@ -52,6 +52,11 @@ class SceneStruct(ctypes.Structure):
                 ("ws", c_void_p), ("ws_bytes", c_size_t)]
 
 
+class EditStruct(ctypes.Structure):
+    _fields_ = [("freq_cut", c_double), ("weight", c_double * 2), ("re_scale", c_double * 2),
+                ("re_shift", c_double * 2), ("im_scale", c_double * 2)]
+
+
 _SIGS = {
     "dmd_abi_version": (c_int32, []),
     "dmd_status_string": (ctypes.c_char_p, [c_int32]),
@@ -69,6 +74,8 @@ _SIGS = {
                                         c_void_p, c_size_t]),
     "dmd_integrate": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_double), c_int32,
                                 c_int32, c_void_p, c_int64, c_void_p, c_size_t]),
+    "dmd_edit_modes": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(EditStruct), c_void_p,
+                                 c_void_p, c_void_p, c_void_p]),
     "dmd_project_workspace_size": (c_int32, [c_int64, c_int32, ctypes.POINTER(c_size_t)]),
     "dmd_project": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_void_p, c_void_p, c_void_p, c_size_t]),
     "dmd_loss_grad_workspace_size": (c_int32, [c_int64, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)]),

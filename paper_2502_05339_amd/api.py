@@ -320,6 +320,57 @@ def integrate(model: Model, ts, mode: str | None = None, out: torch.Tensor | Non
     return out
 
 
+LOW_FREQ_CUT = 0.01
+
+
+def _pair(v, name):
+    a = np.broadcast_to(np.asarray(v, dtype=np.float64), (2,))
+    if not np.all(np.isfinite(a)):
+        raise ValueError(f"{name} must be finite")
+    return a
+
+
+def edit_modes(model: Model, weight=1.0, re_scale=1.0, re_shift=0.0, im_scale=1.0,
+               freq_cut: float = LOW_FREQ_CUT, per_mode: torch.Tensor | None = None, inplace: bool = False):
+    """Temporal editing (Sec. 6.1, eq. edit_temporal); returns (edited Model, cluster labels).
+
+    Omega = Log(lambda)/dt; per frequency cluster (0: |Im Omega| < freq_cut, 1: the rest)
+    Re Omega' = re_scale Re Omega + re_shift, Im Omega' = im_scale Im Omega, b' = weight b.
+    weight, re_scale, re_shift, im_scale: a scalar for both clusters or a (low, high) pair.
+    per_mode: optional (r, 4) float64 device tensor of (w, re_scale, re_shift, im_scale)
+    rows that replaces the cluster parameters.  The edited model shares phi and kind
+    with `model`; with inplace=True it also shares (and overwrites) lam and b.
+    """
+    _require_gpu(model.lam, "model.lam")
+    e = _lib.EditStruct()
+    e.freq_cut = float(freq_cut)
+    for name, v in (("weight", weight), ("re_scale", re_scale), ("re_shift", re_shift), ("im_scale", im_scale)):
+        a = _pair(v, name)
+        getattr(e, name)[0], getattr(e, name)[1] = float(a[0]), float(a[1])
+    pm = 0
+    if per_mode is not None:
+        _require_gpu(per_mode, "per_mode")
+        if per_mode.dtype != torch.float64 or tuple(per_mode.shape) != (model.r, 4) or not per_mode.is_contiguous():
+            raise ValueError("per_mode must be a contiguous (r, 4) float64 device tensor")
+        pm = per_mode.data_ptr()
+    lam = model.lam if inplace else torch.empty_like(model.lam)
+    b = model.b if inplace else torch.empty_like(model.b)
+    clusters = torch.empty(model.r, dtype=torch.int32, device=model.lam.device)
+    ms = model.struct()
+    check(_lib.lib().dmd_edit_modes(_stream(), ctypes.byref(ms), ctypes.byref(e), pm, lam.data_ptr(), b.data_ptr(),
+                                    clusters.data_ptr()), "dmd_edit_modes")
+    edited = model if inplace else dataclasses.replace(model, lam=lam, b=b)
+    return edited, clusters
+
+
+def reverse(model: Model, u: torch.Tensor, ks, mode: str | None = None, out: torch.Tensor | None = None):
+    """Backward roll-out (Sec. 6.2, eq. reverse_simulation): z = Phi^+ u, then frame j is
+    Re(Phi Lambda^-ks[j] z), the state ks[j] steps before u."""
+    z = project(model, u)
+    back = dataclasses.replace(model, b=z)
+    return reconstruct(back, -np.asarray(ks, dtype=np.int64), mode, out)
+
+
 def project(model: Model, u: torch.Tensor) -> torch.Tensor:
     """z = Phi^+ u (Sec. 3.1, eq. projection); returns (r,) complex128 on the device."""
     _require_gpu(u, "u")

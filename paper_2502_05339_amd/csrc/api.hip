@@ -533,6 +533,23 @@ int32_t dmd_integrate(void* stream, const dmd_model* model, const double* t_host
     return recon_enqueue((hipStream_t)stream, model, nullptr, t_host, T, mode, U, ldu, ws, ws_bytes, -1);
 }
 
+int32_t dmd_edit_modes(void* stream, const dmd_model* model, const dmd_edit* edit, const double* mode_edit,
+                       double* lam_out, double* b_out, int32_t* cluster_out)
+{
+    if (int32_t e = validate_model(model)) return e;
+    if (!edit || !lam_out || !b_out) return DMD_ERR_ARG;
+    if (!(model->dt > 0.0) || !isfinite(model->dt)) return DMD_ERR_ARG;
+    if (!isfinite(edit->freq_cut) || edit->freq_cut < 0.0) return DMD_ERR_ARG;
+    for (int c = 0; c < 2; ++c)
+        if (!isfinite(edit->weight[c]) || !isfinite(edit->re_scale[c]) || !isfinite(edit->re_shift[c]) ||
+            !isfinite(edit->im_scale[c]))
+            return DMD_ERR_ARG;
+    if (int32_t e0 = ensure_init()) return e0;
+    HIPCHK(edit_modes((hipStream_t)stream, model->r, model->dt, *edit, mode_edit, model->lam, model->b, lam_out,
+                      b_out, cluster_out));
+    return DMD_OK;
+}
+
 int32_t dmd_project_workspace_size(int64_t n, int32_t r, size_t* bytes)
 {
     if (!bytes) return DMD_ERR_ARG;

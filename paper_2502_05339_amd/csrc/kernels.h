@@ -102,6 +102,12 @@ size_t eig_workspace_bytes(int n);
 hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* ws, double* lam,
                       int32_t* kind, double* W, int32_t* info, double defl_tol);
 
+// ---- temporal editing (edit.hip)
+// lam_out / b_out may alias lam / b; mode_edit (r x 4, row-major) overrides the cluster
+// parameters when not null; cluster_out may be null.
+hipError_t edit_modes(hipStream_t s, int r, double dt, const dmd_edit& e, const double* mode_edit,
+                      const double* lam, const double* b, double* lam_out, double* b_out, int32_t* cluster_out);
+
 // ---- adjoint (adjoint.hip)
 hipError_t grad_reduce(hipStream_t s, int r, int ncols, const double* G, const double* lam,
                        const double* b, const int32_t* kind, const double* expo,

@@ -57,6 +57,7 @@ def test_struct_layout_matches_header():
 int main(void) {
   printf("%zu %zu %zu\n", sizeof(dmd_fit_opts), sizeof(dmd_model), sizeof(dmd_scene));
   printf("%zu %zu %zu\n", offsetof(dmd_fit_opts, omega), offsetof(dmd_model, info), offsetof(dmd_scene, ws_bytes));
+  printf("%zu %zu %zu\n", sizeof(dmd_edit), offsetof(dmd_edit, re_shift), offsetof(dmd_edit, im_scale));
   return 0;
 }
 """
@@ -71,6 +72,8 @@ int main(void) {
     assert sizes[3] == _lib.FitOpts.omega.offset
     assert sizes[4] == _lib.ModelStruct.info.offset
     assert sizes[5] == _lib.SceneStruct.ws_bytes.offset
+    assert sizes[6:] == [ctypes.sizeof(_lib.EditStruct), _lib.EditStruct.re_shift.offset,
+                         _lib.EditStruct.im_scale.offset]
 
 
 def _opts(r=10, p=4, q=1, precision="mixed", omega=0x1000):
@@ -219,3 +222,31 @@ def test_binding_refuses_cpu_tensors():
     Z = torch.zeros((10, 100), dtype=torch.float32)
     with pytest.raises((RuntimeError, ValueError)):
         dmd.fit(Z, 4)
+
+
+def test_edit_modes_validation(L):
+    """Every rejected argument returns DMD_ERR_ARG before anything is enqueued."""
+    from paper_2502_05339_amd import _lib
+    m = _model_struct(r=10)
+
+    def edit(**kw):
+        e = _lib.EditStruct()
+        e.freq_cut = kw.get("freq_cut", 0.01)
+        for f in ("weight", "re_scale", "im_scale"):
+            getattr(e, f)[0] = getattr(e, f)[1] = 1.0
+        for k, v in kw.items():
+            if k != "freq_cut":
+                getattr(e, k)[1] = v
+        return e
+    e = edit()
+    assert L.dmd_edit_modes(None, ctypes.byref(m), None, 0, 0x1000, 0x2000, 0) == 1
+    assert L.dmd_edit_modes(None, ctypes.byref(m), ctypes.byref(e), 0, 0, 0x2000, 0) == 1
+    assert L.dmd_edit_modes(None, ctypes.byref(m), ctypes.byref(e), 0, 0x1000, 0, 0) == 1
+    assert L.dmd_edit_modes(None, None, ctypes.byref(e), 0, 0x1000, 0x2000, 0) == 1
+    for bad in (edit(freq_cut=-0.5), edit(freq_cut=float("nan")), edit(weight=float("inf")),
+                edit(re_shift=float("nan")), edit(im_scale=float("-inf"))):
+        assert L.dmd_edit_modes(None, ctypes.byref(m), ctypes.byref(bad), 0, 0x1000, 0x2000, 0) == 1
+    m.dt = 0.0
+    assert L.dmd_edit_modes(None, ctypes.byref(m), ctypes.byref(e), 0, 0x1000, 0x2000, 0) == 1
+    m.dt = float("inf")
+    assert L.dmd_edit_modes(None, ctypes.byref(m), ctypes.byref(e), 0, 0x1000, 0x2000, 0) == 1
