@@ -287,7 +287,8 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
     __shared__ int sh_lc[2];     // deflation search result (double-buffered)
     __shared__ double sh_red[4];
 
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nw = nt >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: wave-level branches stay scalar
     const int hsize = hp_col(n, n);
     double* Zs = Hs + hsize;                                    // nr x n
     HP H{Hs, n};
@@ -462,6 +463,7 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
             const double z0 = H(l + 1, l) * H(l + 2, l + 1);
             __syncthreads();   // every thread has read the shift inputs before H changes
             int pk = -1;       // column reduced by the previous step, written one step late
+            int poff = 0;      // its packed offset
             double pbeta = 0.0;
             // packed offsets of columns k-1 .. k+2, advanced by the column lengths min(j+4, n)
             int hm = hp_col(max(l - 1, 0), n), hk0 = hp_col(l, n), hk1 = hp_col(l + 1, n), hk2 = hp_col(l + 2, n);
@@ -492,13 +494,16 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
                 prole = role;
                 // the corner C(a, b) = H(k+a, k+b) is needed only by the waves holding rows k..k+m-1
                 const bool cw = (wave == (k >> 6)) || (wave == ((k + m - 1) >> 6));
-                double c00 = 0.0, c10 = 0.0, c20 = 0.0, c01 = 0.0, c11 = 0.0, c21 = 0.0, c02 = 0.0, c12 = 0.0, c22 = 0.0;
+                double c00, c10, c20, c01, c11, c21, c02, c12, c22;   // read only where cw
                 if (cw) {
                     c00 = Hs[hk0 + k]; c10 = Hs[hk0 + k + 1]; c20 = Hs[hk0 + k + 2];
                     c01 = Hs[hk1 + k]; c11 = Hs[hk1 + k + 1]; c21 = Hs[hk1 + k + 2];
                     c02 = Hs[hk2 + k]; c12 = Hs[hk2 + k + 1]; c22 = Hs[hk2 + k + 2];
                 }
-                if (G && m == 2) { z = 0.0; e2 = 0.0; c20 = 0.0; c21 = 0.0; c02 = 0.0; c12 = 0.0; c22 = 0.0; }
+                if (G && m == 2) {
+                    z = 0.0; e2 = 0.0;
+                    if (cw) { c20 = 0.0; c21 = 0.0; c02 = 0.0; c12 = 0.0; c22 = 0.0; }
+                }
                 double d, t, beta;
                 reflector3(x, y, z, &d, &t, &beta);
                 // ---- P_k = I - t u u^T, u = (d, y, z), applied to the operands: rows k..k+m-1
@@ -526,10 +531,10 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
                     }
                 }
                 if (tid == pend_t && pk >= 0) {             // column pk: (beta, 0, 0) below its subdiagonal
-                    H(pk + 1, pk) = pbeta; H(pk + 2, pk) = 0.0;
-                    if (pk + 3 <= hi) H(pk + 3, pk) = 0.0;
+                    Hs[poff + pk + 1] = pbeta; Hs[poff + pk + 2] = 0.0;
+                    if (pk + 3 <= hi) Hs[poff + pk + 3] = 0.0;
                 }
-                if (!G || k > l) { pk = k - 1; pbeta = beta; }
+                if (!G || k > l) { pk = k - 1; poff = hm; pbeta = beta; }
                 // operands of the next step: this step's second and third entries
                 e0 = e1; e1 = e2;
                 __syncthreads();
@@ -538,8 +543,8 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
             for (int k = l + 1; k <= hi - 3; ++k) step(k, std::false_type{});
             for (int k = max(l + 1, hi - 2); k <= hi - 1; ++k) step(k, std::true_type{});
             if (tid == pend_t && pk >= 0) {
-                H(pk + 1, pk) = pbeta; H(pk + 2, pk) = 0.0;
-                if (pk + 3 <= hi) H(pk + 3, pk) = 0.0;
+                Hs[poff + pk + 1] = pbeta; Hs[poff + pk + 2] = 0.0;
+                if (pk + 3 <= hi) Hs[poff + pk + 3] = 0.0;
             }
             __syncthreads();
         }
