@@ -251,6 +251,32 @@ def reverse(phi, lam, u, ks):
     return reconstruct(phi, lam, z, -np.asarray(ks, dtype=np.float64))
 
 
+def rollout(phi, lam, z0, F=None, dt=1.0, steps=None):
+    """Forced reduced roll-out, eq. external_forces (Sec. 4.2, DMD with control).
+
+    z_0 = z0 and, for s = 0 .. T-1,  z_{s+1} = Lambda z_s + dt Phi^+ f_s, where f_s is
+    column s of the full-space forcing F (N x T; the paper's sum of B_i q_i and f_j at
+    step s) and Phi^+ is the least-squares projection of eq. projection.  F = None runs
+    `steps` unforced steps.  Returns (Z, U): the states Z (T+1, r) and the frames
+    U = Re(Phi z_s) (N, T+1).
+    """
+    phi = np.asarray(phi, dtype=np.complex128)
+    lam = np.asarray(lam, dtype=np.complex128)
+    if F is None:
+        T = int(steps)
+        G = np.zeros((lam.size, T), dtype=np.complex128)
+    else:
+        F = np.asarray(F, dtype=np.float64)
+        T = F.shape[1]
+        G = np.linalg.lstsq(phi, F.astype(np.complex128), rcond=None)[0]   # Phi^+ f_s, all s
+    Z = np.zeros((T + 1, lam.size), dtype=np.complex128)
+    Z[0] = np.asarray(z0, dtype=np.complex128)
+    for s in range(T):
+        Z[s + 1] = lam * Z[s] + dt * G[:, s]
+    U = (phi @ Z.T).real
+    return Z, U
+
+
 def project(phi, u):
     """z = Phi^+ u: eq. projection (Sec. 3.1)."""
     return np.linalg.lstsq(np.asarray(phi, dtype=np.complex128),

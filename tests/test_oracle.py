@@ -310,6 +310,82 @@ def test_reverse_recovers_earlier_snapshots():
     assert field_errors(U, g.Z[:, T - ks])["max_frame"] <= 1e-9
 
 
+# ------------------------------------------- forced roll-out (Sec. 4.2, DMDc)
+def _paired_vector(rng, kind_like):
+    """A complex vector conjugate-paired like a fitted eigenvalue list."""
+    v = rng.standard_normal(kind_like.size) + 1j * rng.standard_normal(kind_like.size)
+    i = 0
+    while i < kind_like.size:
+        if abs(kind_like[i].imag) < 1e-12:
+            v[i] = v[i].real
+            i += 1
+        else:
+            v[i + 1] = np.conj(v[i])
+            i += 2
+    return v
+
+
+def test_rollout_unforced_is_reconstruction():
+    cfg = synth.config("c1-cf", seed=102)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    Z, U = oracle.rollout(f.phi, f.lam, f.b, None, dt=0.3, steps=40)
+    assert field_errors(U, oracle.reconstruct(f.phi, f.lam, f.b, np.arange(41)))["max_frame"] <= 1e-13
+    assert np.allclose(Z[17], f.b * f.lam ** 17, rtol=1e-12, atol=0)
+
+
+def test_rollout_constant_forcing_geometric_series():
+    """f_s = Phi c for every s gives z_s = lambda^s z0 + dt (1 - lambda^s) / (1 - lambda) c."""
+    cfg = synth.config("c1-cf", seed=103)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    rng = np.random.default_rng(4)
+    c = _paired_vector(rng, f.lam)
+    fs = (f.phi @ c).real
+    T, dt = 25, 0.4
+    F = np.repeat(fs[:, None], T, axis=1)
+    Z, _ = oracle.rollout(f.phi, f.lam, f.b, F, dt=dt)
+    s = np.arange(T + 1)[:, None]
+    expect = f.lam[None, :] ** s * f.b[None, :] + dt * (1 - f.lam[None, :] ** s) / (1 - f.lam[None, :]) * c[None, :]
+    assert np.max(np.abs(Z - expect)) <= 1e-10 * np.max(np.abs(expect))
+
+
+def test_rollout_orthogonal_forcing_and_linearity():
+    """Forcing orthogonal to the modes' real span changes nothing; the response is linear in F."""
+    cfg = synth.config("c1-cf", seed=104)
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    rng = np.random.default_rng(5)
+    T = 12
+    basis = np.concatenate([f.phi.real, f.phi.imag], axis=1)
+    F = rng.standard_normal((f.phi.shape[0], T))
+    Fperp = F - basis @ np.linalg.lstsq(basis, F, rcond=None)[0]
+    Z0, _ = oracle.rollout(f.phi, f.lam, f.b, None, steps=T)
+    Zp, _ = oracle.rollout(f.phi, f.lam, f.b, Fperp, dt=0.7)
+    assert np.max(np.abs(Zp - Z0)) <= 1e-10 * np.max(np.abs(Z0))
+    F1, F2 = rng.standard_normal((2, f.phi.shape[0], T))
+    Za, _ = oracle.rollout(f.phi, f.lam, f.b, F1, dt=0.7)
+    Zb, _ = oracle.rollout(f.phi, f.lam, f.b, F2, dt=0.7)
+    Zc, _ = oracle.rollout(f.phi, f.lam, f.b, F1 + F2, dt=0.7)
+    assert np.max(np.abs((Zc - Z0) - (Za - Z0) - (Zb - Z0))) <= 1e-10 * np.max(np.abs(Zc))
+
+
+def test_rollout_two_mode_by_hand():
+    """Orthonormal complex pair: Phi^+ = Phi^H; two steps written out."""
+    v = np.array([1.0, 1j, 0.0]) / np.sqrt(2.0)
+    phi = np.stack([v, np.conj(v)], axis=1)
+    lam = np.array([0.9 * np.exp(0.2j), 0.9 * np.exp(-0.2j)])
+    z0 = np.array([1 + 1j, 1 - 1j])
+    F = np.array([[1.0, 0.0], [0.0, 2.0], [5.0, 5.0]])     # the third row is outside the span
+    dt = 0.5
+    g = np.conj(phi).T @ F                                   # Phi^H f_s
+    z1 = lam * z0 + dt * g[:, 0]
+    z2 = lam * z1 + dt * g[:, 1]
+    Z, U = oracle.rollout(phi, lam, z0, F, dt=dt)
+    assert np.allclose(Z, [z0, z1, z2], rtol=0, atol=1e-14)
+    assert np.allclose(U[:, 2], (phi @ z2).real, atol=1e-14)
+
+
 def test_integrate_matches_integer_steps_and_semigroup():
     """exp(Omega t) at t = k dt equals Lambda^k; exp(Omega(t1+t2)) = exp(Omega t1) exp(Omega t2)."""
     cfg = synth.config("c1-cf", seed=102)
@@ -484,3 +560,24 @@ def test_planted_edit_without_imaginary_unit_is_caught(monkeypatch):
     lam, b, dt = _edit_case()
     l2, _ = od.edit_modes(lam, b, dt, 1.0, 2.0, 0.0, 2.0)
     assert np.max(np.abs(l2 - lam * lam) / np.abs(lam * lam)) > 1e-3
+
+
+def test_planted_rollout_without_dt_is_caught(monkeypatch):
+    """Dropping dt from the forcing term must fail the geometric-series pin."""
+    import oracle.dmd as od
+    real = od.rollout
+    monkeypatch.setattr(od, "rollout", lambda phi, lam, z0, F=None, dt=1.0, steps=None: real(phi, lam, z0, F, 1.0, steps))
+    _geometric_check(od, expect_pass=False)
+
+
+def _geometric_check(od, expect_pass=True):
+    cfg = synth.config("c1-cf", seed=103)
+    g = synth.generate(cfg)
+    f = od.fit_exact(g.Z, cfg.r)
+    c = _paired_vector(np.random.default_rng(4), f.lam)
+    F = np.repeat((f.phi @ c).real[:, None], 25, axis=1)
+    Z, _ = od.rollout(f.phi, f.lam, f.b, F, dt=0.4)
+    s = np.arange(26)[:, None]
+    expect = f.lam ** s * f.b + 0.4 * (1 - f.lam ** s) / (1 - f.lam) * c
+    ok = np.max(np.abs(Z - expect)) <= 1e-10 * np.max(np.abs(expect))
+    assert ok == expect_pass
