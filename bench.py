@@ -207,6 +207,12 @@ def main():
     edited_recon_ms = _events_ms(lambda: dmd.reconstruct(em, ks, "bf16x3", out=Ubuf), reps)
     u_last = Z[-1].contiguous()
     reverse_ms = _events_ms(lambda: dmd.reverse(m, u_last, ks + 1, "bf16x3", out=Ubuf), reps)
+    # forced roll-out (Sec. 4.6): K-1 steps of synthetic forcing, K frames
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    forcing = 1e-3 * torch.randn((cfg.K - 1, cfg.N), device="cuda", generator=gen)
+    rollout_ms = _events_ms(lambda: dmd.rollout(m, forcing, mode="bf16x3"), reps)
+    rollout_bytes = 4 * cfg.N * (cfg.K - 1) + 4 * cfg.N * cfg.K + 2 * 4 * cfg.N * cfg.r
+    del forcing
 
     fp64 = None
     if not args.no_fp64:
@@ -277,7 +283,11 @@ def main():
                   "recon_fp32_ms": round(recon32_ms, 4), "loss_grad_ms": round(adj_ms, 4)},
         "editing": {"edit_ms": round(edit_ms, 4), "edited_recon_ms": round(edited_recon_ms, 4),
                     "reverse_ms": round(reverse_ms, 4),
-                    "reverse": "project the last snapshot, then 1000 frames of Lambda^-k (bf16x3)"},
+                    "reverse": "project the last snapshot, then 1000 frames of Lambda^-k (bf16x3)",
+                    "rollout_ms": round(rollout_ms, 4),
+                    "rollout_gb_s": round(rollout_bytes / (rollout_ms * 1e-3) / 1e9, 1),
+                    "rollout": "999 forced steps (N x 999 FP32 forcing projected on the modes) and 1000 "
+                               "bf16x3 frames"},
         "fp64": fp64,
         "accuracy": accuracy,
         "paper_context": {"precompute_s": 79.0, "subspace_step_us": 8.9,

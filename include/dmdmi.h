@@ -274,6 +274,32 @@ int32_t dmd_project_workspace_size(int64_t n, int32_t r, size_t* bytes);
 int32_t dmd_project(void* stream, const dmd_model* model, const void* u, double* z,
                     void* ws, size_t ws_bytes);
 
+/* Workspace bytes for dmd_rollout of T forced steps (any f / U / z_out combination). */
+int32_t dmd_rollout_workspace_size(int64_t n, int32_t r, int32_t T, int32_t mode, size_t* bytes);
+
+/*
+ * Forced roll-out in the reduced space (Sec. 4.6, eq. external_forces, DMD with control):
+ *   z_0 = z0,   z_{s+1} = Lambda z_s + dt Phi^+ f_s   (s = 0 .. T-1, dt = model->dt),
+ * and the frames u_s = Re(Phi z_s), s = 0 .. T.
+ *   z0      device, r complex (interleaved), conjugate-paired like lam; NULL starts from
+ *           model->b (the fitted state at k = 0)
+ *   f       device, N x T column-major (ldf >= N), the model's dtype: column s is the
+ *           full-space forcing of step s, i.e. the paper's sum of B_i q_i(t) and f_j(t),
+ *           formed by the caller; NULL runs the unforced recurrence (lambda^s z0)
+ *   mode    dmd_recon_mode of U, as for dmd_reconstruct (checked also when U is NULL)
+ *   U       device, N x (T+1) column-major (ldu >= N), frame s in column s; or NULL
+ *   z_out   device, (T+1) x r complex, state s at z_out + 2 r s; or NULL
+ * Phi^+ f_s is the least-squares projection of eq. projection: the FP64 Gram of Phi, its
+ * Cholesky inverse, then R^-1 R^-T Phi^T F over all steps (Phi^T F in the model's precision,
+ * split-N partial sums in FP64).  The recurrence runs in FP64,
+ * one scan per mode; the frames are one reconstruction GEMM over the T+1 states.
+ * Errors: DMD_ERR_SHAPE for T < 1, DMD_ERR_ARG for dt <= 0, ldf < N, a bad mode or a
+ * mode / dtype / ldu mismatch of U, DMD_ERR_WORKSPACE; nothing is enqueued then.
+ */
+int32_t dmd_rollout(void* stream, const dmd_model* model, const double* z0, const void* f,
+                    int64_t ldf, int32_t T, int32_t mode, void* U, int64_t ldu, double* z_out,
+                    void* ws, size_t ws_bytes);
+
 /* Workspace bytes for dmd_loss_grad. */
 int32_t dmd_loss_grad_workspace_size(int64_t n, int32_t r, int32_t ncols, int32_t dtype,
                                      size_t* bytes);

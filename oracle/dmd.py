@@ -252,7 +252,7 @@ def reverse(phi, lam, u, ks):
 
 
 def rollout(phi, lam, z0, F=None, dt=1.0, steps=None):
-    """Forced reduced roll-out, eq. external_forces (Sec. 4.2, DMD with control).
+    """Forced reduced roll-out, eq. external_forces (Sec. 4.6, DMD with control).
 
     z_0 = z0 and, for s = 0 .. T-1,  z_{s+1} = Lambda z_s + dt Phi^+ f_s, where f_s is
     column s of the full-space forcing F (N x T; the paper's sum of B_i q_i and f_j at

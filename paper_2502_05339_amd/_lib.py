@@ -76,6 +76,9 @@ _SIGS = {
                                 c_int32, c_void_p, c_int64, c_void_p, c_size_t]),
     "dmd_edit_modes": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(EditStruct), c_void_p,
                                  c_void_p, c_void_p, c_void_p]),
+    "dmd_rollout_workspace_size": (c_int32, [c_int64, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
+    "dmd_rollout": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_void_p, c_void_p, c_int64, c_int32, c_int32,
+                              c_void_p, c_int64, c_void_p, c_void_p, c_size_t]),
     "dmd_project_workspace_size": (c_int32, [c_int64, c_int32, ctypes.POINTER(c_size_t)]),
     "dmd_project": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_void_p, c_void_p, c_void_p, c_size_t]),
     "dmd_loss_grad_workspace_size": (c_int32, [c_int64, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)]),

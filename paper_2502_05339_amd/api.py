@@ -371,6 +371,48 @@ def reverse(model: Model, u: torch.Tensor, ks, mode: str | None = None, out: tor
     return reconstruct(back, -np.asarray(ks, dtype=np.int64), mode, out)
 
 
+def rollout(model: Model, forcing: torch.Tensor | None = None, steps: int | None = None,
+            z0: torch.Tensor | None = None, mode: str | None = None, frames: bool = True):
+    """Forced reduced roll-out (Sec. 4.6, eq. external_forces): z_{s+1} = Lambda z_s + dt Phi^+ f_s.
+
+    forcing: (T, N) tensor of the model's dtype, row s = full-space forcing of step s (the
+    paper's sum of B_i q_i and f_j), or None with `steps` = T for the unforced recurrence.
+    z0: (r,) complex128 device tensor, default the model's amplitudes b.
+    Returns (states (T+1, r) complex128, frames (T+1, N) or None): frame s = Re(Phi z_s).
+    """
+    _require_gpu(model.phi, "model.phi")
+    if forcing is not None:
+        _require_gpu(forcing, "forcing")
+        if forcing.dim() != 2 or forcing.shape[1] != model.n or forcing.stride(1) != 1 or forcing.dtype != model.phi.dtype:
+            raise ValueError("forcing must be a (T, N) tensor of the model's dtype with unit stride along N")
+        T = forcing.shape[0]
+        fptr, ldf = forcing.data_ptr(), forcing.stride(0)
+    else:
+        if steps is None or steps < 1:
+            raise ValueError("steps must be given (>= 1) without forcing")
+        T, fptr, ldf = int(steps), 0, model.n
+    if z0 is not None:
+        _require_gpu(z0, "z0")
+        if z0.dtype != torch.complex128 or z0.numel() != model.r or not z0.is_contiguous():
+            raise ValueError("z0 must be a contiguous (r,) complex128 tensor")
+    m = mode or _default_mode(model)
+    mcode = RECON_MODES[m]
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    check(L.dmd_rollout_workspace_size(model.n, model.r, T, mcode, ctypes.byref(nb)), "dmd_rollout_workspace_size")
+    ws = _workspace(nb.value, model.phi.device)
+    states = torch.empty((T + 1, model.r), dtype=torch.complex128, device=model.phi.device)
+    U = None
+    if frames:
+        odt = torch.float64 if mcode == RECON_FP64 else torch.float32
+        U = torch.empty((T + 1, model.n), dtype=odt, device=model.phi.device)
+    ms = model.struct()
+    check(L.dmd_rollout(_stream(), ctypes.byref(ms), _ptr(z0), fptr, ldf, T, mcode, _ptr(U),
+                        U.stride(0) if U is not None else model.n, states.data_ptr(), ws.data_ptr(), ws.numel()),
+          "dmd_rollout")
+    return states, U
+
+
 def project(model: Model, u: torch.Tensor) -> torch.Tensor:
     """z = Phi^+ u (Sec. 3.1, eq. projection); returns (r,) complex128 on the device."""
     _require_gpu(u, "u")

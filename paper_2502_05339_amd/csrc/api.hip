@@ -425,6 +425,37 @@ int32_t recon_enqueue(hipStream_t st, const dmd_model* m, const int64_t* k_host,
     return recon_apply(st, m, K, mode, U, ldu, ws, ws_bytes, cfg_override);
 }
 
+// ---- forced roll-out workspace
+// forcing columns per projection GEMM: 12 output blocks of 16, which the 5 x 3 wave tile
+// covers without recomputed blocks for r up to 160
+constexpr int ROLL_TC = 192;
+
+struct RollPlan {
+    double* P;        // split-N partial products
+    double* PhiG;     // r x r FP64 Gram of Phi
+    double* Rinv;     // r x r
+    int32_t* scratch;
+    double* rhs;      // r x T: Phi^T F
+    double* tmp;      // r x T: R^-T rhs, then beta
+    double* states;   // (T+1) x r complex
+    ReconPlan rec;    // coefficients of the T+1 frames
+};
+
+RollPlan roll_carve(Carver& cv, int64_t n, int r, int T, int mode)
+{
+    RollPlan p;
+    const int tc = std::min(T, ROLL_TC);
+    p.P = cv.take<double>((size_t)tn_max_splits(n) * r * std::max(r, tc));
+    p.PhiG = cv.take<double>((size_t)r * r);
+    p.Rinv = cv.take<double>((size_t)r * r);
+    p.scratch = cv.take<int32_t>(16);
+    p.rhs = cv.take<double>((size_t)r * T);
+    p.tmp = cv.take<double>((size_t)r * T);
+    p.states = cv.take<double>((size_t)2 * r * (T + 1));
+    p.rec = recon_carve(cv, r, T + 1, mode);
+    return p;
+}
+
 }  // namespace
 
 // ====================================================================== extern "C"
@@ -602,6 +633,73 @@ int32_t dmd_project(void* stream, const dmd_model* model, const void* u, double*
         HIPCHK(normal_solve(st, r, Rinv, r, rhs2, beta, 1));
     }
     HIPCHK(beta_to_b(st, r, beta, model->kind, z));
+    return DMD_OK;
+}
+
+int32_t dmd_rollout_workspace_size(int64_t n, int32_t r, int32_t T, int32_t mode, size_t* bytes)
+{
+    if (!bytes) return DMD_ERR_ARG;
+    if (n < 1 || r < 1 || T < 1) return DMD_ERR_SHAPE;
+    if (mode < DMD_RECON_FP64 || mode > DMD_RECON_BF16X3) return DMD_ERR_ARG;
+    Carver c(nullptr);
+    roll_carve(c, n, r, T, mode);
+    *bytes = c.bytes();
+    return DMD_OK;
+}
+
+int32_t dmd_rollout(void* stream, const dmd_model* model, const double* z0, const void* f, int64_t ldf, int32_t T,
+                    int32_t mode, void* U, int64_t ldu, double* z_out, void* ws, size_t ws_bytes)
+{
+    if (int32_t e = validate_model(model)) return e;
+    if (T < 1) return DMD_ERR_SHAPE;
+    if (!(model->dt > 0.0) || !isfinite(model->dt)) return DMD_ERR_ARG;
+    if (f && ldf < model->n) return DMD_ERR_ARG;
+    if (mode < DMD_RECON_FP64 || mode > DMD_RECON_BF16X3) return DMD_ERR_ARG;
+    if (U && ((mode == DMD_RECON_FP64) != (model->dtype == DMD_F64) || ldu < model->n)) return DMD_ERR_ARG;
+    size_t need = 0;
+    if (int32_t e = dmd_rollout_workspace_size(model->n, model->r, T, mode, &need)) return e;
+    if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    if (int32_t e0 = ensure_init()) return e0;
+    hipStream_t st = (hipStream_t)stream;
+    const int r = model->r;
+    const int64_t n = model->n;
+    Carver cv(ws);
+    RollPlan p = roll_carve(cv, n, r, T, mode);
+    double* states = z_out ? z_out : p.states;
+    const double* beta = nullptr;
+    if (f) {
+        // g_s = Phi^+ f_s for every step: FP64 normal equations through the Gram of Phi
+        const size_t esz = model->dtype == DMD_F64 ? 8 : 4;
+        HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, model->phi, model->ldphi, 1, r, 1,
+                       n, p.P, p.PhiG, r, nullptr, 0, nullptr));
+        HIPCHK(fill_i32(st, p.scratch, 16, 0));
+        HIPCHK(chol_inv(st, p.PhiG, r, r, p.Rinv, r, nullptr, 0, 0.0, nullptr, p.scratch, nullptr));
+        for (int c0 = 0; c0 < T; c0 += ROLL_TC) {
+            const int nc = std::min(ROLL_TC, T - c0);
+            const void* fc = (const char*)f + (size_t)c0 * (size_t)ldf * esz;
+            // FP32 models: FP32 MFMA products, split-N partials summed in FP64 (as the fit's X^T Q)
+            HIPCHK(gemm_tn(st, model->dtype, model->dtype, model->phi, model->ldphi, 1, r, fc, ldf, 0, nc, 0, n,
+                           p.P, p.rhs + (size_t)c0 * r, r, nullptr, 0, nullptr));
+        }
+        HIPCHK(small_gemm(st, 1, 0, r, T, r, 1.0, p.Rinv, r, p.rhs, r, 0.0, p.tmp, r));   // R^-T (Phi^T F)
+        HIPCHK(small_gemm(st, 0, 0, r, T, r, 1.0, p.Rinv, r, p.tmp, r, 0.0, p.rhs, r));   // beta = R^-1 (...)
+        beta = p.rhs;
+    }
+    HIPCHK(rollout_scan(st, r, T, model->lam, z0 ? z0 : model->b, beta, r, model->kind, model->dt, states));
+    if (U) {
+        const int rp = (int)dmd_phi_ld(r);
+        const int K = T + 1;
+        const int Kp = (int)round_up(K, RECON_KPAD);
+        HIPCHK(pack_states(st, states, model->kind, r, K, Kp, rp, mode, p.rec.chi, p.rec.clo));
+        ReconArgs ra{};
+        ra.mode = mode;
+        ra.phi = model->phi; ra.ldphi = model->ldphi; ra.N = n; ra.rp = rp;
+        ra.c_hi = p.rec.chi; ra.c_lo = p.rec.clo; ra.K = K;
+        ra.U = U; ra.ldu = ldu;
+        const int vw = mode == DMD_RECON_FP64 ? 2 : 4;
+        ra.vec_store = (ldu % vw == 0) && aligned16(U);
+        HIPCHK(recon_launch(st, ra, tune_lookup(mode, rp, n, K)));
+    }
     return DMD_OK;
 }
 

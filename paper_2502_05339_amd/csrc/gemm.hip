@@ -599,7 +599,7 @@ static size_t tn_lds(int rc, int ka, int nb, int sym) {
 
 // wave tiles (RI x RJ output blocks) instantiated per accumulator type
 #define TN_TILES_F32(X, Ti, Tc, RC) X(Ti, Tc, RC, 2, 2) X(Ti, Tc, RC, 3, 3) X(Ti, Tc, RC, 5, 1) \
-    X(Ti, Tc, RC, 5, 4) X(Ti, Tc, RC, 5, 5) X(Ti, Tc, RC, 7, 3) X(Ti, Tc, RC, 10, 3)
+    X(Ti, Tc, RC, 5, 3) X(Ti, Tc, RC, 5, 4) X(Ti, Tc, RC, 5, 5) X(Ti, Tc, RC, 7, 3) X(Ti, Tc, RC, 10, 3)
 #define TN_TILES_F64(X, Ti, Tc, RC) X(Ti, Tc, RC, 2, 2) X(Ti, Tc, RC, 3, 3) X(Ti, Tc, RC, 4, 4) \
     X(Ti, Tc, RC, 5, 1) X(Ti, Tc, RC, 5, 3)
 #define TN_INSTANCES(X) \
@@ -682,9 +682,11 @@ static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_r
 #define TN_CASE(k, RI, RJ) \
     case k: return launch_tn_k<Tin, Tc, RC, RI, RJ>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
     if constexpr (sizeof(Tc) == 4) {
-        consider(2, 2); consider(3, 3); consider(5, 1); consider(5, 4); consider(5, 5); consider(7, 3); consider(10, 3);
+        consider(2, 2); consider(3, 3); consider(5, 1); consider(5, 3); consider(5, 4); consider(5, 5); consider(7, 3);
+        consider(10, 3);
         switch (best) {
-            TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 4) TN_CASE(4, 5, 5) TN_CASE(5, 7, 3)
+            TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 3) TN_CASE(4, 5, 4) TN_CASE(5, 5, 5)
+            TN_CASE(6, 7, 3)
             default: return launch_tn_k<Tin, Tc, RC, 10, 3>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
         }
     } else {

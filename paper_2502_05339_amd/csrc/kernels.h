@@ -108,6 +108,14 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
 hipError_t edit_modes(hipStream_t s, int r, double dt, const dmd_edit& e, const double* mode_edit,
                       const double* lam, const double* b, double* lam_out, double* b_out, int32_t* cluster_out);
 
+// ---- forced roll-out (rollout.hip)
+// states: (T+1) x r complex, state s at states + 2 r s; beta (r x T, ld ldb) may be null
+// (unforced).
+hipError_t rollout_scan(hipStream_t s, int r, int T, const double* lam, const double* z0, const double* beta,
+                        int64_t ldb, const int32_t* kind, double dt, double* states);
+hipError_t pack_states(hipStream_t s, const double* states, const int32_t* kind, int r, int K, int Kp, int rp,
+                       int mode, void* hi, void* lo);
+
 // ---- adjoint (adjoint.hip)
 hipError_t grad_reduce(hipStream_t s, int r, int ncols, const double* G, const double* lam,
                        const double* b, const int32_t* kind, const double* expo,

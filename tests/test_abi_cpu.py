@@ -250,3 +250,22 @@ def test_edit_modes_validation(L):
     assert L.dmd_edit_modes(None, ctypes.byref(m), ctypes.byref(e), 0, 0x1000, 0x2000, 0) == 1
     m.dt = float("inf")
     assert L.dmd_edit_modes(None, ctypes.byref(m), ctypes.byref(e), 0, 0x1000, 0x2000, 0) == 1
+
+
+def test_rollout_validation(L):
+    """Shape, mode and workspace errors of the forced roll-out, before any GPU work."""
+    m = _model_struct(n=1000, r=10)
+    nb = ctypes.c_size_t(0)
+    assert L.dmd_rollout_workspace_size(1000, 10, 5, 1, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert L.dmd_rollout_workspace_size(1000, 10, 0, 1, ctypes.byref(nb)) == 2
+    assert L.dmd_rollout_workspace_size(1000, 10, 5, 7, ctypes.byref(nb)) == 1
+    need = nb.value
+    big = 1 << 30
+    assert L.dmd_rollout(None, ctypes.byref(m), 0, 0, 1000, 0, 1, 0, 1000, 0, 0x1000, big) == 2      # T = 0
+    assert L.dmd_rollout(None, ctypes.byref(m), 0, 0x100, 999, 5, 1, 0, 1000, 0, 0x1000, big) == 1   # ldf < N
+    assert L.dmd_rollout(None, ctypes.byref(m), 0, 0, 1000, 5, 0, 0x2000, 1000, 0, 0x1000, big) == 1  # FP64 U, FP32 model
+    assert L.dmd_rollout(None, ctypes.byref(m), 0, 0, 1000, 5, 1, 0x2000, 999, 0, 0x1000, big) == 1   # ldu < N
+    assert L.dmd_rollout(None, ctypes.byref(m), 0, 0, 1000, 5, 9, 0, 1000, 0, 0x1000, big) == 1       # mode
+    assert L.dmd_rollout(None, ctypes.byref(m), 0, 0, 1000, 5, 1, 0, 1000, 0, 0x1000, need - 1) == 3  # workspace
+    m.dt = 0.0
+    assert L.dmd_rollout(None, ctypes.byref(m), 0, 0, 1000, 5, 1, 0, 1000, 0, 0x1000, big) == 1

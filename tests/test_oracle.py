@@ -310,7 +310,7 @@ def test_reverse_recovers_earlier_snapshots():
     assert field_errors(U, g.Z[:, T - ks])["max_frame"] <= 1e-9
 
 
-# ------------------------------------------- forced roll-out (Sec. 4.2, DMDc)
+# ------------------------------------------- forced roll-out (Sec. 4.6, DMDc)
 def _paired_vector(rng, kind_like):
     """A complex vector conjugate-paired like a fitted eigenvalue list."""
     v = rng.standard_normal(kind_like.size) + 1j * rng.standard_normal(kind_like.size)
