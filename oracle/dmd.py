@@ -277,6 +277,56 @@ def rollout(phi, lam, z0, F=None, dt=1.0, steps=None):
     return Z, U
 
 
+def upsample_evolve(phi, lam, h0, L, low):
+    """Upsampling evolution of Sec. 6.3.1 (high-res basis, low-res guide).
+
+    R_0 = Phi^+ h0; for t = 1 .. T:  R*_t = Lambda R_{t-1},  P_t = Phi^+ l_t,
+    R_t = S^L P_t + S^H R*_t (low-order modes from the guide, the others evolved),
+    and H_t = Re(Phi R_t).  L (N x T) holds the guide frames l_1 .. l_T on the high-res
+    grid; low (r bools) marks the low-order modes.  Returns (R (T+1, r), H (N, T+1)).
+    """
+    phi = np.asarray(phi, dtype=np.complex128)
+    lam = np.asarray(lam, dtype=np.complex128)
+    low = np.asarray(low, dtype=bool)
+    L = np.asarray(L, dtype=np.float64)
+    T = L.shape[1]
+    R = np.zeros((T + 1, lam.size), dtype=np.complex128)
+    R[0] = project(phi, h0)
+    for t in range(1, T + 1):
+        r_star = lam * R[t - 1]
+        P = project(phi, L[:, t - 1])
+        R[t] = np.where(low, P, r_star)
+    return R, (phi @ R.T).real
+
+
+def block_average_matrix(ncomp, nz, ny, nx, f):
+    """Dense downsampling operator A of Sec. 6.3.2: each coarse cell of each component is
+    the mean of its f x f (x f) fine cells; fields are component-major (c, z, y, x) with x
+    fastest, z not coarsened when nz = 1."""
+    fz = 1 if nz == 1 else f
+    cz, cy, cx = nz // fz, ny // f, nx // f
+    A = np.zeros((ncomp * cz * cy * cx, ncomp * nz * ny * nx))
+    w = 1.0 / (fz * f * f)
+    for c in range(ncomp):
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    row = ((c * cz + z // fz) * cy + y // f) * cx + x // f
+                    col = ((c * nz + z) * ny + y) * nx + x
+                    A[row, col] = w
+    return A
+
+
+def kkt_project(h, l, A):
+    """argmin_x 1/2 ||x - h||^2 subject to A x = l (Sec. 6.3.2), from the KKT system
+    [[I, A^T], [A, 0]] [x; mu] = [h; l]."""
+    h = np.asarray(h, dtype=np.float64)
+    l = np.asarray(l, dtype=np.float64)
+    n, m = h.size, l.size
+    K = np.block([[np.eye(n), A.T], [A, np.zeros((m, m))]])
+    return np.linalg.solve(K, np.concatenate([h, l]))[:n]
+
+
 def project(phi, u):
     """z = Phi^+ u: eq. projection (Sec. 3.1)."""
     return np.linalg.lstsq(np.asarray(phi, dtype=np.complex128),

@@ -386,6 +386,66 @@ def test_rollout_two_mode_by_hand():
     assert np.allclose(U[:, 2], (phi @ z2).real, atol=1e-14)
 
 
+# ------------------------------------------------- upsampling (Sec. 6.3)
+def _upsample_case(seed=102):
+    cfg = synth.config("c1-cf", seed=seed)
+    g = synth.generate(cfg)
+    return oracle.fit_exact(g.Z, cfg.r)
+
+
+def test_upsample_all_high_is_dmd_evolution():
+    f = _upsample_case()
+    rng = np.random.default_rng(6)
+    h0 = rng.standard_normal(f.phi.shape[0])
+    L = rng.standard_normal((f.phi.shape[0], 9))
+    R, H = oracle.upsample_evolve(f.phi, f.lam, h0, L, np.zeros(f.lam.size, bool))
+    z0 = oracle.project(f.phi, h0)
+    assert field_errors(H, oracle.reconstruct(f.phi, f.lam, z0, np.arange(10)))["max_frame"] <= 1e-12
+
+
+def test_upsample_guide_in_span_and_zero_guide():
+    """A guide inside the modes' span is reproduced by the low-order modes; with a zero
+    guide the low-order modes vanish and the others follow Lambda^t."""
+    f = _upsample_case(103)
+    rng = np.random.default_rng(7)
+    T = 6
+    cs = [_paired_vector(rng, f.lam) for _ in range(T + 1)]
+    L = np.stack([(f.phi @ c).real for c in cs[1:]], axis=1)
+    h0 = (f.phi @ cs[0]).real
+    R, H = oracle.upsample_evolve(f.phi, f.lam, h0, L, np.ones(f.lam.size, bool))
+    assert field_errors(H[:, 1:], L)["max_frame"] <= 1e-10
+    low = np.abs(np.angle(f.lam)) < np.median(np.abs(np.angle(f.lam)))
+    R0, H0 = oracle.upsample_evolve(f.phi, f.lam, h0, np.zeros_like(L), low)
+    expect = np.where(low[None, :], 0.0, cs[0][None, :] * f.lam[None, :] ** np.arange(T + 1)[:, None])
+    expect[0] = cs[0]                                        # R_0 = Phi^+ h0 in every mode
+    assert np.max(np.abs(R0 - expect)) <= 1e-10 * np.max(np.abs(expect))
+
+
+def test_block_average_and_kkt_projection():
+    """x = argmin ||x - h|| with A x = l: the constraint holds, x - h is constant over each
+    block (it lies in the range of A^T), a feasible h is kept, and a 4 x 4 case by hand."""
+    rng = np.random.default_rng(8)
+    for (nc, nz, ny, nx, fct) in [(2, 1, 8, 8, 2), (1, 4, 6, 6, 2), (3, 1, 9, 6, 3)]:
+        A = oracle.block_average_matrix(nc, nz, ny, nx, fct)
+        assert np.allclose(A.sum(axis=1), 1.0) and np.allclose(A @ A.T, np.eye(A.shape[0]) * A.max())
+        h = rng.standard_normal(A.shape[1])
+        l = rng.standard_normal(A.shape[0])
+        x = oracle.kkt_project(h, l, A)
+        assert np.max(np.abs(A @ x - l)) <= 1e-12
+        d = x - h                                            # in the range of A^T
+        assert np.max(np.abs(d - A.T @ np.linalg.lstsq(A.T, d, rcond=None)[0])) <= 1e-12
+        assert np.max(np.abs(oracle.kkt_project(x, l, A) - x)) <= 1e-12
+    h = np.arange(16.0)
+    l = np.array([1.0, 2.0, 3.0, 4.0])
+    A = oracle.block_average_matrix(1, 1, 4, 4, 2)
+    x = oracle.kkt_project(h, l, A).reshape(4, 4)
+    H = h.reshape(4, 4)
+    for by in range(2):
+        for bx in range(2):
+            blk = H[2 * by:2 * by + 2, 2 * bx:2 * bx + 2]
+            assert np.allclose(x[2 * by:2 * by + 2, 2 * bx:2 * bx + 2], blk - (blk.mean() - l[2 * by + bx]), atol=1e-12)
+
+
 def test_integrate_matches_integer_steps_and_semigroup():
     """exp(Omega t) at t = k dt equals Lambda^k; exp(Omega(t1+t2)) = exp(Omega t1) exp(Omega t2)."""
     cfg = synth.config("c1-cf", seed=102)
@@ -581,3 +641,15 @@ def _geometric_check(od, expect_pass=True):
     expect = f.lam ** s * f.b + 0.4 * (1 - f.lam ** s) / (1 - f.lam) * c
     ok = np.max(np.abs(Z - expect)) <= 1e-10 * np.max(np.abs(expect))
     assert ok == expect_pass
+
+
+def test_planted_swapped_selection_is_caught(monkeypatch):
+    """Taking the evolved state for the low-order modes (S^L and S^H swapped) must fail the
+    zero-guide pin."""
+    import oracle.dmd as od
+    real = od.upsample_evolve
+    swapped = lambda phi, lam, h0, L, low: real(phi, lam, h0, L, ~np.asarray(low))
+    monkeypatch.setattr(od, "upsample_evolve", swapped)
+    monkeypatch.setattr(oracle, "upsample_evolve", swapped)
+    with pytest.raises(AssertionError):
+        test_upsample_guide_in_span_and_zero_guide()
