@@ -212,7 +212,16 @@ def main():
     forcing = 1e-3 * torch.randn((cfg.K - 1, cfg.N), device="cuda", generator=gen)
     rollout_ms = _events_ms(lambda: dmd.rollout(m, forcing, mode="bf16x3"), reps)
     rollout_bytes = 4 * cfg.N * (cfg.K - 1) + 4 * cfg.N * cfg.K + 2 * 4 * cfg.N * cfg.r
-    del forcing
+    # upsampling (Sec. 6.3): K-1 guide frames, low-order half of the modes from the guide;
+    # the guide buffer is reused for the constrained projection of the K-1 frames
+    low = np.zeros(m.r, dtype=bool)
+    low[: m.r // 2] = True
+    upsample_ms = _events_ms(lambda: dmd.upsample(m, Z[0], forcing, low, mode="bf16x3"), reps)
+    grid, fct = (2, 1, 256, 256), 4
+    coarse = torch.randn((cfg.K - 1, cfg.N // fct ** 2), device="cuda", generator=gen)
+    lowres_ms = _events_ms(lambda: dmd.lowres_project(forcing, coarse, grid, fct, out=forcing), reps)
+    lowres_bytes = 2 * 4 * cfg.N * (cfg.K - 1) + 4 * (cfg.N // fct ** 2) * (cfg.K - 1)
+    del forcing, coarse
 
     fp64 = None
     if not args.no_fp64:
@@ -287,7 +296,13 @@ def main():
                     "rollout_ms": round(rollout_ms, 4),
                     "rollout_gb_s": round(rollout_bytes / (rollout_ms * 1e-3) / 1e9, 1),
                     "rollout": "999 forced steps (N x 999 FP32 forcing projected on the modes) and 1000 "
-                               "bf16x3 frames"},
+                               "bf16x3 frames",
+                    "upsample_ms": round(upsample_ms, 4),
+                    "upsample": "999 guide frames projected, 75 low-order modes from the guide, 75 evolved, "
+                                "1000 bf16x3 frames",
+                    "lowres_project_ms": round(lowres_ms, 4),
+                    "lowres_project_gb_s": round(lowres_bytes / (lowres_ms * 1e-3) / 1e9, 1),
+                    "lowres_project": "999 frames of the 2x256x256 grid onto 4x4 block averages, in place"},
         "fp64": fp64,
         "accuracy": accuracy,
         "paper_context": {"precompute_s": 79.0, "subspace_step_us": 8.9,

@@ -300,6 +300,47 @@ int32_t dmd_rollout(void* stream, const dmd_model* model, const double* z0, cons
                     int64_t ldf, int32_t T, int32_t mode, void* U, int64_t ldu, double* z_out,
                     void* ws, size_t ws_bytes);
 
+/* Workspace bytes for dmd_upsample of T guide frames. */
+int32_t dmd_upsample_workspace_size(int64_t n, int32_t r, int32_t T, int32_t mode, size_t* bytes);
+
+/*
+ * Upsampling evolution (Sec. 6.3.1): a high-res model adds its high-order modes to a
+ * low-res guide.  R_0 = Phi^+ h0; for t = 1 .. T, R*_t = Lambda R_{t-1},
+ * P_t = Phi^+ l_t and R_t = S^L P_t + S^H R*_t (low-order modes from the guide, the
+ * others evolved, i.e. lambda^t R_0); frames H_t = Re(Phi R_t), t = 0 .. T.
+ *   h0        device, N values (model dtype): the high-res initial field
+ *   l         device, N x T column-major (ldl >= N): guide frames l_1 .. l_T on the
+ *             high-res grid (the caller prolongs the low-res frames)
+ *   low_host  host, r int32 flags, non-zero = low-order mode (taken from the guide); a
+ *             conjugate pair follows its first member's flag
+ *   mode, U, ldu   frames as for dmd_rollout (U may be NULL)
+ *   r_out     device, (T+1) x r complex states, or NULL
+ * Projections as in dmd_rollout (FP64 Gram and Cholesky inverse, MFMA products).
+ * Errors: DMD_ERR_SHAPE for T < 1; DMD_ERR_ARG for missing h0 / l / low_host,
+ * ldl < N, a bad mode or U mismatch; DMD_ERR_WORKSPACE.
+ */
+int32_t dmd_upsample(void* stream, const dmd_model* model, const void* h0, const void* l,
+                     int64_t ldl, int32_t T, const int32_t* low_host, int32_t mode, void* U,
+                     int64_t ldu, double* r_out, void* ws, size_t ws_bytes);
+
+/*
+ * Projection onto the fields that match a low-res guide (Sec. 6.3.2):
+ *   x = argmin ||x - h||^2  subject to  A x = l,
+ * A = average over factor x factor (x factor) blocks of a regular grid, per component.
+ * A A^T = factor^-d I, so the KKT solution is x = h - A^T factor^d (A h - l): every fine
+ * cell moves by its block's mean mismatch.  One pass over h, l and x.
+ *   dtype        DMD_F32 or DMD_F64 (h, l, x)
+ *   h, x         device, nframes frames of N = ncomp * nz * ny * nx values, component-major
+ *                (c, z, y, x) with x fastest, frame f at h + f ldh (ldh, ldx >= N); x may be h
+ *   l            device, nframes coarse frames of ncomp * (nz/fz) * (ny/factor) * (nx/factor)
+ *                values in the same order, ld ldl; fz = factor, or 1 when nz = 1 (2D)
+ * Errors: DMD_ERR_SHAPE for non-positive sizes or dimensions not divisible by factor,
+ * DMD_ERR_ARG for a bad dtype, null pointer or short leading dimension.
+ */
+int32_t dmd_lowres_project(void* stream, int32_t dtype, const void* h, int64_t ldh, const void* l,
+                           int64_t ldl, void* x, int64_t ldx, int64_t nframes, int32_t ncomp,
+                           int32_t nz, int32_t ny, int32_t nx, int32_t factor);
+
 /* Workspace bytes for dmd_loss_grad. */
 int32_t dmd_loss_grad_workspace_size(int64_t n, int32_t r, int32_t ncols, int32_t dtype,
                                      size_t* bytes);

@@ -79,6 +79,11 @@ _SIGS = {
     "dmd_rollout_workspace_size": (c_int32, [c_int64, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
     "dmd_rollout": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_void_p, c_void_p, c_int64, c_int32, c_int32,
                               c_void_p, c_int64, c_void_p, c_void_p, c_size_t]),
+    "dmd_upsample_workspace_size": (c_int32, [c_int64, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
+    "dmd_upsample": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_void_p, c_void_p, c_int64, c_int32,
+                               ctypes.POINTER(c_int32), c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_size_t]),
+    "dmd_lowres_project": (c_int32, [c_void_p, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_void_p, c_int64,
+                                     c_int64, c_int32, c_int32, c_int32, c_int32, c_int32]),
     "dmd_project_workspace_size": (c_int32, [c_int64, c_int32, ctypes.POINTER(c_size_t)]),
     "dmd_project": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_void_p, c_void_p, c_void_p, c_size_t]),
     "dmd_loss_grad_workspace_size": (c_int32, [c_int64, c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)]),

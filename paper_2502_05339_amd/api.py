@@ -413,6 +413,65 @@ def rollout(model: Model, forcing: torch.Tensor | None = None, steps: int | None
     return states, U
 
 
+def upsample(model: Model, h0: torch.Tensor, guide: torch.Tensor, low, mode: str | None = None,
+             frames: bool = True):
+    """Upsampling evolution (Sec. 6.3.1): R_0 = Phi^+ h0, R_t = S^L Phi^+ l_t + S^H Lambda R_{t-1}.
+
+    h0: (N,) high-res initial field; guide: (T, N) guide frames l_1 .. l_T on the high-res
+    grid (model dtype); low: r booleans, True for the low-order modes taken from the guide.
+    Returns (states (T+1, r) complex128, frames (T+1, N) or None), frame t = Re(Phi R_t).
+    """
+    _require_gpu(model.phi, "model.phi")
+    for t, name in ((h0, "h0"), (guide, "guide")):
+        _require_gpu(t, name)
+        if t.dtype != model.phi.dtype or t.stride(-1) != 1:
+            raise ValueError(f"{name} must have the model's dtype and unit stride along N")
+    if h0.numel() != model.n or guide.dim() != 2 or guide.shape[1] != model.n:
+        raise ValueError("h0 must hold N values and guide must be (T, N)")
+    flags = np.ascontiguousarray(np.asarray(low, dtype=bool).astype(np.int32).ravel())
+    if flags.size != model.r:
+        raise ValueError("low must hold one flag per mode")
+    T = guide.shape[0]
+    mcode = RECON_MODES[mode or _default_mode(model)]
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    check(L.dmd_upsample_workspace_size(model.n, model.r, T, mcode, ctypes.byref(nb)), "dmd_upsample_workspace_size")
+    ws = _workspace(nb.value, model.phi.device)
+    states = torch.empty((T + 1, model.r), dtype=torch.complex128, device=model.phi.device)
+    U = None
+    if frames:
+        odt = torch.float64 if mcode == RECON_FP64 else torch.float32
+        U = torch.empty((T + 1, model.n), dtype=odt, device=model.phi.device)
+    ms = model.struct()
+    check(L.dmd_upsample(_stream(), ctypes.byref(ms), h0.data_ptr(), guide.data_ptr(), guide.stride(0), T,
+                         flags.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), mcode, _ptr(U),
+                         U.stride(0) if U is not None else model.n, states.data_ptr(), ws.data_ptr(), ws.numel()),
+          "dmd_upsample")
+    return states, U
+
+
+def lowres_project(h: torch.Tensor, l: torch.Tensor, grid, factor: int, out: torch.Tensor | None = None):
+    """Projection of Sec. 6.3.2: the fields closest to h whose block averages equal l.
+
+    h: (F, N) or (N,) fine frames on grid = (ncomp, nz, ny, nx) (component-major, x fastest;
+    nz = 1 for 2D); l: the coarse frames, (F, M) or (M,); factor: block size per axis.
+    out may be h (in place).  Returns out.
+    """
+    _require_gpu(h, "h")
+    _require_gpu(l, "l")
+    ncomp, nz, ny, nx = (int(v) for v in grid)
+    h2 = h.reshape(-1, h.shape[-1])
+    l2 = l.reshape(-1, l.shape[-1])
+    if h2.stride(-1) != 1 or l2.stride(-1) != 1 or l.dtype != h.dtype or h2.shape[0] != l2.shape[0]:
+        raise ValueError("h and l must share dtype and frame count, with unit stride along the grid")
+    x = torch.empty_like(h2) if out is None else out.reshape(-1, h.shape[-1])
+    dcode = DMD_F64 if h.dtype == torch.float64 else DMD_F32
+    check(_lib.lib().dmd_lowres_project(_stream(), dcode, h2.data_ptr(), h2.stride(0), l2.data_ptr(), l2.stride(0),
+                                         x.data_ptr(), x.stride(0), h2.shape[0], ncomp, nz, ny, nx, int(factor)),
+          "dmd_lowres_project")
+    return x.reshape(h.shape)
+
+
 def project(model: Model, u: torch.Tensor) -> torch.Tensor:
     """z = Phi^+ u (Sec. 3.1, eq. projection); returns (r,) complex128 on the device."""
     _require_gpu(u, "u")

@@ -456,6 +456,70 @@ RollPlan roll_carve(Carver& cv, int64_t n, int r, int T, int mode)
     return p;
 }
 
+// beta (r x T, ld r) = least-squares coefficients of the folded basis for the T columns of
+// F (N x T, ld ldf): FP64 Gram of Phi and its Cholesky inverse, Phi^T F as split-N MFMA
+// products in chunks of ROLL_TC columns, then R^-1 R^-T (Phi^T F).  The result lands in
+// p.rhs; p.tmp is scratch.
+hipError_t project_columns(hipStream_t st, const dmd_model* m, const void* F, int64_t ldf, int T, const RollPlan& p,
+                           bool have_rinv)
+{
+    const int r = m->r;
+    const int64_t n = m->n;
+    const size_t esz = m->dtype == DMD_F64 ? 8 : 4;
+    hipError_t e;
+    if (!have_rinv) {
+        if ((e = gemm_tn(st, m->dtype, DMD_F64, m->phi, m->ldphi, 1, r, m->phi, m->ldphi, 1, r, 1, n, p.P, p.PhiG, r,
+                         nullptr, 0, nullptr)) != hipSuccess) return e;
+        if ((e = fill_i32(st, p.scratch, 16, 0)) != hipSuccess) return e;
+        if ((e = chol_inv(st, p.PhiG, r, r, p.Rinv, r, nullptr, 0, 0.0, nullptr, p.scratch, nullptr)) != hipSuccess)
+            return e;
+    }
+    for (int c0 = 0; c0 < T; c0 += ROLL_TC) {
+        const int nc = std::min(ROLL_TC, T - c0);
+        const void* fc = (const char*)F + (size_t)c0 * (size_t)ldf * esz;
+        // FP32 models: FP32 MFMA products, split-N partials summed in FP64 (as the fit's X^T Q)
+        if ((e = gemm_tn(st, m->dtype, m->dtype, m->phi, m->ldphi, 1, r, fc, ldf, 0, nc, 0, n, p.P,
+                         p.rhs + (size_t)c0 * r, r, nullptr, 0, nullptr)) != hipSuccess) return e;
+    }
+    if ((e = small_gemm(st, 1, 0, r, T, r, 1.0, p.Rinv, r, p.rhs, r, 0.0, p.tmp, r)) != hipSuccess) return e;
+    return small_gemm(st, 0, 0, r, T, r, 1.0, p.Rinv, r, p.tmp, r, 0.0, p.rhs, r);
+}
+
+struct UpPlan {
+    RollPlan rp;
+    double* beta0;    // r: coefficients of h0
+    double* tmp0;     // r
+    int32_t* low;     // r flags
+};
+
+UpPlan up_carve(Carver& cv, int64_t n, int r, int T, int mode)
+{
+    UpPlan u;
+    u.rp = roll_carve(cv, n, r, T, mode);
+    u.beta0 = cv.take<double>((size_t)r);
+    u.tmp0 = cv.take<double>((size_t)r);
+    u.low = cv.take<int32_t>((size_t)r);
+    return u;
+}
+
+// frames Re(Phi z_s), s = 0 .. K-1, from K reduced states
+hipError_t frames_from_states(hipStream_t st, const dmd_model* m, const double* states, int K, int mode,
+                              const ReconPlan& rec, void* U, int64_t ldu)
+{
+    const int rp = (int)dmd_phi_ld(m->r);
+    const int Kp = (int)round_up(K, RECON_KPAD);
+    hipError_t e = pack_states(st, states, m->kind, m->r, K, Kp, rp, mode, rec.chi, rec.clo);
+    if (e != hipSuccess) return e;
+    ReconArgs ra{};
+    ra.mode = mode;
+    ra.phi = m->phi; ra.ldphi = m->ldphi; ra.N = m->n; ra.rp = rp;
+    ra.c_hi = rec.chi; ra.c_lo = rec.clo; ra.K = K;
+    ra.U = U; ra.ldu = ldu;
+    const int vw = mode == DMD_RECON_FP64 ? 2 : 4;
+    ra.vec_store = (ldu % vw == 0) && aligned16(U);
+    return recon_launch(st, ra, tune_lookup(mode, rp, m->n, K));
+}
+
 }  // namespace
 
 // ====================================================================== extern "C"
@@ -668,38 +732,69 @@ int32_t dmd_rollout(void* stream, const dmd_model* model, const double* z0, cons
     double* states = z_out ? z_out : p.states;
     const double* beta = nullptr;
     if (f) {
-        // g_s = Phi^+ f_s for every step: FP64 normal equations through the Gram of Phi
-        const size_t esz = model->dtype == DMD_F64 ? 8 : 4;
-        HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, model->phi, model->ldphi, 1, r, 1,
-                       n, p.P, p.PhiG, r, nullptr, 0, nullptr));
-        HIPCHK(fill_i32(st, p.scratch, 16, 0));
-        HIPCHK(chol_inv(st, p.PhiG, r, r, p.Rinv, r, nullptr, 0, 0.0, nullptr, p.scratch, nullptr));
-        for (int c0 = 0; c0 < T; c0 += ROLL_TC) {
-            const int nc = std::min(ROLL_TC, T - c0);
-            const void* fc = (const char*)f + (size_t)c0 * (size_t)ldf * esz;
-            // FP32 models: FP32 MFMA products, split-N partials summed in FP64 (as the fit's X^T Q)
-            HIPCHK(gemm_tn(st, model->dtype, model->dtype, model->phi, model->ldphi, 1, r, fc, ldf, 0, nc, 0, n,
-                           p.P, p.rhs + (size_t)c0 * r, r, nullptr, 0, nullptr));
-        }
-        HIPCHK(small_gemm(st, 1, 0, r, T, r, 1.0, p.Rinv, r, p.rhs, r, 0.0, p.tmp, r));   // R^-T (Phi^T F)
-        HIPCHK(small_gemm(st, 0, 0, r, T, r, 1.0, p.Rinv, r, p.tmp, r, 0.0, p.rhs, r));   // beta = R^-1 (...)
+        HIPCHK(project_columns(st, model, f, ldf, T, p, false));   // g_s = Phi^+ f_s, every step
         beta = p.rhs;
     }
     HIPCHK(rollout_scan(st, r, T, model->lam, z0 ? z0 : model->b, beta, r, model->kind, model->dt, states));
-    if (U) {
-        const int rp = (int)dmd_phi_ld(r);
-        const int K = T + 1;
-        const int Kp = (int)round_up(K, RECON_KPAD);
-        HIPCHK(pack_states(st, states, model->kind, r, K, Kp, rp, mode, p.rec.chi, p.rec.clo));
-        ReconArgs ra{};
-        ra.mode = mode;
-        ra.phi = model->phi; ra.ldphi = model->ldphi; ra.N = n; ra.rp = rp;
-        ra.c_hi = p.rec.chi; ra.c_lo = p.rec.clo; ra.K = K;
-        ra.U = U; ra.ldu = ldu;
-        const int vw = mode == DMD_RECON_FP64 ? 2 : 4;
-        ra.vec_store = (ldu % vw == 0) && aligned16(U);
-        HIPCHK(recon_launch(st, ra, tune_lookup(mode, rp, n, K)));
-    }
+    if (U) HIPCHK(frames_from_states(st, model, states, T + 1, mode, p.rec, U, ldu));
+    return DMD_OK;
+}
+
+int32_t dmd_upsample_workspace_size(int64_t n, int32_t r, int32_t T, int32_t mode, size_t* bytes)
+{
+    if (!bytes) return DMD_ERR_ARG;
+    if (n < 1 || r < 1 || T < 1) return DMD_ERR_SHAPE;
+    if (mode < DMD_RECON_FP64 || mode > DMD_RECON_BF16X3) return DMD_ERR_ARG;
+    Carver c(nullptr);
+    up_carve(c, n, r, T, mode);
+    *bytes = c.bytes();
+    return DMD_OK;
+}
+
+int32_t dmd_upsample(void* stream, const dmd_model* model, const void* h0, const void* l, int64_t ldl, int32_t T,
+                     const int32_t* low_host, int32_t mode, void* U, int64_t ldu, double* r_out, void* ws,
+                     size_t ws_bytes)
+{
+    if (int32_t e = validate_model(model)) return e;
+    if (T < 1) return DMD_ERR_SHAPE;
+    if (!h0 || !l || !low_host || ldl < model->n) return DMD_ERR_ARG;
+    if (mode < DMD_RECON_FP64 || mode > DMD_RECON_BF16X3) return DMD_ERR_ARG;
+    if (U && ((mode == DMD_RECON_FP64) != (model->dtype == DMD_F64) || ldu < model->n)) return DMD_ERR_ARG;
+    size_t need = 0;
+    if (int32_t e = dmd_upsample_workspace_size(model->n, model->r, T, mode, &need)) return e;
+    if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    if (int32_t e0 = ensure_init()) return e0;
+    hipStream_t st = (hipStream_t)stream;
+    const int r = model->r;
+    Carver cv(ws);
+    UpPlan u = up_carve(cv, model->n, r, T, mode);
+    RollPlan p0 = u.rp;                 // h0 uses the same Gram and inverse, its own coefficients
+    p0.rhs = u.beta0;
+    p0.tmp = u.tmp0;
+    HIPCHK(project_columns(st, model, h0, model->n, 1, p0, false));
+    HIPCHK(project_columns(st, model, l, ldl, T, u.rp, true));
+    HIPCHK(hipMemcpyAsync(u.low, low_host, (size_t)r * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    double* states = r_out ? r_out : u.rp.states;
+    HIPCHK(upsample_states(st, r, T, model->lam, u.beta0, u.rp.rhs, r, model->kind, u.low, states));
+    if (U) HIPCHK(frames_from_states(st, model, states, T + 1, mode, u.rp.rec, U, ldu));
+    return DMD_OK;
+}
+
+int32_t dmd_lowres_project(void* stream, int32_t dtype, const void* h, int64_t ldh, const void* l, int64_t ldl,
+                           void* x, int64_t ldx, int64_t nframes, int32_t ncomp, int32_t nz, int32_t ny, int32_t nx,
+                           int32_t factor)
+{
+    if (dtype != DMD_F32 && dtype != DMD_F64) return DMD_ERR_ARG;
+    if (!h || !l || !x) return DMD_ERR_ARG;
+    if (nframes < 0 || ncomp < 1 || nz < 1 || ny < 1 || nx < 1 || factor < 1) return DMD_ERR_SHAPE;
+    if (ny % factor || nx % factor || (nz > 1 && nz % factor)) return DMD_ERR_SHAPE;
+    const int fz = nz == 1 ? 1 : factor;
+    const int64_t nfine = (int64_t)ncomp * nz * ny * nx;
+    const int64_t ncoarse = (int64_t)ncomp * (nz / fz) * (ny / factor) * (nx / factor);
+    if (ldh < nfine || ldx < nfine || ldl < ncoarse) return DMD_ERR_ARG;
+    if (nframes == 0) return DMD_OK;
+    if (int32_t e0 = ensure_init()) return e0;
+    HIPCHK(lowres_project((hipStream_t)stream, dtype, h, ldh, l, ldl, x, ldx, nframes, ncomp, nz, ny, nx, factor));
     return DMD_OK;
 }
 

@@ -116,6 +116,12 @@ hipError_t rollout_scan(hipStream_t s, int r, int T, const double* lam, const do
 hipError_t pack_states(hipStream_t s, const double* states, const int32_t* kind, int r, int K, int Kp, int rp,
                        int mode, void* hi, void* lo);
 
+// ---- upsampling (upsample.hip)
+hipError_t upsample_states(hipStream_t s, int r, int T, const double* lam, const double* beta0, const double* beta,
+                           int64_t ldb, const int32_t* kind, const int32_t* low, double* states);
+hipError_t lowres_project(hipStream_t s, int dtype, const void* h, int64_t ldh, const void* l, int64_t ldl, void* x,
+                          int64_t ldx, int64_t nframes, int ncomp, int nz, int ny, int nx, int f);
+
 // ---- adjoint (adjoint.hip)
 hipError_t grad_reduce(hipStream_t s, int r, int ncols, const double* G, const double* lam,
                        const double* b, const int32_t* kind, const double* expo,

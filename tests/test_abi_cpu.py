@@ -269,3 +269,26 @@ def test_rollout_validation(L):
     assert L.dmd_rollout(None, ctypes.byref(m), 0, 0, 1000, 5, 1, 0, 1000, 0, 0x1000, need - 1) == 3  # workspace
     m.dt = 0.0
     assert L.dmd_rollout(None, ctypes.byref(m), 0, 0, 1000, 5, 1, 0, 1000, 0, 0x1000, big) == 1
+
+
+def test_upsample_and_lowres_validation(L):
+    m = _model_struct(n=1000, r=10)
+    nb = ctypes.c_size_t(0)
+    assert L.dmd_upsample_workspace_size(1000, 10, 4, 1, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert L.dmd_upsample_workspace_size(1000, 10, 0, 1, ctypes.byref(nb)) == 2
+    flags = (ctypes.c_int32 * 10)()
+    big = 1 << 30
+    assert L.dmd_upsample(None, ctypes.byref(m), 0, 0x100, 1000, 4, flags, 1, 0, 1000, 0, 0x1000, big) == 1   # h0
+    assert L.dmd_upsample(None, ctypes.byref(m), 0x100, 0x200, 999, 4, flags, 1, 0, 1000, 0, 0x1000, big) == 1
+    assert L.dmd_upsample(None, ctypes.byref(m), 0x100, 0x200, 1000, 4, None, 1, 0, 1000, 0, 0x1000, big) == 1
+    assert L.dmd_upsample(None, ctypes.byref(m), 0x100, 0x200, 1000, 0, flags, 1, 0, 1000, 0, 0x1000, big) == 2
+    assert L.dmd_upsample(None, ctypes.byref(m), 0x100, 0x200, 1000, 4, flags, 1, 0, 1000, 0, 0x1000, 16) == 3
+    # low-res projection: shapes, dtype, leading dimensions
+    P = L.dmd_lowres_project
+    assert P(None, 0, 0x100, 200, 0x200, 50, 0x300, 200, 1, 2, 1, 10, 10, 3) == 2           # 10 % 3
+    assert P(None, 0, 0x100, 200, 0x200, 50, 0x300, 200, 1, 2, 4, 10, 10, 3) == 2
+    assert P(None, 5, 0x100, 200, 0x200, 50, 0x300, 200, 1, 2, 1, 10, 10, 2) == 1           # dtype
+    assert P(None, 0, 0x100, 199, 0x200, 50, 0x300, 200, 1, 2, 1, 10, 10, 2) == 1           # ldh < N
+    assert P(None, 0, 0x100, 200, 0x200, 49, 0x300, 200, 1, 2, 1, 10, 10, 2) == 1           # ldl < M
+    assert P(None, 0, 0x100, 200, 0x200, 50, 0, 200, 1, 2, 1, 10, 10, 2) == 1               # null x
+    assert P(None, 0, 0x100, 200, 0x200, 50, 0x300, 200, 0, 2, 1, 10, 10, 2) == 0           # no frames: no-op
