@@ -267,28 +267,28 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
               double* Vout, int32_t* info, double rtol)
 {
     extern __shared__ __align__(16) double sm[];
-    const int n2 = n + (n & 1);
+    const int n2 = n + (n & 1);          // odd n: a zero row and column n complete the pairs
     const int np = n2 / 2;
     const int m = n2 - 1;
-    double* A = sm;                                               // n(n+1)/2 (rounded to even)
-    double* Vs = A + round_up(n * (n + 1) / 2, 2);                // nr x n (rounded to even)
-    double2* rcs = reinterpret_cast<double2*>(Vs + round_up(nr * n, 2));   // np: (c, s)
+    double* A = sm;                                               // n2(n2+1)/2 (rounded to even)
+    double* Vs = A + round_up(n2 * (n2 + 1) / 2, 2);              // nr x n2 (rounded to even)
+    double2* rcs = reinterpret_cast<double2*>(Vs + round_up(nr * n2, 2));   // np: (c, s)
     double* tn = reinterpret_cast<double*>(rcs + np);             // np
-    int2* rpq = reinterpret_cast<int2*>(tn + round_up(np, 2));    // np: (p, q)
+    int4* rpq = reinterpret_cast<int4*>(tn + round_up(np, 2));    // np: (p, q, p(p+1)/2, q(q+1)/2)
     int* rank = reinterpret_cast<int*>(rpq + np);                 // n
-    __shared__ int rot_count;
+    __shared__ int rot_flag;
     __shared__ double dmax_s;
 
     const int tid = threadIdx.x, nt = blockDim.x;
     const int r0 = blockIdx.x * nr;
     const int nrows = min(nr, n - r0);
 
-    for (int e = tid; e < n * n; e += nt) {
-        const int i = e % n, j = e / n;
-        if (i <= j) A[up_idx(i, j)] = S[(int64_t)j * lds + i];
+    for (int e = tid; e < n2 * n2; e += nt) {
+        const int i = e % n2, j = e / n2;
+        if (i <= j) A[up_idx(i, j)] = j < n ? S[(int64_t)j * lds + i] : 0.0;
     }
-    for (int e = tid; e < nr * n; e += nt) {
-        const int rl = e / n, c = e % n;
+    for (int e = tid; e < nr * n2; e += nt) {
+        const int rl = e / n2, c = e % n2;
         Vs[e] = (rl < nrows && r0 + rl == c) ? 1.0 : 0.0;
     }
     // this thread's pairs of pairs (k1 <= k2), fixed for every round
@@ -323,90 +323,84 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
     int sweep = 0;
     bool converged = false;
     for (; sweep < 40; ++sweep) {
-        if (tid == 0) rot_count = 0;
+        if (tid == 0) rot_flag = 0;
         __syncthreads();
         for (int t = 0; t < m; ++t) {
             for (int k = tid; k < np; k += nt) {
                 int p, q;
                 rr_pair(k, t, m, &p, &q);
                 double c = 1.0, s = 0.0, tt = 0.0;
-                if (q < n) {
-                    const double apq = A[up_idx(p, q)];
-                    const double app = A[up_idx(p, p)], aqq = A[up_idx(q, q)];
-                    if (fabs(apq) > floor_abs && fabs(apq) > rtol * sqrt(fabs(app) * fabs(aqq))) {
-                        // tan(theta) of the rotation that zeroes a_pq, the smaller root; |tau| stays
-                        // below about 1e17 because |a_pq| > floor_abs
-                        const double tau = (aqq - app) * rcp_nr(2.0 * apq);
-                        const double u = fma(tau, tau, 1.0);
-                        const double root = u * rsqrt_nr(u);                  // sqrt(1 + tau^2)
-                        tt = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + root);
-                        c = rsqrt_nr(fma(tt, tt, 1.0));
-                        s = tt * c;
-                        atomicAdd(&rot_count, 1);
-                    }
+                const double apq = A[up_idx(p, q)];
+                const double app = A[up_idx(p, p)], aqq = A[up_idx(q, q)];
+                if (fabs(apq) > floor_abs && fabs(apq) > rtol * sqrt(fabs(app) * fabs(aqq))) {
+                    // tan(theta) of the rotation that zeroes a_pq, the smaller root; |tau| stays
+                    // below about 1e17 because |a_pq| > floor_abs
+                    const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+                    const double u = fma(tau, tau, 1.0);
+                    const double root = u * rsqrt_nr(u);                  // sqrt(1 + tau^2)
+                    tt = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + root);
+                    c = rsqrt_nr(fma(tt, tt, 1.0));
+                    s = tt * c;
+                    rot_flag = 1;                                         // every writer stores 1
                 }
-                rpq[k] = make_int2(p, q);
+                rpq[k] = make_int4(p, q, p * (p + 1) / 2, q * (q + 1) / 2);
                 rcs[k] = make_double2(c, s);
                 tn[k] = tt;
             }
             __syncthreads();
-            // 2x2 blocks of every pair of pairs: B' = J1^T B J2 (independent, disjoint entries)
+            // 2x2 blocks of every pair of pairs: B' = J1^T B J2 (independent, disjoint entries).
+            // Packed index of (a, b): a <= b ? b(b+1)/2 + a : a(a+1)/2 + b, from the pair records.
 #pragma unroll
             for (int u = 0; u < JAC_BLK; ++u) {
                 const int k2 = bk2[u];
                 if (k2 < 0) continue;
                 const int k1 = bk1[u];
-                const int2 pq1 = rpq[k1];
-                const int p1 = pq1.x, q1 = pq1.y;
+                // every record first (one LDS round trip), then the branches
+                const int4 P1 = rpq[k1], P2 = rpq[k2];
+                const double2 cs1 = rcs[k1], cs2 = rcs[k2];
                 if (k1 == k2) {
                     const double t1 = tn[k1];
-                    if (t1 == 0.0 || q1 >= n) continue;
-                    const double apq = A[up_idx(p1, q1)];
-                    A[up_idx(p1, p1)] -= t1 * apq;
-                    A[up_idx(q1, q1)] += t1 * apq;
-                    A[up_idx(p1, q1)] = 0.0;
+                    if (t1 == 0.0) continue;
+                    const int ipq = P1.w + P1.x;
+                    const double apq = A[ipq];
+                    A[P1.z + P1.x] -= t1 * apq;
+                    A[P1.w + P1.y] += t1 * apq;
+                    A[ipq] = 0.0;
                     continue;
                 }
-                const int2 pq2 = rpq[k2];
-                const int p2 = pq2.x, q2 = pq2.y;
-                const bool r1 = q1 < n, r2 = q2 < n;
-                const double2 cs1 = rcs[k1], cs2 = rcs[k2];
-                const double c1 = r1 ? cs1.x : 1.0, s1 = r1 ? cs1.y : 0.0;
-                const double c2 = r2 ? cs2.x : 1.0, s2 = r2 ? cs2.y : 0.0;
-                if (s1 == 0.0 && s2 == 0.0) continue;
-                const int i00 = sym_idx(p1, p2);
-                const int i10 = sym_idx(q1 < n ? q1 : p1, p2);
-                const int i01 = sym_idx(p1, q2 < n ? q2 : p2);
-                const int i11 = sym_idx(q1 < n ? q1 : p1, q2 < n ? q2 : p2);
-                const double b00 = A[i00];
-                const double b01 = r2 ? A[i01] : 0.0;
-                const double b10 = r1 ? A[i10] : 0.0;
-                const double b11 = (r1 && r2) ? A[i11] : 0.0;
+                if (cs1.y == 0.0 && cs2.y == 0.0) continue;            // both rotations skipped
+                const int i00 = P1.x <= P2.x ? P2.z + P1.x : P1.z + P2.x;
+                const int i01 = P1.x <= P2.y ? P2.w + P1.x : P1.z + P2.y;
+                const int i10 = P1.y <= P2.x ? P2.z + P1.y : P1.w + P2.x;
+                const int i11 = P1.y <= P2.y ? P2.w + P1.y : P1.w + P2.y;
+                const double b00 = A[i00], b01 = A[i01], b10 = A[i10], b11 = A[i11];
+                const double c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
                 const double x00 = c2 * b00 - s2 * b01, x01 = s2 * b00 + c2 * b01;
                 const double x10 = c2 * b10 - s2 * b11, x11 = s2 * b10 + c2 * b11;
                 A[i00] = c1 * x00 - s1 * x10;
-                if (r2) A[i01] = c1 * x01 - s1 * x11;
-                if (r1) A[i10] = s1 * x00 + c1 * x10;
-                if (r1 && r2) A[i11] = s1 * x01 + c1 * x11;
+                A[i01] = c1 * x01 - s1 * x11;
+                A[i10] = s1 * x00 + c1 * x10;
+                A[i11] = s1 * x01 + c1 * x11;
             }
             // eigenvector rows owned by this work-group: V <- V J
 #pragma unroll
             for (int u = 0; u < JAC_VT; ++u) {
                 const int rl = vt_rl[u], k = vt_k[u];
                 if (rl >= nrows) continue;
-                const int2 pq = rpq[k];
-                if (pq.y >= n || tn[k] == 0.0) continue;
                 const double2 cs = rcs[k];
-                const double vp = Vs[rl * n + pq.x], vq = Vs[rl * n + pq.y];
-                Vs[rl * n + pq.x] = cs.x * vp - cs.y * vq;
-                Vs[rl * n + pq.y] = cs.y * vp + cs.x * vq;
+                if (cs.y == 0.0) continue;
+                const int4 pq = rpq[k];
+                double* vr = Vs + rl * n2;
+                const double vp = vr[pq.x], vq = vr[pq.y];
+                vr[pq.x] = cs.x * vp - cs.y * vq;
+                vr[pq.y] = cs.y * vp + cs.x * vq;
             }
             __syncthreads();
         }
-        if (rot_count == 0) { converged = true; break; }
+        if (rot_flag == 0) { converged = true; break; }
         __syncthreads();
     }
-    // order: descending eigenvalue, ties by index (NaN last)
+    // order: descending eigenvalue, ties by index (NaN last); the padding row is not an eigenvalue
     for (int i = tid; i < n; i += nt) {
         const double di = A[up_idx(i, i)];
         const double ki = isnan(di) ? -__builtin_inf() : di;
@@ -421,7 +415,7 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
     __syncthreads();
     for (int e = tid; e < nrows * n; e += nt) {
         const int rl = e / n, i = e % n;
-        Vout[(int64_t)rank[i] * n + r0 + rl] = Vs[rl * n + i];
+        Vout[(int64_t)rank[i] * n + r0 + rl] = Vs[rl * n2 + i];
     }
     if (blockIdx.x == 0) {
         for (int i = tid; i < n; i += nt) evals[rank[i]] = A[up_idx(i, i)];
@@ -438,16 +432,17 @@ hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* e
     if (n <= 0) return hipSuccess;
     if (n > SMALL_MAX) return hipErrorInvalidValue;
     const int n2 = n + (n & 1), np = n2 / 2;
-    // A (rounded to even), (c, s), t (rounded to even), (p, q), the ranks; V rows rounded to even
-    const size_t fixed = (size_t)round_up((int64_t)n * (n + 1) / 2, 2) * 8 + (size_t)np * 16 +
-                         (size_t)round_up(np, 2) * 8 + (size_t)np * 8 + (size_t)n * 4 + 16;
+    // A (n2 x n2 packed, rounded to even), (c, s), t (rounded to even), pair records
+    // (int4), the ranks; V rows of n2 entries, rounded to even
+    const size_t fixed = (size_t)round_up((int64_t)n2 * (n2 + 1) / 2, 2) * 8 + (size_t)np * 16 +
+                         (size_t)round_up(np, 2) * 8 + (size_t)np * 16 + (size_t)n * 4 + 16;
     const size_t budget = 160 * 1024 - 1024;   // the kernel's LDS attribute (static LDS is 16 bytes)
-    if (fixed + (size_t)n * 8 + 8 > budget) return hipErrorInvalidValue;
-    int nr = (int)((budget - fixed - 8) / ((size_t)n * 8));
+    if (fixed + (size_t)n2 * 8 + 8 > budget) return hipErrorInvalidValue;
+    int nr = (int)((budget - fixed - 8) / ((size_t)n2 * 8));
     if (nr > 32) nr = 32;
     if (nr > n) nr = n;
     const int grid = (int)ceil_div(n, nr);
-    const size_t lds_bytes = fixed + (size_t)round_up((int64_t)nr * n, 2) * 8;
+    const size_t lds_bytes = fixed + (size_t)round_up((int64_t)nr * n2, 2) * 8;
     hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(JAC_THREADS), lds_bytes, s, S, lds, n, nr, evals, Vout, info,
                        rtol);
     return hipGetLastError();
