@@ -439,7 +439,9 @@ hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* e
     const size_t budget = 160 * 1024 - 1024;   // the kernel's LDS attribute (static LDS is 16 bytes)
     if (fixed + (size_t)n2 * 8 + 8 > budget) return hipErrorInvalidValue;
     int nr = (int)((budget - fixed - 8) / ((size_t)n2 * 8));
-    if (nr > 32) nr = 32;
+    // few eigenvector rows per work-group: every work-group repeats the rotations, so a
+    // thinner slab only shortens each round's V update (more work-groups, idle CUs anyway)
+    if (nr > 8) nr = 8;
     if (nr > n) nr = n;
     const int grid = (int)ceil_div(n, nr);
     const size_t lds_bytes = fixed + (size_t)round_up((int64_t)nr * n2, 2) * 8;
