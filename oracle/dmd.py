@@ -327,6 +327,85 @@ def kkt_project(h, l, A):
     return np.linalg.solve(K, np.concatenate([h, l]))[:n]
 
 
+def vandermonde(alpha, T):
+    """Phi(alpha) of eq. variable_projection: entry (i, j) = alpha_j^(i-1), i = 1 .. T."""
+    alpha = np.asarray(alpha, dtype=np.complex128)
+    return alpha[None, :] ** np.arange(T)[:, None]
+
+
+def varpro_residual(alpha, Y):
+    """B = Phi(alpha)^+ Y (least squares) and the residual Y - Phi(alpha) B."""
+    Phi = vandermonde(alpha, Y.shape[0])
+    B = np.linalg.lstsq(Phi, Y, rcond=None)[0]
+    return Y - Phi @ B, B, Phi
+
+
+def varpro_normal_equations(alpha, Y, R, B, Phi):
+    """Gauss-Newton normal matrix and gradient of the variable-projection residual with
+    the Kaufman Jacobian J_j = -P_perp (dPhi/dalpha_j) B (Askham & Kutz 2018).
+
+    Column j of dPhi/dalpha_j is d_j(t) = t alpha_j^(t-1); J_j is the rank-one matrix
+    -(P_perp d_j) B[j, :], so <J_j, J_k> = (D~^H D~)_jk (conj(B) B^T)_jk and
+    <J_j, R> = -sum_l (D~^H R)_jl conj(B_jl), with D~ = P_perp D.
+    """
+    T = Y.shape[0]
+    t = np.arange(T)[:, None]
+    D = t * np.asarray(alpha)[None, :] ** (t - 1)
+    Qb, _ = np.linalg.qr(Phi)
+    Dt = D - Qb @ (Qb.conj().T @ D)
+    JhJ = (Dt.conj().T @ Dt) * (B.conj() @ B.T)
+    g = -np.sum((Dt.conj().T @ R) * B.conj(), axis=1)
+    return JhJ, g
+
+
+def varpro(Y, alpha0, max_iter=200, tol=1e-13):
+    """min over alpha, B of ||Y - Phi(alpha) B||_F, eq. variable_projection (Sec. 4.2).
+
+    B is eliminated by least squares and alpha takes Levenberg-Marquardt steps
+    (J^H J + mu diag(J^H J)) delta = -J^H r; a step is kept when it lowers the cost,
+    then mu shrinks, else mu grows and the step is retried.  Stops when a kept step
+    lowers the cost by less than tol relative.  Returns (alpha, B, cost, iterations).
+    """
+    Y = np.asarray(Y, dtype=np.complex128)
+    alpha = np.asarray(alpha0, dtype=np.complex128).copy()
+    R, B, Phi = varpro_residual(alpha, Y)
+    cost = float(np.sum(np.abs(R) ** 2))
+    mu = 1e-3
+    it = 0
+    for it in range(1, max_iter + 1):
+        JhJ, g = varpro_normal_equations(alpha, Y, R, B, Phi)
+        dg = np.diag(np.diag(JhJ).real)
+        while True:
+            delta = np.linalg.solve(JhJ + mu * dg, -g)
+            a_new = alpha + delta
+            R_new, B_new, Phi_new = varpro_residual(a_new, Y)
+            c_new = float(np.sum(np.abs(R_new) ** 2))
+            if c_new < cost:
+                break
+            mu *= 4.0
+            if mu > 1e20:
+                return alpha, B, cost, it
+        gain = cost - c_new
+        alpha, R, B, Phi, cost = a_new, R_new, B_new, Phi_new, c_new
+        mu = max(mu / 4.0, 1e-12)
+        if gain <= tol * cost:
+            break
+    return alpha, B, cost, it
+
+
+def fit_optdmd(U_r, s_r, V_r, alpha0, max_iter=200, tol=1e-13):
+    """OptDMD of Sec. 4.2: with X ~ U_r S_r V_r^T, solve eq. variable_projection on
+    Y = conj(V_r) S_r starting from alpha0, then the modes of eq. phi_optdmd,
+    phi_i = U_r B^T(:, i) / ||U_r B^T(:, i)||, with amplitudes b_i = ||U_r B^T(:, i)||
+    (so that x_t ~ sum_i phi_i b_i alpha_i^t, t = 0 .. T-1).
+    Returns (alpha, phi, b, cost, iterations)."""
+    Y = np.conj(np.asarray(V_r, dtype=np.complex128)) * np.asarray(s_r)[None, :]
+    alpha, B, cost, it = varpro(Y, alpha0, max_iter, tol)
+    M = np.asarray(U_r, dtype=np.complex128) @ B.T
+    b = np.linalg.norm(M, axis=0)
+    return alpha, M / b[None, :], b.astype(np.complex128), cost, it
+
+
 def project(phi, u):
     """z = Phi^+ u: eq. projection (Sec. 3.1)."""
     return np.linalg.lstsq(np.asarray(phi, dtype=np.complex128),
