@@ -101,6 +101,11 @@ typedef enum dmd_recon_mode {
 /* Fit flags. */
 #define DMD_FIT_ASYNC 1u         /* do not wait for the stream; status stays in model->info[0] */
 #define DMD_FIT_CHECK_FINITE 2u  /* scan X and X' for NaN/Inf first */
+#define DMD_FIT_OPTDMD 4u        /* OptDMD (Sec. 4.2): refine lambda and the modes by variable
+                                    projection on all snapshots of X (eq. variable_projection,
+                                    eq. phi_optdmd), starting from the fit's eigenvalues; the
+                                    call then waits for the device (not with DMD_FIT_ASYNC or
+                                    in dmd_fit_batched); info[4] = Levenberg-Marquardt steps */
 
 /* Options of a fit. */
 typedef struct dmd_fit_opts {
@@ -120,7 +125,7 @@ typedef struct dmd_fit_opts {
 /* Number of int32 words in model->info. */
 #define DMD_INFO_WORDS 8
 /* info[0] status, [1] Jacobi sweeps, [2] Francis QR iterations, [3] shifted
- * CholeskyQR retries, [4..7] reserved. */
+ * CholeskyQR retries, [4] OptDMD Levenberg-Marquardt steps, [5..7] reserved. */
 
 /* A DMD model; every pointer is device memory owned by the caller. */
 typedef struct dmd_model {

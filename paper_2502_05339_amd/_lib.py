@@ -28,7 +28,7 @@ DMD_ERR_UNSUPPORTED = 11
 DMD_F32, DMD_F64 = 0, 1
 FIT_MIXED, FIT_FP64_RANDOMIZED, FIT_FP64_EXACT = 0, 1, 2
 RECON_FP64, RECON_FP32, RECON_BF16, RECON_BF16X3 = 0, 1, 2, 3
-FIT_ASYNC, FIT_CHECK_FINITE = 1, 2
+FIT_ASYNC, FIT_CHECK_FINITE, FIT_OPTDMD = 1, 2, 4
 INFO_WORDS = 8
 MAX_SMALL = 192
 MAX_RANK = 160

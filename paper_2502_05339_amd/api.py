@@ -21,7 +21,7 @@ import torch
 
 from . import _lib
 from ._lib import (DMD_F32, DMD_F64, FIT_ASYNC, FIT_CHECK_FINITE, FIT_FP64_EXACT, FIT_FP64_RANDOMIZED,
-                   FIT_MIXED, RECON_BF16, RECON_BF16X3, RECON_FP32, RECON_FP64, check)
+                   FIT_MIXED, FIT_OPTDMD, RECON_BF16, RECON_BF16X3, RECON_FP32, RECON_FP64, check)
 
 PRECISIONS = {"mixed": FIT_MIXED, "fp64": FIT_FP64_RANDOMIZED, "fp64_exact": FIT_FP64_EXACT}
 RECON_MODES = {"fp64": RECON_FP64, "fp32": RECON_FP32, "bf16": RECON_BF16, "bf16x3": RECON_BF16X3}
@@ -206,21 +206,27 @@ def _xview(Z: torch.Tensor | None, X: torch.Tensor | None, Xp: torch.Tensor | No
 
 
 def fit_opts(r: int, p: int = 10, q: int = 2, precision: str = "mixed", omega: torch.Tensor | None = None,
-             dt: float = 1.0, rank_tol: float = 0.0, check_finite: bool = False, asynchronous: bool = False):
+             dt: float = 1.0, rank_tol: float = 0.0, check_finite: bool = False, asynchronous: bool = False,
+             optdmd: bool = False):
     o = _lib.FitOpts()
     o.r, o.p, o.q = int(r), int(p), int(q)
     o.precision = PRECISIONS[precision]
     o.dt = float(dt)
     o.rank_tol = float(rank_tol)
     o.omega = _ptr(omega)
-    o.flags = (FIT_CHECK_FINITE if check_finite else 0) | (FIT_ASYNC if asynchronous else 0)
+    o.flags = ((FIT_CHECK_FINITE if check_finite else 0) | (FIT_ASYNC if asynchronous else 0) |
+               (FIT_OPTDMD if optdmd else 0))
     return o
 
 
 def fit(Z: torch.Tensor | None = None, r: int = 0, *, X: torch.Tensor | None = None, Xp: torch.Tensor | None = None,
         p: int = 10, q: int = 2, omega: torch.Tensor | None = None, precision: str = "mixed", dt: float = 1.0,
-        rank_tol: float = 0.0, check_finite: bool = False, asynchronous: bool = False) -> Model:
+        rank_tol: float = 0.0, check_finite: bool = False, asynchronous: bool = False,
+        optdmd: bool = False) -> Model:
     """Fit a rank-r DMD model (Sec. 4.3 randomized SVD, then Sec. 3.1).
+
+    optdmd=True refines the eigenvalues and modes by variable projection over all
+    snapshots of X (OptDMD, Sec. 4.2); the call then waits for the device.
 
     Z: (m, N) snapshots (or X, Xp: (m-1, N) each); omega: (l, m-1) tensor holding the
     column-major (m-1) x l Gaussian sketch (i.e. omega.T is the sketch), same dtype as Z;
@@ -229,7 +235,7 @@ def fit(Z: torch.Tensor | None = None, r: int = 0, *, X: torch.Tensor | None = N
     src = Z if Z is not None else X
     _require_gpu(src, "snapshots")
     x, xp, n, ncols, ld, ldp, code = _xview(Z, X, Xp)
-    o = fit_opts(r, p, q, precision, omega, dt, rank_tol, check_finite, asynchronous)
+    o = fit_opts(r, p, q, precision, omega, dt, rank_tol, check_finite, asynchronous, optdmd)
     L = _lib.lib()
     nb = ctypes.c_size_t(0)
     check(L.dmd_fit_workspace_size(n, ncols, code, ctypes.byref(o), ctypes.byref(nb)), "dmd_fit_workspace_size")

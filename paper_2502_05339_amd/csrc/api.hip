@@ -83,6 +83,7 @@ int32_t validate_fit(const FitArgs& a, const dmd_model* model, bool need_ptrs)
     if (o.r > DMD_MAX_RANK) return DMD_ERR_UNSUPPORTED;
     if (!(o.dt > 0.0) || !isfinite(o.dt)) return DMD_ERR_ARG;
     if (o.rank_tol < 0.0 || !isfinite(o.rank_tol)) return DMD_ERR_ARG;
+    if ((o.flags & DMD_FIT_OPTDMD) && (o.flags & DMD_FIT_ASYNC)) return DMD_ERR_ARG;
     if (o.precision == DMD_FIT_FP64_EXACT) {
         if (a.ncols > DMD_MAX_SMALL) return DMD_ERR_UNSUPPORTED;
     } else {
@@ -105,8 +106,54 @@ int32_t validate_fit(const FitArgs& a, const dmd_model* model, bool need_ptrs)
     return DMD_OK;
 }
 
+// OptDMD buffers (variable projection on the T x r data Y = V_r S_r); two slots hold the
+// current and the trial point of the Levenberg-Marquardt iteration
+struct OptPlan {
+    double *Yd, *Phi, *E, *R, *Et;          // T x r
+    double *PtP, *Rv, *K, *Wm, *ER, *H;     // r x r
+    double *PtYE, *tmp;                     // r x 2r
+    double *BF[2], *G[2], *g[2], *theta[2]; // r x 2r (B | Phi^+ E), r x r, r, r
+    double *cost;                           // 2
+    double *A, *RinvA, *delta, *scale;      // r x r, r x r, r, r
+    double *C;                              // rows x r (rows = l, or T on the exact path)
+    void* Cf;                               // rows x ldphi in the data type
+    int32_t* scr;                           // 16
+};
+
+OptPlan opt_carve(Carver& cv, int T, int r, int rows, int64_t ldphi, int fdt)
+{
+    OptPlan o;
+    const size_t tr = (size_t)T * r, rr = (size_t)r * r;
+    o.Yd = cv.take<double>(tr); o.Phi = cv.take<double>(tr); o.E = cv.take<double>(tr);
+    o.R = cv.take<double>(tr); o.Et = cv.take<double>(tr);
+    o.PtP = cv.take<double>(rr); o.Rv = cv.take<double>(rr); o.K = cv.take<double>(rr);
+    o.Wm = cv.take<double>(rr); o.ER = cv.take<double>(rr); o.H = cv.take<double>(rr);
+    o.PtYE = cv.take<double>(2 * rr); o.tmp = cv.take<double>(2 * rr);
+    for (int k = 0; k < 2; ++k) {
+        o.BF[k] = cv.take<double>(2 * rr); o.G[k] = cv.take<double>(rr);
+        o.g[k] = cv.take<double>((size_t)r); o.theta[k] = cv.take<double>((size_t)r);
+    }
+    o.cost = cv.take<double>(2);
+    o.A = cv.take<double>(rr); o.RinvA = cv.take<double>(rr);
+    o.delta = cv.take<double>((size_t)r); o.scale = cv.take<double>((size_t)r);
+    o.C = cv.take<double>((size_t)rows * r);
+    o.Cf = cv.take<char>((size_t)rows * ldphi * esize(fdt));
+    o.scr = cv.take<int32_t>(16);
+    return o;
+}
+
+// what the OptDMD refinement reads from a finished fit
+struct FitBufs {
+    const void* Q; int64_t ldq;   // orthonormal basis (randomized paths)
+    double* Bx;                   // l x (m-1): Q^T X
+    double* Ueig;                 // eigenvectors of B B^T (l x l) or of X^T X (m-1 x m-1)
+    double* sigma;                // r singular values
+    int l;
+    OptPlan op;
+};
+
 // Carves (and, with base != nullptr, enqueues) the whole fit.
-int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
+int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model, FitBufs* fb = nullptr)
 {
     const bool run = cv.base != nullptr;
     const dmd_fit_opts& o = a.o;
@@ -170,6 +217,12 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
             Bx = cv.take<double>((size_t)l * mm);
             Bp = cv.take<double>((size_t)l * mm);
         }
+    }
+    OptPlan op{};
+    if (o.flags & DMD_FIT_OPTDMD) op = opt_carve(cv, mm, r, exact ? mm : l, ldphi, fdt);
+    if (fb) {
+        fb->Q = Y; fb->ldq = ldy; fb->Bx = Bx; fb->Ueig = Ueig; fb->sigma = sigma; fb->l = l;
+        fb->op = op;
     }
     if (!run) return DMD_OK;
 
@@ -279,6 +332,123 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model)
         HIPCHK(normal_solve(st, r, RinvPhi, r, rhs2, beta, 1));
     }
     HIPCHK(beta_to_b(st, r, beta, model->kind, model->b));
+    return DMD_OK;
+}
+
+// ---------------------------------------------------------------- OptDMD refinement
+// Levenberg-Marquardt on theta (real folded parameters, one per column) for
+// min ||Y - Phi(theta) B||_F with B = Phi^+ Y eliminated (eq. variable_projection), then
+// the modes of eq. phi_optdmd written into the model.  Host-driven: each trial point is
+// evaluated on the device and its cost read back; a step is kept when it lowers the cost
+// (mu / 4), else mu * 4 and a new trial.  Stops when a kept step gains less than 1e-13
+// of the cost, after 60 kept steps, or when mu passes 1e20.
+constexpr int VP_MAX_STEPS = 60;
+constexpr int VP_MAX_TRIES = 40;
+
+int32_t optdmd_refine(hipStream_t st, const FitArgs& a, dmd_model* model, FitBufs& fb, int* steps_out)
+{
+    const dmd_fit_opts& o = a.o;
+    const bool exact = o.precision == DMD_FIT_FP64_EXACT;
+    const int T = a.ncols, r = o.r, l = fb.l;
+    const int rows = exact ? T : l;
+    OptPlan& op = fb.op;
+    const double u = 1.1102230246251565e-16;
+    const double shift_scale = 11.0 * ((double)T * r + (double)r * (r + 1)) * u;
+    // data Y = V_r S_r: B^T U_r on the randomized paths (B = Q^T X), V_r S_r on the exact one
+    if (!exact) {
+        HIPCHK(small_gemm(st, 1, 0, T, r, l, 1.0, fb.Bx, l, fb.Ueig, l, 0.0, op.Yd, T));
+    } else {
+        HIPCHK(copy_f64(st, T, r, r, fb.Ueig, T, op.Yd, T));
+        HIPCHK(scale_cols(st, T, r, op.Yd, T, fb.sigma, 0));
+    }
+    HIPCHK(vp_theta_init(st, r, model->lam, model->kind, op.theta[0]));
+    auto evaluate = [&](int k) -> hipError_t {
+        hipError_t e;
+        double* B = op.BF[k];
+        double* F = op.BF[k] + (size_t)r * r;
+        if ((e = vp_basis(st, T, r, op.theta[k], model->kind, op.Phi, op.E))) return e;
+        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.Phi, T, op.Phi, T, 0.0, op.PtP, r))) return e;
+        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.Phi, T, op.Yd, T, 0.0, op.PtYE, r))) return e;
+        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.Phi, T, op.E, T, 0.0, op.PtYE + (size_t)r * r, r))) return e;
+        if ((e = fill_i32(st, op.scr, 16, 0))) return e;
+        if ((e = chol_inv(st, op.PtP, r, r, op.Rv, r, nullptr, 0, shift_scale, op.scr + 1, op.scr, nullptr))) return e;
+        // [B | F] = (Phi^T Phi)^-1 Phi^T [Y | E]
+        if ((e = small_gemm(st, 1, 0, r, 2 * r, r, 1.0, op.Rv, r, op.PtYE, r, 0.0, op.tmp, r))) return e;
+        if ((e = small_gemm(st, 0, 0, r, 2 * r, r, 1.0, op.Rv, r, op.tmp, r, 0.0, op.BF[k], r))) return e;
+        // R = Y - Phi B, E~ = E - Phi F
+        if ((e = copy_f64(st, T, r, r, op.Yd, T, op.R, T))) return e;
+        if ((e = small_gemm(st, 0, 0, T, r, r, -1.0, op.Phi, T, B, r, 1.0, op.R, T))) return e;
+        if ((e = copy_f64(st, T, r, r, op.E, T, op.Et, T))) return e;
+        if ((e = small_gemm(st, 0, 0, T, r, r, -1.0, op.Phi, T, F, r, 1.0, op.Et, T))) return e;
+        // K = E~^T E~, W = B B^T, H = E^T R B^T
+        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.Et, T, op.Et, T, 0.0, op.K, r))) return e;
+        if ((e = small_gemm(st, 0, 1, r, r, r, 1.0, B, r, B, r, 0.0, op.Wm, r))) return e;
+        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.E, T, op.R, T, 0.0, op.ER, r))) return e;
+        if ((e = small_gemm(st, 0, 1, r, r, r, 1.0, op.ER, r, B, r, 0.0, op.H, r))) return e;
+        if ((e = vp_sumsq(st, T, r, op.R, T, op.cost + k))) return e;
+        return vp_assemble(st, r, model->kind, op.K, op.Wm, op.H, op.G[k], op.g[k]);
+    };
+    auto read_cost = [&](int k, double* c, int32_t* chol_status) -> hipError_t {
+        hipError_t e = hipMemcpyAsync(c, op.cost + k, sizeof(double), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(chol_status, op.scr, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        return e;
+    };
+    HIPCHK(evaluate(0));
+    double cost = 0.0;
+    int32_t cs = 0;
+    HIPCHK(read_cost(0, &cost, &cs));
+    int cur = 0, steps = 0;
+    double mu = 1e-3;
+    if (cs == 0 && isfinite(cost)) {
+        for (; steps < VP_MAX_STEPS; ++steps) {
+            bool kept = false;
+            double gain = 0.0;
+            for (int tr = 0; tr < VP_MAX_TRIES && mu <= 1e20; ++tr) {
+                const int nx = cur ^ 1;
+                HIPCHK(vp_damp(st, r, op.G[cur], mu, op.A));
+                HIPCHK(fill_i32(st, op.scr, 16, 0));
+                HIPCHK(chol_inv(st, op.A, r, r, op.RinvA, r, nullptr, 0, 0.0, nullptr, op.scr, nullptr));
+                HIPCHK(normal_solve(st, r, op.RinvA, r, op.g[cur], op.delta, 0));
+                int32_t cs_a = 0;
+                HIPCHK(hipMemcpyAsync(&cs_a, op.scr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                HIPCHK(vp_update(st, r, op.theta[cur], op.delta, op.theta[nx]));
+                HIPCHK(evaluate(nx));
+                double c_new = 0.0;
+                int32_t cs_n = 0;
+                HIPCHK(read_cost(nx, &c_new, &cs_n));
+                if (cs_a == 0 && cs_n == 0 && isfinite(c_new) && c_new < cost) {
+                    gain = cost - c_new;
+                    cost = c_new;
+                    cur = nx;
+                    mu = std::max(mu * 0.25, 1e-12);
+                    kept = true;
+                    break;
+                }
+                mu *= 4.0;
+            }
+            if (!kept) break;
+            if (gain <= 1e-13 * cost) { ++steps; break; }
+        }
+    }
+    *steps_out = steps;
+    // modes of eq. phi_optdmd: Phi = basis C with C = U_B,r B^T (randomized; basis Q) or
+    // V_r S_r^-1 B^T (exact; basis X), columns scaled into the folded unit-norm form
+    const double* B = op.BF[cur];
+    HIPCHK(vp_lift(st, r, model->kind, op.theta[cur], B, model->lam, model->b, op.scale));
+    if (!exact) {
+        HIPCHK(small_gemm(st, 0, 1, l, r, r, 1.0, fb.Ueig, l, B, r, 0.0, op.C, l));
+    } else {
+        HIPCHK(copy_f64(st, T, r, r, fb.Ueig, T, op.Et, T));          // V_r S_r^-1 (scratch)
+        HIPCHK(scale_cols(st, T, r, op.Et, T, fb.sigma, 1));
+        HIPCHK(small_gemm(st, 0, 1, T, r, r, 1.0, op.Et, T, B, r, 0.0, op.C, T));
+    }
+    HIPCHK(scale_cols(st, rows, r, op.C, rows, op.scale, 0));
+    const int64_t ldphi = model->ldphi;
+    if (a.xdtype == DMD_F32) HIPCHK(to_f32(st, rows, r, (int)ldphi, op.C, rows, (float*)op.Cf, rows));
+    else HIPCHK(copy_f64(st, rows, r, (int)ldphi, op.C, rows, (double*)op.Cf, rows));
+    if (!exact) HIPCHK(gemm_nn(st, a.xdtype, fb.Q, fb.ldq, op.Cf, rows, model->phi, ldphi, 1, a.n, rows, (int)ldphi, nullptr));
+    else HIPCHK(gemm_nn(st, a.xdtype, a.x, a.ldx, op.Cf, rows, model->phi, ldphi, 1, a.n, rows, (int)ldphi, nullptr));
     return DMD_OK;
 }
 
@@ -579,7 +749,17 @@ int32_t dmd_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t 
     model->dtype = xdtype;
     model->dt = opts->dt;
     Carver cv(ws);
-    if (int32_t e = fit_plan(cv, st, a, model)) return e;
+    FitBufs fb{};
+    if (int32_t e = fit_plan(cv, st, a, model, &fb)) return e;
+    if (opts->flags & DMD_FIT_OPTDMD) {
+        int32_t status = 0;
+        HIPCHK(hipMemcpyAsync(&status, model->info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (status != DMD_OK) return status;
+        int steps = 0;
+        if (int32_t e = optdmd_refine(st, a, model, fb, &steps)) return e;
+        HIPCHK(fill_i32(st, model->info + 4, 1, steps));
+    }
     if (opts->flags & DMD_FIT_ASYNC) return DMD_OK;
     int32_t status = 0;
     HIPCHK(hipMemcpyAsync(&status, model->info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -877,6 +1057,7 @@ int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes, 
         FitArgs a{sc.x, sc.xp, sc.n, sc.ncols, sc.ldx, sc.ldxp, sc.xdtype, sc.opts,
                   is_shifted_view(sc.x, sc.xp, sc.ldx, sc.ldxp, sc.xdtype)};
         if (int32_t e = validate_fit(a, &models[i], true)) return e;
+        if (sc.opts.flags & DMD_FIT_OPTDMD) return DMD_ERR_UNSUPPORTED;   // host-driven refinement
         size_t need = 0;
         if (int32_t e = dmd_fit_workspace_size(sc.n, sc.ncols, sc.xdtype, &sc.opts, &need)) return e;
         if (!sc.ws || sc.ws_bytes < need) return DMD_ERR_WORKSPACE;

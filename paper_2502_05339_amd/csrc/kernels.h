@@ -122,6 +122,17 @@ hipError_t upsample_states(hipStream_t s, int r, int T, const double* lam, const
 hipError_t lowres_project(hipStream_t s, int dtype, const void* h, int64_t ldh, const void* l, int64_t ldl, void* x,
                           int64_t ldx, int64_t nframes, int ncomp, int nz, int ny, int nx, int f);
 
+// ---- OptDMD by variable projection (optdmd.hip), real folded parameters theta
+hipError_t vp_theta_init(hipStream_t s, int r, const double* lam, const int32_t* kind, double* theta);
+hipError_t vp_basis(hipStream_t s, int T, int r, const double* theta, const int32_t* kind, double* Phi, double* E);
+hipError_t vp_assemble(hipStream_t s, int r, const int32_t* kind, const double* K, const double* W, const double* H,
+                       double* G, double* g);
+hipError_t vp_sumsq(hipStream_t s, int m, int n, const double* A, int64_t lda, double* out);
+hipError_t vp_damp(hipStream_t s, int r, const double* G, double mu, double* A);
+hipError_t vp_update(hipStream_t s, int r, const double* theta, const double* delta, double* out);
+hipError_t vp_lift(hipStream_t s, int r, const int32_t* kind, const double* theta, const double* B, double* lam,
+                   double* b, double* scale);
+
 // ---- adjoint (adjoint.hip)
 hipError_t grad_reduce(hipStream_t s, int r, int ncols, const double* G, const double* lam,
                        const double* b, const int32_t* kind, const double* expo,
