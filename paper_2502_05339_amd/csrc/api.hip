@@ -118,6 +118,7 @@ struct OptPlan {
     double *C;                              // rows x r (rows = l, or T on the exact path)
     void* Cf;                               // rows x ldphi in the data type
     int32_t* scr;                           // 16
+    double* Ptn;                            // split partial products of the T-reductions
 };
 
 OptPlan opt_carve(Carver& cv, int T, int r, int rows, int64_t ldphi, int fdt)
@@ -139,6 +140,7 @@ OptPlan opt_carve(Carver& cv, int T, int r, int rows, int64_t ldphi, int fdt)
     o.C = cv.take<double>((size_t)rows * r);
     o.Cf = cv.take<char>((size_t)rows * ldphi * esize(fdt));
     o.scr = cv.take<int32_t>(16);
+    o.Ptn = cv.take<double>((size_t)tn_max_splits(T) * rr);
     return o;
 }
 
@@ -362,14 +364,19 @@ int32_t optdmd_refine(hipStream_t st, const FitArgs& a, dmd_model* model, FitBuf
         HIPCHK(scale_cols(st, T, r, op.Yd, T, fb.sigma, 0));
     }
     HIPCHK(vp_theta_init(st, r, model->lam, model->kind, op.theta[0]));
+    // out (r x r) = A^T B for T x r column-major A, B
+    auto tn64 = [&](const double* A, const double* B, int sym, double* out) -> hipError_t {
+        return gemm_tn(st, DMD_F64, DMD_F64, A, T, 0, r, B, T, 0, r, sym, T, op.Ptn, out, r, nullptr, 0, nullptr);
+    };
     auto evaluate = [&](int k) -> hipError_t {
         hipError_t e;
         double* B = op.BF[k];
         double* F = op.BF[k] + (size_t)r * r;
         if ((e = vp_basis(st, T, r, op.theta[k], model->kind, op.Phi, op.E))) return e;
-        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.Phi, T, op.Phi, T, 0.0, op.PtP, r))) return e;
-        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.Phi, T, op.Yd, T, 0.0, op.PtYE, r))) return e;
-        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.Phi, T, op.E, T, 0.0, op.PtYE + (size_t)r * r, r))) return e;
+        // products over the T snapshots as FP64 MFMA reductions
+        if ((e = tn64(op.Phi, op.Phi, 1, op.PtP))) return e;
+        if ((e = tn64(op.Phi, op.Yd, 0, op.PtYE))) return e;
+        if ((e = tn64(op.Phi, op.E, 0, op.PtYE + (size_t)r * r))) return e;
         if ((e = fill_i32(st, op.scr, 16, 0))) return e;
         if ((e = chol_inv(st, op.PtP, r, r, op.Rv, r, nullptr, 0, shift_scale, op.scr + 1, op.scr, nullptr))) return e;
         // [B | F] = (Phi^T Phi)^-1 Phi^T [Y | E]
@@ -381,9 +388,9 @@ int32_t optdmd_refine(hipStream_t st, const FitArgs& a, dmd_model* model, FitBuf
         if ((e = copy_f64(st, T, r, r, op.E, T, op.Et, T))) return e;
         if ((e = small_gemm(st, 0, 0, T, r, r, -1.0, op.Phi, T, F, r, 1.0, op.Et, T))) return e;
         // K = E~^T E~, W = B B^T, H = E^T R B^T
-        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.Et, T, op.Et, T, 0.0, op.K, r))) return e;
+        if ((e = tn64(op.Et, op.Et, 1, op.K))) return e;
         if ((e = small_gemm(st, 0, 1, r, r, r, 1.0, B, r, B, r, 0.0, op.Wm, r))) return e;
-        if ((e = small_gemm(st, 1, 0, r, r, T, 1.0, op.E, T, op.R, T, 0.0, op.ER, r))) return e;
+        if ((e = tn64(op.E, op.R, 0, op.ER))) return e;
         if ((e = small_gemm(st, 0, 1, r, r, r, 1.0, op.ER, r, B, r, 0.0, op.H, r))) return e;
         if ((e = vp_sumsq(st, T, r, op.R, T, op.cost + k))) return e;
         return vp_assemble(st, r, model->kind, op.K, op.Wm, op.H, op.G[k], op.g[k]);
