@@ -309,8 +309,8 @@ struct TnStage {
     }
 };
 
-template <typename Tin, typename Tc, int RC, int RI, int RJ>
-__global__ void __launch_bounds__(TN_THREADS)
+template <typename Tin, typename Tc, int RC, int RI, int RJ, int WI>
+__global__ void __launch_bounds__(256 * WI)
 gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
                const Tin* __restrict__ B, int64_t ldb, int b_rowmajor, int nb,
                int sym, int64_t N, int64_t rows_per_split, int vec, double* __restrict__ P,
@@ -333,10 +333,11 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
     const int64_t r_begin = split * rows_per_split;
     const int64_t r_end = min(N, r_begin + rows_per_split);
 
-    // this wave's RI x RJ piece of the work-group's 2RI x 4RJ tile
+    // this wave's RI x RJ piece of the work-group's (WI RI) x (4 RJ) tile
+    constexpr int NT = 256 * WI;
     const int ntj = (int)ceil_div(nbj, 4 * RJ);
     const int ti = blockIdx.y / ntj, tj = blockIdx.y % ntj;
-    const int bi0 = ti * 2 * RI + (wave >> 2) * RI;
+    const int bi0 = ti * WI * RI + (wave >> 2) * RI;
     const int bj0 = tj * 4 * RJ + (wave & 3) * RJ;
     V acc[RI][RJ];
 #pragma unroll
@@ -351,7 +352,7 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
     bool has[TN_MAXT];
 #pragma unroll
     for (int q = 0; q < TN_MAXT; ++q) {
-        const int t = tid + q * TN_THREADS;
+        const int t = tid + q * NT;
         has[q] = t < ntask;
         if (t < na) task[q].init(A + r_begin * (a_rowmajor ? lda : 1), lda, a_rowmajor, ka, ka_p, RC, t, lda_s, 0);
         else task[q].init(B + r_begin * (b_rowmajor ? ldb : 1), ldb, b_rowmajor, nb, nb_p, RC,
@@ -602,6 +603,8 @@ static size_t tn_lds(int rc, int ka, int nb, int sym) {
     X(Ti, Tc, RC, 5, 3) X(Ti, Tc, RC, 5, 4) X(Ti, Tc, RC, 5, 5) X(Ti, Tc, RC, 7, 3) X(Ti, Tc, RC, 10, 3)
 #define TN_TILES_F64(X, Ti, Tc, RC) X(Ti, Tc, RC, 2, 2) X(Ti, Tc, RC, 3, 3) X(Ti, Tc, RC, 4, 4) \
     X(Ti, Tc, RC, 5, 1) X(Ti, Tc, RC, 5, 3)
+// FP32 products with 16 waves (4 x 4): smaller wave tiles, four waves per SIMD
+#define TN_TILES_F32_W4(X) X(3, 3) X(3, 4) X(3, 5) X(4, 3) X(5, 3)
 #define TN_INSTANCES(X) \
     TN_TILES_F32(X, float, float, 16) TN_TILES_F32(X, float, float, 8) \
     TN_TILES_F64(X, float, double, 16) TN_TILES_F64(X, float, double, 8) \
@@ -611,10 +614,15 @@ hipError_t gemm_prepare()
 {
     hipError_t e = hipSuccess;
 #define TN_ATTR(Ti, Tc, RC, RI, RJ) \
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_tn_kernel<Ti, Tc, RC, RI, RJ>, \
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_tn_kernel<Ti, Tc, RC, RI, RJ, 2>, \
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     TN_INSTANCES(TN_ATTR)
 #undef TN_ATTR
+#define TN_ATTR4(RI, RJ) \
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_tn_kernel<float, float, 16, RI, RJ, 4>, \
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    TN_TILES_F32_W4(TN_ATTR4)
+#undef TN_ATTR4
 #define SYM_ATTR(Ti, Tc, RC) \
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_sym_kernel<Ti, Tc, RC>, \
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -628,18 +636,18 @@ size_t gemm_tn_partial_bytes(int64_t N, int ka, int nb) {
     return (size_t)tn_max_splits(N) * (size_t)ka * (size_t)nb * sizeof(double);
 }
 
-template <typename Tin, typename Tc, int RC, int RI, int RJ>
+template <typename Tin, typename Tc, int RC, int RI, int RJ, int WI = 2>
 static hipError_t launch_tn_k(hipStream_t s, const Tin* A, int64_t lda, int a_rm, int ka,
                               const Tin* B, int64_t ldb, int b_rm, int nb, int sym, int64_t N, int vec,
                               double* P, int* nsplit_out, const int32_t* skip_unless)
 {
     const int nbi = (int)ceil_div(ka, 16), nbj = (int)ceil_div(nb, 16);
-    const int gy = (int)(ceil_div(nbi, 2 * RI) * ceil_div(nbj, 4 * RJ));
+    const int gy = (int)(ceil_div(nbi, WI * RI) * ceil_div(nbj, 4 * RJ));
     const int ns = tn_splits(N, RC);
     const int64_t rps = round_up(ceil_div(N, ns), RC);
     const int ns_eff = (int)ceil_div(N, rps);
     const size_t lds = tn_lds<Tin, Tc>(RC, ka, nb, sym);
-    hipLaunchKernelGGL((gemm_tn_kernel<Tin, Tc, RC, RI, RJ>), dim3(ns_eff, gy), dim3(TN_THREADS), lds, s,
+    hipLaunchKernelGGL((gemm_tn_kernel<Tin, Tc, RC, RI, RJ, WI>), dim3(ns_eff, gy), dim3(256 * WI), lds, s,
                        A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, rps, vec, P, skip_unless);
     *nsplit_out = ns_eff;
     return hipGetLastError();
@@ -673,30 +681,45 @@ static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_r
     int best = -1;
     int64_t best_cost = INT64_MAX;
     int idx = 0;
-    auto consider = [&](int ri, int rj) {
-        const int64_t gy = ceil_div(nbi, 2 * ri) * ceil_div(nbj, 4 * rj);
-        const int64_t cost = gy * 100000 + gy * 8 * ri * rj;   // fewest re-reads first, then MFMA work
+    // fewest work-groups per row split (each re-reads the panels) first, then MFMA work
+    // (recomputed clamped blocks); 16-wave tiles count half, for their occupancy
+    auto consider = [&](int ri, int rj, int wi) {
+        const int64_t gy = ceil_div(nbi, wi * ri) * ceil_div(nbj, 4 * rj);
+        const int64_t cost = gy * 100000 + gy * 4 * wi * ri * rj * (wi == 4 ? 5 : 10);
         if (cost < best_cost) { best_cost = cost; best = idx; }
         ++idx;
     };
 #define TN_CASE(k, RI, RJ) \
     case k: return launch_tn_k<Tin, Tc, RC, RI, RJ>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
-    if constexpr (sizeof(Tc) == 4) {
-        consider(2, 2); consider(3, 3); consider(5, 1); consider(5, 3); consider(5, 4); consider(5, 5); consider(7, 3);
-        consider(10, 3);
+#define TN_CASE4(k, RI, RJ) \
+    case k: return launch_tn_k<Tin, Tc, RC, RI, RJ, 4>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
+    if constexpr (sizeof(Tc) == 4 && sizeof(Tin) == 4 && RC == 16) {
+        consider(2, 2, 2); consider(3, 3, 2); consider(5, 1, 2); consider(5, 3, 2); consider(5, 4, 2); consider(5, 5, 2);
+        consider(7, 3, 2); consider(10, 3, 2);
+        consider(3, 3, 4); consider(3, 4, 4); consider(3, 5, 4); consider(4, 3, 4); consider(5, 3, 4);
+        switch (best) {
+            TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 3) TN_CASE(4, 5, 4) TN_CASE(5, 5, 5)
+            TN_CASE(6, 7, 3) TN_CASE(7, 10, 3)
+            TN_CASE4(8, 3, 3) TN_CASE4(9, 3, 4) TN_CASE4(10, 3, 5) TN_CASE4(11, 4, 3)
+            default: return launch_tn_k<Tin, Tc, RC, 5, 3, 4>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
+        }
+    } else if constexpr (sizeof(Tc) == 4) {
+        consider(2, 2, 2); consider(3, 3, 2); consider(5, 1, 2); consider(5, 3, 2); consider(5, 4, 2); consider(5, 5, 2);
+        consider(7, 3, 2); consider(10, 3, 2);
         switch (best) {
             TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 3) TN_CASE(4, 5, 4) TN_CASE(5, 5, 5)
             TN_CASE(6, 7, 3)
             default: return launch_tn_k<Tin, Tc, RC, 10, 3>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
         }
     } else {
-        consider(2, 2); consider(3, 3); consider(4, 4); consider(5, 1); consider(5, 3);
+        consider(2, 2, 2); consider(3, 3, 2); consider(4, 4, 2); consider(5, 1, 2); consider(5, 3, 2);
         switch (best) {
             TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 4, 4) TN_CASE(3, 5, 1)
             default: return launch_tn_k<Tin, Tc, RC, 5, 3>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
         }
     }
 #undef TN_CASE
+#undef TN_CASE4
 }
 
 // Largest row chunk whose two LDS buffers and staging registers fit.
