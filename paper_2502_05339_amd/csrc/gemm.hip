@@ -747,6 +747,71 @@ static hipError_t launch_tn_t(hipStream_t s, const Tin* A, int64_t lda, int a_rm
     return hipErrorInvalidValue;
 }
 
+// A^T b for a row-major A (N x ka, ka <= 192, 16-byte aligned rows) and one column b: a
+// memory-bound pass, so no MFMA and no staging.  Lane l < ka/VW of a wave reads the VW
+// consecutive columns VW l .. VW l + VW-1 of a row as one 16-byte load (a row is one
+// contiguous read across the wave) and accumulates them in FP64; each wave walks its rows
+// GEMV_ROWS_UNROLL at a time; the four waves of a work-group sum in LDS, one FP64 partial
+// per split.
+constexpr int GEMV_ROWS_UNROLL = 8;
+template <typename T>
+__global__ void __launch_bounds__(256)
+gemv_tn_kernel(const T* __restrict__ A, int64_t lda, int ka, const T* __restrict__ b, int64_t N,
+               int64_t rows_per_split, double* __restrict__ P, const int32_t* skip_unless)
+{
+    if (skip_unless && *skip_unless == 0) return;
+    constexpr int VW = 16 / sizeof(T);
+    typedef T vec __attribute__((ext_vector_type(VW)));
+    __shared__ double part[4][192];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t r0 = blockIdx.x * rows_per_split;
+    const int64_t r1 = min(N, r0 + rows_per_split);
+    const bool act = lane * VW < ka;
+    const int col = act ? lane * VW : 0;
+    double acc[VW];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+    int64_t row = r0 + wave;
+    for (; row + 4 * (GEMV_ROWS_UNROLL - 1) < r1; row += 4 * GEMV_ROWS_UNROLL) {
+        vec a[GEMV_ROWS_UNROLL];
+        T bv[GEMV_ROWS_UNROLL];
+#pragma unroll
+        for (int u = 0; u < GEMV_ROWS_UNROLL; ++u) {
+            a[u] = *reinterpret_cast<const vec*>(A + (row + 4 * u) * lda + col);
+            bv[u] = b[row + 4 * u];
+        }
+#pragma unroll
+        for (int u = 0; u < GEMV_ROWS_UNROLL; ++u)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) acc[e] = fma((double)a[u][e], (double)bv[u], acc[e]);
+    }
+    for (; row < r1; row += 4) {
+        const vec a = *reinterpret_cast<const vec*>(A + row * lda + col);
+        const double bb = (double)b[row];
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = fma((double)a[e], bb, acc[e]);
+    }
+    if (act)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) part[wave][col + e] = acc[e];
+    __syncthreads();
+    for (int c = threadIdx.x; c < ka; c += blockDim.x)
+        P[blockIdx.x * (int64_t)ka + c] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
+}
+
+template <typename T>
+static hipError_t launch_gemv_tn(hipStream_t s, const T* A, int64_t lda, int ka, const T* b, int64_t N, double* P,
+                                 int* nsplit_out, const int32_t* skip_unless)
+{
+    // at least 4 rows per wave per split, at most the split count the partial buffer holds
+    const int64_t ns = std::max<int64_t>(1, std::min<int64_t>(tn_max_splits(N), ceil_div(N, (int64_t)64)));
+    const int64_t rps = ceil_div(N, ns);
+    const int ns_eff = (int)ceil_div(N, rps);
+    hipLaunchKernelGGL(gemv_tn_kernel<T>, dim3(ns_eff), dim3(256), 0, s, A, lda, ka, b, N, rps, P, skip_unless);
+    *nsplit_out = ns_eff;
+    return hipGetLastError();
+}
+
 hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A, int64_t lda,
                    int a_rowmajor, int ka, const void* B, int64_t ldb, int b_rowmajor, int nb,
                    int sym, int64_t N, double* P, double* out, int64_t ldo, float* out32,
@@ -761,6 +826,11 @@ hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A
         hipLaunchKernelGGL(fill_f64_kernel, dim3(64), dim3(256), 0, s, P, (int64_t)ka * nb, 0.0);
         ns = 1;
         e = hipGetLastError();
+    } else if (nb == 1 && a_rowmajor && !sym && ka <= 192 && !b_rowmajor && (uintptr_t)A % 16 == 0 &&
+               lda % (in_dtype == DMD_F32 ? 4 : 2) == 0 && lda >= round_up(ka, in_dtype == DMD_F32 ? 4 : 2)) {
+        // one column against a row-major panel: FP64 accumulation for either compute type
+        if (in_dtype == DMD_F32) e = launch_gemv_tn<float>(s, (const float*)A, lda, ka, (const float*)B, N, P, &ns, skip_unless);
+        else e = launch_gemv_tn<double>(s, (const double*)A, lda, ka, (const double*)B, N, P, &ns, skip_unless);
     } else if (in_dtype == DMD_F32 && compute_dtype == DMD_F32) {
         e = launch_tn_t<float, float>(s, (const float*)A, lda, a_rowmajor, ka, (const float*)B, ldb, b_rowmajor, nb, sym, N, P, &ns, skip_unless);
     } else if (in_dtype == DMD_F32) {
