@@ -86,7 +86,10 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
     __shared__ double col[EIG_MAX];           // column k of H (rows > k), for v
     __shared__ double colpre[EIG_MAX];        // column k + 1 before step k
     __shared__ double us[EIG_MAX], ws[EIG_MAX];
-    __shared__ double upart[32 * EIG_MAX];    // partial u per column group jb
+    // partial u per column group jb; rows of odd length so that the 32 lanes of a store
+    // (32 column groups, one row) fall in different banks
+    constexpr int UPS = EIG_MAX + 1;
+    __shared__ double upart[32 * UPS];
     __shared__ double wpart[32 * EIG_MAX];    // partial w per row group ib
     __shared__ double gpart[1024];
     __shared__ double refl[4];                // tau, beta, 1 / (alpha - beta), gamma
@@ -144,7 +147,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
 #pragma unroll
             for (int c = 0; c < HS_N; ++c) t = fma(h[a][c], vc[c], t);
             const int i = ib + 32 * a;
-            if (i < n) upart[jb * EIG_MAX + i] = t;
+            if (i < n) upart[jb * UPS + i] = t;
         }
 #pragma unroll
         for (int c = 0; c < HS_N; ++c) {
@@ -164,7 +167,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
         // ---- sums in a fixed order
         if (tid < n) {
             double t = 0.0;
-            for (int q = 0; q < 32; ++q) t += upart[q * EIG_MAX + tid];
+            for (int q = 0; q < 32; ++q) t += upart[q * UPS + tid];
             us[tid] = t;
         } else if (tid >= 256 && tid - 256 < n) {
             const int j = tid - 256;
