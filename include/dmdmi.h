@@ -94,8 +94,10 @@ typedef enum dmd_recon_mode {
     DMD_RECON_BF16X3 = 3  /* split-BF16 (hi+lo, three products), FP32 accumulate/output */
 } dmd_recon_mode;
 
-/* Limits of the single-workgroup FP64 kernels (packed matrices held in LDS). */
-#define DMD_MAX_SMALL 192   /* l = r + p, and m-1 for DMD_FIT_FP64_EXACT */
+/* Limits of the single-workgroup FP64 kernels (packed matrices held in LDS).  A fit
+ * beyond them returns DMD_ERR_UNSUPPORTED. */
+#define DMD_MAX_SMALL 192   /* m-1 for DMD_FIT_FP64_EXACT (symmetric eigen-solver) */
+#define DMD_MAX_SKETCH 160  /* l = r + p on the randomized paths (Cholesky of the l x l Gram) */
 #define DMD_MAX_RANK 160    /* r (nonsymmetric eigen-solver) */
 
 /* Fit flags. */

@@ -31,6 +31,7 @@ RECON_FP64, RECON_FP32, RECON_BF16, RECON_BF16X3 = 0, 1, 2, 3
 FIT_ASYNC, FIT_CHECK_FINITE, FIT_OPTDMD = 1, 2, 4
 INFO_WORDS = 8
 MAX_SMALL = 192
+MAX_SKETCH = 160
 MAX_RANK = 160
 
 

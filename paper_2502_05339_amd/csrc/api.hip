@@ -90,7 +90,7 @@ int32_t validate_fit(const FitArgs& a, const dmd_model* model, bool need_ptrs)
         if (o.p < 0 || o.q < 0 || o.q > 64) return DMD_ERR_ARG;
         const int l = o.r + o.p;
         if (l > a.ncols || l > a.n) return DMD_ERR_SHAPE;
-        if (l > DMD_MAX_SMALL) return DMD_ERR_UNSUPPORTED;
+        if (l > DMD_MAX_SKETCH) return DMD_ERR_UNSUPPORTED;
         if (need_ptrs && !o.omega) return DMD_ERR_ARG;
     }
     if (need_ptrs) {

@@ -748,12 +748,14 @@ static hipError_t launch_tn_t(hipStream_t s, const Tin* A, int64_t lda, int a_rm
 }
 
 // A^T b for a row-major A (N x ka, ka <= 192, 16-byte aligned rows) and one column b: a
-// memory-bound pass, so no MFMA and no staging.  Lane l < ka/VW of a wave reads the VW
-// consecutive columns VW l .. VW l + VW-1 of a row as one 16-byte load (a row is one
-// contiguous read across the wave) and accumulates them in FP64; each wave walks its rows
-// GEMV_ROWS_UNROLL at a time; the four waves of a work-group sum in LDS, one FP64 partial
-// per split.
+// memory-bound pass, so no MFMA and no staging.  A row is cut into chunks of 64 VW
+// columns; in chunk h, lane l reads the VW consecutive columns 64 VW h + VW l .. + VW-1 as
+// one 16-byte load (each chunk of a row is one contiguous read across the wave) and
+// accumulates them in FP64.  FP32 rows (VW = 4) need one chunk for 192 columns, FP64 rows
+// (VW = 2) two.  Each wave walks its rows GEMV_ROWS_UNROLL at a time; the four waves of a
+// work-group sum in LDS, one FP64 partial per split.
 constexpr int GEMV_ROWS_UNROLL = 8;
+constexpr int GEMV_MAX_KA = 192;
 template <typename T>
 __global__ void __launch_bounds__(256)
 gemv_tn_kernel(const T* __restrict__ A, int64_t lda, int ka, const T* __restrict__ b, int64_t N,
@@ -761,39 +763,62 @@ gemv_tn_kernel(const T* __restrict__ A, int64_t lda, int ka, const T* __restrict
 {
     if (skip_unless && *skip_unless == 0) return;
     constexpr int VW = 16 / sizeof(T);
+    constexpr int NCH = (GEMV_MAX_KA + 64 * VW - 1) / (64 * VW);
     typedef T vec __attribute__((ext_vector_type(VW)));
-    __shared__ double part[4][192];
+    __shared__ double part[4][GEMV_MAX_KA];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t r0 = blockIdx.x * rows_per_split;
     const int64_t r1 = min(N, r0 + rows_per_split);
-    const bool act = lane * VW < ka;
-    const int col = act ? lane * VW : 0;
-    double acc[VW];
+    bool act[NCH];
+    int col[NCH];
 #pragma unroll
-    for (int e = 0; e < VW; ++e) acc[e] = 0.0;
+    for (int h = 0; h < NCH; ++h) {
+        const int c = (64 * h + lane) * VW;
+        act[h] = c < ka;
+        col[h] = act[h] ? c : 0;
+    }
+    // the first chunk is read by every lane (inactive lanes re-read column 0, in bounds);
+    // later chunks only where they hold columns
+    auto load = [&](int64_t rw, int h) -> vec {
+        if (h == 0 || act[h]) return *reinterpret_cast<const vec*>(A + rw * lda + col[h]);
+        return vec{};
+    };
+    double acc[NCH][VW];
+#pragma unroll
+    for (int h = 0; h < NCH; ++h)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[h][e] = 0.0;
     int64_t row = r0 + wave;
     for (; row + 4 * (GEMV_ROWS_UNROLL - 1) < r1; row += 4 * GEMV_ROWS_UNROLL) {
-        vec a[GEMV_ROWS_UNROLL];
+        vec a[GEMV_ROWS_UNROLL][NCH];
         T bv[GEMV_ROWS_UNROLL];
 #pragma unroll
         for (int u = 0; u < GEMV_ROWS_UNROLL; ++u) {
-            a[u] = *reinterpret_cast<const vec*>(A + (row + 4 * u) * lda + col);
+#pragma unroll
+            for (int h = 0; h < NCH; ++h) a[u][h] = load(row + 4 * u, h);
             bv[u] = b[row + 4 * u];
         }
 #pragma unroll
         for (int u = 0; u < GEMV_ROWS_UNROLL; ++u)
 #pragma unroll
-            for (int e = 0; e < VW; ++e) acc[e] = fma((double)a[u][e], (double)bv[u], acc[e]);
+            for (int h = 0; h < NCH; ++h)
+#pragma unroll
+                for (int e = 0; e < VW; ++e) acc[h][e] = fma((double)a[u][h][e], (double)bv[u], acc[h][e]);
     }
     for (; row < r1; row += 4) {
-        const vec a = *reinterpret_cast<const vec*>(A + row * lda + col);
         const double bb = (double)b[row];
 #pragma unroll
-        for (int e = 0; e < VW; ++e) acc[e] = fma((double)a[e], bb, acc[e]);
-    }
-    if (act)
+        for (int h = 0; h < NCH; ++h) {
+            const vec a = load(row, h);
 #pragma unroll
-        for (int e = 0; e < VW; ++e) part[wave][col + e] = acc[e];
+            for (int e = 0; e < VW; ++e) acc[h][e] = fma((double)a[e], bb, acc[h][e]);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < NCH; ++h)
+        if (act[h])
+#pragma unroll
+            for (int e = 0; e < VW; ++e) part[wave][col[h] + e] = acc[h][e];
     __syncthreads();
     for (int c = threadIdx.x; c < ka; c += blockDim.x)
         P[blockIdx.x * (int64_t)ka + c] = (part[0][c] + part[1][c]) + (part[2][c] + part[3][c]);
@@ -826,7 +851,7 @@ hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A
         hipLaunchKernelGGL(fill_f64_kernel, dim3(64), dim3(256), 0, s, P, (int64_t)ka * nb, 0.0);
         ns = 1;
         e = hipGetLastError();
-    } else if (nb == 1 && a_rowmajor && !sym && ka <= 192 && !b_rowmajor && (uintptr_t)A % 16 == 0 &&
+    } else if (nb == 1 && a_rowmajor && !sym && ka <= GEMV_MAX_KA && !b_rowmajor && (uintptr_t)A % 16 == 0 &&
                lda % (in_dtype == DMD_F32 ? 4 : 2) == 0 && lda >= round_up(ka, in_dtype == DMD_F32 ? 4 : 2)) {
         // one column against a row-major panel: FP64 accumulation for either compute type
         if (in_dtype == DMD_F32) e = launch_gemv_tn<float>(s, (const float*)A, lda, ka, (const float*)B, N, P, &ns, skip_unless);

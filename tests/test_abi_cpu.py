@@ -96,7 +96,10 @@ def _ws_size(L, n, ncols, dtype, o):
     (10, 30, 8, 4, 2),         # l > N
     (0, 30, 8, 4, 2),          # empty
     (1000, 400, 170, 10, 11),  # r beyond the eigen-solver limit
-    (1000, 400, 150, 60, 11),  # l beyond the small-matrix limit
+    (1000, 400, 150, 60, 11),  # l beyond the sketch limit
+    (1000, 400, 150, 10, 0),   # l = 160, the largest sketch
+    (1000, 400, 150, 11, 11),  # l = 161
+    (1000, 400, 160, 32, 11),  # r at the eigen-solver limit, l = 192
 ])
 def test_fit_shape_validation(L, n, ncols, r, p, expect):
     st, _ = _ws_size(L, n, ncols, 0, _opts(r, p))

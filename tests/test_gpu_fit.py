@@ -254,3 +254,104 @@ def test_batched_graph_matches_single_fits(gpu_lib):
         for a, b in zip(bf.models, singles):
             assert torch.equal(a.lam, b.lam) and torch.equal(a.phi, b.phi) and torch.equal(a.b, b.b)
     bf.close()
+
+
+# Ranks at both ends of the supported range: r = 1 (a single real eigenvalue), r = 2
+# and 3 (one pair, a pair plus a real value), r = 149 (odd) and r = 150 with l = r + p =
+# 160, the largest sketch, and r = 160 (the eigen-solver limit) with p = 0; the FP64
+# products of one column against the modes then span more than 128 columns.  Signals are
+# rank 6-180 with
+# persistent modes (|lambda| >= 0.99) so the truncation falls between two singular
+# values at least 1e-3 apart (relative to the largest): the twin comparison is then well
+# conditioned.  The tolerances are the gates of the two precisions.
+_EDGE = {
+    "r1": (1, 10, 3, 611, 200),
+    "r2": (2, 10, 3, 612, 200),
+    "r3": (3, 10, 4, 613, 200),
+    "r149-l159": (149, 10, 90, 614, 200),
+    "r150-l160": (150, 10, 90, 615, 200),
+    "r160-p0": (160, 0, 90, 621, 200),
+}
+
+
+def _edge_cfg(name):
+    r, p, nc, seed, m = _EDGE[name]
+    return synth.Config(f"edge-{name}", (2, 64, 64), m, nc, 0.99, 1e-6, seed, r=r, p=p, q=2, jitter=True)
+
+
+def _edge_generate(cfg):
+    g = synth.generate(cfg)
+    if g.Omega is None:                  # p = 0: the sketch still has l = r columns
+        g.Omega = synth.sketch(cfg.seed, cfg.m, cfg.l)
+    return g
+
+
+def _twin_errors(m, g, cfg, precision):
+    tw = oracle.fit_randomized(g.Z.astype(np.float64), cfg.r, g.Omega.astype(np.float64), cfg.q)
+    w = oracle.amplitude_weights(tw.phi, tw.b)
+    lam = m.lam_host()
+    assert lam.shape == tw.lam.shape
+    ia, ib = oracle.match_eigs(lam, tw.lam)
+    d = np.abs(lam[ia] - tw.lam[ib])
+    wrel = float(np.sum(w[ib] * d) / np.sum(w[ib] * np.abs(tw.lam[ib])))
+    ks = np.arange(cfg.m)
+    U = _fields(m, ks, "fp64" if precision == "fp64" else "fp32")
+    Uo = oracle.reconstruct(tw.phi, tw.lam, tw.b, ks).T
+    return wrel, max_frame_rel(U, Uo)
+
+
+@pytest.mark.parametrize("name", list(_EDGE))
+def test_rank_extremes_fp64_vs_twin(gpu_lib, name):
+    cfg = _edge_cfg(name)
+    _print(f"case: rank extreme {name} (r={cfg.r}, l={cfg.l}) fp64 vs FP64 twin")
+    g = _edge_generate(cfg)
+    g.Omega = g.Omega.astype(np.float64)
+    s = np.linalg.svd(g.Z[:, :-1].astype(np.float64), compute_uv=False)
+    assert (s[cfg.r - 1] - s[cfg.r]) / s[0] >= 1e-3      # the premise of the tolerances
+    m, _ = _gpu_fit(g, cfg, "fp64")
+    wrel, ferr = _twin_errors(m, g, cfg, "fp64")
+    _print(f"  lambda weighted {wrel:.3e} fields {ferr:.3e}")
+    assert int(m.info[0].item()) == 0
+    assert wrel <= 1e-9
+    assert ferr <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["r150-l160", "r160-p0"])
+def test_rank_extreme_mixed_max_sketch(gpu_lib, name):
+    cfg = _edge_cfg(name)
+    _print(f"case: rank extreme {name} mixed vs FP64 twin")
+    g = _edge_generate(cfg)
+    m, _ = _gpu_fit(g, cfg, "mixed")
+    wrel, ferr = _twin_errors(m, g, cfg, "mixed")
+    _print(f"  lambda weighted {wrel:.3e} fields {ferr:.3e}")
+    assert int(m.info[0].item()) == 0
+    assert wrel <= 1e-5
+    assert ferr <= 1e-4
+
+
+def test_exact_path_max_rank_and_columns(gpu_lib):
+    """FP64 exact path at its limits: r = 160 (eigen-solver) from m - 1 = 192 columns
+    (Gram eigen-decomposition), against the oracle's SVD-based exact DMD."""
+    cfg = synth.Config("edge-exact", (2, 64, 64), 193, 90, 0.99, 1e-6, 618, r=160, p=0, q=0, jitter=True,
+                       dtype="f64")
+    _print("case: fp64_exact r=160, m-1=192 vs oracle")
+    g = synth.generate(cfg)
+    s = np.linalg.svd(g.Z[:, :-1], compute_uv=False)
+    assert (s[cfg.r - 1] - s[cfg.r]) / s[0] >= 1e-3
+    m, _ = _gpu_fit(g, cfg, "fp64_exact")
+    f = oracle.fit_exact(g.Z, cfg.r)
+    ks = np.arange(cfg.m)
+    err = max_frame_rel(_fields(m, ks, "fp64"), oracle.reconstruct(f.phi, f.lam, f.b, ks).T)
+    _print(f"  fields vs oracle {err:.3e}")
+    assert int(m.info[0].item()) == 0
+    assert err <= 1e-9
+
+
+def test_sketch_beyond_limit_is_unsupported(gpu_lib):
+    """l = r + p above the sketch limit is refused before any launch (status 11)."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.Config("edge-l161", (2, 32, 32), 200, 80, 0.99, 1e-6, 619, r=150, p=11, q=1, jitter=True)
+    g = synth.generate(cfg)
+    with pytest.raises(dmd.DMDError) as ei:
+        _gpu_fit(g, cfg, "mixed")
+    assert ei.value.code == 11
