@@ -1,4 +1,6 @@
 """Shared test helpers: oracle fits in the library's folded storage, error metrics."""
+import functools
+
 import numpy as np
 
 
@@ -56,3 +58,15 @@ def max_frame_rel(U, Uref):
     num = np.linalg.norm(U - Uref, axis=1)
     den = np.linalg.norm(Uref, axis=1)
     return float(np.max(num / np.maximum(den, 1e-300)))
+
+
+@functools.lru_cache(maxsize=1)
+def rank150_fit():
+    """Oracle exact fit of rank 150 (2 x 64 x 64 grid, 160 snapshot pairs of a rank-180
+    signal with persistent modes): a model whose FP64 products against one column span
+    more than 128 columns.  Its folded modes have condition number about 8."""
+    import oracle
+    import synth
+    cfg = synth.Config("rank150", (2, 64, 64), 161, 90, 0.99, 1e-6, 618, r=150, p=0, q=0, jitter=True, dtype="f64")
+    g = synth.generate(cfg)
+    return cfg, g, oracle.fit_exact(g.Z, cfg.r)

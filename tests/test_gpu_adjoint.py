@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import synth
-from helpers import model_from_oracle
+from helpers import model_from_oracle, rank150_fit
 
 pytestmark = pytest.mark.gpu
 
@@ -51,6 +51,23 @@ def test_loss_grad_matches_closed_form(gpu_lib, dtype, tol):
     assert abs(L.item() - Lo) <= tol * abs(Lo)
     assert _relerr(gl.cpu().numpy(), glo) <= tol
     assert _relerr(gb.cpu().numpy(), gbo) <= tol
+
+
+def test_loss_grad_rank150_fp64(gpu_lib):
+    """FP64 model of rank 150 (products against more than 128 mode columns)."""
+    import paper_2502_05339_amd as dmd
+    cfg, g, f = rank150_fit()
+    _print("case: loss/grad rank 150 fp64")
+    m = model_from_oracle(f, torch.float64)
+    lam, b = _perturbed(f, np.random.default_rng(3), scale=1e-4)
+    ks = np.arange(0, cfg.m, 2)
+    X = torch.from_numpy(np.ascontiguousarray(g.Z[:, ks].T)).cuda()
+    L, gl, gb = dmd.loss_grad(m, torch.from_numpy(lam).cuda(), torch.from_numpy(b).cuda(), X, ks)
+    Lo, glo, gbo = oracle.loss_grad(m.complex_modes(), lam, b, g.Z[:, ks], ks)
+    _print(f"  loss {L.item():.6e} vs {Lo:.6e}")
+    assert abs(L.item() - Lo) <= 1e-10 * abs(Lo)
+    assert _relerr(gl.cpu().numpy(), glo) <= 1e-10
+    assert _relerr(gb.cpu().numpy(), gbo) <= 1e-10
 
 
 def test_loss_grad_c4_shape_with_strided_targets(gpu_lib):

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from helpers import max_frame_rel, model_from_oracle
+from helpers import max_frame_rel, model_from_oracle, rank150_fit
 
 pytestmark = pytest.mark.gpu
 
@@ -164,6 +164,17 @@ def test_project_matches_oracle(gpu_lib, c1cf_fit):
     u = torch.from_numpy(np.ascontiguousarray(g.Z[:, 5])).cuda()
     z = m.project(u).cpu().numpy()
     zo = oracle.project(m.complex_modes(), g.Z[:, 5])
+    assert np.max(np.abs(z - zo)) <= 1e-9 * np.max(np.abs(zo))
+
+
+def test_project_rank150_matches_oracle(gpu_lib):
+    """z = Phi^+ u for a rank-150 FP64 model (one column against 150 modes)."""
+    cfg, g, f = rank150_fit()
+    _print("case: project z = Phi^+ u, r = 150")
+    m = model_from_oracle(f, torch.float64)
+    u = torch.from_numpy(np.ascontiguousarray(g.Z[:, 7])).cuda()
+    z = m.project(u).cpu().numpy()
+    zo = oracle.project(m.complex_modes(), g.Z[:, 7])
     assert np.max(np.abs(z - zo)) <= 1e-9 * np.max(np.abs(zo))
 
 

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from helpers import max_frame_rel, model_from_oracle
+from helpers import max_frame_rel, model_from_oracle, rank150_fit
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +41,22 @@ def test_rollout_fp64_parity(gpu_lib, c1cf, T):
     m = model_from_oracle(f, torch.float64, dt=dt)
     _print(f"case: rollout fp64 N={m.n} r={m.r} T={T}")
     rng = np.random.default_rng(T)
+    F = 0.05 * rng.standard_normal((T, m.n))
+    Z, U = rollout(m, torch.from_numpy(F).cuda(), mode="fp64")
+    Zo, Uo = oracle.rollout(m.complex_modes(), m.lam.cpu().numpy(), m.b.cpu().numpy(), F.T, dt=dt)
+    es, ef = _rel_states(Z.cpu().numpy(), Zo), max_frame_rel(U.cpu().numpy(), Uo.T)
+    _print(f"  states {es:.3e} frames {ef:.3e}")
+    assert es <= 1e-10 and ef <= 1e-10
+
+
+@pytest.mark.parametrize("T", [1, 100])
+def test_rollout_fp64_parity_rank150(gpu_lib, T):
+    from paper_2502_05339_amd import rollout
+    cfg, g, f = rank150_fit()
+    dt = 0.7
+    m = model_from_oracle(f, torch.float64, dt=dt)
+    _print(f"case: rollout fp64 N={m.n} r={m.r} T={T}")
+    rng = np.random.default_rng(1000 + T)
     F = 0.05 * rng.standard_normal((T, m.n))
     Z, U = rollout(m, torch.from_numpy(F).cuda(), mode="fp64")
     Zo, Uo = oracle.rollout(m.complex_modes(), m.lam.cpu().numpy(), m.b.cpu().numpy(), F.T, dt=dt)

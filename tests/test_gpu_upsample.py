@@ -14,7 +14,7 @@ import torch
 
 import oracle
 import synth
-from helpers import max_frame_rel, model_from_oracle
+from helpers import max_frame_rel, model_from_oracle, rank150_fit
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +42,24 @@ def test_upsample_fp64_parity(gpu_lib, c1cf, T):
     lam = m.lam.cpu().numpy()
     low = np.abs(np.angle(lam)) < np.median(np.abs(np.angle(lam)))
     rng = np.random.default_rng(T)
+    h0 = rng.standard_normal(m.n)
+    L = rng.standard_normal((T, m.n))
+    _print(f"case: upsample fp64 N={m.n} r={m.r} T={T} low={int(low.sum())}")
+    R, H = upsample(m, torch.from_numpy(h0).cuda(), torch.from_numpy(L).cuda(), low, mode="fp64")
+    Ro, Ho = oracle.upsample_evolve(m.complex_modes(), lam, h0, L.T, low)
+    es, ef = _rel(R.cpu().numpy(), Ro), max_frame_rel(H.cpu().numpy(), Ho.T)
+    _print(f"  states {es:.3e} frames {ef:.3e}")
+    assert es <= 1e-10 and ef <= 1e-10
+
+
+@pytest.mark.parametrize("T", [1, 30])
+def test_upsample_fp64_parity_rank150(gpu_lib, T):
+    from paper_2502_05339_amd import upsample
+    cfg, g, f = rank150_fit()
+    m = model_from_oracle(f, torch.float64)
+    lam = m.lam.cpu().numpy()
+    low = np.abs(np.angle(lam)) < np.median(np.abs(np.angle(lam)))
+    rng = np.random.default_rng(2000 + T)
     h0 = rng.standard_normal(m.n)
     L = rng.standard_normal((T, m.n))
     _print(f"case: upsample fp64 N={m.n} r={m.r} T={T} low={int(low.sum())}")
