@@ -8,7 +8,7 @@ from .dmd import (LOW_FREQ_CUT, DMDFit, block_average_matrix, canonical_order, c
                   fit_exact, fit_optdmd, fit_randomized, frequency_clusters, integrate, kkt_project,
                   koopman_least_squares, loss, loss_grad, powers, project,
                   range_finder, reconstruct, reverse, rollout, split_snapshots, thin_svd, upsample_evolve,
-                  vandermonde, varpro, varpro_normal_equations, varpro_residual,
+                  vandermonde, varpro, varpro_normal_equations, varpro_residual, varpro_trial,
                   thin_svd_qr_route)
 from .metrics import (amplitude_weights, complex_modes_from_folded, eig_errors,
                       field_errors, match_eigs)
@@ -16,7 +16,7 @@ from .metrics import (amplitude_weights, complex_modes_from_folded, eig_errors,
 __all__ = [
     "LOW_FREQ_CUT", "DMDFit", "canonical_order", "cluster_edit", "edit_modes",
     "frequency_clusters", "reverse", "rollout", "block_average_matrix", "kkt_project", "upsample_evolve",
-    "fit_optdmd", "vandermonde", "varpro", "varpro_normal_equations", "varpro_residual", "fit_exact", "fit_randomized", "integrate",
+    "fit_optdmd", "vandermonde", "varpro", "varpro_normal_equations", "varpro_residual", "varpro_trial", "fit_exact", "fit_randomized", "integrate",
     "koopman_least_squares", "loss", "loss_grad", "powers", "project",
     "range_finder", "reconstruct", "split_snapshots", "thin_svd",
     "thin_svd_qr_route", "amplitude_weights", "complex_modes_from_folded",

@@ -340,6 +340,17 @@ def varpro_residual(alpha, Y):
     return Y - Phi @ B, B, Phi
 
 
+def varpro_trial(alpha, Y):
+    """(R, B, Phi, cost) at a trial point of the Levenberg-Marquardt iteration.  A point
+    whose basis overflows (|alpha|^(T-1) beyond the double range) gets an infinite cost,
+    so the iteration rejects it like any point that raises the cost."""
+    Phi = vandermonde(alpha, Y.shape[0])
+    if not np.all(np.isfinite(Phi)):
+        return None, None, Phi, np.inf
+    R, B, Phi = varpro_residual(alpha, Y)
+    return R, B, Phi, float(np.sum(np.abs(R) ** 2))
+
+
 def varpro_normal_equations(alpha, Y, R, B, Phi):
     """Gauss-Newton normal matrix and gradient of the variable-projection residual with
     the Kaufman Jacobian J_j = -P_perp (dPhi/dalpha_j) B (Askham & Kutz 2018).
@@ -378,8 +389,7 @@ def varpro(Y, alpha0, max_iter=200, tol=1e-13):
         while True:
             delta = np.linalg.solve(JhJ + mu * dg, -g)
             a_new = alpha + delta
-            R_new, B_new, Phi_new = varpro_residual(a_new, Y)
-            c_new = float(np.sum(np.abs(R_new) ** 2))
+            R_new, B_new, Phi_new, c_new = varpro_trial(a_new, Y)
             if c_new < cost:
                 break
             mu *= 4.0

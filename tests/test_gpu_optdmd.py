@@ -73,6 +73,32 @@ def test_optdmd_fp64_parity(gpu_lib, precision, seed):
     assert e_opt < 0.5 * e_dmd
 
 
+def test_optdmd_fp64_parity_rank150(gpu_lib):
+    """r = 150 from a l = 160 sketch (the c2 rank) on a 2 x 64 x 64 grid, 80 pairs with
+    noise 1e-3: the oracle converges in 17 steps, well inside the GPU's step limit."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.Config("optdmd-r150", (2, 64, 64), 200, 80, 0.99, 1e-3, 632, r=150, p=10, q=2, jitter=True)
+    g = synth.generate(cfg)
+    Z, om = _inputs(g, np.float64)
+    _print("case: optdmd fp64 r=150 l=160")
+    m = dmd.fit(Z, cfg.r, p=cfg.p, q=cfg.q, omega=om, precision="fp64", optdmd=True)
+    steps = int(m.info.cpu().numpy()[4])
+    U_r, s_r, V_r, lam0 = _oracle_svd(g, cfg, "fp64")
+    a, phi, b, cost, it = oracle.fit_optdmd(U_r, s_r, V_r, lam0)
+    lam = m.lam_host()
+    ia, ib = match_eigs(lam, a)
+    e_par = float(np.max(np.abs(lam[ia] - a[ib]) / np.abs(a[ib])))
+    T = cfg.m - 1
+    U = m.reconstruct(np.arange(T), "fp64").cpu().numpy()
+    Uo = oracle.reconstruct(phi, a, b, np.arange(T)).T
+    e_f = max_frame_rel(U, Uo)
+    _print(f"  LM steps {steps} (oracle {it}); lambda vs oracle {e_par:.3e}; fields {e_f:.3e}")
+    assert int(m.info[0].item()) == 0
+    assert steps >= 1
+    assert e_par <= 1e-6
+    assert e_f <= 1e-5
+
+
 def test_optdmd_mixed_close_to_fp64(gpu_lib):
     import paper_2502_05339_amd as dmd
     cfg = synth.config("c1-cf", seed=12, sigma=1e-2, p=4, q=1)

@@ -462,6 +462,19 @@ def test_varpro_recovers_exact_exponentials():
     assert cost <= 1e-20 * np.sum(np.abs(Y) ** 2)
 
 
+def test_varpro_trial_rejects_overflowing_basis():
+    """A trial point whose Vandermonde basis overflows gets an infinite cost (rejected),
+    and one in range gets the plain residual norm."""
+    rng = np.random.default_rng(23)
+    Y = rng.standard_normal((200, 3)) + 1j * rng.standard_normal((200, 3))
+    R, B, Phi, c = oracle.varpro_trial(np.array([0.9, 40.0, 0.5j]), Y)
+    assert R is None and c == np.inf
+    al = np.array([0.9, 0.8 * np.exp(0.2j), 0.5j])
+    R, B, Phi, c = oracle.varpro_trial(al, Y)
+    Rr, _, _ = oracle.varpro_residual(al, Y)
+    assert c == float(np.sum(np.abs(Rr) ** 2)) and np.isfinite(c)
+
+
 def test_varpro_normal_equations_match_explicit_jacobian():
     """The structured J^H J and J^H r equal products with the explicit Kaufman Jacobian."""
     rng = np.random.default_rng(22)
