@@ -344,7 +344,8 @@ def varpro_trial(alpha, Y):
     """(R, B, Phi, cost) at a trial point of the Levenberg-Marquardt iteration.  A point
     whose basis overflows (|alpha|^(T-1) beyond the double range) gets an infinite cost,
     so the iteration rejects it like any point that raises the cost."""
-    Phi = vandermonde(alpha, Y.shape[0])
+    with np.errstate(over="ignore", invalid="ignore"):
+        Phi = vandermonde(alpha, Y.shape[0])
     if not np.all(np.isfinite(Phi)):
         return None, None, Phi, np.inf
     R, B, Phi = varpro_residual(alpha, Y)
