@@ -568,7 +568,16 @@ reduce_partials_kernel(const double* __restrict__ P, int nsplit, int ka, int nb,
         int si = i, sj = j;
         if (sym && (i / 16) > (j / 16)) { si = j; sj = i; }
         const double* p = P + (int64_t)sj * ka + si;
-        for (int k = q; k < nsplit; k += RQ) s += p[(int64_t)k * tot];
+        // eight loads in flight per lane, added in the same (split) order as one at a time
+        int k = q;
+        for (; k + 7 * RQ < nsplit; k += 8 * RQ) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(k + u * RQ) * tot];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s += v[u];
+        }
+        for (; k < nsplit; k += RQ) s += p[(int64_t)k * tot];
     }
     part[q][o] = s;
     __syncthreads();
