@@ -451,24 +451,60 @@ hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* e
 }
 
 // ====================================================================== helpers
-__global__ void small_gemm_kernel(int ta, int tb, int m, int n, int k, double alpha,
-                                  const double* __restrict__ A, int64_t lda,
-                                  const double* __restrict__ B, int64_t ldb, double beta,
-                                  double* __restrict__ C, int64_t ldc)
+// C = alpha op(A) op(B) + beta C by 32 x 32 output tiles: 256 threads, each owning a 2 x 2
+// block (rows 2 tx, 2 tx + 1, columns 2 ty, 2 ty + 1), over k in chunks of 32 staged in
+// LDS as [k][row] and [k][column] panels (the transposes are taken while staging, with
+// the contiguous index of either layout on consecutive threads).  Each k step is two
+// 16-byte LDS reads and four FMAs; every output sums its products in ascending k.
+constexpr int SG_T = 32;
+constexpr int SG_KC = 32;
+constexpr int SG_LD = SG_T + 2;   // 16-byte aligned rows
+__global__ void __launch_bounds__(256)
+small_gemm_kernel(int ta, int tb, int m, int n, int k, double alpha, const double* __restrict__ A, int64_t lda,
+                  const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc)
 {
-    const int64_t tot = (int64_t)m * n;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e % m), j = (int)(e / m);
-        double s = 0.0;
-        for (int kk = 0; kk < k; ++kk) {
-            const double a = ta ? A[(int64_t)i * lda + kk] : A[(int64_t)kk * lda + i];
-            const double b = tb ? B[(int64_t)kk * ldb + j] : B[(int64_t)j * ldb + kk];
-            s += a * b;
+    __shared__ __align__(16) double As[SG_KC * SG_LD];
+    __shared__ __align__(16) double Bs[SG_KC * SG_LD];
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int i0 = blockIdx.x * SG_T, j0 = blockIdx.y * SG_T;
+    double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
+    for (int k0 = 0; k0 < k; k0 += SG_KC) {
+#pragma unroll
+        for (int u = 0; u < SG_KC * SG_T / 256; ++u) {
+            const int e = tid + 256 * u;
+            int ii, qa, jj, qb;
+            if (ta) { qa = e % SG_KC; ii = e / SG_KC; } else { ii = e % SG_T; qa = e / SG_T; }
+            if (tb) { jj = e % SG_T; qb = e / SG_T; } else { qb = e % SG_KC; jj = e / SG_KC; }
+            const int gi = i0 + ii, gka = k0 + qa, gj = j0 + jj, gkb = k0 + qb;
+            double a = 0.0, b = 0.0;
+            if (gi < m && gka < k) a = ta ? A[(int64_t)gi * lda + gka] : A[(int64_t)gka * lda + gi];
+            if (gj < n && gkb < k) b = tb ? B[(int64_t)gkb * ldb + gj] : B[(int64_t)gj * ldb + gkb];
+            As[qa * SG_LD + ii] = a;
+            Bs[qb * SG_LD + jj] = b;
         }
-        double* c = C + (int64_t)j * ldc + i;
-        *c = alpha * s + (beta == 0.0 ? 0.0 : beta * *c);
+        __syncthreads();
+        const int kc = min(SG_KC, k - k0);
+        for (int q = 0; q < kc; ++q) {
+            const double2 a = *reinterpret_cast<const double2*>(As + q * SG_LD + 2 * tx);
+            const double2 b = *reinterpret_cast<const double2*>(Bs + q * SG_LD + 2 * ty);
+            c00 = fma(a.x, b.x, c00);
+            c10 = fma(a.y, b.x, c10);
+            c01 = fma(a.x, b.y, c01);
+            c11 = fma(a.y, b.y, c11);
+        }
+        __syncthreads();
     }
+    const int i = i0 + 2 * tx, j = j0 + 2 * ty;
+    auto put = [&](int ii, int jj, double v) {
+        if (ii < m && jj < n) {
+            double* c = C + (int64_t)jj * ldc + ii;
+            *c = alpha * v + (beta == 0.0 ? 0.0 : beta * *c);
+        }
+    };
+    put(i, j, c00);
+    put(i + 1, j, c10);
+    put(i, j + 1, c01);
+    put(i + 1, j + 1, c11);
 }
 
 hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
@@ -476,9 +512,8 @@ hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double
                       double* C, int64_t ldc)
 {
     if (m <= 0 || n <= 0) return hipSuccess;
-    const int64_t tot = (int64_t)m * n;
-    hipLaunchKernelGGL(small_gemm_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(tot, 128), 1024)), dim3(128), 0, s,
-                       ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    const dim3 grid((unsigned)ceil_div(m, SG_T), (unsigned)ceil_div(n, SG_T));
+    hipLaunchKernelGGL(small_gemm_kernel, grid, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
     return hipGetLastError();
 }
 
