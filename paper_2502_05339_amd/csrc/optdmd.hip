@@ -86,28 +86,48 @@ __global__ void vp_assemble_kernel(int r, const int32_t* __restrict__ kind, cons
     }
 }
 
-// sum of squares of an m x n column-major matrix into *out (one work-group)
-__global__ void __launch_bounds__(256) vp_sumsq_kernel(int m, int n, const double* __restrict__ A, int64_t lda,
-                                                       double* __restrict__ out)
+// sum of squares of an m x n column-major matrix into *out (one work-group of 1024
+// threads, four loads in flight per thread, fixed-order combination)
+constexpr int VP_SS_THREADS = 1024;
+__global__ void __launch_bounds__(VP_SS_THREADS) vp_sumsq_kernel(int m, int n, const double* __restrict__ A,
+                                                                 int64_t lda, double* __restrict__ out)
 {
-    __shared__ double part[4];
+    __shared__ double part[VP_SS_THREADS / 64];
+    const int64_t tot = (int64_t)m * n;
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < (int64_t)m * n; e += blockDim.x) {
-        const double v = A[(e / m) * lda + e % m];
-        s = fma(v, v, s);
+    for (int64_t e0 = threadIdx.x; e0 < tot; e0 += 4 * VP_SS_THREADS) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = e0 + (int64_t)u * VP_SS_THREADS;
+            v[u] = e < tot ? A[(e / m) * lda + e % m] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s = fma(v[u], v[u], s);
     }
     s = wave_sum(s);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) *out = (part[0] + part[1]) + (part[2] + part[3]);
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < VP_SS_THREADS / 64; ++w) t += part[w];
+        *out = t;
+    }
 }
 
 // A = G + mu diag(G) (a small floor keeps the diagonal positive)
-__global__ void vp_damp_kernel(int r, const double* __restrict__ G, double mu, double* __restrict__ A)
+__global__ void __launch_bounds__(256) vp_damp_kernel(int r, const double* __restrict__ G, double mu,
+                                                      double* __restrict__ A)
 {
+    __shared__ double part[4];
     const int64_t tot = (int64_t)r * r;
-    double dmax = 0.0;
-    for (int i = 0; i < r; ++i) dmax = fmax(dmax, G[(int64_t)i * r + i]);
+    double dm = 0.0;                                     // max of the diagonal, per work-group
+    for (int i = threadIdx.x; i < r; i += blockDim.x) dm = fmax(dm, G[(int64_t)i * r + i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = dm;
+    __syncthreads();
+    const double dmax = fmax(fmax(part[0], part[1]), fmax(part[2], part[3]));
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % r), j = (int)(e / r);
         double v = G[e];
@@ -168,7 +188,7 @@ hipError_t vp_assemble(hipStream_t s, int r, const int32_t* kind, const double* 
 }
 hipError_t vp_sumsq(hipStream_t s, int m, int n, const double* A, int64_t lda, double* out)
 {
-    hipLaunchKernelGGL(vp_sumsq_kernel, dim3(1), dim3(256), 0, s, m, n, A, lda, out);
+    hipLaunchKernelGGL(vp_sumsq_kernel, dim3(1), dim3(VP_SS_THREADS), 0, s, m, n, A, lda, out);
     return hipGetLastError();
 }
 hipError_t vp_damp(hipStream_t s, int r, const double* G, double mu, double* A)

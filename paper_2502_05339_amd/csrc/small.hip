@@ -593,22 +593,33 @@ hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int
 }
 
 // beta (+)= R^-1 R^-T rhs  (the normal equations G beta = rhs with G = R^T R)
-__global__ void normal_solve_kernel(int r, const double* __restrict__ Rinv, int64_t ldr,
-                                    const double* __restrict__ rhs, double* __restrict__ beta, int accumulate)
+// beta = R^-1 R^-T rhs (R^-1 upper triangular, column-major): t = R^-T rhs, then
+// beta = R^-1 t, one wave per row (rows w, w + 16, ...), lanes over the row's terms and a
+// fixed-shape wave sum; t is kept in LDS.
+constexpr int NS_THREADS = 1024;
+__global__ void __launch_bounds__(NS_THREADS)
+normal_solve_kernel(int r, const double* __restrict__ Rinv, int64_t ldr, const double* __restrict__ rhs,
+                    double* __restrict__ beta, int accumulate)
 {
     extern __shared__ double sh[];
-    double* t = sh;          // r
-    const int tid = threadIdx.x;
-    for (int i = tid; i < r; i += blockDim.x) {          // t = R^-T rhs
+    double* x = sh;          // rhs (r)
+    double* t = sh + r;      // R^-T rhs (r)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = NS_THREADS / 64;
+    for (int i = tid; i < r; i += NS_THREADS) x[i] = rhs[i];
+    __syncthreads();
+    for (int i = wave; i < r; i += nw) {                 // t_i = sum_{j <= i} R^-1(j, i) rhs_j
+        const double* col = Rinv + (int64_t)i * ldr;
         double s = 0.0;
-        for (int j = 0; j <= i; ++j) s += Rinv[(int64_t)i * ldr + j] * rhs[j];
-        t[i] = s;
+        for (int j = lane; j <= i; j += 64) s = fma(col[j], x[j], s);
+        s = wave_sum(s);
+        if (lane == 0) t[i] = s;
     }
     __syncthreads();
-    for (int i = tid; i < r; i += blockDim.x) {          // beta = R^-1 t
+    for (int i = wave; i < r; i += nw) {                 // beta_i = sum_{j >= i} R^-1(i, j) t_j
         double s = 0.0;
-        for (int j = i; j < r; ++j) s += Rinv[(int64_t)j * ldr + i] * t[j];
-        beta[i] = accumulate ? beta[i] + s : s;
+        for (int j = i + lane; j < r; j += 64) s = fma(Rinv[(int64_t)j * ldr + i], t[j], s);
+        s = wave_sum(s);
+        if (lane == 0) beta[i] = accumulate ? beta[i] + s : s;
     }
 }
 
@@ -643,8 +654,8 @@ __global__ void residual_kernel(int64_t N, int r, const T* __restrict__ phi, int
 hipError_t normal_solve(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs, double* beta,
                         int accumulate)
 {
-    hipLaunchKernelGGL(normal_solve_kernel, dim3(1), dim3(256), r * sizeof(double), s, r, Rinv, ldr, rhs, beta,
-                       accumulate);
+    hipLaunchKernelGGL(normal_solve_kernel, dim3(1), dim3(NS_THREADS), 2 * r * sizeof(double), s, r, Rinv, ldr, rhs,
+                       beta, accumulate);
     return hipGetLastError();
 }
 
