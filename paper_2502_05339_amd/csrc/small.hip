@@ -21,8 +21,9 @@ namespace dmd {
 // G = L L^T and X = L^-1 by 16 x 16 blocks in one work-group of 16 waves, every block in
 // LDS (padded rows): the lower blocks of G, overwritten by L and then by X, and the
 // inverses S_p = L_pp^-1 of the diagonal blocks.  Cholesky, for each block column p:
-//   D  one wave factors block (p, p) in place and forms S_p by the same column sweep on
-//      [G_pp | I] (unscaled entries times 1/d, rows of S scaled by 1/sqrt(d));
+//   D  one wave forms S_p = L_pp^-1 by a column sweep on [G_pp | I] held in its registers
+//      (unscaled entries times 1/d, rows of S scaled by 1/sqrt(d)); L_pp itself is never
+//      needed again (P uses S_p, the inverse uses S_p and the blocks below the diagonal);
 //   P  L_ip = G_ip S_p^T (i > p), one wave per block, FP64 MFMA, in place;
 //   U  G_ij -= L_ip L_jp^T (i >= j > p), FP64 MFMA; wave 0 takes block (p+1, p+1) alone
 //      and runs D for p+1 right after it.
@@ -45,31 +46,52 @@ static size_t cm_lds_bytes(int n)
     return (size_t)(T * (T + 1) / 2 + T) * CM_BLK * sizeof(double);
 }
 
-// column sweep of one 16 x 16 diagonal block by one wave: Db (G'_pp) is consumed, Sb
-// receives S = L_pp^-1.  Returns false on a non-positive or non-finite pivot.
-__device__ __forceinline__ bool cm_diag(double* Db, double* Sb, int lane)
+// column sweep of one 16 x 16 diagonal block by one wave: Db (G'_pp) is read, Sb receives
+// S = L_pp^-1.  The block and S live in registers (lane: row i = lane / 4, columns
+// 4 (lane % 4) .. + 3); each step takes its pivot by readlane and column j and row j of S
+// by lane shuffles, so no step waits on LDS.  Returns false on a non-positive or
+// non-finite pivot.
+__device__ __forceinline__ double readlane_f64(double x, int l)
 {
-    const int i = lane >> 2, c0 = (lane & 3) * 4;
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ bool cm_diag(const double* Db, double* Sb, int lane)
+{
+    const int i = lane >> 2, q = lane & 3, c0 = q * 4;
+    double dv[4], sv[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) Sb[i * CM_LD + c0 + b] = (i == c0 + b) ? 1.0 : 0.0;
-    wave_sync_lds();
+    for (int b = 0; b < 4; ++b) {
+        dv[b] = Db[i * CM_LD + c0 + b];
+        sv[b] = (i == c0 + b) ? 1.0 : 0.0;
+    }
+#pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const double d = Db[j * CM_LD + j];
-        if (!(d > 0.0) || !isfinite(d)) return false;           // uniform
-        const double sj = rsqrt_nr(d);
-        const double lij = Db[i * CM_LD + j] * (sj * sj);
+        const double x = dv[j & 3];                        // column j, in the lanes with q = j / 4
+        const double d = readlane_f64(x, (j << 2) | (j >> 2));
+        if (!(d > 0.0) || !isfinite(d)) return false;      // uniform
+        const double lraw = __shfl(x, (i << 2) | (j >> 2), 64);
         double gc[4], xr[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) { gc[b] = Db[(c0 + b) * CM_LD + j]; xr[b] = Sb[j * CM_LD + c0 + b]; }
+        for (int b = 0; b < 4; ++b) {
+            gc[b] = __shfl(x, ((c0 + b) << 2) | (j >> 2), 64);   // D(c0 + b, j)
+            xr[b] = __shfl(sv[b], (j << 2) | q, 64);              // S(j, c0 + b)
+        }
+        const double sj = rsqrt_nr(d);
+        const double lij = lraw * (sj * sj);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int c = c0 + b;
-            if (i > j && c > j && c <= i) Db[i * CM_LD + c] -= lij * gc[b];
-            if (i > j && c <= j) Sb[i * CM_LD + c] -= lij * xr[b];
-            if (i == j && c <= j) Sb[i * CM_LD + c] = xr[b] * sj;
+            if (i > j && c > j && c <= i) dv[b] -= lij * gc[b];
+            if (i > j && c <= j) sv[b] -= lij * xr[b];
+            if (i == j && c <= j) sv[b] = xr[b] * sj;
         }
-        wave_sync_lds();
     }
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Sb[i * CM_LD + c0 + b] = sv[b];
     return true;
 }
 
