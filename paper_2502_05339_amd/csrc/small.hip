@@ -132,17 +132,25 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
     __syncthreads();
     const double sh = shift;
     // lower blocks of G (the lower triangle only, also for both halves of a diagonal block)
-    for (int e = tid; e < NG * 256; e += CM_THREADS) {
-        const int b = e >> 8, r = (e >> 4) & 15, c = e & 15;
-        int I = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
-        if (I * (I + 1) / 2 > b) --I;
-        if ((I + 1) * (I + 2) / 2 <= b) ++I;
+    // one block per wave at a time (block index and its (I, J) uniform), four entries per lane
+    for (int b = wave; b < NG; b += CM_NW) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= b) ++I;
         const int J = b - I * (I + 1) / 2;
-        const int row = I * 16 + c, col = J * 16 + r;         // consecutive threads: consecutive rows
-        const int rlo = max(row, col), clo = min(row, col);
-        const double x = (row < n && col < n) ? G[(int64_t)clo * ldg + rlo] + (row == col ? sh : 0.0)
-                                              : (row == col ? 1.0 : 0.0);
-        Gs[b * CM_BLK + c * CM_LD + r] = x;
+        double xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u, r = e >> 4, c = e & 15;
+            const int row = I * 16 + c, col = J * 16 + r;       // consecutive lanes: consecutive rows
+            const int rlo = max(row, col), clo = min(row, col);
+            xv[u] = (row < n && col < n) ? G[(int64_t)clo * ldg + rlo] + (row == col ? sh : 0.0)
+                                         : (row == col ? 1.0 : 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = lane + 64 * u;
+            Gs[b * CM_BLK + (e & 15) * CM_LD + (e >> 4)] = xv[u];
+        }
     }
     __syncthreads();
     if (wave == 0 && !cm_diag(gblk(0, 0), Ss, lane) && lane == 0) sh_fail = 1;
@@ -210,13 +218,23 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
         doublex4 x = zero_acc<doublex4>();
         if (I < T) {
             // W^T = sum_k L_kj^T X_ik^T (X_ii = S_i), then X_ij = -W S_j
-            doublex4 wt = zero_acc<doublex4>();
-            for (int K = j + 1; K <= I; ++K) {
+            // two independent accumulation chains (K - j odd / even), added at the end
+            doublex4 wa = zero_acc<doublex4>(), wb = zero_acc<doublex4>();
+            for (int K = j + 1; K <= I; K += 2) {
                 const double* Lk = gblk(K, j);
                 const double* Xk = K == I ? Ss + I * CM_BLK : gblk(I, K);
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) wt = mfma_f64(cm_b(Lk, kk, l16, lg), cm_a(Xk, kk, l16, lg), wt);
+                for (int kk = 0; kk < 4; ++kk) wa = mfma_f64(cm_b(Lk, kk, l16, lg), cm_a(Xk, kk, l16, lg), wa);
+                if (K + 1 <= I) {
+                    const double* Lk1 = gblk(K + 1, j);
+                    const double* Xk1 = K + 1 == I ? Ss + I * CM_BLK : gblk(I, K + 1);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) wb = mfma_f64(cm_b(Lk1, kk, l16, lg), cm_a(Xk1, kk, l16, lg), wb);
+                }
             }
+            doublex4 wt;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) wt[v] = wa[v] + wb[v];
             const double* Sj = Ss + j * CM_BLK;
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) x = mfma_f64(-wt[kk], cm_b(Sj, kk, l16, lg), x);
@@ -229,17 +247,19 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
         }
         __syncthreads();
     }
-    // R^-1(r, c) = X(c, r) for r <= c, zero below
-    for (int e = tid; e < n * n; e += CM_THREADS) {
-        const int r = e % n, c = e / n;
-        double v = 0.0;
-        if (r <= c) {
-            const int I = c >> 4, J = r >> 4;
-            const double* M = I == J ? Ss + I * CM_BLK : gblk(I, J);
-            v = M[(c & 15) * CM_LD + (r & 15)];
+    // R^-1(r, c) = X(c, r) for r <= c, zero below: one column per wave at a time
+    for (int c = wave; c < n; c += CM_NW) {
+        const int I = c >> 4;
+        for (int r = lane; r < n; r += 64) {
+            double v = 0.0;
+            if (r <= c) {
+                const int J = r >> 4;
+                const double* M = I == J ? Ss + I * CM_BLK : gblk(I, J);
+                v = M[(c & 15) * CM_LD + (r & 15)];
+            }
+            Rinv[(int64_t)c * ldr + r] = v;
+            if (Rinv32) Rinv32[(int64_t)c * ldr32 + r] = (float)v;
         }
-        Rinv[(int64_t)c * ldr + r] = v;
-        if (Rinv32) Rinv32[(int64_t)c * ldr32 + r] = (float)v;
     }
 }
 
