@@ -182,21 +182,9 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
             if (lane == 0) refl[3] = t;
         }
         __syncthreads();
-        // ---- H <- P H P on columns > k; column k -> (.., beta, 0, ..)
         const double tg = tk * tk * refl[3];
-#pragma unroll
-        for (int a = 0; a < HS_N; ++a) {
-            const int i = ib + 32 * a;
-            const double ui = us[i < n ? i : 0];
-#pragma unroll
-            for (int c = 0; c < HS_N; ++c) {
-                const int j = jb + 32 * c;
-                if (j > k && j < n) h[a][c] -= tk * fma(vr[a], ws[j], ui * vc[c]) - tg * vr[a] * vc[c];
-                if (j == k && tk != 0.0 && i == k + 1) h[a][c] = beta;
-                if (j == k && i > k + 1) h[a][c] = 0.0;
-            }
-        }
-        // ---- wave 0: column k + 1 after the step, and the reflector of step k + 1
+        // ---- wave 0 first: column k + 1 after the step, and the reflector of step k + 1 (a
+        // latency chain that the other waves' updates hide; it reads no entry of h)
         if (wave == 0 && k + 3 < n) {
             const double wk = ws[k + 1], vk = k + 1 < n ? 1.0 : 0.0;    // v_{k+1} = 1
             for (int i = k + 2 + lane; i < n; i += 64) {
@@ -205,6 +193,34 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
             }
             wave_sync_lds();
             reflector(k + 1);
+        }
+        // ---- H <- P H P on columns > k; column k -> (.., beta, 0, ..).  Per entry
+        // tau (v_i w_j + u_i v_j) - tau^2 gamma v_i v_j = v_i A_j + v_j B_i with
+        // A_j = tau w_j and B_i = tau u_i - tau^2 gamma v_i: two FMAs; columns <= k and
+        // past n take A = v = 0 and rows past n take B = v = 0, which leaves them unchanged
+        double Aj[HS_N], vcm[HS_N], Bi[HS_N];
+#pragma unroll
+        for (int c = 0; c < HS_N; ++c) {
+            const int j = jb + 32 * c;
+            const bool upd = j > k && j < n;
+            Aj[c] = upd ? tk * ws[j] : 0.0;
+            vcm[c] = upd ? vc[c] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < HS_N; ++a) {
+            const int i = ib + 32 * a;
+            Bi[a] = i < n ? fma(tk, us[i], -tg * vr[a]) : 0.0;    // padding rows stay as they are
+        }
+#pragma unroll
+        for (int a = 0; a < HS_N; ++a) {
+            const int i = ib + 32 * a;
+#pragma unroll
+            for (int c = 0; c < HS_N; ++c) {
+                const int j = jb + 32 * c;
+                h[a][c] = fma(-vr[a], Aj[c], fma(-vcm[c], Bi[a], h[a][c]));
+                if (j == k && tk != 0.0 && i == k + 1) h[a][c] = beta;
+                if (j == k && i > k + 1) h[a][c] = 0.0;
+            }
         }
         __syncthreads();
     }
