@@ -759,22 +759,35 @@ eigvec_kernel(int n, const double* __restrict__ Tg, const int32_t* __restrict__ 
 }
 
 // ====================================================================== 3. canonical order
-__global__ void sort_modes_kernel(int n, const double* __restrict__ wr, const double* __restrict__ wi,
-                                  const int32_t* __restrict__ kind0, const double* __restrict__ Wraw,
-                                  double* lam, int32_t* kind, double* W)
+__global__ void __launch_bounds__(256)
+sort_modes_kernel(int n, const double* __restrict__ wr, const double* __restrict__ wi,
+                  const int32_t* __restrict__ kind0, const double* __restrict__ Wraw, double* lam,
+                  int32_t* kind, double* W)
 {
-    extern __shared__ int pos[];   // n: output position of each unit head
-    const int tid = threadIdx.x, nt = blockDim.x;
+    // LDS: the sort keys |arg|, modulus (n doubles each), then the kinds and the output
+    // position of each unit head (n ints each)
+    extern __shared__ double skey[];
+    double* ang = skey;
+    double* mag = skey + n;
+    int* k0 = reinterpret_cast<int*>(skey + 2 * n);
+    int* pos = k0 + n;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
+    for (int u = tid; u < n; u += nt) {
+        k0[u] = kind0[u];
+        ang[u] = fabs(atan2(wi[u], wr[u]));
+        mag[u] = hypot(wr[u], wi[u]);
+    }
+    __syncthreads();
     for (int u = tid; u < n; u += nt) {
         pos[u] = -1;
-        if (kind0[u] == 2) continue;
-        const double au = fabs(atan2(wi[u], wr[u])), mu = hypot(wr[u], wi[u]);
+        if (k0[u] == 2) continue;
+        const double au = ang[u], mu = mag[u];
         int p = 0;
         for (int v = 0; v < n; ++v) {
-            if (kind0[v] == 2 || v == u) continue;
-            const double av = fabs(atan2(wi[v], wr[v])), mv = hypot(wr[v], wi[v]);
+            if (k0[v] == 2 || v == u) continue;
+            const double av = ang[v], mv = mag[v];
             const bool before = (av < au) || (av == au && mv > mu) || (av == au && mv == mu && v < u);
-            if (before) p += (kind0[v] == 1) ? 2 : 1;
+            if (before) p += (k0[v] == 1) ? 2 : 1;
         }
         pos[u] = p;
     }
@@ -782,7 +795,7 @@ __global__ void sort_modes_kernel(int n, const double* __restrict__ wr, const do
     for (int u = tid; u < n; u += nt) {
         const int p = pos[u];
         if (p < 0) continue;
-        if (kind0[u] == 0) {
+        if (k0[u] == 0) {
             lam[2 * p] = wr[u]; lam[2 * p + 1] = 0.0; kind[p] = 0;
         } else {
             lam[2 * p] = wr[u]; lam[2 * p + 1] = fabs(wi[u]);
@@ -790,12 +803,15 @@ __global__ void sort_modes_kernel(int n, const double* __restrict__ wr, const do
             kind[p] = 1; kind[p + 1] = 2;
         }
     }
-    for (int64_t e = tid; e < (int64_t)n * n; e += nt) {
-        const int row = (int)(e % n), u = (int)(e / n);
+    // permuted eigenvector columns: one source column per wave at a time
+    for (int u = wave; u < n; u += nw) {
         const int p = pos[u];
         if (p < 0) continue;
-        W[(int64_t)p * n + row] = Wraw[(int64_t)u * n + row];
-        if (kind0[u] == 1) W[(int64_t)(p + 1) * n + row] = Wraw[(int64_t)(u + 1) * n + row];
+        const bool pair = k0[u] == 1;
+        for (int row = lane; row < n; row += 64) {
+            W[(int64_t)p * n + row] = Wraw[(int64_t)u * n + row];
+            if (pair) W[(int64_t)(p + 1) * n + row] = Wraw[(int64_t)(u + 1) * n + row];
+        }
     }
 }
 
@@ -822,8 +838,8 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
     hipLaunchKernelGGL(eigvec_kernel, dim3(n), dim3(64), evlds, s, n, w.T, w.blk, w.Z, w.Wraw, defl_tol);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sort_modes_kernel, dim3(1), dim3(256), n * sizeof(int), s, n, w.wr, w.wi, w.kind0,
-                       w.Wraw, lam, kind, W);
+    hipLaunchKernelGGL(sort_modes_kernel, dim3(1), dim3(256), (size_t)n * (2 * sizeof(double) + 2 * sizeof(int)), s,
+                       n, w.wr, w.wi, w.kind0, w.Wraw, lam, kind, W);
     return hipGetLastError();
 }
 
