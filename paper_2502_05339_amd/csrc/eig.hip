@@ -759,7 +759,8 @@ eigvec_kernel(int n, const double* __restrict__ Tg, const int32_t* __restrict__ 
 }
 
 // ====================================================================== 3. canonical order
-__global__ void __launch_bounds__(256)
+constexpr int SM_THREADS = 1024;
+__global__ void __launch_bounds__(SM_THREADS)
 sort_modes_kernel(int n, const double* __restrict__ wr, const double* __restrict__ wi,
                   const int32_t* __restrict__ kind0, const double* __restrict__ Wraw, double* lam,
                   int32_t* kind, double* W)
@@ -771,28 +772,34 @@ sort_modes_kernel(int n, const double* __restrict__ wr, const double* __restrict
     double* mag = skey + n;
     int* k0 = reinterpret_cast<int*>(skey + 2 * n);
     int* pos = k0 + n;
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = nt >> 6;
-    for (int u = tid; u < n; u += nt) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = SM_THREADS >> 6;
+    for (int u = tid; u < n; u += SM_THREADS) {
         k0[u] = kind0[u];
         ang[u] = fabs(atan2(wi[u], wr[u]));
         mag[u] = hypot(wr[u], wi[u]);
     }
     __syncthreads();
-    for (int u = tid; u < n; u += nt) {
-        pos[u] = -1;
-        if (k0[u] == 2) continue;
-        const double au = ang[u], mu = mag[u];
+    // position of unit u: four lanes per unit, each counting the units v = q mod 4 placed
+    // before it, then a sum over the four lanes
+    for (int t = tid; t < 4 * round_up(n, 16); t += SM_THREADS) {
+        const int u = t >> 2, q = t & 3;
         int p = 0;
-        for (int v = 0; v < n; ++v) {
-            if (k0[v] == 2 || v == u) continue;
-            const double av = ang[v], mv = mag[v];
-            const bool before = (av < au) || (av == au && mv > mu) || (av == au && mv == mu && v < u);
-            if (before) p += (k0[v] == 1) ? 2 : 1;
+        const bool head = u < n && k0[u] != 2;
+        if (head) {
+            const double au = ang[u], mu = mag[u];
+            for (int v = q; v < n; v += 4) {
+                if (k0[v] == 2 || v == u) continue;
+                const double av = ang[v], mv = mag[v];
+                const bool before = (av < au) || (av == au && mv > mu) || (av == au && mv == mu && v < u);
+                if (before) p += (k0[v] == 1) ? 2 : 1;
+            }
         }
-        pos[u] = p;
+        p += __shfl_xor(p, 1, 64);
+        p += __shfl_xor(p, 2, 64);
+        if (q == 0 && u < n) pos[u] = head ? p : -1;
     }
     __syncthreads();
-    for (int u = tid; u < n; u += nt) {
+    for (int u = tid; u < n; u += SM_THREADS) {
         const int p = pos[u];
         if (p < 0) continue;
         if (k0[u] == 0) {
@@ -803,14 +810,27 @@ sort_modes_kernel(int n, const double* __restrict__ wr, const double* __restrict
             kind[p] = 1; kind[p + 1] = 2;
         }
     }
-    // permuted eigenvector columns: one source column per wave at a time
+    // permuted eigenvector columns: one source column (and its partner) per wave at a time,
+    // every row of it loaded before the stores
+    static_assert(EIG_MAX <= 3 * 64, "sort_modes_kernel keeps 3 rows per lane");
     for (int u = wave; u < n; u += nw) {
         const int p = pos[u];
         if (p < 0) continue;
         const bool pair = k0[u] == 1;
-        for (int row = lane; row < n; row += 64) {
-            W[(int64_t)p * n + row] = Wraw[(int64_t)u * n + row];
-            if (pair) W[(int64_t)(p + 1) * n + row] = Wraw[(int64_t)(u + 1) * n + row];
+        double a[3], b[3];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int row = lane + 64 * s;
+            a[s] = row < n ? Wraw[(int64_t)u * n + row] : 0.0;
+            b[s] = (pair && row < n) ? Wraw[(int64_t)(u + 1) * n + row] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            const int row = lane + 64 * s;
+            if (row < n) {
+                W[(int64_t)p * n + row] = a[s];
+                if (pair) W[(int64_t)(p + 1) * n + row] = b[s];
+            }
         }
     }
 }
@@ -838,8 +858,8 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
     hipLaunchKernelGGL(eigvec_kernel, dim3(n), dim3(64), evlds, s, n, w.T, w.blk, w.Z, w.Wraw, defl_tol);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sort_modes_kernel, dim3(1), dim3(256), (size_t)n * (2 * sizeof(double) + 2 * sizeof(int)), s,
-                       n, w.wr, w.wi, w.kind0, w.Wraw, lam, kind, W);
+    hipLaunchKernelGGL(sort_modes_kernel, dim3(1), dim3(SM_THREADS), (size_t)n * (2 * sizeof(double) + 2 * sizeof(int)),
+                       s, n, w.wr, w.wi, w.kind0, w.Wraw, lam, kind, W);
     return hipGetLastError();
 }
 
