@@ -742,19 +742,45 @@ eigvec_kernel(int n, const double* __restrict__ Tg, const int32_t* __restrict__ 
         if (row < n) { xs[row] = xr[s] * inv; xs[n + row] = xi[s] * inv; }
     }
     __syncthreads();
-    // W[:, k] = Z Re(x) (and W[:, k+1] = Z Im(x) for a pair); Z is column-major
+    // W[:, k] = Z Re(x) (and W[:, k+1] = Z Im(x) for a pair); Z is column-major.  Columns
+    // of Z are taken eight at a time, every row slot's entries loaded before the FMAs (each
+    // sum still runs over j in ascending order)
+    double wre[EV_SLOTS], wim[EV_SLOTS];
+#pragma unroll
+    for (int s = 0; s < EV_SLOTS; ++s) { wre[s] = 0.0; wim[s] = 0.0; }
+    int j = 0;
+    for (; j + 7 <= top; j += 8) {
+        double z[8][EV_SLOTS];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int s = 0; s < EV_SLOTS; ++s) {
+                const int row = lane + 64 * s;
+                z[u][s] = row < n ? Zg[(int64_t)(j + u) * n + row] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double xre = xs[j + u], xim = xs[n + j + u];
+#pragma unroll
+            for (int s = 0; s < EV_SLOTS; ++s) { wre[s] += z[u][s] * xre; wim[s] += z[u][s] * xim; }
+        }
+    }
+    for (; j <= top; ++j) {
+        const double xre = xs[j], xim = xs[n + j];
+#pragma unroll
+        for (int s = 0; s < EV_SLOTS; ++s) {
+            const int row = lane + 64 * s;
+            const double z = row < n ? Zg[(int64_t)j * n + row] : 0.0;
+            wre[s] += z * xre;
+            wim[s] += z * xim;
+        }
+    }
 #pragma unroll
     for (int s = 0; s < EV_SLOTS; ++s) {
         const int row = lane + 64 * s;
         if (row >= n) continue;
-        double wre = 0.0, wim = 0.0;
-        for (int j = 0; j <= top; ++j) {
-            const double z = Zg[(int64_t)j * n + row];
-            wre += z * xs[j];
-            wim += z * xs[n + j];
-        }
-        Wraw[(int64_t)k * n + row] = wre;
-        if (pair) Wraw[(int64_t)(k + 1) * n + row] = wim;
+        Wraw[(int64_t)k * n + row] = wre[s];
+        if (pair) Wraw[(int64_t)(k + 1) * n + row] = wim[s];
     }
 }
 
