@@ -243,6 +243,7 @@ __host__ __device__ __forceinline__ int hp_col(int j, int n) {
 }
 constexpr int FR_THREADS = 256;
 constexpr int FR_ZROWS = 4;   // Z-slab rows per wave in the setup (rows per work-group <= 16)
+constexpr int FR_VCH = 16;    // reflectors staged in LDS at a time in the Z-slab setup
 // row-update roles use threads 1..n, Z-slab roles the last 16, plus one deferred-write thread
 static_assert(EIG_MAX + 1 + 1 + 16 <= FR_THREADS, "francis_kernel thread roles overlap");
 
@@ -314,31 +315,58 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
     const int r0 = blockIdx.x * nr;
     const int nrows = min(nr, n - r0);
 
-    for (int j = 0; j < n; ++j)
-        for (int i = tid; i <= min(j + 3, n - 1); i += nt) H(i, j) = (i <= j + 1) ? Hg[(int64_t)j * n + i] : 0.0;
+    // packed H, eight columns at a time with their loads in flight (nt > n + 3: one entry
+    // of a column per thread)
+    static_assert(FR_THREADS > EIG_MAX + 3, "francis_kernel loads one entry per column and thread");
+    for (int j0 = 0; j0 < n; j0 += 8) {
+        double hv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u;
+            hv[u] = (j < n && tid <= j + 1 && tid < n) ? Hg[(int64_t)j * n + tid] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int j = j0 + u;
+            if (j < n && tid <= min(j + 3, n - 1)) H(tid, j) = hv[u];
+        }
+    }
     // Z slab = rows r0.. of Q = P_0 P_1 ... P_{n-3}: start from identity rows, apply reflectors on the right
     for (int e = tid; e < nr * n; e += nt) { const int rl = e / n, c = e % n; Zs[e] = (rl < nrows && r0 + rl == c) ? 1.0 : 0.0; }
     __syncthreads();
     // Each wave takes rows wave, wave + nw, ... of the slab (at most FR_ZROWS) through all
-    // reflectors together: one load of v_k per reflector (issued one reflector ahead),
-    // interleaved row products, one pass of updates.
+    // reflectors together: interleaved row products, one pass of updates.  The reflectors
+    // come in chunks of FR_VCH columns of V (and their tau) copied to LDS by the whole
+    // work-group with all loads in flight, so a reflector never waits on global memory.
     {
         static_assert(EIG_MAX <= 3 * 64, "Z slab setup keeps 3 columns per lane");
-        auto load_v = [&](int k, double& a0, double& a1, double& a2) {
-            const double* v = Vg + (int64_t)k * n;
-            const int j0 = k + 1 + lane;
-            a0 = (j0 < n) ? v[j0] : 0.0;
-            a1 = (j0 + 64 < n) ? v[j0 + 64] : 0.0;
-            a2 = (j0 + 128 < n) ? v[j0 + 128] : 0.0;
-        };
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-        if (n > 2) load_v(0, v0, v1, v2);
-        for (int k = 0; k + 2 < n; ++k) {
-            const double tk = taug[k];
-            double w0 = 0.0, w1 = 0.0, w2 = 0.0;
-            if (k + 3 < n) load_v(k + 1, w0, w1, w2);
-            const int j0 = k + 1 + lane;
-            if (tk != 0.0) {
+        double* Vst = Zs + nr * n;                                  // FR_VCH x n
+        double* tst = Vst + FR_VCH * n;                             // FR_VCH
+        for (int k0 = 0; k0 + 2 < n; k0 += FR_VCH) {
+            const int kc = min(FR_VCH, n - 2 - k0);
+            __syncthreads();                                        // the previous chunk is consumed
+            for (int e0 = tid; e0 < kc * n; e0 += 4 * nt) {
+                double t4[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int e = e0 + u * nt;
+                    t4[u] = e < kc * n ? Vg[(int64_t)k0 * n + e] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (e0 + u * nt < kc * n) Vst[e0 + u * nt] = t4[u];
+            }
+            if (tid < kc) tst[tid] = taug[k0 + tid];
+            __syncthreads();
+            for (int kk = 0; kk < kc; ++kk) {
+                const int k = k0 + kk;
+                const double tk = tst[kk];
+                if (tk == 0.0) continue;                            // uniform
+                const double* v = Vst + kk * n;
+                const int j0 = k + 1 + lane;
+                const double v0 = (j0 < n) ? v[j0] : 0.0;
+                const double v1 = (j0 + 64 < n) ? v[j0 + 64] : 0.0;
+                const double v2 = (j0 + 128 < n) ? v[j0 + 128] : 0.0;
                 doublex4 d = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int a = 0; a < FR_ZROWS; ++a) {
@@ -365,7 +393,6 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
                     }
                 }
             }
-            v0 = w0; v1 = w1; v2 = w2;
         }
     }
     __syncthreads();
@@ -653,7 +680,14 @@ eigvec_kernel(int n, const double* __restrict__ Tg, const int32_t* __restrict__ 
     double* Ts = evs;
     double* xs = evs + round_up(hp_col(n, n), 2);          // 2n: normalised Re, Im of x
     int* bs = reinterpret_cast<int*>(xs + 2 * n);          // n: block structure
-    for (int e = lane; e < tsize; e += 64) Ts[e] = Tg[e];
+    for (int e0 = lane; e0 < tsize; e0 += 8 * 64) {          // eight loads in flight per lane
+        double tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tv[u] = e0 + 64 * u < tsize ? Tg[e0 + 64 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (e0 + 64 * u < tsize) Ts[e0 + 64 * u] = tv[u];
+    }
     for (int e = lane; e < n; e += 64) bs[e] = blkg[e];
     __syncthreads();
     HP T{Ts, n};
@@ -874,7 +908,9 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
     const int grid = eig_grid(n);
     const int hsize = hp_col(n, n);
     const int nw = FR_THREADS / 64;
-    const size_t lds = (size_t)(round_up(n, 2) / 2) * 8 + (size_t)hsize * 8 + (size_t)nr * n * 8;
+    // blk ints, packed H, the Z slab, then the staged reflectors (FR_VCH columns and their tau)
+    const size_t lds = (size_t)(round_up(n, 2) / 2) * 8 + (size_t)hsize * 8 + (size_t)nr * n * 8 +
+                       (size_t)FR_VCH * (n + 1) * 8;
     if (lds > 160 * 1024 - 512) return hipErrorInvalidValue;
     hipLaunchKernelGGL(francis_kernel, dim3(grid), dim3(64 * nw), lds, s, n, nr, w.H, w.V, w.tau, w.Z, w.T,
                        w.blk, w.wr, w.wi, w.kind0, info, defl_tol);
