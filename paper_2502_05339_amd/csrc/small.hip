@@ -440,7 +440,22 @@ jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* 
             __syncthreads();
         }
         if (rot_flag == 0) { converged = true; break; }
+        // would the next sweep rotate at all?  The rotation test on A as it stands: a sweep
+        // without rotations changes nothing, so when no pair passes, the sweep that would
+        // only confirm it is counted and skipped
         __syncthreads();
+        if (tid == 0) rot_flag = 0;
+        __syncthreads();
+        for (int q = 1 + (tid >> 6); q < n2; q += nt >> 6) {
+            const double aqq = A[up_idx(q, q)];
+            for (int p = tid & 63; p < q; p += 64) {
+                const double apq = A[up_idx(p, q)], app = A[up_idx(p, p)];
+                if (fabs(apq) > floor_abs && fabs(apq) > rtol * sqrt(fabs(app) * fabs(aqq))) rot_flag = 1;
+            }
+        }
+        __syncthreads();
+        if (rot_flag == 0) { ++sweep; converged = true; break; }
+        __syncthreads();                       // every thread has read the flag before its reset
     }
     // order: descending eigenvalue, ties by index (NaN last); the padding row is not an eigenvalue
     for (int i = tid; i < n; i += nt) {
