@@ -8,7 +8,7 @@ float64 / complex128 and writes every step the way the paper defines it.
 Paper: Chen et al., "Fast Subspace Fluid Simulation with a Temporally-Aware
 Basis" (ACM TOG 2025).
 
-Readings where the paper is silent or garbled (each also listed in the design doc):
+Readings where the paper is silent or garbled:
   * X = U S V^T is the ordinary thin SVD (the paper's Sec. 3.1 swaps the names
     of the singular-vector factors).
   * Modes are the exact DMD modes  Phi = X' V_r S_r^-1 W  (the paper writes the
