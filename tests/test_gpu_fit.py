@@ -300,6 +300,24 @@ def _twin_errors(m, g, cfg, precision):
     return wrel, max_frame_rel(U, Uo)
 
 
+def _check_canonical(m):
+    """Modes in canonical order: |arg lambda| non-decreasing, then |lambda| non-increasing;
+    a conjugate pair is (kind 1, kind 2) with the Im > 0 member first; real modes kind 0."""
+    lam, kind = m.lam_host(), m.kind.cpu().numpy()
+    heads = [i for i in range(lam.size) if kind[i] != 2]
+    keys = [(abs(np.angle(lam[i])), -abs(lam[i])) for i in heads]
+    for a, b in zip(keys, keys[1:]):
+        assert a[0] < b[0] + 1e-12 and (a[0] < b[0] - 1e-12 or a[1] <= b[1] + 1e-12), (a, b)
+    for i in range(lam.size):
+        if kind[i] == 1:
+            assert i + 1 < lam.size and kind[i + 1] == 2 and lam[i].imag > 0
+            assert lam[i + 1] == np.conj(lam[i])
+        elif kind[i] == 0:
+            assert lam[i].imag == 0
+        else:
+            assert i > 0 and kind[i - 1] == 1
+
+
 @pytest.mark.parametrize("name", list(_EDGE))
 def test_rank_extremes_fp64_vs_twin(gpu_lib, name):
     cfg = _edge_cfg(name)
@@ -314,6 +332,7 @@ def test_rank_extremes_fp64_vs_twin(gpu_lib, name):
     assert int(m.info[0].item()) == 0
     assert wrel <= 1e-9
     assert ferr <= 1e-9
+    _check_canonical(m)
 
 
 @pytest.mark.parametrize("name", ["r150-l160", "r160-p0"])
