@@ -189,6 +189,10 @@ int32_t dmd_fit_workspace_size(int64_t n, int32_t ncols, int32_t xdtype,
  * of the FP64 Gram B B^T by Jacobi (singular values and left vectors of B);
  * Atilde = U_r^T B' V_r S_r^-1; Hessenberg + Francis double-shift QR for
  * lambda and W; exact modes Phi = X' V_r S_r^-1 W; b = Phi^+ x_0.
+ * Sizes: 1 <= r <= min(ncols, N, DMD_MAX_RANK); on the randomized paths
+ * l = r + p <= min(ncols, N, DMD_MAX_SKETCH); on DMD_FIT_FP64_EXACT
+ * ncols <= DMD_MAX_SMALL.  Violations return DMD_ERR_SHAPE (inconsistent sizes) or
+ * DMD_ERR_UNSUPPORTED (beyond a limit) before any device work.
  * Returns the device status unless DMD_FIT_ASYNC is set.
  */
 int32_t dmd_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t ncols,
