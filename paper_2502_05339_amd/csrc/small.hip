@@ -19,8 +19,9 @@ namespace dmd {
 
 // ====================================================================== Cholesky
 // G = L L^T and X = L^-1 by 16 x 16 blocks in one work-group of 16 waves, every block in
-// LDS (padded rows): the lower blocks of G, overwritten by L and then by X, and the
-// inverses S_p = L_pp^-1 of the diagonal blocks.  Cholesky, for each block column p:
+// LDS (padded rows): the lower blocks of G (those below the diagonal overwritten by L and
+// then by X), and the inverses S_p = L_pp^-1 of the diagonal blocks.  Cholesky, for each
+// block column p:
 //   D  one wave forms S_p = L_pp^-1 by a column sweep on [G_pp | I] held in its registers
 //      (unscaled entries times 1/d, rows of S scaled by 1/sqrt(d)); L_pp itself is never
 //      needed again (P uses S_p, the inverse uses S_p and the blocks below the diagonal);
