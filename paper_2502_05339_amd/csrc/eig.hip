@@ -242,7 +242,6 @@ __host__ __device__ __forceinline__ int hp_col(int j, int n) {
     return n <= 4 ? j * n : (j <= n - 3 ? head : tail);
 }
 constexpr int FR_THREADS = 256;
-constexpr int FR_ZROWS = 4;   // Z-slab rows per wave in the setup (rows per work-group <= 16)
 constexpr int FR_VCH = 16;    // reflectors staged in LDS at a time in the Z-slab setup
 // row-update roles use threads 1..n, Z-slab roles the last 16, plus one deferred-write thread
 static_assert(EIG_MAX + 1 + 1 + 16 <= FR_THREADS, "francis_kernel thread roles overlap");
@@ -331,15 +330,24 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
             if (j < n && tid <= min(j + 3, n - 1)) H(tid, j) = hv[u];
         }
     }
-    // Z slab = rows r0.. of Q = P_0 P_1 ... P_{n-3}: start from identity rows, apply reflectors on the right
-    for (int e = tid; e < nr * n; e += nt) { const int rl = e / n, c = e % n; Zs[e] = (rl < nrows && r0 + rl == c) ? 1.0 : 0.0; }
+    // Z slab = rows r0.. of Q = P_0 P_1 ... P_{n-3}: identity rows with the reflectors applied
+    // on the right (below)
     __syncthreads();
-    // Each wave takes rows wave, wave + nw, ... of the slab (at most FR_ZROWS) through all
-    // reflectors together: interleaved row products, one pass of updates.  The reflectors
-    // come in chunks of FR_VCH columns of V (and their tau) copied to LDS by the whole
-    // work-group with all loads in flight, so a reflector never waits on global memory.
+    // Each group of 16 lanes keeps one row of the slab in registers (entries gl + 16 s) and
+    // takes it through the reflectors in order: per reflector a 16-lane dot product (a
+    // fixed-shape sum inside the group) and an update.  The reflectors come in chunks of
+    // FR_VCH columns of V (and their tau) copied to LDS by the whole work-group with all
+    // loads in flight.  V is zero above the start of each reflector, so every slot takes part.
     {
-        static_assert(EIG_MAX <= 3 * 64, "Z slab setup keeps 3 columns per lane");
+        constexpr int ZS = (EIG_MAX + 15) / 16;                     // row entries per lane
+        static_assert(FR_THREADS / 16 >= 16, "one 16-lane group per Z-slab row (16 rows at most)");
+        const int grp = tid >> 4, gl = tid & 15;
+        double zr[ZS];
+#pragma unroll
+        for (int sl = 0; sl < ZS; ++sl) {
+            const int j = gl + 16 * sl;
+            zr[sl] = (grp < nrows && j < n && r0 + grp == j) ? 1.0 : 0.0;
+        }
         double* Vst = Zs + nr * n;                                  // FR_VCH x n
         double* tst = Vst + FR_VCH * n;                             // FR_VCH
         for (int k0 = 0; k0 + 2 < n; k0 += FR_VCH) {
@@ -359,41 +367,33 @@ francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __res
             if (tid < kc) tst[tid] = taug[k0 + tid];
             __syncthreads();
             for (int kk = 0; kk < kc; ++kk) {
-                const int k = k0 + kk;
                 const double tk = tst[kk];
                 if (tk == 0.0) continue;                            // uniform
                 const double* v = Vst + kk * n;
-                const int j0 = k + 1 + lane;
-                const double v0 = (j0 < n) ? v[j0] : 0.0;
-                const double v1 = (j0 + 64 < n) ? v[j0 + 64] : 0.0;
-                const double v2 = (j0 + 128 < n) ? v[j0 + 128] : 0.0;
-                doublex4 d = {0.0, 0.0, 0.0, 0.0};
+                double vv[ZS];
+                double d = 0.0;
 #pragma unroll
-                for (int a = 0; a < FR_ZROWS; ++a) {
-                    const int rl = wave + a * nw;
-                    if (rl < nrows) {
-                        const double* z = Zs + rl * n;
-                        double t = 0.0;
-                        if (j0 < n) t = fma(z[j0], v0, t);
-                        if (j0 + 64 < n) t = fma(z[j0 + 64], v1, t);
-                        if (j0 + 128 < n) t = fma(z[j0 + 128], v2, t);
-                        d[a] = t;
-                    }
+                for (int sl = 0; sl < ZS; ++sl) {
+                    const int j = gl + 16 * sl;
+                    vv[sl] = j < n ? v[j] : 0.0;
+                    d = fma(zr[sl], vv[sl], d);
                 }
+                d += __shfl_xor(d, 8, 16);
+                d += __shfl_xor(d, 4, 16);
+                d += __shfl_xor(d, 2, 16);
+                d += __shfl_xor(d, 1, 16);
+                d *= tk;
 #pragma unroll
-                for (int a = 0; a < FR_ZROWS; ++a) d[a] = wave_sum(d[a]) * tk;
-#pragma unroll
-                for (int a = 0; a < FR_ZROWS; ++a) {
-                    const int rl = wave + a * nw;
-                    if (rl < nrows) {
-                        double* z = Zs + rl * n;
-                        if (j0 < n) z[j0] -= d[a] * v0;
-                        if (j0 + 64 < n) z[j0 + 64] -= d[a] * v1;
-                        if (j0 + 128 < n) z[j0 + 128] -= d[a] * v2;
-                    }
-                }
+                for (int sl = 0; sl < ZS; ++sl) zr[sl] -= d * vv[sl];
             }
         }
+        // the slab into LDS for the QR iteration (rows past nrows are zero)
+        if (grp < nr)
+#pragma unroll
+            for (int sl = 0; sl < ZS; ++sl) {
+                const int j = gl + 16 * sl;
+                if (j < n) Zs[grp * n + j] = zr[sl];
+            }
     }
     __syncthreads();
 
