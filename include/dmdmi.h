@@ -28,8 +28,10 @@
  *     the host before any HIP call; on error nothing is enqueued.  Errors found
  *     on the device during a fit (Cholesky breakdown, rank loss, eigen-solver
  *     non-convergence) are written to model->info[0] and returned by the
- *     synchronous dmd_fit.  No exception or exit() crosses the ABI.  On error
- *     the outputs are unspecified and nothing leaks.
+ *     synchronous dmd_fit.  Domain and overflow errors of the powers lambda^k
+ *     (evaluation calls) are written to a status word at the start of the
+ *     call's workspace, read by dmd_status_word.  No exception or exit() crosses
+ *     the ABI.  On error the outputs are unspecified and nothing leaks.
  *
  * Model storage (real "folded" modes).  For real snapshots the DMD eigenvalues
  * and modes come in exact complex-conjugate pairs.  The model stores each pair
@@ -53,7 +55,7 @@
 extern "C" {
 #endif
 
-#define DMDMI_ABI_VERSION 1
+#define DMDMI_ABI_VERSION 2
 
 /* Status codes. */
 typedef enum dmd_status {
@@ -65,10 +67,13 @@ typedef enum dmd_status {
     DMD_ERR_CHOL_BREAKDOWN = 5, /* CholeskyQR failed even after the shifted retry */
     DMD_ERR_RANK = 6,           /* sigma_r <= rank_tol * sigma_1 */
     DMD_ERR_EIG_NOCONV = 7,     /* Jacobi or Francis QR iteration limit reached */
-    DMD_ERR_DOMAIN = 8,         /* reserved: lambda = 0 raised to a negative or fractional power */
-    DMD_ERR_OVERFLOW = 9,       /* reserved: |b| |lambda|^k beyond the output type's range */
+    DMD_ERR_DOMAIN = 8,         /* lambda = 0 raised to a negative or fractional power (device
+                                   status word, see dmd_status_word) */
+    DMD_ERR_OVERFLOW = 9,       /* |b| |lambda|^k beyond the output type's finite range (device
+                                   status word, see dmd_status_word) */
     DMD_ERR_HIP = 10,           /* a HIP runtime call failed */
-    DMD_ERR_UNSUPPORTED = 11    /* size beyond what a single-workgroup small-matrix kernel holds */
+    DMD_ERR_UNSUPPORTED = 11,   /* size beyond what a single-workgroup small-matrix kernel holds */
+    DMD_ERR_IO = 12             /* model file missing, unwritable, truncated or failing its checks */
 } dmd_status;
 
 /* Element types. */
@@ -209,8 +214,12 @@ int32_t dmd_reconstruct_workspace_size(int32_t r, int32_t K, int32_t mode, size_
  *   mode    dmd_recon_mode; DMD_RECON_FP64 needs an F64 model and an FP64 U,
  *           the other modes an F32 model and an FP32 U
  *   U       device, N x K column-major (frame j contiguous), ldu >= N
- * lambda^k is evaluated in FP64 as exp(k Log lambda) (0^0 = 1, 0^k = 0 for k > 0);
- * lambda = 0 with k < 0 gives non-finite values.
+ * lambda^k is evaluated in FP64 as exp(k Log lambda) (0^0 = 1, 0^k = 0 for k > 0).
+ * Sec. 6.1 takes Omega = Log(lambda) / dt, which has no value at lambda = 0: a power of
+ * lambda = 0 with a negative or fractional exponent, and a term |b_i| |lambda_i|^k beyond the
+ * largest finite value of the output type (FP64 for DMD_RECON_FP64, FP32 otherwise), are
+ * recorded in the device status word at the start of the workspace (the call itself stays
+ * asynchronous and returns DMD_OK); dmd_status_word reads it.
  */
 int32_t dmd_reconstruct(void* stream, const dmd_model* model, const int64_t* k_host,
                         int32_t K, int32_t mode, void* U, int64_t ldu, void* ws,
@@ -357,6 +366,19 @@ int32_t dmd_loss_grad_workspace_size(int64_t n, int32_t r, int32_t ncols, int32_
                                      size_t* bytes);
 
 /*
+ * Device status of the last coefficient pass that used workspace `ws` (dmd_reconstruct,
+ * dmd_reconstruct_prepare, dmd_integrate, dmd_rollout, dmd_upsample, dmd_loss_grad all
+ * clear it and then record into it): waits for `stream`, then stores in *status
+ * DMD_ERR_DOMAIN when a power of lambda = 0 had a negative or fractional exponent (Sec. 6.1:
+ * Omega = Log(lambda) / dt is undefined there), else DMD_ERR_OVERFLOW when a coefficient
+ * b_i lambda_i^k (or a reduced state of a roll-out) exceeded the output type's finite range,
+ * else DMD_OK.  The affected outputs hold zeros (domain) or non-finite values (overflow).
+ *   ws      device, the workspace passed to that call (its first 4 bytes hold the word)
+ * Returns DMD_ERR_ARG for null pointers, DMD_ERR_HIP when the copy fails.
+ */
+int32_t dmd_status_word(void* stream, const void* ws, int32_t* status);
+
+/*
  * Loss and adjoint of the full-space reconstruction with the modes held fixed:
  *   L(lambda, b) = sum_j || x_j - Re(Phi (b .* lambda^{k_j})) ||^2
  *   G = Phi^T R (transpose), grad_b = -2 conj(sum_j G_ij lambda_i^{k_j}),
@@ -368,6 +390,9 @@ int32_t dmd_loss_grad_workspace_size(int64_t n, int32_t r, int32_t ncols, int32_
  *   out      device, 1 + 4r doubles: loss, grad_lambda (r complex), grad_b (r complex)
  * The residual and G run as MFMA GEMMs in the model's precision; loss, lambda^k
  * and the r-reductions are FP64.
+ * Limits: r * ncols <= 102400 (the G = Phi^T R product's output, e.g. 682 frames at
+ * r = 150); larger calls return DMD_ERR_UNSUPPORTED before anything is enqueued.
+ * Domain and overflow of lambda^k are recorded as for dmd_reconstruct (dmd_status_word).
  */
 int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam,
                       const double* b, const void* xt, int64_t ldxt, const int64_t* k_host,
@@ -407,6 +432,30 @@ int32_t dmd_autotune_reconstruct(void* stream, const dmd_model* model, int32_t K
 
 /* Load autotuner entries from a cache file written by dmd_autotune_reconstruct. */
 int32_t dmd_autotune_load(const char* cache_path);
+
+/*
+ * Model files.  The fit is the offline precomputation whose result the run-time
+ * evaluation loads (Sec. 4.4: the reduced model is stepped, or evaluated for many frames
+ * in one product).  A file holds a 64-byte versioned header (magic "DMDMODEL", format
+ * version 1, N, r, dtype, dt, payload size, FNV-1a 64 hash of the payload, writer ABI
+ * version), then lambda, b (2r FP64 each, interleaved), sigma (r FP64), kind (r int32)
+ * and Phi (N x r, row-major, the model's dtype; padding columns are not stored).
+ *
+ * dmd_model_save: waits for `stream`, copies the model's device arrays through host
+ *   memory (staging buffers of at most 65536 rows) and writes `path`.  Returns
+ *   DMD_ERR_IO when the file cannot be written.
+ * dmd_model_file_info: host only, no HIP call; reads and checks the header and the payload
+ *   hash and returns N, r, dtype and dt, so the caller can allocate the model's arrays.
+ * dmd_model_load: fills the caller's model (n and dtype must match the file; phi holds
+ *   N x ldphi with ldphi >= dmd_phi_ld(r), a multiple of 32; lam, b: r complex; sigma: r;
+ *   kind: r; info may be NULL, else it is zeroed) and sets r and dt; the padding columns of
+ *   phi are written as zeros.  Waits for `stream` before returning.
+ * Errors: DMD_ERR_ARG (null pointer, dtype / ldphi mismatch), DMD_ERR_SHAPE (N differs),
+ * DMD_ERR_IO (missing, truncated, foreign or corrupted file), DMD_ERR_HIP.
+ */
+int32_t dmd_model_save(void* stream, const dmd_model* model, const char* path);
+int32_t dmd_model_file_info(const char* path, int64_t* n, int32_t* r, int32_t* dtype, double* dt);
+int32_t dmd_model_load(void* stream, const char* path, dmd_model* model);
 
 #ifdef __cplusplus
 }

@@ -85,19 +85,28 @@ def reduced_operator(Ur_t_Xp, V_r, s_r):
     return (Ur_t_Xp @ V_r) / s_r[None, :]
 
 
-def dmd_from_svd(Xp, U_t_Xp, s, V, r, x0):
+def dmd_from_svd(Xp, U_t_Xp, s, V, r, x0, rows=None):
     """Steps shared by the exact and randomized oracles once an SVD is known.
 
     U_t_Xp: U^T X' for all available left singular vectors (rows beyond r are
     ignored); s, V: singular values and right singular vectors (descending).
+    rows: None, or the rows of Phi to return (for inputs too tall to hold Phi whole).
+    Phi = X' M then never exists in full; b = Phi^+ x0 is the same least-squares
+    solution written through its normal equations (Phi^H Phi) b = Phi^H x0, with
+    Phi^H Phi = M^H (X'^T X') M and Phi^H x0 = M^H (X'^T x0) (Phi has full column rank).
     """
     s_r = s[:r]
     V_r = V[:, :r]
     at = reduced_operator(U_t_Xp[:r], V_r, s_r)          # r x r
     lam, W = np.linalg.eig(at)                             # LAPACK geev, unit columns
     M = (V_r / s_r[None, :]) @ W                           # (m-1) x r complex
-    phi = Xp @ M                                           # exact modes X' V S^-1 W
-    b = np.linalg.lstsq(phi, x0.astype(np.complex128), rcond=None)[0]   # b = Phi^+ x0
+    if rows is None:
+        phi = Xp @ M                                       # exact modes X' V S^-1 W
+        b = np.linalg.lstsq(phi, x0.astype(np.complex128), rcond=None)[0]   # b = Phi^+ x0
+    else:
+        phi = np.asarray(Xp[rows], dtype=np.float64) @ M
+        G = M.conj().T @ (Xp.T @ Xp) @ M
+        b = np.linalg.solve(G, M.conj().T @ (Xp.T @ x0))
     order = canonical_order(lam)
     return DMDFit(lam[order], phi[:, order], b[order], s_r.copy(), at, W[:, order], V_r)
 
@@ -132,20 +141,20 @@ def range_finder(X, Omega, q):
     return Q
 
 
-def fit_randomized(Z, r, Omega, q):
+def fit_randomized(Z, r, Omega, q, rows=None):
     """FP64 randomized twin of the GPU fit (Sec. 4.3 then Sec. 3.1).
 
     Uses the given sketch Omega ((m-1) x l, the values handed to the GPU), the
     basis Q from range_finder, B = Q^T X and Q^T X' from one product Q^T Z, the
     SVD of the small B, then the same reduced operator / eigen / mode / amplitude
-    steps as the exact DMD.
+    steps as the exact DMD.  rows: return Phi on these rows only (see dmd_from_svd).
     """
     X, Xp = split_snapshots(Z)
     Q = range_finder(X, np.asarray(Omega, dtype=np.float64), q)
     Bz = Q.T @ np.asarray(Z, dtype=np.float64)
     B, Bp = Bz[:, :-1], Bz[:, 1:]
     Ub, s, Vt = np.linalg.svd(B, full_matrices=False)
-    return dmd_from_svd(Xp, Ub.T @ Bp, s, Vt.T, r, X[:, 0])
+    return dmd_from_svd(Xp, Ub.T @ Bp, s, Vt.T, r, X[:, 0], rows)
 
 
 def canonical_order(lam):

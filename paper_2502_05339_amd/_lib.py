@@ -24,6 +24,7 @@ DMD_ERR_DOMAIN = 8
 DMD_ERR_OVERFLOW = 9
 DMD_ERR_HIP = 10
 DMD_ERR_UNSUPPORTED = 11
+DMD_ERR_IO = 12
 
 DMD_F32, DMD_F64 = 0, 1
 FIT_MIXED, FIT_FP64_RANDOMIZED, FIT_FP64_EXACT = 0, 1, 2
@@ -98,6 +99,11 @@ _SIGS = {
                                            c_int64, c_void_p, c_size_t, ctypes.c_char_p,
                                            ctypes.POINTER(c_int32)]),
     "dmd_autotune_load": (c_int32, [ctypes.c_char_p]),
+    "dmd_status_word": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_int32)]),
+    "dmd_model_save": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.c_char_p]),
+    "dmd_model_file_info": (c_int32, [ctypes.c_char_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int32),
+                                      ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
+    "dmd_model_load": (c_int32, [c_void_p, ctypes.c_char_p, ctypes.POINTER(ModelStruct)]),
 }
 
 _lock = threading.Lock()

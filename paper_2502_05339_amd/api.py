@@ -161,29 +161,53 @@ class Model:
         return out
 
     # ---- evaluation
-    def reconstruct(self, ks, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
-        return reconstruct(self, ks, mode, out)
+    def reconstruct(self, ks, mode: str | None = None, out: torch.Tensor | None = None,
+                    check_status: bool = False) -> torch.Tensor:
+        return reconstruct(self, ks, mode, out, check_status)
 
-    def integrate(self, ts, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
-        return integrate(self, ts, mode, out)
+    def integrate(self, ts, mode: str | None = None, out: torch.Tensor | None = None,
+                  check_status: bool = False) -> torch.Tensor:
+        return integrate(self, ts, mode, out, check_status)
 
     def project(self, u: torch.Tensor) -> torch.Tensor:
         return project(self, u)
 
-    # ---- checkpoint
+    # ---- checkpoint (versioned model file, written and read by the library)
     def save(self, path: str):
-        np.savez(path, phi=self.phi.cpu().numpy(), lam=self.lam_host(), b=self.b_host(),
-                 sigma=self.sigma.cpu().numpy(), kind=self.kind_host(), dt=np.float64(self.dt),
-                 version=np.int32(_lib.lib().dmd_abi_version()))
+        """Write the model file (dmd_model_save: header, lambda, b, sigma, kind, Phi)."""
+        ms = self.struct()
+        check(_lib.lib().dmd_model_save(_stream(), ctypes.byref(ms), str(path).encode()), "dmd_model_save")
+
+    @staticmethod
+    def file_info(path: str):
+        """(N, r, dtype code, dt) from a model file's header (host only)."""
+        n, r, dt_code, dt = ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0.0)
+        check(_lib.lib().dmd_model_file_info(str(path).encode(), ctypes.byref(n), ctypes.byref(r),
+                                             ctypes.byref(dt_code), ctypes.byref(dt)), "dmd_model_file_info")
+        return n.value, r.value, dt_code.value, dt.value
 
     @staticmethod
     def load(path: str, device="cuda") -> "Model":
-        with np.load(path, allow_pickle=False) as z:
-            phi = torch.from_numpy(z["phi"]).to(device)
-            m = Model(phi=phi, lam=torch.from_numpy(z["lam"]).to(device), b=torch.from_numpy(z["b"]).to(device),
-                      sigma=torch.from_numpy(z["sigma"]).to(device), kind=torch.from_numpy(z["kind"]).to(device),
-                      info=torch.zeros(_lib.INFO_WORDS, dtype=torch.int32, device=device), dt=float(z["dt"]))
+        """Read a model file into new device tensors (dmd_model_load)."""
+        n, r, code, dt = Model.file_info(path)
+        m = Model.empty(n, r, torch.float64 if code == DMD_F64 else torch.float32, device, dt)
+        _require_gpu(m.phi, "model.phi")
+        ms = m.struct()
+        check(_lib.lib().dmd_model_load(_stream(), str(path).encode(), ctypes.byref(ms)), "dmd_model_load")
+        m.dt = ms.dt
         return m
+
+
+def status_word(ws: torch.Tensor) -> int:
+    """Device status (DMD_OK, DMD_ERR_DOMAIN or DMD_ERR_OVERFLOW) of the last coefficient
+    pass that used workspace `ws`; waits for the current stream."""
+    st = ctypes.c_int32(0)
+    check(_lib.lib().dmd_status_word(_stream(), ws.data_ptr(), ctypes.byref(st)), "dmd_status_word")
+    return st.value
+
+
+def _check_status(ws: torch.Tensor, where: str):
+    check(status_word(ws), where)
 
 
 def _xview(Z: torch.Tensor | None, X: torch.Tensor | None, Xp: torch.Tensor | None):
@@ -267,8 +291,12 @@ def _recon_common(model: Model, K: int, mode: str | None, out: torch.Tensor | No
     return mcode, out, ws
 
 
-def reconstruct(model: Model, ks, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
-    """U[k] = Re(Phi diag(lambda^k) b) for every integer k in ks (Sec. 4.4)."""
+def reconstruct(model: Model, ks, mode: str | None = None, out: torch.Tensor | None = None,
+                check_status: bool = False) -> torch.Tensor:
+    """U[k] = Re(Phi diag(lambda^k) b) for every integer k in ks (Sec. 4.4).
+
+    check_status=True waits for the device and raises DMDError for DMD_ERR_DOMAIN
+    (a power of lambda = 0 with k < 0) or DMD_ERR_OVERFLOW (|b| |lambda|^k past FP32/FP64)."""
     _require_gpu(model.phi, "model.phi")
     k = np.ascontiguousarray(np.asarray(ks, dtype=np.int64).ravel())
     mcode, out, ws = _recon_common(model, k.size, mode, out)
@@ -276,6 +304,8 @@ def reconstruct(model: Model, ks, mode: str | None = None, out: torch.Tensor | N
     st = _lib.lib().dmd_reconstruct(_stream(), ctypes.byref(ms), k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                     k.size, mcode, out.data_ptr(), out.stride(0), ws.data_ptr(), ws.numel())
     check(st, "dmd_reconstruct")
+    if check_status:
+        _check_status(ws, "dmd_reconstruct")
     return out
 
 
@@ -314,8 +344,10 @@ class PreparedReconstruction:
         return out
 
 
-def integrate(model: Model, ts, mode: str | None = None, out: torch.Tensor | None = None) -> torch.Tensor:
-    """U[j] = Re(Phi exp(Omega t_j) b), Omega = Log(Lambda)/dt (Sec. 6.1)."""
+def integrate(model: Model, ts, mode: str | None = None, out: torch.Tensor | None = None,
+              check_status: bool = False) -> torch.Tensor:
+    """U[j] = Re(Phi exp(Omega t_j) b), Omega = Log(Lambda)/dt (Sec. 6.1); check_status as
+    for reconstruct (lambda = 0 has no logarithm: negative or fractional t/dt is a domain error)."""
     _require_gpu(model.phi, "model.phi")
     t = np.ascontiguousarray(np.asarray(ts, dtype=np.float64).ravel())
     mcode, out, ws = _recon_common(model, t.size, mode, out)
@@ -323,6 +355,8 @@ def integrate(model: Model, ts, mode: str | None = None, out: torch.Tensor | Non
     st = _lib.lib().dmd_integrate(_stream(), ctypes.byref(ms), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                   t.size, mcode, out.data_ptr(), out.stride(0), ws.data_ptr(), ws.numel())
     check(st, "dmd_integrate")
+    if check_status:
+        _check_status(ws, "dmd_integrate")
     return out
 
 

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "libdmdmi.so")
 OBJDIR = os.path.join(ROOT, "_build")
-SOURCES = ["gemm.hip", "recon.hip", "small.hip", "eig.hip", "adjoint.hip", "edit.hip", "rollout.hip", "upsample.hip", "optdmd.hip", "api.hip"]
+SOURCES = ["gemm.hip", "recon.hip", "small.hip", "eig.hip", "adjoint.hip", "edit.hip", "rollout.hip", "upsample.hip",
+           "optdmd.hip", "modelio.hip", "api.hip"]
 ARCH = "gfx950"
 
 

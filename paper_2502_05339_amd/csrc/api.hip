@@ -167,6 +167,9 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     const int l = exact ? mm : r + o.p;
     const bool shifted = a.shifted;
     const int64_t ldphi = model ? model->ldphi : dmd_phi_ld(r);
+    // staging of the mode coefficients is carved for the largest ldphi the header allows,
+    // so the size query (which has no model) covers every valid model
+    const int64_t ldphi_ws = 16 * NN_MAX_CB;
     const int64_t ldy = round_up(n, 4);
     const double u = 1.1102230246251565e-16;
     // Convergence of the FP64 small factors: full FP64 accuracy on the FP64 paths; on the
@@ -194,7 +197,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     double* At = cv.take<double>((size_t)r * r);
     double* W = cv.take<double>((size_t)r * r);
     double* M = cv.take<double>((size_t)mm * r);
-    void* Mf = cv.take<char>((size_t)mm * ldphi * esize(fdt));
+    void* Mf = cv.take<char>((size_t)mm * ldphi_ws * esize(fdt));
     double* PhiG = cv.take<double>((size_t)r * r);
     double* rhs = cv.take<double>((size_t)r);
     double* RinvPhi = cv.take<double>((size_t)r * r);
@@ -221,7 +224,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
         }
     }
     OptPlan op{};
-    if (o.flags & DMD_FIT_OPTDMD) op = opt_carve(cv, mm, r, exact ? mm : l, ldphi, fdt);
+    if (o.flags & DMD_FIT_OPTDMD) op = opt_carve(cv, mm, r, exact ? mm : l, ldphi_ws, fdt);
     if (fb) {
         fb->Q = Y; fb->ldq = ldy; fb->Bx = Bx; fb->Ueig = Ueig; fb->sigma = sigma; fb->l = l;
         fb->op = op;
@@ -343,8 +346,8 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
 // the modes of eq. phi_optdmd written into the model.  Host-driven: each trial point is
 // evaluated on the device and its cost read back; a step is kept when it lowers the cost
 // (mu / 4), else mu * 4 and a new trial.  Stops when a kept step gains less than 1e-13
-// of the cost, after 60 kept steps, or when mu passes 1e20.
-constexpr int VP_MAX_STEPS = 60;
+// of the cost, after 200 kept steps, or when mu passes 1e20.
+constexpr int VP_MAX_STEPS = 200;   // the oracle's step cap
 constexpr int VP_MAX_TRIES = 40;
 
 int32_t optdmd_refine(hipStream_t st, const FitArgs& a, dmd_model* model, FitBufs& fb, int* steps_out)
@@ -461,6 +464,7 @@ int32_t optdmd_refine(hipStream_t st, const FitArgs& a, dmd_model* model, FitBuf
 
 // ---------------------------------------------------------------- reconstruction plan
 struct ReconPlan {
+    int32_t* status;   // COEF_DOMAIN / COEF_OVERFLOW bits of the last coefficient pass
     int64_t* kdev;
     double* expo;
     void* chi;
@@ -474,6 +478,7 @@ ReconPlan recon_carve(Carver& cv, int r, int K, int mode)
     ReconPlan p;
     const int rp = (int)dmd_phi_ld(r);
     const int Kp = (int)round_up(K, RECON_KPAD);
+    p.status = cv.take<int32_t>(64);
     p.kdev = cv.take<int64_t>((size_t)K);
     p.expo = cv.take<double>((size_t)K);
     p.chi = cv.take<char>((size_t)Kp * rp * c_elem(mode));
@@ -567,7 +572,8 @@ int32_t recon_prepare(hipStream_t st, const dmd_model* m, const int64_t* k_host,
         HIPCHK(hipMemcpyAsync(p.expo, t_host, (size_t)K * sizeof(double), hipMemcpyHostToDevice, st));
         HIPCHK(exponents(st, nullptr, p.expo, 1.0 / m->dt, K, p.expo));
     }
-    HIPCHK(powers_pack(st, m->lam, m->b, m->kind, m->r, p.expo, K, Kp, rp, mode, p.chi, p.clo));
+    HIPCHK(fill_i32(st, p.status, 1, 0));
+    HIPCHK(powers_pack(st, m->lam, m->b, m->kind, m->r, p.expo, K, Kp, rp, mode, p.chi, p.clo, p.status));
     return DMD_OK;
 }
 
@@ -621,6 +627,7 @@ struct RollPlan {
 RollPlan roll_carve(Carver& cv, int64_t n, int r, int T, int mode)
 {
     RollPlan p;
+    p.rec = recon_carve(cv, r, T + 1, mode);   // first: its status word opens the workspace
     const int tc = std::min(T, ROLL_TC);
     p.P = cv.take<double>((size_t)tn_max_splits(n) * r * std::max(r, tc));
     p.PhiG = cv.take<double>((size_t)r * r);
@@ -629,7 +636,6 @@ RollPlan roll_carve(Carver& cv, int64_t n, int r, int T, int mode)
     p.rhs = cv.take<double>((size_t)r * T);
     p.tmp = cv.take<double>((size_t)r * T);
     p.states = cv.take<double>((size_t)2 * r * (T + 1));
-    p.rec = recon_carve(cv, r, T + 1, mode);
     return p;
 }
 
@@ -685,7 +691,7 @@ hipError_t frames_from_states(hipStream_t st, const dmd_model* m, const double* 
 {
     const int rp = (int)dmd_phi_ld(m->r);
     const int Kp = (int)round_up(K, RECON_KPAD);
-    hipError_t e = pack_states(st, states, m->kind, m->r, K, Kp, rp, mode, rec.chi, rec.clo);
+    hipError_t e = pack_states(st, states, m->kind, m->r, K, Kp, rp, mode, rec.chi, rec.clo, rec.status);
     if (e != hipSuccess) return e;
     ReconArgs ra{};
     ra.mode = mode;
@@ -719,6 +725,7 @@ const char* dmd_status_string(int32_t s)
     case DMD_ERR_OVERFLOW: return "result outside the output type's range";
     case DMD_ERR_HIP: return "HIP runtime error";
     case DMD_ERR_UNSUPPORTED: return "size beyond the small-matrix kernels' limits";
+    case DMD_ERR_IO: return "model file missing, unwritable, truncated or corrupted";
     default: return "unknown status";
     }
 }
@@ -750,6 +757,12 @@ int32_t dmd_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t 
     size_t need = 0;
     if (int32_t e = dmd_fit_workspace_size(n, ncols, xdtype, opts, &need)) return e;
     if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    {
+        // the carve of this very call (its layout and the caller's ldphi) must fit as well
+        Carver dry(nullptr);
+        fit_plan(dry, nullptr, a, model);
+        if (dry.bytes() > ws_bytes) return DMD_ERR_WORKSPACE;
+    }
     if (int32_t e0 = ensure_init()) return e0;
     hipStream_t st = (hipStream_t)stream;
     model->r = opts->r;
@@ -918,6 +931,7 @@ int32_t dmd_rollout(void* stream, const dmd_model* model, const double* z0, cons
     RollPlan p = roll_carve(cv, n, r, T, mode);
     double* states = z_out ? z_out : p.states;
     const double* beta = nullptr;
+    HIPCHK(fill_i32(st, p.rec.status, 1, 0));
     if (f) {
         HIPCHK(project_columns(st, model, f, ldf, T, p, false));   // g_s = Phi^+ f_s, every step
         beta = p.rhs;
@@ -955,6 +969,7 @@ int32_t dmd_upsample(void* stream, const dmd_model* model, const void* h0, const
     const int r = model->r;
     Carver cv(ws);
     UpPlan u = up_carve(cv, model->n, r, T, mode);
+    HIPCHK(fill_i32(st, u.rp.rec.status, 1, 0));
     RollPlan p0 = u.rp;                 // h0 uses the same Gram and inverse, its own coefficients
     p0.rhs = u.beta0;
     p0.tmp = u.tmp0;
@@ -994,7 +1009,7 @@ int32_t dmd_loss_grad_workspace_size(int64_t n, int32_t r, int32_t ncols, int32_
     Carver c(nullptr);
     recon_carve(c, r, ncols, mode);
     c.take<char>((size_t)round_up(n, 4) * ncols * esize(dtype));
-    c.take<double>(4096);
+    c.take<double>(LG_SS_SLOTS);
     c.take<double>((size_t)tn_max_splits(n) * r * ncols);
     c.take<double>((size_t)r * ncols);
     *bytes = c.bytes();
@@ -1013,6 +1028,8 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam, c
     dmd_loss_grad_workspace_size(model->n, model->r, ncols, model->dtype, &need);
     if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
     if (int32_t e0 = ensure_init()) return e0;
+    // one FP64 loss partial per work-group of the residual launch: its largest grid must fit
+    if (recon_max_grid() > LG_SS_SLOTS) return DMD_ERR_UNSUPPORTED;
     hipStream_t st = (hipStream_t)stream;
     const int r = model->r, rp = (int)dmd_phi_ld(r);
     const int64_t n = model->n, ldr = round_up(n, 4);
@@ -1020,12 +1037,14 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam, c
     Carver cv(ws);
     ReconPlan p = recon_carve(cv, r, ncols, mode);
     void* R = cv.take<char>((size_t)ldr * ncols * esize(model->dtype));
-    double* ss = cv.take<double>(4096);
+    double* ss = cv.take<double>(LG_SS_SLOTS);
     double* P = cv.take<double>((size_t)tn_max_splits(n) * r * ncols);
     double* G = cv.take<double>((size_t)r * ncols);
+    HIPCHK(fill_i32(st, p.status, 1, 0));
     HIPCHK(hipMemcpyAsync(p.kdev, k_host, (size_t)ncols * sizeof(int64_t), hipMemcpyHostToDevice, st));
     HIPCHK(exponents(st, p.kdev, nullptr, 1.0, ncols, p.expo));
-    HIPCHK(powers_pack(st, lam, b, model->kind, r, p.expo, ncols, (int)round_up(ncols, RECON_KPAD), rp, mode, p.chi, nullptr));
+    HIPCHK(powers_pack(st, lam, b, model->kind, r, p.expo, ncols, (int)round_up(ncols, RECON_KPAD), rp, mode, p.chi,
+                       nullptr, p.status));
     int grid = 0;
     ReconArgs ra{};
     ra.mode = mode;
@@ -1034,10 +1053,21 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam, c
     ra.U = R; ra.ldu = ldr; ra.vec_store = 1;
     ra.xt = xt; ra.ldxt = ldxt; ra.ss_partial = ss; ra.grid_out = &grid;
     HIPCHK(recon_launch(st, ra, 0));
-    if (grid > 4096) return DMD_ERR_UNSUPPORTED;
     HIPCHK(gemm_tn(st, model->dtype, model->dtype, model->phi, model->ldphi, 1, r, R, ldr, 0, ncols, 0, n, P, G, r,
                    nullptr, 0, nullptr));
     HIPCHK(grad_reduce(st, r, ncols, G, lam, b, model->kind, p.expo, ss, grid, out));
+    return DMD_OK;
+}
+
+int32_t dmd_status_word(void* stream, const void* ws, int32_t* status)
+{
+    if (!ws || !status) return DMD_ERR_ARG;
+    if (int32_t e0 = ensure_init()) return e0;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t bits = 0;
+    HIPCHK(hipMemcpyAsync(&bits, ws, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    *status = (bits & COEF_DOMAIN) ? DMD_ERR_DOMAIN : ((bits & COEF_OVERFLOW) ? DMD_ERR_OVERFLOW : DMD_OK);
     return DMD_OK;
 }
 
@@ -1068,6 +1098,9 @@ int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes, 
         size_t need = 0;
         if (int32_t e = dmd_fit_workspace_size(sc.n, sc.ncols, sc.xdtype, &sc.opts, &need)) return e;
         if (!sc.ws || sc.ws_bytes < need) return DMD_ERR_WORKSPACE;
+        Carver dry(nullptr);
+        fit_plan(dry, nullptr, a, &models[i]);
+        if (dry.bytes() > sc.ws_bytes) return DMD_ERR_WORKSPACE;
     }
     if (int32_t e0 = ensure_init()) return e0;
     hipStream_t origin = (hipStream_t)stream;

@@ -129,6 +129,11 @@ __device__ __forceinline__ cplx cpow_real(cplx lam, double e) {
     return {mag * c, mag * s};
 }
 
+// Status bits of a coefficient pass, or-ed into one device word that the host reads back
+// (a power of lambda = 0 outside its domain; a coefficient beyond the output type's range).
+constexpr int32_t COEF_DOMAIN = 1;
+constexpr int32_t COEF_OVERFLOW = 2;
+
 // ---------------------------------------------------------------- misc
 __host__ __device__ __forceinline__ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 __host__ __device__ __forceinline__ int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }

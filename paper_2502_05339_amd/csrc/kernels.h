@@ -49,9 +49,13 @@ struct ReconArgs {
     int* grid_out;
 };
 constexpr int RECON_NCFG = 6;
+constexpr int RECON_MAX_WG_PER_CU = 4;  // the largest work-groups-per-CU of any tile candidate
+constexpr int LG_SS_SLOTS = 4096;       // loss partials (one per work-group) of the residual launch
+inline int recon_max_grid() { return device_cu_count() * RECON_MAX_WG_PER_CU; }
 hipError_t recon_launch(hipStream_t s, const ReconArgs& ra, int cfg);
+// status (may be null): COEF_DOMAIN / COEF_OVERFLOW bits or-ed in (common.h)
 hipError_t powers_pack(hipStream_t s, const double* lam, const double* b, const int32_t* kind, int r,
-                       const double* expo, int K, int Kp, int rp, int mode, void* hi, void* lo);
+                       const double* expo, int K, int Kp, int rp, int mode, void* hi, void* lo, int32_t* status);
 hipError_t exponents(hipStream_t s, const int64_t* k, const double* t, double inv_dt, int K, double* e);
 
 // ---- small FP64 matrices (small.hip)
@@ -114,7 +118,7 @@ hipError_t edit_modes(hipStream_t s, int r, double dt, const dmd_edit& e, const 
 hipError_t rollout_scan(hipStream_t s, int r, int T, const double* lam, const double* z0, const double* beta,
                         int64_t ldb, const int32_t* kind, double dt, double* states);
 hipError_t pack_states(hipStream_t s, const double* states, const int32_t* kind, int r, int K, int Kp, int rp,
-                       int mode, void* hi, void* lo);
+                       int mode, void* hi, void* lo, int32_t* status);
 
 // ---- upsampling (upsample.hip)
 hipError_t upsample_states(hipStream_t s, int r, int T, const double* lam, const double* beta0, const double* beta,

@@ -24,34 +24,56 @@ namespace dmd {
 // c1 = b_i lambda_i^e and c2 = b_{i+1} lambda_{i+1}^e has
 //   C_i = Re c1 + Re c2,   C_{i+1} = Im c2 - Im c1
 // because Re(phi c1 + conj(phi) c2) = Re(phi)(Re c1 + Re c2) + Im(phi)(Im c2 - Im c1).
+// Each member also reports, in *flags, a power of lambda = 0 with a negative or
+// fractional exponent (COEF_DOMAIN: Omega = Log(lambda) / dt has no value there) and a
+// magnitude |b| |lambda|^e beyond vmax, the largest finite value of the output type
+// (COEF_OVERFLOW).
+__device__ __forceinline__ cplx checked_member(const double* lam, const double* b, int i, double e, double vmax,
+                                               int* flags)
+{
+    const cplx l = {lam[2 * i], lam[2 * i + 1]};
+    if (l.re == 0.0 && l.im == 0.0 && (e < 0.0 || e != floor(e))) { *flags |= COEF_DOMAIN; return {0.0, 0.0}; }
+    const cplx c = cmul({b[2 * i], b[2 * i + 1]}, cpow_real(l, e));
+    if (!(hypot(c.re, c.im) <= vmax)) *flags |= COEF_OVERFLOW;   // also catches NaN
+    return c;
+}
+
 __device__ __forceinline__ double folded_coeff(const double* lam, const double* b,
-                                               const int32_t* kind, int r, int i, double e)
+                                               const int32_t* kind, int r, int i, double e, double vmax,
+                                               int* flags)
 {
     int kd = kind[i];
     if ((kd == 1 && i + 1 >= r) || (kd == 2 && i == 0) || kd < 0 || kd > 2) kd = 0;   // malformed pair marker
-    if (kd == 0) {
-        cplx c = cmul({b[2 * i], b[2 * i + 1]}, cpow_real({lam[2 * i], lam[2 * i + 1]}, e));
-        return c.re;
-    }
+    if (kd == 0) return checked_member(lam, b, i, e, vmax, flags).re;
     const int i1 = (kd == 1) ? i : i - 1;
     const int i2 = i1 + 1;
-    cplx c1 = cmul({b[2 * i1], b[2 * i1 + 1]}, cpow_real({lam[2 * i1], lam[2 * i1 + 1]}, e));
-    cplx c2 = cmul({b[2 * i2], b[2 * i2 + 1]}, cpow_real({lam[2 * i2], lam[2 * i2 + 1]}, e));
-    return (kd == 1) ? (c1.re + c2.re) : (c2.im - c1.im);
+    const cplx c1 = checked_member(lam, b, i1, e, vmax, flags);
+    const cplx c2 = checked_member(lam, b, i2, e, vmax, flags);
+    const double v = (kd == 1) ? (c1.re + c2.re) : (c2.im - c1.im);
+    if (!(fabs(v) <= vmax)) *flags |= COEF_OVERFLOW;
+    return v;
+}
+
+// Largest finite value of the coefficient / output type of a reconstruction mode.
+__device__ __forceinline__ double mode_vmax(int mode)
+{
+    return mode == DMD_RECON_FP64 ? 1.7976931348623157e308 : 3.4028234663852886e38;
 }
 
 __global__ void powers_pack_kernel(const double* __restrict__ lam, const double* __restrict__ b,
                                    const int32_t* __restrict__ kind, int r,
                                    const double* __restrict__ expo, int K, int Kp, int rp,
-                                   int mode, void* out_hi, void* out_lo)
+                                   int mode, void* out_hi, void* out_lo, int32_t* status)
 {
     const int64_t tot = (int64_t)Kp * rp;
+    const double vmax = mode_vmax(mode);
+    int flags = 0;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(idx % rp);
         const int j = (int)(idx / rp);
         double v = 0.0;
-        if (i < r && j < K) v = folded_coeff(lam, b, kind, r, i, expo[j]);
+        if (i < r && j < K) v = folded_coeff(lam, b, kind, r, i, expo[j], vmax, &flags);
         switch (mode) {
         case DMD_RECON_FP64: ((double*)out_hi)[idx] = v; break;
         case DMD_RECON_FP32: ((float*)out_hi)[idx] = (float)v; break;
@@ -64,6 +86,7 @@ __global__ void powers_pack_kernel(const double* __restrict__ lam, const double*
         }
         }
     }
+    if (flags && status) atomicOr(status, flags);
 }
 
 // Integer exponents to doubles; real times t to t / dt.
@@ -627,12 +650,12 @@ hipError_t recon_launch(hipStream_t s, const ReconArgs& ra, int cfg)
 }
 
 hipError_t powers_pack(hipStream_t s, const double* lam, const double* b, const int32_t* kind, int r,
-                       const double* expo, int K, int Kp, int rp, int mode, void* hi, void* lo)
+                       const double* expo, int K, int Kp, int rp, int mode, void* hi, void* lo, int32_t* status)
 {
     const int64_t tot = (int64_t)Kp * rp;
     const int blocks = (int)std::min<int64_t>(ceil_div(tot, 256), 2048);
     hipLaunchKernelGGL(powers_pack_kernel, dim3(blocks), dim3(256), 0, s, lam, b, kind, r, expo, K,
-                       Kp, rp, mode, hi, lo);
+                       Kp, rp, mode, hi, lo, status);
     return hipGetLastError();
 }
 

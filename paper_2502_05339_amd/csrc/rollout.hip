@@ -73,11 +73,14 @@ rollout_scan_kernel(int r, int T, const double* __restrict__ lam, const double* 
 
 // Coefficients of the reconstruction GEMM from reduced states (frame j = state j), in
 // the folded basis: kind 0 -> Re z_i; a pair (i, i+1) -> Re z_i + Re z_{i+1} and
-// Im z_{i+1} - Im z_i, so that Re(Phi z) = sum_i phi_folded_i C_i.
+// Im z_{i+1} - Im z_i, so that Re(Phi z) = sum_i phi_folded_i C_i.  A coefficient beyond
+// the output type's finite range sets COEF_OVERFLOW in *status.
 __global__ void pack_states_kernel(const double* __restrict__ states, const int32_t* __restrict__ kind, int r,
-                                   int K, int Kp, int rp, int mode, void* out_hi, void* out_lo)
+                                   int K, int Kp, int rp, int mode, void* out_hi, void* out_lo, int32_t* status)
 {
     const int64_t tot = (int64_t)Kp * rp;
+    const double vmax = mode == DMD_RECON_FP64 ? 1.7976931348623157e308 : 3.4028234663852886e38;
+    int flags = 0;
     for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < tot;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(idx % rp);
@@ -90,6 +93,7 @@ __global__ void pack_states_kernel(const double* __restrict__ states, const int3
             if (kd == 0) v = z[2 * i];
             else if (kd == 1) v = z[2 * i] + z[2 * i + 2];
             else v = z[2 * i + 1] - z[2 * i - 1];
+            if (!(fabs(v) <= vmax)) flags |= COEF_OVERFLOW;
         }
         switch (mode) {
         case DMD_RECON_FP64: ((double*)out_hi)[idx] = v; break;
@@ -103,6 +107,7 @@ __global__ void pack_states_kernel(const double* __restrict__ states, const int3
         }
         }
     }
+    if (flags && status) atomicOr(status, flags);
 }
 
 hipError_t rollout_scan(hipStream_t s, int r, int T, const double* lam, const double* z0, const double* beta,
@@ -113,11 +118,12 @@ hipError_t rollout_scan(hipStream_t s, int r, int T, const double* lam, const do
 }
 
 hipError_t pack_states(hipStream_t s, const double* states, const int32_t* kind, int r, int K, int Kp, int rp,
-                       int mode, void* hi, void* lo)
+                       int mode, void* hi, void* lo, int32_t* status)
 {
     const int64_t tot = (int64_t)Kp * rp;
     const int blocks = (int)std::min<int64_t>(ceil_div(tot, 256), 2048);
-    hipLaunchKernelGGL(pack_states_kernel, dim3(blocks), dim3(256), 0, s, states, kind, r, K, Kp, rp, mode, hi, lo);
+    hipLaunchKernelGGL(pack_states_kernel, dim3(blocks), dim3(256), 0, s, states, kind, r, K, Kp, rp, mode, hi, lo,
+                       status);
     return hipGetLastError();
 }
 

@@ -41,8 +41,8 @@ def test_no_extra_exports():
 
 def test_version_and_strings(L):
     from paper_2502_05339_amd import _lib
-    assert L.dmd_abi_version() == 1
-    for code in range(0, 12):
+    assert L.dmd_abi_version() == 2
+    for code in range(0, 13):
         assert len(_lib.status_string(code)) >= 2
     assert "unknown" in _lib.status_string(99)
     assert L.dmd_phi_ld(1) == 32 and L.dmd_phi_ld(150) == 160 and L.dmd_phi_ld(160) == 160
@@ -295,3 +295,90 @@ def test_upsample_and_lowres_validation(L):
     assert P(None, 0, 0x100, 200, 0x200, 49, 0x300, 200, 1, 2, 1, 10, 10, 2) == 1           # ldl < M
     assert P(None, 0, 0x100, 200, 0x200, 50, 0, 200, 1, 2, 1, 10, 10, 2) == 1               # null x
     assert P(None, 0, 0x100, 200, 0x200, 50, 0x300, 200, 0, 2, 1, 10, 10, 2) == 0           # no frames: no-op
+
+
+def test_fit_workspace_covers_every_valid_ldphi(L):
+    """The size query has no model, so it must cover the largest ldphi the header allows
+    (192), in both snapshot layouts: a fit into a workspace of exactly the queried size
+    passes the workspace checks (it then stops at the HIP runtime, which has no GPU here)."""
+    for precision, dt, ncols in (("mixed", 0, 199), ("fp64", 1, 199), ("fp64_exact", 1, 64)):
+        o = _opts(150 if precision != "fp64_exact" else 16, 10 if precision != "fp64_exact" else 0, 2, precision)
+        n = 4096
+        st, need = _ws_size(L, n, ncols, dt, o)
+        assert st == 0
+        for ldphi in (160 if precision != "fp64_exact" else 32, 192):
+            m = _model_struct(n=n, r=o.r, dtype=dt, ldphi=ldphi)
+            # separate X and X' (not the shifted view of one buffer)
+            code = L.dmd_fit(None, 0x100000, 0x90000000, n, ncols, n, n, dt, ctypes.byref(o), 0x1000, need,
+                             ctypes.byref(m))
+            assert code not in (1, 2, 3), (precision, ldphi, code)
+            assert L.dmd_fit(None, 0x100000, 0x90000000, n, ncols, n, n, dt, ctypes.byref(o), 0x1000, need - 1,
+                             ctypes.byref(m)) == 3
+
+
+def test_status_word_arguments(L):
+    st = ctypes.c_int32(0)
+    assert L.dmd_status_word(None, None, ctypes.byref(st)) == 1
+    assert L.dmd_status_word(None, 0x1000, None) == 1
+
+
+def _model_file(path, n=5, r=3, dtype=0, dt=0.5, corrupt=None):
+    """A model file written byte by byte from the format the header documents."""
+    import struct
+    import numpy as np
+    rng = np.random.default_rng(7)
+    lam = rng.standard_normal(2 * r)
+    b = rng.standard_normal(2 * r)
+    sigma = np.abs(rng.standard_normal(r))
+    kind = np.array([1, 2, 0][:r] + [0] * max(0, r - 3), dtype=np.int32)
+    phi = rng.standard_normal((n, r)).astype(np.float64 if dtype == 1 else np.float32)
+    payload = lam.tobytes() + b.tobytes() + sigma.tobytes() + kind.tobytes() + phi.tobytes()
+    h = 1469598103934665603
+    for c in payload:
+        h = ((h ^ c) * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    if corrupt == "hash":
+        h ^= 1
+    magic = b"DMDMODEL" if corrupt != "magic" else b"DMDMODEX"
+    version = 1 if corrupt != "version" else 2
+    header = magic + struct.pack("<IIqiidQQII", version, 64, n, r, dtype, dt, len(payload), h, 2, 0)
+    assert len(header) == 64
+    data = header + payload
+    if corrupt == "truncated":
+        data = data[:-3]
+    if corrupt == "trailing":
+        data = data + b"\0"
+    with open(path, "wb") as f:
+        f.write(data)
+    return lam, b, sigma, kind, phi
+
+
+def test_model_file_header(L, tmp_path):
+    """dmd_model_file_info reads the documented layout and rejects foreign, damaged,
+    truncated and over-long files (host only)."""
+    n_, r_, d_, t_ = ctypes.c_int64(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_double(0)
+    args = (ctypes.byref(n_), ctypes.byref(r_), ctypes.byref(d_), ctypes.byref(t_))
+    for dtype in (0, 1):
+        p = tmp_path / f"ok{dtype}.dmd"
+        _model_file(p, n=7, r=3, dtype=dtype, dt=0.25)
+        assert L.dmd_model_file_info(str(p).encode(), *args) == 0
+        assert (n_.value, r_.value, d_.value, t_.value) == (7, 3, dtype, 0.25)
+    for bad in ("hash", "magic", "version", "truncated", "trailing"):
+        p = tmp_path / f"{bad}.dmd"
+        _model_file(p, corrupt=bad)
+        assert L.dmd_model_file_info(str(p).encode(), *args) == 12, bad
+    assert L.dmd_model_file_info(str(tmp_path / "missing.dmd").encode(), *args) == 12
+    assert L.dmd_model_file_info(None, *args) == 1
+
+
+def test_model_load_validation(L, tmp_path):
+    """A file that does not fit the caller's model is refused before any device copy."""
+    p = tmp_path / "m.dmd"
+    _model_file(p, n=7, r=3, dtype=0)
+    assert L.dmd_model_load(None, str(p).encode(), ctypes.byref(_model_struct(n=8, r=3))) == 2      # N differs
+    assert L.dmd_model_load(None, str(p).encode(), ctypes.byref(_model_struct(n=7, r=3, dtype=1))) == 1
+    assert L.dmd_model_load(None, str(p).encode(), ctypes.byref(_model_struct(n=7, r=3, ldphi=16))) == 1
+    assert L.dmd_model_load(None, str(tmp_path / "none.dmd").encode(), ctypes.byref(_model_struct(n=7))) == 12
+    m = _model_struct(n=7)
+    m.phi = 0
+    assert L.dmd_model_load(None, str(p).encode(), ctypes.byref(m)) == 1
+    assert L.dmd_model_save(None, None, str(p).encode()) == 1

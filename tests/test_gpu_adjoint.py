@@ -31,6 +31,22 @@ def _relerr(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
 
 
+def _elemerr(a, ref, floor):
+    """Largest element-wise relative error, each component against its own magnitude
+    (floored at `floor` times the largest one), so a wrong small component cannot hide
+    under the norm of the large ones."""
+    a = np.asarray(a)
+    ref = np.asarray(ref)
+    den = np.maximum(np.abs(ref), floor * np.max(np.abs(ref)))
+    return float(np.max(np.abs(a - ref) / den))
+
+
+# element-wise floors: FP64 models resolve components down to 1e-6 of the largest one;
+# FP32 products carry an absolute error near 1e-7 of the largest term, so components are
+# held to the tolerance down to 1e-2 of the largest one
+FLOOR = {torch.float64: 1e-6, torch.float32: 1e-2}
+
+
 @pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-10), (torch.float32, 1e-4)])
 def test_loss_grad_matches_closed_form(gpu_lib, dtype, tol):
     import paper_2502_05339_amd as dmd
@@ -49,8 +65,10 @@ def test_loss_grad_matches_closed_form(gpu_lib, dtype, tol):
     Lo, glo, gbo = oracle.loss_grad(phi, lam, b, Xo, ks)
     _print(f"  loss {L.item():.6e} vs {Lo:.6e}")
     assert abs(L.item() - Lo) <= tol * abs(Lo)
-    assert _relerr(gl.cpu().numpy(), glo) <= tol
-    assert _relerr(gb.cpu().numpy(), gbo) <= tol
+    e_l = _elemerr(gl.cpu().numpy(), glo, FLOOR[dtype])
+    e_b = _elemerr(gb.cpu().numpy(), gbo, FLOOR[dtype])
+    _print(f"  element-wise grad_lambda {e_l:.2e}, grad_b {e_b:.2e}")
+    assert e_l <= tol and e_b <= tol
 
 
 def test_loss_grad_rank150_fp64(gpu_lib):
@@ -66,8 +84,10 @@ def test_loss_grad_rank150_fp64(gpu_lib):
     Lo, glo, gbo = oracle.loss_grad(m.complex_modes(), lam, b, g.Z[:, ks], ks)
     _print(f"  loss {L.item():.6e} vs {Lo:.6e}")
     assert abs(L.item() - Lo) <= 1e-10 * abs(Lo)
-    assert _relerr(gl.cpu().numpy(), glo) <= 1e-10
-    assert _relerr(gb.cpu().numpy(), gbo) <= 1e-10
+    e_l = _elemerr(gl.cpu().numpy(), glo, FLOOR[torch.float64])
+    e_b = _elemerr(gb.cpu().numpy(), gbo, FLOOR[torch.float64])
+    _print(f"  element-wise grad_lambda {e_l:.2e}, grad_b {e_b:.2e}")
+    assert e_l <= 1e-10 and e_b <= 1e-10
 
 
 def test_loss_grad_c4_shape_with_strided_targets(gpu_lib):
@@ -92,8 +112,10 @@ def test_loss_grad_c4_shape_with_strided_targets(gpu_lib):
     # the oracle above uses k = 0..m-1 against reversed targets, i.e. the same pairs
     _print(f"  loss {L.item():.6e} vs {Lo:.6e}")
     assert abs(L.item() - Lo) <= 1e-4 * abs(Lo)
-    assert _relerr(gl.cpu().numpy(), glo) <= 1e-4
-    assert _relerr(gb.cpu().numpy(), gbo) <= 1e-4
+    e_l = _elemerr(gl.cpu().numpy(), glo, FLOOR[torch.float32])
+    e_b = _elemerr(gb.cpu().numpy(), gbo, FLOOR[torch.float32])
+    _print(f"  element-wise grad_lambda {e_l:.2e}, grad_b {e_b:.2e} (norm-wise {_relerr(gl.cpu().numpy(), glo):.2e})")
+    assert e_l <= 1e-4 and e_b <= 1e-4
 
 
 def test_autograd_function_and_refit(gpu_lib):

@@ -728,3 +728,59 @@ def test_planted_swapped_selection_is_caught(monkeypatch):
     monkeypatch.setattr(oracle, "upsample_evolve", swapped)
     with pytest.raises(AssertionError):
         test_upsample_guide_in_span_and_zero_guide()
+
+
+def test_amplitude_weights_hand_case_and_invariance():
+    """w_i = |b_i| ||phi_i||: the size of mode i's term phi_i b_i, the weight of the
+    amplitude-weighted eigenvalue error.  Pinned by a hand-computed case, by the scale
+    freedom of an eigenvector (phi_i -> c phi_i, b_i -> b_i / c leaves the model and so the
+    weight unchanged; a weight from |b| or ||phi|| alone changes), and by the norm of the
+    single-mode field at k = 0 for a real mode."""
+    phi = np.array([[3.0, 0.0], [4.0, 0.0], [0.0, 1.0]], dtype=np.complex128)
+    b = np.array([2j, -0.5])
+    assert np.allclose(oracle.amplitude_weights(phi, b), [10.0, 0.5], rtol=0, atol=1e-15)
+    rng = np.random.default_rng(11)
+    phi = rng.standard_normal((40, 6)) + 1j * rng.standard_normal((40, 6))
+    b = rng.standard_normal(6) + 1j * rng.standard_normal(6)
+    c = rng.standard_normal(6) * 3 + 1j * rng.standard_normal(6)
+    w = oracle.amplitude_weights(phi, b)
+    assert np.allclose(oracle.amplitude_weights(phi * c, b / c), w, rtol=1e-13)
+    assert not np.allclose(np.abs(b / c), np.abs(b), rtol=1e-3)      # |b| alone would move
+    # a real mode: its weight is the norm of its field at k = 0
+    phr = rng.standard_normal((40, 1))
+    br = np.array([-1.7])
+    u0 = oracle.reconstruct(phr, np.array([0.9]), br, np.array([0]))[:, 0]
+    assert abs(oracle.amplitude_weights(phr, br)[0] - np.linalg.norm(u0)) <= 1e-13 * np.linalg.norm(u0)
+
+
+def test_weighted_eig_error_follows_the_weights():
+    """A large eigenvalue error on a mode of negligible weight hardly moves the weighted
+    error, while the same error on the heavy mode moves it in full."""
+    lam = np.array([0.9 + 0.1j, 0.5 - 0.3j, 0.99])
+    w = np.array([1.0, 1e-8, 1.0])
+    bad_light = lam + np.array([0, 0.1, 0])
+    bad_heavy = lam + np.array([0.1, 0, 0])
+    e_light = oracle.eig_errors(bad_light, lam, w)
+    e_heavy = oracle.eig_errors(bad_heavy, lam, w)
+    assert e_light["weighted_rel"] < 1e-8 and e_light["max_rel"] > 0.1
+    assert abs(e_heavy["weighted_rel"] - 0.1 / np.sum(w * np.abs(lam))) < 1e-12
+
+
+def test_row_subset_route_matches_full_fit():
+    """fit_randomized(rows=...) returns the same eigenvalues, the same modes on the chosen
+    rows and the same least-squares amplitudes (normal equations instead of lstsq) as
+    the full fit, on an input small enough to hold Phi whole."""
+    cfg = synth.Config("rows", (2, 40, 40), 70, 18, 0.95, 1e-4, 314, r=30, p=8, q=2)
+    g = synth.generate(cfg)
+    Zd = g.Z.astype(np.float64)
+    Om = g.Omega.astype(np.float64)
+    full = oracle.fit_randomized(Zd, cfg.r, Om, cfg.q)
+    rows = np.sort(np.random.default_rng(1).choice(cfg.N, 500, replace=False))
+    sub = oracle.fit_randomized(Zd, cfg.r, Om, cfg.q, rows=rows)
+    assert np.array_equal(sub.lam, full.lam)
+    assert np.allclose(sub.phi, full.phi[rows], rtol=0, atol=1e-13 * np.abs(full.phi).max())
+    assert np.allclose(sub.b, full.b, rtol=1e-9, atol=1e-12 * np.abs(full.b).max())
+    ks = np.arange(cfg.m)
+    U1 = oracle.reconstruct(full.phi[rows], full.lam, full.b, ks)
+    U2 = oracle.reconstruct(sub.phi, sub.lam, sub.b, ks)
+    assert np.linalg.norm(U1 - U2) <= 1e-10 * np.linalg.norm(U1)
