@@ -179,7 +179,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     const double jac_tol = mixed ? 1e-10 : 4.5e-16;
     const double defl_tol = mixed ? 1e-10 : 2.220446049250313e-16;
 
-    int32_t* flags = cv.take<int32_t>(16);
+    int32_t* flags = cv.take<int32_t>(64);
     int32_t* info = model ? model->info : nullptr;
     // partial buffer: largest TN product of the fit
     const int wide = shifted ? mm + 1 : mm;
@@ -232,7 +232,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     if (!run) return DMD_OK;
 
     HIPCHK(fill_i32(st, info, DMD_INFO_WORDS, 0));
-    HIPCHK(fill_i32(st, flags, 16, 0));
+    HIPCHK(fill_i32(st, flags, 64, 0));
     if (o.flags & DMD_FIT_CHECK_FINITE) {
         HIPCHK(check_finite(st, fdt, a.x, a.ldx, n, mm, info));
         HIPCHK(check_finite(st, fdt, a.xp, a.ldxp, n, mm, info));
@@ -242,19 +242,27 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
 
     if (!exact) {
         const int cdt = mixed ? DMD_F32 : DMD_F64;   // MFMA type of the streaming products
-        // CholeskyQR2 of an N x l (or mm x l) matrix in place, with a shifted first pass
-        // on breakdown and then a conditional third pass (shifted CholeskyQR3).
-        // `two` = false: a single pass (an intermediate basis of the power iteration only
-        // has to be well conditioned; the next pass re-orthonormalises it)
-        auto cholqr = [&](void* Yb, int64_t ld, int64_t rows, int dtype, int32_t* flag, bool two) -> int32_t {
-            HIPCHK(fill_i32(st, flag, 1, 0));
+        // CholeskyQR2 of an N x l (or mm x l) matrix in place (`two`), or one pass for an
+        // intermediate basis of the power iteration (it only has to be well conditioned;
+        // the next pass re-orthonormalises it).  A pass whose Cholesky breaks down retries
+        // with a diagonal shift (shifted CholeskyQR); a shifted pass leaves a basis of
+        // condition up to about u^-1/2, so it is followed by as many clean passes as the
+        // mode asks for (two, or one), which run only when their run flag is set.  Shifts
+        // are allowed in the first npass - need passes, so a sketch too ill-conditioned even
+        // for one shifted pass (condition past u^-1) gets a second one; a breakdown in a
+        // pass without a shift is DMD_ERR_CHOL_BREAKDOWN.
+        // fl[0..npass): attempt flags of the passes; fl[8..8+npass): their run flags.
+        auto cholqr = [&](void* Yb, int64_t ld, int64_t rows, int dtype, int32_t* fl, bool two) -> int32_t {
+            const int need = two ? 2 : 1, npass = two ? 4 : 2;
+            HIPCHK(fill_i32(st, fl, 16, 0));
             const double shift_scale = 11.0 * ((double)rows * l + (double)l * (l + 1)) * u;
-            for (int pass = 0; pass < 3; ++pass) {
-                if (pass == 1 && !two) break;
-                const int32_t* skip = pass == 2 ? flag : nullptr;
+            for (int pass = 0; pass < npass; ++pass) {
+                const int32_t* skip = pass < need ? nullptr : fl + 8 + pass;
+                const bool can_shift = pass < npass - need;
                 HIPCHK(gemm_tn(st, dtype, DMD_F64, Yb, ld, 0, l, Yb, ld, 0, l, 1, rows, P, G, l, nullptr, 0, skip));
                 HIPCHK(chol_inv(st, G, l, l, Rinv, l, dtype == DMD_F32 ? Rinv32 : nullptr, l,
-                                pass == 0 ? shift_scale : 0.0, pass == 0 ? flag : nullptr, info, skip));
+                                can_shift ? shift_scale : 0.0, can_shift ? fl + pass : nullptr, info, skip,
+                                fl + 8 + pass + 1, can_shift ? need : 0));
                 HIPCHK(gemm_nn(st, dtype, Yb, ld, dtype == DMD_F32 ? (const void*)Rinv32 : (const void*)Rinv, l,
                                Yb, ld, 0, rows, l, l, skip));
             }
@@ -266,11 +274,11 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
         // power iterations: W = orth(X^T Q), Y = X W, Q = orth(Y)
         for (int it = 0; it < o.q; ++it) {
             HIPCHK(gemm_tn(st, fdt, cdt, a.x, a.ldx, 0, mm, Y, ldy, 0, l, 0, n, P, Wt, mm, nullptr, 0, nullptr));
-            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 1, false)) return e;
+            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 16, false)) return e;
             if (fdt == DMD_F32) HIPCHK(to_f32(st, mm, l, l, Wt, mm, (float*)Wtf, mm));
             else HIPCHK(copy_f64(st, mm, l, l, Wt, mm, (double*)Wtf, mm));
             HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, Wtf, mm, Y, ldy, 0, n, mm, l, nullptr));
-            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 2, it == o.q - 1)) return e;
+            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 32, it == o.q - 1)) return e;
         }
         // projection B = Q^T X, B' = Q^T X' (one pass over Z when X' is the shifted view)
         if (shifted) {
@@ -328,7 +336,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     HIPCHK(gemm_tn(st, fdt, DMD_F64, model->phi, ldphi, 1, r, model->phi, ldphi, 1, r, 1, n, P, PhiG, r, nullptr, 0, nullptr));
     HIPCHK(gemm_tn(st, fdt, DMD_F64, model->phi, ldphi, 1, r, a.x, a.ldx, 0, 1, 0, n, P, rhs, r, nullptr, 0, nullptr));
     HIPCHK(chol_inv(st, PhiG, r, r, RinvPhi, r, nullptr, 0, 11.0 * ((double)n * r + (double)r * (r + 1)) * u,
-                    flags + 3, info, nullptr));
+                    flags + 48, info, nullptr));
     HIPCHK(normal_solve(st, r, RinvPhi, r, rhs, beta, 0));
     if (fdt == DMD_F64) {
         // one step of iterative refinement: beta += G^-1 Phi^T (x0 - Phi beta)

@@ -60,11 +60,12 @@ hipError_t exponents(hipStream_t s, const int64_t* k, const double* t, double in
 
 // ---- small FP64 matrices (small.hip)
 // Cholesky G = R^T R of an n x n SPD matrix and R^-1 (upper).  On breakdown retry
-// once with a diagonal shift (flagging *shifted = 1); a second failure writes
-// DMD_ERR_CHOL_BREAKDOWN to info[0] and an identity R^-1.
+// once with a diagonal shift (flagging *shifted = 1 and run_next[0..nnext-1] = 1, the
+// run flags of the passes that must follow a shifted one); a failure without a shift,
+// or of the shifted retry, writes DMD_ERR_CHOL_BREAKDOWN to info[0] and an identity R^-1.
 hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* Rinv, int64_t ldr,
                     float* Rinv32, int64_t ldr32, double shift_scale, int32_t* shifted,
-                    int32_t* info, const int32_t* skip_unless);
+                    int32_t* info, const int32_t* skip_unless, int32_t* run_next = nullptr, int nnext = 0);
 // Jacobi eigen-decomposition of a symmetric n x n matrix: eigenvalues descending,
 // eigenvectors in the columns of Vout (n x n, ld n).
 // rtol: rotate while |a_pq| > rtol sqrt(|a_pp a_qq|) (about 2 ulp for full FP64 accuracy).

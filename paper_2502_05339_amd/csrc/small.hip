@@ -102,13 +102,14 @@ __device__ __forceinline__ double cm_a(const double* M, int kk, int l16, int lg)
 __device__ __forceinline__ double cm_b(const double* M, int kk, int l16, int lg) { return M[(4 * kk + lg) * CM_LD + l16]; }
 
 // attempt 0 factors G as given; when it breaks down and shift_scale > 0 it only sets
-// *shifted, and attempt 1 (launched right after, a no-op unless *shifted is set)
-// factors G + shift_scale * trace(G) * I.  A breakdown without a further attempt
-// reports DMD_ERR_CHOL_BREAKDOWN and leaves the identity.
+// *shifted (and the nnext run flags of the passes a shifted pass needs after it), and
+// attempt 1 (launched right after, a no-op unless *shifted is set) factors
+// G + shift_scale * trace(G) * I.  A breakdown without a further attempt reports
+// DMD_ERR_CHOL_BREAKDOWN and leaves the identity.
 __global__ void __launch_bounds__(CM_THREADS)
 chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, int64_t ldr,
                 float* Rinv32, int64_t ldr32, double shift_scale, int attempt, int32_t* shifted,
-                int32_t* info, const int32_t* skip_unless)
+                int32_t* info, const int32_t* skip_unless, int32_t* run_next, int nnext)
 {
     if (skip_unless && *skip_unless == 0) return;
     if (attempt == 1 && (!shifted || *shifted == 0)) return;
@@ -198,6 +199,7 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
     if (fail && attempt == 0 && shift_scale > 0.0 && shifted) {
         if (tid == 0) {
             *shifted = 1;
+            for (int j = 0; j < nnext; ++j) run_next[j] = 1;
             if (info) atomicAdd(&info[3], 1);
         }
         return;
@@ -266,9 +268,10 @@ chol_inv_kernel(const double* __restrict__ G, int64_t ldg, int n, double* Rinv, 
 
 hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* Rinv, int64_t ldr,
                     float* Rinv32, int64_t ldr32, double shift_scale, int32_t* shifted,
-                    int32_t* info, const int32_t* skip_unless)
+                    int32_t* info, const int32_t* skip_unless, int32_t* run_next, int nnext)
 {
     if (n <= 0) return hipSuccess;
+    if (nnext > 0 && !run_next) return hipErrorInvalidValue;
     if (n > SMALL_MAX) return hipErrorInvalidValue;
     static_assert(CM_T - 1 <= CM_NW, "chol_inv_kernel: one block row per wave in the inverse");
     const size_t lds = cm_lds_bytes(n);
@@ -276,7 +279,7 @@ hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* 
     const int attempts = (shift_scale > 0.0 && shifted) ? 2 : 1;
     for (int at = 0; at < attempts; ++at) {
         hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(CM_THREADS), lds, s, G, ldg, n, Rinv, ldr, Rinv32, ldr32,
-                           shift_scale, at, shifted, info, skip_unless);
+                           shift_scale, at, shifted, info, skip_unless, run_next, nnext);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
