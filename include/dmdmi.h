@@ -66,7 +66,7 @@ typedef enum dmd_status {
     DMD_ERR_NONFINITE = 4,      /* NaN or Inf in the input (only with DMD_FIT_CHECK_FINITE) */
     DMD_ERR_CHOL_BREAKDOWN = 5, /* CholeskyQR failed even after the shifted retry */
     DMD_ERR_RANK = 6,           /* sigma_r <= rank_tol * sigma_1 */
-    DMD_ERR_EIG_NOCONV = 7,     /* Jacobi or Francis QR iteration limit reached */
+    DMD_ERR_EIG_NOCONV = 7,     /* an eigenvalue iteration reached its limit */
     DMD_ERR_DOMAIN = 8,         /* lambda = 0 raised to a negative or fractional power (device
                                    status word, see dmd_status_word) */
     DMD_ERR_OVERFLOW = 9,       /* |b| |lambda|^k beyond the output type's finite range (device
@@ -131,8 +131,9 @@ typedef struct dmd_fit_opts {
 
 /* Number of int32 words in model->info. */
 #define DMD_INFO_WORDS 8
-/* info[0] status, [1] Jacobi sweeps, [2] Francis QR iterations, [3] shifted
- * CholeskyQR retries, [4] OptDMD Levenberg-Marquardt steps, [5..7] reserved. */
+/* info[0] status, [1] Jacobi sweeps, [2] Ehrlich-Aberth iterations of the eigenvalues
+ * of Atilde, [3] shifted CholeskyQR retries, [4] OptDMD Levenberg-Marquardt steps,
+ * [5..7] reserved. */
 
 /* A DMD model; every pointer is device memory owned by the caller. */
 typedef struct dmd_model {
@@ -192,8 +193,9 @@ int32_t dmd_fit_workspace_size(int64_t n, int32_t ncols, int32_t xdtype,
  * Steps (Sec. 4.3 then Sec. 3.1): sketch Y = X Omega; CholeskyQR2 (FP64 Gram);
  * q power iterations W = orth(X^T Q), Y = X W; B = Q^T [X X']; eigen-decomposition
  * of the FP64 Gram B B^T by Jacobi (singular values and left vectors of B);
- * Atilde = U_r^T B' V_r S_r^-1; Hessenberg + Francis double-shift QR for
- * lambda and W; exact modes Phi = X' V_r S_r^-1 W; b = Phi^+ x_0.
+ * Atilde = U_r^T B' V_r S_r^-1; Hessenberg reduction, eigenvalues as the roots of
+ * det(zI - H) by the Ehrlich-Aberth iteration, eigenvectors W by inverse iteration;
+ * exact modes Phi = X' V_r S_r^-1 W; b = Phi^+ x_0.
  * Sizes: 1 <= r <= min(ncols, N, DMD_MAX_RANK); on the randomized paths
  * l = r + p <= min(ncols, N, DMD_MAX_SKETCH); on DMD_FIT_FP64_EXACT
  * ncols <= DMD_MAX_SMALL.  Violations return DMD_ERR_SHAPE (inconsistent sizes) or

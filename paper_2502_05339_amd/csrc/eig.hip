@@ -1,27 +1,20 @@
 // FP64 eigen-decomposition of the reduced operator Atilde W = W Lambda (Sec. 3.1).
 //
-// Real nonsymmetric n x n matrix (n <= DMD_MAX_RANK), three kernels:
+// Real nonsymmetric n x n matrix (n <= DMD_MAX_RANK), five kernels:
 //  1. hessenberg_kernel (1 work-group): Householder reduction A = Q H Q^T, H in
 //     registers across the work-group, the reflectors (v_k, tau_k) kept for
-//     rebuilding Q.
-//  2. francis_kernel (ceil(n / nr) work-groups): every work-group holds H packed
-//     in LDS (upper Hessenberg plus the two extra sub-diagonals a double-shift
-//     bulge needs) and runs the same implicit double-shift QR iteration with
-//     deflation, producing the real Schur form T; each work-group rebuilds and
-//     updates only its own nr rows of the Schur vectors Z (Z = Q * product of
-//     the QR reflectors), so no work-group ever waits for another.  2 x 2
-//     diagonal blocks with real eigenvalues are split by a rotation.  T, its block
-//     structure and Z go to global scratch.
-//  2b. eigvec_kernel (one single-wave work-group per eigenvalue): the eigenvector x
-//     of T by back-substitution, column by column (each lane keeps the residual of
-//     its rows, so a row costs one complex product and a broadcast), normalised to
-//     unit 2-norm (Z is orthogonal, so the norm carries over), then the column
-//     Z x of the eigenvector matrix (folded: [Re, Im] for a conjugate pair).
+//     rebuilding Q; H is written row-major with its trace and squared Frobenius norm.
+//  2. aberth_kernel (n single-wave work-groups): the eigenvalues as the roots of
+//     det(zI - H), all refined at once by the Ehrlich-Aberth iteration, each Newton
+//     ratio from a pivoted LU factorisation of H - zI differentiated in z.
+//  2b. eig_pair_kernel (1 work-group): real eigenvalues and conjugate pairs told apart
+//     and made exact (real, or exactly conjugate).
+//  2c. invit_kernel (one single-wave work-group per real eigenvalue or pair): the
+//     eigenvector by inverse iteration on H, taken through Q, normalised to unit 2-norm
+//     (folded: [Re, Im] for a conjugate pair).
 //  3. sort_modes_kernel (1 work-group): canonical order (ascending |arg lambda|,
 //     ties by descending |lambda|, Im > 0 member of a pair first), lambda, kind
 //     and the permuted folded eigenvectors (pair -> [Re w, Im w], LAPACK storage).
-#include <type_traits>
-
 #include "common.h"
 #include "kernels.h"
 
@@ -29,44 +22,47 @@ namespace dmd {
 
 // workspace layout (doubles unless noted)
 struct EigWs {
-    double* H;      // n x n
-    double* V;      // n x n reflector vectors (column k: rows k+1..n-1)
-    double* tau;    // n
-    double* Wraw;   // n x n unsorted folded eigenvectors
-    double* wr;     // n
-    double* wi;     // n
-    int32_t* kind0; // n
-    double* Z;      // n x n Schur vectors, column-major
-    double* T;      // real Schur form, packed as in francis_kernel (<= n x n), then max |T_ij|
-    int32_t* blk;   // n: 0 real eigenvalue, 1/2 first/second of a 2 x 2 block
+    double* H;        // n x n row-major Hessenberg matrix, then trace(H) and ||H||_F^2
+    double* V;        // n x n reflector vectors (column k: rows k+1..n-1)
+    double* tau;      // n
+    double* Wraw;     // n x n unsorted folded eigenvectors
+    double* wr;       // n
+    double* wi;       // n
+    double* zbuf;     // 2 x 2n: two iterates of the eigenvalue approximations (re, im)
+    double* zfin;     // 2n: converged approximations
+    double* Us;       // per output position, the packed rows of U (complex): n * n(n+1)/2 * 2
+    int32_t* kind0;   // n
+    int32_t* conv;    // 2 x n: converged flags of the two iterates
+    uint32_t* counter;
 };
 
-static int eig_rows_per_wg(int n) { return n <= 64 ? 8 : 16; }
-static int eig_grid(int n) { return (int)ceil_div(n, eig_rows_per_wg(n)); }
+static size_t eig_upk(int n) { return (size_t)n * (n + 1) / 2; }
 
 size_t eig_workspace_bytes(int n)
 {
-    size_t nn = (size_t)n * n;
-    return (5 * nn + 2 + 4 * (size_t)n) * sizeof(double) + 2 * (size_t)round_up((int64_t)n * sizeof(int32_t), 64) + 256;
+    const size_t nn = (size_t)n * n;
+    const size_t dbl = (nn + 2) + nn + n + nn + 2 * (size_t)n + 4 * (size_t)n + 2 * (size_t)n + (size_t)n * 2 * eig_upk(n);
+    return dbl * sizeof(double) + 3 * (size_t)round_up((int64_t)n * sizeof(int32_t), 64) + 64 + 256;
 }
 
 static EigWs eig_carve(void* ws, int n)
 {
     EigWs w;
     double* p = (double*)ws;
-    size_t nn = (size_t)n * n;
-    w.H = p; p += nn;
+    const size_t nn = (size_t)n * n;
+    w.H = p; p += nn + 2;
     w.V = p; p += nn;
-    w.Wraw = p; p += nn;
-    w.Z = p; p += nn;
-    w.T = p; p += nn + 2;                // + max |T_ij|
     w.tau = p; p += n;
+    w.Wraw = p; p += nn;
     w.wr = p; p += n;
     w.wi = p; p += n;
-    p += n;
-    w.kind0 = (int32_t*)p;
-    p = (double*)((char*)p + round_up((int64_t)n * sizeof(int32_t), 64));
-    w.blk = (int32_t*)p;
+    w.zbuf = p; p += 4 * (size_t)n;
+    w.zfin = p; p += 2 * (size_t)n;
+    w.Us = p; p += (size_t)n * 2 * eig_upk(n);
+    char* q = (char*)p;
+    w.kind0 = (int32_t*)q; q += round_up((int64_t)n * sizeof(int32_t), 64);
+    w.conv = (int32_t*)q; q += 2 * round_up((int64_t)n * sizeof(int32_t), 64);
+    w.counter = (uint32_t*)q;
     return w;
 }
 
@@ -224,440 +220,57 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
         }
         __syncthreads();
     }
+    // H row-major, then its trace and squared Frobenius norm (fixed-order sums)
+    double tr = 0.0, f2 = 0.0;
 #pragma unroll
     for (int a = 0; a < HS_N; ++a)
 #pragma unroll
         for (int c = 0; c < HS_N; ++c) {
             const int i = ib + 32 * a, j = jb + 32 * c;
-            if (i < n && j < n) H[(int64_t)j * n + i] = h[a][c];
+            if (i < n && j < n) {
+                H[(int64_t)i * n + j] = h[a][c];
+                f2 = fma(h[a][c], h[a][c], f2);
+                if (i == j) tr += h[a][c];
+            }
         }
-}
-
-// ====================================================================== 2. Francis QR
-// Packed Hessenberg with 3 sub-diagonals: column j holds rows 0..min(j+3, n-1), i.e.
-// min(j+4, n) entries; the offset of column j is computed, not looked up.
-__host__ __device__ __forceinline__ int hp_col(int j, int n) {
-    const int head = (j * (j + 7)) >> 1;                             // columns 0..j-1 all hold i+4 rows
-    const int tail = (((n - 3) * (n + 4)) >> 1) + (j - (n - 3)) * n;  // full columns from n-3 on
-    return n <= 4 ? j * n : (j <= n - 3 ? head : tail);
-}
-constexpr int FR_THREADS = 256;
-constexpr int FR_VCH = 16;    // reflectors staged in LDS at a time in the Z-slab setup
-// row-update roles use threads 1..n, Z-slab roles the last 16, plus one deferred-write thread
-static_assert(EIG_MAX + 1 + 1 + 16 <= FR_THREADS, "francis_kernel thread roles overlap");
-
-struct HP {
-    double* a;
-    int n;
-    __device__ __forceinline__ double& operator()(int i, int j) const { return a[hp_col(j, n) + i]; }
-};
-
-
-__device__ __forceinline__ void house3(double x, double y, double z, double* v1, double* v2, double* tau, double* beta)
-{
-    const double nrm = sqrt(x * x + y * y + z * z);
-    if (nrm == 0.0 || (y == 0.0 && z == 0.0)) { *tau = 0.0; *v1 = 0.0; *v2 = 0.0; *beta = x; return; }
-    const double b = x >= 0.0 ? -nrm : nrm;
-    const double d = x - b;                 // |d| >= |x|, never zero here
-    const double ibd = 1.0 / (b * d);       // one division gives 1/b and 1/d
-    *tau = -d * d * ibd;                    // (b - x) / b
-    const double sc = b * ibd;              // 1 / (x - b)
-    *v1 = y * sc;
-    *v2 = z * sc;
-    *beta = b;
-}
-
-// Reflector of the bulge step in unnormalised form: P = I - t u u^T with u = (d, y, z),
-// d = x - beta, beta = -sign(x) ||(x, y, z)||, and t = 2 / (u^T u) taken from the u that
-// is actually used, so P is orthogonal to rounding whatever the error of the norm.
-// P (x, y, z)^T = (beta, 0, 0)^T.  t = 0 when y = z = 0 (P = I).
-__device__ __forceinline__ void reflector3(double x, double y, double z, double* d, double* t, double* beta)
-{
-    const double yz = fma(y, y, z * z);
-    const double sig = fma(x, x, yz);
-    if (yz == 0.0 || !(sig >= 1e-280)) {      // nothing to annihilate, or too small to scale safely
-        if (yz == 0.0) { *t = 0.0; *d = 0.0; *beta = x; return; }
-        double v1, v2, tau, b;
-        house3(x, y, z, &v1, &v2, &tau, &b);
-        // same reflector: u = (x - b) (1, v1, v2), t = tau / (x - b)^2
-        const double dd = x - b;
-        *d = dd; *t = tau / (dd * dd); *beta = b;
-        return;
-    }
-    const double r = rsqrt_nr(sig);
-    const double nrm = sig * r;
-    const double dd = x >= 0.0 ? x + nrm : x - nrm;
-    *d = dd;
-    *beta = x >= 0.0 ? -nrm : nrm;
-    *t = 2.0 * rcp_nr(fma(dd, dd, yz));
-}
-
-__global__ void __launch_bounds__(FR_THREADS)
-francis_kernel(int n, int nr, const double* __restrict__ Hg, const double* __restrict__ Vg,
-               const double* __restrict__ taug, double* Zg, double* Tg, int32_t* blkg, double* wr, double* wi,
-               int32_t* kind0, int32_t* info, double defl_tol)
-{
-    extern __shared__ double sm[];
-    int* blk = reinterpret_cast<int*>(sm);                      // n ints
-    const int ioff = (int)round_up(n, 2) / 2;                   // in doubles
-    double* Hs = sm + ioff;
-    __shared__ int sh_l, sh_stop, sh_iter_total;
-    __shared__ double sh_v[4];   // rotation of a 2x2 block split
-    __shared__ int sh_lc[2];     // deflation search result (double-buffered)
-    __shared__ double sh_red[4];
-
-    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, nw = nt >> 6;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: wave-level branches stay scalar
-    const int hsize = hp_col(n, n);
-    double* Zs = Hs + hsize;                                    // nr x n
-    HP H{Hs, n};
-    const int r0 = blockIdx.x * nr;
-    const int nrows = min(nr, n - r0);
-
-    // packed H, eight columns at a time with their loads in flight (nt > n + 3: one entry
-    // of a column per thread)
-    static_assert(FR_THREADS > EIG_MAX + 3, "francis_kernel loads one entry per column and thread");
-    for (int j0 = 0; j0 < n; j0 += 8) {
-        double hv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = j0 + u;
-            hv[u] = (j < n && tid <= j + 1 && tid < n) ? Hg[(int64_t)j * n + tid] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const int j = j0 + u;
-            if (j < n && tid <= min(j + 3, n - 1)) H(tid, j) = hv[u];
-        }
-    }
-    // Z slab = rows r0.. of Q = P_0 P_1 ... P_{n-3}: identity rows with the reflectors applied
-    // on the right (below)
+    gpart[tid] = f2;
+    upart[tid] = tr;
     __syncthreads();
-    // Each group of 16 lanes keeps one row of the slab in registers (entries gl + 16 s) and
-    // takes it through the reflectors in order: per reflector a 16-lane dot product (a
-    // fixed-shape sum inside the group) and an update.  The reflectors come in chunks of
-    // FR_VCH columns of V (and their tau) copied to LDS by the whole work-group with all
-    // loads in flight.  V is zero above the start of each reflector, so every slot takes part.
-    {
-        constexpr int ZS = (EIG_MAX + 15) / 16;                     // row entries per lane
-        static_assert(FR_THREADS / 16 >= 16, "one 16-lane group per Z-slab row (16 rows at most)");
-        const int grp = tid >> 4, gl = tid & 15;
-        double zr[ZS];
+    if (wave == 0) {
+        double a = 0.0, b = 0.0;
 #pragma unroll
-        for (int sl = 0; sl < ZS; ++sl) {
-            const int j = gl + 16 * sl;
-            zr[sl] = (grp < nrows && j < n && r0 + grp == j) ? 1.0 : 0.0;
-        }
-        double* Vst = Zs + nr * n;                                  // FR_VCH x n
-        double* tst = Vst + FR_VCH * n;                             // FR_VCH
-        for (int k0 = 0; k0 + 2 < n; k0 += FR_VCH) {
-            const int kc = min(FR_VCH, n - 2 - k0);
-            __syncthreads();                                        // the previous chunk is consumed
-            for (int e0 = tid; e0 < kc * n; e0 += 4 * nt) {
-                double t4[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int e = e0 + u * nt;
-                    t4[u] = e < kc * n ? Vg[(int64_t)k0 * n + e] : 0.0;
-                }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    if (e0 + u * nt < kc * n) Vst[e0 + u * nt] = t4[u];
-            }
-            if (tid < kc) tst[tid] = taug[k0 + tid];
-            __syncthreads();
-            for (int kk = 0; kk < kc; ++kk) {
-                const double tk = tst[kk];
-                if (tk == 0.0) continue;                            // uniform
-                const double* v = Vst + kk * n;
-                double vv[ZS];
-                double d = 0.0;
-#pragma unroll
-                for (int sl = 0; sl < ZS; ++sl) {
-                    const int j = gl + 16 * sl;
-                    vv[sl] = j < n ? v[j] : 0.0;
-                    d = fma(zr[sl], vv[sl], d);
-                }
-                d += __shfl_xor(d, 8, 16);
-                d += __shfl_xor(d, 4, 16);
-                d += __shfl_xor(d, 2, 16);
-                d += __shfl_xor(d, 1, 16);
-                d *= tk;
-#pragma unroll
-                for (int sl = 0; sl < ZS; ++sl) zr[sl] -= d * vv[sl];
-            }
-        }
-        // the slab into LDS for the QR iteration (rows past nrows are zero)
-        if (grp < nr)
-#pragma unroll
-            for (int sl = 0; sl < ZS; ++sl) {
-                const int j = gl + 16 * sl;
-                if (j < n) Zs[grp * n + j] = zr[sl];
-            }
-    }
-    __syncthreads();
-
-    // max |H_ij| (used when a diagonal pair is exactly zero, and for the pivot floor)
-    {
-        double mx = 0.0;
-        for (int j = tid; j < n; j += nt)
-            for (int i = 0; i <= min(j + 1, n - 1); ++i) mx = fmax(mx, fabs(H(i, j)));
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        if (lane == 0) sh_red[wave] = mx;
-        __syncthreads();
-        if (tid == 0) { double m = 0.0; for (int w = 0; w < nw; ++w) m = fmax(m, sh_red[w]); sh_red[0] = m; }
-        __syncthreads();
-    }
-    const double hnorm = sh_red[0];
-    const double eps = defl_tol;             // deflation: |h(k,k-1)| <= eps (|h(k-1,k-1)| + |h(k,k)|)
-    if (tid == 0) { sh_stop = 0; sh_iter_total = 0; }
-    __syncthreads();
-    // ---- implicit double-shift QR (all waves; one barrier per bulge step)
-    // Roles within bulge step k (reflector P_k on rows/columns k .. k+m-1, m = 3, or 2
-    // for the final step of a sweep), fixed by the thread index:
-    //   tid <= min(k+3, hi)      column update of row tid; the rows k .. k+m-1 first
-    //                            apply the row update to their corner entries
-    //   k+m <= tid-1 < n         row update of column tid-1
-    //   tid >= nt - nrows        column update of one row of this work-group's Z slab
-    //   tid == nt - nrows - 1    deferred write of the column that step k-1 reduced
-    // The roles touch disjoint entries, so the only barrier is the one that ends the step.
-    {
-        int hi = n - 1, its = 0, total = 0, parity = 0;
-        bool stop = false;
-        const int zt0 = nt - nrows;              // first Z-role thread
-        const int pend_t = zt0 - 1;              // thread doing the deferred writes
-        const bool zrole = tid >= zt0;
-        // offset (from Hs) of this thread's row-update column tid-1 or Z-slab row
-        const int base_t = (tid >= 1 && tid <= n) ? hp_col(tid - 1, n) : (zrole ? hsize + (tid - zt0) * n : 0);
-        if (tid == 0) { sh_lc[0] = 0; sh_lc[1] = 0; }
-        __syncthreads();
-        while (hi >= 0) {
-            // deflation point: largest l <= hi with negligible H(l, l-1), searched in parallel
-            for (int k = hi - tid; k >= 1; k -= nt) {
-                double sd = fabs(H(k - 1, k - 1)) + fabs(H(k, k));
-                if (sd == 0.0) sd = hnorm;
-                if (fabs(H(k, k - 1)) <= eps * sd) { atomicMax(&sh_lc[parity], k); break; }
-            }
-            __syncthreads();
-            const int l = sh_lc[parity];
-            if (tid == 0) {
-                sh_lc[parity ^ 1] = 0;
-                if (l > 0) H(l, l - 1) = 0.0;   // deflate exactly (read again only after a barrier)
-            }
-            parity ^= 1;
-            if (l == hi) { hi -= 1; its = 0; __syncthreads(); continue; }
-            if (l == hi - 1) {
-                // 2x2 block (p, q): split it if its eigenvalues are real
-                const int p = hi - 1, q = hi;
-                const double a = H(p, p), b = H(p, q), c = H(q, p), d = H(q, q);
-                double cs_ = 1.0, sn_ = 0.0;
-                bool rot = false;
-                if (c != 0.0) {
-                    const double hp = 0.5 * (a - d);
-                    const double disc = hp * hp + b * c;
-                    if (disc >= 0.0) {
-                        const double sq = sqrt(disc);
-                        const double mu = 0.5 * (a + d) + (hp >= 0.0 ? sq : -sq);
-                        double e1 = b, e2 = mu - a;             // eigenvector (b, mu - a)
-                        double f1 = mu - d, f2 = c;             // or (mu - d, c)
-                        if (e1 * e1 + e2 * e2 < f1 * f1 + f2 * f2) { e1 = f1; e2 = f2; }
-                        const double nr_ = sqrt(e1 * e1 + e2 * e2);
-                        if (nr_ > 0.0) { cs_ = e1 / nr_; sn_ = e2 / nr_; rot = true; }
-                    }
-                }
-                __syncthreads();
-                if (rot) {
-                    for (int j = p + tid; j < n; j += nt) {          // rows p, q <- G^T rows
-                        const double x = H(p, j), y = H(q, j);
-                        H(p, j) = cs_ * x + sn_ * y;
-                        H(q, j) = -sn_ * x + cs_ * y;
-                    }
-                    __syncthreads();
-                    for (int i = tid; i <= q; i += nt) {             // columns p, q <- columns G
-                        const double x = H(i, p), y = H(i, q);
-                        H(i, p) = cs_ * x + sn_ * y;
-                        H(i, q) = -sn_ * x + cs_ * y;
-                    }
-                    for (int rl = tid; rl < nrows; rl += nt) {
-                        const double x = Zs[rl * n + p], y = Zs[rl * n + q];
-                        Zs[rl * n + p] = cs_ * x + sn_ * y;
-                        Zs[rl * n + q] = -sn_ * x + cs_ * y;
-                    }
-                    __syncthreads();
-                    if (tid == 0) H(q, p) = 0.0;
-                }
-                hi -= 2; its = 0;
-                __syncthreads();
-                continue;
-            }
-            ++its;
-            if (++total > 40 * n) { stop = true; break; }   // uniform: every thread counts alike
-            // shifts: eigenvalues of the trailing 2x2 block (exceptional shifts at 10 and 20)
-            double s, t;
-            if (its == 10 || its == 20) {
-                const double w = fabs(H(hi, hi - 1)) + (hi >= 2 ? fabs(H(hi - 1, hi - 2)) : 0.0);
-                s = 2.0 * H(hi, hi) + 1.5 * w;
-                t = (H(hi, hi) + 0.75 * w) * (H(hi, hi) + 0.75 * w);
-            } else {
-                s = H(hi - 1, hi - 1) + H(hi, hi);
-                t = H(hi - 1, hi - 1) * H(hi, hi) - H(hi - 1, hi) * H(hi, hi - 1);
-            }
-            // first column of (H - mu1)(H - mu2) on the active block
-            const double x0 = H(l, l) * H(l, l) + H(l, l + 1) * H(l + 1, l) - s * H(l, l) + t;
-            const double y0 = H(l + 1, l) * (H(l, l) + H(l + 1, l + 1) - s);
-            const double z0 = H(l + 1, l) * H(l + 2, l + 1);
-            __syncthreads();   // every thread has read the shift inputs before H changes
-            int pk = -1;       // column reduced by the previous step, written one step late
-            int poff = 0;      // its packed offset
-            double pbeta = 0.0;
-            // packed offsets of columns k-1 .. k+2, advanced by the column lengths min(j+4, n)
-            int hm = hp_col(max(l - 1, 0), n), hk0 = hp_col(l, n), hk1 = hp_col(l + 1, n), hk2 = hp_col(l + 2, n);
-            double e0 = 0.0, e1 = 0.0, e2 = 0.0;   // this thread's operands, carried between steps
-            int prole = 0;
-            // One bulge step k.  G (general) covers the first step of the sweep (vector from
-            // the shift polynomial) and the last two (the block ends: m = 2 or rows past
-            // hi); every other step takes the lean path with m = 3 and rows up to k+3.
-            auto step = [&](const int k, auto general) {
-                constexpr bool G = decltype(general)::value;
-                const int m = G ? ((k == hi - 1) ? 2 : 3) : 3;
-                const int crow = G ? min(k + 3, hi) : k + 3;
-                if (!G || k > l) { hm = hk0; hk0 = hk1; hk1 = hk2; hk2 += min(k + 5, n); }
-                // ---- loads, all issued before the reflector is formed
-                double x, y, z;
-                if (G && k == l) { x = x0; y = y0; z = z0; }
-                else { x = Hs[hm + k]; y = Hs[hm + k + 1]; z = Hs[hm + k + 2]; }
-                // role: 1 column update of row tid, 2 row update of column tid-1, 3 Z row
-                const bool colr = tid <= crow;
-                const int role = colr ? 1 : (zrole ? 3 : ((tid - 1 >= k + m && tid <= n) ? 2 : 0));
-                const int o0 = colr ? hk0 + tid : base_t + k;
-                const int o1 = colr ? hk1 + tid : base_t + k + 1;
-                const int o2 = colr ? hk2 + tid : base_t + k + 2;
-                // a thread that keeps its role finds two of its operands in registers (the
-                // entries it updated in the previous step); only the third is new
-                if (role != prole || (G && k == l)) { e0 = Hs[o0]; e1 = Hs[o1]; }
-                e2 = Hs[o2];
-                prole = role;
-                // the corner C(a, b) = H(k+a, k+b) is needed only by the waves holding rows k..k+m-1
-                const bool cw = (wave == (k >> 6)) || (wave == ((k + m - 1) >> 6));
-                double c00, c10, c20, c01, c11, c21, c02, c12, c22;   // read only where cw
-                if (cw) {
-                    c00 = Hs[hk0 + k]; c10 = Hs[hk0 + k + 1]; c20 = Hs[hk0 + k + 2];
-                    c01 = Hs[hk1 + k]; c11 = Hs[hk1 + k + 1]; c21 = Hs[hk1 + k + 2];
-                    c02 = Hs[hk2 + k]; c12 = Hs[hk2 + k + 1]; c22 = Hs[hk2 + k + 2];
-                }
-                if (G && m == 2) {
-                    z = 0.0; e2 = 0.0;
-                    if (cw) { c20 = 0.0; c21 = 0.0; c02 = 0.0; c12 = 0.0; c22 = 0.0; }
-                }
-                double d, t, beta;
-                reflector3(x, y, z, &d, &t, &beta);
-                // ---- P_k = I - t u u^T, u = (d, y, z), applied to the operands: rows k..k+m-1
-                // of the corner first take the row update (s_b), then every role applies the
-                // same formula (P is symmetric, so rows and columns transform alike)
-                if (t != 0.0) {
-                    if (cw) {
-                        const double s0 = (d * c00 + y * c10 + z * c20) * t;
-                        const double s1 = (d * c01 + y * c11 + z * c21) * t;
-                        const double s2 = (d * c02 + y * c12 + z * c22) * t;
-                        const int a = tid - k;
-                        const double ua = !colr ? 0.0 : (a == 0 ? d : (a == 1 ? y : (a == 2 ? z : 0.0)));
-                        e0 -= ua * s0;
-                        e1 -= ua * s1;
-                        e2 -= ua * s2;
-                    }
-                    const double w = (d * e0 + y * e1 + z * e2) * t;
-                    e0 -= w * d;
-                    e1 -= w * y;
-                    e2 -= w * z;
-                    if (role != 0) {
-                        Hs[o0] = e0;
-                        Hs[o1] = e1;
-                        if (!G || m == 3) Hs[o2] = e2;
-                    }
-                }
-                if (tid == pend_t && pk >= 0) {             // column pk: (beta, 0, 0) below its subdiagonal
-                    Hs[poff + pk + 1] = pbeta; Hs[poff + pk + 2] = 0.0;
-                    if (pk + 3 <= hi) Hs[poff + pk + 3] = 0.0;
-                }
-                if (!G || k > l) { pk = k - 1; poff = hm; pbeta = beta; }
-                // operands of the next step: this step's second and third entries
-                e0 = e1; e1 = e2;
-                __syncthreads();
-            };
-            step(l, std::true_type{});
-            for (int k = l + 1; k <= hi - 3; ++k) step(k, std::false_type{});
-            for (int k = max(l + 1, hi - 2); k <= hi - 1; ++k) step(k, std::true_type{});
-            if (tid == pend_t && pk >= 0) {
-                Hs[poff + pk + 1] = pbeta; Hs[poff + pk + 2] = 0.0;
-                if (pk + 3 <= hi) Hs[poff + pk + 3] = 0.0;
-            }
-            __syncthreads();
-        }
-        if (tid == 0) { sh_stop = stop ? 1 : 0; sh_iter_total = total; }
-    }
-    __syncthreads();
-    if (sh_stop) {
-        if (blockIdx.x == 0 && tid == 0) set_status(info, DMD_ERR_EIG_NOCONV);
-    }
-    if (blockIdx.x == 0 && tid == 0 && info) atomicAdd(&info[2], sh_iter_total);
-
-    // ---- block structure of T and eigenvalues
-    if (tid == 0) {
-        int k = 0;
-        while (k < n) {
-            if (k + 1 < n && H(k + 1, k) != 0.0) { blk[k] = 1; blk[k + 1] = 2; k += 2; }
-            else { blk[k] = 0; k += 1; }
-        }
-    }
-    __syncthreads();
-    if (blockIdx.x == 0) {
-        for (int k = tid; k < n; k += nt) {
-            if (blk[k] == 0) { wr[k] = H(k, k); wi[k] = 0.0; kind0[k] = 0; }
-            else {
-                const int p = blk[k] == 1 ? k : k - 1;
-                const double a = H(p, p), b = H(p, p + 1), c = H(p + 1, p), d = H(p + 1, p + 1);
-                const double hp = 0.5 * (a - d);
-                const double im = sqrt(fmax(-(hp * hp + b * c), 0.0));
-                wr[k] = 0.5 * (a + d);
-                wi[k] = blk[k] == 1 ? im : -im;
-                kind0[k] = blk[k];
-            }
-        }
-    }
-    // ---- T, max |T_ij| (stored after T), the block structure and this work-group's rows
-    // of Z to global scratch
-    if (blockIdx.x == 0) {
-        double mx = 0.0;
-        for (int j = tid; j < n; j += nt)
-            for (int i = 0; i <= min(j + 1, n - 1); ++i) mx = fmax(mx, fabs(H(i, j)));
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-        __syncthreads();
-        if (lane == 0) sh_red[wave] = mx;
-        __syncthreads();
-        if (tid == 0) { double m = 0.0; for (int w = 0; w < nw; ++w) m = fmax(m, sh_red[w]); Tg[hsize] = m; }
-        for (int e = tid; e < hsize; e += nt) Tg[e] = Hs[e];
-        for (int k = tid; k < n; k += nt) blkg[k] = blk[k];
-    }
-    for (int e = tid; e < nrows * n; e += nt) {
-        const int rl = e % nrows, c = e / nrows;
-        Zg[(int64_t)c * n + r0 + rl] = Zs[rl * n + c];
+        for (int q = 0; q < 16; ++q) { a += gpart[q * 64 + lane]; b += upart[q * 64 + lane]; }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        if (lane == 0) { H[(int64_t)n * n] = b; H[(int64_t)n * n + 1] = a; }
     }
 }
 
-// ====================================================================== 2b. eigenvectors
-// Eigenvector of the quasi-triangular T for eigenvalue index k (lambda = lre + i lim; a
-// pair's first member has lim > 0), by back-substitution on (T - lambda) x = 0 with x_j = 0
-// for j > top.  Column-oriented: lane l keeps the residuals r_i = -sum_{j > i} T(i, j) x_j
-// of rows i = l, l + 64, l + 128; once x_i (or the pair x_ia, x_i of a 2 x 2 block) is known
-// from the owner lane's residual, every lane subtracts T(i', i) x_i from its rows i' above.
-// Tiny pivots are raised to smin; entries past 1e100 rescale x and r.
-constexpr int EV_SLOTS = (EIG_MAX + 63) / 64;
-static_assert(EV_SLOTS <= 4, "eigvec_kernel keeps at most 4 rows per lane");
-// rows of one lane, as one vector value: a run-time element index on a vector stays in
+// ====================================================================== 2. eigenvalues
+// Ehrlich-Aberth iteration on p(z) = det(zI - H), all n approximations at once:
+//   z_i <- z_i - 1 / (p'(z_i)/p(z_i) - sum_{j != i} 1 / (z_i - z_j)).
+// p'/p(z) = d/dz log det(H - zI) = sum_k u'_kk / u_kk over the pivots of the LU
+// factorisation of H - zI with partial pivoting, differentiated in z alongside.  A
+// Hessenberg matrix has one candidate row below each pivot, so the elimination carries a
+// single active row (and its derivative) and reads row k + 1 of H at step k.
+// One single-wave work-group per approximation, lanes over the columns of the active row.
+// Iterations are separated by a grid-wide barrier (a counter in the workspace), so every
+// approximation is updated from the same previous iterate and the result does not depend
+// on scheduling.  The barrier's wait is bounded: a work-group that waits past the bound
+// reports DMD_ERR_EIG_NOCONV and leaves, which ends the other work-groups' waits too.
+// Start: n points on the circle about trace(H)/n whose radius is the spread
+// (||H||_F^2 / n - |trace(H)/n|^2)^(1/2) that bounds the eigenvalues' deviation from their
+// mean (Schur's inequality).  A root is converged when its correction falls below tol
+// relative to |z| (the next correction of a simple root is of the cube of that size), or
+// below 1e-9 |z| without shrinking by a factor 4 any more (the rounding floor of the
+// evaluation, reached by clustered roots).
+constexpr int AB_SLOTS = (EIG_MAX + 63) / 64;
+static_assert(AB_SLOTS <= 4, "aberth_kernel keeps at most 4 columns per lane");
+// columns of one lane, as one vector value: a run-time element index on a vector stays in
 // registers, where the same index on a private array would put it in scratch
-typedef double evrow __attribute__((ext_vector_type(4)));
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+constexpr int AB_MAX_IT = 200;
+constexpr uint32_t AB_SPIN_CAP = 1u << 22;
 
 __device__ __forceinline__ double bcast(double v, int src)
 {
@@ -666,155 +279,477 @@ __device__ __forceinline__ double bcast(double v, int src)
     return __hiloint2double(hi, lo);
 }
 
-__global__ void __launch_bounds__(64)
-eigvec_kernel(int n, const double* __restrict__ Tg, const int32_t* __restrict__ blkg,
-              const double* __restrict__ Zg, double* __restrict__ Wraw, double eps)
+// Start point j of the iteration (the same formula on every work-group).
+__device__ __forceinline__ void ab_start(int j, int n, double cr, double rho, double* zr, double* zi)
 {
-    extern __shared__ __align__(16) double evs[];
-    const int k = blockIdx.x, lane = threadIdx.x;
-    const int bk = blkg[k];
-    if (bk == 2) return;                                   // second member: done with the first
-    const bool pair = bk == 1;
-    const int top = pair ? k + 1 : k;
-    const int tsize = hp_col(top + 1, n);                  // columns 0..top of T
-    double* Ts = evs;
-    double* xs = evs + round_up(hp_col(n, n), 2);          // 2n: normalised Re, Im of x
-    int* bs = reinterpret_cast<int*>(xs + 2 * n);          // n: block structure
-    for (int e0 = lane; e0 < tsize; e0 += 8 * 64) {          // eight loads in flight per lane
-        double tv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) tv[u] = e0 + 64 * u < tsize ? Tg[e0 + 64 * u] : 0.0;
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (e0 + 64 * u < tsize) Ts[e0 + 64 * u] = tv[u];
-    }
-    for (int e = lane; e < n; e += 64) bs[e] = blkg[e];
-    __syncthreads();
-    HP T{Ts, n};
+    double s, c;
+    sincospi(2.0 * (j + 0.4) / n, &s, &c);
+    *zr = fma(rho, c, cr);
+    *zi = rho * s;
+}
 
-    const double smin = fmax(eps * Tg[hp_col(n, n)], 1e-290);   // max |T_ij| is stored after T
-    double lre, lim;
-    cplx xk, xk1 = {0.0, 0.0};
-    if (!pair) { lre = T(k, k); lim = 0.0; xk = {1.0, 0.0}; }
-    else {
-        const double a = T(k, k), b = T(k, k + 1), c = T(k + 1, k), d = T(k + 1, k + 1);
-        const double hp = 0.5 * (a - d);
-        lre = 0.5 * (a + d);
-        lim = sqrt(fmax(-(hp * hp + b * c), 0.0));
-        // eigenvector of [[a b][c d]] for lre + i lim: (b, lambda - a) or (lambda - d, c)
-        double e1r = b, e1i = 0.0, e2r = lre - a, e2i = lim;
-        const double f1r = lre - d, f1i = lim, f2r = c, f2i = 0.0;
-        if (e1r * e1r + e2r * e2r + e2i * e2i < f1r * f1r + f1i * f1i + f2r * f2r) {
-            e1r = f1r; e1i = f1i; e2r = f2r; e2i = f2i;
-        }
-        xk = {e1r, e1i};
-        xk1 = {e2r, e2i};
-    }
-    // this lane's rows: residuals and solution entries
-    evrow rr, ri, xr, xi;
+// Row k + 1 of H for the lane's columns c > k (zero elsewhere), and the sub-diagonal
+// entry H(k + 1, k): the operands of elimination step k.
+struct AbRow {
+    dvec4 v;
+    double sub;
+};
+__device__ __forceinline__ AbRow ab_load_row(const double* __restrict__ Hr, int n, int k, int lane)
+{
+    AbRow r;
+    const double* row = Hr + (int64_t)(k + 1) * n;
 #pragma unroll
-    for (int s = 0; s < EV_SLOTS; ++s) {
-        const int row = lane + 64 * s;
-        rr[s] = 0.0; ri[s] = 0.0;
-        xr[s] = row == k ? xk.re : (pair && row == k + 1 ? xk1.re : 0.0);
-        xi[s] = row == k ? xk.im : (pair && row == k + 1 ? xk1.im : 0.0);
-        if (row < k) {
-            const double t0 = T(row, k);
-            rr[s] = -t0 * xk.re; ri[s] = -t0 * xk.im;
-            if (pair) { const double t1 = T(row, k + 1); rr[s] -= t1 * xk1.re; ri[s] -= t1 * xk1.im; }
-        }
+    for (int s = 0; s < AB_SLOTS; ++s) {
+        const int c = lane + 64 * s;
+        r.v[s] = (c > k && c < n) ? row[c] : 0.0;
     }
-    int i = k - 1;
-    while (i >= 0) {
-        const bool two = bs[i] == 2;
-        const int ia = two ? i - 1 : i;
-        // residuals of rows ia, i from their owner lanes
-        auto slot_val = [&](const evrow& v, int row) { return bcast(v[row >> 6], row & 63); };
-        cplx x1, x0 = {0.0, 0.0};
-        const cplx s1 = {slot_val(rr, i), slot_val(ri, i)};
-        if (!two) {
-            cplx d = {T(i, i) - lre, -lim};
-            if (fabs(d.re) + fabs(d.im) < smin) d = {smin, 0.0};
-            x1 = cdiv(s1, d);
+    r.sub = row[k];
+    return r;
+}
+
+// p'/p at z for the row-major Hessenberg matrix Hr; false when H - zI has an exactly zero
+// pivot (z is an eigenvalue).  Row k + 2 is loaded while step k runs.
+__device__ bool ab_logdet_deriv(const double* __restrict__ Hr, int n, int lane, double zr, double zi,
+                                double* sr_out, double* si_out)
+{
+    dvec4 ar, ai, dr, di;
+#pragma unroll
+    for (int s = 0; s < AB_SLOTS; ++s) {
+        const int c = lane + 64 * s;
+        ar[s] = c < n ? Hr[c] : 0.0;
+        ai[s] = 0.0;
+        dr[s] = 0.0;
+        di[s] = 0.0;
+        if (c == 0) { ar[s] -= zr; ai[s] = -zi; dr[s] = -1.0; }
+    }
+    double sr = 0.0, si = 0.0;
+    bool sing = false;
+    AbRow nxt = ab_load_row(Hr, n, 0, lane);
+    for (int k = 0; k + 1 < n; ++k) {
+        const AbRow cur = nxt;
+        if (k + 2 < n) nxt = ab_load_row(Hr, n, k + 1, lane);
+        const int ks = k >> 6, kl = k & 63;
+        const double akr = bcast(ar[ks], kl), aki = bcast(ai[ks], kl);
+        const double dkr = bcast(dr[ks], kl), dki = bcast(di[ks], kl);
+        const double bk = cur.sub;
+        if (fabs(bk) > fabs(akr) + fabs(aki)) {
+            // pivot on row k + 1 (real pivot, no z at column k): a <- a - l b, l = a_k / b_k
+            const double ib = 1.0 / bk;
+            const double lr = akr * ib, li = aki * ib;
+            const double dlr = dkr * ib, dli = dki * ib;
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) {
+                const int c = lane + 64 * s;
+                if (c <= k || c >= n) continue;
+                double bcr = cur.v[s], bci = 0.0, dbr = 0.0;
+                if (c == k + 1) { bcr -= zr; bci = -zi; dbr = -1.0; }
+                const double nr = ar[s] - fma(lr, bcr, -li * bci), ni = ai[s] - fma(lr, bci, li * bcr);
+                const double ndr = dr[s] - fma(dlr, bcr, -dli * bci) - lr * dbr;
+                const double ndi = di[s] - fma(dlr, bci, dli * bcr) - li * dbr;
+                ar[s] = nr; ai[s] = ni; dr[s] = ndr; di[s] = ndi;
+            }
         } else {
-            const cplx s0 = {slot_val(rr, ia), slot_val(ri, ia)};
-            // [[T(ia,ia)-lam, T(ia,i)], [T(i,ia), T(i,i)-lam]] [x_ia; x_i] = [s0; s1]
-            const cplx a11 = {T(ia, ia) - lre, -lim}, a12 = {T(ia, i), 0.0};
-            const cplx a21 = {T(i, ia), 0.0}, a22 = {T(i, i) - lre, -lim};
-            cplx det = csub(cmul(a11, a22), cmul(a12, a21));
-            if (fabs(det.re) + fabs(det.im) < smin * smin) det = {smin * smin, 0.0};
-            x0 = cdiv(csub(cmul(s0, a22), cmul(a12, s1)), det);
-            x1 = cdiv(csub(cmul(a11, s1), cmul(a21, s0)), det);
-        }
-        // guard against overflow: rescale x and r when the new entries grow large
-        const double big = fmax(fabs(x1.re) + fabs(x1.im), fabs(x0.re) + fabs(x0.im));
-        const double sc = big > 1e100 ? 1e-100 : 1.0;
-        x1.re *= sc; x1.im *= sc; x0.re *= sc; x0.im *= sc;
+            // pivot on the active row: a <- b - l a, l = b_k / a_k, p'/p += a'_k / a_k
+            const double m2 = fma(akr, akr, aki * aki);
+            if (m2 == 0.0) { sing = true; break; }
+            const double im2 = 1.0 / m2;
+            const double ir = akr * im2, ii = -aki * im2;                   // 1 / a_k
+            sr += fma(dkr, ir, -dki * ii);
+            si += fma(dkr, ii, dki * ir);
+            const double lr = bk * ir, li = bk * ii;
+            const double tr = fma(lr, dkr, -li * dki), ti = fma(lr, dki, li * dkr);   // l a'_k
+            const double dlr = -fma(tr, ir, -ti * ii), dli = -fma(tr, ii, ti * ir);  // l' = -l a'_k / a_k
 #pragma unroll
-        for (int s = 0; s < EV_SLOTS; ++s) {
-            const int row = lane + 64 * s;
-            rr[s] *= sc; ri[s] *= sc; xr[s] *= sc; xi[s] *= sc;
-            if (row == i) { xr[s] = x1.re; xi[s] = x1.im; }
-            if (two && row == ia) { xr[s] = x0.re; xi[s] = x0.im; }
-            if (row < ia) {
-                const double t1 = T(row, i);
-                rr[s] -= t1 * x1.re; ri[s] -= t1 * x1.im;
-                if (two) { const double t0 = T(row, ia); rr[s] -= t0 * x0.re; ri[s] -= t0 * x0.im; }
+            for (int s = 0; s < AB_SLOTS; ++s) {
+                const int c = lane + 64 * s;
+                if (c <= k || c >= n) continue;
+                double bcr = cur.v[s], bci = 0.0, dbr = 0.0;
+                if (c == k + 1) { bcr -= zr; bci = -zi; dbr = -1.0; }
+                const double xr = ar[s], xi = ai[s], yr = dr[s], yi = di[s];
+                ar[s] = bcr - fma(lr, xr, -li * xi);
+                ai[s] = bci - fma(lr, xi, li * xr);
+                dr[s] = dbr - fma(dlr, xr, -dli * xi) - fma(lr, yr, -li * yi);
+                di[s] = -fma(dlr, xi, dli * xr) - fma(lr, yi, li * yr);
             }
         }
-        i = ia - 1;
     }
-    // normalise (complex 2-norm) and stage x for the product with Z
+    if (!sing) {
+        const int ks = (n - 1) >> 6, kl = (n - 1) & 63;
+        const double akr = bcast(ar[ks], kl), aki = bcast(ai[ks], kl);
+        const double dkr = bcast(dr[ks], kl), dki = bcast(di[ks], kl);
+        const double m2 = fma(akr, akr, aki * aki);
+        if (m2 == 0.0) {
+            sing = true;
+        } else {
+            const double ir = akr / m2, ii = -aki / m2;
+            sr += fma(dkr, ir, -dki * ii);
+            si += fma(dkr, ii, dki * ir);
+        }
+    }
+    *sr_out = sr;
+    *si_out = si;
+    return !sing;
+}
+
+__device__ __forceinline__ int wave_sum_i(int v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, DMD_WAVE);
+    return v;
+}
+
+__global__ void __launch_bounds__(64)
+aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv, uint32_t* counter,
+              double* zfin, int32_t* info, double tol, int max_it)
+{
+    const int i = blockIdx.x, lane = threadIdx.x;
+    const double tr = Hr[(int64_t)n * n], f2 = Hr[(int64_t)n * n + 1];
+    const double cr = tr / n;
+    const double hscale = sqrt(f2 / n);
+    const double rho = sqrt(fmax(f2 / n - cr * cr, 1e-30 * (f2 / n) + 1e-300));
+    double zr, zi;
+    ab_start(i, n, cr, rho, &zr, &zi);
+    bool done = false, timeout = false;
+    double wp = __builtin_inf();
+    int it = 0;
+    for (;; ++it) {
+        const double* zc = zbuf + (size_t)(it & 1) * 2 * n;     // iterate it (it >= 1)
+        if (!done) {
+            double sr = 0.0, si = 0.0;
+            const bool ok = ab_logdet_deriv(Hr, n, lane, zr, zi, &sr, &si);
+            // sum over j != i of 1 / (z_i - z_j), fixed-order
+            double qr = 0.0, qi = 0.0;
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) {
+                const int j = lane + 64 * s;
+                if (j >= n || j == i) continue;
+                double zjr, zji;
+                if (it == 0) {
+                    ab_start(j, n, cr, rho, &zjr, &zji);
+                } else {
+                    zjr = __hip_atomic_load(zc + 2 * j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    zji = __hip_atomic_load(zc + 2 * j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                const double ddr = zr - zjr, ddi = zi - zji;
+                const double m = fma(ddr, ddr, ddi * ddi);
+                if (m > 0.0) { qr += ddr / m; qi -= ddi / m; }
+            }
+            qr = wave_sum(qr);
+            qi = wave_sum(qi);
+            double wr = 0.0, wi = 0.0;
+            if (ok) {
+                const double er = sr - qr, ei = si - qi;
+                const double m = fma(er, er, ei * ei);
+                if (m > 0.0 && m < __builtin_inf()) { wr = er / m; wi = -ei / m; }
+            }
+            zr -= wr;
+            zi -= wi;
+            const double aw = hypot(wr, wi), az = hypot(zr, zi) + 1e-6 * hscale;
+            if (!ok || aw <= tol * az || (aw <= 1e-9 * az && aw > 0.25 * wp)) done = true;
+            wp = aw;
+        }
+        // publish iterate it + 1 and its converged flag (both double-buffered: a work-group
+        // that is already one iteration ahead writes the other copy), then wait for every
+        // work-group to have done the same
+        double* zn = zbuf + (size_t)((it + 1) & 1) * 2 * n;
+        int32_t* cn = conv + (size_t)((it + 1) & 1) * n;
+        if (lane == 0) {
+            __hip_atomic_store(zn + 2 * i, zr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(zn + 2 * i + 1, zi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(cn + i, done ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t target = (uint32_t)(it + 1) * (uint32_t)n;
+            uint32_t polls = 0;
+            while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                __builtin_amdgcn_s_sleep(2);
+                if (++polls > AB_SPIN_CAP) { timeout = true; break; }
+            }
+        }
+        timeout = __shfl(timeout ? 1 : 0, 0, 64) != 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (timeout) break;
+        int nc = 0;
+#pragma unroll
+        for (int s = 0; s < AB_SLOTS; ++s) {
+            const int j = lane + 64 * s;
+            if (j < n) nc += __hip_atomic_load(cn + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        nc = wave_sum_i(nc);
+        if (nc == n || it + 1 >= max_it) break;
+    }
+    if (lane == 0) {
+        zfin[2 * i] = zr;
+        zfin[2 * i + 1] = zi;
+        if (timeout || (!done && wp > 1e-6 * (hypot(zr, zi) + 1e-6 * hscale))) set_status(info, DMD_ERR_EIG_NOCONV);
+        if (i == 0 && info) info[2] = it + 1;
+    }
+}
+
+// ====================================================================== 2b. pairs
+// A real matrix has real eigenvalues and conjugate pairs; the independent approximations
+// carry rounding-level imaginary parts and asymmetries.  An approximation is real when
+// |Im z| <= tau (|z| + 1e-6 ||H||_F / sqrt(n)), tau = 1e-12, raised tenfold until as
+// many approximations lie above the real axis as below it; each upper one is paired with
+// the lower one nearest to its conjugate (mutually nearest, else in index order), and a
+// pair becomes (z_i + conj(z_j)) / 2 and its conjugate.  Output positions follow the index
+// of the real root or of the upper member (a pair takes two adjacent positions).
+constexpr int EP_THREADS = 256;
+static_assert(EIG_MAX <= EP_THREADS, "eig_pair_kernel: one thread per approximation");
+
+__global__ void __launch_bounds__(EP_THREADS)
+eig_pair_kernel(int n, const double* __restrict__ zfin, const double* __restrict__ Hr, double* wr, double* wi,
+                int32_t* kind0, int32_t* info)
+{
+    __shared__ double zs[2 * EIG_MAX];
+    __shared__ int cls[EIG_MAX];
+    __shared__ int mate[EIG_MAX], back[EIG_MAX];
+    __shared__ int cnt[2], ok;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < 2 * n; e += EP_THREADS) zs[e] = zfin[e];
+    const double hscale = sqrt(Hr[(int64_t)n * n + 1] / n);
+    __syncthreads();
+    double tau = 1e-12;
+    for (int t = 0; t < 9; ++t) {
+        if (tid < 2) cnt[tid] = 0;
+        __syncthreads();
+        if (tid < n) {
+            const double re = zs[2 * tid], im = zs[2 * tid + 1];
+            const int c = fabs(im) <= tau * (hypot(re, im) + 1e-6 * hscale) ? 0 : (im > 0.0 ? 1 : -1);
+            cls[tid] = c;
+            if (c != 0) atomicAdd(&cnt[c > 0 ? 0 : 1], 1);
+        }
+        __syncthreads();
+        const bool even = cnt[0] == cnt[1];
+        __syncthreads();
+        if (even) break;
+        tau *= 10.0;
+    }
+    if (cnt[0] != cnt[1]) {
+        if (tid == 0) set_status(info, DMD_ERR_EIG_NOCONV);
+        return;
+    }
+    // nearest partner of every upper root among the lower ones, and back
+    if (tid < n) {
+        mate[tid] = -1;
+        back[tid] = -1;
+        const int c = cls[tid];
+        if (c != 0) {
+            const double re = zs[2 * tid], im = -zs[2 * tid + 1];     // conjugate
+            double best = __builtin_inf();
+            int bj = -1;
+            for (int j = 0; j < n; ++j) {
+                if (cls[j] != -c) continue;
+                const double dr = zs[2 * j] - re, di = zs[2 * j + 1] - im;
+                const double d = fma(dr, dr, di * di);
+                if (d < best) { best = d; bj = j; }
+            }
+            if (c > 0) mate[tid] = bj; else back[tid] = bj;
+        }
+    }
+    if (tid == 0) ok = 1;
+    __syncthreads();
+    if (tid < n && cls[tid] > 0 && back[mate[tid]] != tid) ok = 0;
+    __syncthreads();
+    if (tid == 0) {
+        if (!ok) {
+            // greedy in index order over the upper roots
+            for (int j = 0; j < n; ++j) back[j] = 0;
+            for (int u = 0; u < n; ++u) {
+                if (cls[u] <= 0) continue;
+                const double re = zs[2 * u], im = -zs[2 * u + 1];
+                double best = __builtin_inf();
+                int bj = -1;
+                for (int j = 0; j < n; ++j) {
+                    if (cls[j] >= 0 || back[j]) continue;
+                    const double dr = zs[2 * j] - re, di = zs[2 * j + 1] - im;
+                    const double d = fma(dr, dr, di * di);
+                    if (d < best) { best = d; bj = j; }
+                }
+                mate[u] = bj;
+                back[bj] = 1;
+            }
+        }
+        int p = 0;
+        for (int u = 0; u < n; ++u) {
+            if (cls[u] == 0) {
+                wr[p] = zs[2 * u]; wi[p] = 0.0; kind0[p] = 0;
+                ++p;
+            } else if (cls[u] > 0) {
+                const int j = mate[u];
+                const double re = 0.5 * (zs[2 * u] + zs[2 * j]);
+                const double im = 0.5 * (zs[2 * u + 1] - zs[2 * j + 1]);
+                wr[p] = re; wi[p] = im; kind0[p] = 1;
+                wr[p + 1] = re; wi[p + 1] = -im; kind0[p + 1] = 2;
+                p += 2;
+            }
+        }
+    }
+}
+
+// ====================================================================== 2c. eigenvectors
+// Inverse iteration on the Hessenberg matrix, one single-wave work-group per real
+// eigenvalue or pair: the LU factorisation of H - lambda I with partial pivoting (as in
+// the eigenvalue iteration, pivots below eps ||H||_F raised to that value) writes the
+// rows of U to the workspace; x = U^-1 (1, .., 1)^T by back-substitution (one dot product
+// per row, rescaled when it grows past 1e100) is the eigenvector of H, normalised to unit
+// 2-norm; the Hessenberg reflectors (A = Q H Q^T) then give the eigenvector Q x of A.
+// A pair stores [Re, Im] in its two columns.
+__global__ void __launch_bounds__(64)
+invit_kernel(int n, const double* __restrict__ Hr, const double* __restrict__ Vg, const double* __restrict__ taug,
+             const double* __restrict__ wr, const double* __restrict__ wi, const int32_t* __restrict__ kind0,
+             double* Us, double* Wraw)
+{
+    const int p = blockIdx.x, lane = threadIdx.x;
+    const int kd = kind0[p];
+    if (kd == 2) return;
+    const bool pair = kd == 1;
+    const double lr = wr[p], li = pair ? wi[p] : 0.0;
+    const double eps3 = 2.220446049250313e-16 * sqrt(Hr[(int64_t)n * n + 1]) + 1e-300;
+    const int64_t npk = (int64_t)n * (n + 1) / 2;
+    double* U = Us + (size_t)p * 2 * npk;                         // packed rows, complex
+    auto rowoff = [&](int k) -> int64_t { return (int64_t)k * n - (int64_t)k * (k - 1) / 2; };
+    dvec4 ar, ai;
+#pragma unroll
+    for (int s = 0; s < AB_SLOTS; ++s) {
+        const int c = lane + 64 * s;
+        ar[s] = c < n ? Hr[c] : 0.0;
+        ai[s] = 0.0;
+        if (c == 0) { ar[s] -= lr; ai[s] = -li; }
+    }
+    AbRow nxt = ab_load_row(Hr, n, 0, lane);
+    for (int k = 0; k + 1 < n; ++k) {
+        const AbRow cur = nxt;
+        if (k + 2 < n) nxt = ab_load_row(Hr, n, k + 1, lane);
+        const int ks = k >> 6, kl = k & 63;
+        const double akr = bcast(ar[ks], kl), aki = bcast(ai[ks], kl);
+        const double bk = cur.sub;
+        double* Urow = U + 2 * rowoff(k);
+        if (fabs(bk) > fabs(akr) + fabs(aki)) {
+            const double piv = fabs(bk) < eps3 ? (bk < 0.0 ? -eps3 : eps3) : bk;
+            const double ib = 1.0 / piv;
+            const double l_r = akr * ib, l_i = aki * ib;
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) {
+                const int c = lane + 64 * s;
+                if (c < k || c >= n) continue;
+                double bcr = c == k ? piv : cur.v[s], bci = 0.0;
+                if (c == k + 1) { bcr -= lr; bci = -li; }
+                Urow[2 * (c - k)] = bcr;
+                Urow[2 * (c - k) + 1] = bci;
+                if (c == k) continue;
+                const double nr = ar[s] - fma(l_r, bcr, -l_i * bci), ni = ai[s] - fma(l_r, bci, l_i * bcr);
+                ar[s] = nr; ai[s] = ni;
+            }
+        } else {
+            double pr = akr, pi = aki;
+            if (fabs(pr) + fabs(pi) < eps3) { pr = eps3; pi = 0.0; }
+            const double m2 = fma(pr, pr, pi * pi);
+            const double ir = pr / m2, ii = -pi / m2;
+            const double l_r = bk * ir, l_i = bk * ii;
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) {
+                const int c = lane + 64 * s;
+                if (c < k || c >= n) continue;
+                const double xr = c == k ? pr : ar[s], xi = c == k ? pi : ai[s];
+                Urow[2 * (c - k)] = xr;
+                Urow[2 * (c - k) + 1] = xi;
+                if (c == k) continue;
+                double bcr = cur.v[s], bci = 0.0;
+                if (c == k + 1) { bcr -= lr; bci = -li; }
+                ar[s] = bcr - fma(l_r, xr, -l_i * xi);
+                ai[s] = bci - fma(l_r, xi, l_i * xr);
+            }
+        }
+    }
+    {
+        const int k = n - 1, ks = k >> 6, kl = k & 63;
+        double pr = bcast(ar[ks], kl), pi = bcast(ai[ks], kl);
+        if (fabs(pr) + fabs(pi) < eps3) { pr = eps3; pi = 0.0; }
+        if (lane == kl) { U[2 * rowoff(k)] = pr; U[2 * rowoff(k) + 1] = pi; }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");    // the rows of U are read back below
+    // back-substitution U x = rs (1, .., 1)^T, rows from the last; row k - 1 loaded while
+    // row k is solved
+    dvec4 xr, xi;
+#pragma unroll
+    for (int s = 0; s < AB_SLOTS; ++s) { xr[s] = 0.0; xi[s] = 0.0; }
+    double rs = 1.0;
+    auto load_u = [&](int k, dvec4& vr, dvec4& vi) {
+        const double* Urow = U + 2 * rowoff(k);
+#pragma unroll
+        for (int s = 0; s < AB_SLOTS; ++s) {
+            const int c = lane + 64 * s;
+            const bool in = c >= k && c < n;
+            vr[s] = in ? Urow[2 * (c - k)] : 0.0;
+            vi[s] = in ? Urow[2 * (c - k) + 1] : 0.0;
+        }
+    };
+    dvec4 nur, nui;
+    load_u(n - 1, nur, nui);
+    for (int k = n - 1; k >= 0; --k) {
+        const dvec4 ur = nur, ui = nui;
+        if (k > 0) load_u(k - 1, nur, nui);
+        const int ks = k >> 6, kl = k & 63;
+        double tr = 0.0, ti = 0.0;
+#pragma unroll
+        for (int s = 0; s < AB_SLOTS; ++s) {
+            const int c = lane + 64 * s;
+            if (c <= k) continue;
+            tr += fma(ur[s], xr[s], -ui[s] * xi[s]);
+            ti += fma(ur[s], xi[s], ui[s] * xr[s]);
+        }
+        tr = wave_sum(tr);
+        ti = wave_sum(ti);
+        const double dr = bcast(ur[ks], kl), di = bcast(ui[ks], kl);
+        const double nr = rs - tr, ni = -ti;
+        const double m2 = fma(dr, dr, di * di);
+        double vr = fma(nr, dr, ni * di) / m2, vi = fma(ni, dr, -nr * di) / m2;
+        if (fabs(vr) + fabs(vi) > 1e100) {
+            xr *= 1e-100; xi *= 1e-100; rs *= 1e-100;
+            vr *= 1e-100; vi *= 1e-100;
+        }
+#pragma unroll
+        for (int s = 0; s < AB_SLOTS; ++s)
+            if (s == ks && lane == kl) { xr[s] = vr; xi[s] = vi; }
+    }
+    // unit 2-norm
     double nn2 = 0.0;
 #pragma unroll
-    for (int s = 0; s < EV_SLOTS; ++s) nn2 += xr[s] * xr[s] + xi[s] * xi[s];
+    for (int s = 0; s < AB_SLOTS; ++s) nn2 = fma(xr[s], xr[s], fma(xi[s], xi[s], nn2));
     nn2 = wave_sum(nn2);
     const double inv = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 0.0;
+    xr *= inv;
+    xi *= inv;
+    // y = Q x with Q = P_0 P_1 .. P_{n-3}: P_k = I - tau_k v_k v_k^T (v_k rows k+1.., v_{k+1} = 1)
+    auto load_v = [&](int k, dvec4& v) {
 #pragma unroll
-    for (int s = 0; s < EV_SLOTS; ++s) {
-        const int row = lane + 64 * s;
-        if (row < n) { xs[row] = xr[s] * inv; xs[n + row] = xi[s] * inv; }
-    }
-    __syncthreads();
-    // W[:, k] = Z Re(x) (and W[:, k+1] = Z Im(x) for a pair); Z is column-major.  Columns
-    // of Z are taken eight at a time, every row slot's entries loaded before the FMAs (each
-    // sum still runs over j in ascending order)
-    double wre[EV_SLOTS], wim[EV_SLOTS];
-#pragma unroll
-    for (int s = 0; s < EV_SLOTS; ++s) { wre[s] = 0.0; wim[s] = 0.0; }
-    int j = 0;
-    for (; j + 7 <= top; j += 8) {
-        double z[8][EV_SLOTS];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-            for (int s = 0; s < EV_SLOTS; ++s) {
-                const int row = lane + 64 * s;
-                z[u][s] = row < n ? Zg[(int64_t)(j + u) * n + row] : 0.0;
-            }
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double xre = xs[j + u], xim = xs[n + j + u];
-#pragma unroll
-            for (int s = 0; s < EV_SLOTS; ++s) { wre[s] += z[u][s] * xre; wim[s] += z[u][s] * xim; }
+        for (int s = 0; s < AB_SLOTS; ++s) {
+            const int c = lane + 64 * s;
+            v[s] = (c > k && c < n) ? Vg[(int64_t)k * n + c] : 0.0;
         }
-    }
-    for (; j <= top; ++j) {
-        const double xre = xs[j], xim = xs[n + j];
+    };
+    if (n > 2) {
+        dvec4 nv;
+        load_v(n - 3, nv);
+        for (int k = n - 3; k >= 0; --k) {
+            const dvec4 v = nv;
+            if (k > 0) load_v(k - 1, nv);
+            const double t = taug[k];
+            double gr = 0.0, gi = 0.0;
 #pragma unroll
-        for (int s = 0; s < EV_SLOTS; ++s) {
-            const int row = lane + 64 * s;
-            const double z = row < n ? Zg[(int64_t)j * n + row] : 0.0;
-            wre[s] += z * xre;
-            wim[s] += z * xim;
+            for (int s = 0; s < AB_SLOTS; ++s) { gr = fma(v[s], xr[s], gr); gi = fma(v[s], xi[s], gi); }
+            gr = wave_sum(gr) * t;
+            gi = wave_sum(gi) * t;
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) { xr[s] = fma(-gr, v[s], xr[s]); xi[s] = fma(-gi, v[s], xi[s]); }
         }
     }
 #pragma unroll
-    for (int s = 0; s < EV_SLOTS; ++s) {
+    for (int s = 0; s < AB_SLOTS; ++s) {
         const int row = lane + 64 * s;
         if (row >= n) continue;
-        Wraw[(int64_t)k * n + row] = wre[s];
-        if (pair) Wraw[(int64_t)(k + 1) * n + row] = wim[s];
+        Wraw[(int64_t)p * n + row] = xr[s];
+        if (pair) Wraw[(int64_t)(p + 1) * n + row] = xi[s];
     }
 }
 
@@ -896,7 +831,7 @@ sort_modes_kernel(int n, const double* __restrict__ wr, const double* __restrict
 }
 
 hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* ws, double* lam,
-                      int32_t* kind, double* W, int32_t* info, double defl_tol)
+                      int32_t* kind, double* W, int32_t* info, double tol)
 {
     if (n <= 0) return hipSuccess;
     if (n > EIG_MAX) return hipErrorInvalidValue;
@@ -904,35 +839,20 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
     hipLaunchKernelGGL(hessenberg_kernel, dim3(1), dim3(1024), 0, s, A, lda, n, w.H, w.V, w.tau);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int nr = eig_rows_per_wg(n);
-    const int grid = eig_grid(n);
-    const int hsize = hp_col(n, n);
-    const int nw = FR_THREADS / 64;
-    // blk ints, packed H, the Z slab, then the staged reflectors (FR_VCH columns and their tau)
-    const size_t lds = (size_t)(round_up(n, 2) / 2) * 8 + (size_t)hsize * 8 + (size_t)nr * n * 8 +
-                       (size_t)FR_VCH * (n + 1) * 8;
-    if (lds > 160 * 1024 - 512) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(francis_kernel, dim3(grid), dim3(64 * nw), lds, s, n, nr, w.H, w.V, w.tau, w.Z, w.T,
-                       w.blk, w.wr, w.wi, w.kind0, info, defl_tol);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t evlds = ((size_t)round_up(hsize, 2) + 2 * (size_t)n) * 8 + (size_t)n * 4;
-    hipLaunchKernelGGL(eigvec_kernel, dim3(n), dim3(64), evlds, s, n, w.T, w.blk, w.Z, w.Wraw, defl_tol);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if ((e = fill_i32(s, (int32_t*)w.counter, 1, 0)) != hipSuccess) return e;
+    hipLaunchKernelGGL(aberth_kernel, dim3(n), dim3(64), 0, s, n, w.H, w.zbuf, w.conv, w.counter, w.zfin, info,
+                       fmax(tol, 4e-16), AB_MAX_IT);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(eig_pair_kernel, dim3(1), dim3(EP_THREADS), 0, s, n, w.zfin, w.H, w.wr, w.wi, w.kind0, info);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(invit_kernel, dim3(n), dim3(64), 0, s, n, w.H, w.V, w.tau, w.wr, w.wi, w.kind0, w.Us, w.Wraw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(sort_modes_kernel, dim3(1), dim3(SM_THREADS), (size_t)n * (2 * sizeof(double) + 2 * sizeof(int)),
                        s, n, w.wr, w.wi, w.kind0, w.Wraw, lam, kind, W);
     return hipGetLastError();
 }
 
-hipError_t eig_prepare()
-{
-    hipError_t e = hipFuncSetAttribute((const void*)eigvec_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024 - 256);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)francis_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
-}
-
+hipError_t eig_prepare() { return hipSuccess; }
 hipError_t prepare_kernels()
 {
     hipError_t e = gemm_prepare();

@@ -101,11 +101,11 @@ hipError_t check_finite(hipStream_t s, int dtype, const void* X, int64_t ld, int
 // ---- nonsymmetric eigen-decomposition (eig.hip)
 size_t eig_workspace_bytes(int n);
 // lam (2n doubles), kind (n), W (n x n folded real eigenvectors, ld n) sorted in
-// the canonical order; M = Vs W (m x n) where Vs = V_r S_r^-1 (m x n, ld ldv).
-// defl_tol: relative size below which a sub-diagonal entry of the Hessenberg form is
-// treated as zero (machine epsilon for full FP64 accuracy).
+// the canonical order.  tol: an eigenvalue approximation is converged once its
+// correction falls below tol relative to its size (at least 4e-16).  info[2] receives
+// the number of eigenvalue iterations.
 hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* ws, double* lam,
-                      int32_t* kind, double* W, int32_t* info, double defl_tol);
+                      int32_t* kind, double* W, int32_t* info, double tol);
 
 // ---- temporal editing (edit.hip)
 // lam_out / b_out may alias lam / b; mode_edit (r x 4, row-major) overrides the cluster
