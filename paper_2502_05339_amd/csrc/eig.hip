@@ -4,14 +4,15 @@
 //  1. hessenberg_kernel (1 work-group): Householder reduction A = Q H Q^T, H in
 //     registers across the work-group, the reflectors (v_k, tau_k) kept for
 //     rebuilding Q; H is written row-major with its trace and squared Frobenius norm.
-//  2. aberth_kernel (n single-wave work-groups): the eigenvalues as the roots of
-//     det(zI - H), all refined at once by the Ehrlich-Aberth iteration, each Newton
-//     ratio from a pivoted LU factorisation of H - zI differentiated in z.
+//  2. aberth_kernel (one wave per eigenvalue, four per work-group sharing H in LDS):
+//     the eigenvalues as the roots of det(zI - H), all refined at once by the
+//     Ehrlich-Aberth iteration, each Newton ratio from Hyman's method (the determinant of
+//     a Hessenberg matrix by back-substitution on its sub-diagonal) differentiated in z.
 //  2b. eig_pair_kernel (1 work-group): real eigenvalues and conjugate pairs told apart
 //     and made exact (real, or exactly conjugate).
-//  2c. invit_kernel (one single-wave work-group per real eigenvalue or pair): the
-//     eigenvector by inverse iteration on H, taken through Q, normalised to unit 2-norm
-//     (folded: [Re, Im] for a conjugate pair).
+//  2c. invit_kernel (one wave per real eigenvalue or pair, up to four per work-group
+//     sharing H in LDS): the eigenvector by inverse iteration on H, taken through Q,
+//     normalised to unit 2-norm (folded: [Re, Im] for a conjugate pair).
 //  3. sort_modes_kernel (1 work-group): canonical order (ascending |arg lambda|,
 //     ties by descending |lambda|, Im > 0 member of a pair first), lambda, kind
 //     and the permuted folded eigenvectors (pair -> [Re w, Im w], LAPACK storage).
@@ -30,18 +31,15 @@ struct EigWs {
     double* wi;       // n
     double* zbuf;     // 2 x 2n: two iterates of the eigenvalue approximations (re, im)
     double* zfin;     // 2n: converged approximations
-    double* Us;       // per output position, the packed rows of U (complex): n * n(n+1)/2 * 2
     int32_t* kind0;   // n
     int32_t* conv;    // 2 x n: converged flags of the two iterates
     uint32_t* counter;
 };
 
-static size_t eig_upk(int n) { return (size_t)n * (n + 1) / 2; }
-
 size_t eig_workspace_bytes(int n)
 {
     const size_t nn = (size_t)n * n;
-    const size_t dbl = (nn + 2) + nn + n + nn + 2 * (size_t)n + 4 * (size_t)n + 2 * (size_t)n + (size_t)n * 2 * eig_upk(n);
+    const size_t dbl = (nn + 2) + nn + n + nn + 2 * (size_t)n + 4 * (size_t)n + 2 * (size_t)n;
     return dbl * sizeof(double) + 3 * (size_t)round_up((int64_t)n * sizeof(int32_t), 64) + 64 + 256;
 }
 
@@ -58,7 +56,6 @@ static EigWs eig_carve(void* ws, int n)
     w.wi = p; p += n;
     w.zbuf = p; p += 4 * (size_t)n;
     w.zfin = p; p += 2 * (size_t)n;
-    w.Us = p; p += (size_t)n * 2 * eig_upk(n);
     char* q = (char*)p;
     w.kind0 = (int32_t*)q; q += round_up((int64_t)n * sizeof(int32_t), 64);
     w.conv = (int32_t*)q; q += 2 * round_up((int64_t)n * sizeof(int32_t), 64);
@@ -248,29 +245,25 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
 
 // ====================================================================== 2. eigenvalues
 // Ehrlich-Aberth iteration on p(z) = det(zI - H), all n approximations at once:
-//   z_i <- z_i - 1 / (p'(z_i)/p(z_i) - sum_{j != i} 1 / (z_i - z_j)).
-// p'/p(z) = d/dz log det(H - zI) = sum_k u'_kk / u_kk over the pivots of the LU
-// factorisation of H - zI with partial pivoting, differentiated in z alongside.  A
-// Hessenberg matrix has one candidate row below each pivot, so the elimination carries a
-// single active row (and its derivative) and reads row k + 1 of H at step k.
-// One single-wave work-group per approximation, lanes over the columns of the active row.
+//   z_i <- z_i - 1 / (p'(z_i)/p(z_i) - sum_{j != i} 1 / (z_i - z_j)),
+// with p'/p from Hyman's method (ab_logdet_deriv below).  Each wave refines one
+// approximation, lanes over the rows; the four waves of a work-group share one copy of H
+// in LDS (column-packed, scaled by the power of two that brings ||H||_F near 1).
 // Iterations are separated by a grid-wide barrier (a counter in the workspace), so every
 // approximation is updated from the same previous iterate and the result does not depend
-// on scheduling.  The barrier's wait is bounded: a work-group that waits past the bound
-// reports DMD_ERR_EIG_NOCONV and leaves, which ends the other work-groups' waits too.
+// on scheduling.  The barrier's wait is bounded: a wave that waits past the bound reports
+// DMD_ERR_EIG_NOCONV and leaves, which ends the other waves' waits too.
 // Start: n points on the circle about trace(H)/n whose radius is the spread
 // (||H||_F^2 / n - |trace(H)/n|^2)^(1/2) that bounds the eigenvalues' deviation from their
 // mean (Schur's inequality).  A root is converged when its correction falls below tol
 // relative to |z| (the next correction of a simple root is of the cube of that size), or
 // below 1e-9 |z| without shrinking by a factor 4 any more (the rounding floor of the
 // evaluation, reached by clustered roots).
-constexpr int AB_SLOTS = (EIG_MAX + 63) / 64;
-static_assert(AB_SLOTS <= 4, "aberth_kernel keeps at most 4 columns per lane");
-// columns of one lane, as one vector value: a run-time element index on a vector stays in
-// registers, where the same index on a private array would put it in scratch
-typedef double dvec4 __attribute__((ext_vector_type(4)));
+constexpr int AB_SLOTS = 3;                 // columns (rows) per lane: n <= 192
+static_assert(EIG_MAX <= 64 * AB_SLOTS, "aberth_kernel keeps at most 3 columns per lane");
 constexpr int AB_MAX_IT = 200;
 constexpr uint32_t AB_SPIN_CAP = 1u << 22;
+constexpr int AB_WAVES = 4;                 // approximations (waves) per work-group
 
 __device__ __forceinline__ double bcast(double v, int src)
 {
@@ -279,7 +272,14 @@ __device__ __forceinline__ double bcast(double v, int src)
     return __hiloint2double(hi, lo);
 }
 
-// Start point j of the iteration (the same formula on every work-group).
+// Column-packed Hessenberg: column c holds rows 0 .. min(c + 1, n - 1).
+__host__ __device__ __forceinline__ int hcol_off(int c) { return (c * (c + 3)) / 2; }
+__host__ __device__ __forceinline__ int hcol_size(int n) { return n <= 1 ? n : hcol_off(n - 1) + n; }
+// Packed reflectors: column k (k <= n - 3) holds v_k on rows k + 1 .. n - 1.
+__host__ __device__ __forceinline__ int vcol_off(int k, int n) { return k * (n - 1) - (k * (k - 1)) / 2; }
+__host__ __device__ __forceinline__ int vcol_size(int n) { return n < 3 ? 0 : vcol_off(n - 2, n); }
+
+// Start point j of the iteration (the same formula on every wave).
 __device__ __forceinline__ void ab_start(int j, int n, double cr, double rho, double* zr, double* zi)
 {
     double s, c;
@@ -288,107 +288,120 @@ __device__ __forceinline__ void ab_start(int j, int n, double cr, double rho, do
     *zi = rho * s;
 }
 
-// Row k + 1 of H for the lane's columns c > k (zero elsewhere), and the sub-diagonal
-// entry H(k + 1, k): the operands of elimination step k.
-struct AbRow {
-    dvec4 v;
-    double sub;
-};
-__device__ __forceinline__ AbRow ab_load_row(const double* __restrict__ Hr, int n, int k, int lane)
+// 1/a for complex a: conj(a) / |a|^2 with the hardware reciprocal refined by two Newton
+// steps (a few ulp); a = 0 gives a non-finite result.
+__device__ __forceinline__ void crcp(double ar, double ai, double* rr, double* ri)
 {
-    AbRow r;
-    const double* row = Hr + (int64_t)(k + 1) * n;
-#pragma unroll
-    for (int s = 0; s < AB_SLOTS; ++s) {
-        const int c = lane + 64 * s;
-        r.v[s] = (c > k && c < n) ? row[c] : 0.0;
-    }
-    r.sub = row[k];
-    return r;
+    const double im2 = rcp_nr(fma(ar, ar, ai * ai));
+    *rr = ar * im2;
+    *ri = -ai * im2;
 }
 
-// p'/p at z for the row-major Hessenberg matrix Hr; false when H - zI has an exactly zero
-// pivot (z is an eigenvalue).  Row k + 2 is loaded while step k runs.
-__device__ bool ab_logdet_deriv(const double* __restrict__ Hr, int n, int lane, double zr, double zi,
+// p'/p(z) for p(z) = det(zI - H) by Hyman's method.  With x_{n-1} = 1, rows n-1 .. 1 of
+// (zI - H) x = 0 give x_{j-1} = r_j / h_{j,j-1}, where r_j = sum_{c >= j} (z d_jc - h_jc) x_c
+// is complete once x_j is known; row 0 is left with r_0, and det(zI - H) = r_0 times the
+// product of the sub-diagonal entries, which do not depend on z, so p'/p = r'_0 / r_0
+// (r' and x' carried along).  Column-oriented: each lane keeps r and r' of its rows and
+// adds column j times x_j to them; the only divisions are the precomputed reciprocals of
+// the sub-diagonal.  Sub-diagonal entries below eps ||H||_F have been raised to that size
+// (a backward-stable perturbation), and x, x', r, r' are rescaled every four steps once
+// |x| passes 1e100 (the ratio does not change).
+// Slot s of a lane holds row i = lane + 64 s.  In steps j with j >> 6 == JS the rows still
+// accumulating (i <= j) lie in slots 0 .. JS; the rows of those slots take the update
+// without a lane mask (column j is zero below row j + 1 in the packed layout, read as 0).
+struct HyState {
+    double rr[AB_SLOTS], ri[AB_SLOTS], pr[AB_SLOTS], pi[AB_SLOTS];   // r and r' of the rows
+    double hc[AB_SLOTS];                                             // column j of H
+    double xr, xi, xpr, xpi;                                         // x_j and x'_j
+};
+
+template <int JS>
+__device__ __forceinline__ void hy_load_col(const double* Hs, int j, int lane, double (&hc)[AB_SLOTS])
+{
+    const double* col = Hs + hcol_off(j);                          // rows 0 .. j + 1
+#pragma unroll
+    for (int s = 0; s <= JS; ++s) {
+        const int i = lane + 64 * s;
+        hc[s] = (s < JS || i <= j) ? col[i] : 0.0;
+    }
+}
+
+// steps j = j_hi down to j_lo (all with j >> 6 == JS, j_lo >= 1): add column j to the rows,
+// then x_{j-1} = r_j / h_{j,j-1}
+template <int JS>
+__device__ void hy_segment(const double* Hs, const double* inv_sub, int lane, double zr, double zi, int j_hi,
+                           int j_lo, HyState& st)
+{
+    for (int j = j_hi; j >= j_lo; --j) {
+        double hc[AB_SLOTS];
+#pragma unroll
+        for (int s = 0; s <= JS; ++s) hc[s] = st.hc[s];
+        if (j - 1 >= 0) {
+            if (((j - 1) >> 6) == JS) hy_load_col<JS>(Hs, j - 1, lane, st.hc);
+            else hy_load_col<(JS > 0 ? JS - 1 : 0)>(Hs, j - 1, lane, st.hc);
+        }
+        const double xr = st.xr, xi = st.xi, xpr = st.xpr, xpi = st.xpi;
+        // z x and x + z x' for the diagonal row j
+        const double zxr = fma(zr, xr, -zi * xi), zxi = fma(zr, xi, zi * xr);
+        const double zpr = xr + fma(zr, xpr, -zi * xpi), zpi = xi + fma(zr, xpi, zi * xpr);
+#pragma unroll
+        for (int s = 0; s <= JS; ++s) {
+            const int i = lane + 64 * s;
+            const bool dg = i == j;
+            st.rr[s] = fma(-hc[s], xr, st.rr[s]) + (dg ? zxr : 0.0);
+            st.ri[s] = fma(-hc[s], xi, st.ri[s]) + (dg ? zxi : 0.0);
+            st.pr[s] = fma(-hc[s], xpr, st.pr[s]) + (dg ? zpr : 0.0);
+            st.pi[s] = fma(-hc[s], xpi, st.pi[s]) + (dg ? zpi : 0.0);
+        }
+        const int jl = j & 63;
+        const double is = inv_sub[j];
+        st.xr = bcast(st.rr[JS], jl) * is;
+        st.xi = bcast(st.ri[JS], jl) * is;
+        st.xpr = bcast(st.pr[JS], jl) * is;
+        st.xpi = bcast(st.pi[JS], jl) * is;
+        if ((j & 3) == 0) {
+            const double f = fabs(st.xr) + fabs(st.xi) > 1e100 ? 1e-100 : 1.0;
+            st.xr *= f; st.xi *= f; st.xpr *= f; st.xpi *= f;
+#pragma unroll
+            for (int s = 0; s <= JS; ++s) { st.rr[s] *= f; st.ri[s] *= f; st.pr[s] *= f; st.pi[s] *= f; }
+        }
+    }
+}
+
+// p'/p at z for the column-packed Hessenberg matrix Hs in LDS (inv_sub[j] = 1 / h_{j,j-1});
+// false when the ratio is not finite (r_0 = 0: z is an eigenvalue to working precision).
+__device__ bool ab_logdet_deriv(const double* Hs, const double* inv_sub, int n, int lane, double zr, double zi,
                                 double* sr_out, double* si_out)
 {
-    dvec4 ar, ai, dr, di;
+    HyState st;
 #pragma unroll
-    for (int s = 0; s < AB_SLOTS; ++s) {
-        const int c = lane + 64 * s;
-        ar[s] = c < n ? Hr[c] : 0.0;
-        ai[s] = 0.0;
-        dr[s] = 0.0;
-        di[s] = 0.0;
-        if (c == 0) { ar[s] -= zr; ai[s] = -zi; dr[s] = -1.0; }
+    for (int s = 0; s < AB_SLOTS; ++s) { st.rr[s] = 0.0; st.ri[s] = 0.0; st.pr[s] = 0.0; st.pi[s] = 0.0; st.hc[s] = 0.0; }
+    st.xr = 1.0; st.xi = 0.0; st.xpr = 0.0; st.xpi = 0.0;
+    const int j0 = n - 1;
+    if ((j0 >> 6) == 2) hy_load_col<2>(Hs, j0, lane, st.hc);
+    else if ((j0 >> 6) == 1) hy_load_col<1>(Hs, j0, lane, st.hc);
+    else hy_load_col<0>(Hs, j0, lane, st.hc);
+    if (j0 >= 128) hy_segment<2>(Hs, inv_sub, lane, zr, zi, j0, 128, st);
+    if (j0 >= 64) hy_segment<1>(Hs, inv_sub, lane, zr, zi, min(j0, 127), 64, st);
+    if (j0 >= 1) hy_segment<0>(Hs, inv_sub, lane, zr, zi, min(j0, 63), 1, st);
+    // column 0 into row 0
+    {
+        const double hv = st.hc[0];
+        const bool l0 = lane == 0;
+        const double zxr = fma(zr, st.xr, -zi * st.xi), zxi = fma(zr, st.xi, zi * st.xr);
+        const double zpr = st.xr + fma(zr, st.xpr, -zi * st.xpi), zpi = st.xi + fma(zr, st.xpi, zi * st.xpr);
+        st.rr[0] = fma(-hv, st.xr, st.rr[0]) + (l0 ? zxr : 0.0);
+        st.ri[0] = fma(-hv, st.xi, st.ri[0]) + (l0 ? zxi : 0.0);
+        st.pr[0] = fma(-hv, st.xpr, st.pr[0]) + (l0 ? zpr : 0.0);
+        st.pi[0] = fma(-hv, st.xpi, st.pi[0]) + (l0 ? zpi : 0.0);
     }
-    double sr = 0.0, si = 0.0;
-    bool sing = false;
-    AbRow nxt = ab_load_row(Hr, n, 0, lane);
-    for (int k = 0; k + 1 < n; ++k) {
-        const AbRow cur = nxt;
-        if (k + 2 < n) nxt = ab_load_row(Hr, n, k + 1, lane);
-        const int ks = k >> 6, kl = k & 63;
-        const double akr = bcast(ar[ks], kl), aki = bcast(ai[ks], kl);
-        const double dkr = bcast(dr[ks], kl), dki = bcast(di[ks], kl);
-        const double bk = cur.sub;
-        if (fabs(bk) > fabs(akr) + fabs(aki)) {
-            // pivot on row k + 1 (real pivot, no z at column k): a <- a - l b, l = a_k / b_k
-            const double ib = 1.0 / bk;
-            const double lr = akr * ib, li = aki * ib;
-            const double dlr = dkr * ib, dli = dki * ib;
-#pragma unroll
-            for (int s = 0; s < AB_SLOTS; ++s) {
-                const int c = lane + 64 * s;
-                if (c <= k || c >= n) continue;
-                double bcr = cur.v[s], bci = 0.0, dbr = 0.0;
-                if (c == k + 1) { bcr -= zr; bci = -zi; dbr = -1.0; }
-                const double nr = ar[s] - fma(lr, bcr, -li * bci), ni = ai[s] - fma(lr, bci, li * bcr);
-                const double ndr = dr[s] - fma(dlr, bcr, -dli * bci) - lr * dbr;
-                const double ndi = di[s] - fma(dlr, bci, dli * bcr) - li * dbr;
-                ar[s] = nr; ai[s] = ni; dr[s] = ndr; di[s] = ndi;
-            }
-        } else {
-            // pivot on the active row: a <- b - l a, l = b_k / a_k, p'/p += a'_k / a_k
-            const double m2 = fma(akr, akr, aki * aki);
-            if (m2 == 0.0) { sing = true; break; }
-            const double im2 = 1.0 / m2;
-            const double ir = akr * im2, ii = -aki * im2;                   // 1 / a_k
-            sr += fma(dkr, ir, -dki * ii);
-            si += fma(dkr, ii, dki * ir);
-            const double lr = bk * ir, li = bk * ii;
-            const double tr = fma(lr, dkr, -li * dki), ti = fma(lr, dki, li * dkr);   // l a'_k
-            const double dlr = -fma(tr, ir, -ti * ii), dli = -fma(tr, ii, ti * ir);  // l' = -l a'_k / a_k
-#pragma unroll
-            for (int s = 0; s < AB_SLOTS; ++s) {
-                const int c = lane + 64 * s;
-                if (c <= k || c >= n) continue;
-                double bcr = cur.v[s], bci = 0.0, dbr = 0.0;
-                if (c == k + 1) { bcr -= zr; bci = -zi; dbr = -1.0; }
-                const double xr = ar[s], xi = ai[s], yr = dr[s], yi = di[s];
-                ar[s] = bcr - fma(lr, xr, -li * xi);
-                ai[s] = bci - fma(lr, xi, li * xr);
-                dr[s] = dbr - fma(dlr, xr, -dli * xi) - fma(lr, yr, -li * yi);
-                di[s] = -fma(dlr, xi, dli * xr) - fma(lr, yi, li * yr);
-            }
-        }
-    }
-    if (!sing) {
-        const int ks = (n - 1) >> 6, kl = (n - 1) & 63;
-        const double akr = bcast(ar[ks], kl), aki = bcast(ai[ks], kl);
-        const double dkr = bcast(dr[ks], kl), dki = bcast(di[ks], kl);
-        const double m2 = fma(akr, akr, aki * aki);
-        if (m2 == 0.0) {
-            sing = true;
-        } else {
-            const double ir = akr / m2, ii = -aki / m2;
-            sr += fma(dkr, ir, -dki * ii);
-            si += fma(dkr, ii, dki * ir);
-        }
-    }
-    *sr_out = sr;
-    *si_out = si;
-    return !sing;
+    const double r0r = bcast(st.rr[0], 0), r0i = bcast(st.ri[0], 0);
+    const double p0r = bcast(st.pr[0], 0), p0i = bcast(st.pi[0], 0);
+    double ir, ii;
+    crcp(r0r, r0i, &ir, &ii);
+    *sr_out = fma(p0r, ir, -p0i * ii);
+    *si_out = fma(p0r, ii, p0i * ir);
+    return isfinite(*sr_out) && isfinite(*si_out);
 }
 
 __device__ __forceinline__ int wave_sum_i(int v)
@@ -398,12 +411,33 @@ __device__ __forceinline__ int wave_sum_i(int v)
     return v;
 }
 
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64 * AB_WAVES)
 aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv, uint32_t* counter,
               double* zfin, int32_t* info, double tol, int max_it)
 {
-    const int i = blockIdx.x, lane = threadIdx.x;
-    const double tr = Hr[(int64_t)n * n], f2 = Hr[(int64_t)n * n + 1];
+    extern __shared__ __align__(16) double ab_sm[];
+    double* Hs = ab_sm;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int i = blockIdx.x * AB_WAVES + wave;
+    // H / 2^e into LDS, column-packed, with 2^e near ||H||_F (exact scaling: the eigenvalues
+    // scale by the same power of two), then the reciprocals of its sub-diagonal; row r is
+    // read whole (coalesced) and entry (r, c) stored at column c
+    const double f2raw = Hr[(int64_t)n * n + 1];
+    const double sc = f2raw > 0.0 ? ldexp(1.0, -ilogb(sqrt(f2raw))) : 1.0;
+    double* inv_sub = Hs + hcol_size(n);
+    const double floor_sub = 2.220446049250313e-16 * sqrt(f2raw) * sc;
+    for (int r = wave; r < n; r += AB_WAVES) {
+        const int c0 = r == 0 ? 0 : r - 1;
+        for (int c = c0 + lane; c < n; c += 64) {
+            const double v = Hr[(int64_t)r * n + c] * sc;
+            Hs[hcol_off(c) + r] = v;
+            if (c == r - 1) inv_sub[r] = 1.0 / (fabs(v) >= floor_sub ? v : (v < 0.0 ? -floor_sub : floor_sub));
+        }
+    }
+    __syncthreads();
+    if (i >= n) return;                     // no approximation for this wave (no barrier below)
+    const double tr = Hr[(int64_t)n * n] * sc, f2 = f2raw * sc * sc;
     const double cr = tr / n;
     const double hscale = sqrt(f2 / n);
     const double rho = sqrt(fmax(f2 / n - cr * cr, 1e-30 * (f2 / n) + 1e-300));
@@ -416,7 +450,7 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
         const double* zc = zbuf + (size_t)(it & 1) * 2 * n;     // iterate it (it >= 1)
         if (!done) {
             double sr = 0.0, si = 0.0;
-            const bool ok = ab_logdet_deriv(Hr, n, lane, zr, zi, &sr, &si);
+            const bool ok = ab_logdet_deriv(Hs, inv_sub, n, lane, zr, zi, &sr, &si);
             // sum over j != i of 1 / (z_i - z_j), fixed-order
             double qr = 0.0, qi = 0.0;
 #pragma unroll
@@ -431,8 +465,12 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
                     zji = __hip_atomic_load(zc + 2 * j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
                 const double ddr = zr - zjr, ddi = zi - zji;
-                const double m = fma(ddr, ddr, ddi * ddi);
-                if (m > 0.0) { qr += ddr / m; qi -= ddi / m; }
+                if (ddr != 0.0 || ddi != 0.0) {
+                    double tr_, ti_;
+                    crcp(ddr, ddi, &tr_, &ti_);
+                    qr += tr_;
+                    qi += ti_;
+                }
             }
             qr = wave_sum(qr);
             qi = wave_sum(qi);
@@ -448,9 +486,9 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
             if (!ok || aw <= tol * az || (aw <= 1e-9 * az && aw > 0.25 * wp)) done = true;
             wp = aw;
         }
-        // publish iterate it + 1 and its converged flag (both double-buffered: a work-group
-        // that is already one iteration ahead writes the other copy), then wait for every
-        // work-group to have done the same
+        // publish iterate it + 1 and its converged flag (both double-buffered: a wave that
+        // is already one iteration ahead writes the other copy), then wait for every wave
+        // to have done the same
         double* zn = zbuf + (size_t)((it + 1) & 1) * 2 * n;
         int32_t* cn = conv + (size_t)((it + 1) & 1) * n;
         if (lane == 0) {
@@ -461,7 +499,7 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
             const uint32_t target = (uint32_t)(it + 1) * (uint32_t)n;
             uint32_t polls = 0;
             while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                __builtin_amdgcn_s_sleep(2);
+                __builtin_amdgcn_s_sleep(1);
                 if (++polls > AB_SPIN_CAP) { timeout = true; break; }
             }
         }
@@ -478,8 +516,8 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
         if (nc == n || it + 1 >= max_it) break;
     }
     if (lane == 0) {
-        zfin[2 * i] = zr;
-        zfin[2 * i + 1] = zi;
+        zfin[2 * i] = zr / sc;
+        zfin[2 * i + 1] = zi / sc;
         if (timeout || (!done && wp > 1e-6 * (hypot(zr, zi) + 1e-6 * hscale))) set_status(info, DMD_ERR_EIG_NOCONV);
         if (i == 0 && info) info[2] = it + 1;
     }
@@ -587,161 +625,249 @@ eig_pair_kernel(int n, const double* __restrict__ zfin, const double* __restrict
 }
 
 // ====================================================================== 2c. eigenvectors
-// Inverse iteration on the Hessenberg matrix, one single-wave work-group per real
-// eigenvalue or pair: the LU factorisation of H - lambda I with partial pivoting (as in
-// the eigenvalue iteration, pivots below eps ||H||_F raised to that value) writes the
-// rows of U to the workspace; x = U^-1 (1, .., 1)^T by back-substitution (one dot product
-// per row, rescaled when it grows past 1e100) is the eigenvector of H, normalised to unit
-// 2-norm; the Hessenberg reflectors (A = Q H Q^T) then give the eigenvector Q x of A.
-// A pair stores [Re, Im] in its two columns.
-__global__ void __launch_bounds__(64)
-invit_kernel(int n, const double* __restrict__ Hr, const double* __restrict__ Vg, const double* __restrict__ taug,
-             const double* __restrict__ wr, const double* __restrict__ wi, const int32_t* __restrict__ kind0,
-             double* Us, double* Wraw)
+// Inverse iteration on the Hessenberg matrix: x = (H - lambda I)^-1 (1, .., 1)^T, one wave
+// per real eigenvalue or pair.  The factorisation eliminates the sub-diagonal from the
+// bottom with column operations and partial pivoting: (H - lambda I) E_{n-1} .. E_1 = R,
+// where E_j combines (and may swap) columns j - 1 and j.  Column j of R is final at step
+// j, and R y = 1 is solved along with it (y_j from the running sums of the finished
+// columns), so neither R nor the factors are stored; x = E_{n-1} .. E_1 y then follows
+// from the kept multipliers and swaps.  H and lambda are scaled by the power of two that
+// brings ||H||_F near 1; pivots below eps ||H||_F are raised to that value, and y is
+// rescaled when it grows past 1e100.  x, normalised to unit 2-norm, is taken
+// through the Hessenberg reflectors (A = Q H Q^T) to the eigenvector Q x of A; a pair
+// stores [Re, Im] in its two columns.  The waves of a work-group share H (column-packed)
+// in LDS, then the reflectors in the same space.
+constexpr int IV_MAXW = 4;
+static int invit_big(int n) { return std::max(hcol_size(n), vcol_size(n) + n); }
+static size_t invit_lds_bytes(int n, int waves)
 {
-    const int p = blockIdx.x, lane = threadIdx.x;
-    const int kd = kind0[p];
-    if (kd == 2) return;
-    const bool pair = kd == 1;
-    const double lr = wr[p], li = pair ? wi[p] : 0.0;
-    const double eps3 = 2.220446049250313e-16 * sqrt(Hr[(int64_t)n * n + 1]) + 1e-300;
-    const int64_t npk = (int64_t)n * (n + 1) / 2;
-    double* U = Us + (size_t)p * 2 * npk;                         // packed rows, complex
-    auto rowoff = [&](int k) -> int64_t { return (int64_t)k * n - (int64_t)k * (k - 1) / 2; };
-    dvec4 ar, ai;
+    return ((size_t)invit_big(n) + (size_t)waves * 5 * n) * sizeof(double) + (size_t)waves * round_up(n, 2) * sizeof(int);
+}
+static int invit_waves(int n)
+{
+    for (int w = IV_MAXW; w > 1; w >>= 1)
+        if (invit_lds_bytes(n, w) <= 160 * 1024 - 256) return w;
+    return 1;
+}
+
+// Slot s of a lane holds row i = lane + 64 s.  In steps j with j >> 6 == JS, rows i < j
+// (the ones still updated) lie in slots 0 .. JS, all of them in slots below JS.  The rows
+// of those slots take the update without a lane mask: rows i >= j are never read again.
+struct IvState {
+    double acr[AB_SLOTS], aci[AB_SLOTS];   // active column
+    double rhr[AB_SLOTS], rhi[AB_SLOTS];   // rho_i = sum over finished columns c of R(i, c) y_c
+    double ncr[AB_SLOTS];                  // column j - 1 of H, rows < j (the next step's)
+    double hsub;                           // H(j, j - 1)
+    double rs;                             // right-hand side scale
+};
+
+template <int JS>
+__device__ __forceinline__ void iv_load_col(const double* Hs, int j, int lane, double (&ncr)[AB_SLOTS], double& hsub)
+{
+    const double* nc = Hs + hcol_off(j - 1);                       // column j - 1: rows 0 .. j
 #pragma unroll
-    for (int s = 0; s < AB_SLOTS; ++s) {
-        const int c = lane + 64 * s;
-        ar[s] = c < n ? Hr[c] : 0.0;
-        ai[s] = 0.0;
-        if (c == 0) { ar[s] -= lr; ai[s] = -li; }
+    for (int s = 0; s <= JS; ++s) {
+        const int i = lane + 64 * s;
+        ncr[s] = (s < JS || i < j) ? nc[i] : 0.0;
     }
-    AbRow nxt = ab_load_row(Hr, n, 0, lane);
-    for (int k = 0; k + 1 < n; ++k) {
-        const AbRow cur = nxt;
-        if (k + 2 < n) nxt = ab_load_row(Hr, n, k + 1, lane);
-        const int ks = k >> 6, kl = k & 63;
-        const double akr = bcast(ar[ks], kl), aki = bcast(ai[ks], kl);
-        const double bk = cur.sub;
-        double* Urow = U + 2 * rowoff(k);
-        if (fabs(bk) > fabs(akr) + fabs(aki)) {
-            const double piv = fabs(bk) < eps3 ? (bk < 0.0 ? -eps3 : eps3) : bk;
-            const double ib = 1.0 / piv;
-            const double l_r = akr * ib, l_i = aki * ib;
+    hsub = nc[j];
+}
+
+template <int JS>
+__device__ void iv_segment(const double* Hs, int n, int lane, double lr, double li, double eps3, int j_hi, int j_lo,
+                           IvState& st, double* yv, double* mu, double* fs, int* swp)
+{
+    for (int j = j_hi; j >= j_lo; --j) {
+        double ncr[AB_SLOTS];
+        const double hs = st.hsub;
 #pragma unroll
-            for (int s = 0; s < AB_SLOTS; ++s) {
-                const int c = lane + 64 * s;
-                if (c < k || c >= n) continue;
-                double bcr = c == k ? piv : cur.v[s], bci = 0.0;
-                if (c == k + 1) { bcr -= lr; bci = -li; }
-                Urow[2 * (c - k)] = bcr;
-                Urow[2 * (c - k) + 1] = bci;
-                if (c == k) continue;
-                const double nr = ar[s] - fma(l_r, bcr, -l_i * bci), ni = ai[s] - fma(l_r, bci, l_i * bcr);
-                ar[s] = nr; ai[s] = ni;
-            }
-        } else {
-            double pr = akr, pi = aki;
-            if (fabs(pr) + fabs(pi) < eps3) { pr = eps3; pi = 0.0; }
-            const double m2 = fma(pr, pr, pi * pi);
-            const double ir = pr / m2, ii = -pi / m2;
-            const double l_r = bk * ir, l_i = bk * ii;
+        for (int s = 0; s <= JS; ++s) ncr[s] = st.ncr[s];
+        if (j - 1 >= 1) {
+            if (((j - 1) >> 6) == JS) iv_load_col<JS>(Hs, j - 1, lane, st.ncr, st.hsub);
+            else iv_load_col<(JS > 0 ? JS - 1 : 0)>(Hs, j - 1, lane, st.ncr, st.hsub);
+        }
+        const int jl = j & 63;
+        const double ajr = bcast(st.acr[JS], jl), aji = bcast(st.aci[JS], jl);
+        const double qjr = bcast(st.rhr[JS], jl), qji = bcast(st.rhi[JS], jl);
+        double nci[AB_SLOTS];
 #pragma unroll
-            for (int s = 0; s < AB_SLOTS; ++s) {
-                const int c = lane + 64 * s;
-                if (c < k || c >= n) continue;
-                const double xr = c == k ? pr : ar[s], xi = c == k ? pi : ai[s];
-                Urow[2 * (c - k)] = xr;
-                Urow[2 * (c - k) + 1] = xi;
-                if (c == k) continue;
-                double bcr = cur.v[s], bci = 0.0;
-                if (c == k + 1) { bcr -= lr; bci = -li; }
-                ar[s] = bcr - fma(l_r, xr, -l_i * xi);
-                ai[s] = bci - fma(l_r, xi, l_i * xr);
-            }
+        for (int s = 0; s <= JS; ++s) {
+            const int i = lane + 64 * s;
+            nci[s] = 0.0;
+            if (i == j - 1) { ncr[s] -= lr; nci[s] = -li; }
+        }
+        // pivot: H(j, j - 1) of the new column when it is larger, else the active column's
+        // entry (a select, not a branch); raised to eps3 when below it
+        const bool swap = fabs(hs) > fabs(ajr) + fabs(aji);
+        double pvr = swap ? hs : ajr, pvi = swap ? 0.0 : aji;
+        const bool tiny = fabs(pvr) + fabs(pvi) < eps3;
+        pvr = tiny ? (pvr < 0.0 ? -eps3 : eps3) : pvr;
+        pvi = tiny ? 0.0 : pvi;
+        const double orr = swap ? ajr : hs, oi = swap ? aji : 0.0;
+        double ipr, ipi;
+        crcp(pvr, pvi, &ipr, &ipi);
+        const double mur = fma(orr, ipr, -oi * ipi), mui = fma(orr, ipi, oi * ipr);
+        // y_j = (rs - rho_j) / pivot
+        const double tr = st.rs - qjr, ti = -qji;
+        double yr = fma(tr, ipr, -ti * ipi), yi = fma(tr, ipi, ti * ipr);
+        // growth guard without a branch: past 1e100 this step's y, the right-hand side and
+        // the running sums take a factor 1e-100, kept in fs[j]; the y stored before are
+        // brought to the same scale when x is formed
+        const double f = fabs(yr) + fabs(yi) > 1e100 ? 1e-100 : 1.0;
+        yr *= f; yi *= f; st.rs *= f;
+#pragma unroll
+        for (int s = 0; s < AB_SLOTS; ++s) { st.rhr[s] *= f; st.rhi[s] *= f; }
+#pragma unroll
+        for (int s = 0; s <= JS; ++s) {
+            const double rcr = swap ? ncr[s] : st.acr[s], rci = swap ? nci[s] : st.aci[s];   // R(i, j)
+            const double ocr = swap ? st.acr[s] : ncr[s], oci = swap ? st.aci[s] : nci[s];
+            st.rhr[s] += fma(rcr, yr, -rci * yi);
+            st.rhi[s] += fma(rcr, yi, rci * yr);
+            st.acr[s] = ocr - fma(mur, rcr, -mui * rci);
+            st.aci[s] = oci - fma(mur, rci, mui * rcr);
+        }
+        if (lane == 0) {
+            yv[2 * j] = yr; yv[2 * j + 1] = yi;
+            mu[2 * j] = mur; mu[2 * j + 1] = mui;
+            fs[j] = f;
+            swp[j] = swap ? 1 : 0;
         }
     }
-    {
-        const int k = n - 1, ks = k >> 6, kl = k & 63;
-        double pr = bcast(ar[ks], kl), pi = bcast(ai[ks], kl);
-        if (fabs(pr) + fabs(pi) < eps3) { pr = eps3; pi = 0.0; }
-        if (lane == kl) { U[2 * rowoff(k)] = pr; U[2 * rowoff(k) + 1] = pi; }
+}
+
+__global__ void __launch_bounds__(64 * IV_MAXW)
+invit_kernel(int n, int waves, const double* __restrict__ Hr, const double* __restrict__ Vg,
+             const double* __restrict__ taug, const double* __restrict__ wr, const double* __restrict__ wi,
+             const int32_t* __restrict__ kind0, double* Wraw)
+{
+    extern __shared__ __align__(16) double iv_sm[];
+    const int big = max(hcol_size(n), vcol_size(n) + n);
+    double* Hs = iv_sm;                                   // column-packed H, later the reflectors
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    double* yv = iv_sm + big + (size_t)wave * 5 * n;      // y, then x (re, im interleaved)
+    double* mu = yv + 2 * n;                              // multipliers (re, im)
+    double* fs = mu + 2 * n;                              // growth-guard factors
+    int* swp = reinterpret_cast<int*>(iv_sm + big + (size_t)waves * 5 * n) + wave * round_up(n, 2);
+    const int p = blockIdx.x * waves + wave;
+    const int nthr = 64 * waves;
+    // H / 2^e column-packed (2^e near ||H||_F, as in the eigenvalue iteration): row r read
+    // whole (coalesced), entry (r, c) stored at column c
+    const double f2raw = Hr[(int64_t)n * n + 1];
+    const double sc = f2raw > 0.0 ? ldexp(1.0, -ilogb(sqrt(f2raw))) : 1.0;
+    for (int r = wave; r < n; r += waves) {
+        const int c0 = r == 0 ? 0 : r - 1;
+        for (int c = c0 + lane; c < n; c += 64) Hs[hcol_off(c) + r] = Hr[(int64_t)r * n + c] * sc;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");    // the rows of U are read back below
-    // back-substitution U x = rs (1, .., 1)^T, rows from the last; row k - 1 loaded while
-    // row k is solved
-    dvec4 xr, xi;
+    __syncthreads();
+    const bool valid = p < n && kind0[p] != 2;
+    const bool pair = valid && kind0[p] == 1;
+    double xr[AB_SLOTS], xi[AB_SLOTS];
 #pragma unroll
     for (int s = 0; s < AB_SLOTS; ++s) { xr[s] = 0.0; xi[s] = 0.0; }
-    double rs = 1.0;
-    auto load_u = [&](int k, dvec4& vr, dvec4& vi) {
-        const double* Urow = U + 2 * rowoff(k);
+    if (valid) {
+        const double lr = wr[p] * sc, li = pair ? wi[p] * sc : 0.0;
+        const double eps3 = 2.220446049250313e-16 * sqrt(f2raw) * sc + 1e-300;
+        IvState st;
+        const double* cl = Hs + hcol_off(n - 1);
 #pragma unroll
         for (int s = 0; s < AB_SLOTS; ++s) {
-            const int c = lane + 64 * s;
-            const bool in = c >= k && c < n;
-            vr[s] = in ? Urow[2 * (c - k)] : 0.0;
-            vi[s] = in ? Urow[2 * (c - k) + 1] : 0.0;
+            const int i = lane + 64 * s;
+            st.acr[s] = i < n ? cl[i] : 0.0;
+            st.aci[s] = 0.0;
+            if (i == n - 1) { st.acr[s] -= lr; st.aci[s] = -li; }
+            st.rhr[s] = 0.0;
+            st.rhi[s] = 0.0;
+            st.ncr[s] = 0.0;
         }
-    };
-    dvec4 nur, nui;
-    load_u(n - 1, nur, nui);
-    for (int k = n - 1; k >= 0; --k) {
-        const dvec4 ur = nur, ui = nui;
-        if (k > 0) load_u(k - 1, nur, nui);
-        const int ks = k >> 6, kl = k & 63;
-        double tr = 0.0, ti = 0.0;
+        st.rs = 1.0;
+        st.hsub = 0.0;
+        if (n > 1) {
+            const int j0 = n - 1;                              // first step's column j0 - 1
+            if ((j0 >> 6) == 2) iv_load_col<2>(Hs, j0, lane, st.ncr, st.hsub);
+            else if ((j0 >> 6) == 1) iv_load_col<1>(Hs, j0, lane, st.ncr, st.hsub);
+            else iv_load_col<0>(Hs, j0, lane, st.ncr, st.hsub);
+        }
+        // steps j = n - 1 .. 1 by segments of 64
+        if (n - 1 >= 128) iv_segment<2>(Hs, n, lane, lr, li, eps3, n - 1, 128, st, yv, mu, fs, swp);
+        if (n - 1 >= 64) iv_segment<1>(Hs, n, lane, lr, li, eps3, min(n - 1, 127), 64, st, yv, mu, fs, swp);
+        if (n - 1 >= 1) iv_segment<0>(Hs, n, lane, lr, li, eps3, min(n - 1, 63), 1, st, yv, mu, fs, swp);
+        {
+            double pvr = bcast(st.acr[0], 0), pvi = bcast(st.aci[0], 0);
+            if (fabs(pvr) + fabs(pvi) < eps3) { pvr = eps3; pvi = 0.0; }
+            const double qr = bcast(st.rhr[0], 0), qi = bcast(st.rhi[0], 0);
+            const double tr = st.rs - qr, ti = -qi;
+            double ipr, ipi;
+            crcp(pvr, pvi, &ipr, &ipi);
+            if (lane == 0) { yv[0] = fma(tr, ipr, -ti * ipi); yv[1] = fma(tr, ipi, ti * ipr); }
+        }
+        wave_sync_lds();
+        // x = E_{n-1} .. E_1 y: E_j takes v_j -= mu_j v_{j-1}, then swaps v_{j-1}, v_j if
+        // the step pivoted; component j - 1 is final after E_j.  y_j is brought to the scale
+        // of y_0 by the factors of the steps after it (steps run from j = n - 1 down).
+        if (lane == 0) {
+            double cr = yv[0], ci = yv[1];
+            double g = 1.0;
+            for (int j = 1; j < n; ++j) {
+                if (j >= 2) g *= fs[j - 1];                   // factors of steps 1 .. j - 1
+                const double yr_ = yv[2 * j] * g, yi_ = yv[2 * j + 1] * g;
+                const double vr = yr_ - fma(mu[2 * j], cr, -mu[2 * j + 1] * ci);
+                const double vi = yi_ - fma(mu[2 * j], ci, mu[2 * j + 1] * cr);
+                if (swp[j]) {
+                    yv[2 * (j - 1)] = vr; yv[2 * (j - 1) + 1] = vi;
+                } else {
+                    yv[2 * (j - 1)] = cr; yv[2 * (j - 1) + 1] = ci;
+                    cr = vr; ci = vi;
+                }
+            }
+            yv[2 * (n - 1)] = cr; yv[2 * (n - 1) + 1] = ci;
+        }
+        wave_sync_lds();
 #pragma unroll
         for (int s = 0; s < AB_SLOTS; ++s) {
-            const int c = lane + 64 * s;
-            if (c <= k) continue;
-            tr += fma(ur[s], xr[s], -ui[s] * xi[s]);
-            ti += fma(ur[s], xi[s], ui[s] * xr[s]);
+            const int i = lane + 64 * s;
+            xr[s] = i < n ? yv[2 * i] : 0.0;
+            xi[s] = i < n ? yv[2 * i + 1] : 0.0;
         }
-        tr = wave_sum(tr);
-        ti = wave_sum(ti);
-        const double dr = bcast(ur[ks], kl), di = bcast(ui[ks], kl);
-        const double nr = rs - tr, ni = -ti;
-        const double m2 = fma(dr, dr, di * di);
-        double vr = fma(nr, dr, ni * di) / m2, vi = fma(ni, dr, -nr * di) / m2;
-        if (fabs(vr) + fabs(vi) > 1e100) {
-            xr *= 1e-100; xi *= 1e-100; rs *= 1e-100;
-            vr *= 1e-100; vi *= 1e-100;
-        }
+        double nn2 = 0.0;
 #pragma unroll
-        for (int s = 0; s < AB_SLOTS; ++s)
-            if (s == ks && lane == kl) { xr[s] = vr; xi[s] = vi; }
+        for (int s = 0; s < AB_SLOTS; ++s) nn2 = fma(xr[s], xr[s], fma(xi[s], xi[s], nn2));
+        nn2 = wave_sum(nn2);
+        const double inv = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 0.0;
+#pragma unroll
+        for (int s = 0; s < AB_SLOTS; ++s) { xr[s] *= inv; xi[s] *= inv; }
     }
-    // unit 2-norm
-    double nn2 = 0.0;
-#pragma unroll
-    for (int s = 0; s < AB_SLOTS; ++s) nn2 = fma(xr[s], xr[s], fma(xi[s], xi[s], nn2));
-    nn2 = wave_sum(nn2);
-    const double inv = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 0.0;
-    xr *= inv;
-    xi *= inv;
-    // y = Q x with Q = P_0 P_1 .. P_{n-3}: P_k = I - tau_k v_k v_k^T (v_k rows k+1.., v_{k+1} = 1)
-    auto load_v = [&](int k, dvec4& v) {
-#pragma unroll
-        for (int s = 0; s < AB_SLOTS; ++s) {
-            const int c = lane + 64 * s;
-            v[s] = (c > k && c < n) ? Vg[(int64_t)k * n + c] : 0.0;
-        }
-    };
+    // reflectors into the space H held: column k (rows k + 1 ..) packed, then tau
+    __syncthreads();
     if (n > 2) {
-        dvec4 nv;
-        load_v(n - 3, nv);
+        double* taus = Hs + vcol_size(n);
+        for (int k = 0; k + 2 < n; ++k) {
+            const int len = n - k - 1;
+            for (int e = tid; e < len; e += nthr) Hs[vcol_off(k, n) + e] = Vg[(int64_t)k * n + k + 1 + e];
+        }
+        for (int k = tid; k + 2 < n; k += nthr) taus[k] = taug[k];
+    }
+    __syncthreads();
+    if (!valid) return;
+    // y = Q x with Q = P_0 P_1 .. P_{n-3}: P_k = I - tau_k v_k v_k^T (v_k rows k+1.., v_{k+1} = 1)
+    if (n > 2) {
+        const double* taus = Hs + vcol_size(n);
         for (int k = n - 3; k >= 0; --k) {
-            const dvec4 v = nv;
-            if (k > 0) load_v(k - 1, nv);
-            const double t = taug[k];
+            const double* v = Hs + vcol_off(k, n) - (k + 1);      // entry i at v[i]
+            double vv[AB_SLOTS];
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) {
+                const int i = lane + 64 * s;
+                vv[s] = (i > k && i < n) ? v[i] : 0.0;
+            }
             double gr = 0.0, gi = 0.0;
 #pragma unroll
-            for (int s = 0; s < AB_SLOTS; ++s) { gr = fma(v[s], xr[s], gr); gi = fma(v[s], xi[s], gi); }
+            for (int s = 0; s < AB_SLOTS; ++s) { gr = fma(vv[s], xr[s], gr); gi = fma(vv[s], xi[s], gi); }
+            const double t = taus[k];
             gr = wave_sum(gr) * t;
             gi = wave_sum(gi) * t;
 #pragma unroll
-            for (int s = 0; s < AB_SLOTS; ++s) { xr[s] = fma(-gr, v[s], xr[s]); xi[s] = fma(-gi, v[s], xi[s]); }
+            for (int s = 0; s < AB_SLOTS; ++s) { xr[s] = fma(-gr, vv[s], xr[s]); xi[s] = fma(-gi, vv[s], xi[s]); }
         }
     }
 #pragma unroll
@@ -840,19 +966,29 @@ hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = fill_i32(s, (int32_t*)w.counter, 1, 0)) != hipSuccess) return e;
-    hipLaunchKernelGGL(aberth_kernel, dim3(n), dim3(64), 0, s, n, w.H, w.zbuf, w.conv, w.counter, w.zfin, info,
+    hipLaunchKernelGGL(aberth_kernel, dim3((unsigned)ceil_div(n, AB_WAVES)), dim3(64 * AB_WAVES),
+                       (size_t)(hcol_size(n) + n) * sizeof(double), s, n, w.H, w.zbuf, w.conv, w.counter, w.zfin, info,
                        fmax(tol, 4e-16), AB_MAX_IT);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(eig_pair_kernel, dim3(1), dim3(EP_THREADS), 0, s, n, w.zfin, w.H, w.wr, w.wi, w.kind0, info);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(invit_kernel, dim3(n), dim3(64), 0, s, n, w.H, w.V, w.tau, w.wr, w.wi, w.kind0, w.Us, w.Wraw);
+    const int iw = invit_waves(n);
+    hipLaunchKernelGGL(invit_kernel, dim3((unsigned)ceil_div(n, iw)), dim3(64 * iw), invit_lds_bytes(n, iw), s, n, iw,
+                       w.H, w.V, w.tau, w.wr, w.wi, w.kind0, w.Wraw);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(sort_modes_kernel, dim3(1), dim3(SM_THREADS), (size_t)n * (2 * sizeof(double) + 2 * sizeof(int)),
                        s, n, w.wr, w.wi, w.kind0, w.Wraw, lam, kind, W);
     return hipGetLastError();
 }
 
-hipError_t eig_prepare() { return hipSuccess; }
+hipError_t eig_prepare()
+{
+    hipError_t e = hipFuncSetAttribute((const void*)aberth_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024 - 256);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
+}
+
 hipError_t prepare_kernels()
 {
     hipError_t e = gemm_prepare();
