@@ -173,7 +173,7 @@ def main():
     print(f"# reconstruction tile configs (autotuned): {recon_cfg}", file=sys.stderr, flush=True)
     st = int(m.info[0].item())
     info = m.info.cpu().tolist()
-    print(f"# fit info: status {info[0]}, Jacobi sweeps {info[1]}, eigenvalue (Aberth) iterations {info[2]}, "
+    print(f"# fit info: status {info[0]}, bisection rounds {info[1]}, eigenvalue (Aberth) iterations {info[2]}, "
           f"shifted CholeskyQR retries {info[3]}", file=sys.stderr, flush=True)
     if st != 0:
         print(json.dumps({"error": f"fit status {st}: {dmd.status_string(st)}"}), flush=True)
@@ -365,7 +365,7 @@ def run_c3(args):
     m = step()
     torch.cuda.synchronize()
     info = m.info.cpu().tolist()
-    _say(f"fit info: status {info[0]}, Jacobi sweeps {info[1]}, eigenvalue (Aberth) iterations {info[2]}")
+    _say(f"fit info: status {info[0]}, bisection rounds {info[1]}, eigenvalue (Aberth) iterations {info[2]}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -421,7 +421,7 @@ def run_c3(args):
                                "frames, N=6291456 (3x128^3), m=300, r=150, p=10, q=2, noise 1e-3",
                    "N": cfg.N, "m": cfg.m, "r": cfg.r, "p": cfg.p, "q": cfg.q, "K": cfg.m},
         "mixed": {"fit_ms": round(fit_ms, 3), "recon_bf16x3_ms": round(recon_ms, 3),
-                  "fit_info": {"jacobi_sweeps": info[1], "aberth_iterations": info[2]}},
+                  "fit_info": {"bisection_rounds": info[1], "aberth_iterations": info[2]}},
         "fp64": fp64,
         "accuracy": {"fields_mixed_vs_fp64_rel": agree, "fields_vs_data_rel": resid,
                      "rows_sampled": int(rows.size)},

@@ -131,7 +131,8 @@ typedef struct dmd_fit_opts {
 
 /* Number of int32 words in model->info. */
 #define DMD_INFO_WORDS 8
-/* info[0] status, [1] Jacobi sweeps, [2] Ehrlich-Aberth iterations of the eigenvalues
+/* info[0] status, [1] bisection rounds of the symmetric eigenvalues, [2] Ehrlich-Aberth
+ * iterations of the eigenvalues
  * of Atilde, [3] shifted CholeskyQR retries, [4] OptDMD Levenberg-Marquardt steps,
  * [5..7] reserved. */
 
@@ -192,7 +193,8 @@ int32_t dmd_fit_workspace_size(int64_t n, int32_t ncols, int32_t xdtype,
  *            every array.
  * Steps (Sec. 4.3 then Sec. 3.1): sketch Y = X Omega; CholeskyQR2 (FP64 Gram);
  * q power iterations W = orth(X^T Q), Y = X W; B = Q^T [X X']; eigen-decomposition
- * of the FP64 Gram B B^T by Jacobi (singular values and left vectors of B);
+ * of the FP64 Gram B B^T (Householder tridiagonalisation, bisection on Sturm counts,
+ * inverse iteration: singular values and left vectors of B);
  * Atilde = U_r^T B' V_r S_r^-1; Hessenberg reduction, eigenvalues as the roots of
  * det(zI - H) by the Ehrlich-Aberth iteration, eigenvectors W by inverse iteration;
  * exact modes Phi = X' V_r S_r^-1 W; b = Phi^+ x_0.

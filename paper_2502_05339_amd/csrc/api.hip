@@ -172,11 +172,10 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     const int64_t ldphi_ws = 16 * NN_MAX_CB;
     const int64_t ldy = round_up(n, 4);
     const double u = 1.1102230246251565e-16;
-    // Convergence of the FP64 small factors: full FP64 accuracy on the FP64 paths; on the
-    // mixed path (FP32 data, 1e-5 eigenvalue target) 1e-10 relative is almost three orders
-    // below the rounding of the FP32 data (6e-8), and saves the last Jacobi sweep and about
-    // 8% of the QR iterations.
-    const double jac_tol = mixed ? 1e-10 : 4.5e-16;
+    // Convergence of the eigenvalue iteration: full FP64 accuracy on the FP64 paths; on the
+    // mixed path (FP32 data, 1e-5 eigenvalue target) a last correction below 1e-10
+    // relative, almost three orders below the rounding of the FP32 data (6e-8); the
+    // iteration converges cubically, so the eigenvalues themselves are far closer.
     const double defl_tol = mixed ? 1e-10 : 2.220446049250313e-16;
 
     int32_t* flags = cv.take<int32_t>(64);
@@ -205,6 +204,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     double* rhs2 = cv.take<double>((size_t)r);
     void* res = cv.take<char>((size_t)n * esize(fdt));
     void* eigws = cv.take<char>(eig_workspace_bytes(r));
+    void* symws = cv.take<char>(sym_eig_workspace_bytes(std::max(l, mm)));
     double* Gxp2 = (exact && !shifted) ? cv.take<double>((size_t)mm * mm) : nullptr;
     void* Y = nullptr;
     double* Wt = nullptr;
@@ -291,13 +291,21 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
             HIPCHK(gemm_tn(st, fdt, DMD_F64, Y, ldy, 0, l, a.x, a.ldx, 0, mm, 0, n, P, Bx, l, nullptr, 0, nullptr));
             HIPCHK(gemm_tn(st, fdt, DMD_F64, Y, ldy, 0, l, Xp, ldxp, 0, mm, 0, n, P, Bp, l, nullptr, 0, nullptr));
         }
-        // SVD of B through the Jacobi eigen-decomposition of B B^T
+        // SVD of B through the symmetric eigen-decomposition of B B^T: sigma_i^2 and the
+        // left vectors U_r of the r largest
         HIPCHK(small_gemm(st, 0, 1, l, l, mm, 1.0, Bx, l, Bx, l, 0.0, G, l));
-        HIPCHK(sym_eig(st, G, l, l, evals, Ueig, info, jac_tol));
+        HIPCHK(sym_eig(st, G, l, l, r, evals, Ueig, l, symws, info));
         HIPCHK(sigma_from_evals(st, evals, r, o.rank_tol, sigma, model->sigma, info));
-        // Vs = V_r S_r^-1 = B^T U_r S_r^-2
+        // Vs = V_r S_r^-1, written for the computed U_r as B^T U_r (U_r^T B B^T U_r)^-1 (the
+        // same matrix when U_r holds exact singular vectors; for any basis of their span it
+        // gives a reduced operator similar to the exact one and the same modes).  With
+        // C = B^T U_r S_r^-1 (close to V_r) and C^T C = R^T R:  Vs = C R^-1 R^-T S_r^-1.
         HIPCHK(small_gemm(st, 1, 0, mm, r, l, 1.0, Bx, l, Ueig, l, 0.0, Vs, mm));
         HIPCHK(scale_cols(st, mm, r, Vs, mm, sigma, 1));
+        HIPCHK(small_gemm(st, 1, 0, r, r, mm, 1.0, Vs, mm, Vs, mm, 0.0, G, r));
+        HIPCHK(chol_inv(st, G, r, r, Rinv, r, nullptr, 0, 0.0, nullptr, info, nullptr));
+        HIPCHK(small_gemm(st, 0, 0, mm, r, r, 1.0, Vs, mm, Rinv, r, 0.0, T1, mm));
+        HIPCHK(small_gemm(st, 0, 1, mm, r, r, 1.0, T1, mm, Rinv, r, 0.0, Vs, mm));
         HIPCHK(scale_cols(st, mm, r, Vs, mm, sigma, 1));
         // Atilde = U_r^T B' V_r S_r^-1
         HIPCHK(small_gemm(st, 0, 0, l, r, mm, 1.0, Bp, l, Vs, mm, 0.0, T1, l));
@@ -320,14 +328,22 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
             Gxp = Gxp2;
             ldg = mm;
         }
-        HIPCHK(sym_eig(st, Gxx, ldg, mm, evals, Ueig, info, jac_tol));
+        HIPCHK(sym_eig(st, Gxx, ldg, mm, r, evals, Ueig, mm, symws, info));
         HIPCHK(sigma_from_evals(st, evals, r, o.rank_tol, sigma, model->sigma, info));
         HIPCHK(copy_f64(st, mm, r, r, Ueig, mm, Vs, mm));
         HIPCHK(scale_cols(st, mm, r, Vs, mm, sigma, 1));
-        // Atilde = S^-1 V_r^T (X^T X') V_r S^-1
+        // Atilde = (Vs^T X^T X Vs)^-1 Vs^T (X^T X') Vs with Vs = V_r S_r^-1: the operator on
+        // the span of X Vs in that basis (the inverse is the identity for exact singular
+        // vectors; for any basis of their span the operator is the same).  The modes are
+        // X' Vs W.  Vs^T X^T X Vs = R^T R.
         double* T2 = M;   // scratch (mm x r), overwritten below
+        HIPCHK(small_gemm(st, 0, 0, mm, r, mm, 1.0, Gxx, ldg, Vs, mm, 0.0, T2, mm));
+        HIPCHK(small_gemm(st, 1, 0, r, r, mm, 1.0, Vs, mm, T2, mm, 0.0, PhiG, r));
+        HIPCHK(chol_inv(st, PhiG, r, r, Rinv, r, nullptr, 0, 0.0, nullptr, info, nullptr));
         HIPCHK(small_gemm(st, 0, 0, mm, r, mm, 1.0, Gxp, ldg, Vs, mm, 0.0, T2, mm));
-        HIPCHK(small_gemm(st, 1, 0, r, r, mm, 1.0, Vs, mm, T2, mm, 0.0, At, r));
+        HIPCHK(small_gemm(st, 1, 0, r, r, mm, 1.0, Vs, mm, T2, mm, 0.0, W, r));
+        HIPCHK(small_gemm(st, 1, 0, r, r, r, 1.0, Rinv, r, W, r, 0.0, PhiG, r));
+        HIPCHK(small_gemm(st, 0, 0, r, r, r, 1.0, Rinv, r, PhiG, r, 0.0, At, r));
     }
     // eigen-decomposition, canonical order, folded eigenvectors
     HIPCHK(nonsym_eig(st, At, r, r, eigws, model->lam, model->kind, W, info, defl_tol));

@@ -65,25 +65,25 @@ static EigWs eig_carve(void* ws, int n)
 
 // ====================================================================== 1. Hessenberg
 // Householder reduction A = Q H Q^T, H held in registers: thread (ib, jb) of a 32 x 32
-// grid keeps H(ib + 32 a, jb + 32 c), a, c < HS_N.  Step k, reflector P = I - tau v v^T of
+// grid keeps H(ib + 32 a, jb + 32 c), a, c < HN (n <= 32 HN).  Step k, reflector P = I - tau v v^T of
 // column k (rows k+1..):  with u = H v, w = H^T v and gamma = v^T H v taken from H before
 // the step, P H P = H - tau (v w^T + u v^T) + tau^2 gamma v v^T on columns > k, and column
 // k becomes (.., beta, 0, ..).  u, w and gamma are summed from per-thread partials in LDS
 // (fixed order).  While the others update their entries, wave 0 forms the next column and
 // the next reflector.  Three barriers per step.
-constexpr int HS_N = (EIG_MAX + 31) / 32;
-
+template <int HN>
 __global__ void __launch_bounds__(1024)
 hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, double* V, double* tau)
 {
-    __shared__ double col[EIG_MAX];           // column k of H (rows > k), for v
-    __shared__ double colpre[EIG_MAX];        // column k + 1 before step k
-    __shared__ double us[EIG_MAX], ws[EIG_MAX];
+    constexpr int HS_N = HN, NMAX = 32 * HN;
+    __shared__ double col[NMAX];              // column k of H (rows > k), for v
+    __shared__ double colpre[NMAX];           // column k + 1 before step k
+    __shared__ double us[NMAX], ws[NMAX];
     // partial u per column group jb; rows of odd length so that the 32 lanes of a store
     // (32 column groups, one row) fall in different banks
-    constexpr int UPS = EIG_MAX + 1;
+    constexpr int UPS = NMAX + 1;
     __shared__ double upart[32 * UPS];
-    __shared__ double wpart[32 * EIG_MAX];    // partial w per row group ib
+    __shared__ double wpart[32 * NMAX];       // partial w per row group ib
     __shared__ double gpart[1024];
     __shared__ double refl[4];                // tau, beta, 1 / (alpha - beta), gamma
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -149,7 +149,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
             for (int a = 0; a < HS_N; ++a) t = fma(vr[a], h[a][c], t);
             g = fma(t, vc[c], g);
             const int j = jb + 32 * c;
-            if (j < n) wpart[ib * EIG_MAX + j] = t;
+            if (j < n) wpart[ib * NMAX + j] = t;
             if (j == k + 1)
 #pragma unroll
                 for (int a = 0; a < HS_N; ++a)
@@ -165,7 +165,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
         } else if (tid >= 256 && tid - 256 < n) {
             const int j = tid - 256;
             double t = 0.0;
-            for (int q = 0; q < 32; ++q) t += wpart[q * EIG_MAX + j];
+            for (int q = 0; q < 32; ++q) t += wpart[q * NMAX + j];
             ws[j] = t;
         } else if (wave == 15) {
             double t = 0.0;
@@ -956,13 +956,271 @@ sort_modes_kernel(int n, const double* __restrict__ wr, const double* __restrict
     }
 }
 
+// ====================================================================== 4. symmetric
+// Eigen-decomposition of a symmetric n x n matrix S (n <= DMD_MAX_SMALL): every eigenvalue
+// (descending) and the eigenvectors of the nv largest, in three launches:
+//  1. hessenberg_kernel: the Householder reduction of a symmetric matrix is tridiagonal,
+//     S = Q T Q^T; its diagonal d and sub-diagonal e are read from H (the entries above
+//     the super-diagonal are rounding-level and dropped).
+//  2. tri_bisect_kernel (one wave per eigenvalue): bisection on Sturm counts, the number
+//     of negative pivots of the LDL^T factorisation of T - xI, with the 64 lanes counting
+//     at 64 points of the current interval, so one round narrows it 65-fold; from the
+//     Gershgorin interval down to 4 eps max|x| (the absolute accuracy eps ||T|| that any
+//     backward-stable method reaches).
+//  3. tri_invit_kernel (one wave per wanted eigenvector): inverse iteration on T, two
+//     solves of (T - lambda I) x = b by Gaussian elimination with partial pivoting (three
+//     bands of U kept in LDS), from a start vector that differs between eigenvalues, so
+//     equal or close eigenvalues still get independent vectors; then Q x through the
+//     reflectors.  The vectors are unit-norm but, inside clusters of close eigenvalues,
+//     only as orthogonal as inverse iteration makes them: callers that need an exact
+//     basis form it from their span.
+// T is scaled by the power of two that brings ||S||_F near 1 (exact), so pivots and Sturm
+// recurrences stay in range.
+constexpr int TB_WAVES = 4;
+constexpr int TB_MAX_ROUNDS = 40;
+constexpr double TB_PIVMIN = 1e-290;
+
+__device__ __forceinline__ int sturm_count(const double* d, const double* e2, int n, double x)
+{
+    double q = d[0] - x;
+    q = fabs(q) < TB_PIVMIN ? -TB_PIVMIN : q;
+    int c = q < 0.0 ? 1 : 0;
+    for (int i = 1; i < n; ++i) {
+        q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
+        q = fabs(q) < TB_PIVMIN ? -TB_PIVMIN : q;
+        c += q < 0.0 ? 1 : 0;
+    }
+    return c;
+}
+
+__device__ __forceinline__ double tb_scale(const double* Hr, int n)
+{
+    const double f2 = Hr[(int64_t)n * n + 1];
+    return f2 > 0.0 ? ldexp(1.0, -ilogb(sqrt(f2))) : 1.0;
+}
+
+__global__ void __launch_bounds__(64 * TB_WAVES)
+tri_bisect_kernel(int n, const double* __restrict__ Hr, double* evals, int32_t* info)
+{
+    extern __shared__ __align__(16) double tb_sm[];
+    double* d = tb_sm;               // diagonal
+    double* e2 = tb_sm + n;          // squared sub-diagonal
+    double* ea = tb_sm + 2 * n;      // |sub-diagonal|
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const double sc = tb_scale(Hr, n);
+    for (int i = tid; i < n; i += 64 * TB_WAVES) {
+        d[i] = Hr[(int64_t)i * n + i] * sc;
+        const double b = i + 1 < n ? Hr[(int64_t)(i + 1) * n + i] * sc : 0.0;
+        e2[i] = b * b;
+        ea[i] = fabs(b);
+    }
+    __syncthreads();
+    const int k = blockIdx.x * TB_WAVES + wave;          // k-th largest
+    if (k >= n) return;
+    // Gershgorin interval, widened by the rounding of its sums
+    double glo = __builtin_inf(), ghi = -__builtin_inf();
+    for (int i = lane; i < n; i += 64) {
+        const double rad = (i > 0 ? ea[i - 1] : 0.0) + ea[i];
+        glo = fmin(glo, d[i] - rad);
+        ghi = fmax(ghi, d[i] + rad);
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        glo = fmin(glo, __shfl_xor(glo, o, 64));
+        ghi = fmax(ghi, __shfl_xor(ghi, o, 64));
+    }
+    const double tnorm = fmax(fabs(glo), fabs(ghi));
+    double lo = glo - 4.0 * 2.220446049250313e-16 * n * tnorm - 2.0 * TB_PIVMIN;
+    double hi = ghi + 4.0 * 2.220446049250313e-16 * n * tnorm + 2.0 * TB_PIVMIN;
+    const int j = n - 1 - k;                             // j-th smallest: count(lo) <= j < count(hi)
+    const double atol = 4.0 * 2.220446049250313e-16 * tnorm + TB_PIVMIN;
+    int round = 0;
+    for (; round < TB_MAX_ROUNDS; ++round) {
+        const double w = hi - lo;
+        if (w <= fmax(4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)), atol)) break;
+        const double x = fma(w, (lane + 1) * (1.0 / 65.0), lo);
+        const int c = sturm_count(d, e2, n, x);
+        const uint64_t m = __ballot(c <= j);
+        const int t = m ? 63 - __clzll((long long)m) : -1;   // last point with count <= j
+        const double nlo = t >= 0 ? bcast(x, t) : lo;
+        const double nhi = t < 63 ? bcast(x, t + 1) : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (lane == 0) {
+        evals[k] = 0.5 * (lo + hi) / sc;
+        if (info) atomicMax(&info[1], round);
+    }
+}
+
+// per-wave LDS of tri_invit_kernel: the bands of U (u0 diagonal, u1, u2), the multipliers,
+// the row swaps and the right-hand side / solution
+constexpr int TI_ARR = 6;
+__host__ __device__ __forceinline__ int tinv_big(int n) { return vcol_size(n) + n; }
+static size_t tinv_lds_bytes(int n, int waves)
+{
+    return ((size_t)2 * n + tinv_big(n) + (size_t)waves * TI_ARR * n) * sizeof(double);
+}
+static int tinv_waves(int n)
+{
+    for (int w = IV_MAXW; w > 1; w >>= 1)
+        if (tinv_lds_bytes(n, w) <= 160 * 1024 - 256) return w;
+    return 1;
+}
+
+// start vector entry i of eigenvector k: a fixed pseudo-random value in (-1, 1)
+__device__ __forceinline__ double ti_start(int k, int i)
+{
+    uint64_t z = (uint64_t)(k + 1) * 0x9E3779B97F4A7C15ull + (uint64_t)(i + 1) * 0xD1B54A32D192ED03ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+__global__ void __launch_bounds__(64 * IV_MAXW)
+tri_invit_kernel(int n, int nv, int waves, const double* __restrict__ Hr, const double* __restrict__ Vg,
+                 const double* __restrict__ taug, const double* __restrict__ evals, double* Vout, int64_t ldv)
+{
+    extern __shared__ __align__(16) double ti_sm[];
+    double* d = ti_sm;                                   // diagonal (scaled)
+    double* e = ti_sm + n;                               // sub-diagonal (scaled, signed)
+    double* Vs = ti_sm + 2 * n;                          // packed reflectors, then tau
+    double* taus = Vs + vcol_size(n);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nthr = 64 * waves;
+    double* u0 = ti_sm + 2 * n + tinv_big(n) + (size_t)wave * TI_ARR * n;
+    double* u1 = u0 + n;
+    double* u2 = u1 + n;
+    double* mu = u2 + n;
+    double* sw = mu + n;                                 // 1.0 where rows i, i + 1 swapped
+    double* y = sw + n;
+    const double sc = tb_scale(Hr, n);
+    for (int i = tid; i < n; i += nthr) {
+        d[i] = Hr[(int64_t)i * n + i] * sc;
+        e[i] = i + 1 < n ? Hr[(int64_t)(i + 1) * n + i] * sc : 0.0;
+    }
+    if (n > 2) {
+        for (int k = 0; k + 2 < n; ++k) {
+            const int len = n - k - 1;
+            for (int q = tid; q < len; q += nthr) Vs[vcol_off(k, n) + q] = Vg[(int64_t)k * n + k + 1 + q];
+        }
+        for (int k = tid; k + 2 < n; k += nthr) taus[k] = taug[k];
+    }
+    __syncthreads();
+    const int kv = blockIdx.x * waves + wave;
+    if (kv >= nv) return;
+    const double lam = evals[kv] * sc;
+    const double eps3 = 2.220446049250313e-16 * sqrt(Hr[(int64_t)n * n + 1]) * sc + 1e-300;
+    if (lane == 0) {
+        // factorisation of T - lam I with partial pivoting; rows enter as (cu, cv) = the
+        // entries of the current row at columns i, i + 1
+        double cu = d[0] - lam, cv = n > 1 ? e[0] : 0.0;
+        for (int i = 0; i + 1 < n; ++i) {
+            const double bsub = e[i];                                    // T(i + 1, i)
+            const double an = d[i + 1] - lam, gn = i + 2 < n ? e[i + 1] : 0.0;   // row i + 1 at i + 1, i + 2
+            const bool s = fabs(bsub) > fabs(cu);
+            double p = s ? bsub : cu;
+            p = fabs(p) < eps3 ? (p < 0.0 ? -eps3 : eps3) : p;
+            const double m = (s ? cu : bsub) * rcp_nr(p);
+            u0[i] = p;
+            u1[i] = s ? an : cv;
+            u2[i] = s ? gn : 0.0;
+            mu[i] = m;
+            sw[i] = s ? 1.0 : 0.0;
+            const double ncu = s ? cv - m * an : an - m * cv;
+            const double ncv = s ? -m * gn : gn;
+            cu = ncu;
+            cv = ncv;
+        }
+        u0[n - 1] = fabs(cu) < eps3 ? (cu < 0.0 ? -eps3 : eps3) : cu;
+        for (int i = 0; i < n; ++i) y[i] = ti_start(kv, i);
+        for (int pass = 0; pass < 2; ++pass) {
+            // forward: the row swaps and multipliers on the right-hand side
+            for (int i = 0; i + 1 < n; ++i) {
+                double a = y[i], b = y[i + 1];
+                if (sw[i] != 0.0) { const double t = a; a = b; b = t; }
+                y[i] = a;
+                y[i + 1] = b - mu[i] * a;
+            }
+            // back-substitution with the three bands of U, then unit 2-norm
+            double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+            for (int i = n - 1; i >= 0; --i) {
+                const double xi = (y[i] - u1[i] * x1 - u2[i] * x2) * rcp_nr(u0[i]);
+                y[i] = xi;
+                x2 = x1;
+                x1 = xi;
+                nrm = fma(xi, xi, nrm);
+            }
+            const double inv = nrm > 0.0 ? rsqrt_nr(nrm) : 0.0;
+            for (int i = 0; i < n; ++i) y[i] *= inv;
+        }
+    }
+    wave_sync_lds();
+    double xr[AB_SLOTS];
+#pragma unroll
+    for (int s = 0; s < AB_SLOTS; ++s) {
+        const int i = lane + 64 * s;
+        xr[s] = i < n ? y[i] : 0.0;
+    }
+    // y = Q x with Q = P_0 P_1 .. P_{n-3}
+    if (n > 2) {
+        for (int k = n - 3; k >= 0; --k) {
+            const double* v = Vs + vcol_off(k, n) - (k + 1);
+            double vv[AB_SLOTS];
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) {
+                const int i = lane + 64 * s;
+                vv[s] = (i > k && i < n) ? v[i] : 0.0;
+            }
+            double g = 0.0;
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) g = fma(vv[s], xr[s], g);
+            g = wave_sum(g) * taus[k];
+#pragma unroll
+            for (int s = 0; s < AB_SLOTS; ++s) xr[s] = fma(-g, vv[s], xr[s]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < AB_SLOTS; ++s) {
+        const int row = lane + 64 * s;
+        if (row < n) Vout[(int64_t)kv * ldv + row] = xr[s];
+    }
+}
+
+size_t sym_eig_workspace_bytes(int n) { return ((size_t)2 * n * n + n + 2) * sizeof(double) + 256; }
+
+hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, int nv, double* evals, double* Vout,
+                   int64_t ldv, void* ws, int32_t* info)
+{
+    if (n <= 0) return hipSuccess;
+    if (n > 192 || nv > n) return hipErrorInvalidValue;
+    double* H = (double*)ws;
+    double* V = H + (size_t)n * n + 2;
+    double* tau = V + (size_t)n * n;
+    if (n <= 160) hipLaunchKernelGGL(hessenberg_kernel<5>, dim3(1), dim3(1024), 0, s, S, lds, n, H, V, tau);
+    else hipLaunchKernelGGL(hessenberg_kernel<6>, dim3(1), dim3(1024), 0, s, S, lds, n, H, V, tau);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(tri_bisect_kernel, dim3((unsigned)ceil_div(n, TB_WAVES)), dim3(64 * TB_WAVES),
+                       (size_t)3 * n * sizeof(double), s, n, H, evals, info);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (nv <= 0) return hipSuccess;
+    const int w = tinv_waves(n);
+    hipLaunchKernelGGL(tri_invit_kernel, dim3((unsigned)ceil_div(nv, w)), dim3(64 * w), tinv_lds_bytes(n, w), s, n, nv,
+                       w, H, V, tau, evals, Vout, ldv);
+    return hipGetLastError();
+}
+
 hipError_t nonsym_eig(hipStream_t s, const double* A, int64_t lda, int n, void* ws, double* lam,
                       int32_t* kind, double* W, int32_t* info, double tol)
 {
     if (n <= 0) return hipSuccess;
     if (n > EIG_MAX) return hipErrorInvalidValue;
     EigWs w = eig_carve(ws, n);
-    hipLaunchKernelGGL(hessenberg_kernel, dim3(1), dim3(1024), 0, s, A, lda, n, w.H, w.V, w.tau);
+    hipLaunchKernelGGL(hessenberg_kernel<5>, dim3(1), dim3(1024), 0, s, A, lda, n, w.H, w.V, w.tau);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = fill_i32(s, (int32_t*)w.counter, 1, 0)) != hipSuccess) return e;
@@ -985,6 +1243,8 @@ hipError_t eig_prepare()
 {
     hipError_t e = hipFuncSetAttribute((const void*)aberth_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024 - 256);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute((const void*)tri_invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
     if (e != hipSuccess) return e;
     return hipFuncSetAttribute((const void*)invit_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 256);
 }

@@ -66,11 +66,13 @@ hipError_t exponents(hipStream_t s, const int64_t* k, const double* t, double in
 hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* Rinv, int64_t ldr,
                     float* Rinv32, int64_t ldr32, double shift_scale, int32_t* shifted,
                     int32_t* info, const int32_t* skip_unless, int32_t* run_next = nullptr, int nnext = 0);
-// Jacobi eigen-decomposition of a symmetric n x n matrix: eigenvalues descending,
-// eigenvectors in the columns of Vout (n x n, ld n).
-// rtol: rotate while |a_pq| > rtol sqrt(|a_pp a_qq|) (about 2 ulp for full FP64 accuracy).
-hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* evals, double* Vout,
-                   int32_t* info, double rtol);
+// Symmetric eigen-decomposition (eig.hip): all n eigenvalues of the symmetric n x n
+// matrix S (n <= 192) in descending order, and unit eigenvectors of the nv largest in the
+// columns of Vout (ld ldv).  Eigenvectors of clustered eigenvalues are independent but not
+// orthogonal to working precision.  info[1] receives the bisection rounds.
+size_t sym_eig_workspace_bytes(int n);
+hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, int nv, double* evals, double* Vout,
+                   int64_t ldv, void* ws, int32_t* info);
 // C = alpha op(A) op(B) + beta C, all FP64 column-major, small sizes.
 hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta,

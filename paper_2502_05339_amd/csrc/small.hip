@@ -5,11 +5,6 @@
 //             FP64 MFMA block updates, block column by block column.
 //             Breakdown -> one retry with a diagonal shift (shifted CholeskyQR),
 //             then a status code.
-//  sym_eig    cyclic Jacobi eigen-decomposition of a symmetric matrix with a
-//             round-robin parallel ordering.  Every work-group holds the whole
-//             (packed) matrix in LDS and performs the same rotations; each one
-//             owns a slice of rows of the eigenvector matrix, so rotating the
-//             eigenvectors needs no communication between work-groups.
 //  small_gemm, scale_cols, sigma_from_evals, conversions, amplitudes, check_finite.
 #include "common.h"
 #include "kernels.h"
@@ -286,230 +281,6 @@ hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* 
     return hipSuccess;
 }
 
-// ====================================================================== Jacobi
-__device__ __forceinline__ int up_idx(int i, int j) {   // packed upper, i <= j
-    return j * (j + 1) / 2 + i;
-}
-__device__ __forceinline__ int sym_idx(int i, int j) { return i <= j ? up_idx(i, j) : up_idx(j, i); }
-// Round-robin (circle) schedule on n2 (even) players, m = n2 - 1 rounds: in round t
-// (0 <= t < m), pair 0 is (0, 1 + t) and pair k >= 1 is {1 + (t + k) mod m, 1 + (t - k) mod m}
-// (one conditional add or subtract each, no integer division).
-__device__ __forceinline__ void rr_pair(int k, int t, int m, int* p, int* q) {
-    if (k == 0) { *p = 0; *q = 1 + t; return; }
-    int a = t + k;
-    if (a >= m) a -= m;
-    int b = t - k;
-    if (b < 0) b += m;
-    *p = 1 + min(a, b);
-    *q = 1 + max(a, b);
-}
-
-constexpr int JAC_THREADS = 1024;
-constexpr int JAC_BLK = ((SMALL_MAX / 2) * (SMALL_MAX / 2 + 1) / 2 + JAC_THREADS - 1) / JAC_THREADS;
-constexpr int JAC_VT = ((SMALL_MAX / 2) * 32 + JAC_THREADS - 1) / JAC_THREADS;   // V-update tasks per thread
-
-__global__ void __launch_bounds__(JAC_THREADS)
-jacobi_kernel(const double* __restrict__ S, int64_t lds, int n, int nr, double* evals,
-              double* Vout, int32_t* info, double rtol)
-{
-    extern __shared__ __align__(16) double sm[];
-    const int n2 = n + (n & 1);          // odd n: a zero row and column n complete the pairs
-    const int np = n2 / 2;
-    const int m = n2 - 1;
-    double* A = sm;                                               // n2(n2+1)/2 (rounded to even)
-    double* Vs = A + round_up(n2 * (n2 + 1) / 2, 2);              // nr x n2 (rounded to even)
-    double2* rcs = reinterpret_cast<double2*>(Vs + round_up(nr * n2, 2));   // np: (c, s)
-    double* tn = reinterpret_cast<double*>(rcs + np);             // np
-    int4* rpq = reinterpret_cast<int4*>(tn + round_up(np, 2));    // np: (p, q, p(p+1)/2, q(q+1)/2)
-    int* rank = reinterpret_cast<int*>(rpq + np);                 // n
-    __shared__ int rot_flag;
-    __shared__ double dmax_s;
-
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int r0 = blockIdx.x * nr;
-    const int nrows = min(nr, n - r0);
-
-    for (int e = tid; e < n2 * n2; e += nt) {
-        const int i = e % n2, j = e / n2;
-        if (i <= j) A[up_idx(i, j)] = j < n ? S[(int64_t)j * lds + i] : 0.0;
-    }
-    for (int e = tid; e < nr * n2; e += nt) {
-        const int rl = e / n2, c = e % n2;
-        Vs[e] = (rl < nrows && r0 + rl == c) ? 1.0 : 0.0;
-    }
-    // this thread's pairs of pairs (k1 <= k2), fixed for every round
-    const int nblk = np * (np + 1) / 2;
-    int bk1[JAC_BLK], bk2[JAC_BLK];
-#pragma unroll
-    for (int t = 0; t < JAC_BLK; ++t) {
-        const int b = tid + t * nt;
-        int k2 = (int)((sqrtf(8.0f * (float)b + 1.0f) - 1.0f) * 0.5f);
-        while (k2 * (k2 + 1) / 2 > b) --k2;
-        while ((k2 + 1) * (k2 + 2) / 2 <= b) ++k2;
-        bk2[t] = b < nblk ? k2 : -1;
-        bk1[t] = b - k2 * (k2 + 1) / 2;
-    }
-    // this thread's V-update tasks (row of the slab, pair), fixed for every round
-    int vt_rl[JAC_VT], vt_k[JAC_VT];
-#pragma unroll
-    for (int u = 0; u < JAC_VT; ++u) {
-        const int e = tid + u * nt;
-        vt_rl[u] = e / np;
-        vt_k[u] = e % np;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        double d = 0.0;
-        for (int i = 0; i < n; ++i) d = fmax(d, fabs(A[up_idx(i, i)]));
-        dmax_s = d;
-    }
-    __syncthreads();
-    const double floor_abs = (rtol > 1e-15 ? 1e-3 * rtol : 1e-17) * dmax_s;
-
-    int sweep = 0;
-    bool converged = false;
-    for (; sweep < 40; ++sweep) {
-        if (tid == 0) rot_flag = 0;
-        __syncthreads();
-        for (int t = 0; t < m; ++t) {
-            for (int k = tid; k < np; k += nt) {
-                int p, q;
-                rr_pair(k, t, m, &p, &q);
-                double c = 1.0, s = 0.0, tt = 0.0;
-                const double apq = A[up_idx(p, q)];
-                const double app = A[up_idx(p, p)], aqq = A[up_idx(q, q)];
-                if (fabs(apq) > floor_abs && fabs(apq) > rtol * sqrt(fabs(app) * fabs(aqq))) {
-                    // tan(theta) of the rotation that zeroes a_pq, the smaller root; |tau| stays
-                    // below about 1e17 because |a_pq| > floor_abs
-                    const double tau = (aqq - app) * rcp_nr(2.0 * apq);
-                    const double u = fma(tau, tau, 1.0);
-                    const double root = u * rsqrt_nr(u);                  // sqrt(1 + tau^2)
-                    tt = (tau >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(tau) + root);
-                    c = rsqrt_nr(fma(tt, tt, 1.0));
-                    s = tt * c;
-                    rot_flag = 1;                                         // every writer stores 1
-                }
-                rpq[k] = make_int4(p, q, p * (p + 1) / 2, q * (q + 1) / 2);
-                rcs[k] = make_double2(c, s);
-                tn[k] = tt;
-            }
-            __syncthreads();
-            // 2x2 blocks of every pair of pairs: B' = J1^T B J2 (independent, disjoint entries).
-            // Packed index of (a, b): a <= b ? b(b+1)/2 + a : a(a+1)/2 + b, from the pair records.
-#pragma unroll
-            for (int u = 0; u < JAC_BLK; ++u) {
-                const int k2 = bk2[u];
-                if (k2 < 0) continue;
-                const int k1 = bk1[u];
-                // every record first (one LDS round trip), then the branches
-                const int4 P1 = rpq[k1], P2 = rpq[k2];
-                const double2 cs1 = rcs[k1], cs2 = rcs[k2];
-                if (k1 == k2) {
-                    const double t1 = tn[k1];
-                    if (t1 == 0.0) continue;
-                    const int ipq = P1.w + P1.x;
-                    const double apq = A[ipq];
-                    A[P1.z + P1.x] -= t1 * apq;
-                    A[P1.w + P1.y] += t1 * apq;
-                    A[ipq] = 0.0;
-                    continue;
-                }
-                if (cs1.y == 0.0 && cs2.y == 0.0) continue;            // both rotations skipped
-                const int i00 = P1.x <= P2.x ? P2.z + P1.x : P1.z + P2.x;
-                const int i01 = P1.x <= P2.y ? P2.w + P1.x : P1.z + P2.y;
-                const int i10 = P1.y <= P2.x ? P2.z + P1.y : P1.w + P2.x;
-                const int i11 = P1.y <= P2.y ? P2.w + P1.y : P1.w + P2.y;
-                const double b00 = A[i00], b01 = A[i01], b10 = A[i10], b11 = A[i11];
-                const double c1 = cs1.x, s1 = cs1.y, c2 = cs2.x, s2 = cs2.y;
-                const double x00 = c2 * b00 - s2 * b01, x01 = s2 * b00 + c2 * b01;
-                const double x10 = c2 * b10 - s2 * b11, x11 = s2 * b10 + c2 * b11;
-                A[i00] = c1 * x00 - s1 * x10;
-                A[i01] = c1 * x01 - s1 * x11;
-                A[i10] = s1 * x00 + c1 * x10;
-                A[i11] = s1 * x01 + c1 * x11;
-            }
-            // eigenvector rows owned by this work-group: V <- V J
-#pragma unroll
-            for (int u = 0; u < JAC_VT; ++u) {
-                const int rl = vt_rl[u], k = vt_k[u];
-                if (rl >= nrows) continue;
-                const double2 cs = rcs[k];
-                if (cs.y == 0.0) continue;
-                const int4 pq = rpq[k];
-                double* vr = Vs + rl * n2;
-                const double vp = vr[pq.x], vq = vr[pq.y];
-                vr[pq.x] = cs.x * vp - cs.y * vq;
-                vr[pq.y] = cs.y * vp + cs.x * vq;
-            }
-            __syncthreads();
-        }
-        if (rot_flag == 0) { converged = true; break; }
-        // would the next sweep rotate at all?  The rotation test on A as it stands: a sweep
-        // without rotations changes nothing, so when no pair passes, the sweep that would
-        // only confirm it is counted and skipped
-        __syncthreads();
-        if (tid == 0) rot_flag = 0;
-        __syncthreads();
-        for (int q = 1 + (tid >> 6); q < n2; q += nt >> 6) {
-            const double aqq = A[up_idx(q, q)];
-            for (int p = tid & 63; p < q; p += 64) {
-                const double apq = A[up_idx(p, q)], app = A[up_idx(p, p)];
-                if (fabs(apq) > floor_abs && fabs(apq) > rtol * sqrt(fabs(app) * fabs(aqq))) rot_flag = 1;
-            }
-        }
-        __syncthreads();
-        if (rot_flag == 0) { ++sweep; converged = true; break; }
-        __syncthreads();                       // every thread has read the flag before its reset
-    }
-    // order: descending eigenvalue, ties by index (NaN last); the padding row is not an eigenvalue
-    for (int i = tid; i < n; i += nt) {
-        const double di = A[up_idx(i, i)];
-        const double ki = isnan(di) ? -__builtin_inf() : di;
-        int rk = 0;
-        for (int j = 0; j < n; ++j) {
-            const double dj = A[up_idx(j, j)];
-            const double kj = isnan(dj) ? -__builtin_inf() : dj;
-            if (kj > ki || (kj == ki && j < i)) ++rk;
-        }
-        rank[i] = rk;
-    }
-    __syncthreads();
-    for (int e = tid; e < nrows * n; e += nt) {
-        const int rl = e / n, i = e % n;
-        Vout[(int64_t)rank[i] * n + r0 + rl] = Vs[rl * n2 + i];
-    }
-    if (blockIdx.x == 0) {
-        for (int i = tid; i < n; i += nt) evals[rank[i]] = A[up_idx(i, i)];
-        if (tid == 0 && info) {
-            info[1] += sweep + 1;
-            if (!converged) set_status(info, DMD_ERR_EIG_NOCONV);
-        }
-    }
-}
-
-hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, double* evals, double* Vout,
-                   int32_t* info, double rtol)
-{
-    if (n <= 0) return hipSuccess;
-    if (n > SMALL_MAX) return hipErrorInvalidValue;
-    const int n2 = n + (n & 1), np = n2 / 2;
-    // A (n2 x n2 packed, rounded to even), (c, s), t (rounded to even), pair records
-    // (int4), the ranks; V rows of n2 entries, rounded to even
-    const size_t fixed = (size_t)round_up((int64_t)n2 * (n2 + 1) / 2, 2) * 8 + (size_t)np * 16 +
-                         (size_t)round_up(np, 2) * 8 + (size_t)np * 16 + (size_t)n * 4 + 16;
-    const size_t budget = 160 * 1024 - 1024;   // the kernel's LDS attribute (static LDS is 16 bytes)
-    if (fixed + (size_t)n2 * 8 + 8 > budget) return hipErrorInvalidValue;
-    int nr = (int)((budget - fixed - 8) / ((size_t)n2 * 8));
-    // few eigenvector rows per work-group: every work-group repeats the rotations, so a
-    // thinner slab only shortens each round's V update (more work-groups, idle CUs anyway)
-    if (nr > 8) nr = 8;
-    if (nr > n) nr = n;
-    const int grid = (int)ceil_div(n, nr);
-    const size_t lds_bytes = fixed + (size_t)round_up((int64_t)nr * n2, 2) * 8;
-    hipLaunchKernelGGL(jacobi_kernel, dim3(grid), dim3(JAC_THREADS), lds_bytes, s, S, lds, n, nr, evals, Vout, info,
-                       rtol);
-    return hipGetLastError();
-}
 
 // ====================================================================== helpers
 // C = alpha op(A) op(B) + beta C by 32 x 32 output tiles: 256 threads, each owning a 2 x 2
@@ -774,10 +545,8 @@ hipError_t check_finite(hipStream_t s, int dtype, const void* X, int64_t ld, int
 
 hipError_t small_prepare()
 {
-    hipError_t e = hipFuncSetAttribute((const void*)chol_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024 - 1024);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)jacobi_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 1024);
+    return hipFuncSetAttribute((const void*)chol_inv_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               160 * 1024 - 1024);
 }
 
 }  // namespace dmd
