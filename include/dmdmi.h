@@ -230,6 +230,26 @@ int32_t dmd_reconstruct(void* stream, const dmd_model* model, const int64_t* k_h
                         size_t ws_bytes);
 
 /*
+ * dmd_reconstruct with no workspace argument and no allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, layout and result as dmd_reconstruct; the
+ * exponents and packed coefficients go to a library-owned device array of
+ * DMD_NOALLOC_SCRATCH_BYTES per GPU, held from the first call (or library set-up) on
+ * that GPU until the process ends.  A call needs dmd_reconstruct_workspace_size(r, K,
+ * mode) bytes of it (with r = 160: about 6,400 frames in DMD_RECON_FP64, 12,800 in
+ * DMD_RECON_BF16X3); a larger request returns DMD_ERR_WORKSPACE before any device work.
+ * Every call on one GPU uses the same array and leaves its contents there: calls that
+ * overlap on one GPU (other streams, other host threads) race and must be serialised by
+ * the caller.  status: NULL, or a device int32 that receives the coefficient pass's
+ * status bits (bit 0: a power of lambda = 0 outside its domain, DMD_ERR_DOMAIN; bit 1: a
+ * term beyond the output type's range, DMD_ERR_OVERFLOW), stream-ordered.  Calls no
+ * hipMalloc, hipFree or allocating library routine.
+ */
+#define DMD_NOALLOC_SCRATCH_BYTES ((size_t)8 << 20)
+int32_t dmd_reconstruct_noalloc(void* stream, const dmd_model* model, const int64_t* k_host,
+                                int32_t K, int32_t mode, void* U, int64_t ldu, int32_t* status);
+
+/*
  * The two halves of dmd_reconstruct, for callers that evaluate one exponent list
  * many times (the coefficients depend only on lambda, b and the exponents):
  *   prepare: exponents (k_host integers, or t_host / dt when k_host is NULL) and the

@@ -34,6 +34,7 @@ INFO_WORDS = 8
 MAX_SMALL = 192
 MAX_SKETCH = 160
 MAX_RANK = 160
+NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class FitOpts(ctypes.Structure):
@@ -70,6 +71,8 @@ _SIGS = {
     "dmd_reconstruct_workspace_size": (c_int32, [c_int32, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
     "dmd_reconstruct": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_int64), c_int32,
                                   c_int32, c_void_p, c_int64, c_void_p, c_size_t]),
+    "dmd_reconstruct_noalloc": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_int64), c_int32,
+                                          c_int32, c_void_p, c_int64, c_void_p]),
     "dmd_reconstruct_prepare": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_int64),
                                           ctypes.POINTER(c_double), c_int32, c_int32, c_void_p, c_size_t]),
     "dmd_reconstruct_apply": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_int32, c_int32, c_void_p, c_int64,

@@ -49,6 +49,7 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 std::once_flag g_init_once;
 hipError_t g_init_error = hipSuccess;
 void lib_init();
+hipError_t scratch_address(void** out);
 // one-time set-up (kernel LDS limits, autotune cache); its failure fails every call
 static int32_t ensure_init()
 {
@@ -565,6 +566,10 @@ void lib_init()
 {
     (void)device_cu_count();
     g_init_error = prepare_kernels();
+    if (g_init_error == hipSuccess) {
+        void* p = nullptr;
+        g_init_error = scratch_address(&p);
+    }
     const char* c = getenv("DMDMI_AUTOTUNE_CACHE");
     if (c && *c) load_cache(c);
 }
@@ -634,6 +639,34 @@ int32_t recon_enqueue(hipStream_t st, const dmd_model* m, const int64_t* k_host,
     if (!U || ldu < m->n) return DMD_ERR_ARG;
     if (int32_t e = recon_prepare(st, m, k_host, t_host, K, mode, ws, ws_bytes)) return e;
     return recon_apply(st, m, K, mode, U, ldu, ws, ws_bytes, cfg_override);
+}
+
+// ---------------------------------------------------------------- allocation-free reconstruction
+// The workspace of dmd_reconstruct_noalloc: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  In host code `scratch`
+// names a host-side stand-in, so the array is reached only through the device address
+// hipGetSymbolAddress gives for each device, taken once per device (at set-up for the
+// device current then, else at the first call on a device) and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[DMD_NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES] = {};
+
+hipError_t scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 // ---- forced roll-out workspace
@@ -831,6 +864,27 @@ int32_t dmd_reconstruct(void* stream, const dmd_model* model, const int64_t* k_h
 {
     if (!k_host) return DMD_ERR_ARG;
     return recon_enqueue((hipStream_t)stream, model, k_host, nullptr, K, mode, U, ldu, ws, ws_bytes, -1);
+}
+
+int32_t dmd_reconstruct_noalloc(void* stream, const dmd_model* model, const int64_t* k_host, int32_t K, int32_t mode,
+                                void* U, int64_t ldu, int32_t* status)
+{
+    if (!k_host) return DMD_ERR_ARG;
+    if (int32_t e = validate_model(model)) return e;
+    if (K < 1) return DMD_ERR_SHAPE;
+    if (mode < DMD_RECON_FP64 || mode > DMD_RECON_BF16X3) return DMD_ERR_ARG;
+    Carver dry(nullptr);
+    recon_carve(dry, model->r, K, mode);
+    if (dry.bytes() > DMD_NOALLOC_SCRATCH_BYTES) return DMD_ERR_WORKSPACE;
+    if (int32_t e0 = ensure_init()) return e0;
+    void* ws = nullptr;
+    HIPCHK(scratch_address(&ws));
+    hipStream_t st = (hipStream_t)stream;
+    if (int32_t e = recon_enqueue(st, model, k_host, nullptr, K, mode, U, ldu, ws, DMD_NOALLOC_SCRATCH_BYTES, -1))
+        return e;
+    // the status word sits at the start of the scratch (as at the start of a workspace)
+    if (status) HIPCHK(hipMemcpyAsync(status, ws, sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    return DMD_OK;
 }
 
 int32_t dmd_reconstruct_prepare(void* stream, const dmd_model* model, const int64_t* k_host, const double* t_host,
