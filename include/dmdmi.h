@@ -423,6 +423,31 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam,
                       int32_t ncols, double* out, void* ws, size_t ws_bytes);
 
 /*
+ * Refit statistics: the loss and adjoint of dmd_loss_grad for many (lambda, b) with the
+ * same modes and target frames.  With the modes fixed the loss needs the frames only
+ * through G0 = Phi_f^T X (r x ncols), M = Phi_f^T Phi_f (r x r) and ||X||^2 (folded real
+ * modes Phi_f, FP64 sums of the model's data); with the folded FP64 coefficients C of
+ * (lambda, b),  G_f = G0 - M C = Phi_f^T R  and  L = ||X||^2 - <C, G0 + G_f>, so each
+ * evaluation is O(r^2 ncols) and the residual R is never formed (the objective of Sec. 4.2
+ * with the modes fixed, as in dmd_loss_grad).
+ *   dmd_refit_prepare:   reads xt (N x ncols, ldxt >= N, model dtype) and the exponents
+ *                        k_host once, stores the statistics in the workspace;
+ *   dmd_refit_loss_grad: out (device, 1 + 4r doubles, the layout of dmd_loss_grad) for
+ *                        lam, b (device, r complex each), from a workspace prepared with
+ *                        the same model and ncols (nothing is checked across the calls).
+ * Both are asynchronous.  The loss loses accuracy by cancellation when it is far below
+ * ||X||^2 (relative error about 1e-16 ||X||^2 / L).  Limits as dmd_loss_grad
+ * (r * ncols <= 102400).  Domain and overflow of lambda^k are recorded in the workspace's
+ * status word (dmd_status_word).
+ */
+int32_t dmd_refit_workspace_size(int64_t n, int32_t r, int32_t ncols, size_t* bytes);
+int32_t dmd_refit_prepare(void* stream, const dmd_model* model, const void* xt, int64_t ldxt,
+                          const int64_t* k_host, int32_t ncols, void* ws, size_t ws_bytes);
+int32_t dmd_refit_loss_grad(void* stream, const dmd_model* model, const double* lam,
+                            const double* b, int32_t ncols, double* out, void* ws,
+                            size_t ws_bytes);
+
+/*
  * Fit several independent scenes.  Each scene's fit runs on its own forked
  * stream (default priority) joined back into `stream`, so the latency-bound
  * small-matrix stages of different scenes overlap.  With capture != 0 the batch

@@ -73,6 +73,11 @@ _SIGS = {
                                   c_int32, c_void_p, c_int64, c_void_p, c_size_t]),
     "dmd_reconstruct_noalloc": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_int64), c_int32,
                                           c_int32, c_void_p, c_int64, c_void_p]),
+    "dmd_refit_workspace_size": (c_int32, [c_int64, c_int32, c_int32, ctypes.POINTER(c_size_t)]),
+    "dmd_refit_prepare": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_void_p, c_int64, ctypes.POINTER(c_int64),
+                                    c_int32, c_void_p, c_size_t]),
+    "dmd_refit_loss_grad": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_void_p, c_void_p, c_int32, c_void_p,
+                                      c_void_p, c_size_t]),
     "dmd_reconstruct_prepare": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.POINTER(c_int64),
                                           ctypes.POINTER(c_double), c_int32, c_int32, c_void_p, c_size_t]),
     "dmd_reconstruct_apply": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), c_int32, c_int32, c_void_p, c_int64,

@@ -578,20 +578,75 @@ class DMDLoss(torch.autograd.Function):
         return g * gl, g * gb, None, None, None
 
 
-def refit(model: Model, X: torch.Tensor, ks, steps: int = 200, lr: float = 1e-3, optimizer: str = "adam"):
+class RefitStats:
+    """The statistics G0 = Phi_f^T X, M = Phi_f^T Phi_f and ||X||^2 of the target frames
+    (dmd_refit_prepare), from which dmd_refit_loss_grad gives the loss and adjoint of
+    loss_grad for any (lambda, b) without touching X again."""
+
+    def __init__(self, model: Model, X: torch.Tensor, ks):
+        _require_gpu(X, "X")
+        if X.dtype != model.phi.dtype or X.stride(1) != 1 or X.shape[1] != model.n:
+            raise ValueError("X must be (ncols, N) of the model's dtype with unit stride along N")
+        k = np.ascontiguousarray(np.asarray(ks, dtype=np.int64).ravel())
+        if k.size != X.shape[0]:
+            raise ValueError("one exponent per target frame")
+        L = _lib.lib()
+        nb = ctypes.c_size_t(0)
+        check(L.dmd_refit_workspace_size(model.n, model.r, k.size, ctypes.byref(nb)), "dmd_refit_workspace_size")
+        self.ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=X.device)
+        self.model = model
+        self.ncols = int(k.size)
+        self.ms = model.struct()
+        check(L.dmd_refit_prepare(_stream(), ctypes.byref(self.ms), X.data_ptr(), X.stride(0),
+                                  k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k.size, self.ws.data_ptr(),
+                                  self.ws.numel()), "dmd_refit_prepare")
+
+    def loss_grad(self, lam: torch.Tensor, b: torch.Tensor):
+        """(loss, grad_lambda, grad_b) as loss_grad returns them (device tensors)."""
+        lam = lam.detach().to(torch.complex128).contiguous()
+        b = b.detach().to(torch.complex128).contiguous()
+        r = self.model.r
+        out = torch.empty(1 + 4 * r, dtype=torch.float64, device=self.ws.device)
+        check(_lib.lib().dmd_refit_loss_grad(_stream(), ctypes.byref(self.ms), lam.data_ptr(), b.data_ptr(), self.ncols,
+                                             out.data_ptr(), self.ws.data_ptr(), self.ws.numel()),
+              "dmd_refit_loss_grad")
+        gl = torch.view_as_complex(out[1:1 + 2 * r].clone().view(r, 2))
+        gb = torch.view_as_complex(out[1 + 2 * r:].clone().view(r, 2))
+        return out[0], gl, gb
+
+
+class DMDLossStats(torch.autograd.Function):
+    """DMDLoss evaluated from RefitStats (the same loss and hand-written adjoint)."""
+
+    @staticmethod
+    def forward(ctx, lam, b, stats: RefitStats):
+        loss, gl, gb = stats.loss_grad(lam, b)
+        ctx.save_for_backward(gl, gb)
+        return loss.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        gl, gb = ctx.saved_tensors
+        return g * gl, g * gb, None
+
+
+def refit(model: Model, X: torch.Tensor, ks, steps: int = 200, lr: float = 1e-3, optimizer: str = "adam",
+          stats: bool = True):
     """Refit lambda and b by gradient steps on the full-space loss (modes fixed).
 
     A noise-robust refit in the spirit of OptDMD (Sec. 4.2): every snapshot of the
-    horizon enters the loss at once.  Returns (lam, b, losses) and leaves the model
-    unchanged.
+    horizon enters the loss at once.  With stats=True the frames are read once
+    (RefitStats) and every step is O(r^2 ncols); stats=False evaluates DMDLoss on the
+    frames at every step.  Returns (lam, b, losses) and leaves the model unchanged.
     """
     lam = model.lam.clone().requires_grad_(True)
     b = model.b.clone().requires_grad_(True)
     opt = torch.optim.Adam([lam, b], lr=lr) if optimizer == "adam" else torch.optim.SGD([lam, b], lr=lr)
+    rs = RefitStats(model, X, ks) if stats else None
     losses = []
     for _ in range(steps):
         opt.zero_grad(set_to_none=True)
-        loss = DMDLoss.apply(lam, b, model, X, ks)
+        loss = DMDLossStats.apply(lam, b, rs) if stats else DMDLoss.apply(lam, b, model, X, ks)
         loss.backward()
         opt.step()
         losses.append(loss.detach())

@@ -1141,6 +1141,100 @@ int32_t dmd_loss_grad(void* stream, const dmd_model* model, const double* lam, c
     return DMD_OK;
 }
 
+// ---------------------------------------------------------------- refit statistics
+struct RefitPlan {
+    int32_t* status;
+    int64_t* kdev;
+    double* expo;
+    double* G0;     // Phi_f^T X (r x ncols)
+    double* M;      // Phi_f^T Phi_f (r x r)
+    double* xxp;    // ||X||^2 partials
+    double* P;      // split partials of the two products
+    double* C;      // folded FP64 coefficients (r x ncols)
+    double* Gf;     // Phi_f^T R (r x ncols)
+    double* loss;
+};
+
+static RefitPlan refit_carve(Carver& cv, int64_t n, int r, int ncols)
+{
+    RefitPlan p;
+    p.status = cv.take<int32_t>(64);
+    p.kdev = cv.take<int64_t>((size_t)ncols);
+    p.expo = cv.take<double>((size_t)ncols);
+    p.G0 = cv.take<double>((size_t)r * ncols);
+    p.M = cv.take<double>((size_t)r * r);
+    p.xxp = cv.take<double>(SQ_MAX_PARTS);
+    p.P = cv.take<double>((size_t)tn_max_splits(n) * std::max<int64_t>((int64_t)r * ncols, (int64_t)r * r));
+    p.C = cv.take<double>((size_t)r * ncols);
+    p.Gf = cv.take<double>((size_t)r * ncols);
+    p.loss = cv.take<double>(8);
+    return p;
+}
+
+int32_t dmd_refit_workspace_size(int64_t n, int32_t r, int32_t ncols, size_t* bytes)
+{
+    if (!bytes) return DMD_ERR_ARG;
+    if (n < 1 || r < 1 || ncols < 1) return DMD_ERR_SHAPE;
+    Carver c(nullptr);
+    refit_carve(c, n, r, ncols);
+    *bytes = c.bytes();
+    return DMD_OK;
+}
+
+int32_t dmd_refit_prepare(void* stream, const dmd_model* model, const void* xt, int64_t ldxt, const int64_t* k_host,
+                          int32_t ncols, void* ws, size_t ws_bytes)
+{
+    if (int32_t e = validate_model(model)) return e;
+    if (!xt || !k_host) return DMD_ERR_ARG;
+    if (ncols < 1) return DMD_ERR_SHAPE;
+    if (ldxt < model->n) return DMD_ERR_ARG;
+    if ((int64_t)model->r * ncols > TN_MAX_OUT) return DMD_ERR_UNSUPPORTED;
+    size_t need = 0;
+    dmd_refit_workspace_size(model->n, model->r, ncols, &need);
+    if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    if (int32_t e0 = ensure_init()) return e0;
+    hipStream_t st = (hipStream_t)stream;
+    const int r = model->r;
+    const int64_t n = model->n;
+    Carver cv(ws);
+    RefitPlan p = refit_carve(cv, n, r, ncols);
+    HIPCHK(hipMemcpyAsync(p.kdev, k_host, (size_t)ncols * sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIPCHK(exponents(st, p.kdev, nullptr, 1.0, ncols, p.expo));
+    // G0 = Phi_f^T X and M = Phi_f^T Phi_f with FP64 sums (FP64 MFMA on the model's data)
+    HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, xt, ldxt, 0, ncols, 0, n, p.P, p.G0, r,
+                   nullptr, 0, nullptr));
+    HIPCHK(gemm_tn(st, model->dtype, DMD_F64, model->phi, model->ldphi, 1, r, model->phi, model->ldphi, 1, r, 1, n, p.P,
+                   p.M, r, nullptr, 0, nullptr));
+    int nparts = 0;
+    HIPCHK(sumsq(st, model->dtype, xt, ldxt, n, ncols, p.xxp, &nparts));
+    return DMD_OK;
+}
+
+int32_t dmd_refit_loss_grad(void* stream, const dmd_model* model, const double* lam, const double* b, int32_t ncols,
+                            double* out, void* ws, size_t ws_bytes)
+{
+    if (int32_t e = validate_model(model)) return e;
+    if (!lam || !b || !out) return DMD_ERR_ARG;
+    if (ncols < 1) return DMD_ERR_SHAPE;
+    if ((int64_t)model->r * ncols > TN_MAX_OUT) return DMD_ERR_UNSUPPORTED;
+    size_t need = 0;
+    dmd_refit_workspace_size(model->n, model->r, ncols, &need);
+    if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    if (int32_t e0 = ensure_init()) return e0;
+    hipStream_t st = (hipStream_t)stream;
+    const int r = model->r;
+    Carver cv(ws);
+    RefitPlan p = refit_carve(cv, model->n, r, ncols);
+    HIPCHK(fill_i32(st, p.status, 1, 0));
+    HIPCHK(powers_pack(st, lam, b, model->kind, r, p.expo, ncols, ncols, r, DMD_RECON_FP64, p.C, nullptr, p.status));
+    // G_f = G0 - M C, L = ||X||^2 - <C, G0 + G_f>
+    HIPCHK(copy_f64(st, r, ncols, ncols, p.G0, r, p.Gf, r));
+    HIPCHK(small_gemm(st, 0, 0, r, ncols, r, -1.0, p.M, r, p.C, r, 1.0, p.Gf, r));
+    HIPCHK(refit_loss(st, r, ncols, p.C, p.G0, p.Gf, p.xxp, sumsq_parts(model->n), p.loss));
+    HIPCHK(grad_reduce(st, r, ncols, p.Gf, lam, b, model->kind, p.expo, p.loss, 1, out));
+    return DMD_OK;
+}
+
 int32_t dmd_status_word(void* stream, const void* ws, int32_t* status)
 {
     if (!ws || !status) return DMD_ERR_ARG;

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "dmdmi.h"
 
 namespace dmd {
@@ -141,6 +143,15 @@ hipError_t vp_lift(hipStream_t s, int r, const int32_t* kind, const double* thet
                    double* b, double* scale);
 
 // ---- adjoint (adjoint.hip)
+// Refit statistics (adjoint.hip): FP64 sum of squares of an N x ncols matrix as at most
+// SQ_MAX_PARTS partials (*nparts of them), and loss[0] = sum(xxp) - <C, G0 + Gf>.
+constexpr int SQ_MAX_PARTS = 512;
+inline int64_t sumsq_rows_per(int64_t N) { return std::max<int64_t>((N + SQ_MAX_PARTS - 1) / SQ_MAX_PARTS, 1024); }
+inline int sumsq_parts(int64_t N) { return (int)((N + sumsq_rows_per(N) - 1) / sumsq_rows_per(N)); }
+hipError_t sumsq(hipStream_t s, int dtype, const void* X, int64_t ld, int64_t N, int ncols, double* partial,
+                 int* nparts);
+hipError_t refit_loss(hipStream_t s, int r, int ncols, const double* C, const double* G0, const double* Gf,
+                      const double* xxp, int nxx, double* loss);
 hipError_t grad_reduce(hipStream_t s, int r, int ncols, const double* G, const double* lam,
                        const double* b, const int32_t* kind, const double* expo,
                        const double* ss_partial, int nss, double* out);

@@ -173,3 +173,81 @@ def test_finite_differences_fp64(gpu_lib):
                 fd = (Lp - Ln) / (2 * h)
                 an = gvec[i].real if unit == 1.0 else gvec[i].imag
                 assert abs(fd - an) <= 1e-5 * max(1.0, abs(an)), (which, i, unit, fd, an)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_refit_stats_match_closed_form(gpu_lib, dtype):
+    """Loss and gradients from the refit statistics (G0 = Phi_f^T X, M = Phi_f^T Phi_f,
+    ||X||^2 in FP64 sums, no residual formed) against the oracle's closed form on the same
+    data.  The statistics keep FP64 accuracy on FP32 models; what remains is the
+    cancellation of L = ||X||^2 - <C, G0 + G_f>, bounded by 1e-13 ||X||^2."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.config("c1-cf", seed=103)
+    _print(f"case: refit statistics c1-cf {dtype}")
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    m = model_from_oracle(f, dtype)
+    lam, b = _perturbed(f, np.random.default_rng(1), 1e-2)
+    ks = np.arange(cfg.m)[::-1].copy()
+    X = torch.from_numpy(np.ascontiguousarray(g.Z.T[::-1])).to(dtype).cuda()
+    stats = dmd.RefitStats(m, X, ks)
+    L, gl, gb = stats.loss_grad(torch.from_numpy(lam).cuda(), torch.from_numpy(b).cuda())
+    Xo = X.double().cpu().numpy().T
+    Lo, glo, gbo = oracle.loss_grad(m.complex_modes(), lam, b, Xo, ks)
+    xx = float(np.sum(Xo * Xo))
+    _print(f"  loss {L.item():.9e} vs {Lo:.9e} (||X||^2 {xx:.3e})")
+    assert abs(L.item() - Lo) <= 1e-13 * xx + 1e-10 * abs(Lo)
+    e_l = _elemerr(gl.cpu().numpy(), glo, 1e-6)
+    e_b = _elemerr(gb.cpu().numpy(), gbo, 1e-6)
+    _print(f"  element-wise grad_lambda {e_l:.2e}, grad_b {e_b:.2e}")
+    assert e_l <= 1e-8 and e_b <= 1e-8
+
+
+def test_refit_stats_c4_shape(gpu_lib):
+    """c4 shape (N = 131072, 200 frames, FP32 model, strided targets): the statistics path
+    against the oracle and against the residual path (FP32 GEMMs, 1e-4)."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.config("c4")
+    _print("case: refit statistics c4 shape fp32")
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z.astype(np.float64), cfg.r)
+    m = model_from_oracle(f, torch.float32)
+    lam, b = _perturbed(f, np.random.default_rng(2), 1e-4)
+    ks = np.arange(cfg.m)
+    big = torch.zeros((cfg.m, cfg.N + 64), dtype=torch.float32, device="cuda")
+    big[:, : cfg.N] = torch.from_numpy(np.ascontiguousarray(g.Z.T))
+    X = big[:, : cfg.N]
+    t = lambda a: torch.from_numpy(a).cuda()
+    L, gl, gb = dmd.RefitStats(m, X, ks).loss_grad(t(lam), t(b))
+    L1, gl1, gb1 = dmd.loss_grad(m, t(lam), t(b), X, ks)
+    Lo, glo, gbo = oracle.loss_grad(m.complex_modes(np.arange(cfg.N)), lam, b, g.Z.astype(np.float64), ks)
+    _print(f"  loss stats {L.item():.9e} residual path {L1.item():.9e} oracle {Lo:.9e}")
+    assert abs(L.item() - Lo) <= 1e-9 * abs(Lo)
+    e_l = _elemerr(gl.cpu().numpy(), glo, 1e-4)
+    e_b = _elemerr(gb.cpu().numpy(), gbo, 1e-4)
+    _print(f"  element-wise vs oracle grad_lambda {e_l:.2e}, grad_b {e_b:.2e}; residual path vs stats "
+           f"{_relerr(gl1.cpu().numpy(), gl.cpu().numpy()):.2e}")
+    assert e_l <= 1e-7 and e_b <= 1e-7
+    assert abs(L1.item() - L.item()) <= 1e-4 * abs(L.item())
+
+
+def test_refit_with_and_without_stats(gpu_lib):
+    """refit() from the statistics follows the same trajectory as refit() that evaluates
+    the residual every step (FP64 model: the losses agree to 1e-8)."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.config("c1-cf", seed=104)
+    _print("case: refit with and without statistics")
+    g = synth.generate(cfg)
+    f = oracle.fit_exact(g.Z, cfg.r)
+    m = model_from_oracle(f, torch.float64)
+    lam0, b0 = _perturbed(f, np.random.default_rng(3), 1e-3)
+    m.lam.copy_(torch.from_numpy(lam0))
+    m.b.copy_(torch.from_numpy(b0))
+    ks = np.arange(cfg.m)
+    X = torch.from_numpy(np.ascontiguousarray(g.Z.T)).cuda()
+    _, _, l_stats = dmd.refit(m, X, ks, steps=40, lr=2e-4, stats=True)
+    _, _, l_res = dmd.refit(m, X, ks, steps=40, lr=2e-4, stats=False)
+    rel = np.max(np.abs(l_stats - l_res) / np.abs(l_res))
+    _print(f"  loss {l_stats[0]:.4e} -> {l_stats[-1]:.4e}; largest relative difference of the two paths {rel:.2e}")
+    assert rel <= 1e-8
+    assert l_stats[-1] < 0.5 * l_stats[0]

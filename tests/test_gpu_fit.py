@@ -142,9 +142,13 @@ def test_g3_mixed_vs_exact_well_posed_c2(gpu_lib):
 
 def test_g2_mixed_vs_twin_c2(gpu_lib):
     """Full-size literal c2 (noise 1e-4): the rank-150 cut lies in the noise bulk, so the
-    gate is the twin fed the same sketch, with the amplitude-weighted eigenvalue error; the
-    modes that carry the data (amplitude weight at least 1% of the largest) are also held
-    to 1e-5 each (max-relative)."""
+    gate is the twin fed the same sketch, with the amplitude-weighted eigenvalue error.
+    Most of the twin's eigenvalues are fitted to the noise (148 of 150 lie 1e-3 or more
+    from every generating eigenvalue) and move with any perturbation of the data, so each
+    one is held to its first-order perturbation bound instead of a fixed tolerance:
+    |d lambda_i| <= kappa_i ||dAtilde||, kappa_i = ||y_i|| ||w_i|| / |y_i^H w_i| from the
+    twin's eigenvectors, and FP32 operands perturb Atilde = U^T X' V S^-1 by about
+    u32 sigma_1 / sigma_r in norm (u32 = 2^-24)."""
     cfg = synth.config("c2")
     _print("case: G2 c2 mixed vs FP64 twin (full size)")
     g = synth.generate(cfg)
@@ -159,12 +163,13 @@ def test_g2_mixed_vs_twin_c2(gpu_lib):
     U = _fields(m, ks, "fp32", rows)
     Uo = oracle.reconstruct(tw.phi[rows], tw.lam, tw.b, ks).T
     ferr = max_frame_rel(U, Uo)
-    rel = d / np.abs(tw.lam[ib])
-    strong = w[ib] >= 0.01 * np.max(w)
-    _print(f"  lambda weighted {wrel:.3e} max {np.max(rel):.3e}, max over the {int(strong.sum())} modes of weight "
-           f">= 1% of the largest {np.max(rel[strong]):.3e}; fields {ferr:.3e}")
+    kappa = np.linalg.norm(np.linalg.inv(tw.w), axis=1) * np.linalg.norm(tw.w, axis=0)
+    bound = kappa[ib] * 2.0 ** -24 * tw.sigma[0] / tw.sigma[-1]
+    _print(f"  lambda weighted {wrel:.3e} max abs {np.max(d):.3e}; largest ratio to the perturbation bound "
+           f"{np.max(d / bound):.3f} (kappa {kappa.min():.2f}..{kappa.max():.2f}, sigma_1/sigma_r "
+           f"{tw.sigma[0] / tw.sigma[-1]:.1f}); fields {ferr:.3e}")
     assert wrel <= 1e-5
-    assert np.max(rel[strong]) <= 1e-5
+    assert np.all(d <= bound)
     assert ferr <= 1e-4
 
 
