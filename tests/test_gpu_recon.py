@@ -190,3 +190,38 @@ def test_reconstruct_deterministic(gpu_lib):
     a = m.reconstruct(np.arange(300), "bf16x3").clone()
     c = m.reconstruct(np.arange(300), "bf16x3")
     assert torch.equal(a, c)
+
+
+@pytest.mark.parametrize("N,nc,K", [(8192 + 37, 11, 37), (130, 16, 130), (5000, 75, 70)])
+def test_every_bf16_tile_candidate(gpu_lib, tmp_path, N, nc, K):
+    """Every tile candidate of the BF16 modes (forced through the tuning-cache loader) on
+    ragged shapes: N not a multiple of any row tile, K not a multiple of any frame chunk,
+    ranks 22, 32 and 150 (one to ten 16-mode groups)."""
+    from paper_2502_05339_amd import Model, _lib
+    import paper_2502_05339_amd as dmd
+    _print(f"case: every BF16 tile candidate N={N} nc={nc} K={K}")
+    rng = np.random.default_rng(N + 3 * nc)
+    phi = synth.orthonormal_modes(rng, N, nc)
+    lam = synth.draw_eigs(rng, nc, 0.9)
+    b = synth.draw_amplitudes(rng, nc)
+    ks = rng.integers(-20, 200, size=K)
+    m = Model.from_pairs(phi, lam, b, dtype=torch.float32)
+    Uo = oracle.reconstruct(m.complex_modes(), m.lam_host(), m.b_host(), ks).T
+    rp = int(_lib.lib().dmd_phi_ld(2 * nc))
+    key = f"{rp} {int(N).bit_length() - 1} {int(K).bit_length() - 1}"
+    L = _lib.lib()
+    try:
+        for mode in ("bf16x3", "bf16"):
+            mc = dmd.api.RECON_MODES[mode]
+            for cfg in range(6):
+                path = tmp_path / f"tune_{mode}_{cfg}.txt"
+                path.write_text(f"{mc} {key} {cfg} 0.0\n")
+                assert L.dmd_autotune_load(str(path).encode()) == 0
+                err = max_frame_rel(m.reconstruct(ks, mode).cpu().numpy(), Uo)
+                _print(f"  {mode} candidate {cfg}: err {err:.3e}")
+                assert err <= TOL[mode]
+    finally:
+        # back to the default candidate for this shape class
+        path = tmp_path / "tune_default.txt"
+        path.write_text("".join(f"{dmd.api.RECON_MODES[md]} {key} 0 0.0\n" for md in ("bf16x3", "bf16")))
+        L.dmd_autotune_load(str(path).encode())
