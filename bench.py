@@ -93,6 +93,28 @@ def cpu_baseline(g, cfg, rows_sample=65536):
     oracle.loss_grad(tw.phi[rows], tw.lam, tw.b, Zd[rows], np.arange(cfg.m))
     t_adj = (time.perf_counter() - t0) * cfg.N / rows_sample
     t_step = t_fit + t_rec + t_adj
+    # the same step on one host thread: one twin fit, reconstruction and loss+gradient on
+    # a smaller row sample, scaled to N
+    single = None
+    try:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oracle.fit_randomized(Zd, cfg.r, g.Omega.astype(np.float64), cfg.q)
+            t_fit1 = time.perf_counter() - t0
+            rows1 = rows[: rows_sample // 8]
+            t0 = time.perf_counter()
+            oracle.reconstruct(tw.phi[rows1], tw.lam, tw.b, ks)
+            t_rec1 = (time.perf_counter() - t0) * cfg.N / rows1.size
+            t0 = time.perf_counter()
+            oracle.loss_grad(tw.phi[rows1], tw.lam, tw.b, Zd[rows1], np.arange(cfg.m))
+            t_adj1 = (time.perf_counter() - t0) * cfg.N / rows1.size
+        single = {"value": round(cfg.K / (t_fit1 + t_rec1 + t_adj1), 3), "unit": "frames/s", "cores": 1,
+                  "sample": (f"the same step on one host thread: twin fit {t_fit1:.2f} s, reconstruction "
+                             f"{t_rec1:.2f} s and loss+gradient {t_adj1:.2f} s (the latter two on {rows1.size} rows, "
+                             f"scaled to N)")}
+    except ImportError:
+        pass
     return tw, rows, Us, {
         "value": round(cfg.K / t_step, 3),
         "unit": "frames/s",
@@ -103,6 +125,7 @@ def cpu_baseline(g, cfg, rows_sample=65536):
                    f"loss+gradient over {cfg.m} frames ({t_adj:.2f} s), the latter two measured on "
                    f"{rows_sample} of {cfg.N} rows and scaled linearly to N"),
         "fit_s": round(t_fit, 3),
+        "single_thread": single,
     }
 
 

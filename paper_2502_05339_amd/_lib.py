@@ -6,7 +6,8 @@ import os
 import threading
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdmdmi.so")
+# DMDMI_LIBRARY selects another build of the same library (the host-sanitized one in tests)
+LIB_PATH = os.environ.get("DMDMI_LIBRARY") or os.path.join(HERE, "libdmdmi.so")
 
 c_int32, c_int64, c_double, c_void_p, c_size_t = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                                   ctypes.c_void_p, ctypes.c_size_t)

@@ -218,7 +218,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
         Wtf = cv.take<char>((size_t)mm * l * esize(fdt));
         if (shifted) {
             Bx = cv.take<double>((size_t)l * (mm + 1));
-            Bp = Bx + l;
+            Bp = Bx ? Bx + l : nullptr;          // a size query carves from a null base
         } else {
             Bx = cv.take<double>((size_t)l * mm);
             Bp = cv.take<double>((size_t)l * mm);
