@@ -86,8 +86,13 @@ typedef enum dmd_fit_precision {
     DMD_FIT_MIXED = 0,
     /* The same randomized algorithm entirely in FP64 (the plain path). X is FP64. */
     DMD_FIT_FP64_RANDOMIZED = 1,
-    /* Exact thin SVD of X (no sketch) through the FP64 Gram of the snapshots
-     * (method of snapshots).  X is FP64; m-1 <= DMD_MAX_SMALL. */
+    /* Exact thin SVD of X (no sketch; Sec. 3.1), X FP64, m-1 <= DMD_MAX_SMALL.  For
+     * m-1 <= DMD_EXACT_QR_MAX through a triangular factor: Q R = [X X'] by shifted
+     * CholeskyQR in FP64, then the singular values and right vectors of R from the
+     * symmetric eigen-decomposition of [[0, R], [R^T, 0]] (relative accuracy u kappa for
+     * the small singular values; the workspace holds an N x m FP64 copy of the snapshots).
+     * Above it, through the FP64 Gram of the snapshots (method of snapshots), which
+     * squares the condition number. */
     DMD_FIT_FP64_EXACT = 2
 } dmd_fit_precision;
 
@@ -102,6 +107,8 @@ typedef enum dmd_recon_mode {
 /* Limits of the single-workgroup FP64 kernels (packed matrices held in LDS).  A fit
  * beyond them returns DMD_ERR_UNSUPPORTED. */
 #define DMD_MAX_SMALL 192   /* m-1 for DMD_FIT_FP64_EXACT (symmetric eigen-solver) */
+#define DMD_EXACT_QR_MAX 96 /* m-1 up to which DMD_FIT_FP64_EXACT takes the triangular-factor
+                               route (the symmetric solver takes 2(m-1) <= DMD_MAX_SMALL) */
 #define DMD_MAX_SKETCH 160  /* l = r + p on the randomized paths (Cholesky of the l x l Gram) */
 #define DMD_MAX_RANK 160    /* r (nonsymmetric eigen-solver) */
 

@@ -187,7 +187,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
                                          (int64_t)r * r, (int64_t)r, (int64_t)wide * wide});
     double* P = cv.take<double>((size_t)tn_max_splits(n) * maxprod);
     double* G = cv.take<double>((size_t)std::max(l, wide) * std::max(l, wide));
-    double* Rinv = cv.take<double>((size_t)l * l);
+    double* Rinv = cv.take<double>((size_t)std::max(l, wide) * std::max(l, wide));
     float* Rinv32 = cv.take<float>((size_t)l * l);
     double* evals = cv.take<double>((size_t)std::max(l, mm));
     double* Ueig = cv.take<double>((size_t)std::max(l, mm) * std::max(l, mm));
@@ -205,8 +205,19 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     double* rhs2 = cv.take<double>((size_t)r);
     void* res = cv.take<char>((size_t)n * esize(fdt));
     void* eigws = cv.take<char>(eig_workspace_bytes(r));
-    void* symws = cv.take<char>(sym_eig_workspace_bytes(std::max(l, mm)));
-    double* Gxp2 = (exact && !shifted) ? cv.take<double>((size_t)mm * mm) : nullptr;
+    // exact path by the QR route (m - 1 <= EXACT_QR_MAX): an FP64 copy of [X X'] factored by
+    // CholeskyQR, its triangular factor, and the 2(m-1) x 2(m-1) matrix [[0, R], [R^T, 0]]
+    const bool qr_route = exact && mm <= EXACT_QR_MAX && n <= INT32_MAX;
+    const int nc = shifted ? mm + 1 : mm;
+    void* symws = cv.take<char>(sym_eig_workspace_bytes(qr_route ? 2 * mm : std::max(l, mm)));
+    double* Gxp2 = (exact && !shifted && !qr_route) ? cv.take<double>((size_t)mm * mm) : nullptr;
+    double* Qb = qr_route ? cv.take<double>((size_t)ldy * nc) : nullptr;
+    double* RZ = qr_route ? cv.take<double>((size_t)nc * nc) : nullptr;
+    double* RP = (qr_route && !shifted) ? cv.take<double>((size_t)mm * mm) : nullptr;
+    double* Jm = qr_route ? cv.take<double>((size_t)4 * mm * mm) : nullptr;
+    double* Ujw = qr_route ? cv.take<double>((size_t)2 * mm * r) : nullptr;
+    double* Ys = qr_route ? cv.take<double>((size_t)nc * r) : nullptr;
+    double* Yp = qr_route ? cv.take<double>((size_t)nc * r) : nullptr;
     void* Y = nullptr;
     double* Wt = nullptr;
     void* Wtf = nullptr;
@@ -241,45 +252,45 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     const void* Xp = a.xp;
     const int64_t ldxp = a.ldxp;
 
+    // CholeskyQR2 of an N x nq (or mm x nq) matrix in place (`two`), or one pass for an
+    // intermediate basis of the power iteration (it only has to be well conditioned;
+    // the next pass re-orthonormalises it).  A pass whose Cholesky breaks down retries
+    // with a diagonal shift (shifted CholeskyQR); a shifted pass leaves a basis of
+    // condition up to about u^-1/2, so it is followed by as many clean passes as the
+    // mode asks for (two, or one), which run only when their run flag is set.  Shifts
+    // are allowed in the first npass - need passes, so a sketch too ill-conditioned even
+    // for one shifted pass (condition past u^-1) gets a second one; a breakdown in a
+    // pass without a shift is DMD_ERR_CHOL_BREAKDOWN.
+    // fl[0..npass): attempt flags of the passes; fl[8..8+npass): their run flags.
+    auto cholqr = [&](void* Yb, int64_t ld, int64_t rows, int dtype, int32_t* fl, bool two, int nq) -> int32_t {
+        const int need = two ? 2 : 1, npass = two ? 4 : 2;
+        HIPCHK(fill_i32(st, fl, 16, 0));
+        const double shift_scale = 11.0 * ((double)rows * nq + (double)nq * (nq + 1)) * u;
+        for (int pass = 0; pass < npass; ++pass) {
+            const int32_t* skip = pass < need ? nullptr : fl + 8 + pass;
+            const bool can_shift = pass < npass - need;
+            HIPCHK(gemm_tn(st, dtype, DMD_F64, Yb, ld, 0, nq, Yb, ld, 0, nq, 1, rows, P, G, nq, nullptr, 0, skip));
+            HIPCHK(chol_inv(st, G, nq, nq, Rinv, nq, dtype == DMD_F32 ? Rinv32 : nullptr, nq,
+                            can_shift ? shift_scale : 0.0, can_shift ? fl + pass : nullptr, info, skip,
+                            fl + 8 + pass + 1, can_shift ? need : 0));
+            HIPCHK(gemm_nn(st, dtype, Yb, ld, dtype == DMD_F32 ? (const void*)Rinv32 : (const void*)Rinv, nq,
+                           Yb, ld, 0, rows, nq, nq, skip));
+        }
+        return DMD_OK;
+    };
     if (!exact) {
         const int cdt = mixed ? DMD_F32 : DMD_F64;   // MFMA type of the streaming products
-        // CholeskyQR2 of an N x l (or mm x l) matrix in place (`two`), or one pass for an
-        // intermediate basis of the power iteration (it only has to be well conditioned;
-        // the next pass re-orthonormalises it).  A pass whose Cholesky breaks down retries
-        // with a diagonal shift (shifted CholeskyQR); a shifted pass leaves a basis of
-        // condition up to about u^-1/2, so it is followed by as many clean passes as the
-        // mode asks for (two, or one), which run only when their run flag is set.  Shifts
-        // are allowed in the first npass - need passes, so a sketch too ill-conditioned even
-        // for one shifted pass (condition past u^-1) gets a second one; a breakdown in a
-        // pass without a shift is DMD_ERR_CHOL_BREAKDOWN.
-        // fl[0..npass): attempt flags of the passes; fl[8..8+npass): their run flags.
-        auto cholqr = [&](void* Yb, int64_t ld, int64_t rows, int dtype, int32_t* fl, bool two) -> int32_t {
-            const int need = two ? 2 : 1, npass = two ? 4 : 2;
-            HIPCHK(fill_i32(st, fl, 16, 0));
-            const double shift_scale = 11.0 * ((double)rows * l + (double)l * (l + 1)) * u;
-            for (int pass = 0; pass < npass; ++pass) {
-                const int32_t* skip = pass < need ? nullptr : fl + 8 + pass;
-                const bool can_shift = pass < npass - need;
-                HIPCHK(gemm_tn(st, dtype, DMD_F64, Yb, ld, 0, l, Yb, ld, 0, l, 1, rows, P, G, l, nullptr, 0, skip));
-                HIPCHK(chol_inv(st, G, l, l, Rinv, l, dtype == DMD_F32 ? Rinv32 : nullptr, l,
-                                can_shift ? shift_scale : 0.0, can_shift ? fl + pass : nullptr, info, skip,
-                                fl + 8 + pass + 1, can_shift ? need : 0));
-                HIPCHK(gemm_nn(st, dtype, Yb, ld, dtype == DMD_F32 ? (const void*)Rinv32 : (const void*)Rinv, l,
-                               Yb, ld, 0, rows, l, l, skip));
-            }
-            return DMD_OK;
-        };
         // sketch Y = X Omega (Sec. 4.3)
         HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, o.omega, mm, Y, ldy, 0, n, mm, l, nullptr));
-        if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 0, o.q == 0)) return e;
+        if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 0, o.q == 0, l)) return e;
         // power iterations: W = orth(X^T Q), Y = X W, Q = orth(Y)
         for (int it = 0; it < o.q; ++it) {
             HIPCHK(gemm_tn(st, fdt, cdt, a.x, a.ldx, 0, mm, Y, ldy, 0, l, 0, n, P, Wt, mm, nullptr, 0, nullptr));
-            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 16, false)) return e;
+            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 16, false, l)) return e;
             if (fdt == DMD_F32) HIPCHK(to_f32(st, mm, l, l, Wt, mm, (float*)Wtf, mm));
             else HIPCHK(copy_f64(st, mm, l, l, Wt, mm, (double*)Wtf, mm));
             HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, Wtf, mm, Y, ldy, 0, n, mm, l, nullptr));
-            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 32, it == o.q - 1)) return e;
+            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 32, it == o.q - 1, l)) return e;
         }
         // projection B = Q^T X, B' = Q^T X' (one pass over Z when X' is the shifted view).
         // Its sums over N run on the FP64 MFMA on both paths: B feeds the small factors
@@ -311,8 +322,37 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
         // Atilde = U_r^T B' V_r S_r^-1
         HIPCHK(small_gemm(st, 0, 0, l, r, mm, 1.0, Bp, l, Vs, mm, 0.0, T1, l));
         HIPCHK(small_gemm(st, 1, 0, r, r, l, 1.0, Ueig, l, T1, l, 0.0, At, r));
+    } else if (qr_route) {
+        // Q R_Z = [X X'] (or X) by shifted CholeskyQR in FP64, R_Z = Q^T [X X'] (one more pass,
+        // exact up to rounding), and the singular values and right vectors of R = R_Z(0:m-1,
+        // 0:m-1), X's own, from the symmetric matrix [[0, R], [R^T, 0]]: its eigenvalues are
+        // +-sigma_i, so the small singular values keep relative accuracy u kappa (the Gram
+        // X^T X would square kappa), and the eigenvector of +sigma_i is [u_i; v_i] / sqrt(2).
+        HIPCHK(copy_f64(st, (int)n, nc, nc, (const double*)a.x, a.ldx, Qb, ldy));
+        if (int32_t e = cholqr(Qb, ldy, n, DMD_F64, flags + 0, true, nc)) return e;
+        HIPCHK(gemm_tn(st, DMD_F64, DMD_F64, Qb, ldy, 0, nc, a.x, a.ldx, 0, nc, 0, n, P, RZ, nc, nullptr, 0, nullptr));
+        if (!shifted)
+            HIPCHK(gemm_tn(st, DMD_F64, DMD_F64, Qb, ldy, 0, mm, Xp, ldxp, 0, mm, 0, n, P, RP, mm, nullptr, 0, nullptr));
+        HIPCHK(jw_build(st, mm, RZ, nc, Jm));
+        HIPCHK(sym_eig(st, Jm, 2 * mm, 2 * mm, r, evals, Ujw, 2 * mm, symws, info));
+        HIPCHK(sigma_from_evals(st, evals, r, o.rank_tol, sigma, model->sigma, info, 0));
+        // V_r (unit columns, also read by the OptDMD refinement), then Vs = V_r S_r^-1
+        HIPCHK(copy_f64(st, mm, r, r, Ujw + mm, 2 * mm, Ueig, mm, 1.4142135623730951));
+        HIPCHK(copy_f64(st, mm, r, r, Ueig, mm, Vs, mm));
+        HIPCHK(scale_cols(st, mm, r, Vs, mm, sigma, 1));
+        // X Vs = Q Ys and X' Vs = Q Yp with Ys = R_Z(:, 0:m-1) Vs, Yp = R_Z(:, 1:m) Vs (or
+        // Q^T X' Vs); Atilde = (Ys^T Ys)^-1 Ys^T Yp, the operator on the span of X Vs in that
+        // basis (similar to the exact one for any basis of the span, the same modes X' Vs W).
+        HIPCHK(small_gemm(st, 0, 0, nc, r, mm, 1.0, RZ, nc, Vs, mm, 0.0, Ys, nc));
+        if (shifted) HIPCHK(small_gemm(st, 0, 0, nc, r, mm, 1.0, RZ + nc, nc, Vs, mm, 0.0, Yp, nc));
+        else HIPCHK(small_gemm(st, 0, 0, mm, r, mm, 1.0, RP, mm, Vs, mm, 0.0, Yp, mm));
+        HIPCHK(small_gemm(st, 1, 0, r, r, nc, 1.0, Ys, nc, Ys, nc, 0.0, PhiG, r));
+        HIPCHK(chol_inv(st, PhiG, r, r, Rinv, r, nullptr, 0, 0.0, nullptr, info, nullptr));
+        HIPCHK(small_gemm(st, 1, 0, r, r, nc, 1.0, Ys, nc, Yp, nc, 0.0, W, r));
+        HIPCHK(small_gemm(st, 1, 0, r, r, r, 1.0, Rinv, r, W, r, 0.0, PhiG, r));
+        HIPCHK(small_gemm(st, 0, 0, r, r, r, 1.0, Rinv, r, PhiG, r, 0.0, At, r));
     } else {
-        // method of snapshots: Gram of [X X'] in FP64
+        // method of snapshots (m - 1 > EXACT_QR_MAX): Gram of [X X'] in FP64
         double* Gxx;
         double* Gxp;
         int64_t ldg;

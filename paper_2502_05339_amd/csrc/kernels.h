@@ -16,6 +16,7 @@ constexpr int64_t TN_MAX_OUT = 320 * 320;
 constexpr int RECON_MAX_RP = 160;      // padded rank held in registers by the reconstruction
 constexpr int RECON_KPAD = 64;         // frame padding of the coefficient matrix
 constexpr int SMALL_MAX = DMD_MAX_SMALL;
+constexpr int EXACT_QR_MAX = DMD_EXACT_QR_MAX;
 constexpr int EIG_MAX = DMD_MAX_RANK;
 
 __global__ void fill_f64_kernel(double* p, int64_t n, double v);
@@ -81,14 +82,17 @@ hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double
                       double* C, int64_t ldc);
 // Scale column j of A (m x n) by d[j] (or 1/d[j] with inv): A(:, j) *= f(d[j]).
 hipError_t scale_cols(hipStream_t s, int m, int n, double* A, int64_t lda, const double* d, int mode);
-// sigma = sqrt(max(evals, 0))[0..r), rank check against rank_tol.
+// sigma = sqrt(max(evals, 0))[0..r) (squared = 1: evals are squares) or max(evals, 0)
+// (squared = 0), rank check against rank_tol.
 hipError_t sigma_from_evals(hipStream_t s, const double* evals, int r, double rank_tol, double* sigma,
-                            double* sigma_out, int32_t* info);
+                            double* sigma_out, int32_t* info, int squared = 1);
+// J = [[0, R], [R^T, 0]] (2n x 2n, ld 2n) from the n x n block R (ld ldr).
+hipError_t jw_build(hipStream_t s, int n, const double* R, int64_t ldr, double* J);
 // Copy a double matrix into float (m x n), zero-filling columns n..n_pad-1.
 hipError_t to_f32(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, float* B,
                   int64_t ldb);
 hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, double* B,
-                    int64_t ldb);
+                    int64_t ldb, double scale = 1.0);   // B = scale A
 // Least-squares amplitudes from the Gram of the folded modes: beta = G^-1 rhs via
 // Rinv (beta_ws: r doubles), then complex b for each (real | pair) mode.
 hipError_t amplitudes(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs,

@@ -368,25 +368,49 @@ hipError_t scale_cols(hipStream_t s, int m, int n, double* A, int64_t lda, const
 }
 
 __global__ void sigma_kernel(const double* ev, int r, double rank_tol, double* sigma, double* sigma_out,
-                             int32_t* info)
+                             int32_t* info, int squared)
 {
     const int i = threadIdx.x + blockIdx.x * blockDim.x;
+    auto sv = [&](double e) { return squared ? sqrt(fmax(e, 0.0)) : fmax(e, 0.0); };
     if (i < r) {
-        const double v = sqrt(fmax(ev[i], 0.0));
+        const double v = sv(ev[i]);
         sigma[i] = v;
         if (sigma_out) sigma_out[i] = v;
     }
     if (i == 0) {
-        const double s1 = sqrt(fmax(ev[0], 0.0)), sr = sqrt(fmax(ev[r - 1], 0.0));
+        const double s1 = sv(ev[0]), sr = sv(ev[r - 1]);
         if (!(sr > 0.0) || (rank_tol > 0.0 && sr <= rank_tol * s1)) set_status(info, DMD_ERR_RANK);
     }
 }
 
 hipError_t sigma_from_evals(hipStream_t s, const double* evals, int r, double rank_tol, double* sigma,
-                            double* sigma_out, int32_t* info)
+                            double* sigma_out, int32_t* info, int squared)
 {
     hipLaunchKernelGGL(sigma_kernel, dim3((unsigned)ceil_div(r, 256)), dim3(256), 0, s, evals, r, rank_tol,
-                       sigma, sigma_out, info);
+                       sigma, sigma_out, info, squared);
+    return hipGetLastError();
+}
+
+// J = [[0, R], [R^T, 0]] (2n x 2n, column-major, ld 2n) from the n x n block R (ld ldr):
+// its eigenvalues are +-sigma_i(R), with eigenvectors [u_i; v_i] / sqrt(2) for +sigma_i.
+__global__ void jw_build_kernel(int n, const double* __restrict__ R, int64_t ldr, double* __restrict__ J)
+{
+    const int64_t m = 2 * (int64_t)n;
+    for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < m * m;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx % m, j = idx / m;          // J(i, j)
+        double v = 0.0;
+        if (i < n && j >= n) v = R[(j - n) * ldr + i];                 // R(i, j - n)
+        else if (i >= n && j < n) v = R[(i - n) * ldr + j];            // R^T(i - n, j) = R(j, i - n)
+        J[idx] = v;
+    }
+}
+
+hipError_t jw_build(hipStream_t s, int n, const double* R, int64_t ldr, double* J)
+{
+    const int64_t tot = 4 * (int64_t)n * n;
+    hipLaunchKernelGGL(jw_build_kernel, dim3((unsigned)std::min<int64_t>(ceil_div(tot, 256), 1024)), dim3(256), 0, s,
+                       n, R, ldr, J);
     return hipGetLastError();
 }
 
@@ -399,13 +423,14 @@ __global__ void to_f32_kernel(int m, int n, int n_pad, const double* A, int64_t 
         B[(int64_t)j * ldb + i] = j < n ? (float)A[(int64_t)j * lda + i] : 0.0f;
     }
 }
-__global__ void copy_f64_kernel(int m, int n, int n_pad, const double* A, int64_t lda, double* B, int64_t ldb)
+__global__ void copy_f64_kernel(int m, int n, int n_pad, const double* A, int64_t lda, double* B, int64_t ldb,
+                                double scale)
 {
     const int64_t tot = (int64_t)m * n_pad;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(e % m), j = (int)(e / m);
-        B[(int64_t)j * ldb + i] = j < n ? A[(int64_t)j * lda + i] : 0.0;
+        B[(int64_t)j * ldb + i] = j < n ? scale * A[(int64_t)j * lda + i] : 0.0;
     }
 }
 
@@ -416,11 +441,12 @@ hipError_t to_f32(hipStream_t s, int m, int n, int n_pad, const double* A, int64
                        m, n, n_pad, A, lda, B, ldb);
     return hipGetLastError();
 }
-hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, double* B, int64_t ldb)
+hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, double* B, int64_t ldb,
+                    double scale)
 {
     if (m <= 0 || n_pad <= 0) return hipSuccess;
     hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)m * n_pad, 256), 1024)), dim3(256), 0, s,
-                       m, n, n_pad, A, lda, B, ldb);
+                       m, n, n_pad, A, lda, B, ldb, scale);
     return hipGetLastError();
 }
 

@@ -72,8 +72,11 @@ def test_g1_fp64_exact_closed_form(gpu_lib, seed):
 
 
 def test_fp64_exact_vs_oracle_literal_c1(gpu_lib):
-    """Literal c1 (noise 1e-8, ill-conditioned frequencies): the FP64 path and the
-    oracle agree on the fields to well below the noise level."""
+    """Literal c1 (noise 1e-8, ill-conditioned frequencies, sigma_16 / sigma_1 ~ 2e-7): the
+    exact path's triangular-factor route keeps relative accuracy about n u kappa
+    (64 x 1.1e-16 x 5e6 = 3.5e-8) in every kept singular value, so all 16 are held to 1e-7
+    against the oracle's LAPACK SVD, and the fields to 1e-8 on the fitted frames and 1e-6
+    with extrapolation (a Gram route would lose u kappa^2 ~ 3e-3 in sigma_16)."""
     cfg = synth.config("c1")
     _print("case: c1 literal fp64_exact vs oracle")
     g = synth.generate(cfg)
@@ -85,12 +88,12 @@ def test_fp64_exact_vs_oracle_literal_c1(gpu_lib):
     fitted = max_frame_rel(U[: cfg.m], Uo[: cfg.m])
     extrap = max_frame_rel(U, Uo)
     _print(f"  fields vs oracle: fitted frames {fitted:.3e}, with extrapolated frames {extrap:.3e}")
-    # fitted frames agree to the noise level (1e-8); extrapolation beyond them amplifies the
-    # noise-level modes whose eigenvalues the data do not determine (sigma_16/sigma_1 ~ 2e-7)
-    assert fitted <= 1e-7
-    assert extrap <= 1e-5
     s = m.sigma.cpu().numpy()
-    assert np.allclose(s[:8], f.sigma[:8], rtol=1e-10)
+    srel = np.abs(s - f.sigma) / f.sigma
+    _print(f"  sigma relative errors: max {np.max(srel):.3e} (sigma_r / sigma_1 = {f.sigma[-1] / f.sigma[0]:.2e})")
+    assert np.max(srel) <= 1e-7
+    assert fitted <= 1e-8
+    assert extrap <= 1e-6
 
 
 def _small_randomized_cfg(sigma=1e-4, seed=211, jitter=False):
