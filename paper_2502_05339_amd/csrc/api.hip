@@ -274,7 +274,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
                             can_shift ? shift_scale : 0.0, can_shift ? fl + pass : nullptr, info, skip,
                             fl + 8 + pass + 1, can_shift ? need : 0));
             HIPCHK(gemm_nn(st, dtype, Yb, ld, dtype == DMD_F32 ? (const void*)Rinv32 : (const void*)Rinv, nq,
-                           Yb, ld, 0, rows, nq, nq, skip));
+                           Yb, ld, 0, rows, nq, nq, skip, 1));
         }
         return DMD_OK;
     };

@@ -32,9 +32,10 @@ hipError_t small_prepare();
 hipError_t eig_prepare();
 
 // ---- tall-skinny GEMMs (gemm.hip)
+// b_upper: B is upper triangular (B(k, j) = 0 for k > j), its zero part is not multiplied
 hipError_t gemm_nn(hipStream_t s, int dtype, const void* A, int64_t lda, const void* B, int64_t ldb,
                    void* C, int64_t ldc, int c_rowmajor, int64_t N, int K, int n,
-                   const int32_t* skip_unless);
+                   const int32_t* skip_unless, int b_upper = 0);
 hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A, int64_t lda,
                    int a_rowmajor, int ka, const void* B, int64_t ldb, int b_rowmajor, int nb,
                    int sym, int64_t N, double* P, double* out, int64_t ldo, float* out32,
