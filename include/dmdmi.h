@@ -486,7 +486,22 @@ int32_t dmd_autotune_reconstruct(void* stream, const dmd_model* model, int32_t K
                                  size_t ws_bytes, const char* cache_path,
                                  int32_t* best_cfg);
 
-/* Load autotuner entries from a cache file written by dmd_autotune_reconstruct. */
+/*
+ * Fit-product autotuner.  Runs the fit of dmd_fit (same arguments; the model receives
+ * its result) while recording every streaming TN product of the fit (X^T Q, Q^T Z, the
+ * Grams that do not take the triangle-only kernel), then times each recorded shape
+ * class (input and compute type, row chunk, output blocks, log2 N) with every tile
+ * candidate of the TN kernel, three launches each, keeps the fastest for later fits and
+ * products of the same class in this process, and appends one line per class to
+ * `cache_path` (may be NULL).  The replays rewrite workspace buffers only.  Without an
+ * entry a product takes its tile from a cost model.  Synchronous; errors as dmd_fit.
+ */
+int32_t dmd_autotune_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t ncols,
+                         int64_t ldx, int64_t ldxp, int32_t xdtype, const dmd_fit_opts* opts,
+                         void* ws, size_t ws_bytes, dmd_model* model, const char* cache_path);
+
+/* Load autotuner entries (reconstruction and fit products) from a cache file written by
+ * dmd_autotune_reconstruct or dmd_autotune_fit. */
 int32_t dmd_autotune_load(const char* cache_path);
 
 /*

@@ -108,6 +108,9 @@ _SIGS = {
                                            c_int64, c_void_p, c_size_t, ctypes.c_char_p,
                                            ctypes.POINTER(c_int32)]),
     "dmd_autotune_load": (c_int32, [ctypes.c_char_p]),
+    "dmd_autotune_fit": (c_int32, [c_void_p, c_void_p, c_void_p, c_int64, c_int32, c_int64, c_int64, c_int32,
+                                   ctypes.POINTER(FitOpts), c_void_p, c_size_t, ctypes.POINTER(ModelStruct),
+                                   ctypes.c_char_p]),
     "dmd_status_word": (c_int32, [c_void_p, c_void_p, ctypes.POINTER(c_int32)]),
     "dmd_model_save": (c_int32, [c_void_p, ctypes.POINTER(ModelStruct), ctypes.c_char_p]),
     "dmd_model_file_info": (c_int32, [ctypes.c_char_p, ctypes.POINTER(c_int64), ctypes.POINTER(c_int32),

@@ -720,6 +720,25 @@ class BatchedFit:
             pass
 
 
+def autotune_fit(Z: torch.Tensor, r: int, *, p: int = 10, q: int = 2, omega: torch.Tensor | None = None,
+                 precision: str = "mixed", dt: float = 1.0, cache_path: str | None = None) -> Model:
+    """Fit once while timing every tile candidate of the fit's TN products for this shape
+    class (dmd_autotune_fit); later fits of the class take the fastest.  Returns the model."""
+    _require_gpu(Z, "snapshots")
+    x, xp, n, ncols, ld, ldp, code = _xview(Z, None, None)
+    o = fit_opts(r, p, q, precision, omega, dt)
+    L = _lib.lib()
+    nb = ctypes.c_size_t(0)
+    check(L.dmd_fit_workspace_size(n, ncols, code, ctypes.byref(o), ctypes.byref(nb)), "dmd_fit_workspace_size")
+    ws = _workspace(nb.value, Z.device)
+    model = Model.empty(n, r, torch.float32 if code == DMD_F32 else torch.float64, Z.device, dt)
+    ms = model.struct()
+    check(L.dmd_autotune_fit(_stream(), x, xp, n, ncols, ld, ldp, code, ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                             ctypes.byref(ms), None if cache_path is None else cache_path.encode()),
+          "dmd_autotune_fit")
+    return model
+
+
 def autotune_reconstruct(model: Model, K: int, mode: str | None = None, cache_path: str | None = None) -> int:
     """Time the reconstruction kernel's tile-shape candidates on this model; keep the fastest."""
     mcode, out, ws = _recon_common(model, K, mode, None)

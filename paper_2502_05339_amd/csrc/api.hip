@@ -595,6 +595,13 @@ int32_t load_cache(const char* path)
         int mode, rp, ln, lk, cfg;
         double us;
         if (line[0] == '#') continue;
+        if (line[0] == 't' && line[1] == 'n') {
+            int in_dt, c_dt, rc, nbi, nbj, lnn, cand;
+            if (sscanf(line + 2, "%d %d %d %d %d %d %d %lf", &in_dt, &c_dt, &rc, &nbi, &nbj, &lnn, &cand, &us) == 8 &&
+                cand >= 0 && cand < 64)
+                tn_table_set(in_dt, c_dt, rc, nbi, nbj, lnn, cand);
+            continue;
+        }
         if (sscanf(line, "%d %d %d %d %d %lf", &mode, &rp, &ln, &lk, &cfg, &us) == 6 && cfg >= 0 && cfg < RECON_NCFG)
             g_tune[std::make_tuple(mode, rp, ln, lk)] = cfg;
     }
@@ -882,6 +889,48 @@ int32_t dmd_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t 
         HIPCHK(fill_i32(st, model->info + 4, 1, steps));
     }
     if (opts->flags & DMD_FIT_ASYNC) return DMD_OK;
+    int32_t status = 0;
+    HIPCHK(hipMemcpyAsync(&status, model->info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return status;
+}
+
+int32_t dmd_autotune_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t ncols, int64_t ldx,
+                         int64_t ldxp, int32_t xdtype, const dmd_fit_opts* opts, void* ws, size_t ws_bytes,
+                         dmd_model* model, const char* cache_path)
+{
+    if (!opts) return DMD_ERR_ARG;
+    dmd_fit_opts o = *opts;
+    o.flags &= ~(DMD_FIT_ASYNC | DMD_FIT_OPTDMD);
+    FitArgs a{x, xp, n, ncols, ldx, ldxp, xdtype, o, is_shifted_view(x, xp, ldx, ldxp, xdtype)};
+    if (int32_t e = validate_fit(a, model, true)) return e;
+    size_t need = 0;
+    if (int32_t e = dmd_fit_workspace_size(n, ncols, xdtype, &o, &need)) return e;
+    if (!ws || ws_bytes < need) return DMD_ERR_WORKSPACE;
+    {
+        Carver dry(nullptr);
+        fit_plan(dry, nullptr, a, model);
+        if (dry.bytes() > ws_bytes) return DMD_ERR_WORKSPACE;
+    }
+    if (int32_t e0 = ensure_init()) return e0;
+    hipStream_t st = (hipStream_t)stream;
+    model->r = o.r;
+    model->dtype = xdtype;
+    model->dt = o.dt;
+    Carver cv(ws);
+    tn_record(true);
+    const int32_t fe = fit_plan(cv, st, a, model);
+    tn_record(false);
+    if (fe) return fe;
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<std::string> lines;
+    HIPCHK(tn_tune_recorded(st, &lines));
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (!f) return DMD_ERR_IO;
+        for (auto& l : lines) fprintf(f, "%s\n", l.c_str());
+        fclose(f);
+    }
     int32_t status = 0;
     HIPCHK(hipMemcpyAsync(&status, model->info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));

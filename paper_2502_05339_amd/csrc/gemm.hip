@@ -11,6 +11,12 @@
 #include <algorithm>
 #include <type_traits>
 
+#include <functional>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -686,6 +692,37 @@ static hipError_t launch_sym_k(hipStream_t s, const Tin* A, int64_t lda, int a_r
     return hipGetLastError();
 }
 
+// ---- tile choice of the TN products: the cost model below, or a timed choice per shape
+// class (input and compute type, row chunk, output blocks, log2 N) from tn_tune_recorded.
+// While recording, each product that reaches the tile choice is kept (its arguments by
+// value) so the tuner can replay it with every candidate forced.
+typedef std::tuple<int, int, int, int, int, int> TnKey;
+static std::mutex g_tn_mu;
+static std::map<TnKey, int> g_tn_table;
+typedef std::vector<std::pair<TnKey, std::function<hipError_t(hipStream_t, int)>>> TnCalls;
+static bool g_tn_recording = false;
+static TnCalls g_tn_calls;
+static thread_local int g_tn_force = -1;
+
+template <typename T> constexpr int tn_type_code() { return sizeof(T) == 4 ? DMD_F32 : DMD_F64; }
+
+// The candidate to launch among ncand: the forced one during a tuner replay (a force past
+// the last candidate is hipErrorNotFound, nothing launched), else the tuned one, else the
+// cost model's *best.
+static hipError_t tn_pick(const TnKey& key, int ncand, int* best)
+{
+    if (g_tn_force >= 0) {
+        if (g_tn_force >= ncand) return hipErrorNotFound;
+        *best = g_tn_force;
+        return hipSuccess;
+    }
+    std::lock_guard<std::mutex> g(g_tn_mu);
+    auto it = g_tn_table.find(key);
+    if (it != g_tn_table.end() && it->second >= 0 && it->second < ncand) *best = it->second;
+    return hipSuccess;
+}
+static int tn_log2(int64_t n) { int l = 0; while ((int64_t(1) << (l + 1)) <= n) ++l; return l; }
+
 template <typename Tin, typename Tc, int RC>
 static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_rm, int ka,
                                const Tin* B, int64_t ldb, int b_rm, int nb, int sym, int64_t N, int vec,
@@ -695,6 +732,19 @@ static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_r
     // symmetric products whose upper super-blocks fit the waves: triangle-only kernel
     if (sym && ((nbi + 1) / 2) * ((nbi + 1) / 2 + 1) / 2 <= SB_MAXW * (TN_THREADS / 64))
         return launch_sym_k<Tin, Tc, RC>(s, A, lda, a_rm, ka, N, vec, P, nsplit_out, skip_unless);
+    const TnKey key{tn_type_code<Tin>(), tn_type_code<Tc>(), RC, nbi, nbj, tn_log2(N)};
+    if (g_tn_force < 0) {
+        std::lock_guard<std::mutex> g(g_tn_mu);
+        if (g_tn_recording)
+            g_tn_calls.emplace_back(key, [=](hipStream_t s2, int force) {
+                int ns = 0;
+                g_tn_force = force;
+                const hipError_t e = launch_tn_rc<Tin, Tc, RC>(s2, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P,
+                                                              &ns, skip_unless);
+                g_tn_force = -1;
+                return e;
+            });
+    }
     int best = -1;
     int64_t best_cost = INT64_MAX;
     int idx = 0;
@@ -714,6 +764,7 @@ static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_r
         consider(2, 2, 2); consider(3, 3, 2); consider(5, 1, 2); consider(5, 3, 2); consider(5, 4, 2); consider(5, 5, 2);
         consider(7, 3, 2); consider(10, 3, 2);
         consider(3, 3, 4); consider(3, 4, 4); consider(3, 5, 4); consider(4, 3, 4); consider(5, 3, 4);
+        if (hipError_t e = tn_pick(key, idx, &best)) return e;
         switch (best) {
             TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 3) TN_CASE(4, 5, 4) TN_CASE(5, 5, 5)
             TN_CASE(6, 7, 3) TN_CASE(7, 10, 3)
@@ -723,6 +774,7 @@ static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_r
     } else if constexpr (sizeof(Tc) == 4) {
         consider(2, 2, 2); consider(3, 3, 2); consider(5, 1, 2); consider(5, 3, 2); consider(5, 4, 2); consider(5, 5, 2);
         consider(7, 3, 2); consider(10, 3, 2);
+        if (hipError_t e = tn_pick(key, idx, &best)) return e;
         switch (best) {
             TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 3) TN_CASE(4, 5, 4) TN_CASE(5, 5, 5)
             TN_CASE(6, 7, 3)
@@ -730,6 +782,7 @@ static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_r
         }
     } else {
         consider(2, 2, 2); consider(3, 3, 2); consider(4, 4, 2); consider(5, 1, 2); consider(5, 3, 2);
+        if (hipError_t e = tn_pick(key, idx, &best)) return e;
         switch (best) {
             TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 4, 4) TN_CASE(3, 5, 1)
             default: return launch_tn_k<Tin, Tc, RC, 5, 3>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
@@ -885,6 +938,76 @@ hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(tot, (int64_t)64)), dim3(64 * RQ), 0, s, P, ns,
                        ka, nb, sym, out, ldo, out32, ldo32, skip_unless);
     return hipGetLastError();
+}
+
+
+// ---- TN tile tuner
+void tn_record(bool on)
+{
+    std::lock_guard<std::mutex> g(g_tn_mu);
+    if (on) g_tn_calls.clear();
+    g_tn_recording = on;
+}
+
+hipError_t tn_tune_recorded(hipStream_t s, std::vector<std::string>* lines)
+{
+    TnCalls calls;
+    {
+        std::lock_guard<std::mutex> g(g_tn_mu);
+        calls.swap(g_tn_calls);
+    }
+    std::map<TnKey, std::pair<int, float>> done;
+    hipEvent_t e0, e1;
+    hipError_t err = hipEventCreate(&e0);
+    if (err != hipSuccess) return err;
+    if ((err = hipEventCreate(&e1)) != hipSuccess) { (void)hipEventDestroy(e0); return err; }
+    for (auto& rec : calls) {
+        if (done.count(rec.first)) continue;
+        int best = -1;
+        float best_ms = 1e30f;
+        for (int c = 0; c < 64; ++c) {
+            err = rec.second(s, c);                                   // warm-up
+            if (err == hipErrorNotFound) { err = hipSuccess; break; }
+            if (err != hipSuccess) break;
+            (void)hipEventRecord(e0, s);
+            for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) err = rec.second(s, c);
+            (void)hipEventRecord(e1, s);
+            if (err != hipSuccess || (err = hipEventSynchronize(e1)) != hipSuccess) break;
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best_ms) { best_ms = ms; best = c; }
+        }
+        if (err != hipSuccess) break;
+        done[rec.first] = {best, best_ms / 3.0f};
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return err;
+    std::lock_guard<std::mutex> g(g_tn_mu);
+    for (auto& kv : done) {
+        if (kv.second.first < 0) continue;
+        g_tn_table[kv.first] = kv.second.first;
+        if (lines) {
+            char buf[160];
+            const TnKey& k = kv.first;
+            snprintf(buf, sizeof buf, "tn %d %d %d %d %d %d %d %.3f", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                     std::get<3>(k), std::get<4>(k), std::get<5>(k), kv.second.first, kv.second.second * 1000.0f);
+            lines->push_back(buf);
+        }
+    }
+    return hipSuccess;
+}
+
+void tn_table_set(int in_dt, int c_dt, int rc, int nbi, int nbj, int ln, int cand)
+{
+    std::lock_guard<std::mutex> g(g_tn_mu);
+    g_tn_table[TnKey{in_dt, c_dt, rc, nbi, nbj, ln}] = cand;
+}
+
+size_t tn_table_size()
+{
+    std::lock_guard<std::mutex> g(g_tn_mu);
+    return g_tn_table.size();
 }
 
 }  // namespace dmd

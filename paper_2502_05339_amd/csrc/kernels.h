@@ -5,6 +5,8 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <string>
+#include <vector>
 
 #include "dmdmi.h"
 
@@ -41,6 +43,13 @@ hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A
                    int sym, int64_t N, double* P, double* out, int64_t ldo, float* out32,
                    int64_t ldo32, const int32_t* skip_unless);
 size_t gemm_tn_partial_bytes(int64_t N, int ka, int nb);
+// Tile tuner of gemm_tn: record the products that reach the tile choice (tn_record(true)
+// ... tn_record(false)), then time every candidate of each recorded shape class and keep
+// the fastest (lines: one cache line "tn ..." per class); tn_table_set loads a choice.
+void tn_record(bool on);
+hipError_t tn_tune_recorded(hipStream_t s, std::vector<std::string>* lines);
+void tn_table_set(int in_dt, int c_dt, int rc, int nbi, int nbj, int ln, int cand);
+size_t tn_table_size();
 int tn_max_splits(int64_t N);          // row splits (FP64 partial products) gemm_tn uses for N rows
 
 // ---- reconstruction (recon.hip)

@@ -120,6 +120,20 @@ def test_fit_dtype_and_enum_validation(L):
     assert _ws_size(L, 8192, 250, 1, _opts(r=16, p=0, q=0, precision="fp64_exact"))[0] == 11
 
 
+def test_autotune_fit_argument_errors(L):
+    """The fit autotuner validates like dmd_fit before touching the device: no options,
+    inconsistent sizes, a too small workspace."""
+    m = _model_struct(n=1000, r=10)
+    assert L.dmd_autotune_fit(None, 0x1000, 0x2000, 1000, 30, 1000, 1000, 0, None, 0x3000, 1 << 30,
+                              ctypes.byref(m), None) == 1
+    o = _opts(r=40, p=10)
+    assert L.dmd_autotune_fit(None, 0x1000, 0x2000, 1000, 30, 1000, 1000, 0, ctypes.byref(o), 0x3000, 1 << 30,
+                              ctypes.byref(m), None) != 0
+    o = _opts(r=10, p=4)
+    assert L.dmd_autotune_fit(None, 0x1000, 0x2000, 1000, 30, 1000, 1000, 0, ctypes.byref(o), 0x3000, 16,
+                              ctypes.byref(m), None) == 3
+
+
 def test_workspace_sizes_scale(L):
     st, small = _ws_size(L, 131072, 199, 0, _opts(150, 10, 2))
     st2, big = _ws_size(L, 6291456, 299, 0, _opts(150, 10, 2))

@@ -388,3 +388,31 @@ def test_sketch_beyond_limit_is_unsupported(gpu_lib):
     with pytest.raises(dmd.DMDError) as ei:
         _gpu_fit(g, cfg, "mixed")
     assert ei.value.code == 11
+
+
+def test_autotune_fit_tiles(gpu_lib, tmp_path):
+    """dmd_autotune_fit times every TN tile candidate of the fit's products per shape class and
+    keeps the fastest; it writes one cache line per class, a fit after it (tuned tiles) still
+    matches the FP64 twin to the mixed path's bar, and the cache file loads again."""
+    import paper_2502_05339_amd as dmd
+    from paper_2502_05339_amd import _lib
+    cfg = _small_randomized_cfg(seed=212)
+    _print("case: fit autotuner")
+    g = synth.generate(cfg)
+    Z = torch.from_numpy(np.ascontiguousarray(g.Z.T)).cuda()
+    om = torch.from_numpy(np.ascontiguousarray(g.Omega.T)).cuda()
+    path = tmp_path / "tune.txt"
+    m1 = dmd.autotune_fit(Z, cfg.r, p=cfg.p, q=cfg.q, omega=om, cache_path=str(path))
+    lines = [ln for ln in open(path) if ln.startswith("tn ")]
+    _print("  " + "; ".join(ln.strip() for ln in lines))
+    assert len(lines) >= 2 and int(m1.info[0].item()) == 0
+    m2 = dmd.fit(Z, cfg.r, p=cfg.p, q=cfg.q, omega=om)
+    tw = oracle.fit_randomized(g.Z.astype(np.float64), cfg.r, g.Omega.astype(np.float64), cfg.q)
+    w = oracle.amplitude_weights(tw.phi, tw.b)
+    for m in (m1, m2):
+        ia, ib = oracle.match_eigs(m.lam_host(), tw.lam)
+        d = np.abs(m.lam_host()[ia] - tw.lam[ib])
+        wrel = float(np.sum(w[ib] * d) / np.sum(w[ib] * np.abs(tw.lam[ib])))
+        _print(f"  lambda weighted vs twin {wrel:.3e}")
+        assert wrel <= 1e-5
+    assert _lib.lib().dmd_autotune_load(str(path).encode()) == 0
