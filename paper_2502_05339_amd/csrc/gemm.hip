@@ -559,11 +559,13 @@ gemm_sym_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
     }
 }
 
-// out(i, j) = sum_s P_s(i, j) in a fixed order: work-group = 64 consecutive outputs x
-// RQ split ranges; thread (o, q) sums the splits s = q, q + RQ, ... of output o, and
-// the RQ partial sums are added in q order.  In symmetric mode the lower blocks are
-// taken from the mirrored upper ones (the products compute the full square, but the
-// mirror keeps the output exactly symmetric).
+// out(i, j) = sum_s P_s(i, j) in a fixed order: work-group = 64 consecutive rows i of one
+// column j (blockIdx.y) x RQ split ranges; thread (o, q) sums the splits s = q, q + RQ, ...
+// of row o, and the RQ partial sums are added in q order.  Every read of a split is 64
+// consecutive entries of a column.  In symmetric mode the products hold the upper block
+// triangle only: a column is summed down to the end of its diagonal block and each sum
+// above the diagonal block is written to (i, j) and to the mirror (j, i), which keeps the
+// output exactly symmetric.
 constexpr int RQ = 8;
 __global__ void __launch_bounds__(64 * RQ)
 reduce_partials_kernel(const double* __restrict__ P, int nsplit, int ka, int nb,
@@ -574,14 +576,13 @@ reduce_partials_kernel(const double* __restrict__ P, int nsplit, int ka, int nb,
     __shared__ double part[RQ][64];
     const int64_t tot = (int64_t)ka * nb;
     const int o = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int64_t e = (int64_t)blockIdx.x * 64 + o;
+    const int j = blockIdx.y;
+    const int i = blockIdx.x * 64 + o;
+    const int limit = sym ? min(ka, (j / 16 + 1) * 16) : ka;
+    if (blockIdx.x * 64 >= limit) return;                // the whole work-group: uniform
     double s = 0.0;
-    int i = 0, j = 0;
-    if (e < tot) {
-        i = (int)(e % ka); j = (int)(e / ka);
-        int si = i, sj = j;
-        if (sym && (i / 16) > (j / 16)) { si = j; sj = i; }
-        const double* p = P + (int64_t)sj * ka + si;
+    if (i < limit) {
+        const double* p = P + (int64_t)j * ka + i;
         // eight loads in flight per lane, added in the same (split) order as one at a time
         int k = q;
         for (; k + 7 * RQ < nsplit; k += 8 * RQ) {
@@ -595,12 +596,16 @@ reduce_partials_kernel(const double* __restrict__ P, int nsplit, int ka, int nb,
     }
     part[q][o] = s;
     __syncthreads();
-    if (q == 0 && e < tot) {
+    if (q == 0 && i < limit) {
         double t = part[0][o];
 #pragma unroll
         for (int k = 1; k < RQ; ++k) t += part[k][o];
         if (out) out[(int64_t)j * ldo + i] = t;
         if (out32) out32[(int64_t)j * ldo32 + i] = (float)t;
+        if (sym && i / 16 < j / 16) {
+            if (out) out[(int64_t)i * ldo + j] = t;
+            if (out32) out32[(int64_t)i * ldo32 + j] = (float)t;
+        }
     }
 }
 
@@ -935,7 +940,7 @@ hipError_t gemm_tn(hipStream_t s, int in_dtype, int compute_dtype, const void* A
     }
     if (e != hipSuccess) return e;
     const int64_t tot = (int64_t)ka * nb;
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(tot, (int64_t)64)), dim3(64 * RQ), 0, s, P, ns,
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)ceil_div(ka, 64), (unsigned)nb), dim3(64 * RQ), 0, s, P, ns,
                        ka, nb, sym, out, ldo, out32, ldo32, skip_unless);
     return hipGetLastError();
 }
