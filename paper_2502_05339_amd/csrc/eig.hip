@@ -70,8 +70,9 @@ static EigWs eig_carve(void* ws, int n)
 // the step, P H P = H - tau (v w^T + u v^T) + tau^2 gamma v v^T on columns > k, and column
 // k becomes (.., beta, 0, ..).  u, w and gamma are summed from per-thread partials in LDS
 // (fixed order).  While the others update their entries, wave 0 forms the next column and
-// the next reflector.  Three barriers per step.
-template <int HN>
+// the next reflector.  Three barriers per step.  SYMM (a symmetric A, whose reduction is
+// tridiagonal): u = H v equals w = H^T v, so only w is summed and serves for both.
+template <int HN, bool SYMM = false>
 __global__ void __launch_bounds__(1024)
 hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, double* V, double* tau)
 {
@@ -134,13 +135,15 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
         }
         // ---- partials of u = H v, w = H^T v, gamma = v^T H v; column k + 1 before the step
         double g = 0.0;
+        if constexpr (!SYMM) {
 #pragma unroll
-        for (int a = 0; a < HS_N; ++a) {
-            double t = 0.0;
+            for (int a = 0; a < HS_N; ++a) {
+                double t = 0.0;
 #pragma unroll
-            for (int c = 0; c < HS_N; ++c) t = fma(h[a][c], vc[c], t);
-            const int i = ib + 32 * a;
-            if (i < n) upart[jb * UPS + i] = t;
+                for (int c = 0; c < HS_N; ++c) t = fma(h[a][c], vc[c], t);
+                const int i = ib + 32 * a;
+                if (i < n) upart[jb * UPS + i] = t;
+            }
         }
 #pragma unroll
         for (int c = 0; c < HS_N; ++c) {
@@ -158,7 +161,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
         gpart[tid] = g;
         __syncthreads();
         // ---- sums in a fixed order
-        if (tid < n) {
+        if (!SYMM && tid < n) {
             double t = 0.0;
             for (int q = 0; q < 32; ++q) t += upart[q * UPS + tid];
             us[tid] = t;
@@ -175,6 +178,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
             if (lane == 0) refl[3] = t;
         }
         __syncthreads();
+        const double* uv = SYMM ? ws : us;      // u = H v
         const double tg = tk * tk * refl[3];
         // ---- wave 0 first: column k + 1 after the step, and the reflector of step k + 1 (a
         // latency chain that the other waves' updates hide; it reads no entry of h)
@@ -182,7 +186,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
             const double wk = ws[k + 1], vk = k + 1 < n ? 1.0 : 0.0;    // v_{k+1} = 1
             for (int i = k + 2 + lane; i < n; i += 64) {
                 const double vi = vof(i);
-                col[i] = colpre[i] - (tk * fma(vi, wk, us[i] * vk) - tg * vi * vk);
+                col[i] = colpre[i] - (tk * fma(vi, wk, uv[i] * vk) - tg * vi * vk);
             }
             wave_sync_lds();
             reflector(k + 1);
@@ -202,7 +206,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
 #pragma unroll
         for (int a = 0; a < HS_N; ++a) {
             const int i = ib + 32 * a;
-            Bi[a] = i < n ? fma(tk, us[i], -tg * vr[a]) : 0.0;    // padding rows stay as they are
+            Bi[a] = i < n ? fma(tk, uv[i], -tg * vr[a]) : 0.0;    // padding rows stay as they are
         }
 #pragma unroll
         for (int a = 0; a < HS_N; ++a) {
@@ -1200,8 +1204,8 @@ hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, int nv, d
     double* H = (double*)ws;
     double* V = H + (size_t)n * n + 2;
     double* tau = V + (size_t)n * n;
-    if (n <= 160) hipLaunchKernelGGL(hessenberg_kernel<5>, dim3(1), dim3(1024), 0, s, S, lds, n, H, V, tau);
-    else hipLaunchKernelGGL(hessenberg_kernel<6>, dim3(1), dim3(1024), 0, s, S, lds, n, H, V, tau);
+    if (n <= 160) hipLaunchKernelGGL((hessenberg_kernel<5, true>), dim3(1), dim3(1024), 0, s, S, lds, n, H, V, tau);
+    else hipLaunchKernelGGL((hessenberg_kernel<6, true>), dim3(1), dim3(1024), 0, s, S, lds, n, H, V, tau);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(tri_bisect_kernel, dim3((unsigned)ceil_div(n, TB_WAVES)), dim3(64 * TB_WAVES),
