@@ -247,7 +247,8 @@ def main():
     lowres_ms = _events_ms(lambda: dmd.lowres_project(forcing, coarse, grid, fct, out=forcing), reps)
     lowres_bytes = 2 * 4 * cfg.N * (cfg.K - 1) + 4 * (cfg.N // fct ** 2) * (cfg.K - 1)
     del forcing, coarse
-    # OptDMD refinement (Sec. 4.2) on the same snapshots: host-driven, so wall time
+    # OptDMD refinement (Sec. 4.2) on the same snapshots: the waiting call reads a device
+    # flag after every 8 trial points, so wall time
     torch.cuda.synchronize()
     t_opt = time.perf_counter()
     mo = dmd.fit(Z, cfg.r, p=cfg.p, q=cfg.q, omega=om, precision="mixed", optdmd=True)

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define DMDMI_ABI_VERSION 2
+#define DMDMI_ABI_VERSION 3
 
 /* Status codes. */
 typedef enum dmd_status {
@@ -117,9 +117,15 @@ typedef enum dmd_recon_mode {
 #define DMD_FIT_CHECK_FINITE 2u  /* scan X and X' for NaN/Inf first */
 #define DMD_FIT_OPTDMD 4u        /* OptDMD (Sec. 4.2): refine lambda and the modes by variable
                                     projection on all snapshots of X (eq. variable_projection,
-                                    eq. phi_optdmd), starting from the fit's eigenvalues; the
-                                    call then waits for the device (not with DMD_FIT_ASYNC or
-                                    in dmd_fit_batched); info[4] = Levenberg-Marquardt steps */
+                                    eq. phi_optdmd), starting from the fit's eigenvalues, by
+                                    Levenberg-Marquardt steps decided on the device.  Without
+                                    DMD_FIT_ASYNC the call runs the iteration to its stopping
+                                    rule (it reads a device flag after every 8 trial points);
+                                    with DMD_FIT_ASYNC, and in dmd_fit_batched, it enqueues
+                                    opts.optdmd_trials trial points (a fixed launch sequence
+                                    that can be captured; trial points after the stop cost
+                                    their launches only).  info[4..6] report the outcome */
+#define DMD_MAX_OPTDMD_TRIALS 100000
 
 /* Options of a fit. */
 typedef struct dmd_fit_opts {
@@ -133,15 +139,21 @@ typedef struct dmd_fit_opts {
                            element type as X; NULL for DMD_FIT_FP64_EXACT.  The sketch is an
                            input so that a reference implementation can use the same draw. */
     uint32_t flags;     /* DMD_FIT_* */
-    int32_t reserved;
+    int32_t optdmd_trials;  /* DMD_FIT_OPTDMD with DMD_FIT_ASYNC or in dmd_fit_batched: trial
+                               points enqueued (0: 64); 0 <= optdmd_trials <=
+                               DMD_MAX_OPTDMD_TRIALS, else DMD_ERR_ARG; otherwise unused */
 } dmd_fit_opts;
 
 /* Number of int32 words in model->info. */
 #define DMD_INFO_WORDS 8
 /* info[0] status, [1] bisection rounds of the symmetric eigenvalues, [2] Ehrlich-Aberth
  * iterations of the eigenvalues
- * of Atilde, [3] shifted CholeskyQR retries, [4] OptDMD Levenberg-Marquardt steps,
- * [5..7] reserved. */
+ * of Atilde, [3] shifted CholeskyQR retries, [4] OptDMD Levenberg-Marquardt steps kept,
+ * [5] OptDMD trial points evaluated, [6] OptDMD outcome: 0 stopped by its rule (a kept step
+ * gained at most 1e-13 of the cost, 200 kept steps, 40 rejections in a row or the damping
+ * past 1e20), 1 still running when the enqueued trial points ran out (the model holds the
+ * last kept point), 2 not applied (the starting basis was singular or its cost not finite;
+ * the model is the plain fit's), [7] reserved. */
 
 /* A DMD model; every pointer is device memory owned by the caller. */
 typedef struct dmd_model {

@@ -41,7 +41,7 @@ NOALLOC_SCRATCH_BYTES = 8 << 20
 class FitOpts(ctypes.Structure):
     _fields_ = [("r", c_int32), ("p", c_int32), ("q", c_int32), ("precision", c_int32),
                 ("dt", c_double), ("rank_tol", c_double), ("omega", c_void_p),
-                ("flags", ctypes.c_uint32), ("reserved", c_int32)]
+                ("flags", ctypes.c_uint32), ("optdmd_trials", c_int32)]
 
 
 class ModelStruct(ctypes.Structure):

@@ -231,7 +231,7 @@ def _xview(Z: torch.Tensor | None, X: torch.Tensor | None, Xp: torch.Tensor | No
 
 def fit_opts(r: int, p: int = 10, q: int = 2, precision: str = "mixed", omega: torch.Tensor | None = None,
              dt: float = 1.0, rank_tol: float = 0.0, check_finite: bool = False, asynchronous: bool = False,
-             optdmd: bool = False):
+             optdmd: bool = False, optdmd_trials: int = 0):
     o = _lib.FitOpts()
     o.r, o.p, o.q = int(r), int(p), int(q)
     o.precision = PRECISIONS[precision]
@@ -240,17 +240,21 @@ def fit_opts(r: int, p: int = 10, q: int = 2, precision: str = "mixed", omega: t
     o.omega = _ptr(omega)
     o.flags = ((FIT_CHECK_FINITE if check_finite else 0) | (FIT_ASYNC if asynchronous else 0) |
                (FIT_OPTDMD if optdmd else 0))
+    o.optdmd_trials = int(optdmd_trials)
     return o
 
 
 def fit(Z: torch.Tensor | None = None, r: int = 0, *, X: torch.Tensor | None = None, Xp: torch.Tensor | None = None,
         p: int = 10, q: int = 2, omega: torch.Tensor | None = None, precision: str = "mixed", dt: float = 1.0,
         rank_tol: float = 0.0, check_finite: bool = False, asynchronous: bool = False,
-        optdmd: bool = False) -> Model:
+        optdmd: bool = False, optdmd_trials: int = 0) -> Model:
     """Fit a rank-r DMD model (Sec. 4.3 randomized SVD, then Sec. 3.1).
 
     optdmd=True refines the eigenvalues and modes by variable projection over all
-    snapshots of X (OptDMD, Sec. 4.2); the call then waits for the device.
+    snapshots of X (OptDMD, Sec. 4.2), with Levenberg-Marquardt decisions taken on the
+    device.  A waiting call runs it to its stopping rule; with asynchronous=True it
+    enqueues optdmd_trials trial points (0: 64).  model.info[4..6]: kept steps, trial
+    points, outcome (0 stopped by its rule, 1 out of trial points, 2 not applied).
 
     Z: (m, N) snapshots (or X, Xp: (m-1, N) each); omega: (l, m-1) tensor holding the
     column-major (m-1) x l Gaussian sketch (i.e. omega.T is the sketch), same dtype as Z;
@@ -259,7 +263,7 @@ def fit(Z: torch.Tensor | None = None, r: int = 0, *, X: torch.Tensor | None = N
     src = Z if Z is not None else X
     _require_gpu(src, "snapshots")
     x, xp, n, ncols, ld, ldp, code = _xview(Z, X, Xp)
-    o = fit_opts(r, p, q, precision, omega, dt, rank_tol, check_finite, asynchronous, optdmd)
+    o = fit_opts(r, p, q, precision, omega, dt, rank_tol, check_finite, asynchronous, optdmd, optdmd_trials)
     L = _lib.lib()
     nb = ctypes.c_size_t(0)
     check(L.dmd_fit_workspace_size(n, ncols, code, ctypes.byref(o), ctypes.byref(nb)), "dmd_fit_workspace_size")
@@ -657,7 +661,8 @@ class BatchedFit:
     """Several independent fits captured once into a HIP graph (one forked stream per scene)."""
 
     def __init__(self, scenes, capture: bool = True):
-        """scenes: list of dicts with keys Z (m, N tensor), r, p, q, omega, precision, dt."""
+        """scenes: list of dicts with keys Z (m, N tensor), r, p, q, omega, precision, dt, and
+        optionally optdmd (bool) and optdmd_trials (trial points enqueued, 0: 64)."""
         L = _lib.lib()
         self.models = []
         self._keep = []
@@ -669,7 +674,8 @@ class BatchedFit:
             _require_gpu(Z, "Z")
             x, xp, nn, ncols, ld, ldp, code = _xview(Z, None, None)
             o = fit_opts(s["r"], s.get("p", 10), s.get("q", 2), s.get("precision", "mixed"), s.get("omega"),
-                         s.get("dt", 1.0), 0.0, False, True)
+                         s.get("dt", 1.0), 0.0, False, True, bool(s.get("optdmd", False)),
+                         int(s.get("optdmd_trials", 0)))
             nb = ctypes.c_size_t(0)
             check(L.dmd_fit_workspace_size(nn, ncols, code, ctypes.byref(o), ctypes.byref(nb)), "workspace")
             ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=Z.device)

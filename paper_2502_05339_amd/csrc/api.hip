@@ -84,7 +84,7 @@ int32_t validate_fit(const FitArgs& a, const dmd_model* model, bool need_ptrs)
     if (o.r > DMD_MAX_RANK) return DMD_ERR_UNSUPPORTED;
     if (!(o.dt > 0.0) || !isfinite(o.dt)) return DMD_ERR_ARG;
     if (o.rank_tol < 0.0 || !isfinite(o.rank_tol)) return DMD_ERR_ARG;
-    if ((o.flags & DMD_FIT_OPTDMD) && (o.flags & DMD_FIT_ASYNC)) return DMD_ERR_ARG;
+    if (o.optdmd_trials < 0 || o.optdmd_trials > DMD_MAX_OPTDMD_TRIALS) return DMD_ERR_ARG;
     if (o.precision == DMD_FIT_FP64_EXACT) {
         if (a.ncols > DMD_MAX_SMALL) return DMD_ERR_UNSUPPORTED;
     } else {
@@ -110,15 +110,17 @@ int32_t validate_fit(const FitArgs& a, const dmd_model* model, bool need_ptrs)
 // OptDMD buffers (variable projection on the T x r data Y = V_r S_r); two slots hold the
 // current and the trial point of the Levenberg-Marquardt iteration
 struct OptPlan {
-    double *Yd, *Phi, *E, *R, *Et;          // T x r
+    double *YE, *RE, *Phi;                  // T x 2r: [Y | E] and [R | E~]; T x r
     double *PtP, *Rv, *K, *Wm, *ER, *H;     // r x r
     double *PtYE, *tmp;                     // r x 2r
-    double *BF[2], *G[2], *g[2], *theta[2]; // r x 2r (B | Phi^+ E), r x r, r, r
+    double *BF[2], *G[2], *g[2], *theta[2]; // current (0) and trial (1) point: r x 2r (B | Phi^+ E), r x r, r, r
     double *cost;                           // 2
     double *A, *RinvA, *delta, *scale;      // r x r, r x r, r, r
     double *C;                              // rows x r (rows = l, or T on the exact path)
     void* Cf;                               // rows x ldphi in the data type
-    int32_t* scr;                           // 16
+    int32_t* scr;                           // 16: status words of the r x r factorisations
+    int32_t* ist;                           // the iteration's integer state (VP_*)
+    double* vst;                            // cost and mu of the current point
     double* Ptn;                            // split partial products of the T-reductions
 };
 
@@ -126,8 +128,7 @@ OptPlan opt_carve(Carver& cv, int T, int r, int rows, int64_t ldphi, int fdt)
 {
     OptPlan o;
     const size_t tr = (size_t)T * r, rr = (size_t)r * r;
-    o.Yd = cv.take<double>(tr); o.Phi = cv.take<double>(tr); o.E = cv.take<double>(tr);
-    o.R = cv.take<double>(tr); o.Et = cv.take<double>(tr);
+    o.YE = cv.take<double>(2 * tr); o.RE = cv.take<double>(2 * tr); o.Phi = cv.take<double>(tr);
     o.PtP = cv.take<double>(rr); o.Rv = cv.take<double>(rr); o.K = cv.take<double>(rr);
     o.Wm = cv.take<double>(rr); o.ER = cv.take<double>(rr); o.H = cv.take<double>(rr);
     o.PtYE = cv.take<double>(2 * rr); o.tmp = cv.take<double>(2 * rr);
@@ -141,7 +142,9 @@ OptPlan opt_carve(Carver& cv, int T, int r, int rows, int64_t ldphi, int fdt)
     o.C = cv.take<double>((size_t)rows * r);
     o.Cf = cv.take<char>((size_t)rows * ldphi * esize(fdt));
     o.scr = cv.take<int32_t>(16);
-    o.Ptn = cv.take<double>((size_t)tn_max_splits(T) * rr);
+    o.ist = cv.take<int32_t>(VP_IST_WORDS);
+    o.vst = cv.take<double>(2);
+    o.Ptn = cv.take<double>((size_t)tn_max_splits(T) * 2 * rr);   // the widest T-reduction is r x 2r
     return o;
 }
 
@@ -412,14 +415,17 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
 // ---------------------------------------------------------------- OptDMD refinement
 // Levenberg-Marquardt on theta (real folded parameters, one per column) for
 // min ||Y - Phi(theta) B||_F with B = Phi^+ Y eliminated (eq. variable_projection), then
-// the modes of eq. phi_optdmd written into the model.  Host-driven: each trial point is
-// evaluated on the device and its cost read back; a step is kept when it lowers the cost
-// (mu / 4), else mu * 4 and a new trial.  Stops when a kept step gains less than 1e-13
-// of the cost, after 200 kept steps, or when mu passes 1e20.
-constexpr int VP_MAX_STEPS = 200;   // the oracle's step cap
-constexpr int VP_MAX_TRIES = 40;
+// the modes of eq. phi_optdmd written into the model.  Driven from the device: every
+// trial point is the same fixed sequence of launches, run only while the iteration goes
+// on (ist[VP_RUN]); vp_decide keeps a trial point when it lowers the cost (mu / 4), else
+// mu * 4, and stops the iteration when a kept step gains at most 1e-13 of the cost, after
+// 200 kept steps, after 40 rejections in a row, or when mu passes 1e20.  A waiting call
+// enqueues trial points in groups of VP_GROUP and reads the run flag after each group;
+// an asynchronous one (or a scene of dmd_fit_batched) enqueues a fixed number of them.
+constexpr int VP_GROUP = 8;
+constexpr int VP_DEFAULT_TRIALS = 64;
 
-int32_t optdmd_refine(hipStream_t st, const FitArgs& a, dmd_model* model, FitBufs& fb, int* steps_out)
+int32_t optdmd_refine(hipStream_t st, const FitArgs& a, dmd_model* model, FitBufs& fb, bool wait)
 {
     const dmd_fit_opts& o = a.o;
     const bool exact = o.precision == DMD_FIT_FP64_EXACT;
@@ -428,106 +434,95 @@ int32_t optdmd_refine(hipStream_t st, const FitArgs& a, dmd_model* model, FitBuf
     OptPlan& op = fb.op;
     const double u = 1.1102230246251565e-16;
     const double shift_scale = 11.0 * ((double)T * r + (double)r * (r + 1)) * u;
+    const size_t tr = (size_t)T * r;
+    double* Yd = op.YE;              // Y
+    double* E = op.YE + tr;          // t alpha^(t-1) columns
+    double* R = op.RE;               // Y - Phi B
+    double* Et = op.RE + tr;         // E - Phi F
+    int32_t* run = op.ist + VP_RUN;
+    const int32_t* apply = op.ist + VP_APPLY;
+    HIPCHK(vp_begin(st, model->info, op.ist, op.scr));
     // data Y = V_r S_r: B^T U_r on the randomized paths (B = Q^T X), V_r S_r on the exact one
     if (!exact) {
-        HIPCHK(small_gemm(st, 1, 0, T, r, l, 1.0, fb.Bx, l, fb.Ueig, l, 0.0, op.Yd, T));
+        HIPCHK(small_gemm(st, 1, 0, T, r, l, 1.0, fb.Bx, l, fb.Ueig, l, 0.0, Yd, T, apply));
     } else {
-        HIPCHK(copy_f64(st, T, r, r, fb.Ueig, T, op.Yd, T));
-        HIPCHK(scale_cols(st, T, r, op.Yd, T, fb.sigma, 0));
+        HIPCHK(copy_f64(st, T, r, r, fb.Ueig, T, Yd, T, 1.0, apply));
+        HIPCHK(scale_cols(st, T, r, Yd, T, fb.sigma, 0));
     }
     HIPCHK(vp_theta_init(st, r, model->lam, model->kind, op.theta[0]));
-    // out (r x r) = A^T B for T x r column-major A, B
-    auto tn64 = [&](const double* A, const double* B, int sym, double* out) -> hipError_t {
-        return gemm_tn(st, DMD_F64, DMD_F64, A, T, 0, r, B, T, 0, r, sym, T, op.Ptn, out, r, nullptr, 0, nullptr);
+    // out (r x nb) = A^T B for T x r A and T x nb B, column-major
+    auto tn64 = [&](const double* A, const double* B, int nb, int sym, double* out, const int32_t* gate) {
+        return gemm_tn(st, DMD_F64, DMD_F64, A, T, 0, r, B, T, 0, nb, sym, T, op.Ptn, out, r, nullptr, 0, gate);
     };
-    auto evaluate = [&](int k) -> hipError_t {
+    // cost, B, J^T J and J^T r at theta[k], into slot k
+    auto evaluate = [&](int k, const int32_t* gate) -> hipError_t {
         hipError_t e;
-        double* B = op.BF[k];
-        double* F = op.BF[k] + (size_t)r * r;
-        if ((e = vp_basis(st, T, r, op.theta[k], model->kind, op.Phi, op.E))) return e;
+        if ((e = vp_basis(st, T, r, op.theta[k], model->kind, op.Phi, E, gate))) return e;
         // products over the T snapshots as FP64 MFMA reductions
-        if ((e = tn64(op.Phi, op.Phi, 1, op.PtP))) return e;
-        if ((e = tn64(op.Phi, op.Yd, 0, op.PtYE))) return e;
-        if ((e = tn64(op.Phi, op.E, 0, op.PtYE + (size_t)r * r))) return e;
-        if ((e = fill_i32(st, op.scr, 16, 0))) return e;
-        if ((e = chol_inv(st, op.PtP, r, r, op.Rv, r, nullptr, 0, shift_scale, op.scr + 1, op.scr, nullptr))) return e;
+        if ((e = tn64(op.Phi, op.Phi, r, 1, op.PtP, gate))) return e;
+        if ((e = tn64(op.Phi, op.YE, 2 * r, 0, op.PtYE, gate))) return e;     // Phi^T [Y | E]
+        if ((e = chol_inv(st, op.PtP, r, r, op.Rv, r, nullptr, 0, shift_scale, op.scr + 1, op.scr, gate))) return e;
         // [B | F] = (Phi^T Phi)^-1 Phi^T [Y | E]
-        if ((e = small_gemm(st, 1, 0, r, 2 * r, r, 1.0, op.Rv, r, op.PtYE, r, 0.0, op.tmp, r))) return e;
-        if ((e = small_gemm(st, 0, 0, r, 2 * r, r, 1.0, op.Rv, r, op.tmp, r, 0.0, op.BF[k], r))) return e;
-        // R = Y - Phi B, E~ = E - Phi F
-        if ((e = copy_f64(st, T, r, r, op.Yd, T, op.R, T))) return e;
-        if ((e = small_gemm(st, 0, 0, T, r, r, -1.0, op.Phi, T, B, r, 1.0, op.R, T))) return e;
-        if ((e = copy_f64(st, T, r, r, op.E, T, op.Et, T))) return e;
-        if ((e = small_gemm(st, 0, 0, T, r, r, -1.0, op.Phi, T, F, r, 1.0, op.Et, T))) return e;
+        if ((e = small_gemm(st, 1, 0, r, 2 * r, r, 1.0, op.Rv, r, op.PtYE, r, 0.0, op.tmp, r, gate))) return e;
+        if ((e = small_gemm(st, 0, 0, r, 2 * r, r, 1.0, op.Rv, r, op.tmp, r, 0.0, op.BF[k], r, gate))) return e;
+        // [R | E~] = [Y | E] - Phi [B | F]
+        if ((e = copy_f64(st, T, 2 * r, 2 * r, op.YE, T, op.RE, T, 1.0, gate))) return e;
+        if ((e = small_gemm(st, 0, 0, T, 2 * r, r, -1.0, op.Phi, T, op.BF[k], r, 1.0, op.RE, T, gate))) return e;
         // K = E~^T E~, W = B B^T, H = E^T R B^T
-        if ((e = tn64(op.Et, op.Et, 1, op.K))) return e;
-        if ((e = small_gemm(st, 0, 1, r, r, r, 1.0, B, r, B, r, 0.0, op.Wm, r))) return e;
-        if ((e = tn64(op.E, op.R, 0, op.ER))) return e;
-        if ((e = small_gemm(st, 0, 1, r, r, r, 1.0, op.ER, r, B, r, 0.0, op.H, r))) return e;
-        if ((e = vp_sumsq(st, T, r, op.R, T, op.cost + k))) return e;
-        return vp_assemble(st, r, model->kind, op.K, op.Wm, op.H, op.G[k], op.g[k]);
+        if ((e = tn64(Et, Et, r, 1, op.K, gate))) return e;
+        if ((e = small_gemm(st, 0, 1, r, r, r, 1.0, op.BF[k], r, op.BF[k], r, 0.0, op.Wm, r, gate))) return e;
+        if ((e = tn64(E, R, r, 0, op.ER, gate))) return e;
+        if ((e = small_gemm(st, 0, 1, r, r, r, 1.0, op.ER, r, op.BF[k], r, 0.0, op.H, r, gate))) return e;
+        if ((e = vp_sumsq(st, T, r, R, T, op.cost + k, gate))) return e;
+        return vp_assemble(st, r, model->kind, op.K, op.Wm, op.H, op.G[k], op.g[k], gate);
     };
-    auto read_cost = [&](int k, double* c, int32_t* chol_status) -> hipError_t {
-        hipError_t e = hipMemcpyAsync(c, op.cost + k, sizeof(double), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(chol_status, op.scr, sizeof(int32_t), hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-        return e;
+    // one trial point from the current point (slot 0) into slot 1, then the decision
+    auto trial = [&]() -> hipError_t {
+        hipError_t e;
+        if ((e = vp_damp(st, r, op.G[0], op.vst + VP_MU, op.A, run, op.scr))) return e;
+        if ((e = chol_inv(st, op.A, r, r, op.RinvA, r, nullptr, 0, 0.0, nullptr, op.scr, run))) return e;
+        if ((e = normal_solve(st, r, op.RinvA, r, op.g[0], op.delta, 0, run))) return e;
+        if ((e = vp_update(st, r, op.theta[0], op.delta, op.theta[1], run, op.scr, op.ist))) return e;
+        if ((e = evaluate(1, run))) return e;
+        if ((e = vp_decide(st, op.cost + 1, op.scr, op.ist, op.vst))) return e;
+        return vp_commit(st, r, op.ist, op.theta[1], op.theta[0], op.BF[1], op.BF[0], op.G[1], op.G[0], op.g[1],
+                         op.g[0]);
     };
-    HIPCHK(evaluate(0));
-    double cost = 0.0;
-    int32_t cs = 0;
-    HIPCHK(read_cost(0, &cost, &cs));
-    int cur = 0, steps = 0;
-    double mu = 1e-3;
-    if (cs == 0 && isfinite(cost)) {
-        for (; steps < VP_MAX_STEPS; ++steps) {
-            bool kept = false;
-            double gain = 0.0;
-            for (int tr = 0; tr < VP_MAX_TRIES && mu <= 1e20; ++tr) {
-                const int nx = cur ^ 1;
-                HIPCHK(vp_damp(st, r, op.G[cur], mu, op.A));
-                HIPCHK(fill_i32(st, op.scr, 16, 0));
-                HIPCHK(chol_inv(st, op.A, r, r, op.RinvA, r, nullptr, 0, 0.0, nullptr, op.scr, nullptr));
-                HIPCHK(normal_solve(st, r, op.RinvA, r, op.g[cur], op.delta, 0));
-                int32_t cs_a = 0;
-                HIPCHK(hipMemcpyAsync(&cs_a, op.scr, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-                HIPCHK(vp_update(st, r, op.theta[cur], op.delta, op.theta[nx]));
-                HIPCHK(evaluate(nx));
-                double c_new = 0.0;
-                int32_t cs_n = 0;
-                HIPCHK(read_cost(nx, &c_new, &cs_n));
-                if (cs_a == 0 && cs_n == 0 && isfinite(c_new) && c_new < cost) {
-                    gain = cost - c_new;
-                    cost = c_new;
-                    cur = nx;
-                    mu = std::max(mu * 0.25, 1e-12);
-                    kept = true;
-                    break;
-                }
-                mu *= 4.0;
-            }
-            if (!kept) break;
-            if (gain <= 1e-13 * cost) { ++steps; break; }
+    HIPCHK(evaluate(0, apply));
+    HIPCHK(vp_start(st, op.cost, op.scr, op.ist, op.vst));
+    if (wait) {
+        // the device stops the iteration after at most VP_MAX_STEPS (VP_MAX_TRIES + 1) trial points
+        const int cap = VP_MAX_STEPS * (VP_MAX_TRIES + 1) + VP_GROUP;
+        for (int done = 0; done < cap; done += VP_GROUP) {
+            for (int t = 0; t < VP_GROUP; ++t) HIPCHK(trial());
+            int32_t going = 0;
+            HIPCHK(hipMemcpyAsync(&going, run, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            if (!going) break;
         }
-    }
-    *steps_out = steps;
-    // modes of eq. phi_optdmd: Phi = basis C with C = U_B,r B^T (randomized; basis Q) or
-    // V_r S_r^-1 B^T (exact; basis X), columns scaled into the folded unit-norm form
-    const double* B = op.BF[cur];
-    HIPCHK(vp_lift(st, r, model->kind, op.theta[cur], B, model->lam, model->b, op.scale));
-    if (!exact) {
-        HIPCHK(small_gemm(st, 0, 1, l, r, r, 1.0, fb.Ueig, l, B, r, 0.0, op.C, l));
     } else {
-        HIPCHK(copy_f64(st, T, r, r, fb.Ueig, T, op.Et, T));          // V_r S_r^-1 (scratch)
-        HIPCHK(scale_cols(st, T, r, op.Et, T, fb.sigma, 1));
-        HIPCHK(small_gemm(st, 0, 1, T, r, r, 1.0, op.Et, T, B, r, 0.0, op.C, T));
+        const int n_trials = o.optdmd_trials > 0 ? o.optdmd_trials : VP_DEFAULT_TRIALS;
+        for (int t = 0; t < n_trials; ++t) HIPCHK(trial());
+    }
+    // modes of eq. phi_optdmd: Phi = basis C with C = U_B,r B^T (randomized; basis Q) or
+    // V_r S_r^-1 B^T (exact; basis X), columns scaled into the folded unit-norm form; a
+    // refinement that did not apply leaves the fit's model as it is
+    const double* B = op.BF[0];
+    HIPCHK(vp_lift(st, r, model->kind, op.theta[0], B, model->lam, model->b, op.scale, apply));
+    if (!exact) {
+        HIPCHK(small_gemm(st, 0, 1, l, r, r, 1.0, fb.Ueig, l, B, r, 0.0, op.C, l, apply));
+    } else {
+        HIPCHK(copy_f64(st, T, r, r, fb.Ueig, T, Et, T, 1.0, apply));          // V_r S_r^-1 (scratch)
+        HIPCHK(scale_cols(st, T, r, Et, T, fb.sigma, 1));
+        HIPCHK(small_gemm(st, 0, 1, T, r, r, 1.0, Et, T, B, r, 0.0, op.C, T, apply));
     }
     HIPCHK(scale_cols(st, rows, r, op.C, rows, op.scale, 0));
     const int64_t ldphi = model->ldphi;
     if (a.xdtype == DMD_F32) HIPCHK(to_f32(st, rows, r, (int)ldphi, op.C, rows, (float*)op.Cf, rows));
     else HIPCHK(copy_f64(st, rows, r, (int)ldphi, op.C, rows, (double*)op.Cf, rows));
-    if (!exact) HIPCHK(gemm_nn(st, a.xdtype, fb.Q, fb.ldq, op.Cf, rows, model->phi, ldphi, 1, a.n, rows, (int)ldphi, nullptr));
-    else HIPCHK(gemm_nn(st, a.xdtype, a.x, a.ldx, op.Cf, rows, model->phi, ldphi, 1, a.n, rows, (int)ldphi, nullptr));
+    if (!exact) HIPCHK(gemm_nn(st, a.xdtype, fb.Q, fb.ldq, op.Cf, rows, model->phi, ldphi, 1, a.n, rows, (int)ldphi, apply));
+    else HIPCHK(gemm_nn(st, a.xdtype, a.x, a.ldx, op.Cf, rows, model->phi, ldphi, 1, a.n, rows, (int)ldphi, apply));
+    HIPCHK(vp_finish(st, op.ist, model->info));
     return DMD_OK;
 }
 
@@ -879,15 +874,8 @@ int32_t dmd_fit(void* stream, const void* x, const void* xp, int64_t n, int32_t 
     Carver cv(ws);
     FitBufs fb{};
     if (int32_t e = fit_plan(cv, st, a, model, &fb)) return e;
-    if (opts->flags & DMD_FIT_OPTDMD) {
-        int32_t status = 0;
-        HIPCHK(hipMemcpyAsync(&status, model->info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        if (status != DMD_OK) return status;
-        int steps = 0;
-        if (int32_t e = optdmd_refine(st, a, model, fb, &steps)) return e;
-        HIPCHK(fill_i32(st, model->info + 4, 1, steps));
-    }
+    if (opts->flags & DMD_FIT_OPTDMD)
+        if (int32_t e = optdmd_refine(st, a, model, fb, !(opts->flags & DMD_FIT_ASYNC))) return e;
     if (opts->flags & DMD_FIT_ASYNC) return DMD_OK;
     int32_t status = 0;
     HIPCHK(hipMemcpyAsync(&status, model->info, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -1359,7 +1347,6 @@ int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes, 
         FitArgs a{sc.x, sc.xp, sc.n, sc.ncols, sc.ldx, sc.ldxp, sc.xdtype, sc.opts,
                   is_shifted_view(sc.x, sc.xp, sc.ldx, sc.ldxp, sc.xdtype)};
         if (int32_t e = validate_fit(a, &models[i], true)) return e;
-        if (sc.opts.flags & DMD_FIT_OPTDMD) return DMD_ERR_UNSUPPORTED;   // host-driven refinement
         size_t need = 0;
         if (int32_t e = dmd_fit_workspace_size(sc.n, sc.ncols, sc.xdtype, &sc.opts, &need)) return e;
         if (!sc.ws || sc.ws_bytes < need) return DMD_ERR_WORKSPACE;
@@ -1397,7 +1384,10 @@ int32_t dmd_fit_batched(void* stream, int32_t nscenes, const dmd_scene* scenes, 
             models[i].dt = sc.opts.dt;
             if (hipStreamWaitEvent(g->streams[i], g->events[nscenes], 0) != hipSuccess) return DMD_ERR_HIP;
             Carver cv(sc.ws);
-            if (int32_t st = fit_plan(cv, g->streams[i], a, &models[i])) return st;
+            FitBufs fb{};
+            if (int32_t st = fit_plan(cv, g->streams[i], a, &models[i], &fb)) return st;
+            if (a.o.flags & DMD_FIT_OPTDMD)
+                if (int32_t st = optdmd_refine(g->streams[i], a, &models[i], fb, false)) return st;
             if (hipEventRecord(g->events[i], g->streams[i]) != hipSuccess) return DMD_ERR_HIP;
             if (hipStreamWaitEvent(origin, g->events[i], 0) != hipSuccess) return DMD_ERR_HIP;
         }

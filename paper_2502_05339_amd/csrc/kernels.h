@@ -86,10 +86,11 @@ hipError_t chol_inv(hipStream_t s, const double* G, int64_t ldg, int n, double* 
 size_t sym_eig_workspace_bytes(int n);
 hipError_t sym_eig(hipStream_t s, const double* S, int64_t lds, int n, int nv, double* evals, double* Vout,
                    int64_t ldv, void* ws, int32_t* info);
-// C = alpha op(A) op(B) + beta C, all FP64 column-major, small sizes.
+// C = alpha op(A) op(B) + beta C, all FP64 column-major, small sizes.  A launcher's
+// `run` (where present, may be null): the kernel does nothing when *run == 0.
 hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                      double* C, int64_t ldc);
+                      double* C, int64_t ldc, const int32_t* run = nullptr);
 // Scale column j of A (m x n) by d[j] (or 1/d[j] with inv): A(:, j) *= f(d[j]).
 hipError_t scale_cols(hipStream_t s, int m, int n, double* A, int64_t lda, const double* d, int mode);
 // sigma = sqrt(max(evals, 0))[0..r) (squared = 1: evals are squares) or max(evals, 0)
@@ -102,13 +103,13 @@ hipError_t jw_build(hipStream_t s, int n, const double* R, int64_t ldr, double* 
 hipError_t to_f32(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, float* B,
                   int64_t ldb);
 hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, double* B,
-                    int64_t ldb, double scale = 1.0);   // B = scale A
+                    int64_t ldb, double scale = 1.0, const int32_t* run = nullptr);   // B = scale A
 // Least-squares amplitudes from the Gram of the folded modes: beta = G^-1 rhs via
 // Rinv (beta_ws: r doubles), then complex b for each (real | pair) mode.
 hipError_t amplitudes(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs,
                       const int32_t* kind, double* b, double* beta_ws);
 hipError_t normal_solve(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs, double* beta,
-                        int accumulate);
+                        int accumulate, const int32_t* run = nullptr);
 hipError_t beta_to_b(hipStream_t s, int r, const double* beta, const int32_t* kind, double* b);
 // res = x - Phi beta (one FP64 dot per row), in the model's element type
 hipError_t residual(hipStream_t s, int dtype, int64_t N, int r, const void* phi, int64_t ldphi, const double* beta,
@@ -146,15 +147,31 @@ hipError_t lowres_project(hipStream_t s, int dtype, const void* h, int64_t ldh, 
                           int64_t ldx, int64_t nframes, int ncomp, int nz, int ny, int nx, int f);
 
 // ---- OptDMD by variable projection (optdmd.hip), real folded parameters theta
+// Levenberg-Marquardt state on the device: ist (VP_IST_WORDS int32), vst (2 doubles)
+constexpr int VP_RUN = 0, VP_ACCEPT = 1, VP_STEPS = 2, VP_TRIES = 3, VP_TRIALS = 4, VP_DAMPED = 5,
+              VP_APPLY = 6, VP_FIT_OK = 7, VP_IST_WORDS = 8;
+constexpr int VP_COST = 0, VP_MU = 1;
+constexpr int VP_MAX_STEPS = 200;      // kept steps (the oracle's cap)
+constexpr int VP_MAX_TRIES = 40;       // rejected trial points in a row
+constexpr double VP_MU0 = 1e-3, VP_MU_MIN = 1e-12, VP_MU_MAX = 1e20, VP_GAIN_TOL = 1e-13;
 hipError_t vp_theta_init(hipStream_t s, int r, const double* lam, const int32_t* kind, double* theta);
-hipError_t vp_basis(hipStream_t s, int T, int r, const double* theta, const int32_t* kind, double* Phi, double* E);
+hipError_t vp_basis(hipStream_t s, int T, int r, const double* theta, const int32_t* kind, double* Phi, double* E,
+                    const int32_t* run);
 hipError_t vp_assemble(hipStream_t s, int r, const int32_t* kind, const double* K, const double* W, const double* H,
-                       double* G, double* g);
-hipError_t vp_sumsq(hipStream_t s, int m, int n, const double* A, int64_t lda, double* out);
-hipError_t vp_damp(hipStream_t s, int r, const double* G, double mu, double* A);
-hipError_t vp_update(hipStream_t s, int r, const double* theta, const double* delta, double* out);
+                       double* G, double* g, const int32_t* run);
+hipError_t vp_sumsq(hipStream_t s, int m, int n, const double* A, int64_t lda, double* out, const int32_t* run);
+hipError_t vp_damp(hipStream_t s, int r, const double* G, const double* mu, double* A, const int32_t* run,
+                   int32_t* scr);
+hipError_t vp_update(hipStream_t s, int r, const double* theta, const double* delta, double* out, const int32_t* run,
+                     int32_t* scr, int32_t* ist);
 hipError_t vp_lift(hipStream_t s, int r, const int32_t* kind, const double* theta, const double* B, double* lam,
-                   double* b, double* scale);
+                   double* b, double* scale, const int32_t* run);
+hipError_t vp_begin(hipStream_t s, const int32_t* fit_info, int32_t* ist, int32_t* scr);
+hipError_t vp_start(hipStream_t s, const double* cost0, const int32_t* scr, int32_t* ist, double* vst);
+hipError_t vp_decide(hipStream_t s, const double* cost_t, const int32_t* scr, int32_t* ist, double* vst);
+hipError_t vp_commit(hipStream_t s, int r, const int32_t* ist, const double* theta_t, double* theta_c,
+                     const double* bf_t, double* bf_c, const double* G_t, double* G_c, const double* g_t, double* g_c);
+hipError_t vp_finish(hipStream_t s, const int32_t* ist, int32_t* info);
 
 // ---- adjoint (adjoint.hip)
 // Refit statistics (adjoint.hip): FP64 sum of squares of an N x ncols matrix as at most

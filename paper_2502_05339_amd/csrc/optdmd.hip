@@ -44,8 +44,9 @@ __global__ void vp_theta_init_kernel(int r, const double* __restrict__ lam, cons
 
 // Phi(theta) and E(theta), T x r column-major (ld T)
 __global__ void vp_basis_kernel(int T, int r, const double* __restrict__ theta, const int32_t* __restrict__ kind,
-                                double* __restrict__ Phi, double* __restrict__ E)
+                                double* __restrict__ Phi, double* __restrict__ E, const int32_t* __restrict__ run)
 {
+    if (*run == 0) return;
     const int64_t tot = (int64_t)T * r;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
         const int t = (int)(e % T), c = (int)(e / T);
@@ -64,8 +65,9 @@ __global__ void vp_basis_kernel(int T, int r, const double* __restrict__ theta, 
 // G = J^T J and g = J^T r from K, W, H (r x r, column-major); one thread per entry of G
 __global__ void vp_assemble_kernel(int r, const int32_t* __restrict__ kind, const double* __restrict__ K,
                                    const double* __restrict__ W, const double* __restrict__ H,
-                                   double* __restrict__ G, double* __restrict__ g)
+                                   double* __restrict__ G, double* __restrict__ g, const int32_t* __restrict__ run)
 {
+    if (*run == 0) return;
     const int64_t tot = (int64_t)r * r;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
         const int p = (int)(e % r), q = (int)(e / r);
@@ -90,8 +92,10 @@ __global__ void vp_assemble_kernel(int r, const int32_t* __restrict__ kind, cons
 // threads, four loads in flight per thread, fixed-order combination)
 constexpr int VP_SS_THREADS = 1024;
 __global__ void __launch_bounds__(VP_SS_THREADS) vp_sumsq_kernel(int m, int n, const double* __restrict__ A,
-                                                                 int64_t lda, double* __restrict__ out)
+                                                                 int64_t lda, double* __restrict__ out,
+                                                                 const int32_t* __restrict__ run)
 {
+    if (*run == 0) return;
     __shared__ double part[VP_SS_THREADS / 64];
     const int64_t tot = (int64_t)m * n;
     double s = 0.0;
@@ -115,10 +119,15 @@ __global__ void __launch_bounds__(VP_SS_THREADS) vp_sumsq_kernel(int m, int n, c
     }
 }
 
-// A = G + mu diag(G) (a small floor keeps the diagonal positive)
-__global__ void __launch_bounds__(256) vp_damp_kernel(int r, const double* __restrict__ G, double mu,
-                                                      double* __restrict__ A)
+// A = G + mu diag(G) (a small floor keeps the diagonal positive); clears the status
+// words of the Cholesky factorisation that follows
+__global__ void __launch_bounds__(256) vp_damp_kernel(int r, const double* __restrict__ G,
+                                                      const double* __restrict__ mu_p, double* __restrict__ A,
+                                                      const int32_t* __restrict__ run, int32_t* __restrict__ scr)
 {
+    if (*run == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x < 2) scr[threadIdx.x] = 0;
+    const double mu = *mu_p;
     __shared__ double part[4];
     const int64_t tot = (int64_t)r * r;
     double dm = 0.0;                                     // max of the diagonal, per work-group
@@ -136,10 +145,94 @@ __global__ void __launch_bounds__(256) vp_damp_kernel(int r, const double* __res
     }
 }
 
+// trial point theta - delta; keeps the status of the damped solve and clears the status
+// words for the trial's own factorisation
 __global__ void vp_update_kernel(int r, const double* __restrict__ theta, const double* __restrict__ delta,
-                                 double* __restrict__ out)
+                                 double* __restrict__ out, const int32_t* __restrict__ run,
+                                 int32_t* __restrict__ scr, int32_t* __restrict__ ist)
 {
+    if (*run == 0) return;
     for (int c = threadIdx.x; c < r; c += blockDim.x) out[c] = theta[c] - delta[c];
+    if (threadIdx.x == 0) {
+        ist[VP_DAMPED] = scr[0];
+        scr[0] = 0;
+        scr[1] = 0;
+    }
+}
+
+// ---- the iteration's control, on the device.  A trial point is evaluated only while
+// ist[VP_RUN] is set; vp_decide_kernel takes the keep / reject decision and the stopping
+// rule from the device values alone, so the sequence of launches is the same whatever
+// the outcome (and can be captured).
+__global__ void vp_begin_kernel(const int32_t* __restrict__ fit_info, int32_t* __restrict__ ist,
+                                int32_t* __restrict__ scr)
+{
+    const int i = threadIdx.x;
+    if (i < VP_IST_WORDS) ist[i] = i == VP_FIT_OK || i == VP_APPLY ? (fit_info[0] == 0 ? 1 : 0) : 0;
+    if (i < 16) scr[i] = 0;
+}
+
+__global__ void vp_start_kernel(const double* __restrict__ cost0, const int32_t* __restrict__ scr,
+                                int32_t* __restrict__ ist, double* __restrict__ vst)
+{
+    if (threadIdx.x != 0 || ist[VP_APPLY] == 0) return;
+    const double c = *cost0;
+    const bool ok = scr[0] == 0 && isfinite(c);
+    ist[VP_APPLY] = ok ? 1 : 0;      // a singular or non-finite start leaves the plain fit
+    ist[VP_RUN] = ok ? 1 : 0;
+    vst[VP_COST] = c;
+    vst[VP_MU] = VP_MU0;
+}
+
+__global__ void vp_decide_kernel(const double* __restrict__ cost_t, const int32_t* __restrict__ scr,
+                                 int32_t* __restrict__ ist, double* __restrict__ vst)
+{
+    if (threadIdx.x != 0) return;
+    if (ist[VP_RUN] == 0) { ist[VP_ACCEPT] = 0; return; }
+    ist[VP_TRIALS] += 1;
+    const double c_new = *cost_t, cost = vst[VP_COST];
+    double mu = vst[VP_MU];
+    if (ist[VP_DAMPED] == 0 && scr[0] == 0 && isfinite(c_new) && c_new < cost) {
+        const double gain = cost - c_new;
+        vst[VP_COST] = c_new;
+        vst[VP_MU] = fmax(mu * 0.25, VP_MU_MIN);
+        ist[VP_ACCEPT] = 1;
+        ist[VP_TRIES] = 0;
+        ist[VP_STEPS] += 1;
+        if (gain <= VP_GAIN_TOL * c_new || ist[VP_STEPS] >= VP_MAX_STEPS) ist[VP_RUN] = 0;
+    } else {
+        mu *= 4.0;
+        vst[VP_MU] = mu;
+        ist[VP_ACCEPT] = 0;
+        ist[VP_TRIES] += 1;
+        if (ist[VP_TRIES] >= VP_MAX_TRIES || mu > VP_MU_MAX) ist[VP_RUN] = 0;
+    }
+}
+
+// a kept trial point becomes the current one: theta, [B | F], J^T J and J^T r
+__global__ void vp_commit_kernel(int r, const int32_t* __restrict__ ist, const double* __restrict__ theta_t,
+                                 double* __restrict__ theta_c, const double* __restrict__ bf_t,
+                                 double* __restrict__ bf_c, const double* __restrict__ G_t, double* __restrict__ G_c,
+                                 const double* __restrict__ g_t, double* __restrict__ g_c)
+{
+    if (ist[VP_ACCEPT] == 0) return;
+    const int64_t rr = (int64_t)r * r, tot = 3 * rr + 2 * (int64_t)r;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < 2 * rr) bf_c[e] = bf_t[e];
+        else if (e < 3 * rr) G_c[e - 2 * rr] = G_t[e - 2 * rr];
+        else if (e < 3 * rr + r) g_c[e - 3 * rr] = g_t[e - 3 * rr];
+        else theta_c[e - 3 * rr - r] = theta_t[e - 3 * rr - r];
+    }
+}
+
+// info[4] kept steps, info[5] trial points, info[6] outcome (0 stopped by its rule, 1 still
+// running when the trial points ran out, 2 not applied: singular or non-finite start)
+__global__ void vp_finish_kernel(const int32_t* __restrict__ ist, int32_t* __restrict__ info)
+{
+    if (threadIdx.x != 0 || ist[VP_FIT_OK] == 0) return;
+    info[4] = ist[VP_STEPS];
+    info[5] = ist[VP_TRIALS];
+    info[6] = ist[VP_APPLY] == 0 ? 2 : (ist[VP_RUN] != 0 ? 1 : 0);
 }
 
 // eigenvalues, amplitudes and column scales of the lifted modes (eq. phi_optdmd): with
@@ -148,8 +241,9 @@ __global__ void vp_update_kernel(int r, const double* __restrict__ theta, const 
 // folded columns are M_c / (2 b) and -M_{c+1} / (2 b); a real mode has b = ||B_c||.
 __global__ void vp_lift_kernel(int r, const int32_t* __restrict__ kind, const double* __restrict__ theta,
                                const double* __restrict__ B, double* __restrict__ lam, double* __restrict__ b,
-                               double* __restrict__ scale)
+                               double* __restrict__ scale, const int32_t* __restrict__ run)
 {
+    if (*run == 0) return;
     for (int c = threadIdx.x; c < r; c += blockDim.x) {
         int kd = kind[c];
         if ((kd == 1 && c + 1 >= r) || (kd == 2 && c == 0) || kd < 0 || kd > 2) kd = 0;
@@ -173,39 +267,70 @@ hipError_t vp_theta_init(hipStream_t s, int r, const double* lam, const int32_t*
     hipLaunchKernelGGL(vp_theta_init_kernel, dim3(1), dim3(256), 0, s, r, lam, kind, theta);
     return hipGetLastError();
 }
-hipError_t vp_basis(hipStream_t s, int T, int r, const double* theta, const int32_t* kind, double* Phi, double* E)
+hipError_t vp_basis(hipStream_t s, int T, int r, const double* theta, const int32_t* kind, double* Phi, double* E,
+                    const int32_t* run)
 {
     const int blocks = (int)std::min<int64_t>(ceil_div((int64_t)T * r, 256), 1024);
-    hipLaunchKernelGGL(vp_basis_kernel, dim3(blocks), dim3(256), 0, s, T, r, theta, kind, Phi, E);
+    hipLaunchKernelGGL(vp_basis_kernel, dim3(blocks), dim3(256), 0, s, T, r, theta, kind, Phi, E, run);
     return hipGetLastError();
 }
 hipError_t vp_assemble(hipStream_t s, int r, const int32_t* kind, const double* K, const double* W, const double* H,
-                       double* G, double* g)
+                       double* G, double* g, const int32_t* run)
 {
     const int blocks = (int)ceil_div((int64_t)r * r, 256);
-    hipLaunchKernelGGL(vp_assemble_kernel, dim3(blocks), dim3(256), 0, s, r, kind, K, W, H, G, g);
+    hipLaunchKernelGGL(vp_assemble_kernel, dim3(blocks), dim3(256), 0, s, r, kind, K, W, H, G, g, run);
     return hipGetLastError();
 }
-hipError_t vp_sumsq(hipStream_t s, int m, int n, const double* A, int64_t lda, double* out)
+hipError_t vp_sumsq(hipStream_t s, int m, int n, const double* A, int64_t lda, double* out, const int32_t* run)
 {
-    hipLaunchKernelGGL(vp_sumsq_kernel, dim3(1), dim3(VP_SS_THREADS), 0, s, m, n, A, lda, out);
+    hipLaunchKernelGGL(vp_sumsq_kernel, dim3(1), dim3(VP_SS_THREADS), 0, s, m, n, A, lda, out, run);
     return hipGetLastError();
 }
-hipError_t vp_damp(hipStream_t s, int r, const double* G, double mu, double* A)
+hipError_t vp_damp(hipStream_t s, int r, const double* G, const double* mu, double* A, const int32_t* run,
+                   int32_t* scr)
 {
     const int blocks = (int)ceil_div((int64_t)r * r, 256);
-    hipLaunchKernelGGL(vp_damp_kernel, dim3(blocks), dim3(256), 0, s, r, G, mu, A);
+    hipLaunchKernelGGL(vp_damp_kernel, dim3(blocks), dim3(256), 0, s, r, G, mu, A, run, scr);
     return hipGetLastError();
 }
-hipError_t vp_update(hipStream_t s, int r, const double* theta, const double* delta, double* out)
+hipError_t vp_update(hipStream_t s, int r, const double* theta, const double* delta, double* out, const int32_t* run,
+                     int32_t* scr, int32_t* ist)
 {
-    hipLaunchKernelGGL(vp_update_kernel, dim3(1), dim3(256), 0, s, r, theta, delta, out);
+    hipLaunchKernelGGL(vp_update_kernel, dim3(1), dim3(256), 0, s, r, theta, delta, out, run, scr, ist);
     return hipGetLastError();
 }
 hipError_t vp_lift(hipStream_t s, int r, const int32_t* kind, const double* theta, const double* B, double* lam,
-                   double* b, double* scale)
+                   double* b, double* scale, const int32_t* run)
 {
-    hipLaunchKernelGGL(vp_lift_kernel, dim3(1), dim3(256), 0, s, r, kind, theta, B, lam, b, scale);
+    hipLaunchKernelGGL(vp_lift_kernel, dim3(1), dim3(256), 0, s, r, kind, theta, B, lam, b, scale, run);
+    return hipGetLastError();
+}
+hipError_t vp_begin(hipStream_t s, const int32_t* fit_info, int32_t* ist, int32_t* scr)
+{
+    hipLaunchKernelGGL(vp_begin_kernel, dim3(1), dim3(64), 0, s, fit_info, ist, scr);
+    return hipGetLastError();
+}
+hipError_t vp_start(hipStream_t s, const double* cost0, const int32_t* scr, int32_t* ist, double* vst)
+{
+    hipLaunchKernelGGL(vp_start_kernel, dim3(1), dim3(64), 0, s, cost0, scr, ist, vst);
+    return hipGetLastError();
+}
+hipError_t vp_decide(hipStream_t s, const double* cost_t, const int32_t* scr, int32_t* ist, double* vst)
+{
+    hipLaunchKernelGGL(vp_decide_kernel, dim3(1), dim3(64), 0, s, cost_t, scr, ist, vst);
+    return hipGetLastError();
+}
+hipError_t vp_commit(hipStream_t s, int r, const int32_t* ist, const double* theta_t, double* theta_c,
+                     const double* bf_t, double* bf_c, const double* G_t, double* G_c, const double* g_t, double* g_c)
+{
+    const int blocks = (int)std::min<int64_t>(ceil_div(3 * (int64_t)r * r + 2 * r, 256), 256);
+    hipLaunchKernelGGL(vp_commit_kernel, dim3(blocks), dim3(256), 0, s, r, ist, theta_t, theta_c, bf_t, bf_c, G_t, G_c,
+                       g_t, g_c);
+    return hipGetLastError();
+}
+hipError_t vp_finish(hipStream_t s, const int32_t* ist, int32_t* info)
+{
+    hipLaunchKernelGGL(vp_finish_kernel, dim3(1), dim3(64), 0, s, ist, info);
     return hipGetLastError();
 }
 

@@ -293,8 +293,10 @@ constexpr int SG_KC = 32;
 constexpr int SG_LD = SG_T + 2;   // 16-byte aligned rows
 __global__ void __launch_bounds__(256)
 small_gemm_kernel(int ta, int tb, int m, int n, int k, double alpha, const double* __restrict__ A, int64_t lda,
-                  const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc)
+                  const double* __restrict__ B, int64_t ldb, double beta, double* __restrict__ C, int64_t ldc,
+                  const int32_t* __restrict__ run)
 {
+    if (run && *run == 0) return;
     __shared__ __align__(16) double As[SG_KC * SG_LD];
     __shared__ __align__(16) double Bs[SG_KC * SG_LD];
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
@@ -341,11 +343,12 @@ small_gemm_kernel(int ta, int tb, int m, int n, int k, double alpha, const doubl
 
 hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
-                      double* C, int64_t ldc)
+                      double* C, int64_t ldc, const int32_t* run)
 {
     if (m <= 0 || n <= 0) return hipSuccess;
     const dim3 grid((unsigned)ceil_div(m, SG_T), (unsigned)ceil_div(n, SG_T));
-    hipLaunchKernelGGL(small_gemm_kernel, grid, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc);
+    hipLaunchKernelGGL(small_gemm_kernel, grid, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc,
+                       run);
     return hipGetLastError();
 }
 
@@ -424,8 +427,9 @@ __global__ void to_f32_kernel(int m, int n, int n_pad, const double* A, int64_t 
     }
 }
 __global__ void copy_f64_kernel(int m, int n, int n_pad, const double* A, int64_t lda, double* B, int64_t ldb,
-                                double scale)
+                                double scale, const int32_t* run)
 {
+    if (run && *run == 0) return;
     const int64_t tot = (int64_t)m * n_pad;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot;
          e += (int64_t)gridDim.x * blockDim.x) {
@@ -442,11 +446,11 @@ hipError_t to_f32(hipStream_t s, int m, int n, int n_pad, const double* A, int64
     return hipGetLastError();
 }
 hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int64_t lda, double* B, int64_t ldb,
-                    double scale)
+                    double scale, const int32_t* run)
 {
     if (m <= 0 || n_pad <= 0) return hipSuccess;
     hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)std::min<int64_t>(ceil_div((int64_t)m * n_pad, 256), 1024)), dim3(256), 0, s,
-                       m, n, n_pad, A, lda, B, ldb, scale);
+                       m, n, n_pad, A, lda, B, ldb, scale, run);
     return hipGetLastError();
 }
 
@@ -457,8 +461,9 @@ hipError_t copy_f64(hipStream_t s, int m, int n, int n_pad, const double* A, int
 constexpr int NS_THREADS = 1024;
 __global__ void __launch_bounds__(NS_THREADS)
 normal_solve_kernel(int r, const double* __restrict__ Rinv, int64_t ldr, const double* __restrict__ rhs,
-                    double* __restrict__ beta, int accumulate)
+                    double* __restrict__ beta, int accumulate, const int32_t* __restrict__ run)
 {
+    if (run && *run == 0) return;
     extern __shared__ double sh[];
     double* x = sh;          // rhs (r)
     double* t = sh + r;      // R^-T rhs (r)
@@ -510,10 +515,10 @@ __global__ void residual_kernel(int64_t N, int r, const T* __restrict__ phi, int
 }
 
 hipError_t normal_solve(hipStream_t s, int r, const double* Rinv, int64_t ldr, const double* rhs, double* beta,
-                        int accumulate)
+                        int accumulate, const int32_t* run)
 {
     hipLaunchKernelGGL(normal_solve_kernel, dim3(1), dim3(NS_THREADS), 2 * r * sizeof(double), s, r, Rinv, ldr, rhs,
-                       beta, accumulate);
+                       beta, accumulate, run);
     return hipGetLastError();
 }
 

@@ -41,7 +41,7 @@ def test_no_extra_exports():
 
 def test_version_and_strings(L):
     from paper_2502_05339_amd import _lib
-    assert L.dmd_abi_version() == 2
+    assert L.dmd_abi_version() == 3
     for code in range(0, 13):
         assert len(_lib.status_string(code)) >= 2
     assert "unknown" in _lib.status_string(99)
@@ -117,6 +117,11 @@ def test_fit_dtype_and_enum_validation(L):
     assert _ws_size(L, 1000, 30, 0, o)[0] == 1
     o = _opts(r=16, p=0, q=0, precision="fp64_exact")
     assert _ws_size(L, 8192, 64, 1, o)[0] == 0
+    for trials, expect in ((-1, 1), (0, 0), (500, 0), (100000, 0), (100001, 1)):
+        o = _opts()
+        o.flags = 4 | 1                     # OptDMD, asynchronous: a trial budget
+        o.optdmd_trials = trials
+        assert _ws_size(L, 1000, 30, 0, o)[0] == expect, trials
     assert _ws_size(L, 8192, 250, 1, _opts(r=16, p=0, q=0, precision="fp64_exact"))[0] == 11
 
 

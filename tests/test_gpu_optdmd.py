@@ -114,10 +114,94 @@ def test_optdmd_mixed_close_to_fp64(gpu_lib):
     assert err <= 1e-4
 
 
-def test_optdmd_rejects_async(gpu_lib):
+def _same(a, b):
+    return torch.equal(a, b)
+
+
+def test_optdmd_async_matches_waiting_call(gpu_lib):
+    """The iteration is decided on the device: an asynchronous call with enough trial
+    points enqueued gives bit for bit the model of the waiting call (which reads the run
+    flag after every 8 trial points), and reports the same steps and outcome."""
     import paper_2502_05339_amd as dmd
-    cfg = synth.config("c1-cf", seed=11)
+    cfg = synth.config("c1-cf", seed=11, sigma=1e-2, p=4, q=1)
+    g = synth.generate(cfg)
+    Z, om = _inputs(g, np.float64)
+    _print("case: optdmd async vs waiting, fp64 randomized")
+    m1 = dmd.fit(Z, cfg.r, p=cfg.p, q=cfg.q, omega=om, precision="fp64", optdmd=True)
+    m2 = dmd.fit(Z, cfg.r, p=cfg.p, q=cfg.q, omega=om, precision="fp64", optdmd=True, asynchronous=True,
+                 optdmd_trials=300)
+    torch.cuda.synchronize()
+    i1, i2 = m1.info.cpu().numpy(), m2.info.cpu().numpy()
+    _print(f"  waiting: steps {i1[4]} trials {i1[5]} outcome {i1[6]}; async: steps {i2[4]} trials {i2[5]} "
+           f"outcome {i2[6]}")
+    assert i1[0] == 0 and i2[0] == 0
+    assert i1[6] == 0 and i2[6] == 0
+    assert i1[4] >= 1 and i1[4] == i2[4] and i1[5] == i2[5]
+    assert _same(m1.lam, m2.lam) and _same(m1.b, m2.b) and _same(m1.phi, m2.phi)
+
+
+def test_optdmd_trial_budget(gpu_lib):
+    """With fewer trial points than the iteration needs, the asynchronous call stops at
+    the budget (outcome 1) with the model of the last kept point: its cost lies between
+    the start's and the converged one's."""
+    import paper_2502_05339_amd as dmd
+    cfg = synth.config("c1-cf", seed=13, sigma=1e-2, p=0, q=1)
     g = synth.generate(cfg)
     Z, _ = _inputs(g, np.float64)
-    with pytest.raises(dmd.DMDError):
-        dmd.fit(Z, cfg.r, precision="fp64_exact", optdmd=True, asynchronous=True)
+    _print("case: optdmd trial budget 2, fp64 exact")
+    m0 = dmd.fit(Z, cfg.r, precision="fp64_exact")
+    full = dmd.fit(Z, cfg.r, precision="fp64_exact", optdmd=True)
+    part = dmd.fit(Z, cfg.r, precision="fp64_exact", optdmd=True, asynchronous=True, optdmd_trials=2)
+    torch.cuda.synchronize()
+    ifull, ipart = full.info.cpu().numpy(), part.info.cpu().numpy()
+    _print(f"  full: steps {ifull[4]} trials {ifull[5]}; budget 2: steps {ipart[4]} trials {ipart[5]} "
+           f"outcome {ipart[6]}")
+    assert ifull[4] > 2
+    assert ipart[0] == 0 and ipart[5] == 2 and ipart[6] == 1 and 1 <= ipart[4] <= 2
+    X, _ = oracle.split_snapshots(g.Z.astype(np.float64))
+    U, s, V = oracle.thin_svd(X)
+    Yv = np.conj(V[:, :cfg.r].astype(np.complex128)) * s[None, :cfg.r]
+    c0 = oracle.varpro_trial(m0.lam_host(), Yv)[3]
+    cp = oracle.varpro_trial(part.lam_host(), Yv)[3]
+    cf = oracle.varpro_trial(full.lam_host(), Yv)[3]
+    _print(f"  cost start {c0:.9g} budget {cp:.9g} converged {cf:.9g}")
+    assert cf <= cp < c0
+
+
+def test_optdmd_in_captured_batch(gpu_lib):
+    """OptDMD inside dmd_fit_batched: the captured graph runs the device-decided iteration
+    for every scene; each replay reproduces the waiting single-scene fit bit for bit, and
+    the scenes match the oracle's variable projection."""
+    import paper_2502_05339_amd as dmd
+    scenes, cases = [], []
+    for seed, prec in ((11, "fp64_exact"), (12, "fp64"), (13, "fp64_exact")):
+        cfg = synth.config("c1-cf", seed=seed, sigma=1e-2, p=4 if prec == "fp64" else 0, q=1)
+        g = synth.generate(cfg)
+        Z, om = _inputs(g, np.float64)
+        scenes.append(dict(Z=Z, r=cfg.r, p=cfg.p, q=cfg.q, omega=om, precision=prec, optdmd=True,
+                           optdmd_trials=300))
+        cases.append((cfg, g, prec, Z, om))
+    _print("case: optdmd in a captured batch of 3 scenes")
+    bf = dmd.BatchedFit(scenes, capture=True)
+    singles = [dmd.fit(Z, cfg.r, p=cfg.p, q=cfg.q, omega=om, precision=prec, optdmd=True)
+               for cfg, g, prec, Z, om in cases]
+    for rep in range(2):
+        for m in bf.models:
+            m.lam.zero_()
+        bf.launch()
+        torch.cuda.synchronize()
+        for i, (m, s1) in enumerate(zip(bf.models, singles)):
+            info = m.info.cpu().numpy()
+            assert info[0] == 0 and info[6] == 0, (rep, i, info)
+            assert info[4] == int(s1.info[4].item())
+            assert _same(m.lam, s1.lam) and _same(m.b, s1.b) and _same(m.phi, s1.phi), (rep, i)
+    for i, (cfg, g, prec, Z, om) in enumerate(cases):
+        U_r, s_r, V_r, lam0 = _oracle_svd(g, cfg, prec)
+        a, phi, b, cost, it = oracle.fit_optdmd(U_r, s_r, V_r, lam0)
+        lam = bf.models[i].lam_host()
+        ia, ib = match_eigs(lam, a)
+        e_par = float(np.max(np.abs(lam[ia] - a[ib]) / np.abs(a[ib])))
+        _print(f"  scene {i} ({prec}): steps {int(bf.models[i].info[4].item())} (oracle {it}); "
+               f"lambda vs oracle {e_par:.3e}")
+        assert e_par <= 1e-6
+    bf.close()
