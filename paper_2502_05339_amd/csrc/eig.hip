@@ -308,68 +308,90 @@ __device__ __forceinline__ void crcp(double ar, double ai, double* rr, double* r
 // (r' and x' carried along).  Column-oriented: each lane keeps r and r' of its rows and
 // adds column j times x_j to them; the only divisions are the precomputed reciprocals of
 // the sub-diagonal.  Sub-diagonal entries below eps ||H||_F have been raised to that size
-// (a backward-stable perturbation), and x, x', r, r' are rescaled every four steps once
-// |x| passes 1e100 (the ratio does not change).
+// (a backward-stable perturbation), so one step multiplies |x| by at most about
+// n (|z| + ||H||) / (eps ||H||) < 1e19; every eight steps, once |x| passes 1e100, x, x',
+// r and r' are scaled by the power of two that brings |x| to [1, 2) (exact, and the ratio
+// does not change), which keeps them below 1e260.
 // Slot s of a lane holds row i = lane + 64 s.  In steps j with j >> 6 == JS the rows still
 // accumulating (i <= j) lie in slots 0 .. JS; the rows of those slots take the update
 // without a lane mask (column j is zero below row j + 1 in the packed layout, read as 0).
+// The steps run without branches: eight per block, the next column and reciprocal loaded
+// one step ahead by every lane (its own row, clamped into the column, then zeroed below
+// the diagonal), and the rescaling applied by a factor that is 1 when not needed.
 struct HyState {
     double rr[AB_SLOTS], ri[AB_SLOTS], pr[AB_SLOTS], pi[AB_SLOTS];   // r and r' of the rows
     double hc[AB_SLOTS];                                             // column j of H
+    double is;                                                       // 1 / h_{j,j-1}
     double xr, xi, xpr, xpi;                                         // x_j and x'_j
 };
 
+// column c (rows 0 .. c of slots 0 .. JS; the rest 0) into hc
 template <int JS>
-__device__ __forceinline__ void hy_load_col(const double* Hs, int j, int lane, double (&hc)[AB_SLOTS])
+__device__ __forceinline__ void hy_load_col(const double* Hs, int c, int lane, double (&hc)[AB_SLOTS])
 {
-    const double* col = Hs + hcol_off(j);                          // rows 0 .. j + 1
+    const double* col = Hs + hcol_off(c);
 #pragma unroll
     for (int s = 0; s <= JS; ++s) {
         const int i = lane + 64 * s;
-        hc[s] = (s < JS || i <= j) ? col[i] : 0.0;
+        const double v = col[min(i, c)];
+        hc[s] = (s < JS || i <= c) ? v : 0.0;
     }
 }
 
-// steps j = j_hi down to j_lo (all with j >> 6 == JS, j_lo >= 1): add column j to the rows,
-// then x_{j-1} = r_j / h_{j,j-1}
+// step j (j >= 1): add column j to the rows, then x_{j-1} = r_j / h_{j,j-1}
+template <int JS>
+__device__ __forceinline__ void hy_step(const double* Hs, const double* inv_sub, int lane, double zr, double zi,
+                                        int j, HyState& st)
+{
+    double hc[AB_SLOTS];
+#pragma unroll
+    for (int s = 0; s <= JS; ++s) hc[s] = st.hc[s];
+    const double is = st.is;
+    hy_load_col<JS>(Hs, j - 1, lane, st.hc);     // rows of slot JS lie below column j - 1 at a segment's end
+    st.is = inv_sub[j - 1];                      // inv_sub[0] is 0 (not used)
+    const double xr = st.xr, xi = st.xi, xpr = st.xpr, xpi = st.xpi;
+    // z x and x + z x' for the diagonal row j
+    const double zxr = fma(zr, xr, -zi * xi), zxi = fma(zr, xi, zi * xr);
+    const double zpr = xr + fma(zr, xpr, -zi * xpi), zpi = xi + fma(zr, xpi, zi * xpr);
+#pragma unroll
+    for (int s = 0; s <= JS; ++s) {
+        const int i = lane + 64 * s;
+        const bool dg = i == j;
+        st.rr[s] = fma(-hc[s], xr, st.rr[s]) + (dg ? zxr : 0.0);
+        st.ri[s] = fma(-hc[s], xi, st.ri[s]) + (dg ? zxi : 0.0);
+        st.pr[s] = fma(-hc[s], xpr, st.pr[s]) + (dg ? zpr : 0.0);
+        st.pi[s] = fma(-hc[s], xpi, st.pi[s]) + (dg ? zpi : 0.0);
+    }
+    const int jl = j & 63;
+    st.xr = bcast(st.rr[JS], jl) * is;
+    st.xi = bcast(st.ri[JS], jl) * is;
+    st.xpr = bcast(st.pr[JS], jl) * is;
+    st.xpi = bcast(st.pi[JS], jl) * is;
+}
+
+template <int JS>
+__device__ __forceinline__ void hy_rescale(HyState& st)
+{
+    const double big = fabs(st.xr) + fabs(st.xi);
+    const double f = big > 1e100 ? ldexp(1.0, -ilogb(big)) : 1.0;     // exact: a power of two
+    st.xr *= f; st.xi *= f; st.xpr *= f; st.xpi *= f;
+#pragma unroll
+    for (int s = 0; s <= JS; ++s) { st.rr[s] *= f; st.ri[s] *= f; st.pr[s] *= f; st.pi[s] *= f; }
+}
+
+// steps j = j_hi down to j_lo (all with j >> 6 == JS, j_lo >= 1)
 template <int JS>
 __device__ void hy_segment(const double* Hs, const double* inv_sub, int lane, double zr, double zi, int j_hi,
                            int j_lo, HyState& st)
 {
-    for (int j = j_hi; j >= j_lo; --j) {
-        double hc[AB_SLOTS];
+    int j = j_hi;
+    for (; j - 7 >= j_lo; j -= 8) {
 #pragma unroll
-        for (int s = 0; s <= JS; ++s) hc[s] = st.hc[s];
-        if (j - 1 >= 0) {
-            if (((j - 1) >> 6) == JS) hy_load_col<JS>(Hs, j - 1, lane, st.hc);
-            else hy_load_col<(JS > 0 ? JS - 1 : 0)>(Hs, j - 1, lane, st.hc);
-        }
-        const double xr = st.xr, xi = st.xi, xpr = st.xpr, xpi = st.xpi;
-        // z x and x + z x' for the diagonal row j
-        const double zxr = fma(zr, xr, -zi * xi), zxi = fma(zr, xi, zi * xr);
-        const double zpr = xr + fma(zr, xpr, -zi * xpi), zpi = xi + fma(zr, xpi, zi * xpr);
-#pragma unroll
-        for (int s = 0; s <= JS; ++s) {
-            const int i = lane + 64 * s;
-            const bool dg = i == j;
-            st.rr[s] = fma(-hc[s], xr, st.rr[s]) + (dg ? zxr : 0.0);
-            st.ri[s] = fma(-hc[s], xi, st.ri[s]) + (dg ? zxi : 0.0);
-            st.pr[s] = fma(-hc[s], xpr, st.pr[s]) + (dg ? zpr : 0.0);
-            st.pi[s] = fma(-hc[s], xpi, st.pi[s]) + (dg ? zpi : 0.0);
-        }
-        const int jl = j & 63;
-        const double is = inv_sub[j];
-        st.xr = bcast(st.rr[JS], jl) * is;
-        st.xi = bcast(st.ri[JS], jl) * is;
-        st.xpr = bcast(st.pr[JS], jl) * is;
-        st.xpi = bcast(st.pi[JS], jl) * is;
-        if ((j & 3) == 0) {
-            const double f = fabs(st.xr) + fabs(st.xi) > 1e100 ? 1e-100 : 1.0;
-            st.xr *= f; st.xi *= f; st.xpr *= f; st.xpi *= f;
-#pragma unroll
-            for (int s = 0; s <= JS; ++s) { st.rr[s] *= f; st.ri[s] *= f; st.pr[s] *= f; st.pi[s] *= f; }
-        }
+        for (int u = 0; u < 8; ++u) hy_step<JS>(Hs, inv_sub, lane, zr, zi, j - u, st);
+        hy_rescale<JS>(st);
     }
+    for (; j >= j_lo; --j) hy_step<JS>(Hs, inv_sub, lane, zr, zi, j, st);
+    hy_rescale<JS>(st);
 }
 
 // p'/p at z for the column-packed Hessenberg matrix Hs in LDS (inv_sub[j] = 1 / h_{j,j-1});
@@ -385,6 +407,7 @@ __device__ bool ab_logdet_deriv(const double* Hs, const double* inv_sub, int n, 
     if ((j0 >> 6) == 2) hy_load_col<2>(Hs, j0, lane, st.hc);
     else if ((j0 >> 6) == 1) hy_load_col<1>(Hs, j0, lane, st.hc);
     else hy_load_col<0>(Hs, j0, lane, st.hc);
+    st.is = inv_sub[j0];
     if (j0 >= 128) hy_segment<2>(Hs, inv_sub, lane, zr, zi, j0, 128, st);
     if (j0 >= 64) hy_segment<1>(Hs, inv_sub, lane, zr, zi, min(j0, 127), 64, st);
     if (j0 >= 1) hy_segment<0>(Hs, inv_sub, lane, zr, zi, min(j0, 63), 1, st);
@@ -439,6 +462,7 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
             if (c == r - 1) inv_sub[r] = 1.0 / (fabs(v) >= floor_sub ? v : (v < 0.0 ? -floor_sub : floor_sub));
         }
     }
+    if (tid == 0) inv_sub[0] = 0.0;
     __syncthreads();
     if (i >= n) return;                     // no approximation for this wave (no barrier below)
     const double tr = Hr[(int64_t)n * n] * sc, f2 = f2raw * sc * sc;
@@ -492,14 +516,22 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
         }
         // publish iterate it + 1 and its converged flag (both double-buffered: a wave that
         // is already one iteration ahead writes the other copy), then wait for every wave
-        // to have done the same
+        // to have done the same.  Everything exchanged between waves (iterates, flags, the
+        // counter) is written and read by device-scope atomic accesses, which are coherent
+        // across the XCDs' L2 caches on their own; so the release needs only the completion
+        // of the three stores before the count (vmcnt(0)), and the acquire nothing: the
+        // fences of the memory model would write back and invalidate the whole L2 of the
+        // XCD on every iteration for data that is not cached there
         double* zn = zbuf + (size_t)((it + 1) & 1) * 2 * n;
         int32_t* cn = conv + (size_t)((it + 1) & 1) * n;
         if (lane == 0) {
             __hip_atomic_store(zn + 2 * i, zr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(zn + 2 * i + 1, zi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(cn + i, done ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __builtin_amdgcn_s_waitcnt(0x0F70);    // vmcnt(0): the stores above have completed
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t target = (uint32_t)(it + 1) * (uint32_t)n;
             uint32_t polls = 0;
             while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
@@ -508,7 +540,6 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
             }
         }
         timeout = __shfl(timeout ? 1 : 0, 0, 64) != 0;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (timeout) break;
         int nc = 0;
 #pragma unroll
