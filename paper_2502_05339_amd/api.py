@@ -98,15 +98,18 @@ class Model:
         return s
 
     @staticmethod
-    def empty(n: int, r: int, dtype: torch.dtype, device, dt: float = 1.0) -> "Model":
+    def empty(n: int, r: int, dtype: torch.dtype, device, dt: float = 1.0, zero: bool = True) -> "Model":
+        """Storage for a model; zero=False leaves it uninitialised (for a fit, which writes
+        every entry of phi, including its padding columns, and clears info itself)."""
         ld = int(_lib.lib().dmd_phi_ld(r))
+        new = torch.zeros if zero else torch.empty
         return Model(
-            phi=torch.zeros((n, ld), dtype=dtype, device=device),
-            lam=torch.zeros(r, dtype=torch.complex128, device=device),
-            b=torch.zeros(r, dtype=torch.complex128, device=device),
-            sigma=torch.zeros(r, dtype=torch.float64, device=device),
-            kind=torch.zeros(r, dtype=torch.int32, device=device),
-            info=torch.zeros(_lib.INFO_WORDS, dtype=torch.int32, device=device),
+            phi=new((n, ld), dtype=dtype, device=device),
+            lam=new(r, dtype=torch.complex128, device=device),
+            b=new(r, dtype=torch.complex128, device=device),
+            sigma=new(r, dtype=torch.float64, device=device),
+            kind=new(r, dtype=torch.int32, device=device),
+            info=new(_lib.INFO_WORDS, dtype=torch.int32, device=device),
             dt=dt,
         )
 
@@ -268,7 +271,7 @@ def fit(Z: torch.Tensor | None = None, r: int = 0, *, X: torch.Tensor | None = N
     nb = ctypes.c_size_t(0)
     check(L.dmd_fit_workspace_size(n, ncols, code, ctypes.byref(o), ctypes.byref(nb)), "dmd_fit_workspace_size")
     ws = _workspace(nb.value, src.device)
-    model = Model.empty(n, r, torch.float32 if code == DMD_F32 else torch.float64, src.device, dt)
+    model = Model.empty(n, r, torch.float32 if code == DMD_F32 else torch.float64, src.device, dt, zero=False)
     ms = model.struct()
     st = L.dmd_fit(_stream(), x, xp, n, ncols, ld, ldp, code, ctypes.byref(o), ws.data_ptr(), ws.numel(),
                    ctypes.byref(ms))
@@ -551,16 +554,19 @@ def loss_grad(model: Model, lam: torch.Tensor, b: torch.Tensor, X: torch.Tensor,
     check(L.dmd_loss_grad_workspace_size(model.n, model.r, k.size, model.dtype_code, ctypes.byref(nb)),
           "dmd_loss_grad_workspace_size")
     ws = _workspace(nb.value, X.device)
-    out = torch.empty(1 + 4 * model.r, dtype=torch.float64, device=X.device)
+    # the library writes [loss, grad_lambda, grad_b] (1 + 4r doubles) from element 1 of a
+    # fresh buffer, so that the complex gradients start on 16-byte boundaries and are
+    # returned as views
+    buf = torch.empty(2 + 4 * model.r, dtype=torch.float64, device=X.device)
     ms = model.struct()
     st = L.dmd_loss_grad(_stream(), ctypes.byref(ms), lam.data_ptr(), b.data_ptr(), X.data_ptr(), X.stride(0),
-                         k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k.size, out.data_ptr(), ws.data_ptr(),
-                         ws.numel())
+                         k.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), k.size, buf[1:].data_ptr(),
+                         ws.data_ptr(), ws.numel())
     check(st, "dmd_loss_grad")
     r = model.r
-    gl = torch.view_as_complex(out[1:1 + 2 * r].clone().view(r, 2))
-    gb = torch.view_as_complex(out[1 + 2 * r:].clone().view(r, 2))
-    return out[0], gl, gb
+    gl = torch.view_as_complex(buf[2:2 + 2 * r].view(r, 2))
+    gb = torch.view_as_complex(buf[2 + 2 * r:].view(r, 2))
+    return buf[1], gl, gb
 
 
 class DMDLoss(torch.autograd.Function):
