@@ -125,7 +125,11 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
 
     for (int k = 0; k + 2 < n; ++k) {
         const double tk = refl[0], beta = refl[1], sc = refl[2];
-        auto vof = [&](int i) { return i == k + 1 ? 1.0 : (i > k + 1 && i < n ? col[i] * sc : 0.0); };
+        // v_i without branches: every lane reads col[i] (i < NMAX) and selects
+        auto vof = [&](int i) {
+            const double cv = col[i] * sc;
+            return i == k + 1 ? 1.0 : (i > k + 1 && i < n ? cv : 0.0);
+        };
         double vr[HS_N], vc[HS_N];
 #pragma unroll
         for (int a = 0; a < HS_N; ++a) { vr[a] = vof(ib + 32 * a); vc[a] = vof(jb + 32 * a); }
@@ -135,14 +139,14 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
         }
         // ---- partials of u = H v, w = H^T v, gamma = v^T H v; column k + 1 before the step
         double g = 0.0;
+        // (rows and columns past n hold zeros, so their partials are 0: stored unguarded)
         if constexpr (!SYMM) {
 #pragma unroll
             for (int a = 0; a < HS_N; ++a) {
                 double t = 0.0;
 #pragma unroll
                 for (int c = 0; c < HS_N; ++c) t = fma(h[a][c], vc[c], t);
-                const int i = ib + 32 * a;
-                if (i < n) upart[jb * UPS + i] = t;
+                upart[jb * UPS + ib + 32 * a] = t;
             }
         }
 #pragma unroll
@@ -152,11 +156,10 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
             for (int a = 0; a < HS_N; ++a) t = fma(vr[a], h[a][c], t);
             g = fma(t, vc[c], g);
             const int j = jb + 32 * c;
-            if (j < n) wpart[ib * NMAX + j] = t;
-            if (j == k + 1)
+            wpart[ib * NMAX + j] = t;
+            if (c == ((k + 1) >> 5) && jb == ((k + 1) & 31))       // j == k + 1
 #pragma unroll
-                for (int a = 0; a < HS_N; ++a)
-                    if (ib + 32 * a < n) colpre[ib + 32 * a] = h[a][c];
+                for (int a = 0; a < HS_N; ++a) colpre[ib + 32 * a] = h[a][c];
         }
         gpart[tid] = g;
         __syncthreads();
