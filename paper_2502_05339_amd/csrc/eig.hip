@@ -137,20 +137,28 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
             for (int i = k + 1 + lane; i < n; i += 64) V[(int64_t)k * n + i] = vof(i);
             if (lane == 0) tau[k] = tk;
         }
-        // ---- partials of u = H v, w = H^T v, gamma = v^T H v; column k + 1 before the step
+        // ---- partials of u = H v, w = H^T v, gamma = v^T H v; column k + 1 before the step.
+        // Column blocks c < k / 32 lie left of column k: v is 0 there, so they add nothing
+        // to u or gamma, and their entries of w are not used; they are skipped (a uniform
+        // test per block).  Rows and columns past n hold zeros: partials stored unguarded.
+        const int cb_k = k >> 5;
         double g = 0.0;
-        // (rows and columns past n hold zeros, so their partials are 0: stored unguarded)
         if constexpr (!SYMM) {
+            double tu[HS_N];
 #pragma unroll
-            for (int a = 0; a < HS_N; ++a) {
-                double t = 0.0;
+            for (int a = 0; a < HS_N; ++a) tu[a] = 0.0;
 #pragma unroll
-                for (int c = 0; c < HS_N; ++c) t = fma(h[a][c], vc[c], t);
-                upart[jb * UPS + ib + 32 * a] = t;
+            for (int c = 0; c < HS_N; ++c) {
+                if (c < cb_k) continue;
+#pragma unroll
+                for (int a = 0; a < HS_N; ++a) tu[a] = fma(h[a][c], vc[c], tu[a]);
             }
+#pragma unroll
+            for (int a = 0; a < HS_N; ++a) upart[jb * UPS + ib + 32 * a] = tu[a];
         }
 #pragma unroll
         for (int c = 0; c < HS_N; ++c) {
+            if (c < cb_k) continue;
             double t = 0.0;
 #pragma unroll
             for (int a = 0; a < HS_N; ++a) t = fma(vr[a], h[a][c], t);
@@ -198,6 +206,9 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
         // tau (v_i w_j + u_i v_j) - tau^2 gamma v_i v_j = v_i A_j + v_j B_i with
         // A_j = tau w_j and B_i = tau u_i - tau^2 gamma v_i: two FMAs; columns <= k and
         // past n take A = v = 0 and rows past n take B = v = 0, which leaves them unchanged
+        // Column blocks c < k / 32 are skipped (A = v = 0 there).  SYMM: the rows of those
+        // blocks lie above row k, where u (= w, not summed for them) is 0 in exact arithmetic
+        // (row i < k of the symmetric iterate is 0 right of column i + 1), so B = 0 there.
         double Aj[HS_N], vcm[HS_N], Bi[HS_N];
 #pragma unroll
         for (int c = 0; c < HS_N; ++c) {
@@ -209,17 +220,22 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
 #pragma unroll
         for (int a = 0; a < HS_N; ++a) {
             const int i = ib + 32 * a;
-            Bi[a] = i < n ? fma(tk, uv[i], -tg * vr[a]) : 0.0;    // padding rows stay as they are
+            const bool row = i < n && (!SYMM || a >= cb_k);         // padding rows stay as they are
+            Bi[a] = row ? fma(tk, uv[i], -tg * vr[a]) : 0.0;
         }
+        const bool colk = jb == (k & 31);
 #pragma unroll
-        for (int a = 0; a < HS_N; ++a) {
-            const int i = ib + 32 * a;
+        for (int c = 0; c < HS_N; ++c) {
+            if (c < cb_k) continue;
 #pragma unroll
-            for (int c = 0; c < HS_N; ++c) {
-                const int j = jb + 32 * c;
-                h[a][c] = fma(-vr[a], Aj[c], fma(-vcm[c], Bi[a], h[a][c]));
-                if (j == k && tk != 0.0 && i == k + 1) h[a][c] = beta;
-                if (j == k && i > k + 1) h[a][c] = 0.0;
+            for (int a = 0; a < HS_N; ++a) h[a][c] = fma(-vr[a], Aj[c], fma(-vcm[c], Bi[a], h[a][c]));
+            if (c == cb_k) {                    // the block holding column k: (.., beta, 0, ..)
+#pragma unroll
+                for (int a = 0; a < HS_N; ++a) {
+                    const int i = ib + 32 * a;
+                    if (colk && tk != 0.0 && i == k + 1) h[a][c] = beta;
+                    if (colk && i > k + 1) h[a][c] = 0.0;
+                }
             }
         }
         __syncthreads();
