@@ -46,7 +46,8 @@ static size_t cm_lds_bytes(int n)
 // S = L_pp^-1.  The block and S live in registers (lane: row i = lane / 4, columns
 // 4 (lane % 4) .. + 3); each step takes its pivot by readlane and column j and row j of S
 // by lane shuffles, so no step waits on LDS.  Returns false on a non-positive or
-// non-finite pivot.
+// non-finite pivot (tested once after the sweep: a branch per pivot costs more than the
+// sweep's arithmetic on values that are then discarded).
 __device__ __forceinline__ double readlane_f64(double x, int l)
 {
     const unsigned long long u = (unsigned long long)__double_as_longlong(x);
@@ -64,11 +65,12 @@ __device__ __forceinline__ bool cm_diag(const double* Db, double* Sb, int lane)
         dv[b] = Db[i * CM_LD + c0 + b];
         sv[b] = (i == c0 + b) ? 1.0 : 0.0;
     }
+    bool bad = false;                                      // uniform; checked once after the sweep
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const double x = dv[j & 3];                        // column j, in the lanes with q = j / 4
         const double d = readlane_f64(x, (j << 2) | (j >> 2));
-        if (!(d > 0.0) || !isfinite(d)) return false;      // uniform
+        bad = bad || !(d > 0.0) || !isfinite(d);           // a bad pivot only spoils the values discarded
         const double lraw = __shfl(x, (i << 2) | (j >> 2), 64);
         double gc[4], xr[4];
 #pragma unroll
@@ -86,6 +88,7 @@ __device__ __forceinline__ bool cm_diag(const double* Db, double* Sb, int lane)
             if (i == j && c <= j) sv[b] = xr[b] * sj;
         }
     }
+    if (bad) return false;
 #pragma unroll
     for (int b = 0; b < 4; ++b) Sb[i * CM_LD + c0 + b] = sv[b];
     return true;
