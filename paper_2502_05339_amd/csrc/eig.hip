@@ -302,6 +302,67 @@ __host__ __device__ __forceinline__ int hcol_size(int n) { return n <= 1 ? n : h
 __host__ __device__ __forceinline__ int vcol_off(int k, int n) { return k * (n - 1) - (k * (k - 1)) / 2; }
 __host__ __device__ __forceinline__ int vcol_size(int n) { return n < 3 ? 0 : vcol_off(n - 2, n); }
 
+// ---- LDS staging of the small factors with eight global loads in flight per thread.
+// Element e of an n x n source (thread tid takes e = tid, tid + nthr, ...) is read in a
+// batch of eight independent loads, then stored: a loop that stored each value before
+// loading the next waited a full memory latency per element.
+constexpr int STAGE_B = 8;
+
+// H (row-major, n x n) times sc, column-packed (column c holds rows 0 .. c + 1); with
+// inv_sub, also 1 / h_{r,r-1} with the sub-diagonal raised to at least floor_sub
+__device__ __forceinline__ void stage_hessenberg(const double* __restrict__ Hr, int n, double sc, double* Hs,
+                                                 double* inv_sub, double floor_sub, int tid, int nthr)
+{
+    const int tot = n * n;
+    for (int e0 = tid; e0 < tot; e0 += STAGE_B * nthr) {
+        double v[STAGE_B];
+        int rr[STAGE_B], cc[STAGE_B];
+#pragma unroll
+        for (int u = 0; u < STAGE_B; ++u) {
+            const int e = e0 + u * nthr;
+            rr[u] = e / n;
+            cc[u] = e - rr[u] * n;
+            v[u] = (e < tot && cc[u] + 1 >= rr[u]) ? Hr[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_B; ++u) {
+            const int e = e0 + u * nthr, r = rr[u], c = cc[u];
+            if (e < tot && c + 1 >= r) {
+                const double x = v[u] * sc;
+                Hs[hcol_off(c) + r] = x;
+                if (inv_sub && c == r - 1)
+                    inv_sub[r] = 1.0 / (fabs(x) >= floor_sub ? x : (x < 0.0 ? -floor_sub : floor_sub));
+            }
+        }
+    }
+}
+
+// the reflectors v_k (column k of V, n x n column-major, rows k + 1 .. n - 1, k <= n - 3)
+// packed at vcol_off(k, n), and their tau
+__device__ __forceinline__ void stage_reflectors(const double* __restrict__ Vg, const double* __restrict__ taug, int n,
+                                                 double* Vs, double* taus, int tid, int nthr)
+{
+    if (n <= 2) return;
+    const int tot = (n - 2) * n;
+    for (int e0 = tid; e0 < tot; e0 += STAGE_B * nthr) {
+        double v[STAGE_B];
+        int kk[STAGE_B], ii[STAGE_B];
+#pragma unroll
+        for (int u = 0; u < STAGE_B; ++u) {
+            const int e = e0 + u * nthr;
+            kk[u] = e / n;
+            ii[u] = e - kk[u] * n;
+            v[u] = (e < tot && ii[u] > kk[u]) ? Vg[e] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < STAGE_B; ++u) {
+            const int e = e0 + u * nthr, k = kk[u], i = ii[u];
+            if (e < tot && i > k) Vs[vcol_off(k, n) + i - k - 1] = v[u];
+        }
+    }
+    for (int k = tid; k + 2 < n; k += nthr) taus[k] = taug[k];
+}
+
 // Start point j of the iteration (the same formula on every wave).
 __device__ __forceinline__ void ab_start(int j, int n, double cr, double rho, double* zr, double* zi)
 {
@@ -473,14 +534,7 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
     const double sc = f2raw > 0.0 ? ldexp(1.0, -ilogb(sqrt(f2raw))) : 1.0;
     double* inv_sub = Hs + hcol_size(n);
     const double floor_sub = 2.220446049250313e-16 * sqrt(f2raw) * sc;
-    for (int r = wave; r < n; r += AB_WAVES) {
-        const int c0 = r == 0 ? 0 : r - 1;
-        for (int c = c0 + lane; c < n; c += 64) {
-            const double v = Hr[(int64_t)r * n + c] * sc;
-            Hs[hcol_off(c) + r] = v;
-            if (c == r - 1) inv_sub[r] = 1.0 / (fabs(v) >= floor_sub ? v : (v < 0.0 ? -floor_sub : floor_sub));
-        }
-    }
+    stage_hessenberg(Hr, n, sc, Hs, inv_sub, floor_sub, tid, 64 * AB_WAVES);
     if (tid == 0) inv_sub[0] = 0.0;
     __syncthreads();
     if (i >= n) return;                     // no approximation for this wave (no barrier below)
@@ -809,10 +863,7 @@ invit_kernel(int n, int waves, const double* __restrict__ Hr, const double* __re
     // whole (coalesced), entry (r, c) stored at column c
     const double f2raw = Hr[(int64_t)n * n + 1];
     const double sc = f2raw > 0.0 ? ldexp(1.0, -ilogb(sqrt(f2raw))) : 1.0;
-    for (int r = wave; r < n; r += waves) {
-        const int c0 = r == 0 ? 0 : r - 1;
-        for (int c = c0 + lane; c < n; c += 64) Hs[hcol_off(c) + r] = Hr[(int64_t)r * n + c] * sc;
-    }
+    stage_hessenberg(Hr, n, sc, Hs, nullptr, 0.0, tid, nthr);
     __syncthreads();
     const bool valid = p < n && kind0[p] != 2;
     const bool pair = valid && kind0[p] == 1;
@@ -893,14 +944,7 @@ invit_kernel(int n, int waves, const double* __restrict__ Hr, const double* __re
     }
     // reflectors into the space H held: column k (rows k + 1 ..) packed, then tau
     __syncthreads();
-    if (n > 2) {
-        double* taus = Hs + vcol_size(n);
-        for (int k = 0; k + 2 < n; ++k) {
-            const int len = n - k - 1;
-            for (int e = tid; e < len; e += nthr) Hs[vcol_off(k, n) + e] = Vg[(int64_t)k * n + k + 1 + e];
-        }
-        for (int k = tid; k + 2 < n; k += nthr) taus[k] = taug[k];
-    }
+    stage_reflectors(Vg, taug, n, Hs, Hs + vcol_size(n), tid, nthr);
     __syncthreads();
     if (!valid) return;
     // y = Q x with Q = P_0 P_1 .. P_{n-3}: P_k = I - tau_k v_k v_k^T (v_k rows k+1.., v_{k+1} = 1)
@@ -1156,13 +1200,7 @@ tri_invit_kernel(int n, int nv, int waves, const double* __restrict__ Hr, const 
         d[i] = Hr[(int64_t)i * n + i] * sc;
         e[i] = i + 1 < n ? Hr[(int64_t)(i + 1) * n + i] * sc : 0.0;
     }
-    if (n > 2) {
-        for (int k = 0; k + 2 < n; ++k) {
-            const int len = n - k - 1;
-            for (int q = tid; q < len; q += nthr) Vs[vcol_off(k, n) + q] = Vg[(int64_t)k * n + k + 1 + q];
-        }
-        for (int k = tid; k + 2 < n; k += nthr) taus[k] = taug[k];
-    }
+    stage_reflectors(Vg, taug, n, Vs, taus, tid, nthr);
     __syncthreads();
     const int kv = blockIdx.x * waves + wave;
     if (kv >= nv) return;
