@@ -769,78 +769,92 @@ struct IvState {
     double rs;                             // right-hand side scale
 };
 
+// column jn - 1 of H (rows 0 .. jn) for step jn: rows i < jn of slots 0 .. JS (the rest 0),
+// read without branches (every lane reads a row of the column, clamped, and selects), and
+// the sub-diagonal H(jn, jn - 1)
 template <int JS>
-__device__ __forceinline__ void iv_load_col(const double* Hs, int j, int lane, double (&ncr)[AB_SLOTS], double& hsub)
+__device__ __forceinline__ void iv_load_col(const double* Hs, int jn, int lane, double (&ncr)[AB_SLOTS], double& hsub)
 {
-    const double* nc = Hs + hcol_off(j - 1);                       // column j - 1: rows 0 .. j
+    const double* nc = Hs + hcol_off(jn - 1);                      // column jn - 1: rows 0 .. jn
 #pragma unroll
     for (int s = 0; s <= JS; ++s) {
         const int i = lane + 64 * s;
-        ncr[s] = (s < JS || i < j) ? nc[i] : 0.0;
+        const double v = nc[min(i, jn)];
+        ncr[s] = i < jn ? v : 0.0;
     }
-    hsub = nc[j];
+    hsub = nc[jn];
 }
 
+// step j of the column elimination (see invit_kernel)
 template <int JS>
-__device__ void iv_segment(const double* Hs, int n, int lane, double lr, double li, double eps3, int j_hi, int j_lo,
+__device__ __forceinline__ void iv_step(const double* Hs, int lane, double lr, double li, double eps3, int j,
+                                        IvState& st, double* yv, double* mu, double* fs, int* swp)
+{
+    double ncr[AB_SLOTS];
+    const double hs = st.hsub;
+#pragma unroll
+    for (int s = 0; s <= JS; ++s) ncr[s] = st.ncr[s];
+    iv_load_col<JS>(Hs, max(j - 1, 1), lane, st.ncr, st.hsub);    // the next step's (unused after j = 1)
+    const int jl = j & 63;
+    const double ajr = bcast(st.acr[JS], jl), aji = bcast(st.aci[JS], jl);
+    const double qjr = bcast(st.rhr[JS], jl), qji = bcast(st.rhi[JS], jl);
+    double nci[AB_SLOTS];
+#pragma unroll
+    for (int s = 0; s <= JS; ++s) {
+        const int i = lane + 64 * s;
+        const bool dg = i == j - 1;
+        ncr[s] = dg ? ncr[s] - lr : ncr[s];
+        nci[s] = dg ? -li : 0.0;
+    }
+    // pivot: H(j, j - 1) of the new column when it is larger, else the active column's
+    // entry (a select, not a branch); raised to eps3 when below it
+    const bool swap = fabs(hs) > fabs(ajr) + fabs(aji);
+    double pvr = swap ? hs : ajr, pvi = swap ? 0.0 : aji;
+    const bool tiny = fabs(pvr) + fabs(pvi) < eps3;
+    pvr = tiny ? (pvr < 0.0 ? -eps3 : eps3) : pvr;
+    pvi = tiny ? 0.0 : pvi;
+    const double orr = swap ? ajr : hs, oi = swap ? aji : 0.0;
+    double ipr, ipi;
+    crcp(pvr, pvi, &ipr, &ipi);
+    const double mur = fma(orr, ipr, -oi * ipi), mui = fma(orr, ipi, oi * ipr);
+    // y_j = (rs - rho_j) / pivot
+    const double tr = st.rs - qjr, ti = -qji;
+    double yr = fma(tr, ipr, -ti * ipi), yi = fma(tr, ipi, ti * ipr);
+    // growth guard without a branch: past 1e100 this step's y, the right-hand side and
+    // the running sums take a factor 1e-100, kept in fs[j]; the y stored before are
+    // brought to the same scale when x is formed
+    const double f = fabs(yr) + fabs(yi) > 1e100 ? 1e-100 : 1.0;
+    yr *= f; yi *= f; st.rs *= f;
+#pragma unroll
+    for (int s = 0; s < AB_SLOTS; ++s) { st.rhr[s] *= f; st.rhi[s] *= f; }
+#pragma unroll
+    for (int s = 0; s <= JS; ++s) {
+        const double rcr = swap ? ncr[s] : st.acr[s], rci = swap ? nci[s] : st.aci[s];   // R(i, j)
+        const double ocr = swap ? st.acr[s] : ncr[s], oci = swap ? st.aci[s] : nci[s];
+        st.rhr[s] += fma(rcr, yr, -rci * yi);
+        st.rhi[s] += fma(rcr, yi, rci * yr);
+        st.acr[s] = ocr - fma(mur, rcr, -mui * rci);
+        st.aci[s] = oci - fma(mur, rci, mui * rcr);
+    }
+    if (lane == 0) {
+        yv[2 * j] = yr; yv[2 * j + 1] = yi;
+        mu[2 * j] = mur; mu[2 * j + 1] = mui;
+        fs[j] = f;
+        swp[j] = swap ? 1 : 0;
+    }
+}
+
+// steps j = j_hi down to j_lo (all with j >> 6 == JS, j_lo >= 1), in blocks of eight
+template <int JS>
+__device__ void iv_segment(const double* Hs, int lane, double lr, double li, double eps3, int j_hi, int j_lo,
                            IvState& st, double* yv, double* mu, double* fs, int* swp)
 {
-    for (int j = j_hi; j >= j_lo; --j) {
-        double ncr[AB_SLOTS];
-        const double hs = st.hsub;
+    int j = j_hi;
+    for (; j - 7 >= j_lo; j -= 8) {
 #pragma unroll
-        for (int s = 0; s <= JS; ++s) ncr[s] = st.ncr[s];
-        if (j - 1 >= 1) {
-            if (((j - 1) >> 6) == JS) iv_load_col<JS>(Hs, j - 1, lane, st.ncr, st.hsub);
-            else iv_load_col<(JS > 0 ? JS - 1 : 0)>(Hs, j - 1, lane, st.ncr, st.hsub);
-        }
-        const int jl = j & 63;
-        const double ajr = bcast(st.acr[JS], jl), aji = bcast(st.aci[JS], jl);
-        const double qjr = bcast(st.rhr[JS], jl), qji = bcast(st.rhi[JS], jl);
-        double nci[AB_SLOTS];
-#pragma unroll
-        for (int s = 0; s <= JS; ++s) {
-            const int i = lane + 64 * s;
-            nci[s] = 0.0;
-            if (i == j - 1) { ncr[s] -= lr; nci[s] = -li; }
-        }
-        // pivot: H(j, j - 1) of the new column when it is larger, else the active column's
-        // entry (a select, not a branch); raised to eps3 when below it
-        const bool swap = fabs(hs) > fabs(ajr) + fabs(aji);
-        double pvr = swap ? hs : ajr, pvi = swap ? 0.0 : aji;
-        const bool tiny = fabs(pvr) + fabs(pvi) < eps3;
-        pvr = tiny ? (pvr < 0.0 ? -eps3 : eps3) : pvr;
-        pvi = tiny ? 0.0 : pvi;
-        const double orr = swap ? ajr : hs, oi = swap ? aji : 0.0;
-        double ipr, ipi;
-        crcp(pvr, pvi, &ipr, &ipi);
-        const double mur = fma(orr, ipr, -oi * ipi), mui = fma(orr, ipi, oi * ipr);
-        // y_j = (rs - rho_j) / pivot
-        const double tr = st.rs - qjr, ti = -qji;
-        double yr = fma(tr, ipr, -ti * ipi), yi = fma(tr, ipi, ti * ipr);
-        // growth guard without a branch: past 1e100 this step's y, the right-hand side and
-        // the running sums take a factor 1e-100, kept in fs[j]; the y stored before are
-        // brought to the same scale when x is formed
-        const double f = fabs(yr) + fabs(yi) > 1e100 ? 1e-100 : 1.0;
-        yr *= f; yi *= f; st.rs *= f;
-#pragma unroll
-        for (int s = 0; s < AB_SLOTS; ++s) { st.rhr[s] *= f; st.rhi[s] *= f; }
-#pragma unroll
-        for (int s = 0; s <= JS; ++s) {
-            const double rcr = swap ? ncr[s] : st.acr[s], rci = swap ? nci[s] : st.aci[s];   // R(i, j)
-            const double ocr = swap ? st.acr[s] : ncr[s], oci = swap ? st.aci[s] : nci[s];
-            st.rhr[s] += fma(rcr, yr, -rci * yi);
-            st.rhi[s] += fma(rcr, yi, rci * yr);
-            st.acr[s] = ocr - fma(mur, rcr, -mui * rci);
-            st.aci[s] = oci - fma(mur, rci, mui * rcr);
-        }
-        if (lane == 0) {
-            yv[2 * j] = yr; yv[2 * j + 1] = yi;
-            mu[2 * j] = mur; mu[2 * j + 1] = mui;
-            fs[j] = f;
-            swp[j] = swap ? 1 : 0;
-        }
+        for (int u = 0; u < 8; ++u) iv_step<JS>(Hs, lane, lr, li, eps3, j - u, st, yv, mu, fs, swp);
     }
+    for (; j >= j_lo; --j) iv_step<JS>(Hs, lane, lr, li, eps3, j, st, yv, mu, fs, swp);
 }
 
 __global__ void __launch_bounds__(64 * IV_MAXW)
@@ -894,9 +908,9 @@ invit_kernel(int n, int waves, const double* __restrict__ Hr, const double* __re
             else iv_load_col<0>(Hs, j0, lane, st.ncr, st.hsub);
         }
         // steps j = n - 1 .. 1 by segments of 64
-        if (n - 1 >= 128) iv_segment<2>(Hs, n, lane, lr, li, eps3, n - 1, 128, st, yv, mu, fs, swp);
-        if (n - 1 >= 64) iv_segment<1>(Hs, n, lane, lr, li, eps3, min(n - 1, 127), 64, st, yv, mu, fs, swp);
-        if (n - 1 >= 1) iv_segment<0>(Hs, n, lane, lr, li, eps3, min(n - 1, 63), 1, st, yv, mu, fs, swp);
+        if (n - 1 >= 128) iv_segment<2>(Hs, lane, lr, li, eps3, n - 1, 128, st, yv, mu, fs, swp);
+        if (n - 1 >= 64) iv_segment<1>(Hs, lane, lr, li, eps3, min(n - 1, 127), 64, st, yv, mu, fs, swp);
+        if (n - 1 >= 1) iv_segment<0>(Hs, lane, lr, li, eps3, min(n - 1, 63), 1, st, yv, mu, fs, swp);
         {
             double pvr = bcast(st.acr[0], 0), pvi = bcast(st.aci[0], 0);
             if (fabs(pvr) + fabs(pvi) < eps3) { pvr = eps3; pvi = 0.0; }
@@ -913,17 +927,16 @@ invit_kernel(int n, int waves, const double* __restrict__ Hr, const double* __re
         if (lane == 0) {
             double cr = yv[0], ci = yv[1];
             double g = 1.0;
-            for (int j = 1; j < n; ++j) {
-                if (j >= 2) g *= fs[j - 1];                   // factors of steps 1 .. j - 1
+            for (int j = 1; j < n; ++j) {                     // branch-free: selects
+                g *= j >= 2 ? fs[j - 1] : 1.0;                // factors of steps 1 .. j - 1
                 const double yr_ = yv[2 * j] * g, yi_ = yv[2 * j + 1] * g;
                 const double vr = yr_ - fma(mu[2 * j], cr, -mu[2 * j + 1] * ci);
                 const double vi = yi_ - fma(mu[2 * j], ci, mu[2 * j + 1] * cr);
-                if (swp[j]) {
-                    yv[2 * (j - 1)] = vr; yv[2 * (j - 1) + 1] = vi;
-                } else {
-                    yv[2 * (j - 1)] = cr; yv[2 * (j - 1) + 1] = ci;
-                    cr = vr; ci = vi;
-                }
+                const bool sj = swp[j] != 0;
+                yv[2 * (j - 1)] = sj ? vr : cr;
+                yv[2 * (j - 1) + 1] = sj ? vi : ci;
+                cr = sj ? cr : vr;
+                ci = sj ? ci : vi;
             }
             yv[2 * (n - 1)] = cr; yv[2 * (n - 1) + 1] = ci;
         }
@@ -1152,7 +1165,7 @@ tri_bisect_kernel(int n, const double* __restrict__ Hr, double* evals, int32_t* 
     }
 }
 
-// per-wave LDS of tri_invit_kernel: the bands of U (u0 diagonal, u1, u2), the multipliers,
+// per-wave LDS of tri_invit_kernel: the bands of U (u0 the reciprocals of its diagonal, u1, u2), the multipliers,
 // the row swaps and the right-hand side / solution
 constexpr int TI_ARR = 6;
 __host__ __device__ __forceinline__ int tinv_big(int n) { return vcol_size(n) + n; }
@@ -1216,8 +1229,9 @@ tri_invit_kernel(int n, int nv, int waves, const double* __restrict__ Hr, const 
             const bool s = fabs(bsub) > fabs(cu);
             double p = s ? bsub : cu;
             p = fabs(p) < eps3 ? (p < 0.0 ? -eps3 : eps3) : p;
-            const double m = (s ? cu : bsub) * rcp_nr(p);
-            u0[i] = p;
+            const double ip = rcp_nr(p);
+            const double m = (s ? cu : bsub) * ip;
+            u0[i] = ip;                                                  // 1 / pivot
             u1[i] = s ? an : cv;
             u2[i] = s ? gn : 0.0;
             mu[i] = m;
@@ -1227,26 +1241,32 @@ tri_invit_kernel(int n, int nv, int waves, const double* __restrict__ Hr, const 
             cu = ncu;
             cv = ncv;
         }
-        u0[n - 1] = fabs(cu) < eps3 ? (cu < 0.0 ? -eps3 : eps3) : cu;
+        u0[n - 1] = rcp_nr(fabs(cu) < eps3 ? (cu < 0.0 ? -eps3 : eps3) : cu);
+#pragma unroll 8
         for (int i = 0; i < n; ++i) y[i] = ti_start(kv, i);
         for (int pass = 0; pass < 2; ++pass) {
-            // forward: the row swaps and multipliers on the right-hand side
+            // forward: the row swaps and multipliers on the right-hand side; the running
+            // entry is carried in a register (no LDS round trip on the chain), swaps by select
+            double cur = y[0];
             for (int i = 0; i + 1 < n; ++i) {
-                double a = y[i], b = y[i + 1];
-                if (sw[i] != 0.0) { const double t = a; a = b; b = t; }
-                y[i] = a;
-                y[i + 1] = b - mu[i] * a;
+                const double b = y[i + 1];
+                const bool s = sw[i] != 0.0;
+                const double a2 = s ? b : cur, b2 = s ? cur : b;
+                y[i] = a2;
+                cur = b2 - mu[i] * a2;
             }
+            y[n - 1] = cur;
             // back-substitution with the three bands of U, then unit 2-norm
             double x1 = 0.0, x2 = 0.0, nrm = 0.0;
             for (int i = n - 1; i >= 0; --i) {
-                const double xi = (y[i] - u1[i] * x1 - u2[i] * x2) * rcp_nr(u0[i]);
+                const double xi = (y[i] - u1[i] * x1 - u2[i] * x2) * u0[i];
                 y[i] = xi;
                 x2 = x1;
                 x1 = xi;
                 nrm = fma(xi, xi, nrm);
             }
             const double inv = nrm > 0.0 ? rsqrt_nr(nrm) : 0.0;
+#pragma unroll 8
             for (int i = 0; i < n; ++i) y[i] *= inv;
         }
     }
