@@ -435,18 +435,18 @@ __device__ __forceinline__ void hy_step(const double* Hs, const double* inv_sub,
     const double zpr = xr + fma(zr, xpr, -zi * xpi), zpi = xi + fma(zr, xpi, zi * xpr);
 #pragma unroll
     for (int s = 0; s <= JS; ++s) {
-        const int i = lane + 64 * s;
-        const bool dg = i == j;
-        st.rr[s] = fma(-hc[s], xr, st.rr[s]) + (dg ? zxr : 0.0);
-        st.ri[s] = fma(-hc[s], xi, st.ri[s]) + (dg ? zxi : 0.0);
-        st.pr[s] = fma(-hc[s], xpr, st.pr[s]) + (dg ? zpr : 0.0);
-        st.pi[s] = fma(-hc[s], xpi, st.pi[s]) + (dg ? zpi : 0.0);
+        st.rr[s] = fma(-hc[s], xr, st.rr[s]);
+        st.ri[s] = fma(-hc[s], xi, st.ri[s]);
+        st.pr[s] = fma(-hc[s], xpr, st.pr[s]);
+        st.pi[s] = fma(-hc[s], xpi, st.pi[s]);
     }
+    // row j is complete: its diagonal term z x_j (and x_j + z x'_j) is added to the
+    // broadcast value only; the lane's own copy of row j is not read again
     const int jl = j & 63;
-    st.xr = bcast(st.rr[JS], jl) * is;
-    st.xi = bcast(st.ri[JS], jl) * is;
-    st.xpr = bcast(st.pr[JS], jl) * is;
-    st.xpi = bcast(st.pi[JS], jl) * is;
+    st.xr = (bcast(st.rr[JS], jl) + zxr) * is;
+    st.xi = (bcast(st.ri[JS], jl) + zxi) * is;
+    st.xpr = (bcast(st.pr[JS], jl) + zpr) * is;
+    st.xpi = (bcast(st.pi[JS], jl) + zpi) * is;
 }
 
 template <int JS>
