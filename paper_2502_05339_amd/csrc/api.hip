@@ -182,7 +182,12 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     // iteration converges cubically, so the eigenvalues themselves are far closer.
     const double defl_tol = mixed ? 1e-10 : 2.220446049250313e-16;
 
-    int32_t* flags = cv.take<int32_t>(64);
+    // attempt/run flags: 16 words per CholeskyQR call (the sketch basis, then W and Y of
+    // each power iteration), 16 for the shifted Cholesky of the mode Gram; all cleared by
+    // one fill at the start of the fit
+    const int qf = exact ? 0 : std::max(o.q, 0);     // validated <= 64 on the randomized paths
+    const int nflags = 16 * (2 + 2 * qf);
+    int32_t* flags = cv.take<int32_t>((size_t)nflags);
     int32_t* info = model ? model->info : nullptr;
     // partial buffer: largest TN product of the fit
     const int wide = shifted ? mm + 1 : mm;
@@ -247,7 +252,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     if (!run) return DMD_OK;
 
     HIPCHK(fill_i32(st, info, DMD_INFO_WORDS, 0));
-    HIPCHK(fill_i32(st, flags, 64, 0));
+    HIPCHK(fill_i32(st, flags, nflags, 0));
     if (o.flags & DMD_FIT_CHECK_FINITE) {
         HIPCHK(check_finite(st, fdt, a.x, a.ldx, n, mm, info));
         HIPCHK(check_finite(st, fdt, a.xp, a.ldxp, n, mm, info));
@@ -267,7 +272,6 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     // fl[0..npass): attempt flags of the passes; fl[8..8+npass): their run flags.
     auto cholqr = [&](void* Yb, int64_t ld, int64_t rows, int dtype, int32_t* fl, bool two, int nq) -> int32_t {
         const int need = two ? 2 : 1, npass = two ? 4 : 2;
-        HIPCHK(fill_i32(st, fl, 16, 0));
         const double shift_scale = 11.0 * ((double)rows * nq + (double)nq * (nq + 1)) * u;
         for (int pass = 0; pass < npass; ++pass) {
             const int32_t* skip = pass < need ? nullptr : fl + 8 + pass;
@@ -289,11 +293,11 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
         // power iterations: W = orth(X^T Q), Y = X W, Q = orth(Y)
         for (int it = 0; it < o.q; ++it) {
             HIPCHK(gemm_tn(st, fdt, cdt, a.x, a.ldx, 0, mm, Y, ldy, 0, l, 0, n, P, Wt, mm, nullptr, 0, nullptr));
-            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 16, false, l)) return e;
+            if (int32_t e = cholqr(Wt, mm, mm, DMD_F64, flags + 16 * (1 + 2 * it), false, l)) return e;
             if (fdt == DMD_F32) HIPCHK(to_f32(st, mm, l, l, Wt, mm, (float*)Wtf, mm));
             else HIPCHK(copy_f64(st, mm, l, l, Wt, mm, (double*)Wtf, mm));
             HIPCHK(gemm_nn(st, fdt, a.x, a.ldx, Wtf, mm, Y, ldy, 0, n, mm, l, nullptr));
-            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 32, it == o.q - 1, l)) return e;
+            if (int32_t e = cholqr(Y, ldy, n, fdt, flags + 16 * (2 + 2 * it), it == o.q - 1, l)) return e;
         }
         // projection B = Q^T X, B' = Q^T X' (one pass over Z when X' is the shifted view).
         // Its sums over N run on the FP64 MFMA on both paths: B feeds the small factors
@@ -400,7 +404,7 @@ int32_t fit_plan(Carver& cv, hipStream_t st, const FitArgs& a, dmd_model* model,
     HIPCHK(gemm_tn(st, fdt, DMD_F64, model->phi, ldphi, 1, r, model->phi, ldphi, 1, r, 1, n, P, PhiG, r, nullptr, 0, nullptr));
     HIPCHK(gemm_tn(st, fdt, DMD_F64, model->phi, ldphi, 1, r, a.x, a.ldx, 0, 1, 0, n, P, rhs, r, nullptr, 0, nullptr));
     HIPCHK(chol_inv(st, PhiG, r, r, RinvPhi, r, nullptr, 0, 11.0 * ((double)n * r + (double)r * (r + 1)) * u,
-                    flags + 48, info, nullptr));
+                    flags + 16 * (1 + 2 * qf), info, nullptr));
     HIPCHK(normal_solve(st, r, RinvPhi, r, rhs, beta, 0));
     if (fdt == DMD_F64) {
         // one step of iterative refinement: beta += G^-1 Phi^T (x0 - Phi beta)
