@@ -171,21 +171,26 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
         }
         gpart[tid] = g;
         __syncthreads();
-        // ---- sums in a fixed order
+        // ---- sums in a fixed order: four interleaved chains of eight, then pairwise (the
+        // dependent-add chain is 10 long instead of 32)
+        auto sum32 = [](const double* p, int stride) {
+            double c[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+#pragma unroll
+                for (int h = 0; h < 4; ++h) c[h] += p[(8 * h + q) * stride];
+            return (c[0] + c[1]) + (c[2] + c[3]);
+        };
         if (!SYMM && tid < n) {
-            double t = 0.0;
-            for (int q = 0; q < 32; ++q) t += upart[q * UPS + tid];
-            us[tid] = t;
+            us[tid] = sum32(upart + tid, UPS);
         } else if (tid >= 256 && tid - 256 < n) {
             const int j = tid - 256;
-            double t = 0.0;
-            for (int q = 0; q < 32; ++q) t += wpart[q * NMAX + j];
-            ws[j] = t;
+            ws[j] = sum32(wpart + j, NMAX);
         } else if (wave == 15) {
-            double t = 0.0;
+            double t0 = 0.0, t1 = 0.0;
 #pragma unroll
-            for (int q = 0; q < 16; ++q) t += gpart[q * 64 + lane];
-            t = wave_sum(t);
+            for (int q = 0; q < 8; ++q) { t0 += gpart[q * 64 + lane]; t1 += gpart[(q + 8) * 64 + lane]; }
+            const double t = wave_sum(t0 + t1);
             if (lane == 0) refl[3] = t;
         }
         __syncthreads();
