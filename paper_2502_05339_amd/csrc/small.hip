@@ -305,21 +305,42 @@ small_gemm_kernel(int ta, int tb, int m, int n, int k, double alpha, const doubl
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     const int i0 = blockIdx.x * SG_T, j0 = blockIdx.y * SG_T;
     double c00 = 0.0, c01 = 0.0, c10 = 0.0, c11 = 0.0;
-    for (int k0 = 0; k0 < k; k0 += SG_KC) {
+    // the next chunk's operands are loaded into registers while the current one is
+    // multiplied (its memory latency overlaps the FMAs); every load reads an in-bounds
+    // entry (clamped indices) and zero is selected outside the matrices
+    constexpr int SG_U = SG_KC * SG_T / 256;
+    double pa[SG_U], pb[SG_U];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int u = 0; u < SG_KC * SG_T / 256; ++u) {
+        for (int u = 0; u < SG_U; ++u) {
             const int e = tid + 256 * u;
             int ii, qa, jj, qb;
             if (ta) { qa = e % SG_KC; ii = e / SG_KC; } else { ii = e % SG_T; qa = e / SG_T; }
             if (tb) { jj = e % SG_T; qb = e / SG_T; } else { qb = e % SG_KC; jj = e / SG_KC; }
             const int gi = i0 + ii, gka = k0 + qa, gj = j0 + jj, gkb = k0 + qb;
-            double a = 0.0, b = 0.0;
-            if (gi < m && gka < k) a = ta ? A[(int64_t)gi * lda + gka] : A[(int64_t)gka * lda + gi];
-            if (gj < n && gkb < k) b = tb ? B[(int64_t)gkb * ldb + gj] : B[(int64_t)gj * ldb + gkb];
-            As[qa * SG_LD + ii] = a;
-            Bs[qb * SG_LD + jj] = b;
+            const int ci = min(gi, m - 1), cka = min(gka, k - 1), cj = min(gj, n - 1), ckb = min(gkb, k - 1);
+            const double a = ta ? A[(int64_t)ci * lda + cka] : A[(int64_t)cka * lda + ci];
+            const double b = tb ? B[(int64_t)ckb * ldb + cj] : B[(int64_t)cj * ldb + ckb];
+            pa[u] = (gi < m && gka < k) ? a : 0.0;
+            pb[u] = (gj < n && gkb < k) ? b : 0.0;
         }
+    };
+    auto put = [&]() {
+#pragma unroll
+        for (int u = 0; u < SG_U; ++u) {
+            const int e = tid + 256 * u;
+            int ii, qa, jj, qb;
+            if (ta) { qa = e % SG_KC; ii = e / SG_KC; } else { ii = e % SG_T; qa = e / SG_T; }
+            if (tb) { jj = e % SG_T; qb = e / SG_T; } else { qb = e % SG_KC; jj = e / SG_KC; }
+            As[qa * SG_LD + ii] = pa[u];
+            Bs[qb * SG_LD + jj] = pb[u];
+        }
+    };
+    if (k > 0) fetch(0);
+    for (int k0 = 0; k0 < k; k0 += SG_KC) {
+        put();
         __syncthreads();
+        if (k0 + SG_KC < k) fetch(k0 + SG_KC);
         const int kc = min(SG_KC, k - k0);
         for (int q = 0; q < kc; ++q) {
             const double2 a = *reinterpret_cast<const double2*>(As + q * SG_LD + 2 * tx);
@@ -332,16 +353,16 @@ small_gemm_kernel(int ta, int tb, int m, int n, int k, double alpha, const doubl
         __syncthreads();
     }
     const int i = i0 + 2 * tx, j = j0 + 2 * ty;
-    auto put = [&](int ii, int jj, double v) {
+    auto out = [&](int ii, int jj, double v) {
         if (ii < m && jj < n) {
             double* c = C + (int64_t)jj * ldc + ii;
             *c = alpha * v + (beta == 0.0 ? 0.0 : beta * *c);
         }
     };
-    put(i, j, c00);
-    put(i + 1, j, c10);
-    put(i, j + 1, c01);
-    put(i + 1, j + 1, c11);
+    out(i, j, c00);
+    out(i + 1, j, c10);
+    out(i, j + 1, c01);
+    out(i + 1, j + 1, c11);
 }
 
 hipError_t small_gemm(hipStream_t s, int ta, int tb, int m, int n, int k, double alpha,
