@@ -44,8 +44,9 @@ static size_t cm_lds_bytes(int n)
 
 // column sweep of one 16 x 16 diagonal block by one wave: Db (G'_pp) is read, Sb receives
 // S = L_pp^-1.  The block and S live in registers (lane: row i = lane / 4, columns
-// 4 (lane % 4) .. + 3); each step takes its pivot by readlane and column j and row j of S
-// by lane shuffles, so no step waits on LDS.  Returns false on a non-positive or
+// 4 (lane % 4) .. + 3); each round of two pivots takes the 2 x 2 pivot block by readlane
+// and columns j, j + 1 and rows j, j + 1 of S by lane shuffles, so no round waits on
+// LDS.  Returns false on a non-positive or
 // non-finite pivot (tested once after the sweep: a branch per pivot costs more than the
 // sweep's arithmetic on values that are then discarded).
 __device__ __forceinline__ double readlane_f64(double x, int l)
@@ -66,26 +67,42 @@ __device__ __forceinline__ bool cm_diag(const double* Db, double* Sb, int lane)
         sv[b] = (i == c0 + b) ? 1.0 : 0.0;
     }
     bool bad = false;                                      // uniform; checked once after the sweep
+    // two pivots (j, j + 1) per round: the 2 x 2 pivot block is factored from three
+    // broadcast values, and each lane applies both eliminations to its entries at once, so
+    // a round waits on one set of lane shuffles instead of two
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const double x = dv[j & 3];                        // column j, in the lanes with q = j / 4
-        const double d = readlane_f64(x, (j << 2) | (j >> 2));
-        bad = bad || !(d > 0.0) || !isfinite(d);           // a bad pivot only spoils the values discarded
-        const double lraw = __shfl(x, (i << 2) | (j >> 2), 64);
-        double gc[4], xr[4];
+    for (int j = 0; j < 16; j += 2) {
+        const int g = j >> 2;                              // lane column group of columns j, j + 1
+        const double x0 = dv[j & 3], x1 = dv[(j & 3) + 1]; // columns j, j + 1 (in the lanes with q = g)
+        const double d0 = readlane_f64(x0, (j << 2) | g);            // D(j, j)
+        const double e = readlane_f64(x0, ((j + 1) << 2) | g);       // D(j + 1, j)
+        const double f = readlane_f64(x1, ((j + 1) << 2) | g);       // D(j + 1, j + 1)
+        const double a = __shfl(x0, (i << 2) | g, 64);               // D(i, j)
+        const double bb = __shfl(x1, (i << 2) | g, 64);              // D(i, j + 1)
+        double gc0[4], gc1[4], xr0[4], xr1[4];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            gc[b] = __shfl(x, ((c0 + b) << 2) | (j >> 2), 64);   // D(c0 + b, j)
-            xr[b] = __shfl(sv[b], (j << 2) | q, 64);              // S(j, c0 + b)
+            gc0[b] = __shfl(x0, ((c0 + b) << 2) | g, 64);            // D(c0 + b, j)
+            gc1[b] = __shfl(x1, ((c0 + b) << 2) | g, 64);            // D(c0 + b, j + 1)
+            xr0[b] = __shfl(sv[b], (j << 2) | q, 64);                // S(j, c0 + b)
+            xr1[b] = __shfl(sv[b], ((j + 1) << 2) | q, 64);          // S(j + 1, c0 + b)
         }
-        const double sj = rsqrt_nr(d);
-        const double lij = lraw * (sj * sj);
+        const double s0 = rsqrt_nr(d0), inv0 = s0 * s0;
+        const double l10 = e * inv0;
+        const double d1 = f - l10 * e;                    // D(j + 1, j + 1) after pivot j
+        const double s1 = rsqrt_nr(d1), inv1 = s1 * s1;
+        bad = bad || !(d0 > 0.0) || !isfinite(d0) || !(d1 > 0.0) || !isfinite(d1);
+        const double li0 = a * inv0;                       // row i's multipliers (used for i > j + 1)
+        const double li1 = (bb - li0 * e) * inv1;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int c = c0 + b;
-            if (i > j && c > j && c <= i) dv[b] -= lij * gc[b];
-            if (i > j && c <= j) sv[b] -= lij * xr[b];
-            if (i == j && c <= j) sv[b] = xr[b] * sj;
+            const double sp = xr1[b] - l10 * xr0[b];      // S(j + 1, c) after pivot j
+            const double dp = gc1[b] - (gc0[b] * inv0) * e;   // D(c, j + 1) after pivot j
+            if (i > j + 1 && c > j + 1 && c <= i) dv[b] = (dv[b] - li0 * gc0[b]) - li1 * dp;
+            if (i > j + 1 && c <= j + 1) sv[b] = (sv[b] - li0 * xr0[b]) - li1 * sp;
+            if (i == j + 1 && c <= j + 1) sv[b] = sp * s1;
+            if (i == j && c <= j) sv[b] = xr0[b] * s0;
         }
     }
     if (bad) return false;
