@@ -58,6 +58,28 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, DMD_WAVE);
     return v;
 }
+// The same sum with the intra-row steps as DPP lane moves (quad permutations, half-row and
+// row mirrors; no LDS round trip) and the four row sums combined from readlanes.  Every
+// lane gets the bit-identical result (each step adds two equal-order partial sums).  All
+// 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+    v += dpp_move<0xB1>(v);      // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E>(v);      // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141>(v);     // row_half_mirror: the other quad of each 8 lanes
+    v += dpp_move<0x140>(v);     // row_mirror: the other 8 lanes of each row
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, DMD_WAVE);

@@ -104,7 +104,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
     auto reflector = [&](int k) {
         double x2 = 0.0;
         for (int i = k + 2 + lane; i < n; i += 64) { const double x = col[i]; x2 = fma(x, x, x2); }
-        x2 = wave_sum(x2);
+        x2 = wave_sum_dpp(x2);
         const double alpha = col[k + 1];
         double tk = 0.0, beta = alpha, sc = 0.0;
         if (x2 != 0.0) {
@@ -190,7 +190,7 @@ hessenberg_kernel(const double* __restrict__ A, int64_t lda, int n, double* H, d
             double t0 = 0.0, t1 = 0.0;
 #pragma unroll
             for (int q = 0; q < 8; ++q) { t0 += gpart[q * 64 + lane]; t1 += gpart[(q + 8) * 64 + lane]; }
-            const double t = wave_sum(t0 + t1);
+            const double t = wave_sum_dpp(t0 + t1);
             if (lane == 0) refl[3] = t;
         }
         __syncthreads();
@@ -578,8 +578,8 @@ aberth_kernel(int n, const double* __restrict__ Hr, double* zbuf, int32_t* conv,
                     qi += ti_;
                 }
             }
-            qr = wave_sum(qr);
-            qi = wave_sum(qi);
+            qr = wave_sum_dpp(qr);
+            qi = wave_sum_dpp(qi);
             double wr = 0.0, wi = 0.0;
             if (ok) {
                 const double er = sr - qr, ei = si - qi;
@@ -955,7 +955,7 @@ invit_kernel(int n, int waves, const double* __restrict__ Hr, const double* __re
         double nn2 = 0.0;
 #pragma unroll
         for (int s = 0; s < AB_SLOTS; ++s) nn2 = fma(xr[s], xr[s], fma(xi[s], xi[s], nn2));
-        nn2 = wave_sum(nn2);
+        nn2 = wave_sum_dpp(nn2);
         const double inv = nn2 > 0.0 ? 1.0 / sqrt(nn2) : 0.0;
 #pragma unroll
         for (int s = 0; s < AB_SLOTS; ++s) { xr[s] *= inv; xi[s] *= inv; }
@@ -974,14 +974,15 @@ invit_kernel(int n, int waves, const double* __restrict__ Hr, const double* __re
 #pragma unroll
             for (int s = 0; s < AB_SLOTS; ++s) {
                 const int i = lane + 64 * s;
-                vv[s] = (i > k && i < n) ? v[i] : 0.0;
+                const double vi = v[min(max(i, k + 1), n - 1)];   // in the column; selected below
+                vv[s] = (i > k && i < n) ? vi : 0.0;
             }
             double gr = 0.0, gi = 0.0;
 #pragma unroll
             for (int s = 0; s < AB_SLOTS; ++s) { gr = fma(vv[s], xr[s], gr); gi = fma(vv[s], xi[s], gi); }
             const double t = taus[k];
-            gr = wave_sum(gr) * t;
-            gi = wave_sum(gi) * t;
+            gr = wave_sum_dpp(gr) * t;
+            gi = wave_sum_dpp(gi) * t;
 #pragma unroll
             for (int s = 0; s < AB_SLOTS; ++s) { xr[s] = fma(-gr, vv[s], xr[s]); xi[s] = fma(-gi, vv[s], xi[s]); }
         }
@@ -1290,12 +1291,13 @@ tri_invit_kernel(int n, int nv, int waves, const double* __restrict__ Hr, const 
 #pragma unroll
             for (int s = 0; s < AB_SLOTS; ++s) {
                 const int i = lane + 64 * s;
-                vv[s] = (i > k && i < n) ? v[i] : 0.0;
+                const double vi = v[min(max(i, k + 1), n - 1)];   // in the column; selected below
+                vv[s] = (i > k && i < n) ? vi : 0.0;
             }
             double g = 0.0;
 #pragma unroll
             for (int s = 0; s < AB_SLOTS; ++s) g = fma(vv[s], xr[s], g);
-            g = wave_sum(g) * taus[k];
+            g = wave_sum_dpp(g) * taus[k];
 #pragma unroll
             for (int s = 0; s < AB_SLOTS; ++s) xr[s] = fma(-g, vv[s], xr[s]);
         }
