@@ -239,6 +239,8 @@ __device__ __forceinline__ void block_decode(int b, int sym, int nbi, int* bi, i
 
 // Work-group: 512 threads = 8 waves.  Rows are consumed in chunks of RC, staged in
 // LDS as [row][col] (so each MFMA operand read is 16 consecutive columns of one row)
+// in the input type (FP32 inputs of an FP64-summed product are widened as each
+// fragment is read, which is exact and keeps the LDS footprint of the FP32 products)
 // with two buffers: the next chunk is fetched from memory into registers with 16-byte
 // loads while the current one feeds the MFMAs, then written to the other buffer, one
 // barrier per chunk.  Output tiling: the 16x16 blocks of C form an nbi x nbj grid; a
@@ -316,10 +318,13 @@ struct TnStage {
         }
         return v;
     }
-    __device__ void store(Tc* buf, const VT& v) const {
+    // every row of the chunk exists and the operand allows 16-byte loads: one load (the
+    // columns past the last of a row-major operand are cleared by store)
+    __device__ VT load_full(int64_t c0) const { return *reinterpret_cast<const VT*>(src + c0 * step); }
+    __device__ void store(Tin* buf, const VT& v) const {
         const Tin* pv = reinterpret_cast<const Tin*>(&v);
 #pragma unroll
-        for (int e = 0; e < VWI; ++e) buf[soff + e * sstride] = (Tc)pv[e];
+        for (int e = 0; e < VWI; ++e) buf[soff + e * sstride] = e < cvalid ? pv[e] : Tin(0);
     }
 };
 
@@ -336,9 +341,9 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
     typedef typename St::VT VT;
     typedef typename Acc<Tc>::type V;
     const int ka_p = (int)round_up(ka, 16), nb_p = (int)round_up(nb, 16);
-    const int lda_s = tn_ld(ka_p, sizeof(Tc)), ldb_s = tn_ld(nb_p, sizeof(Tc));
+    const int lda_s = tn_ld(ka_p, sizeof(Tin)), ldb_s = tn_ld(nb_p, sizeof(Tin));
     const int bufsz = RC * lda_s + (sym ? 0 : RC * ldb_s);
-    Tc* buf0 = reinterpret_cast<Tc*>(smem_raw);
+    Tin* buf0 = reinterpret_cast<Tin*>(smem_raw);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform -> scalar registers
@@ -373,18 +378,25 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
                           has[q] ? t - na : 0, ldb_s, RC * lda_s);
     }
     VT pre[TN_MAXT];
-    auto fetch = [&](int64_t c0) {   // c0: chunk offset inside the split
+    // c0: chunk offset inside the split
+    auto fetch_whole = [&](int64_t c0) {
+#pragma unroll
+        for (int q = 0; q < TN_MAXT; ++q)
+            if (has[q]) pre[q] = task[q].load_full(c0);
+    };
+    auto fetch = [&](int64_t c0) {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
             if (has[q]) pre[q] = task[q].load(c0, r_end - r_begin, vec);
     };
-    auto put = [&](Tc* buf) {
+    auto put = [&](Tin* buf) {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
             if (has[q]) task[q].store(buf, pre[q]);
     };
 
     const int64_t nchunk = ceil_div(r_end - r_begin, (int64_t)RC);
+    const int64_t nwhole = vec ? (r_end - r_begin) / RC : 0;   // chunks read by 16-byte loads
     if (nchunk > 0) {
         fetch(0);
         put(buf0);
@@ -392,24 +404,30 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
     __syncthreads();
     // clamped fragment columns (in elements)
     const int amax = (nbi - 1) * 16, bmax = (nbj - 1) * 16;
-    for (int64_t ci = 0; ci < nchunk; ++ci) {
-        Tc* cur = buf0 + (ci & 1) * bufsz;
-        Tc* nxt = buf0 + ((ci + 1) & 1) * bufsz;
+    // one chunk: fetch the next one into registers, MFMAs on the current one, then the
+    // next one into the other buffer.  The loop whose next chunk is whole has only the
+    // unguarded loads, which all stay in flight together; the guarded per-element loads
+    // of a ragged chunk run in a loop of their own, since in the same loop they write
+    // the same registers and make each load wait for the one before.
+    auto step = [&](int64_t ci, auto whole_next) {
+        Tin* cur = buf0 + (ci & 1) * bufsz;
+        Tin* nxt = buf0 + ((ci + 1) & 1) * bufsz;
         const bool more = ci + 1 < nchunk;
-        if (more) fetch((ci + 1) * RC);
-        const Tc* As = cur;
-        const Tc* Bs = sym ? cur : cur + RC * lda_s;
+        if constexpr (decltype(whole_next)::value) fetch_whole((ci + 1) * RC);
+        else if (more) fetch((ci + 1) * RC);
+        const Tin* As = cur;
+        const Tin* Bs = sym ? cur : cur + RC * lda_s;
         const int bld = sym ? lda_s : ldb_s;
 #pragma unroll
         for (int ks = 0; ks < RC / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            const Tc* arow = As + kk * lda_s + (lane & 15);
-            const Tc* brow = Bs + kk * bld + (lane & 15);
+            const Tin* arow = As + kk * lda_s + (lane & 15);
+            const Tin* brow = Bs + kk * bld + (lane & 15);
             Tc av[RI], bv[RJ];
 #pragma unroll
-            for (int i = 0; i < RI; ++i) av[i] = arow[min((bi0 + i) * 16, amax)];
+            for (int i = 0; i < RI; ++i) av[i] = (Tc)arow[min((bi0 + i) * 16, amax)];
 #pragma unroll
-            for (int j = 0; j < RJ; ++j) bv[j] = brow[min((bj0 + j) * 16, bmax)];
+            for (int j = 0; j < RJ; ++j) bv[j] = (Tc)brow[min((bj0 + j) * 16, bmax)];
 #pragma unroll
             for (int i = 0; i < RI; ++i)
 #pragma unroll
@@ -417,7 +435,10 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
         }
         if (more) put(nxt);
         __syncthreads();
-    }
+    };
+    int64_t ci = 0;
+    for (; ci + 1 < nwhole; ++ci) step(ci, std::true_type{});
+    for (; ci < nchunk; ++ci) step(ci, std::false_type{});
 
     double* out = P + split * (int64_t)ka * nb;
 #pragma unroll
@@ -453,9 +474,9 @@ gemm_sym_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
     typedef typename St::VT VT;
     typedef typename Acc<Tc>::type V;
     const int ka_p = (int)round_up(ka, 16);
-    const int lda_s = tn_ld(ka_p, sizeof(Tc));
+    const int lda_s = tn_ld(ka_p, sizeof(Tin));
     const int bufsz = RC * lda_s;
-    Tc* buf0 = reinterpret_cast<Tc*>(smem_raw);
+    Tin* buf0 = reinterpret_cast<Tin*>(smem_raw);
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -494,41 +515,49 @@ gemm_sym_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
         task[q].init(A + r_begin * (a_rowmajor ? lda : 1), lda, a_rowmajor, ka, ka_p, RC, has[q] ? t : 0, lda_s, 0);
     }
     VT pre[TN_MAXT];
+    auto fetch_whole = [&](int64_t c0) {
+#pragma unroll
+        for (int q = 0; q < TN_MAXT; ++q)
+            if (has[q]) pre[q] = task[q].load_full(c0);
+    };
     auto fetch = [&](int64_t c0) {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
             if (has[q]) pre[q] = task[q].load(c0, r_end - r_begin, vec);
     };
-    auto put = [&](Tc* buf) {
+    auto put = [&](Tin* buf) {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
             if (has[q]) task[q].store(buf, pre[q]);
     };
 
     const int64_t nchunk = ceil_div(r_end - r_begin, (int64_t)RC);
+    const int64_t nwhole = vec ? (r_end - r_begin) / RC : 0;
     if (nchunk > 0) {
         fetch(0);
         put(buf0);
     }
     __syncthreads();
     const int amax = (nbi - 1) * 16;
-    for (int64_t ci = 0; ci < nchunk; ++ci) {
-        Tc* cur = buf0 + (ci & 1) * bufsz;
-        Tc* nxt = buf0 + ((ci + 1) & 1) * bufsz;
+    // whole next chunks and the ragged rest in loops of their own, as in gemm_tn_kernel
+    auto step = [&](int64_t ci, auto whole_next) {
+        Tin* cur = buf0 + (ci & 1) * bufsz;
+        Tin* nxt = buf0 + ((ci + 1) & 1) * bufsz;
         const bool more = ci + 1 < nchunk;
-        if (more) fetch((ci + 1) * RC);
+        if constexpr (decltype(whole_next)::value) fetch_whole((ci + 1) * RC);
+        else if (more) fetch((ci + 1) * RC);
 #pragma unroll
         for (int ks = 0; ks < RC / 4; ++ks) {
             const int kk = ks * 4 + (lane >> 4);
-            const Tc* row = cur + kk * lda_s + (lane & 15);
+            const Tin* row = cur + kk * lda_s + (lane & 15);
 #pragma unroll
             for (int q = 0; q < SB_MAXW; ++q) {
                 if (!sv[q]) continue;                                 // wave-uniform
                 Tc av[2], bv[2];
 #pragma unroll
-                for (int a = 0; a < 2; ++a) av[a] = row[min((2 * sr[q] + a) * 16, amax)];
+                for (int a = 0; a < 2; ++a) av[a] = (Tc)row[min((2 * sr[q] + a) * 16, amax)];
 #pragma unroll
-                for (int b = 0; b < 2; ++b) bv[b] = row[min((2 * sc[q] + b) * 16, amax)];
+                for (int b = 0; b < 2; ++b) bv[b] = (Tc)row[min((2 * sc[q] + b) * 16, amax)];
 #pragma unroll
                 for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -537,7 +566,10 @@ gemm_sym_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
         }
         if (more) put(nxt);
         __syncthreads();
-    }
+    };
+    int64_t ci = 0;
+    for (; ci + 1 < nwhole; ++ci) step(ci, std::true_type{});
+    for (; ci < nchunk; ++ci) step(ci, std::false_type{});
 
     double* out = P + split * (int64_t)ka * ka;
 #pragma unroll
@@ -621,9 +653,9 @@ int tn_max_splits(int64_t N) { return std::max(tn_splits(N, 8), tn_splits(N, 16)
 
 template <typename Tin, typename Tc>
 static size_t tn_lds(int rc, int ka, int nb, int sym) {
-    const size_t per = (size_t)rc * tn_ld((int)round_up(ka, 16), sizeof(Tc)) +
-                       (sym ? 0 : (size_t)rc * tn_ld((int)round_up(nb, 16), sizeof(Tc)));
-    return 2 * per * sizeof(Tc);
+    const size_t per = (size_t)rc * tn_ld((int)round_up(ka, 16), sizeof(Tin)) +
+                       (sym ? 0 : (size_t)rc * tn_ld((int)round_up(nb, 16), sizeof(Tin)));
+    return 2 * per * sizeof(Tin);
 }
 
 // wave tiles (RI x RJ output blocks) instantiated per accumulator type
@@ -633,6 +665,8 @@ static size_t tn_lds(int rc, int ka, int nb, int sym) {
     X(Ti, Tc, RC, 5, 1) X(Ti, Tc, RC, 5, 3)
 // FP32 products with 16 waves (4 x 4): smaller wave tiles, four waves per SIMD
 #define TN_TILES_F32_W4(X) X(3, 3) X(3, 4) X(3, 5) X(4, 3) X(5, 3)
+// FP32 inputs summed in FP64 with 16 waves (the tiles that fit 128 registers)
+#define TN_TILES_F64_W4(X) X(2, 2) X(5, 1)
 #define TN_INSTANCES(X) \
     TN_TILES_F32(X, float, float, 16) TN_TILES_F32(X, float, float, 8) \
     TN_TILES_F64(X, float, double, 16) TN_TILES_F64(X, float, double, 8) \
@@ -651,6 +685,11 @@ hipError_t gemm_prepare()
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     TN_TILES_F32_W4(TN_ATTR4)
 #undef TN_ATTR4
+#define TN_ATTR4D(RI, RJ) \
+    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_tn_kernel<float, double, 16, RI, RJ, 4>, \
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    TN_TILES_F64_W4(TN_ATTR4D)
+#undef TN_ATTR4D
 #define SYM_ATTR(Ti, Tc, RC) \
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_sym_kernel<Ti, Tc, RC>, \
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -784,6 +823,15 @@ static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_r
             TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 3) TN_CASE(4, 5, 4) TN_CASE(5, 5, 5)
             TN_CASE(6, 7, 3)
             default: return launch_tn_k<Tin, Tc, RC, 10, 3>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
+        }
+    } else if constexpr (sizeof(Tin) == 4 && RC == 16) {
+        consider(2, 2, 2); consider(3, 3, 2); consider(4, 4, 2); consider(5, 1, 2); consider(5, 3, 2);
+        consider(2, 2, 4); consider(5, 1, 4);
+        if (hipError_t e = tn_pick(key, idx, &best)) return e;
+        switch (best) {
+            TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 4, 4) TN_CASE(3, 5, 1) TN_CASE(4, 5, 3)
+            TN_CASE4(5, 2, 2)
+            default: return launch_tn_k<Tin, Tc, RC, 5, 1, 4>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
         }
     } else {
         consider(2, 2, 2); consider(3, 3, 2); consider(4, 4, 2); consider(5, 1, 2); consider(5, 3, 2);
