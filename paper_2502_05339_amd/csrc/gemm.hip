@@ -261,7 +261,9 @@ __host__ __device__ constexpr int tn_ld(int ncol_p, int esz) {
 
 // One staging task moves VWI consecutive elements of one operand: VWI rows of a
 // column (column-major operand) or VWI columns of a row (row-major operand).  The
-// tasks of a thread are the same for every chunk, so they are decoded once.
+// tasks of a thread are the same for every chunk, so they are decoded once; each keeps
+// one running pointer into the next chunk to fetch, advanced after every fetch (one
+// pointer per task for both the whole-chunk and the ragged-chunk loop).
 template <typename Tin, typename Tc>
 struct TnStage {
     static constexpr int VWI = 16 / sizeof(Tin);
@@ -269,8 +271,8 @@ struct TnStage {
     __host__ __device__ static int ntasks(int rowmajor, int ncol, int ncol_p, int rc) {
         return rowmajor ? rc * (ncol_p / VWI) : ncol * (rc / VWI);
     }
-    const Tin* src;     // element of row 0 of the split's first chunk
-    int64_t step;       // elements to advance per row of chunk offset (1 or ld)
+    const Tin* p;       // first element of the task in the next chunk to fetch
+    int64_t adv;        // elements from one chunk to the next (rc, or rc ld if row-major)
     int soff;           // LDS element offset of the first element (buffer-relative)
     int sstride;        // LDS stride between the VWI elements
     int roff;           // row of the task inside the chunk (first of VWI rows if column-major)
@@ -281,8 +283,8 @@ struct TnStage {
         if (rm) {
             const int per = ncol_p / VWI;
             const int rr = t / per, cq = t % per;
-            src = X + (int64_t)rr * ld + VWI * cq;
-            step = ld;
+            p = X + (int64_t)rr * ld + VWI * cq;
+            adv = (int64_t)rc * ld;
             soff = base + rr * ldsld + VWI * cq;
             sstride = 1;
             roff = rr;
@@ -290,18 +292,18 @@ struct TnStage {
         } else {
             const int per = rc / VWI;
             const int c = t / per, q = t % per;
-            src = X + (int64_t)c * ld + VWI * q;
-            step = 1;
+            p = X + (int64_t)c * ld + VWI * q;
+            adv = rc;
             soff = base + VWI * q * ldsld + c;
             sstride = ldsld;
             roff = VWI * q;
             cvalid = VWI;
         }
     }
+    // c0: offset of the chunk at p inside the split (for the row guards)
     __device__ VT load(int64_t c0, int64_t r_end, int vec) const {
         VT v;
         Tin* pv = reinterpret_cast<Tin*>(&v);
-        const Tin* p = src + c0 * step;
         const int64_t row = c0 + roff;
         if (rowmajor) {
             if (vec && row < r_end) v = *reinterpret_cast<const VT*>(p);
@@ -320,7 +322,8 @@ struct TnStage {
     }
     // every row of the chunk exists and the operand allows 16-byte loads: one load (the
     // columns past the last of a row-major operand are cleared by store)
-    __device__ VT load_full(int64_t c0) const { return *reinterpret_cast<const VT*>(src + c0 * step); }
+    __device__ VT load_full() const { return *reinterpret_cast<const VT*>(p); }
+    __device__ void next() { p += adv; }
     __device__ void store(Tin* buf, const VT& v) const {
         const Tin* pv = reinterpret_cast<const Tin*>(&v);
 #pragma unroll
@@ -379,15 +382,15 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
     }
     VT pre[TN_MAXT];
     // c0: chunk offset inside the split
-    auto fetch_whole = [&](int64_t c0) {
+    auto fetch_whole = [&]() {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
-            if (has[q]) pre[q] = task[q].load_full(c0);
+            if (has[q]) { pre[q] = task[q].load_full(); task[q].next(); }
     };
     auto fetch = [&](int64_t c0) {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
-            if (has[q]) pre[q] = task[q].load(c0, r_end - r_begin, vec);
+            if (has[q]) { pre[q] = task[q].load(c0, r_end - r_begin, vec); task[q].next(); }
     };
     auto put = [&](Tin* buf) {
 #pragma unroll
@@ -413,7 +416,7 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
         Tin* cur = buf0 + (ci & 1) * bufsz;
         Tin* nxt = buf0 + ((ci + 1) & 1) * bufsz;
         const bool more = ci + 1 < nchunk;
-        if constexpr (decltype(whole_next)::value) fetch_whole((ci + 1) * RC);
+        if constexpr (decltype(whole_next)::value) fetch_whole();
         else if (more) fetch((ci + 1) * RC);
         const Tin* As = cur;
         const Tin* Bs = sym ? cur : cur + RC * lda_s;
@@ -515,15 +518,15 @@ gemm_sym_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
         task[q].init(A + r_begin * (a_rowmajor ? lda : 1), lda, a_rowmajor, ka, ka_p, RC, has[q] ? t : 0, lda_s, 0);
     }
     VT pre[TN_MAXT];
-    auto fetch_whole = [&](int64_t c0) {
+    auto fetch_whole = [&]() {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
-            if (has[q]) pre[q] = task[q].load_full(c0);
+            if (has[q]) { pre[q] = task[q].load_full(); task[q].next(); }
     };
     auto fetch = [&](int64_t c0) {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
-            if (has[q]) pre[q] = task[q].load(c0, r_end - r_begin, vec);
+            if (has[q]) { pre[q] = task[q].load(c0, r_end - r_begin, vec); task[q].next(); }
     };
     auto put = [&](Tin* buf) {
 #pragma unroll
@@ -544,7 +547,7 @@ gemm_sym_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
         Tin* cur = buf0 + (ci & 1) * bufsz;
         Tin* nxt = buf0 + ((ci + 1) & 1) * bufsz;
         const bool more = ci + 1 < nchunk;
-        if constexpr (decltype(whole_next)::value) fetch_whole((ci + 1) * RC);
+        if constexpr (decltype(whole_next)::value) fetch_whole();
         else if (more) fetch((ci + 1) * RC);
 #pragma unroll
         for (int ks = 0; ks < RC / 4; ++ks) {
@@ -665,8 +668,6 @@ static size_t tn_lds(int rc, int ka, int nb, int sym) {
     X(Ti, Tc, RC, 5, 1) X(Ti, Tc, RC, 5, 3)
 // FP32 products with 16 waves (4 x 4): smaller wave tiles, four waves per SIMD
 #define TN_TILES_F32_W4(X) X(3, 3) X(3, 4) X(3, 5) X(4, 3) X(5, 3)
-// FP32 inputs summed in FP64 with 16 waves (the tiles that fit 128 registers)
-#define TN_TILES_F64_W4(X) X(2, 2) X(5, 1)
 #define TN_INSTANCES(X) \
     TN_TILES_F32(X, float, float, 16) TN_TILES_F32(X, float, float, 8) \
     TN_TILES_F64(X, float, double, 16) TN_TILES_F64(X, float, double, 8) \
@@ -685,11 +686,6 @@ hipError_t gemm_prepare()
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     TN_TILES_F32_W4(TN_ATTR4)
 #undef TN_ATTR4
-#define TN_ATTR4D(RI, RJ) \
-    if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_tn_kernel<float, double, 16, RI, RJ, 4>, \
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    TN_TILES_F64_W4(TN_ATTR4D)
-#undef TN_ATTR4D
 #define SYM_ATTR(Ti, Tc, RC) \
     if (e == hipSuccess) e = hipFuncSetAttribute((const void*)gemm_sym_kernel<Ti, Tc, RC>, \
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -823,15 +819,6 @@ static hipError_t launch_tn_rc(hipStream_t s, const Tin* A, int64_t lda, int a_r
             TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 5, 1) TN_CASE(3, 5, 3) TN_CASE(4, 5, 4) TN_CASE(5, 5, 5)
             TN_CASE(6, 7, 3)
             default: return launch_tn_k<Tin, Tc, RC, 10, 3>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
-        }
-    } else if constexpr (sizeof(Tin) == 4 && RC == 16) {
-        consider(2, 2, 2); consider(3, 3, 2); consider(4, 4, 2); consider(5, 1, 2); consider(5, 3, 2);
-        consider(2, 2, 4); consider(5, 1, 4);
-        if (hipError_t e = tn_pick(key, idx, &best)) return e;
-        switch (best) {
-            TN_CASE(0, 2, 2) TN_CASE(1, 3, 3) TN_CASE(2, 4, 4) TN_CASE(3, 5, 1) TN_CASE(4, 5, 3)
-            TN_CASE4(5, 2, 2)
-            default: return launch_tn_k<Tin, Tc, RC, 5, 1, 4>(s, A, lda, a_rm, ka, B, ldb, b_rm, nb, sym, N, vec, P, nsplit_out, skip_unless);
         }
     } else {
         consider(2, 2, 2); consider(3, 3, 2); consider(4, 4, 2); consider(5, 1, 2); consider(5, 3, 2);
