@@ -122,29 +122,82 @@ template <> struct AFrag<DMD_RECON_FP32> { float v[4]; };
 template <> struct AFrag<DMD_RECON_BF16> { bf16x8 hi; };
 template <> struct AFrag<DMD_RECON_BF16X3> { bf16x8 hi, lo; };
 
+// The A fragments of a row tile.  FP64 and FP32: one row block at a time, the loads of
+// the block's nkg fragments are issued together (rows past N read row 0, which exists),
+// then the values are zeroed for those rows; loading fragment by fragment made each load
+// wait for the one before, a chain of memory latencies at every new row tile.  Fragments
+// past nkg are set to zero, so every fragment is redefined and the previous tile's values
+// are dead while the new ones load.  BF16 modes load and split fragment by fragment: the
+// batched form needs about 50 more registers there, and the bf16x3 kernel ran 25% slower
+// with them.
+template <int MODE> struct ARaw;
+template <> struct ARaw<DMD_RECON_FP64> { double2 x, y; };
+template <> struct ARaw<DMD_RECON_FP32> { float4 x; };
+template <> struct ARaw<DMD_RECON_BF16> { float4 x, y; };
+template <> struct ARaw<DMD_RECON_BF16X3> { float4 x, y; };
+
 template <int MODE>
-__device__ __forceinline__ void load_a(AFrag<MODE>& f, const typename RTraits<MODE>::Tphi* p, bool ok)
+__device__ __forceinline__ void load_a_raw(ARaw<MODE>& r, const typename RTraits<MODE>::Tphi* p)
 {
     if constexpr (MODE == DMD_RECON_FP64) {
-        if (ok) {
-            double2 x = reinterpret_cast<const double2*>(p)[0];
-            double2 y = reinterpret_cast<const double2*>(p)[1];
-            f.v[0] = x.x; f.v[1] = x.y; f.v[2] = y.x; f.v[3] = y.y;
-        } else {
-            f.v[0] = f.v[1] = f.v[2] = f.v[3] = 0.0;
-        }
+        r.x = reinterpret_cast<const double2*>(p)[0];
+        r.y = reinterpret_cast<const double2*>(p)[1];
     } else if constexpr (MODE == DMD_RECON_FP32) {
-        float4 x = ok ? reinterpret_cast<const float4*>(p)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        f.v[0] = x.x; f.v[1] = x.y; f.v[2] = x.z; f.v[3] = x.w;
+        r.x = reinterpret_cast<const float4*>(p)[0];
     } else {
-        float4 x = ok ? reinterpret_cast<const float4*>(p)[0] : make_float4(0.f, 0.f, 0.f, 0.f);
-        float4 y = ok ? reinterpret_cast<const float4*>(p)[1] : make_float4(0.f, 0.f, 0.f, 0.f);
-        float xs[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+        r.x = reinterpret_cast<const float4*>(p)[0];
+        r.y = reinterpret_cast<const float4*>(p)[1];
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void finish_a(AFrag<MODE>& f, const ARaw<MODE>& r, bool ok)
+{
+    if constexpr (MODE == DMD_RECON_FP64) {
+        f.v[0] = ok ? r.x.x : 0.0; f.v[1] = ok ? r.x.y : 0.0;
+        f.v[2] = ok ? r.y.x : 0.0; f.v[3] = ok ? r.y.y : 0.0;
+    } else if constexpr (MODE == DMD_RECON_FP32) {
+        f.v[0] = ok ? r.x.x : 0.f; f.v[1] = ok ? r.x.y : 0.f;
+        f.v[2] = ok ? r.x.z : 0.f; f.v[3] = ok ? r.x.w : 0.f;
+    } else {
+        const float xs[8] = {r.x.x, r.x.y, r.x.z, r.x.w, r.y.x, r.y.y, r.y.z, r.y.w};
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
-            const __bf16 h = (__bf16)xs[e];
+            const float v = ok ? xs[e] : 0.f;
+            const __bf16 h = (__bf16)v;
             f.hi[e] = h;
-            if constexpr (MODE == DMD_RECON_BF16X3) f.lo[e] = (__bf16)(xs[e] - (float)h);
+            if constexpr (MODE == DMD_RECON_BF16X3) f.lo[e] = (__bf16)(v - (float)h);
+        }
+    }
+}
+
+template <int MODE, int RBW, int KGMAX>
+__device__ __forceinline__ void load_tile_a(AFrag<MODE> (&a)[RBW][KGMAX], const typename RTraits<MODE>::Tphi* phi,
+                                            int64_t ldphi, int64_t N, int64_t tile_row0, int nkg, int l16, int lg)
+{
+    constexpr int KW = RTraits<MODE>::KW;
+#pragma unroll
+    for (int rb = 0; rb < RBW; ++rb) {
+        const int64_t row = tile_row0 + rb * 16 + l16;
+        const bool ok = row < N;
+        const typename RTraits<MODE>::Tphi* prow = phi + (ok ? row : 0) * ldphi;
+        if constexpr (MODE == DMD_RECON_FP64 || MODE == DMD_RECON_FP32) {
+            ARaw<MODE> raw[KGMAX] = {};
+#pragma unroll
+            for (int kg = 0; kg < KGMAX; ++kg)
+                if (kg < nkg) load_a_raw<MODE>(raw[kg], prow + kg * 16 + 4 * lg);
+#pragma unroll
+            for (int kg = 0; kg < KGMAX; ++kg) finish_a<MODE>(a[rb][kg], raw[kg], ok && kg < nkg);
+        } else {
+#pragma unroll
+            for (int kg = 0; kg < KGMAX; ++kg) {
+                if (kg < nkg) {
+                    ARaw<MODE> raw;
+                    if (ok) load_a_raw<MODE>(raw, prow + kg * 32 + 8 * lg);
+                    else raw.x = raw.y = make_float4(0.f, 0.f, 0.f, 0.f);
+                    finish_a<MODE>(a[rb][kg], raw, true);
+                }
+            }
         }
     }
 }
@@ -325,19 +378,7 @@ recon_kernel(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ldphi
         const int f_end = min(K, f0 + FC);
         const int64_t tile_row0 = (int64_t)rt * WG_ROWS + wave * RBW * 16;
         if (rt != cur_rt) {
-#pragma unroll
-            for (int rb = 0; rb < RBW; ++rb) {
-                const int64_t row = tile_row0 + rb * 16 + l16;
-                const bool ok = row < N;
-                const typename Tr::Tphi* prow = phi + (ok ? row : 0) * ldphi;
-#pragma unroll
-                for (int kg = 0; kg < KGMAX; ++kg) {
-                    if (kg < nkg) {
-                        const int m0 = (KW == 16) ? (kg * 16 + 4 * lg) : (kg * 32 + 8 * lg);
-                        load_a<MODE>(a[rb][kg], prow + m0, ok);
-                    }
-                }
-            }
+            load_tile_a<MODE, RBW, KGMAX>(a, phi, ldphi, N, tile_row0, nkg, l16, lg);
             cur_rt = rt;
         }
         {
@@ -446,19 +487,7 @@ recon_kernel_sb(const typename RTraits<MODE>::Tphi* __restrict__ phi, int64_t ld
         const int fc = (int)(item % n_fchunks);
         const int64_t tile_row0 = (int64_t)rt * WG_ROWS + wave * RBW * 16;
         if (rt != cur_rt) {
-#pragma unroll
-            for (int rb = 0; rb < RBW; ++rb) {
-                const int64_t row = tile_row0 + rb * 16 + l16;
-                const bool ok = row < N;
-                const typename Tr::Tphi* prow = phi + (ok ? row : 0) * ldphi;
-#pragma unroll
-                for (int kg = 0; kg < KGMAX; ++kg) {
-                    if (kg < nkg) {
-                        const int m0 = (KW == 16) ? (kg * 16 + 4 * lg) : (kg * 32 + 8 * lg);
-                        load_a<MODE>(a[rb][kg], prow + m0, ok);
-                    }
-                }
-            }
+            load_tile_a<MODE, RBW, KGMAX>(a, phi, ldphi, N, tile_row0, nkg, l16, lg);
             cur_rt = rt;
         }
         const int f_begin = fc * frames_per_chunk;
