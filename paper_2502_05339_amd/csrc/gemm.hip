@@ -111,19 +111,36 @@ gemm_nn_kernel(const T* A, int64_t lda, const T* __restrict__ B, int64_t ldb,
             if (idx < KB * NP) Bs[buf][idx % KB][idx / KB] = bpre[q];
         }
     };
+    // VEC (N a multiple of VW): one unguarded load per k-step from an address clamped into
+    // the matrix, so the loads of a chunk are all in flight together; operands of columns
+    // past K or rows past N are zeroed when the chunk is consumed (take_a), after the wait
+    // that precedes it anyway.  A guard per load would make each wait for the one before.
     auto fetch_a = [&](int k0) {
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
             const int k = k0 + 4 * ks + kq;
-            const T* src = A + (int64_t)k * lda + rl;
-            VT v;
-            if (VEC && k < K && rl + VW <= N) v = *reinterpret_cast<const VT*>(src);
-            else {
+            if constexpr (VEC) {
+                apre[ks] = *reinterpret_cast<const VT*>(A + (int64_t)min(k, K - 1) * lda + min(rl, N - VW));
+            } else {
+                const T* src = A + (int64_t)k * lda + rl;
+                VT v;
                 T* pv = reinterpret_cast<T*>(&v);
 #pragma unroll
                 for (int e = 0; e < VW; ++e) pv[e] = (k < K && rl + e < N) ? src[e] : T(0);
+                apre[ks] = v;
             }
-            apre[ks] = v;
+        }
+    };
+    auto take_a = [&](int k0) {
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            acur[ks] = apre[ks];
+            if constexpr (VEC) {
+                const bool valid = k0 + 4 * ks + kq < K && rl < N;
+                T* pv = reinterpret_cast<T*>(&acur[ks]);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) pv[e] = valid ? pv[e] : T(0);
+            }
         }
     };
 
@@ -135,8 +152,7 @@ gemm_nn_kernel(const T* A, int64_t lda, const T* __restrict__ B, int64_t ldb,
     for (int c = 0; c < nchunk; ++c) {
         const int buf = c & 1;
         const bool more = c + 1 < nchunk;
-#pragma unroll
-        for (int ks = 0; ks < NKS; ++ks) acur[ks] = apre[ks];
+        take_a(c * KB);
         if (more) { fetch_b((c + 1) * KB); fetch_a((c + 1) * KB); }
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
@@ -188,7 +204,8 @@ static hipError_t launch_nn_t(hipStream_t s, const T* A, int64_t lda, const T* B
     constexpr int BM = (4 / CS) * 16 * (16 / sizeof(T));
     dim3 grid((unsigned)ceil_div(N, BM));
     const int vw = 16 / sizeof(T);
-    bool vec = (lda % vw == 0) && ((uintptr_t)A % 16 == 0) && (c_rowmajor || ((ldc % vw == 0) && ((uintptr_t)C % 16 == 0)));
+    bool vec = (lda % vw == 0) && ((uintptr_t)A % 16 == 0) && N % vw == 0 &&
+               (c_rowmajor || ((ldc % vw == 0) && ((uintptr_t)C % 16 == 0)));
     if (vec)
         hipLaunchKernelGGL((gemm_nn_kernel<T, NB, CS, true>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, c_rowmajor, N, K, n, skip_unless,
                            b_upper);
