@@ -125,6 +125,31 @@ def test_randomized_vs_twin_small(gpu_lib, precision, tol_lam, tol_field):
     assert int(m.info[0].item()) == 0
 
 
+@pytest.mark.parametrize("precision,tol_lam,tol_field", [("mixed", 1e-5, 1e-4), ("fp64", 1e-9, 1e-9)])
+def test_randomized_vs_twin_ragged_n(gpu_lib, precision, tol_lam, tol_field):
+    """N = 3*61*67 = 12261 (odd): the products take their guarded paths (no 16-byte loads
+    for N not a multiple of 4, ragged last row chunks) against the FP64 twin."""
+    cfg = synth.Config("ragged", (3, 61, 67), 90, 20, 0.95, 1e-4, 223, r=36, p=8, q=2)
+    _print(f"case: ragged N={cfg.N} randomized {precision} vs FP64 twin")
+    g = synth.generate(cfg)
+    if precision == "fp64":
+        g.Omega = g.Omega.astype(np.float64)
+    m, Z = _gpu_fit(g, cfg, precision)
+    tw = oracle.fit_randomized(g.Z.astype(np.float64), cfg.r, g.Omega.astype(np.float64), cfg.q)
+    w = oracle.amplitude_weights(tw.phi, tw.b)
+    ia, ib = oracle.match_eigs(m.lam_host(), tw.lam)
+    d = np.abs(m.lam_host()[ia] - tw.lam[ib])
+    wrel = float(np.sum(w[ib] * d) / np.sum(w[ib] * np.abs(tw.lam[ib])))
+    ks = np.arange(cfg.m)
+    U = _fields(m, ks, "fp64" if precision == "fp64" else "fp32")
+    Uo = oracle.reconstruct(tw.phi, tw.lam, tw.b, ks).T
+    ferr = max_frame_rel(U, Uo)
+    _print(f"  lambda weighted {wrel:.3e} fields {ferr:.3e}")
+    assert wrel <= tol_lam
+    assert ferr <= tol_field
+    assert int(m.info[0].item()) == 0
+
+
 def test_g3_mixed_vs_exact_well_posed_c2(gpu_lib):
     """Full-size c2-wp (N = 131072, m = 200, r = 150, p = 10, q = 2)."""
     cfg = synth.config("c2-wp")
