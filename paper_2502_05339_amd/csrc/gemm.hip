@@ -398,7 +398,8 @@ gemm_tn_kernel(const Tin* __restrict__ A, int64_t lda, int a_rowmajor, int ka,
                           has[q] ? t - na : 0, ldb_s, RC * lda_s);
     }
     VT pre[TN_MAXT];
-    // c0: chunk offset inside the split
+    // the next chunk of every task into registers: fetch_whole for a chunk whose rows all
+    // exist, fetch (c0 = the chunk's row offset inside the split) with row guards
     auto fetch_whole = [&]() {
 #pragma unroll
         for (int q = 0; q < TN_MAXT; ++q)
