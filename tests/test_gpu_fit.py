@@ -125,11 +125,14 @@ def test_randomized_vs_twin_small(gpu_lib, precision, tol_lam, tol_field):
     assert int(m.info[0].item()) == 0
 
 
+@pytest.mark.parametrize("grid", [(3, 61, 67), (2, 50, 98)])
 @pytest.mark.parametrize("precision,tol_lam,tol_field", [("mixed", 1e-5, 1e-4), ("fp64", 1e-9, 1e-9)])
-def test_randomized_vs_twin_ragged_n(gpu_lib, precision, tol_lam, tol_field):
+def test_randomized_vs_twin_ragged_n(gpu_lib, precision, tol_lam, tol_field, grid):
     """N = 3*61*67 = 12261 (odd): the products take their guarded paths (no 16-byte loads
-    for N not a multiple of 4, ragged last row chunks) against the FP64 twin."""
-    cfg = synth.Config("ragged", (3, 61, 67), 90, 20, 0.95, 1e-4, 223, r=36, p=8, q=2)
+    for N not a multiple of 4, ragged last row chunks).  N = 2*50*98 = 9800 (a multiple of
+    4, not of the 128-row tile of the NN product): the 16-byte path whose last row tile
+    reads clamped rows and zeroes them.  Both against the FP64 twin."""
+    cfg = synth.Config("ragged", grid, 90, 20, 0.95, 1e-4, 223, r=36, p=8, q=2)
     _print(f"case: ragged N={cfg.N} randomized {precision} vs FP64 twin")
     g = synth.generate(cfg)
     if precision == "fp64":
